@@ -1,0 +1,67 @@
+"""Spectral checks of the FP64 oracle (test infrastructure only).
+
+The paper's kernel matrices are symmetric: its brute-force construction sets
+K_ij and K_ji together (Section 4, Algorithm 1). A directed k-NN pattern is not
+symmetric, so for spectral checks the oracle also runs every pass on the union
+pattern E u E^T, where the symmetric conjugate S^{-1} Kt S^{-1} - P^{-2}
+(Section 2.2, symmetric discrete Kolmogorov operator) is an exactly symmetric
+matrix similar to the discrete Kolmogorov matrix L. Its eigenvalues approximate
+those of the Kolmogorov operator; on the uniform unit 2-sphere the operator is
+the Laplace-Beltrami operator (Section 5, spherical manifold) whose spectrum is
+-l(l+1) with multiplicity 2l+1.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import (Pattern, adhoc_bandwidth, chi, density, grid_scale, knn, normalize,
+               SYMMETRIC, GENERATOR)
+
+
+def union_pattern(idx: np.ndarray, d2: np.ndarray) -> Pattern:
+    """E u E^T of the directed k-NN pattern, with each entry's squared distance.
+    A pair stored in both directions carries the same exact distance (the
+    oracle computes D2 symmetrically), so duplicates are merged by max."""
+    n, k = idx.shape
+    rows = np.repeat(np.arange(n, dtype=np.int64), k)
+    cols = idx.ravel().astype(np.int64)
+    dd = d2.ravel()
+    r2 = np.concatenate([rows, cols])
+    c2 = np.concatenate([cols, rows])
+    v2 = np.concatenate([dd, dd])
+    order = np.lexsort((c2, r2))
+    r2, c2, v2 = r2[order], c2[order], v2[order]
+    keep = np.ones(len(r2), dtype=bool)
+    keep[1:] = (r2[1:] != r2[:-1]) | (c2[1:] != c2[:-1])
+    r2, c2, v2 = r2[keep], c2[keep], v2[keep]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, r2 + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    return Pattern(rowptr, c2.astype(np.int32), np.ascontiguousarray(v2, dtype=np.float64))
+
+
+def union_operator(X: np.ndarray, k: int, k0: int, d: float, alpha: float, beta: float,
+                   e_min: float = 1e-3, e_max: float = 1e1, G: int = 64,
+                   out_kind: int = SYMMETRIC):
+    """Run the full oracle pipeline on the union pattern; return the sparse
+    matrix (CSR, scipy) of the requested kind, plus the diagonal factors."""
+    idx, d2 = knn(X, k)
+    pat = union_pattern(idx, d2)
+    b = adhoc_bandwidth(d2, k0)
+    ta = chi(pat, b, e_min, e_max, G)
+    psi, rho = density(pat, b, ta.e_star, d, beta)
+    s = grid_scale(b, rho)
+    tb = chi(pat, rho, e_min * s, e_max * s, G)
+    val, q, P, D = normalize(pat, rho, tb.e_star, alpha, d, out_kind)
+    n = pat.n
+    A = sp.csr_matrix((val, pat.col, pat.rowptr), shape=(n, n))
+    return A, dict(P=P, D=D, psi=psi, rho=rho, e_a=ta.e_star, e_b=tb.e_star,
+                   tune_a=ta, tune_b=tb, pattern=pat)
+
+
+def leading_eigenvalues(A, count: int) -> np.ndarray:
+    """The `count` eigenvalues of the symmetric matrix A nearest zero from below
+    (dense symmetric eigensolver; meant for n of a few thousand)."""
+    w = np.linalg.eigvalsh(A.toarray())
+    return np.sort(w)[::-1][:count]

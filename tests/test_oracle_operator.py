@@ -1,0 +1,240 @@
+"""Pins of the oracle's tuning, density and operator normalisation (CPU only).
+
+What fixes each step, other than the oracle itself:
+  * closed forms on the regular n-gon (all rows identical and circulant):
+    the tuning sum chi(e), its log-slope optimum (Section 2.3), and the exact
+    Fourier eigenvalues of the discrete Kolmogorov matrix L (Section 2.2);
+  * invariants of the construction (Section 2.2): D^{-1} Kt is Markov, L 1 = 0,
+    Kt is symmetric (detailed balance D_i M_ij = D_j M_ji), the conjugate
+    S^{-1} Kt S^{-1} - P^{-2} is symmetric and similar to L, and M and L do not
+    change under psi -> c psi, e -> e c^{-2 beta};
+  * the paper's worked examples (tests/golden/paper_values.json): the uniform
+    sphere density 1/(4 pi) and Laplacian spectrum -l(l+1) (Section 5.2), the
+    Gaussian Kolmogorov operator L x_s = -c x_s / Sigma_ss for c = 1 and c = 2
+    (Sections 2 and 5.1), with c = 2 - 2 alpha + d beta + 2 beta (Section 2.2).
+Statistical tolerances cover the known finite-sample, self-term and
+truncation biases of the estimator at these sizes.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads
+from oracle import spectral
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+# ------------------------------------------------------------------ n-gon closed forms
+def polygon_setup(n=101, k=9, k0=8):
+    X = workloads.regular_polygon(n)
+    idx, d2 = oracle.knn(X, k)
+    h = (k - 1) // 2
+    chords = np.array([(2.0 * math.sin(math.pi * r / n)) ** 2 for r in range(1, h + 1)])
+    return X, idx, d2, chords
+
+
+def test_polygon_pattern_is_symmetric_window():
+    n, k = 101, 9
+    _, idx, d2, chords = polygon_setup(n, k)
+    for i in range(n):
+        assert sorted((idx[i] - i) % n) == sorted([0, 1, 2, 3, 4, n - 1, n - 2, n - 3, n - 4])
+    # distances from float32 vertices agree with exact chords to float32 accuracy
+    np.testing.assert_allclose(np.sort(d2[:, 1:], axis=1)[:, ::2], np.tile(chords, (n, 1)), rtol=2e-6)
+
+
+def test_polygon_chi_and_optimum_closed_form():
+    n, k, G = 101, 9, 64
+    _, idx, d2, chords = polygon_setup(n, k)
+    b = oracle.adhoc_bandwidth(d2, 8)
+    b2 = 2.0 * chords.sum()
+    np.testing.assert_allclose(b ** 2, b2, rtol=2e-6)
+    pat = oracle.Pattern.from_knn(idx, d2)
+    t = oracle.chi(pat, b, 1e-3, 1e1, G)
+    e = np.exp(np.log(1e-3) + np.arange(G) * (np.log(1e1) - np.log(1e-3)) / (G - 1))
+    chi_cf = n * (1.0 + 2.0 * np.exp(-chords[None, :] / (e[:, None] * b2)).sum(axis=1))
+    np.testing.assert_allclose(t.chi, chi_cf, rtol=1e-5)
+    np.testing.assert_allclose(t.e_grid, e, rtol=1e-14)
+    slope = np.diff(np.log(chi_cf)) / np.diff(np.log(e))
+    top2 = np.sort(slope)[-2:]
+    if top2[1] - top2[0] > 1e-5:
+        assert t.g_star == int(np.argmax(slope))
+    assert t.dim == pytest.approx(2 * slope.max(), rel=1e-4)
+
+
+def test_polygon_generator_fourier_eigenvalues():
+    """All rows of the n-gon operator are the same circulant, so the Fourier
+    modes cos(2 pi nu i / n) are exact eigenvectors of L with eigenvalue
+    (sum_r M_r cos(2 pi nu r / n) - 1) / (e P^2)."""
+    n, k = 101, 9
+    _, idx, d2, chords = polygon_setup(n, k)
+    pat = oracle.Pattern.from_knn(idx, d2)
+    rho = np.full(n, 1.7)
+    e = 0.05
+    alpha, d = -0.5, 1.0
+    L, q, P, D = oracle.normalize(pat, rho, e, alpha, d, oracle.GENERATOR)
+    Lm = sp.csr_matrix((L, pat.col, pat.rowptr), shape=(n, n))
+    w = np.concatenate([[1.0], np.exp(-chords / (e * rho[0] ** 2))])
+    Msum = w[0] + 2 * w[1:].sum()
+    for nu in range(0, 6):
+        v = np.cos(2 * np.pi * nu * np.arange(n) / n)
+        mu = ((w[0] + 2 * (w[1:] * np.cos(2 * np.pi * nu * np.arange(1, 5) / n)).sum()) / Msum - 1.0) \
+            / (e * (rho[0] / 2) ** 2)
+        np.testing.assert_allclose(Lm @ v, mu * v, rtol=2e-5, atol=1e-9 * max(1.0, abs(mu)))
+    np.testing.assert_allclose(P, rho / 2, rtol=0)
+
+
+# ------------------------------------------------------------------ invariants (sphere, k-NN pattern)
+@pytest.fixture(scope="module")
+def sphere_run():
+    X = workloads.sphere2(2000, seed=0)
+    return X, oracle.pipeline(X, 32, 8, 2.0, -0.5, -0.5)
+
+
+def test_markov_rows_and_csr_layout(sphere_run):
+    X, r = sphere_run
+    n, k = 2000, 32
+    val = r.val.reshape(n, k)
+    assert (val > 0).all()
+    np.testing.assert_allclose(val.sum(axis=1), 1.0, atol=1e-14)
+    col = r.col.reshape(n, k)
+    assert (np.diff(col, axis=1) > 0).all()
+    assert (r.rowptr == np.arange(n + 1) * k).all()
+    # the CSR rows hold exactly the k-NN sets
+    assert (np.sort(r.idx, axis=1) == col).all()
+
+
+def test_detailed_balance_and_generator_rows(sphere_run):
+    X, r = sphere_run
+    n, k = 2000, 32
+    pat = oracle.Pattern.from_knn(r.idx, r.d2)
+    M, q, P, D = oracle.normalize(pat, r.rho, r.tune_b.e_star, -0.5, 2.0, oracle.MARKOV)
+    Mm = sp.csr_matrix((M, pat.col, pat.rowptr), shape=(n, n))
+    Kt = sp.diags(D) @ Mm                       # D M = Kt
+    mutual = Kt.multiply(Kt.T > 0)
+    diff = abs(mutual - mutual.T).max()
+    assert diff <= 1e-13 * abs(mutual).max()
+    L, *_ = oracle.normalize(pat, r.rho, r.tune_b.e_star, -0.5, 2.0, oracle.GENERATOR)
+    Lm = sp.csr_matrix((L, pat.col, pat.rowptr), shape=(n, n))
+    assert abs(Lm @ np.ones(n)).max() <= 1e-12 * abs(L).max()
+    # L = e^-1 P^-2 (M - I), entrywise
+    e = r.tune_b.e_star
+    Lref = sp.diags(1.0 / (e * P ** 2)) @ (Mm - sp.eye(n))
+    assert abs(Lm - Lref).max() <= 1e-12 * abs(L).max()
+
+
+def test_scale_invariance_of_operator(sphere_run):
+    X, r = sphere_run
+    pat = oracle.Pattern.from_knn(r.idx, r.d2)
+    beta, e = -0.5, r.tune_b.e_star
+    for c in (0.37, 5.0):
+        for kind in (oracle.MARKOV, oracle.GENERATOR):
+            v0, *_ = oracle.normalize(pat, r.rho, e, -0.5, 2.0, kind)
+            v1, *_ = oracle.normalize(pat, r.rho * c ** beta, e * c ** (-2 * beta), -0.5, 2.0, kind)
+            np.testing.assert_allclose(v1, v0, rtol=1e-11, atol=1e-12 * abs(v0).max())
+
+
+def test_union_symmetric_conjugate_similar_to_generator():
+    X = workloads.sphere2(800, seed=4)
+    A, info = spectral.union_operator(X, 24, 8, 2.0, -0.5, -0.5)
+    assert abs(A - A.T).max() <= 1e-15 * abs(A).max() * 10
+    pat = info["pattern"]
+    n = pat.n
+    L, q, P, D = oracle.normalize(pat, info["rho"], info["e_b"], -0.5, 2.0, oracle.GENERATOR)
+    Lm = sp.csr_matrix((L, pat.col, pat.rowptr), shape=(n, n)).toarray()
+    S = P * np.sqrt(D)
+    np.testing.assert_allclose(S[:, None] * Lm / S[None, :], A.toarray(),
+                               rtol=1e-10, atol=1e-10 * abs(A).max())
+    w_sym = np.sort(np.linalg.eigvalsh(A.toarray()))
+    w_gen = np.sort(np.linalg.eigvals(Lm).real)
+    np.testing.assert_allclose(w_gen, w_sym, atol=1e-8 * abs(w_sym).max())
+
+
+# ------------------------------------------------------------------ paper's worked examples
+def test_uniform_sphere_density_and_dimension():
+    """Section 5.2: psi_uni = 1/(4 pi). With k = 256 the truncation bias is
+    below 1%; the self term (about 1/(n psi pi e b^2), 3%) and the spread of
+    the ad-hoc bandwidth bias the estimate upward by a few percent."""
+    truth = GOLD["uniform_sphere_density"]["value"]
+    X = workloads.sphere2(4000, seed=1)
+    idx, d2 = oracle.knn(X, 256)
+    pat = oracle.Pattern.from_knn(idx, d2)
+    b = oracle.adhoc_bandwidth(d2, 32)
+    ta = oracle.chi(pat, b, 1e-3, 1e1, 64)
+    psi, rho = oracle.density(pat, b, ta.e_star, 2.0, -0.5)
+    ratio = psi.mean() / truth
+    assert 0.97 < ratio < 1.10, ratio
+    assert 1.85 < ta.dim < 2.05, ta.dim        # 2 max chi' estimates d = 2 (Section 2.3)
+    assert not ta.edge
+    np.testing.assert_allclose(rho, 2 * psi ** -0.5, rtol=1e-14)
+
+
+def test_uniform_sphere_laplacian_spectrum():
+    """Section 5.2: on the uniform sphere the operator is the Laplacian; the
+    leading eigenvalues of the (union-pattern) symmetric conjugate cluster at
+    -2 (3 of them), -6 (5) and -12 (7). The operator bandwidth is fixed so that
+    about 30 samples fall inside one kernel width; the remaining bias grows
+    with |lambda| (discretisation error of order h lambda^2)."""
+    n, k, k0 = 4000, 256, 32
+    X = workloads.sphere2(n, seed=1)
+    idx, d2 = oracle.knn(X, k)
+    pat = spectral.union_pattern(idx, d2)
+    b = oracle.adhoc_bandwidth(d2, k0)
+    ta = oracle.chi(pat, b, 1e-3, 1e1, 64)
+    psi, rho = oracle.density(pat, b, ta.e_star, 2.0, -0.5)
+    h = 30.0 / (math.pi * n / (4 * math.pi))
+    e_b = h / np.median(rho) ** 2
+    val, q, P, D = oracle.normalize(pat, rho, e_b, -0.5, 2.0, oracle.SYMMETRIC)
+    A = sp.csr_matrix((val, pat.col, pat.rowptr), shape=(n, n))
+    w = spectral.leading_eigenvalues(A, 16)
+    assert abs(w[0]) < 1e-8
+    lo = 1
+    for l, lam, mult in GOLD["sphere_laplacian_spectrum"]["value"]:
+        cl = w[lo:lo + mult]
+        tol = 0.05 + 0.01 * l * (l + 1)
+        assert abs(cl.mean() / lam - 1) < tol, (l, cl)
+        lo += mult
+    # clusters are separated: multiplicities 3, 5, 7
+    assert w[3] > -3.5 > w[4] and w[8] > -8.5 > w[9] and w[15] > -15
+
+
+def rayleigh_quotients(X, k, k0, alpha, beta, d):
+    n = len(X)
+    A, info = spectral.union_operator(X, k, k0, d, alpha, beta)
+    S = info["P"] * np.sqrt(info["D"])
+    out = []
+    for c in range(X.shape[1]):
+        f = X[:, c].astype(np.float64)
+        f = f - (S ** 2 * f).sum() / (S ** 2).sum()      # remove the constant mode
+        g = S * f                                        # <f, L f>_S = (Sf)^T Lhat (Sf)
+        out.append(g @ (A @ g) / (g @ g))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("alpha,beta", [(-0.5, -0.5), (0.0, -0.25), (-1.0, -0.5), (0.0, 0.0)])
+def test_gaussian_coordinates_are_eigenfunctions_with_eigenvalue_minus_c(alpha, beta):
+    """For psi = N(0, I_2), L_{psi,c} x_s = -c x_s. The tuned kernel sits close to
+    the sample spacing, which biases |lambda| low by 10-20% at n = 4000."""
+    X = workloads.gaussian_iid(4000, 2, seed=3)
+    d = 2.0
+    c = 2 - 2 * alpha + d * beta + 2 * beta
+    rq = rayleigh_quotients(X, 128, 32, alpha, beta, d)
+    ratio = rq / (-c)
+    assert ((ratio > 0.78) & (ratio < 1.08)).all(), (c, rq)
+
+
+def test_gaussian4d_paper_example():
+    """Section 5.1 (m = 4): Sigma = diag(sqrt2, sqrt2, sqrt3, sqrt3), c = 1 with
+    alpha = -d/4, beta = -1/2; x_1, x_2 have eigenvalue -1/sqrt2 and x_3, x_4
+    have -1/sqrt3."""
+    g = GOLD["gaussian4d_example"]
+    rng = np.random.default_rng(7)
+    cov = np.array(g["covariance_diag"])
+    X = (rng.standard_normal((g["n"], 4)) * np.sqrt(cov)).astype(np.float32)
+    rq = rayleigh_quotients(X, 256, 32, -1.0, -0.5, 4.0)
+    np.testing.assert_allclose(rq, g["eigenvalue_of_coordinate"], rtol=0.07)
