@@ -1,0 +1,217 @@
+/*
+ * kvb — self-tuning variable-bandwidth kernel matrices on MI355X (gfx950).
+ *
+ * C ABI of the HIP library libkvb.so. It builds, from n samples x^(i) in R^m,
+ * the sparse kernel matrix that approximates the Kolmogorov operator
+ * L_{psi,c} (Davis & Giannakis, arXiv 2104.15124, Sections 2 and 4):
+ *
+ *   kvb_knn            k nearest neighbours of every sample (the sparsity
+ *                      pattern; neighbour order I(x, k) of Section 2.1)
+ *   kvb_bandwidth      ad-hoc bandwidth b (Section 2.1, bandwidth eq.) or the
+ *                      density estimate psi and operator bandwidth
+ *                      rho = 2 psi^beta (Section 2.1 density eqs.; Algorithm 1
+ *                      caption)
+ *   kvb_grid_scale     power-of-two placement of the operator-stage e grid
+ *   kvb_tune_eps       bandwidth self-tuning: chi(e) = sum_ij K_ij on a log
+ *                      grid, optimum = argmax d log chi / d log e (Section 2.3)
+ *   kvb_assemble_csr   q, alpha-normalised Kt, degrees D and the Markov matrix
+ *                      D^{-1} Kt (or L, or its symmetric conjugate) as CSR
+ *                      (Section 2.2)
+ *
+ * Notation. e is the paper's epsilon^2. One kernel serves both stages:
+ *   K_ij = exp(-|x_i - x_j|^2 / (e rho_i rho_j)),
+ * with rho = b for the density kernel K_eps (Section 2.1) and rho = 2 psi^beta
+ * for the operator kernel K_{eps,beta} (Section 2.2), where 4 epsilon^2
+ * (psi_i psi_j)^beta = e rho_i rho_j. P_i = psi_i^beta = rho_i / 2.
+ * The pattern is the directed k-NN graph: row i stores i itself and its k-1
+ * nearest other samples, all k entries kept (no threshold truncation).
+ *
+ * Memory. Every pointer argument is a DEVICE pointer unless its name ends in
+ * _host. The caller allocates and owns all inputs and outputs; the library
+ * never frees or retains them beyond the call. The library owns only the
+ * scratch memory inside a context (grown on demand, released by kvb_destroy).
+ * Arrays must be aligned to their element size. Layouts are row-major and dense.
+ *
+ * Streams. A context is bound to one HIP stream at creation. All work of a
+ * call is enqueued on that stream and the call returns without waiting,
+ * except calls that return *_host values (kvb_grid_scale, kvb_tune_eps,
+ * kvb_knn_fallback_rows), which synchronise the context stream before returning.
+ *
+ * Errors. Every int-returning entry point returns a status: 0 = OK, > 0 = OK
+ * with a warning, < 0 = error (nothing useful was written). No call aborts or
+ * throws. kvb_last_error(ctx) describes the last non-zero status of that
+ * context. A context is not thread-safe; distinct contexts are independent.
+ *
+ * Determinism. Reductions run in a fixed order with no floating-point
+ * atomics, so results are bitwise reproducible from run to run.
+ */
+#ifndef KVB_H
+#define KVB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define KVB_OK 0
+#define KVB_W_GRID_EDGE 1    /* tuning optimum on the first or last slope of the grid */
+#define KVB_W_FALLBACK 2     /* kvb_knn_fallback_rows: some rows needed the exact fallback scan */
+#define KVB_E_INVALID (-1)   /* an argument is out of range or a pointer is null/misaligned */
+#define KVB_E_NOMEM (-2)     /* scratch allocation failed or exceeds KVB_OPT_SCRATCH_LIMIT */
+#define KVB_E_HIP (-3)       /* a HIP runtime call failed (message carries its error string) */
+#define KVB_E_UNSUPPORTED (-4) /* valid but beyond this build's capacity, or not a gfx950 device */
+#define KVB_E_NOT_TRAINED (-5) /* learned mode requested before a partitioner exists */
+#define KVB_E_IO (-6)        /* partitioner file missing, short or corrupt */
+
+/* ---- k-NN modes ---- */
+#define KVB_KNN_F32 0        /* FP32 distance tiles (direct differences for m <= 8, FP32 MFMA otherwise) */
+#define KVB_KNN_BF16 1       /* BF16 MFMA distance tiles, FP32 accumulation */
+#define KVB_KNN_LEARNED 2    /* learned partitioner routes queries to candidate buckets */
+
+/* ---- bandwidth modes ---- */
+#define KVB_BW_ADHOC 0       /* rho_i = b_i = sqrt(sum_{r=1..k0} d2[i, r]) */
+#define KVB_BW_DENSITY 1     /* psi_i and rho_i = 2 psi_i^beta from the density kernel with rho = b */
+
+/* ---- output kinds of kvb_assemble_csr ---- */
+#define KVB_OUT_MARKOV 0     /* M = D^{-1} Kt (row-stochastic) */
+#define KVB_OUT_GENERATOR 1  /* L = e^{-1} P^{-2} (M - I) */
+#define KVB_OUT_SYMMETRIC 2  /* Lhat = e^{-1} (S^{-1} Kt S^{-1} - P^{-2}), S = P D^{1/2} */
+
+/* ---- row flags written by kvb_knn ---- */
+#define KVB_ROW_RECHECK 1    /* FP64 recheck decided membership at the k-th neighbour */
+#define KVB_ROW_FALLBACK 2   /* the row was recomputed by the exact fallback scan */
+#define KVB_ROW_UNCERTIFIED 4 /* learned mode: no exactness certificate for this row */
+
+/* ---- options (kvb_set_option) ---- */
+#define KVB_OPT_FORCE_FALLBACK 1 /* value N > 0: also send every N-th row to the fallback (testing) */
+#define KVB_OPT_SCRATCH_LIMIT 2  /* value: maximum scratch bytes; 0 = unlimited */
+
+typedef struct kvb_ctx_s* kvb_ctx;
+
+/* Create a context bound to hip_stream (a hipStream_t; NULL = the null stream)
+ * on the current device. Fails with KVB_E_UNSUPPORTED on a non-gfx950 device. */
+int kvb_create(kvb_ctx* out, void* hip_stream);
+
+/* Release the context and its scratch. Waits for its stream first. NULL is a no-op. */
+void kvb_destroy(kvb_ctx ctx);
+
+/* Message of the last non-zero status of ctx ("" if none). Owned by ctx. */
+const char* kvb_last_error(kvb_ctx ctx);
+
+/* Set an option (KVB_OPT_*). Unknown keys or bad values -> KVB_E_INVALID. */
+int kvb_set_option(kvb_ctx ctx, int32_t key, int64_t value);
+
+/*
+ * Exact k-nearest-neighbour self-join (Section 2.1 neighbour order; the
+ * brute-force pattern of Section 4, Algorithm 1, with a fixed k per row).
+ *   X        [n, m] float32 row-major samples (finite values).
+ *   k        neighbours per row including the row itself, 1 <= k <= n.
+ *   mode     KVB_KNN_F32 or KVB_KNN_BF16 (exact sets), KVB_KNN_LEARNED
+ *            (needs kvb_part_*; recall < 1 possible).
+ *   margin   extra candidates kept by the distance tiles before the exact
+ *            re-rank, 0 <= margin and k + margin <= 256.
+ *   idx      [n, k] int32 out: row i = i, then the k-1 nearest j != i.
+ *   d2       [n, k] float32 out: squared distances (d2[i, 0] = 0), ascending.
+ *   row_flags [n] int32 out (KVB_ROW_* bits) or NULL.
+ * Membership of the k-th neighbour is decided in FP64 (ties by smaller index);
+ * within a row, entries are ordered by their compensated FP32 distance.
+ * Requires n < 2^31 and m <= 1024. Asynchronous: rows that needed the exact
+ * fallback are marked in row_flags and counted by kvb_knn_fallback_rows.
+ * Modes other than KVB_KNN_F32 that this build lacks return KVB_E_UNSUPPORTED.
+ */
+int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k,
+            int32_t mode, int32_t margin, int32_t* idx, float* d2, int32_t* row_flags);
+
+/* Number of rows of the last kvb_knn call on ctx that took the exact fallback
+ * scan. Synchronises the context stream. Returns KVB_W_FALLBACK if > 0. */
+int kvb_knn_fallback_rows(kvb_ctx ctx, int64_t* count_host);
+
+/*
+ * Per-sample bandwidths over the k-NN pattern (idx, d2 as written by kvb_knn).
+ *   KVB_BW_ADHOC:   rho_i = sqrt(sum_{r=1..k0} d2[i, r]), 1 <= k0 < k
+ *                   (Section 2.1, bandwidth eq.). b, e, d, beta, psi unused.
+ *   KVB_BW_DENSITY: psi_i = sum_r exp(-d2[i,r] / (e b_i b_j)) / (n (pi e b_i^2)^{d/2}),
+ *                   rho_i = 2 psi_i^beta, with j = idx[i, r] and n the total
+ *                   sample count (Section 2.1 density eqs.; Algorithm 1 caption).
+ *                   b [n] float32 in; psi [n] float32 out or NULL. e > 0, d > 0.
+ *   rho [n] float32 out.
+ */
+int kvb_bandwidth(kvb_ctx ctx, const int32_t* idx, const float* d2, int64_t n, int32_t k,
+                  int32_t mode, int32_t k0, const float* b, double e, double d, double beta,
+                  float* rho, float* psi);
+
+/*
+ * Operator-stage grid placement: *scale_host = 2^round(log2(gm(ref^2)/gm(rho^2))),
+ * gm = geometric mean over the n samples (FP64, fixed-order reduction). Scaling
+ * the e grid by it moves the grid to where e rho_i rho_j matches the density
+ * stage; the Kolmogorov matrix is invariant under psi -> c psi, e -> e c^{-2 beta}
+ * (Section 2.2), so only the grid's coverage changes. ref, rho [n] float32, > 0.
+ * Synchronises the context stream.
+ */
+int kvb_grid_scale(kvb_ctx ctx, const float* ref, const float* rho, int64_t n,
+                   double* scale_host);
+
+/*
+ * Bandwidth self-tuning (Section 2.3) over the k-NN pattern:
+ *   e_g = exp(ln e_min + g (ln e_max - ln e_min)/(G - 1)), g = 0..G-1,
+ *   chi[g] = sum_i sum_r exp(-d2[i,r] / (e_g rho_i rho_{idx[i,r]})) (self terms included),
+ *   slope_g = (ln chi[g+1] - ln chi[g]) / (ln e_{g+1} - ln e_g), g = 0..G-2,
+ *   g* = first argmax of slope, *e_star_host = e_{g*}, *dim_host = 2 slope_{g*}.
+ * Kernel values are FP32 per entry, summed per row in FP32 and across rows in
+ * FP64 in a fixed order. 3 <= G <= 256, 0 < e_min < e_max.
+ * chi_host [G] (or NULL), e_star_host (required), dim_host (or NULL) are host memory.
+ * Returns KVB_W_GRID_EDGE when g* is 0 or G-2. Synchronises the context stream.
+ */
+int kvb_tune_eps(kvb_ctx ctx, const int32_t* idx, const float* d2, const float* rho,
+                 int64_t n, int32_t k, double e_min, double e_max, int32_t G,
+                 double* chi_host, double* e_star_host, double* dim_host);
+
+/*
+ * Normalisation into CSR (Section 2.2):
+ *   K_ir = exp(-d2[i,r] / (e rho_i rho_j)), P_i = rho_i / 2,
+ *   q_i = P_i^{-d} sum_r K_ir, Kt_ir = K_ir / (q_i q_j)^alpha, D_i = sum_r Kt_ir,
+ *   out_kind KVB_OUT_MARKOV:    val = Kt_ir / D_i
+ *            KVB_OUT_GENERATOR: val = (Kt_ir / D_i - [j == i]) / (e P_i^2)
+ *            KVB_OUT_SYMMETRIC: val = (Kt_ir / (S_i S_j) - [j == i] / P_i^2) / e, S = P sqrt(D)
+ * Entries are evaluated with an FP64 argument and exponential; q and D are
+ * FP64 row sums (compensated). Columns ascend within each row.
+ *   rowptr [n+1] int64 out (rowptr[i] = i k), col [n k] int32 out,
+ *   val [n k] float32 out, P [n] float64 out or NULL, D [n] float64 out or NULL.
+ */
+int kvb_assemble_csr(kvb_ctx ctx, const int32_t* idx, const float* d2, const float* rho,
+                     int64_t n, int32_t k, double e, double alpha, double d, int32_t out_kind,
+                     int64_t* rowptr, int32_t* col, float* val, double* P, double* D);
+
+/* Library identification string (static storage). */
+const char* kvb_version(void);
+
+/* ---- instrumentation: device time per kernel, from HIP events recorded on
+ * the context stream around each launch sequence ---- */
+#define KVB_PROF_KNN_SELECT 0    /* distance tiles + top-(k+margin) selection */
+#define KVB_PROF_KNN_REFINE 1    /* compensated re-rank, FP64 recheck, certificate */
+#define KVB_PROF_KNN_FALLBACK 2  /* exact fallback scan (launched every call; exits early if no rows) */
+#define KVB_PROF_ADHOC 3         /* ad-hoc bandwidth */
+#define KVB_PROF_CHI 4           /* tuning sums: block partials + fixed-order finish */
+#define KVB_PROF_DENSITY 5       /* density estimate and rho */
+#define KVB_PROF_GRID_SCALE 6    /* operator-grid scale reduction */
+#define KVB_PROF_QPASS 7         /* q pass */
+#define KVB_PROF_ASSEMBLE 8      /* Kt, D, output kind, per-row column sort, CSR write */
+#define KVB_PROF_SLOTS 9
+
+/* Turn event timing on (on != 0) or off; either way the totals restart at 0. */
+int kvb_profile_enable(kvb_ctx ctx, int32_t on);
+
+/* Total milliseconds and number of timed launch sequences of one slot since
+ * the last kvb_profile_enable. Synchronises on the recorded events. */
+int kvb_profile_read(kvb_ctx ctx, int32_t slot, double* total_ms_host, int64_t* launches_host);
+
+/* Short name of a slot ("" if out of range; static storage). */
+const char* kvb_profile_name(int32_t slot);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KVB_H */

@@ -1,0 +1,441 @@
+// C ABI of libkvb.so: contexts, argument validation, scratch management and
+// the launch sequence of each entry point. The numerical work of every entry
+// point runs in the kernels of knn_kernels.hip and pass_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kvb_kernels.h"
+
+namespace {
+const char* const kProfNames[KVB_PROF_SLOTS] = {
+    "knn_select", "knn_refine", "knn_fallback", "adhoc_bandwidth", "chi_tuning", "density",
+    "grid_scale", "q_pass", "assemble",
+};
+struct ProfPair {
+    int slot;
+    hipEvent_t a, b;
+};
+}  // namespace
+
+struct kvb_ctx_s {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    size_t scratch_limit = 0;
+    int64_t force_fallback = 0;
+    kvb::TuneResult* tune_dev = nullptr;
+    kvb::TuneResult* tune_host = nullptr;   // pinned
+    int* fb_count_dev = nullptr;            // fallback rows of the last kvb_knn
+    int* fb_count_host = nullptr;           // pinned
+    // instrumentation: HIP events around each kernel launch on the context stream
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<ProfPair> ev_pending;
+    double prof_ms[KVB_PROF_SLOTS] = {};
+    int64_t prof_count[KVB_PROF_SLOTS] = {};
+};
+
+namespace {
+
+int fail(kvb_ctx ctx, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return code;
+}
+
+#define KVB_HIP(ctx, call)                                                                     \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((ctx), KVB_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+#define KVB_REQUIRE(ctx, cond, ...)                                                            \
+    do {                                                                                       \
+        if (!(cond)) return fail((ctx), KVB_E_INVALID, __VA_ARGS__);                           \
+    } while (0)
+
+template <typename T>
+bool aligned(const T* p)
+{
+    return p != nullptr && (reinterpret_cast<uintptr_t>(p) % alignof(T)) == 0;
+}
+
+// Bump allocator over the context scratch buffer; every region is 256-byte aligned.
+struct Carve {
+    char* base;
+    size_t off = 0;
+    explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+    template <typename T>
+    T* take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int ensure_scratch(kvb_ctx ctx, size_t bytes)
+{
+    if (bytes <= ctx->scratch_bytes) return KVB_OK;
+    if (ctx->scratch_limit && bytes > ctx->scratch_limit)
+        return fail(ctx, KVB_E_NOMEM, "scratch of %zu bytes exceeds the limit of %zu bytes", bytes,
+                    ctx->scratch_limit);
+    KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->scratch) {
+        KVB_HIP(ctx, hipFree(ctx->scratch));
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, KVB_E_NOMEM, "hipMalloc of %zu scratch bytes failed", bytes);
+    }
+    ctx->scratch = p;
+    ctx->scratch_bytes = bytes;
+    return KVB_OK;
+}
+
+int check_ctx(kvb_ctx ctx) { return ctx ? KVB_OK : KVB_E_INVALID; }
+
+hipEvent_t pool_event(kvb_ctx ctx)
+{
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one launch sequence with events when instrumentation is on.
+struct Prof {
+    kvb_ctx ctx;
+    int slot;
+    hipEvent_t a = nullptr;
+    Prof(kvb_ctx c, int s) : ctx(c), slot(s)
+    {
+        if (ctx->prof_on && (a = pool_event(ctx)) != nullptr) (void)hipEventRecord(a, ctx->stream);
+    }
+    ~Prof()
+    {
+        if (!a) return;
+        hipEvent_t b = pool_event(ctx);
+        if (!b) {
+            ctx->ev_pool.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->ev_pending.push_back({slot, a, b});
+    }
+};
+
+int prof_collect(kvb_ctx ctx)
+{
+    if (ctx->ev_pending.empty()) return KVB_OK;
+    KVB_HIP(ctx, hipEventSynchronize(ctx->ev_pending.back().b));
+    for (const ProfPair& p : ctx->ev_pending) {
+        float ms = 0.f;
+        KVB_HIP(ctx, hipEventElapsedTime(&ms, p.a, p.b));
+        ctx->prof_ms[p.slot] += ms;
+        ctx->prof_count[p.slot] += 1;
+        ctx->ev_pool.push_back(p.a);
+        ctx->ev_pool.push_back(p.b);
+    }
+    ctx->ev_pending.clear();
+    return KVB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kvb_create(kvb_ctx* out, void* hip_stream)
+{
+    if (!out) return KVB_E_INVALID;
+    *out = nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return KVB_E_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return KVB_E_HIP;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return KVB_E_UNSUPPORTED;
+    kvb_ctx ctx = new kvb_ctx_s();
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->device = dev;
+    if (hipMalloc(reinterpret_cast<void**>(&ctx->tune_dev), sizeof(kvb::TuneResult)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&ctx->tune_host), sizeof(kvb::TuneResult), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&ctx->fb_count_dev), sizeof(int)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&ctx->fb_count_host), sizeof(int), hipHostMallocDefault) !=
+            hipSuccess) {
+        kvb_destroy(ctx);
+        return KVB_E_NOMEM;
+    }
+    *out = ctx;
+    return KVB_OK;
+}
+
+void kvb_destroy(kvb_ctx ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (const ProfPair& p : ctx->ev_pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->tune_dev) (void)hipFree(ctx->tune_dev);
+    if (ctx->tune_host) (void)hipHostFree(ctx->tune_host);
+    if (ctx->fb_count_dev) (void)hipFree(ctx->fb_count_dev);
+    if (ctx->fb_count_host) (void)hipHostFree(ctx->fb_count_host);
+    delete ctx;
+}
+
+const char* kvb_last_error(kvb_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int kvb_set_option(kvb_ctx ctx, int32_t key, int64_t value)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    switch (key) {
+    case KVB_OPT_FORCE_FALLBACK:
+        KVB_REQUIRE(ctx, value >= 0, "KVB_OPT_FORCE_FALLBACK must be >= 0");
+        ctx->force_fallback = value;
+        return KVB_OK;
+    case KVB_OPT_SCRATCH_LIMIT:
+        KVB_REQUIRE(ctx, value >= 0, "KVB_OPT_SCRATCH_LIMIT must be >= 0");
+        ctx->scratch_limit = static_cast<size_t>(value);
+        return KVB_OK;
+    default:
+        return fail(ctx, KVB_E_INVALID, "unknown option key %d", key);
+    }
+}
+
+int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_t mode, int32_t margin,
+            int32_t* idx, float* d2, int32_t* row_flags)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31), got %lld", (long long)n);
+    KVB_REQUIRE(ctx, m >= 1, "m must be >= 1, got %d", m);
+    KVB_REQUIRE(ctx, k >= 1 && k <= n, "k must be in [1, n], got k=%d n=%lld", k, (long long)n);
+    KVB_REQUIRE(ctx, margin >= 0, "margin must be >= 0, got %d", margin);
+    KVB_REQUIRE(ctx, aligned(X), "X must be a non-null float32 device pointer");
+    KVB_REQUIRE(ctx, aligned(idx), "idx must be a non-null int32 device pointer");
+    KVB_REQUIRE(ctx, aligned(d2), "d2 must be a non-null float32 device pointer");
+    KVB_REQUIRE(ctx, row_flags == nullptr || aligned(row_flags), "row_flags must be aligned");
+    KVB_REQUIRE(ctx, mode == KVB_KNN_F32 || mode == KVB_KNN_BF16 || mode == KVB_KNN_LEARNED,
+                "unknown k-NN mode %d", mode);
+    if (k + margin > 256) return fail(ctx, KVB_E_UNSUPPORTED, "k + margin = %d exceeds 256", k + margin);
+    if (m > 1024) return fail(ctx, KVB_E_UNSUPPORTED, "m = %d exceeds 1024", m);
+    if (mode != KVB_KNN_F32) return fail(ctx, KVB_E_UNSUPPORTED, "k-NN mode %d is not available", mode);
+
+    const int nn = static_cast<int>(n);
+    const int kp = static_cast<int>(std::min<int64_t>(k + margin, n));
+    size_t need = round256(size_t(nn) * kp * sizeof(uint64_t)) + round256(size_t(nn) * sizeof(float)) +
+                  round256(size_t(nn) * sizeof(int)) + 1024;
+    int rc = ensure_scratch(ctx, need);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    uint64_t* keys = cv.take<uint64_t>(size_t(nn) * kp);
+    float* slast = cv.take<float>(nn);
+    int* fb_list = cv.take<int>(nn);
+
+    KVB_HIP(ctx, hipMemsetAsync(ctx->fb_count_dev, 0, sizeof(int), ctx->stream));
+    {
+        Prof pr(ctx, KVB_PROF_KNN_SELECT);
+        KVB_HIP(ctx, kvb::launch_select_direct(X, nn, m, kp, keys, slast, ctx->stream));
+    }
+    // the direct tiles compute each squared distance with at most (m + 2) float32
+    // roundings; (m + 4) 2^-23 bounds their relative error with a factor-2 margin
+    const double sel_err = (m + 4) * std::ldexp(1.0, -23);
+    const float lb_scale = static_cast<float>(1.0 / (1.0 + sel_err));
+    {
+        Prof pr(ctx, KVB_PROF_KNN_REFINE);
+        KVB_HIP(ctx, kvb::launch_refine(X, nn, m, k, kp, keys, slast, lb_scale, idx, d2, row_flags,
+                                        ctx->fb_count_dev, fb_list, static_cast<int>(ctx->force_fallback),
+                                        ctx->stream));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_KNN_FALLBACK);
+        KVB_HIP(ctx, kvb::launch_fallback(X, nn, m, k, ctx->fb_count_dev, fb_list, idx, d2, ctx->stream));
+    }
+    return KVB_OK;
+}
+
+int kvb_knn_fallback_rows(kvb_ctx ctx, int64_t* count_host)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, count_host != nullptr, "count_host must be non-null");
+    KVB_HIP(ctx, hipMemcpyAsync(ctx->fb_count_host, ctx->fb_count_dev, sizeof(int), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *count_host = *ctx->fb_count_host;
+    return *count_host > 0 ? KVB_W_FALLBACK : KVB_OK;
+}
+
+int kvb_bandwidth(kvb_ctx ctx, const int32_t* idx, const float* d2, int64_t n, int32_t k, int32_t mode, int32_t k0,
+                  const float* b, double e, double d, double beta, float* rho, float* psi)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
+    KVB_REQUIRE(ctx, k >= 1 && k <= 256, "k must be in [1, 256], got %d", k);
+    KVB_REQUIRE(ctx, aligned(d2), "d2 must be a non-null float32 device pointer");
+    KVB_REQUIRE(ctx, aligned(rho), "rho must be a non-null float32 device pointer");
+    const int nn = static_cast<int>(n);
+    if (mode == KVB_BW_ADHOC) {
+        KVB_REQUIRE(ctx, k0 >= 1 && k0 < k, "k0 must be in [1, k), got k0=%d k=%d", k0, k);
+        Prof pr(ctx, KVB_PROF_ADHOC);
+        KVB_HIP(ctx, kvb::launch_adhoc_bandwidth(d2, nn, k, k0, rho, ctx->stream));
+        return KVB_OK;
+    }
+    KVB_REQUIRE(ctx, mode == KVB_BW_DENSITY, "unknown bandwidth mode %d", mode);
+    KVB_REQUIRE(ctx, aligned(idx), "idx must be a non-null int32 device pointer");
+    KVB_REQUIRE(ctx, aligned(b), "b must be a non-null float32 device pointer");
+    KVB_REQUIRE(ctx, psi == nullptr || aligned(psi), "psi must be aligned");
+    KVB_REQUIRE(ctx, e > 0 && std::isfinite(e), "e must be finite and > 0");
+    KVB_REQUIRE(ctx, d > 0 && std::isfinite(d), "d must be finite and > 0");
+    KVB_REQUIRE(ctx, std::isfinite(beta), "beta must be finite");
+    Prof pr(ctx, KVB_PROF_DENSITY);
+    KVB_HIP(ctx, kvb::launch_density(idx, d2, nn, k, b, e, d, beta, rho, psi, ctx->stream));
+    return KVB_OK;
+}
+
+int kvb_grid_scale(kvb_ctx ctx, const float* ref, const float* rho, int64_t n, double* scale_host)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
+    KVB_REQUIRE(ctx, aligned(ref) && aligned(rho), "ref and rho must be non-null float32 device pointers");
+    KVB_REQUIRE(ctx, scale_host != nullptr, "scale_host must be non-null");
+    const int nn = static_cast<int>(n);
+    const int nb = kvb::logsum_num_blocks(nn);
+    int rc = ensure_scratch(ctx, round256(2 * nb * sizeof(double)) + 512);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    double* part = cv.take<double>(2 * nb);
+    double* out = cv.take<double>(1);
+    {
+        Prof pr(ctx, KVB_PROF_GRID_SCALE);
+        KVB_HIP(ctx, kvb::launch_grid_scale(ref, rho, nn, part, out, ctx->stream));
+    }
+    KVB_HIP(ctx, hipMemcpyAsync(&ctx->tune_host->e_star, out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *scale_host = ctx->tune_host->e_star;
+    if (!(std::isfinite(*scale_host) && *scale_host > 0))
+        return fail(ctx, KVB_E_INVALID, "grid scale is not finite: inputs must be positive and finite");
+    return KVB_OK;
+}
+
+int kvb_tune_eps(kvb_ctx ctx, const int32_t* idx, const float* d2, const float* rho, int64_t n, int32_t k,
+                 double e_min, double e_max, int32_t G, double* chi_host, double* e_star_host, double* dim_host)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
+    KVB_REQUIRE(ctx, k >= 1 && k <= 256, "k must be in [1, 256], got %d", k);
+    KVB_REQUIRE(ctx, G >= 3 && G <= 256, "G must be in [3, 256], got %d", G);
+    KVB_REQUIRE(ctx, e_min > 0 && e_max > e_min && std::isfinite(e_max), "need 0 < e_min < e_max < inf");
+    KVB_REQUIRE(ctx, aligned(idx) && aligned(d2) && aligned(rho), "idx, d2, rho must be non-null device pointers");
+    KVB_REQUIRE(ctx, e_star_host != nullptr, "e_star_host must be non-null");
+    const int64_t nnz = n * k;
+    const int nb = kvb::chi_num_blocks(nnz);
+    int rc = ensure_scratch(ctx, round256(size_t(nb) * G * sizeof(double)) + 256);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    double* part = cv.take<double>(size_t(nb) * G);
+    {
+        Prof pr(ctx, KVB_PROF_CHI);
+        KVB_HIP(ctx, kvb::launch_chi(idx, d2, rho, nnz, k, G, std::log(e_min), std::log(e_max), part,
+                                     ctx->tune_dev, ctx->stream));
+    }
+    KVB_HIP(ctx, hipMemcpyAsync(ctx->tune_host, ctx->tune_dev, sizeof(kvb::TuneResult), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const kvb::TuneResult& t = *ctx->tune_host;
+    if (chi_host) std::memcpy(chi_host, t.chi, sizeof(double) * G);
+    *e_star_host = t.e_star;
+    if (dim_host) *dim_host = t.dim;
+    return (t.g_star == 0 || t.g_star == G - 2) ? KVB_W_GRID_EDGE : KVB_OK;
+}
+
+int kvb_assemble_csr(kvb_ctx ctx, const int32_t* idx, const float* d2, const float* rho, int64_t n, int32_t k,
+                     double e, double alpha, double d, int32_t out_kind, int64_t* rowptr, int32_t* col, float* val,
+                     double* P, double* D)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
+    KVB_REQUIRE(ctx, k >= 1 && k <= 256, "k must be in [1, 256], got %d", k);
+    KVB_REQUIRE(ctx, e > 0 && std::isfinite(e), "e must be finite and > 0");
+    KVB_REQUIRE(ctx, std::isfinite(alpha) && std::isfinite(d) && d > 0, "alpha must be finite and d > 0");
+    KVB_REQUIRE(ctx, out_kind >= KVB_OUT_MARKOV && out_kind <= KVB_OUT_SYMMETRIC, "unknown out_kind %d", out_kind);
+    KVB_REQUIRE(ctx, aligned(idx) && aligned(d2) && aligned(rho), "idx, d2, rho must be non-null device pointers");
+    KVB_REQUIRE(ctx, aligned(rowptr) && aligned(col) && aligned(val), "rowptr, col, val must be non-null");
+    KVB_REQUIRE(ctx, (P == nullptr || aligned(P)) && (D == nullptr || aligned(D)), "P and D must be aligned");
+    const int nn = static_cast<int>(n);
+    int rc = ensure_scratch(ctx, 2 * round256(size_t(nn) * sizeof(double)) + 256);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    double* qa = cv.take<double>(nn);
+    double* Dtmp = cv.take<double>(nn);
+    {
+        Prof pr(ctx, KVB_PROF_QPASS);
+        KVB_HIP(ctx, kvb::launch_qpass(idx, d2, nn, k, rho, e, alpha, d, qa, ctx->stream));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_ASSEMBLE);
+        KVB_HIP(ctx, kvb::launch_assemble(idx, d2, nn, k, rho, e, qa, out_kind, rowptr, col, val, P,
+                                          D ? D : Dtmp, ctx->stream));
+    }
+    return KVB_OK;
+}
+
+const char* kvb_version(void) { return "kvb 0.1 (gfx950)"; }
+
+int kvb_profile_enable(kvb_ctx ctx, int32_t on)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    int rc = prof_collect(ctx);
+    if (rc) return rc;
+    for (int s = 0; s < KVB_PROF_SLOTS; ++s) {
+        ctx->prof_ms[s] = 0.0;
+        ctx->prof_count[s] = 0;
+    }
+    ctx->prof_on = on != 0;
+    return KVB_OK;
+}
+
+int kvb_profile_read(kvb_ctx ctx, int32_t slot, double* total_ms_host, int64_t* launches_host)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, slot >= 0 && slot < KVB_PROF_SLOTS, "profile slot %d out of range", slot);
+    KVB_REQUIRE(ctx, total_ms_host && launches_host, "outputs must be non-null");
+    int rc = prof_collect(ctx);
+    if (rc) return rc;
+    *total_ms_host = ctx->prof_ms[slot];
+    *launches_host = ctx->prof_count[slot];
+    return KVB_OK;
+}
+
+const char* kvb_profile_name(int32_t slot)
+{
+    return (slot >= 0 && slot < KVB_PROF_SLOTS) ? kProfNames[slot] : "";
+}
+
+}  // extern "C"

@@ -1,0 +1,551 @@
+// Exact k-nearest-neighbour kernels (gfx950).
+//
+// The method needs, for every sample, its k-1 nearest other samples in the
+// order I(x, k) of Section 2.1 (ties to the smaller index); this fixes the
+// sparsity pattern of every kernel matrix in Sections 2.1-2.2. The paper's
+// brute-force construction (Section 4, Algorithm 1) evaluates all n^2 pairs;
+// its rows are independent, which is the parallelism used here.
+//
+// Pipeline of kvb_knn for one row i:
+//   select   stream all n candidates through a distance test and keep the
+//            k' = k + margin smallest (distance, index) keys in a register
+//            list (one wavefront owns R rows; lanes hold candidates);
+//   refine   recompute the k' candidates' squared distances with compensated
+//            float32 arithmetic, drop i itself, sort, decide membership at the
+//            k-th neighbour in float64, and check a certificate that no
+//            dropped candidate can be nearer than the k-th kept one;
+//   fallback rows without a certificate are recomputed by an exact float64
+//            radix selection over all n samples.
+#include "kvb_device.h"
+#include "kvb_kernels.h"
+
+namespace kvb {
+
+// -------------------------------------------------------------------- select
+// Direct-difference distance tiles for small m (VALU: m subtractions and m
+// multiply-adds per pair; the query coordinates are wave-uniform and live in
+// scalar registers). Candidates passing the current threshold of a row are
+// appended to a 64-entry LDS buffer; a full buffer is merged into the row's
+// register list by a bitonic network, which also tightens the threshold.
+template <int M, int R, int E>
+__global__ __launch_bounds__(256) void k_select_direct(const float* __restrict__ X, int n, int kp,
+                                                       uint64_t* __restrict__ keys_out,
+                                                       float* __restrict__ slast_out)
+{
+    __shared__ uint64_t sbuf[4][R][WAVE];
+    const int lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int row0 = (blockIdx.x * 4 + wave) * R;
+    if (row0 >= n) return;
+
+    float q[R][M];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = min(row0 + r, n - 1);
+#pragma unroll
+        for (int c = 0; c < M; ++c) q[r][c] = X[static_cast<size_t>(i) * M + c];
+    }
+    uint64_t L[R][E];
+    float tau[R];
+    int bc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int s = 0; s < E; ++s) L[r][s] = KEY_INF;
+        tau[r] = __uint_as_float(0x7F800000u);
+        bc[r] = 0;
+    }
+    uint64_t* buf = &sbuf[wave][0][0];
+
+    for (int j0 = 0; j0 < n; j0 += WAVE) {
+        const int j = j0 + lane;
+        const bool valid = j < n;
+        const int jj = valid ? j : n - 1;
+        float x[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) x[c] = X[static_cast<size_t>(jj) * M + c];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float t = q[r][0] - x[0];
+            float d = t * t;
+#pragma unroll
+            for (int c = 1; c < M; ++c) {
+                t = q[r][c] - x[c];
+                d = fmaf(t, t, d);
+            }
+            uint64_t mask = __ballot(valid && d <= tau[r]);
+            if (mask) {
+                int cnt = __popcll(mask);
+                if (bc[r] + cnt > WAVE) {
+                    wave_lds_sync();
+                    uint64_t b = lane < bc[r] ? buf[r * WAVE + lane] : KEY_INF;
+                    merge_into_list<E>(L[r], b);
+                    bc[r] = 0;
+                    tau[r] = key_dist(list_at<E>(L[r], kp - 1));
+                    mask = __ballot(valid && d <= tau[r]);
+                    cnt = __popcll(mask);
+                    wave_lds_sync();
+                }
+                if ((mask >> lane) & 1ull) buf[r * WAVE + bc[r] + mbcnt64(mask)] = make_key(d, j);
+                bc[r] += cnt;
+            }
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (bc[r] > 0) {
+            uint64_t b = lane < bc[r] ? buf[r * WAVE + lane] : KEY_INF;
+            merge_into_list<E>(L[r], b);
+        }
+        const int i = row0 + r;
+        if (i < n) {
+            uint64_t* dst = keys_out + static_cast<size_t>(i) * kp;
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int t = s * WAVE + lane;
+                if (t < kp) dst[t] = L[r][s];
+            }
+            const float sl = key_dist(list_at<E>(L[r], kp - 1));
+            if (lane == 0) slast_out[i] = sl;
+        }
+    }
+}
+
+// Generic-dimension variant (any m): the query row is read with wave-uniform
+// loads, each lane gathers its candidate's coordinates.
+template <int R, int E>
+__global__ __launch_bounds__(256) void k_select_direct_any(const float* __restrict__ X, int n, int m,
+                                                           int kp, uint64_t* __restrict__ keys_out,
+                                                           float* __restrict__ slast_out)
+{
+    __shared__ uint64_t sbuf[4][R][WAVE];
+    const int lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int row0 = (blockIdx.x * 4 + wave) * R;
+    if (row0 >= n) return;
+    const float* qrow[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) qrow[r] = X + static_cast<size_t>(min(row0 + r, n - 1)) * m;
+    uint64_t L[R][E];
+    float tau[R];
+    int bc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int s = 0; s < E; ++s) L[r][s] = KEY_INF;
+        tau[r] = __uint_as_float(0x7F800000u);
+        bc[r] = 0;
+    }
+    uint64_t* buf = &sbuf[wave][0][0];
+    for (int j0 = 0; j0 < n; j0 += WAVE) {
+        const int j = j0 + lane;
+        const bool valid = j < n;
+        const float* xj = X + static_cast<size_t>(valid ? j : n - 1) * m;
+        float d[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) d[r] = 0.f;
+        for (int c = 0; c < m; ++c) {
+            const float xc = xj[c];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float t = qrow[r][c] - xc;
+                d[r] = fmaf(t, t, d[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            uint64_t mask = __ballot(valid && d[r] <= tau[r]);
+            if (mask) {
+                int cnt = __popcll(mask);
+                if (bc[r] + cnt > WAVE) {
+                    wave_lds_sync();
+                    uint64_t b = lane < bc[r] ? buf[r * WAVE + lane] : KEY_INF;
+                    merge_into_list<E>(L[r], b);
+                    bc[r] = 0;
+                    tau[r] = key_dist(list_at<E>(L[r], kp - 1));
+                    mask = __ballot(valid && d[r] <= tau[r]);
+                    cnt = __popcll(mask);
+                    wave_lds_sync();
+                }
+                if ((mask >> lane) & 1ull) buf[r * WAVE + bc[r] + mbcnt64(mask)] = make_key(d[r], j);
+                bc[r] += cnt;
+            }
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (bc[r] > 0) {
+            uint64_t b = lane < bc[r] ? buf[r * WAVE + lane] : KEY_INF;
+            merge_into_list<E>(L[r], b);
+        }
+        const int i = row0 + r;
+        if (i < n) {
+            uint64_t* dst = keys_out + static_cast<size_t>(i) * kp;
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int t = s * WAVE + lane;
+                if (t < kp) dst[t] = L[r][s];
+            }
+            const float sl = key_dist(list_at<E>(L[r], kp - 1));
+            if (lane == 0) slast_out[i] = sl;
+        }
+    }
+}
+
+// -------------------------------------------------------------------- refine
+__device__ __forceinline__ float comp_dist2(const float* __restrict__ a, const float* __restrict__ b, int m)
+{
+    CompF32 acc;
+    for (int c = 0; c < m; ++c) comp_sqdiff_add(acc, a[c], b[c]);
+    return acc.s + acc.c;
+}
+
+__device__ __forceinline__ double dist2_f64(const float* __restrict__ a, const float* __restrict__ b, int m)
+{
+    double s = 0.0;
+    for (int c = 0; c < m; ++c) {
+        const double t = static_cast<double>(a[c]) - static_cast<double>(b[c]);
+        s = fma(t, t, s);
+    }
+    return s;
+}
+
+// One wavefront per row. keys: [n, kp] candidate keys from a select kernel,
+// slast: the select key of the kp-th candidate (a bound on the dropped ones),
+// converted to a lower bound on their true squared distance by lb_scale
+// (direct tiles: 1/(1 + select error)).
+template <int E>
+__global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int n, int m, int k, int kp,
+                                                const uint64_t* __restrict__ keys,
+                                                const float* __restrict__ slast, float lb_scale,
+                                                int32_t* __restrict__ idx_out, float* __restrict__ d2_out,
+                                                int32_t* __restrict__ flags_out,
+                                                int* __restrict__ fb_count, int* __restrict__ fb_list,
+                                                int force_period)
+{
+    const int lane = lane_id();
+    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i >= n) return;
+    const float* xi = X + static_cast<size_t>(i) * m;
+    // compensated float32 distances of the candidates, self removed
+    uint64_t v[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int t = s * WAVE + lane;
+        uint64_t key = t < kp ? keys[static_cast<size_t>(i) * kp + t] : KEY_INF;
+        if (key != KEY_INF) {
+            const uint32_t j = key_idx(key);
+            if (static_cast<int>(j) == i)
+                key = KEY_INF;
+            else
+                key = make_key(comp_dist2(xi, X + static_cast<size_t>(j) * m, m), j);
+        }
+        v[s] = key;
+    }
+    bitonic_sort<E>(v);
+
+    const int kk = k - 1;  // neighbours other than i
+    int32_t* orow = idx_out + static_cast<size_t>(i) * k;
+    float* drow = d2_out + static_cast<size_t>(i) * k;
+    if (lane == 0) {
+        orow[0] = i;
+        drow[0] = 0.f;
+    }
+    int flags = 0;
+    bool certified = true;
+    if (kk > 0) {
+        // relative error bound of the compensated distances (a few units in
+        // the last place), doubled for the band test
+        const float dl = 4.8e-7f;
+        const float a = key_dist(list_at<E>(v, kk - 1));
+        const float lo_edge = a * (1.f - dl) / (1.f + dl);
+        const float hi_edge = a * (1.f + dl) / (1.f - dl);
+        // positions: sure-in (below lo_edge), band, sure-out (above hi_edge)
+        uint64_t band_m[E];
+        int c_lo = 0, nband = 0, band_beyond = 0;
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int t = s * WAVE + lane;
+            const float dv = key_dist(v[s]);
+            const bool valid = v[s] != KEY_INF;
+            const bool in_lo = valid && dv < lo_edge;
+            const bool in_band = valid && !in_lo && dv <= hi_edge;
+            c_lo += __popcll(__ballot(in_lo));
+            band_m[s] = __ballot(in_band);
+            nband += __popcll(band_m[s]);
+            band_beyond += __popcll(__ballot(in_band && t >= kk));
+        }
+        // FP64 recheck only when the band straddles the k-th position
+        double d64[E];
+        int rank[E];
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            d64[s] = 0.0;
+            rank[s] = 0;
+        }
+        const bool recheck = band_beyond > 0;
+        if (recheck) {
+            flags |= KVB_ROW_RECHECK;
+#pragma unroll
+            for (int s = 0; s < E; ++s)
+                if ((band_m[s] >> lane) & 1ull)
+                    d64[s] = dist2_f64(xi, X + static_cast<size_t>(key_idx(v[s])) * m, m);
+            // rank of every band member among band members by (d64, j)
+#pragma unroll
+            for (int so = 0; so < E; ++so) {
+                uint64_t bm = band_m[so];
+                while (bm) {
+                    const int src = __builtin_ctzll(bm);
+                    bm &= bm - 1;
+                    const double od = __shfl(d64[so], src, WAVE);
+                    const uint32_t oj = __builtin_amdgcn_readlane(static_cast<int>(key_idx(v[so])), src);
+#pragma unroll
+                    for (int s = 0; s < E; ++s) {
+                        const uint32_t mj = key_idx(v[s]);
+                        if ((od < d64[s]) || (od == d64[s] && oj < mj)) rank[s]++;
+                    }
+                }
+            }
+        }
+        // write the k-1 neighbours and find the largest kept distance
+        float kept_max = 0.f;
+        const int need = kk - c_lo;
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int t = s * WAVE + lane;
+            const bool valid = v[s] != KEY_INF;
+            const float dv = key_dist(v[s]);
+            const bool in_lo = valid && dv < lo_edge;
+            const bool in_band = (band_m[s] >> lane) & 1ull;
+            int pos = -1;
+            float outd = dv;
+            if (in_lo) {
+                pos = t;
+            } else if (in_band) {
+                if (recheck) {
+                    if (rank[s] < need) {
+                        pos = c_lo + rank[s];
+                        outd = static_cast<float>(d64[s]);
+                    }
+                } else if (t < kk) {
+                    pos = t;
+                }
+            }
+            if (pos >= 0) {
+                orow[1 + pos] = static_cast<int32_t>(key_idx(v[s]));
+                drow[1 + pos] = outd;
+                kept_max = fmaxf(kept_max, dv);
+            }
+        }
+        kept_max = wave_max_f32(kept_max);
+        // certificate: every candidate the select step dropped has a true
+        // squared distance >= slast * lb_scale; it must exceed the largest kept
+        const float lb = slast[i] * lb_scale;
+        const float ub = kept_max * (1.f + dl) * (1.f + 1e-6f);
+        certified = lb > ub;
+    }
+    if (force_period > 0 && (i % force_period) == 0) certified = false;
+    if (!certified) {
+        flags |= KVB_ROW_FALLBACK;
+        if (lane == 0) {
+            const int slot = atomicAdd(fb_count, 1);
+            fb_list[slot] = i;
+        }
+    }
+    if (flags_out && lane == 0) flags_out[i] = flags;
+}
+
+// -------------------------------------------------------------------- fallback
+// Exact float64 selection for the listed rows: an 8-pass radix select on the
+// bits of the float64 squared distance (non-negative doubles order like their
+// bit patterns) finds the (k-1)-th smallest value V; the neighbours are all j
+// with d < V plus the smallest-index j with d == V, ranked by (d, j).
+constexpr int FB_THREADS = 256;
+
+__global__ __launch_bounds__(FB_THREADS) void k_fallback(const float* __restrict__ X, int n, int m, int k,
+                                                         const int* __restrict__ fb_count,
+                                                         const int* __restrict__ fb_list,
+                                                         int32_t* __restrict__ idx_out,
+                                                         float* __restrict__ d2_out)
+{
+    __shared__ unsigned int hist[256];
+    __shared__ unsigned long long s_prefix;
+    __shared__ int s_remaining;
+    __shared__ double cd[256];
+    __shared__ int cj[256];
+    __shared__ int s_cnt_lt, s_cnt_eq;
+    __shared__ int wsum_lt[FB_THREADS / WAVE], wsum_eq[FB_THREADS / WAVE];
+    const int tid = threadIdx.x;
+    const int total = *fb_count;
+    const int kk = k - 1;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = fb_list[t];
+        const float* xi = X + static_cast<size_t>(i) * m;
+        if (kk == 0) continue;
+        if (tid == 0) {
+            s_prefix = 0ull;
+            s_remaining = kk;
+        }
+        __syncthreads();
+        for (int shift = 56; shift >= 0; shift -= 8) {
+            hist[tid] = 0u;
+            __syncthreads();
+            const unsigned long long pfx = s_prefix;
+            const unsigned long long pmask = (shift == 56) ? 0ull : (~0ull << (shift + 8));
+            for (int j = tid; j < n; j += FB_THREADS) {
+                if (j == i) continue;
+                const double d = dist2_f64(xi, X + static_cast<size_t>(j) * m, m);
+                const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(d));
+                if ((u & pmask) == pfx) atomicAdd(&hist[(u >> shift) & 255ull], 1u);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int rem = s_remaining;
+                int b = 0;
+                for (; b < 256; ++b) {
+                    if (static_cast<int>(hist[b]) >= rem) break;
+                    rem -= static_cast<int>(hist[b]);
+                }
+                s_prefix = pfx | (static_cast<unsigned long long>(b) << shift);
+                s_remaining = rem;
+            }
+            __syncthreads();
+        }
+        const double V = __longlong_as_double(static_cast<long long>(s_prefix));
+        const int need_eq = s_remaining;      // how many d == V entries to take
+        const int n_lt = kk - need_eq;        // entries with d < V
+        if (tid == 0) {
+            s_cnt_lt = 0;
+            s_cnt_eq = 0;
+        }
+        __syncthreads();
+        // ordered compaction in index order
+        for (int j0 = 0; j0 < n; j0 += FB_THREADS) {
+            const int j = j0 + tid;
+            double d = 0.0;
+            bool lt = false, eq = false;
+            if (j < n && j != i) {
+                d = dist2_f64(xi, X + static_cast<size_t>(j) * m, m);
+                lt = d < V;
+                eq = d == V;
+            }
+            const uint64_t bl = __ballot(lt), be = __ballot(eq);
+            const int w = tid / WAVE;
+            if ((tid & (WAVE - 1)) == 0) {
+                wsum_lt[w] = __popcll(bl);
+                wsum_eq[w] = __popcll(be);
+            }
+            __syncthreads();
+            int off_lt = s_cnt_lt, off_eq = s_cnt_eq;
+            for (int u = 0; u < w; ++u) {
+                off_lt += wsum_lt[u];
+                off_eq += wsum_eq[u];
+            }
+            if (lt) {
+                const int p = off_lt + mbcnt64(bl);
+                cd[p] = d;
+                cj[p] = j;
+            }
+            if (eq) {
+                const int p = off_eq + mbcnt64(be);
+                if (p < need_eq) {
+                    cd[n_lt + p] = d;
+                    cj[n_lt + p] = j;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int a = 0, b = 0;
+                for (int u = 0; u < FB_THREADS / WAVE; ++u) {
+                    a += wsum_lt[u];
+                    b += wsum_eq[u];
+                }
+                s_cnt_lt += a;
+                s_cnt_eq += b;
+            }
+            __syncthreads();
+        }
+        // rank by (d, j) and write
+        if (tid < kk) {
+            const double d = cd[tid];
+            const int j = cj[tid];
+            int rank = 0;
+            for (int u = 0; u < kk; ++u) rank += (cd[u] < d) || (cd[u] == d && cj[u] < j);
+            idx_out[static_cast<size_t>(i) * k + 1 + rank] = j;
+            d2_out[static_cast<size_t>(i) * k + 1 + rank] = static_cast<float>(d);
+        }
+        if (tid == 0) {
+            idx_out[static_cast<size_t>(i) * k] = i;
+            d2_out[static_cast<size_t>(i) * k] = 0.f;
+        }
+        __syncthreads();
+    }
+}
+
+// -------------------------------------------------------------------- launchers
+template <int M, int R>
+static hipError_t launch_select_m(const float* X, int n, int kp, uint64_t* keys, float* slast, hipStream_t st)
+{
+    const int rows_per_block = 4 * R;
+    const dim3 grid((n + rows_per_block - 1) / rows_per_block), block(256);
+    if (kp <= 64)
+        hipLaunchKernelGGL((k_select_direct<M, R, 1>), grid, block, 0, st, X, n, kp, keys, slast);
+    else if (kp <= 128)
+        hipLaunchKernelGGL((k_select_direct<M, R, 2>), grid, block, 0, st, X, n, kp, keys, slast);
+    else
+        hipLaunchKernelGGL((k_select_direct<M, R, 4>), grid, block, 0, st, X, n, kp, keys, slast);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_direct(const float* X, int n, int m, int kp, uint64_t* keys, float* slast,
+                                hipStream_t st)
+{
+    switch (m) {
+    case 1: return launch_select_m<1, 8>(X, n, kp, keys, slast, st);
+    case 2: return launch_select_m<2, 8>(X, n, kp, keys, slast, st);
+    case 3: return launch_select_m<3, 8>(X, n, kp, keys, slast, st);
+    case 4: return launch_select_m<4, 8>(X, n, kp, keys, slast, st);
+    case 5: return launch_select_m<5, 4>(X, n, kp, keys, slast, st);
+    case 6: return launch_select_m<6, 4>(X, n, kp, keys, slast, st);
+    case 7: return launch_select_m<7, 4>(X, n, kp, keys, slast, st);
+    case 8: return launch_select_m<8, 4>(X, n, kp, keys, slast, st);
+    default: break;
+    }
+    constexpr int R = 4;
+    const dim3 grid((n + 4 * R - 1) / (4 * R)), block(256);
+    if (kp <= 64)
+        hipLaunchKernelGGL((k_select_direct_any<R, 1>), grid, block, 0, st, X, n, m, kp, keys, slast);
+    else if (kp <= 128)
+        hipLaunchKernelGGL((k_select_direct_any<R, 2>), grid, block, 0, st, X, n, m, kp, keys, slast);
+    else
+        hipLaunchKernelGGL((k_select_direct_any<R, 4>), grid, block, 0, st, X, n, m, kp, keys, slast);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine(const float* X, int n, int m, int k, int kp, const uint64_t* keys,
+                         const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags,
+                         int* fb_count, int* fb_list, int force_period, hipStream_t st)
+{
+    const dim3 grid((n + 3) / 4), block(256);
+    if (kp <= 64)
+        hipLaunchKernelGGL((k_refine<1>), grid, block, 0, st, X, n, m, k, kp, keys, slast, lb_scale, idx, d2,
+                           flags, fb_count, fb_list, force_period);
+    else if (kp <= 128)
+        hipLaunchKernelGGL((k_refine<2>), grid, block, 0, st, X, n, m, k, kp, keys, slast, lb_scale, idx, d2,
+                           flags, fb_count, fb_list, force_period);
+    else
+        hipLaunchKernelGGL((k_refine<4>), grid, block, 0, st, X, n, m, k, kp, keys, slast, lb_scale, idx, d2,
+                           flags, fb_count, fb_list, force_period);
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback(const float* X, int n, int m, int k, const int* fb_count, const int* fb_list,
+                           int32_t* idx, float* d2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fallback, dim3(512), dim3(FB_THREADS), 0, st, X, n, m, k, fb_count, fb_list, idx, d2);
+    return hipGetLastError();
+}
+
+}  // namespace kvb

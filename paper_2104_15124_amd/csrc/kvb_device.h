@@ -1,0 +1,222 @@
+// Device-side building blocks shared by the kvb kernels (gfx950, wave64).
+//
+// Neighbour candidates travel as 64-bit keys: the IEEE bits of a non-negative
+// float32 squared distance in the high word and the column index in the low
+// word. For d >= 0 the float bits are monotone, so unsigned key order is the
+// (distance, index) order of the paper's neighbour ranking I(x, k)
+// (Section 2.1): ties between equal distances go to the smaller index.
+//
+// Per-row candidate lists live in registers, spread over the 64 lanes of a
+// wavefront: element t of a list of capacity 64*E sits in slot t / 64 of
+// lane t % 64. Sorting and merging use bitonic networks; exchanges between
+// lanes go through cross-lane shuffles, exchanges between slots stay in the
+// lane.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kvb {
+
+constexpr uint64_t KEY_INF = 0x7F800000FFFFFFFFull;  // distance +inf, index 0xffffffff
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ uint64_t make_key(float d, uint32_t j)
+{
+    return (static_cast<uint64_t>(__float_as_uint(d)) << 32) | j;
+}
+__device__ __forceinline__ float key_dist(uint64_t k) { return __uint_as_float(static_cast<uint32_t>(k >> 32)); }
+__device__ __forceinline__ uint32_t key_idx(uint64_t k) { return static_cast<uint32_t>(k); }
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask)
+{
+    int lo = static_cast<int>(static_cast<uint32_t>(v));
+    int hi = static_cast<int>(static_cast<uint32_t>(v >> 32));
+    lo = __shfl_xor(lo, mask, WAVE);
+    hi = __shfl_xor(hi, mask, WAVE);
+    return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
+{
+    int lo = static_cast<int>(static_cast<uint32_t>(v));
+    int hi = static_cast<int>(static_cast<uint32_t>(v >> 32));
+    lo = __shfl(lo, src, WAVE);
+    hi = __shfl(hi, src, WAVE);
+    return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int src)
+{
+    uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), src);
+    uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v >> 32)), src);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ int mbcnt64(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
+}
+
+// Order LDS traffic of one wavefront: stores issued before are visible to
+// loads of any lane of the same wavefront issued after.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------- bitonic networks
+// Compare-exchange with partner distance j < 64 (partner in another lane) in a
+// bitonic stage of block size kb (ascending where element index & kb == 0).
+template <int E>
+__device__ __forceinline__ void cx_lanes(uint64_t (&v)[E], int kb, int j, int lane)
+{
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        uint64_t o = shfl_xor_u64(v[s], j);
+        int i = s * WAVE + lane;
+        bool up = (i & kb) == 0;
+        bool lower = (lane & j) == 0;
+        v[s] = (up == lower) ? umin64(v[s], o) : umax64(v[s], o);
+    }
+}
+
+// Compare-exchange with partner distance js*64 (partner in another slot, same lane).
+template <int E>
+__device__ __forceinline__ void cx_slots(uint64_t (&v)[E], int kb, int js, int lane)
+{
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        int p = s ^ js;
+        if (p > s) {
+            int i = s * WAVE + lane;
+            bool up = (i & kb) == 0;
+            uint64_t a = v[s], b = v[p];
+            bool sw = up ? (a > b) : (a < b);
+            v[s] = sw ? b : a;
+            v[p] = sw ? a : b;
+        }
+    }
+}
+
+// Full ascending sort of the 64*E keys held by the wavefront.
+template <int E>
+__device__ __forceinline__ void bitonic_sort(uint64_t (&v)[E])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int kb = 2; kb <= WAVE * E; kb <<= 1) {
+#pragma unroll
+        for (int j = kb >> 1; j > 0; j >>= 1) {
+            if (j >= WAVE)
+                cx_slots<E>(v, kb, j / WAVE, lane);
+            else
+                cx_lanes<E>(v, kb, j, lane);
+        }
+    }
+}
+
+// Ascending sort of a bitonic sequence of 64*E keys.
+template <int E>
+__device__ __forceinline__ void bitonic_merge_asc(uint64_t (&v)[E])
+{
+    const int lane = lane_id();
+    constexpr int N = WAVE * E;
+#pragma unroll
+    for (int j = N >> 1; j > 0; j >>= 1) {
+        if (j >= WAVE)
+            cx_slots<E>(v, 2 * N, j / WAVE, lane);
+        else
+            cx_lanes<E>(v, 2 * N, j, lane);
+    }
+}
+
+// Keep the 64*E smallest of (sorted list L) u (64 unsorted keys b, one per
+// lane), sorted ascending in L. The half-cleaner min(L[t], rev(B)[t]) of a
+// sorted and a reverse-sorted sequence holds the smallest half as a bitonic
+// sequence; only the last slot of L meets real keys of B.
+template <int E>
+__device__ __forceinline__ void merge_into_list(uint64_t (&L)[E], uint64_t b)
+{
+    uint64_t B[1] = {b};
+    bitonic_sort<1>(B);
+    uint64_t rev = shfl_u64(B[0], WAVE - 1 - lane_id());
+    L[E - 1] = umin64(L[E - 1], rev);
+    bitonic_merge_asc<E>(L);
+}
+
+// Key at list position t (wave-uniform t), broadcast to the wavefront.
+template <int E>
+__device__ __forceinline__ uint64_t list_at(const uint64_t (&L)[E], int t)
+{
+    const int slot = t / WAVE, src = t % WAVE;
+    uint64_t v = L[0];
+#pragma unroll
+    for (int s = 1; s < E; ++s)
+        if (s == slot) v = L[s];
+    return readlane_u64(v, src);
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ float wave_max_f32(float v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+// Neumaier-compensated accumulation (sum, compensation).
+struct Comp64 {
+    double s = 0.0, c = 0.0;
+    __device__ __forceinline__ void add(double x)
+    {
+        double t = s + x;
+        c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return s + c; }
+};
+
+// Squared distance of two float32 rows with error-free transformations: each
+// difference a - b is split exactly into t + e (two-sum), t*t is split exactly
+// into p + pe (fused multiply-add), and the pieces are accumulated with
+// Neumaier compensation, so the float32 result is close to correctly rounded
+// whatever the dimension.
+struct CompF32 {
+    float s = 0.f, c = 0.f;
+    __device__ __forceinline__ void add(float x)
+    {
+        float t = s + x;
+        c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    }
+};
+
+__device__ __forceinline__ void comp_sqdiff_add(CompF32& acc, float a, float b)
+{
+    float t = a - b;
+    float bb = t - a;
+    float e = (a - (t - bb)) - (b + bb);      // a - b = t + e exactly (two-sum of a and -b)
+    float p = t * t;
+    float pe = fmaf(t, t, -p);                // t*t = p + pe exactly
+    acc.add(p);
+    acc.c += pe + (2.0f * t * e + e * e);
+}
+
+}  // namespace kvb

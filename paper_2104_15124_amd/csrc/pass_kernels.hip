@@ -1,0 +1,393 @@
+// O(nk) passes over the k-NN pattern (gfx950): bandwidths, the epsilon
+// tuning sums, the density estimate and the alpha/Markov normalisation.
+// These kernels stream idx/d2 (8 bytes per stored entry) and gather per-sample
+// vectors of neighbours; they are bound by HBM bandwidth except the tuning
+// pass, which evaluates one exponential per grid point and entry.
+//
+// One wavefront owns one row for the row-wise passes (k <= 256 entries, lanes
+// strided over them), so row sums reduce inside the wavefront in a fixed
+// butterfly order and no atomics are needed.
+#include "kvb_device.h"
+#include "kvb_kernels.h"
+
+namespace kvb {
+
+// b_i = sqrt(sum_{r=1..k0} d2[i, r])  (Section 2.1, bandwidth eq.; r = 0 is i itself)
+__global__ __launch_bounds__(256) void k_adhoc_bandwidth(const float* __restrict__ d2, int n, int k, int k0,
+                                                         float* __restrict__ b)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* row = d2 + static_cast<size_t>(i) * k;
+    double s = 0.0;
+    for (int r = 1; r <= k0; ++r) s += static_cast<double>(row[r]);
+    b[i] = static_cast<float>(sqrt(s));
+}
+
+// Row sum of exp(-d2/(e rho_i rho_j)) with a float64 argument and exponential,
+// reduced over the wavefront in a fixed order.
+__device__ __forceinline__ double row_kernel_sum(const int32_t* __restrict__ irow, const float* __restrict__ drow,
+                                                 int k, const float* __restrict__ rho, double inv_e_rhoi,
+                                                 int lane)
+{
+    double s = 0.0;
+    for (int r = lane; r < k; r += WAVE) {
+        const double x = static_cast<double>(drow[r]) * inv_e_rhoi / static_cast<double>(rho[irow[r]]);
+        s += exp(-x);
+    }
+    return wave_sum_f64(s);
+}
+
+// psi_i = sum_r K_ir / (n (pi e b_i^2)^{d/2}), rho_i = 2 psi_i^beta
+// (Section 2.1 density eqs.; Algorithm 1 caption)
+__global__ __launch_bounds__(256) void k_density(const int32_t* __restrict__ idx, const float* __restrict__ d2,
+                                                 int n, int k, const float* __restrict__ b, double e, double d,
+                                                 double beta, float* __restrict__ rho, float* __restrict__ psi)
+{
+    const int lane = lane_id();
+    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i >= n) return;
+    const double bi = static_cast<double>(b[i]);
+    const double s = row_kernel_sum(idx + static_cast<size_t>(i) * k, d2 + static_cast<size_t>(i) * k, k, b,
+                                    1.0 / (e * bi), lane);
+    if (lane == 0) {
+        const double pi = 3.14159265358979323846;
+        const double w = static_cast<double>(n) * pow(pi * e * bi * bi, 0.5 * d);
+        const double p = s / w;
+        rho[i] = static_cast<float>(2.0 * pow(p, beta));
+        if (psi) psi[i] = static_cast<float>(p);
+    }
+}
+
+// ------------------------------------------------------------------ tuning sums
+// Block partials of chi[g] = sum over entries of exp(-x / e_g), x = d2/(rho_i rho_j).
+// Each wavefront takes 64 consecutive entries at a time: lane t forms x for
+// entry t, the 64 values go through LDS, then lane g accumulates exp2(x c_g)
+// over them for grid point g (c_g = -log2(e)/e_g), in float32 per 64-entry
+// chunk and float64 across chunks.
+constexpr int CHI_BLOCK = 256;
+
+// ln e_g = ln e_min + g (ln e_max - ln e_min) / (G - 1)
+__device__ __forceinline__ double grid_log(double lo, double hi, int G, int g)
+{
+    return lo + (static_cast<double>(g) * (hi - lo)) / static_cast<double>(G - 1);
+}
+constexpr int CHI_MIN_ENTRIES_PER_BLOCK = 16384;
+constexpr int CHI_MAX_BLOCKS = 2048;
+
+__global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __restrict__ idx,
+                                                           const float* __restrict__ d2,
+                                                           const float* __restrict__ rho, int64_t nnz, int k,
+                                                           int G, double log_emin, double log_emax,
+                                                           int64_t per_block, double* __restrict__ partial)
+{
+    __shared__ float sx[CHI_BLOCK / WAVE][WAVE];
+    __shared__ double sred[CHI_BLOCK / WAVE][256];
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * per_block;
+    const int64_t end = min(base + per_block, nnz);
+    const int ngb = (G + WAVE - 1) / WAVE;
+    for (int gb = 0; gb < ngb; ++gb) {
+        const int g = gb * WAVE + lane;
+        const double eg = exp(grid_log(log_emin, log_emax, G, min(g, G - 1)));
+        const float cg = static_cast<float>(-1.4426950408889634 / eg);
+        double acc = 0.0;
+        for (int64_t p0 = base + wave * WAVE; p0 < end; p0 += CHI_BLOCK) {
+            const int64_t p = p0 + lane;
+            float x = __uint_as_float(0x7F800000u);  // +inf -> exp2(-inf) = 0 for padding
+            if (p < end) {
+                const int64_t i = p / k;
+                const float di = d2[p];
+                const float ri = rho[i], rj = rho[idx[p]];
+                x = static_cast<float>(static_cast<double>(di) / (static_cast<double>(ri) * static_cast<double>(rj)));
+            }
+            sx[wave][lane] = x;
+            wave_lds_sync();
+            float part = 0.f;
+#pragma unroll 8
+            for (int t = 0; t < WAVE; ++t) part += exp2f(sx[wave][t] * cg);
+            acc += static_cast<double>(part);
+            wave_lds_sync();
+        }
+        sred[wave][gb * WAVE + lane] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < G) {
+        double s = 0.0;
+        for (int w = 0; w < CHI_BLOCK / WAVE; ++w) s += sred[w][threadIdx.x];
+        partial[static_cast<size_t>(blockIdx.x) * G + threadIdx.x] = s;
+    }
+}
+
+// Fixed-order reduction of the block partials, then slopes and the optimum
+// (Section 2.3): slope_g = (ln chi_{g+1} - ln chi_g) / (ln e_{g+1} - ln e_g),
+// g* = first argmax, e* = e_{g*}, dimension estimate 2 slope_{g*}.
+__global__ __launch_bounds__(1024) void k_chi_finish(const double* __restrict__ partial, int nblocks, int G,
+                                                    double log_emin, double log_emax, TuneResult* __restrict__ out)
+{
+    __shared__ double chi[256];
+    __shared__ double part4[4][256];
+    const int g = threadIdx.x & 255;
+    const int grp = threadIdx.x >> 8;   // 4 fixed groups of block partials
+    if (g < G) {
+        const int per = (nblocks + 3) / 4;
+        const int b0 = grp * per, b1 = min(nblocks, b0 + per);
+        double s = 0.0;
+        for (int b = b0; b < b1; ++b) s += partial[static_cast<size_t>(b) * G + g];
+        part4[grp][g] = s;
+    }
+    __syncthreads();
+    if (grp == 0 && g < G) {
+        const double s = ((part4[0][g] + part4[1][g]) + part4[2][g]) + part4[3][g];
+        chi[g] = s;
+        out->chi[g] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int best = 0;
+        double best_s = -1.0 / 0.0;
+        for (int t = 0; t + 1 < G; ++t) {
+            const double el = exp(grid_log(log_emin, log_emax, G, t));
+            const double er = exp(grid_log(log_emin, log_emax, G, t + 1));
+            const double sl = (log(chi[t + 1]) - log(chi[t])) / (log(er) - log(el));
+            if (sl > best_s) {
+                best_s = sl;
+                best = t;
+            }
+        }
+        out->g_star = best;
+        out->e_star = exp(grid_log(log_emin, log_emax, G, best));
+        out->dim = 2.0 * best_s;
+    }
+}
+
+// ------------------------------------------------------------------ grid scale
+// Block partial sums of ln(ref_i) and ln(rho_i) in float64.
+__global__ __launch_bounds__(256) void k_logsum_partial(const float* __restrict__ ref, const float* __restrict__ rho,
+                                                        int n, double* __restrict__ partial)
+{
+    __shared__ double sa[4], sb[4];
+    double a = 0.0, c = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        a += log(static_cast<double>(ref[i]));
+        c += log(static_cast<double>(rho[i]));
+    }
+    a = wave_sum_f64(a);
+    c = wave_sum_f64(c);
+    if ((threadIdx.x & 63) == 0) {
+        sa[threadIdx.x >> 6] = a;
+        sb[threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = sa[0] + sa[1] + sa[2] + sa[3];
+        partial[2 * blockIdx.x + 1] = sb[0] + sb[1] + sb[2] + sb[3];
+    }
+}
+
+__global__ void k_logsum_finish(const double* __restrict__ partial, int nblocks, int n, double* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0.0, c = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        a += partial[2 * b];
+        c += partial[2 * b + 1];
+    }
+    const double l2 = 2.0 * (a - c) / static_cast<double>(n) / log(2.0);
+    out[0] = ldexp(1.0, static_cast<int>(round(l2)));
+}
+
+// ------------------------------------------------------------------ normalisation
+// q_i = P_i^{-d} sum_r K_ir, P_i = rho_i/2; stores qa_i = q_i^{-alpha} (Section 2.2)
+__global__ __launch_bounds__(256) void k_qpass(const int32_t* __restrict__ idx, const float* __restrict__ d2, int n,
+                                               int k, const float* __restrict__ rho, double e, double alpha,
+                                               double d, double* __restrict__ qa)
+{
+    const int lane = lane_id();
+    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i >= n) return;
+    const double ri = static_cast<double>(rho[i]);
+    const double s = row_kernel_sum(idx + static_cast<size_t>(i) * k, d2 + static_cast<size_t>(i) * k, k, rho,
+                                    1.0 / (e * ri), lane);
+    if (lane == 0) {
+        const double P = 0.5 * ri;
+        const double q = pow(P, -d) * s;
+        qa[i] = pow(q, -alpha);
+    }
+}
+
+// Kt_ir = K_ir qa_i qa_j, D_i = sum_r Kt_ir (compensated), then the requested
+// output kind, the row sorted by column. For KVB_OUT_SYMMETRIC this pass
+// stores Kt and the finishing pass divides by S_i S_j.
+template <int E>
+__global__ __launch_bounds__(256) void k_assemble(const int32_t* __restrict__ idx, const float* __restrict__ d2,
+                                                  int n, int k, const float* __restrict__ rho, double e,
+                                                  const double* __restrict__ qa, int out_kind,
+                                                  int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                  float* __restrict__ val, double* __restrict__ Pout,
+                                                  double* __restrict__ Dout)
+{
+    const int lane = lane_id();
+    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i >= n) return;
+    const int32_t* irow = idx + static_cast<size_t>(i) * k;
+    const float* drow = d2 + static_cast<size_t>(i) * k;
+    const double ri = static_cast<double>(rho[i]);
+    const double inv = 1.0 / (e * ri);
+    const double qai = qa[i];
+    double kt[E];
+    int cj[E];
+    Comp64 acc;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int r = s * WAVE + lane;
+        kt[s] = 0.0;
+        cj[s] = -1;
+        if (r < k) {
+            const int j = irow[r];
+            const double x = static_cast<double>(drow[r]) * inv / static_cast<double>(rho[j]);
+            kt[s] = exp(-x) * qai * qa[j];
+            cj[s] = j;
+            acc.add(kt[s]);
+        }
+    }
+    // fixed-order butterfly of the (sum, compensation) pairs
+    double Ds = acc.s, Dc = acc.c;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const double os = __shfl_xor(Ds, o, WAVE), oc = __shfl_xor(Dc, o, WAVE);
+        const double t = Ds + os;
+        Dc += oc + ((fabs(Ds) >= fabs(os)) ? ((Ds - t) + os) : ((os - t) + Ds));
+        Ds = t;
+    }
+    const double Di = Ds + Dc;
+    const double Pi = 0.5 * ri;
+    uint64_t key[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        float v = 0.f;
+        if (cj[s] >= 0) {
+            double w;
+            if (out_kind == KVB_OUT_MARKOV)
+                w = kt[s] / Di;
+            else if (out_kind == KVB_OUT_GENERATOR)
+                w = (kt[s] / Di - (cj[s] == i ? 1.0 : 0.0)) / (e * Pi * Pi);
+            else
+                w = kt[s];
+            v = static_cast<float>(w);
+        }
+        // sort key: column in the high word, value bits ride along
+        key[s] = cj[s] >= 0 ? ((static_cast<uint64_t>(static_cast<uint32_t>(cj[s])) << 32) | __float_as_uint(v))
+                            : ~0ull;
+    }
+    bitonic_sort<E>(key);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int r = s * WAVE + lane;
+        if (r < k) {
+            col[static_cast<size_t>(i) * k + r] = static_cast<int32_t>(key[s] >> 32);
+            val[static_cast<size_t>(i) * k + r] = __uint_as_float(static_cast<uint32_t>(key[s]));
+        }
+    }
+    if (lane == 0) {
+        rowptr[i] = static_cast<int64_t>(i) * k;
+        if (i == n - 1) rowptr[n] = static_cast<int64_t>(n) * k;
+        if (Pout) Pout[i] = Pi;
+        Dout[i] = Di;
+    }
+}
+
+// Lhat_ir = (Kt_ir / (S_i S_j) - [j == i] / P_i^2) / e, S = P sqrt(D)
+__global__ __launch_bounds__(256) void k_symmetric_finish(int64_t nnz, int k, const int32_t* __restrict__ col,
+                                                          const float* __restrict__ rho, const double* __restrict__ D,
+                                                          double e, float* __restrict__ val)
+{
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    const int64_t i = p / k;
+    const int j = col[p];
+    const double Pi = 0.5 * static_cast<double>(rho[i]), Pj = 0.5 * static_cast<double>(rho[j]);
+    const double Si = Pi * sqrt(D[i]), Sj = Pj * sqrt(D[j]);
+    const double w = (static_cast<double>(val[p]) / (Si * Sj) - (j == i ? 1.0 / (Pi * Pi) : 0.0)) / e;
+    val[p] = static_cast<float>(w);
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_adhoc_bandwidth(const float* d2, int n, int k, int k0, float* b, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adhoc_bandwidth, dim3((n + 255) / 256), dim3(256), 0, st, d2, n, k, k0, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_density(const int32_t* idx, const float* d2, int n, int k, const float* b, double e, double d,
+                          double beta, float* rho, float* psi, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_density, dim3((n + 3) / 4), dim3(256), 0, st, idx, d2, n, k, b, e, d, beta, rho, psi);
+    return hipGetLastError();
+}
+
+static int64_t chi_per_block(int64_t nnz)
+{
+    int64_t per = (nnz + CHI_MAX_BLOCKS - 1) / CHI_MAX_BLOCKS;
+    per = (per + CHI_BLOCK - 1) / CHI_BLOCK * CHI_BLOCK;
+    return per < CHI_MIN_ENTRIES_PER_BLOCK ? CHI_MIN_ENTRIES_PER_BLOCK : per;
+}
+
+int chi_num_blocks(int64_t nnz)
+{
+    const int64_t per = chi_per_block(nnz);
+    return static_cast<int>((nnz + per - 1) / per);
+}
+
+hipError_t launch_chi(const int32_t* idx, const float* d2, const float* rho, int64_t nnz, int k, int G,
+                      double log_emin, double log_emax, double* partial, TuneResult* out, hipStream_t st)
+{
+    const int nb = chi_num_blocks(nnz);
+    hipLaunchKernelGGL(k_chi_partial, dim3(nb), dim3(CHI_BLOCK), 0, st, idx, d2, rho, nnz, k, G, log_emin, log_emax,
+                       chi_per_block(nnz), partial);
+    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, log_emin, log_emax, out);
+    return hipGetLastError();
+}
+
+int logsum_num_blocks(int n) { return min(1024, (n + 255) / 256); }
+
+hipError_t launch_grid_scale(const float* ref, const float* rho, int n, double* partial, double* out,
+                             hipStream_t st)
+{
+    const int nb = logsum_num_blocks(n);
+    hipLaunchKernelGGL(k_logsum_partial, dim3(nb), dim3(256), 0, st, ref, rho, n, partial);
+    hipLaunchKernelGGL(k_logsum_finish, dim3(1), dim3(64), 0, st, partial, nb, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_qpass(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
+                        double alpha, double d, double* qa, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_qpass, dim3((n + 3) / 4), dim3(256), 0, st, idx, d2, n, k, rho, e, alpha, d, qa);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
+                           const double* qa, int out_kind, int64_t* rowptr, int32_t* col, float* val,
+                           double* P, double* D, hipStream_t st)
+{
+    const dim3 grid((n + 3) / 4), block(256);
+    if (k <= 64)
+        hipLaunchKernelGGL((k_assemble<1>), grid, block, 0, st, idx, d2, n, k, rho, e, qa, out_kind, rowptr, col,
+                           val, P, D);
+    else if (k <= 128)
+        hipLaunchKernelGGL((k_assemble<2>), grid, block, 0, st, idx, d2, n, k, rho, e, qa, out_kind, rowptr, col,
+                           val, P, D);
+    else
+        hipLaunchKernelGGL((k_assemble<4>), grid, block, 0, st, idx, d2, n, k, rho, e, qa, out_kind, rowptr, col,
+                           val, P, D);
+    if (out_kind == KVB_OUT_SYMMETRIC) {
+        const int64_t nnz = static_cast<int64_t>(n) * k;
+        hipLaunchKernelGGL(k_symmetric_finish, dim3(static_cast<unsigned>((nnz + 255) / 256)), dim3(256), 0, st,
+                           nnz, k, col, rho, D, e, val);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace kvb

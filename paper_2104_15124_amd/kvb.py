@@ -1,0 +1,287 @@
+"""Python binding of libkvb.so (ctypes; torch tensors for device memory).
+
+Each function here marshals torch tensors into the C ABI declared in
+``include/kvb.h`` and returns torch tensors; all arithmetic runs in the HIP
+kernels of the library. A missing library or a missing GPU raises
+immediately: there is no CPU path.
+
+Names follow the C ABI without the ``kvb_`` prefix. ``build_kernel_matrix``
+chains the calls in the order of the paper's pipeline (Section 4, steps 1-2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkvb.so")
+
+# status / enum values mirrored from include/kvb.h
+OK, W_GRID_EDGE, W_FALLBACK = 0, 1, 2
+E_INVALID, E_NOMEM, E_HIP, E_UNSUPPORTED, E_NOT_TRAINED, E_IO = -1, -2, -3, -4, -5, -6
+KNN_F32, KNN_BF16, KNN_LEARNED = 0, 1, 2
+BW_ADHOC, BW_DENSITY = 0, 1
+OUT_MARKOV, OUT_GENERATOR, OUT_SYMMETRIC = 0, 1, 2
+ROW_RECHECK, ROW_FALLBACK, ROW_UNCERTIFIED = 1, 2, 4
+OPT_FORCE_FALLBACK, OPT_SCRATCH_LIMIT = 1, 2
+MODES = {"f32": KNN_F32, "bf16": KNN_BF16, "learned": KNN_LEARNED}
+
+EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb_knn",
+           "kvb_knn_fallback_rows", "kvb_bandwidth", "kvb_grid_scale", "kvb_tune_eps",
+           "kvb_assemble_csr", "kvb_version", "kvb_profile_enable", "kvb_profile_read",
+           "kvb_profile_name")
+PROF_SLOTS = 9
+
+
+class KvbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"kvb error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_vp, _i32, _i64, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libkvb.so and declare its C signatures (needs no GPU)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise KvbError(E_UNSUPPORTED, f"HIP library not built: {path} is missing "
+                       "(run __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    L.kvb_create.argtypes = [ctypes.POINTER(_vp), _vp]
+    L.kvb_destroy.argtypes = [_vp]
+    L.kvb_destroy.restype = None
+    L.kvb_last_error.argtypes = [_vp]
+    L.kvb_last_error.restype = ctypes.c_char_p
+    L.kvb_set_option.argtypes = [_vp, _i32, _i64]
+    L.kvb_knn.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp]
+    L.kvb_knn_fallback_rows.argtypes = [_vp, ctypes.POINTER(_i64)]
+    L.kvb_bandwidth.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _vp, _f64, _f64, _f64, _vp, _vp]
+    L.kvb_grid_scale.argtypes = [_vp, _vp, _vp, _i64, ctypes.POINTER(_f64)]
+    L.kvb_tune_eps.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _f64, _f64, _i32,
+                               _vp, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
+    L.kvb_assemble_csr.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _f64, _f64, _f64, _i32,
+                                   _vp, _vp, _vp, _vp, _vp]
+    L.kvb_version.restype = ctypes.c_char_p
+    L.kvb_profile_enable.argtypes = [_vp, _i32]
+    L.kvb_profile_read.argtypes = [_vp, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
+    L.kvb_profile_name.argtypes = [_i32]
+    L.kvb_profile_name.restype = ctypes.c_char_p
+    for name in ("kvb_create", "kvb_set_option", "kvb_knn", "kvb_knn_fallback_rows", "kvb_bandwidth",
+                 "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_profile_enable",
+                 "kvb_profile_read"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+class Context:
+    """A library context bound to one HIP stream of the current device."""
+
+    def __init__(self, stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise KvbError(E_UNSUPPORTED, "no GPU visible: the kvb library has no CPU path")
+        self.lib = load_library()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = self.stream.device
+        h = _vp()
+        with torch.cuda.device(self.device):
+            rc = self.lib.kvb_create(ctypes.byref(h), _vp(self.stream.cuda_stream))
+        if rc != OK:
+            raise KvbError(rc, "kvb_create failed (gfx950 device required)")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.kvb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc: int) -> int:
+        if rc < 0:
+            raise KvbError(rc, self.lib.kvb_last_error(self.h).decode())
+        return rc
+
+    def set_option(self, key: int, value: int):
+        self.check(self.lib.kvb_set_option(self.h, key, int(value)))
+
+    def profile(self, on: bool):
+        """Start (or stop) per-kernel event timing; totals restart at zero."""
+        self.check(self.lib.kvb_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total ms, launch sequences)} since profile(True)."""
+        out = {}
+        for s in range(PROF_SLOTS):
+            ms, cnt = _f64(), _i64()
+            self.check(self.lib.kvb_profile_read(self.h, s, ctypes.byref(ms), ctypes.byref(cnt)))
+            out[self.lib.kvb_profile_name(s).decode()] = (float(ms.value), int(cnt.value))
+        return out
+
+
+_contexts: dict = {}
+
+
+def context() -> Context:
+    """The cached context of the current device and current torch stream."""
+    s = torch.cuda.current_stream()
+    key = (s.device.index, s.cuda_stream)
+    ctx = _contexts.get(key)
+    if ctx is None:
+        ctx = _contexts[key] = Context(s)
+    return ctx
+
+
+def _ptr(t: torch.Tensor | None):
+    return _vp(t.data_ptr()) if t is not None else _vp(0)
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise KvbError(E_INVALID, f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise KvbError(E_INVALID, f"{name} must be {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+# ------------------------------------------------------------------ entry points
+def knn(X: torch.Tensor, k: int, mode: str = "f32", margin: int = 32, ctx: Context | None = None):
+    """Exact k-NN self-join: returns idx [n,k] int32, d2 [n,k] float32, row flags [n] int32."""
+    ctx = ctx or context()
+    X = _dev(X, torch.float32, "X")
+    n, m = X.shape
+    idx = torch.empty((n, k), dtype=torch.int32, device=X.device)
+    d2 = torch.empty((n, k), dtype=torch.float32, device=X.device)
+    flags = torch.empty(n, dtype=torch.int32, device=X.device)
+    ctx.check(ctx.lib.kvb_knn(ctx.h, _ptr(X), n, m, k, MODES[mode], margin, _ptr(idx), _ptr(d2), _ptr(flags)))
+    return idx, d2, flags
+
+
+def knn_fallback_rows(ctx: Context | None = None) -> int:
+    ctx = ctx or context()
+    c = _i64()
+    ctx.check(ctx.lib.kvb_knn_fallback_rows(ctx.h, ctypes.byref(c)))
+    return int(c.value)
+
+
+def bandwidth_adhoc(d2: torch.Tensor, k0: int, ctx: Context | None = None) -> torch.Tensor:
+    ctx = ctx or context()
+    d2 = _dev(d2, torch.float32, "d2")
+    n, k = d2.shape
+    b = torch.empty(n, dtype=torch.float32, device=d2.device)
+    ctx.check(ctx.lib.kvb_bandwidth(ctx.h, _vp(0), _ptr(d2), n, k, BW_ADHOC, k0, _vp(0), 0.0, 0.0, 0.0,
+                                    _ptr(b), _vp(0)))
+    return b
+
+
+def bandwidth_density(idx: torch.Tensor, d2: torch.Tensor, b: torch.Tensor, e: float, d: float, beta: float,
+                      ctx: Context | None = None):
+    """Returns (rho, psi) with psi the density estimate and rho = 2 psi^beta."""
+    ctx = ctx or context()
+    idx = _dev(idx, torch.int32, "idx")
+    d2 = _dev(d2, torch.float32, "d2")
+    b = _dev(b, torch.float32, "b")
+    n, k = d2.shape
+    rho = torch.empty(n, dtype=torch.float32, device=d2.device)
+    psi = torch.empty(n, dtype=torch.float32, device=d2.device)
+    ctx.check(ctx.lib.kvb_bandwidth(ctx.h, _ptr(idx), _ptr(d2), n, k, BW_DENSITY, 0, _ptr(b), e, d, beta,
+                                    _ptr(rho), _ptr(psi)))
+    return rho, psi
+
+
+def grid_scale(ref: torch.Tensor, rho: torch.Tensor, ctx: Context | None = None) -> float:
+    ctx = ctx or context()
+    ref = _dev(ref, torch.float32, "ref")
+    rho = _dev(rho, torch.float32, "rho")
+    s = _f64()
+    ctx.check(ctx.lib.kvb_grid_scale(ctx.h, _ptr(ref), _ptr(rho), ref.numel(), ctypes.byref(s)))
+    return float(s.value)
+
+
+@dataclass
+class Tuning:
+    chi: np.ndarray
+    e_star: float
+    dim: float
+    edge: bool
+
+
+def tune_eps(idx: torch.Tensor, d2: torch.Tensor, rho: torch.Tensor, e_min: float, e_max: float, G: int,
+             ctx: Context | None = None) -> Tuning:
+    ctx = ctx or context()
+    idx = _dev(idx, torch.int32, "idx")
+    d2 = _dev(d2, torch.float32, "d2")
+    rho = _dev(rho, torch.float32, "rho")
+    n, k = d2.shape
+    chi = np.zeros(G, dtype=np.float64)
+    es, dm = _f64(), _f64()
+    rc = ctx.check(ctx.lib.kvb_tune_eps(ctx.h, _ptr(idx), _ptr(d2), _ptr(rho), n, k, e_min, e_max, G,
+                                        chi.ctypes.data_as(_vp), ctypes.byref(es), ctypes.byref(dm)))
+    return Tuning(chi, float(es.value), float(dm.value), rc == W_GRID_EDGE)
+
+
+def assemble_csr(idx: torch.Tensor, d2: torch.Tensor, rho: torch.Tensor, e: float, alpha: float, d: float,
+                 out_kind: int = OUT_MARKOV, ctx: Context | None = None):
+    """Returns rowptr [n+1] int64, col [nnz] int32, val [nnz] float32, P [n] f64, D [n] f64."""
+    ctx = ctx or context()
+    idx = _dev(idx, torch.int32, "idx")
+    d2 = _dev(d2, torch.float32, "d2")
+    rho = _dev(rho, torch.float32, "rho")
+    n, k = d2.shape
+    dev = d2.device
+    rowptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(n * k, dtype=torch.int32, device=dev)
+    val = torch.empty(n * k, dtype=torch.float32, device=dev)
+    P = torch.empty(n, dtype=torch.float64, device=dev)
+    D = torch.empty(n, dtype=torch.float64, device=dev)
+    ctx.check(ctx.lib.kvb_assemble_csr(ctx.h, _ptr(idx), _ptr(d2), _ptr(rho), n, k, e, alpha, d, out_kind,
+                                       _ptr(rowptr), _ptr(col), _ptr(val), _ptr(P), _ptr(D)))
+    return rowptr, col, val, P, D
+
+
+@dataclass
+class KernelMatrix:
+    idx: torch.Tensor
+    d2: torch.Tensor
+    flags: torch.Tensor
+    b: torch.Tensor
+    tune_a: Tuning
+    rho: torch.Tensor
+    psi: torch.Tensor
+    scale_b: float
+    tune_b: Tuning
+    rowptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+    P: torch.Tensor
+    D: torch.Tensor
+
+
+def build_kernel_matrix(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float,
+                        e_min: float = 1e-3, e_max: float = 1e1, G: int = 64, mode: str = "f32",
+                        margin: int = 32, out_kind: int = OUT_MARKOV, ctx: Context | None = None) -> KernelMatrix:
+    """The whole sparse kernel-matrix build, in the paper's order: k-NN ->
+    ad-hoc bandwidth -> tune e (density kernel) -> density psi, rho = 2 psi^beta
+    -> tune e (operator kernel, power-of-two shifted grid) -> q, Kt, D -> CSR."""
+    ctx = ctx or context()
+    idx, d2, flags = knn(X, k, mode, margin, ctx)
+    b = bandwidth_adhoc(d2, k0, ctx)
+    ta = tune_eps(idx, d2, b, e_min, e_max, G, ctx)
+    rho, psi = bandwidth_density(idx, d2, b, ta.e_star, d, beta, ctx)
+    s = grid_scale(b, rho, ctx)
+    tb = tune_eps(idx, d2, rho, e_min * s, e_max * s, G, ctx)
+    rowptr, col, val, P, D = assemble_csr(idx, d2, rho, tb.e_star, alpha, d, out_kind, ctx)
+    return KernelMatrix(idx, d2, flags, b, ta, rho, psi, s, tb, rowptr, col, val, P, D)

@@ -1,0 +1,145 @@
+"""GPU k-NN parity against the FP64 oracle (run on an MI355X).
+
+Every case calls kvb_knn through the C ABI on seeded inputs and compares with
+the oracle's exact (distance, index) neighbour lists (Section 2.1 ordering).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from parity import check_knn_rows, knn_reference, say
+
+pytestmark = pytest.mark.gpu
+
+
+def run_knn(kvb, X, k, margin, mode="f32", ctx=None):
+    Xd = torch.from_numpy(X).cuda()
+    idx, d2, flags = kvb.knn(Xd, k, mode=mode, margin=margin, ctx=ctx)
+    torch.cuda.synchronize()
+    return idx.cpu().numpy(), d2.cpu().numpy(), flags.cpu().numpy()
+
+
+CASES = [
+    # (name, n, m, k, margin, seed)
+    ("tiny_n1", 1, 3, 1, 0, 0),
+    ("n2_k2", 2, 3, 2, 0, 1),
+    ("n3_k3_m1", 3, 1, 3, 4, 2),
+    ("n63_k9", 63, 3, 9, 8, 3),
+    ("n64_k64", 64, 2, 64, 32, 4),
+    ("n65_k33", 65, 3, 33, 32, 5),
+    ("n1037_k32_m3", 1037, 3, 32, 32, 6),
+    ("n1037_k32_m3_margin0", 1037, 3, 32, 0, 7),
+    ("n2049_k64_m5", 2049, 5, 64, 32, 8),
+    ("n1500_k128_m8", 1500, 8, 128, 32, 9),
+    ("n1000_k200_m4", 1000, 4, 200, 56, 10),
+    ("n700_k16_m12", 700, 12, 16, 16, 11),
+    ("n900_k40_m16", 900, 16, 40, 32, 12),
+    ("n500_k20_m64", 500, 64, 20, 8, 13),
+    ("n3000_k64_m1", 3000, 1, 64, 32, 14),
+]
+
+
+@pytest.mark.parametrize("name,n,m,k,margin,seed", CASES, ids=[c[0] for c in CASES])
+def test_knn_random(gpu_lib, name, n, m, k, margin, seed):
+    say(f"[knn] {name}: n={n} m={m} k={k} margin={margin} seed={seed}")
+    X = workloads.gaussian_iid(n, m, seed=seed)
+    gi, gd, fl = run_knn(gpu_lib, X, k, margin)
+    ri, rd = knn_reference(X, k)
+    ties = check_knn_rows(gi, gd, ri, rd, k, np.arange(n))
+    say(f"[knn] {name}: ok, near-tie rows {ties}, fallback rows {int(((fl & 2) > 0).sum())}")
+
+
+@pytest.mark.parametrize("margin", [0, 4, 32])
+def test_knn_chain_lattice_bitwise(gpu_lib, margin):
+    say(f"[knn] chain lattice margin={margin}")
+    X = workloads.chain_lattice(300)
+    gi, gd, fl = run_knn(gpu_lib, X, 9, margin)
+    ri, rd = oracle.knn(X, 9)
+    np.testing.assert_array_equal(gi, ri)
+    np.testing.assert_array_equal(gd, rd.astype(np.float32))
+
+
+@pytest.mark.parametrize("margin", [0, 32])
+def test_knn_cubic_lattice_bitwise(gpu_lib, margin):
+    say(f"[knn] cubic lattice margin={margin}")
+    X = workloads.cubic_lattice(9)
+    gi, gd, fl = run_knn(gpu_lib, X, 19, margin)
+    ri, rd = oracle.knn(X, 19)
+    np.testing.assert_array_equal(gi, ri)
+    np.testing.assert_array_equal(gd, rd.astype(np.float32))
+
+
+def test_knn_duplicates_and_identical_points(gpu_lib):
+    say("[knn] duplicates")
+    rng = np.random.default_rng(11)
+    base = rng.standard_normal((40, 3)).astype(np.float32)
+    X = np.ascontiguousarray(np.repeat(base, 5, axis=0)[rng.permutation(200)])
+    for margin in (0, 4, 32):
+        gi, gd, fl = run_knn(gpu_lib, X, 12, margin)
+        ri, rd = oracle.knn(X, 12)
+        np.testing.assert_array_equal(gi, ri)
+    say("[knn] identical points")
+    Z = np.zeros((300, 3), dtype=np.float32)
+    gi, gd, fl = run_knn(gpu_lib, Z, 10, 16)
+    ri, rd = oracle.knn(Z, 10)
+    np.testing.assert_array_equal(gi, ri)
+    assert (gd == 0).all()
+    assert ((fl & 2) > 0).all(), "every row of identical points needs the exact fallback"
+
+
+def test_knn_forced_fallback_matches(gpu_lib):
+    say("[knn] forced fallback on the sphere")
+    from paper_2104_15124_amd import kvb
+    X = workloads.sphere2(2000, seed=0)
+    ctx = kvb.Context()
+    ctx.set_option(kvb.OPT_FORCE_FALLBACK, 3)
+    gi, gd, fl = run_knn(gpu_lib, X, 32, 32, ctx=ctx)
+    assert kvb.knn_fallback_rows(ctx) == len(range(0, 2000, 3))
+    ri, rd = knn_reference(X, 32)
+    check_knn_rows(gi, gd, ri, rd, 32, np.arange(2000))
+    assert ((fl[::3] & 2) > 0).all()
+    ctx.close()
+
+
+def test_knn_sphere_n2000_k32(gpu_lib):
+    say("[knn] sphere2 n=2000 k=32 (full oracle)")
+    X = workloads.make("sphere2_n2000", seed=0)
+    gi, gd, fl = run_knn(gpu_lib, X, 32, 32)
+    ri, rd = knn_reference(X, 32)
+    check_knn_rows(gi, gd, ri, rd, 32, np.arange(len(X)))
+
+
+def test_knn_torus_n100k_k64_full(gpu_lib):
+    """The measured workload at full size, in the launch configuration the
+    benchmark times, against the oracle on every row."""
+    say("[knn] torus n=100000 k=64 (full oracle)")
+    X = workloads.make("torus_n100k", seed=0)
+    gi, gd, fl = run_knn(gpu_lib, X, 64, 32)
+    ri, rd = knn_reference(X, 64)
+    ties = check_knn_rows(gi, gd, ri, rd, 64, np.arange(len(X)))
+    say(f"[knn] torus: ok, near-tie rows {ties}, fallback rows {int(((fl & 2) > 0).sum())}")
+
+
+def test_knn_deterministic(gpu_lib):
+    say("[knn] determinism")
+    X = workloads.torus(20000, seed=5)
+    a = run_knn(gpu_lib, X, 64, 32)
+    b = run_knn(gpu_lib, X, 64, 32)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_knn_invalid_arguments(gpu_lib):
+    from paper_2104_15124_amd import kvb
+    X = torch.zeros((10, 3), device="cuda")
+    with pytest.raises(kvb.KvbError) as e:
+        kvb.knn(X, 11)                       # k > n
+    assert e.value.code == kvb.E_INVALID
+    with pytest.raises(kvb.KvbError) as e:
+        kvb.knn(X, 5, margin=-1)
+    assert e.value.code == kvb.E_INVALID
+    with pytest.raises(kvb.KvbError) as e:
+        kvb.knn(torch.zeros((300, 3), device="cuda"), 200, margin=100)   # k + margin > 256
+    assert e.value.code == kvb.E_UNSUPPORTED
