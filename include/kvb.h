@@ -87,6 +87,8 @@ extern "C" {
 /* ---- options (kvb_set_option) ---- */
 #define KVB_OPT_FORCE_FALLBACK 1 /* value N > 0: also send every N-th row to the fallback (testing) */
 #define KVB_OPT_SCRATCH_LIMIT 2  /* value: maximum scratch bytes; 0 = unlimited */
+#define KVB_OPT_BF16_SPLIT 3     /* BF16 terms per coordinate product in KVB_KNN_BF16 mode: 1 (x_hi only),
+                                    3 (hi/lo pairs, default) or 6 (hi/mid/lo pairs) */
 
 typedef struct kvb_ctx_s* kvb_ctx;
 
@@ -109,7 +111,10 @@ int kvb_set_option(kvb_ctx ctx, int32_t key, int64_t value);
  *   X        [n, m] float32 row-major samples (finite values).
  *   k        neighbours per row including the row itself, 1 <= k <= n.
  *   mode     KVB_KNN_F32 or KVB_KNN_BF16 (exact sets), KVB_KNN_LEARNED
- *            (needs kvb_part_*; recall < 1 possible).
+ *            (needs kvb_part_*; recall < 1 possible). F32 uses direct
+ *            differences on the vector ALUs for m <= 8 and FP32 matrix-core
+ *            tiles otherwise; BF16 uses BF16 matrix-core tiles with the
+ *            coordinates split into KVB_OPT_BF16_SPLIT terms.
  *   margin   extra candidates kept by the distance tiles before the exact
  *            re-rank, 0 <= margin and k + margin <= 256.
  *   idx      [n, k] int32 out: row i = i, then the k-1 nearest j != i.
@@ -198,7 +203,8 @@ const char* kvb_version(void);
 #define KVB_PROF_GRID_SCALE 6    /* operator-grid scale reduction */
 #define KVB_PROF_QPASS 7         /* q pass */
 #define KVB_PROF_ASSEMBLE 8      /* Kt, D, output kind, per-row column sort, CSR write */
-#define KVB_PROF_SLOTS 9
+#define KVB_PROF_KNN_PREP 9      /* centring and operand layout for the matrix-core distance tiles */
+#define KVB_PROF_SLOTS 10
 
 /* Turn event timing on (on != 0) or off; either way the totals restart at 0. */
 int kvb_profile_enable(kvb_ctx ctx, int32_t on);

@@ -15,7 +15,7 @@
 namespace {
 const char* const kProfNames[KVB_PROF_SLOTS] = {
     "knn_select", "knn_refine", "knn_fallback", "adhoc_bandwidth", "chi_tuning", "density",
-    "grid_scale", "q_pass", "assemble",
+    "grid_scale", "q_pass", "assemble", "knn_prep",
 };
 struct ProfPair {
     int slot;
@@ -31,6 +31,7 @@ struct kvb_ctx_s {
     size_t scratch_bytes = 0;
     size_t scratch_limit = 0;
     int64_t force_fallback = 0;
+    int bf16_split = 3;
     kvb::TuneResult* tune_dev = nullptr;
     kvb::TuneResult* tune_host = nullptr;   // pinned
     int* fb_count_dev = nullptr;            // fallback rows of the last kvb_knn
@@ -225,6 +226,10 @@ int kvb_set_option(kvb_ctx ctx, int32_t key, int64_t value)
         KVB_REQUIRE(ctx, value >= 0, "KVB_OPT_SCRATCH_LIMIT must be >= 0");
         ctx->scratch_limit = static_cast<size_t>(value);
         return KVB_OK;
+    case KVB_OPT_BF16_SPLIT:
+        KVB_REQUIRE(ctx, value == 1 || value == 3 || value == 6, "KVB_OPT_BF16_SPLIT must be 1, 3 or 6");
+        ctx->bf16_split = static_cast<int>(value);
+        return KVB_OK;
     default:
         return fail(ctx, KVB_E_INVALID, "unknown option key %d", key);
     }
@@ -246,31 +251,82 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                 "unknown k-NN mode %d", mode);
     if (k + margin > 256) return fail(ctx, KVB_E_UNSUPPORTED, "k + margin = %d exceeds 256", k + margin);
     if (m > 1024) return fail(ctx, KVB_E_UNSUPPORTED, "m = %d exceeds 1024", m);
-    if (mode != KVB_KNN_F32) return fail(ctx, KVB_E_UNSUPPORTED, "k-NN mode %d is not available", mode);
+    if (mode == KVB_KNN_LEARNED) return fail(ctx, KVB_E_UNSUPPORTED, "k-NN mode %d is not available", mode);
 
     const int nn = static_cast<int>(n);
     const int kp = static_cast<int>(std::min<int64_t>(k + margin, n));
-    size_t need = round256(size_t(nn) * kp * sizeof(uint64_t)) + round256(size_t(nn) * sizeof(float)) +
-                  round256(size_t(nn) * sizeof(int)) + 1024;
+    const bool direct = (mode == KVB_KNN_F32 && m <= 8);
+    const int split = mode == KVB_KNN_F32 ? 0 : ctx->bf16_split;
+    const int cap = kp <= 128 ? 128 : 256;   // list capacities of the matrix-core select kernels
+    int kpad = 0;
+    if (!direct) {
+        const int kraw = split == 0 ? m + 1 : split * m + 3;
+        const int kstep = kvb::mfma_kstep(split);
+        const int ks = kvb::mfma_pick_ksteps(split, (kraw + kstep - 1) / kstep);
+        if (ks < 0)
+            return fail(ctx, KVB_E_UNSUPPORTED, "m = %d is too large for the %s distance tiles", m,
+                        split == 0 ? "FP32" : "BF16");
+        kpad = ks * kstep;
+    }
+    const int colblocks = std::max(1, std::min(1024, (nn + 4095) / 4096));
+    const size_t esz = split == 0 ? sizeof(float) : sizeof(uint16_t);
+    size_t need = round256(size_t(nn) * (direct ? kp : cap) * sizeof(uint64_t)) +
+                  round256(size_t(nn) * sizeof(float)) + round256(size_t(nn) * sizeof(int)) + 2048;
+    if (!direct)
+        need += 2 * round256(size_t(nn + 31) / 32 * 32 * kpad * esz) + round256(size_t(nn) * sizeof(float)) +
+                round256(size_t(m) * sizeof(double)) + round256(size_t(colblocks) * m * sizeof(double)) + 256;
     int rc = ensure_scratch(ctx, need);
     if (rc) return rc;
     Carve cv(ctx->scratch);
-    uint64_t* keys = cv.take<uint64_t>(size_t(nn) * kp);
+    uint64_t* keys = cv.take<uint64_t>(size_t(nn) * (direct ? kp : cap));
     float* slast = cv.take<float>(nn);
     int* fb_list = cv.take<int>(nn);
 
     KVB_HIP(ctx, hipMemsetAsync(ctx->fb_count_dev, 0, sizeof(int), ctx->stream));
-    {
+    float lb_scale = 1.0f;
+    int kstride = kp;
+    if (direct) {
         Prof pr(ctx, KVB_PROF_KNN_SELECT);
         KVB_HIP(ctx, kvb::launch_select_direct(X, nn, m, kp, keys, slast, ctx->stream));
+        // the direct tiles compute each squared distance with at most (m + 2)
+        // float32 roundings; (m + 4) 2^-23 bounds their relative error with a
+        // factor-2 margin
+        const double sel_err = (m + 4) * std::ldexp(1.0, -23);
+        lb_scale = static_cast<float>(1.0 / (1.0 + sel_err));
+    } else {
+        void* Aq = cv.take<char>(size_t(nn) * kpad * esz);
+        void* Bc = cv.take<char>(size_t(nn + 31) / 32 * 32 * kpad * esz);   // tile-major, 32-row padded
+        float* ynorm2 = cv.take<float>(nn);
+        double* mu = cv.take<double>(m);
+        double* colpart = cv.take<double>(size_t(colblocks) * m);
+        unsigned* rmax = cv.take<unsigned>(1);
+        {
+            Prof pr(ctx, KVB_PROF_KNN_PREP);
+            KVB_HIP(ctx, hipMemsetAsync(rmax, 0, sizeof(unsigned), ctx->stream));
+            KVB_HIP(ctx, kvb::launch_prep(X, nn, m, split, kpad, colpart, colblocks, mu, Aq, Bc, ynorm2, rmax,
+                                          ctx->stream));
+        }
+        // error model of the selection score (derivation in knn_mfma.hip)
+        const double u = std::ldexp(1.0, -24);
+        double rep = 0.0, drop = 0.0;
+        if (split == 1) rep = std::ldexp(1.01, -8);
+        if (split == 3) rep = std::ldexp(1.01, -16), drop = std::ldexp(1.03, -16);
+        if (split == 6) rep = std::ldexp(1.01, -24), drop = std::ldexp(1.03, -23);
+        kvb::ErrModel em;
+        em.gamma = (kpad + 4) * u;
+        em.norm = 1.01 * u;
+        em.cross = 2.0 * (2.0 * rep * (1.0 + rep) + drop);
+        em.center = 1.01 * u;
+        {
+            Prof pr(ctx, KVB_PROF_KNN_SELECT);
+            KVB_HIP(ctx, kvb::launch_select_mfma(split, Aq, Bc, nn, kpad, kp, ynorm2, rmax, em, keys, cap, slast,
+                                                 ctx->stream));
+        }
+        kstride = cap;
     }
-    // the direct tiles compute each squared distance with at most (m + 2) float32
-    // roundings; (m + 4) 2^-23 bounds their relative error with a factor-2 margin
-    const double sel_err = (m + 4) * std::ldexp(1.0, -23);
-    const float lb_scale = static_cast<float>(1.0 / (1.0 + sel_err));
     {
         Prof pr(ctx, KVB_PROF_KNN_REFINE);
-        KVB_HIP(ctx, kvb::launch_refine(X, nn, m, k, kp, keys, slast, lb_scale, idx, d2, row_flags,
+        KVB_HIP(ctx, kvb::launch_refine(X, nn, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, row_flags,
                                         ctx->fb_count_dev, fb_list, static_cast<int>(ctx->force_fallback),
                                         ctx->stream));
     }

@@ -212,13 +212,14 @@ __device__ __forceinline__ double dist2_f64(const float* __restrict__ a, const f
     return s;
 }
 
-// One wavefront per row. keys: [n, kp] candidate keys from a select kernel,
-// slast: the select key of the kp-th candidate (a bound on the dropped ones),
-// converted to a lower bound on their true squared distance by lb_scale
-// (direct tiles: 1/(1 + select error)).
+// One wavefront per row. keys: [n, kstride] candidate keys from a select
+// kernel (the first kp of each row are used), slast: per row, a bound on the
+// candidates the select step dropped, turned into a lower bound on their true
+// squared distance by lb_scale (direct tiles: the kp-th score times
+// 1/(1 + select error); matrix-core tiles: the bound itself, lb_scale = 1).
 template <int E>
 __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int n, int m, int k, int kp,
-                                                const uint64_t* __restrict__ keys,
+                                                int kstride, const uint64_t* __restrict__ keys,
                                                 const float* __restrict__ slast, float lb_scale,
                                                 int32_t* __restrict__ idx_out, float* __restrict__ d2_out,
                                                 int32_t* __restrict__ flags_out,
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         const int t = s * WAVE + lane;
-        uint64_t key = t < kp ? keys[static_cast<size_t>(i) * kp + t] : KEY_INF;
+        uint64_t key = t < kp ? keys[static_cast<size_t>(i) * kstride + t] : KEY_INF;
         if (key != KEY_INF) {
             const uint32_t j = key_idx(key);
             if (static_cast<int>(j) == i)
@@ -524,20 +525,20 @@ hipError_t launch_select_direct(const float* X, int n, int m, int kp, uint64_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_refine(const float* X, int n, int m, int k, int kp, const uint64_t* keys,
+hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,
                          const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags,
                          int* fb_count, int* fb_list, int force_period, hipStream_t st)
 {
     const dim3 grid((n + 3) / 4), block(256);
     if (kp <= 64)
-        hipLaunchKernelGGL((k_refine<1>), grid, block, 0, st, X, n, m, k, kp, keys, slast, lb_scale, idx, d2,
-                           flags, fb_count, fb_list, force_period);
+        hipLaunchKernelGGL((k_refine<1>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
+                           d2, flags, fb_count, fb_list, force_period);
     else if (kp <= 128)
-        hipLaunchKernelGGL((k_refine<2>), grid, block, 0, st, X, n, m, k, kp, keys, slast, lb_scale, idx, d2,
-                           flags, fb_count, fb_list, force_period);
+        hipLaunchKernelGGL((k_refine<2>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
+                           d2, flags, fb_count, fb_list, force_period);
     else
-        hipLaunchKernelGGL((k_refine<4>), grid, block, 0, st, X, n, m, k, kp, keys, slast, lb_scale, idx, d2,
-                           flags, fb_count, fb_list, force_period);
+        hipLaunchKernelGGL((k_refine<4>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
+                           d2, flags, fb_count, fb_list, force_period);
     return hipGetLastError();
 }
 

@@ -1,10 +1,12 @@
 // Device-side building blocks shared by the kvb kernels (gfx950, wave64).
 //
-// Neighbour candidates travel as 64-bit keys: the IEEE bits of a non-negative
-// float32 squared distance in the high word and the column index in the low
-// word. For d >= 0 the float bits are monotone, so unsigned key order is the
-// (distance, index) order of the paper's neighbour ranking I(x, k)
-// (Section 2.1): ties between equal distances go to the smaller index.
+// Neighbour candidates travel as 64-bit keys: an order-preserving encoding of
+// a float32 score in the high word (sign bit flipped for non-negative values,
+// all bits flipped for negative ones, so unsigned order equals float order)
+// and the column index in the low word. Unsigned key order is therefore the
+// (score, index) order of the paper's neighbour ranking I(x, k) (Section 2.1):
+// ties between equal scores go to the smaller index. Scores are squared
+// distances, or squared distances shifted by a per-row constant.
 //
 // Per-row candidate lists live in registers, spread over the 64 lanes of a
 // wavefront: element t of a list of capacity 64*E sits in slot t / 64 of
@@ -18,14 +20,23 @@
 
 namespace kvb {
 
-constexpr uint64_t KEY_INF = 0x7F800000FFFFFFFFull;  // distance +inf, index 0xffffffff
+constexpr uint64_t KEY_INF = 0xFF800000FFFFFFFFull;  // score +inf, index 0xffffffff
 constexpr int WAVE = 64;
 
+__device__ __forceinline__ uint32_t float_order_bits(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float order_bits_float(uint32_t u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
 __device__ __forceinline__ uint64_t make_key(float d, uint32_t j)
 {
-    return (static_cast<uint64_t>(__float_as_uint(d)) << 32) | j;
+    return (static_cast<uint64_t>(float_order_bits(d)) << 32) | j;
 }
-__device__ __forceinline__ float key_dist(uint64_t k) { return __uint_as_float(static_cast<uint32_t>(k >> 32)); }
+__device__ __forceinline__ float key_dist(uint64_t k) { return order_bits_float(static_cast<uint32_t>(k >> 32)); }
 __device__ __forceinline__ uint32_t key_idx(uint64_t k) { return static_cast<uint32_t>(k); }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

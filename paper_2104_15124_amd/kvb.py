@@ -27,14 +27,14 @@ KNN_F32, KNN_BF16, KNN_LEARNED = 0, 1, 2
 BW_ADHOC, BW_DENSITY = 0, 1
 OUT_MARKOV, OUT_GENERATOR, OUT_SYMMETRIC = 0, 1, 2
 ROW_RECHECK, ROW_FALLBACK, ROW_UNCERTIFIED = 1, 2, 4
-OPT_FORCE_FALLBACK, OPT_SCRATCH_LIMIT = 1, 2
+OPT_FORCE_FALLBACK, OPT_SCRATCH_LIMIT, OPT_BF16_SPLIT = 1, 2, 3
 MODES = {"f32": KNN_F32, "bf16": KNN_BF16, "learned": KNN_LEARNED}
 
 EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb_knn",
            "kvb_knn_fallback_rows", "kvb_bandwidth", "kvb_grid_scale", "kvb_tune_eps",
            "kvb_assemble_csr", "kvb_version", "kvb_profile_enable", "kvb_profile_read",
            "kvb_profile_name")
-PROF_SLOTS = 9
+PROF_SLOTS = 10
 
 
 class KvbError(RuntimeError):

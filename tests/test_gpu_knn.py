@@ -143,3 +143,88 @@ def test_knn_invalid_arguments(gpu_lib):
     with pytest.raises(kvb.KvbError) as e:
         kvb.knn(torch.zeros((300, 3), device="cuda"), 200, margin=100)   # k + margin > 256
     assert e.value.code == kvb.E_UNSUPPORTED
+
+
+# ---------------------------------------------------------------- matrix-core tiles
+def _gen(kind, n, m, seed):
+    if kind == "gauss":
+        return workloads.gaussian_iid(n, m, seed=seed)
+    if kind == "nonlinear5":
+        return workloads.nonlinear5(n, seed=seed)
+    if kind == "sphere3":
+        return workloads.sphere3_lifted(n, seed=seed, m=m)
+    if kind == "gmm":
+        return workloads.gaussian_mixture(n, seed=seed, m=m)
+    raise ValueError(kind)
+
+
+MFMA_CASES = [
+    # (name, kind, n, m, k, margin, mode, split, seed)
+    ("f32_gauss_m9", "gauss", 1500, 9, 32, 32, "f32", 3, 21),
+    ("f32_gmm_m16", "gmm", 3001, 16, 64, 32, "f32", 3, 22),
+    ("f32_nl5_m64", "nonlinear5", 2500, 64, 64, 32, "f32", 3, 23),
+    ("f32_s3_m128_k128", "sphere3", 2049, 128, 128, 32, "f32", 3, 24),
+    ("bf16x3_gmm_m16", "gmm", 3001, 16, 64, 32, "bf16", 3, 25),
+    ("bf16x3_nl5_m64", "nonlinear5", 2500, 64, 64, 32, "bf16", 3, 26),
+    ("bf16x3_s3_m128_k128", "sphere3", 2049, 128, 128, 32, "bf16", 3, 27),
+    ("bf16x6_gmm_m16", "gmm", 3001, 16, 64, 32, "bf16", 6, 28),
+    ("bf16x6_nl5_m40", "gauss", 1100, 40, 20, 16, "bf16", 6, 29),
+    ("bf16x1_nl5_m64", "nonlinear5", 1200, 64, 32, 32, "bf16", 1, 30),
+    ("bf16x3_tiny_n33", "gauss", 33, 20, 9, 4, "bf16", 3, 31),
+    ("bf16x3_k1", "gauss", 100, 16, 1, 0, "bf16", 3, 32),
+]
+
+
+@pytest.mark.parametrize("name,kind,n,m,k,margin,mode,split,seed", MFMA_CASES, ids=[c[0] for c in MFMA_CASES])
+def test_knn_matrix_core_tiles(gpu_lib, name, kind, n, m, k, margin, mode, split, seed):
+    from paper_2104_15124_amd import kvb
+    say(f"[knn-mfma] {name}: n={n} m={m} k={k} margin={margin} mode={mode} split={split}")
+    X = _gen(kind, n, m, seed)
+    ctx = kvb.Context()
+    ctx.set_option(kvb.OPT_BF16_SPLIT, split)
+    gi, gd, fl = run_knn(gpu_lib, X, k, margin, mode=mode, ctx=ctx)
+    nfb = kvb.knn_fallback_rows(ctx)
+    ctx.close()
+    ri, rd = knn_reference(X, k)
+    ties = check_knn_rows(gi, gd, ri, rd, k, np.arange(n))
+    say(f"[knn-mfma] {name}: ok, near-tie rows {ties}, fallback rows {nfb} of {n}")
+    if split >= 3 and kind != "gauss":
+        assert nfb <= n // 20, "the split-BF16 error bound should certify almost every row"
+
+
+def test_knn_bf16_lattice_and_duplicates(gpu_lib):
+    from paper_2104_15124_amd import kvb
+    say("[knn-mfma] lattice in R^16 and duplicates, BF16")
+    Z = workloads.cubic_lattice(7)
+    X = np.zeros((len(Z), 16), dtype=np.float32)
+    X[:, :3] = Z
+    gi, gd, fl = run_knn(gpu_lib, X, 19, 8, mode="bf16")
+    ri, rd = oracle.knn(X, 19)
+    np.testing.assert_array_equal(gi, ri)
+    rng = np.random.default_rng(3)
+    base = rng.standard_normal((50, 24)).astype(np.float32)
+    D = np.ascontiguousarray(np.repeat(base, 4, axis=0)[rng.permutation(200)])
+    gi, gd, fl = run_knn(gpu_lib, D, 10, 4, mode="bf16")
+    ri, rd = oracle.knn(D, 10)
+    np.testing.assert_array_equal(gi, ri)
+
+
+def test_knn_nonlinear5_n1m_sampled_rows(gpu_lib):
+    """The BF16 workload at full size (n = 1e6, m = 64, k = 64, margin 32),
+    timed launch configuration; 256 sampled rows checked against the oracle,
+    all rows checked for the row invariants."""
+    from paper_2104_15124_amd import kvb
+    w = workloads.WORKLOADS["nonlinear5_n1m"]
+    say(f"[knn-mfma] {w.name}: n={w.n} m={w.m} k={w.k} (sampled oracle rows)")
+    X = workloads.make(w.name, seed=0)
+    ctx = kvb.Context()
+    gi, gd, fl = run_knn(gpu_lib, X, w.k, w.margin, mode="bf16", ctx=ctx)
+    nfb = kvb.knn_fallback_rows(ctx)
+    ctx.close()
+    say(f"[knn-mfma] {w.name}: fallback rows {nfb}")
+    assert (gi[:, 0] == np.arange(w.n)).all()
+    assert (np.diff(gd, axis=1) >= 0).all()
+    rows = np.random.default_rng(7).choice(w.n, 256, replace=False)
+    ri, rd = knn_reference(X, w.k, rows=rows)
+    check_knn_rows(gi[rows], gd[rows], ri, rd, w.k, rows)
+    assert nfb <= w.n // 100
