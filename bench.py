@@ -34,6 +34,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="torus_n100k")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--n", type=int, default=0,
+                    help="sample count override (same recipe, for profiling runs; not a bench line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
@@ -61,8 +63,11 @@ def main() -> int:
     from paper_2104_15124_amd import kvb
 
     w = workloads.WORKLOADS[args.workload]
+    if args.n:
+        import dataclasses
+        w = dataclasses.replace(w, n=args.n)
     log(f"bench: workload {w.name} n={w.n} m={w.m} k={w.k} mode={w.mode} margin={w.margin}")
-    X = workloads.make(w.name, seed=args.seed)
+    X = workloads.make(w.name, seed=args.seed, n=w.n)
     torch.cuda.set_device(0)
     Xd = torch.from_numpy(X).cuda()
     ctx = kvb.context()

@@ -14,11 +14,12 @@
 // three BF16 terms. In FP32 mode the operands are y itself.
 //
 // Tiles are 32 queries x 32 candidates (v_mfma_f32_32x32x16_bf16 or
-// v_mfma_f32_32x32x2_f32, FP32 accumulation). A workgroup of four wavefronts
-// stages 32 or 64 candidates at a time in LDS with asynchronous global->LDS
-// loads (double-buffered, so the next stage streams in while the current one
-// is consumed); every wavefront keeps its query fragments in registers. Scores at or below a query's threshold are appended
-// to that query's 64-entry LDS buffer; a buffer past half full is merged into
+// v_mfma_f32_32x32x2_f32, FP32 accumulation). A workgroup of four or eight
+// wavefronts stages 32 candidates at a time in LDS (two stages; the next tile
+// is prefetched into registers while the current one is consumed); every
+// wavefront keeps its query fragments in registers and loads a stage's
+// candidate fragments in one batch before the MFMA chain. Scores at or below a query's threshold are appended
+// to that query's LDS buffer; a buffer that may not absorb another tile is merged into
 // the query's sorted list (in global scratch) by the wavefront bitonic merge,
 // which lowers the threshold.
 //
@@ -39,6 +40,7 @@ namespace kvb {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ prep
 // Column sums (float64) over blocks of rows, then the fixed-order mean.
@@ -182,11 +184,6 @@ struct TraitsBF16 {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
     }
     __device__ static __forceinline__ frag load(const elem* p) { return *reinterpret_cast<const frag*>(p); }
-    // each lane copies one 16-byte fragment; LDS destination = base + lane * 16
-    __device__ static __forceinline__ void async_copy(const elem* g, frag* lds_base)
-    {
-        __builtin_amdgcn_global_load_lds((const void*)g, (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
-    }
 };
 
 struct TraitsF32 {
@@ -199,60 +196,70 @@ struct TraitsF32 {
         return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
     }
     __device__ static __forceinline__ frag load(const elem* p) { return *p; }
-    // each lane copies one 4-byte fragment; LDS destination = base + lane * 4
-    __device__ static __forceinline__ void async_copy(const elem* g, frag* lds_base)
-    {
-        __builtin_amdgcn_global_load_lds((const void*)g, (__attribute__((address_space(3))) void*)lds_base, 4, 0, 0);
-    }
 };
-
-constexpr int SEL_WAVES = 4;
-constexpr int SEL_BUF = 64;   // per-query LDS buffer entries
 
 // Output row (query) of accumulator register r in lane half h of a 32x32 tile.
 __host__ __device__ constexpr int acc_row(int r, int h) { return 8 * (r / 4) + 4 * h + (r % 4); }
 
-template <class Tr, int KS, int QT, int TW, int E>
-__global__ __launch_bounds__(256) void k_select_mfma(const typename Tr::elem* __restrict__ Aq,
-                                                     const typename Tr::elem* __restrict__ Bc, int n, int kp,
-                                                     const float* __restrict__ ynorm2,
-                                                     const unsigned* __restrict__ rmax_bits, ErrModel em,
-                                                     uint64_t* __restrict__ lists, float* __restrict__ lb_out)
+// Merge query q's LDS buffer into its sorted list in global scratch and return
+// the list's kp-th score (the query's new threshold). Whole wavefront.
+template <int E>
+__device__ __noinline__ float merge_query_list(uint64_t* __restrict__ dst, const uint64_t* buf, int cnt, int kp)
+{
+    const int lane = lane_id();
+    const uint64_t b = lane < cnt ? buf[lane] : KEY_INF;
+    uint64_t L[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) L[s] = dst[s * WAVE + lane];
+    merge_into_list<E>(L, b);
+#pragma unroll
+    for (int s = 0; s < E; ++s) dst[s * WAVE + lane] = L[s];
+    return key_dist(list_at<E>(L, kp - 1));
+}
+
+// WV wavefronts per workgroup share every candidate stage; each wavefront owns
+// 32 queries. Per-query LDS buffers hold BUF keys and are merged once they
+// pass BUF - 32 (a 32-candidate tile adds at most 32 per query).
+template <class Tr, int KS, int WV, int E>
+__global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem* __restrict__ Aq,
+                                                          const typename Tr::elem* __restrict__ Bc, int n, int kp,
+                                                          const float* __restrict__ ynorm2,
+                                                          const unsigned* __restrict__ rmax_bits, ErrModel em,
+                                                          uint64_t* __restrict__ lists, float* __restrict__ lb_out)
 {
     using elem = typename Tr::elem;
     using frag = typename Tr::frag;
     constexpr int CAP = WAVE * E;
-    constexpr int KSMAX = KS;
     constexpr int kpad = KS * Tr::KSTEP;        // padded contraction length
-    constexpr int ks = KS;
-    constexpr int NQ = 32 * QT;                 // queries per wavefront
-    constexpr int NSUB = TW / 32;               // 32-candidate sub-tiles per stage
-    // candidate tiles, fragment-major: [stage][sub][k-step][half][row] so that
-    // lane l reads consecutive fragments (no bank conflicts); two stages
-    // alternate between async global->LDS loads and MFMA consumption
-    __shared__ frag s_tile[2][NSUB][KSMAX][2][32];
-    __shared__ uint64_t s_buf[SEL_WAVES][NQ][SEL_BUF];
-    __shared__ int s_cnt[SEL_WAVES][NQ];
+    constexpr int NQ = 32;                      // queries per wavefront
+    constexpr int BUF = WV == 8 ? 48 : 64;      // per-query LDS buffer entries
+    constexpr int FLUSH_AT = BUF - 32;
+    // two candidate stages, fragment-major: [stage][k-step][half][row] so that
+    // lane l reads consecutive fragments (no bank conflicts). The next tile is
+    // prefetched into registers while the current one is consumed.
+    constexpr int STAGE_BYTES = KS * 64 * static_cast<int>(sizeof(frag));
+    constexpr int CHUNKS = STAGE_BYTES / 16;                 // 16-byte pieces per tile
+    constexpr int PF = (CHUNKS + 64 * WV - 1) / (64 * WV);  // pieces per thread
+    __shared__ __attribute__((aligned(16))) frag s_tile[2][KS][2][32];
+    __shared__ uint64_t s_buf[WV][NQ][BUF];
+    __shared__ int s_cnt[WV][NQ];
 
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int half = lane >> 5;
-    const int q0 = (blockIdx.x * SEL_WAVES + wave) * NQ;
+    const int q0 = (blockIdx.x * WV + wave) * NQ;
 
-    frag qa[QT][KSMAX];
-#pragma unroll
-    for (int qt = 0; qt < QT; ++qt) {
-        const int row = min(q0 + qt * 32 + (lane & 31), n - 1);
+    frag qa[KS];
+    {
+        const int row = min(q0 + (lane & 31), n - 1);
         const elem* src = Aq + static_cast<size_t>(row) * kpad + half * Tr::VEC;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) qa[qt][s] = Tr::load(src + s * Tr::KSTEP);
+        for (int s = 0; s < KS; ++s) qa[s] = Tr::load(src + s * Tr::KSTEP);
     }
-    float tauv[QT][16];
+    float tauv[16];
 #pragma unroll
-    for (int qt = 0; qt < QT; ++qt)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) tauv[qt][r] = __uint_as_float(0x7F800000u);
-    for (int q = lane; q < NQ; q += WAVE) s_cnt[wave][q] = 0;
+    for (int r = 0; r < 16; ++r) tauv[r] = __uint_as_float(0x7F800000u);
+    if (lane < NQ) s_cnt[wave][lane] = 0;
     for (int q = 0; q < NQ; ++q) {
         const int qg = q0 + q;
         if (qg < n)
@@ -260,130 +267,122 @@ __global__ __launch_bounds__(256) void k_select_mfma(const typename Tr::elem* __
     }
     wave_lds_sync();
 
-    // one async load instruction moves the 64 fragments (2 halves x 32 rows)
-    // of one k-step of one sub-tile: a contiguous block of the tile-major
-    // candidate operand; the four wavefronts share the work. Tiles past the
-    // padded end are skipped (their candidates are masked out).
+    // a tile of the tile-major candidate operand is one contiguous block, laid
+    // out exactly like an LDS stage: it moves as 16-byte pieces
     const int ntiles = (n + 31) / 32;
-    auto issue = [&](int stage, int c0) {
-        for (int j = wave; j < NSUB * ks; j += SEL_WAVES) {
-            const int sub = j / ks, s = j % ks;
-            const int tile = c0 / 32 + sub;
-            if (tile >= ntiles) continue;
-            const elem* g = Bc + static_cast<size_t>(tile) * 32 * kpad + (s * 64 + lane) * Tr::VEC;
-            Tr::async_copy(g, &s_tile[stage][sub][s][0][0]);
+    // the query fragments have landed before the loop, so the only vector
+    // loads in flight inside it are the next tile's prefetch
+    __builtin_amdgcn_s_waitcnt(0);
+    u32x4 pf[PF];
+    {
+        const u32x4* g = reinterpret_cast<const u32x4*>(Bc);
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int ch = threadIdx.x + u * 64 * WV;
+            if (ch < CHUNKS) pf[u] = g[ch];
         }
-    };
-
-    uint64_t nonempty = 0;   // queries with buffered entries (wave-uniform)
-    auto merge_query = [&](int q) {
-        const int qg = q0 + q;
-        const int c = s_cnt[wave][q];
-        uint64_t b = lane < c ? s_buf[wave][q][lane] : KEY_INF;
-        float nt = __uint_as_float(0x7F800000u);
-        if (qg < n) {
-            uint64_t L[E];
-            uint64_t* dst = lists + static_cast<size_t>(qg) * CAP;
+    }
+    uint32_t nonempty = 0;   // queries with buffered entries (wave-uniform)
+    for (int tile = 0; tile < ntiles; ++tile) {
+        const int stage = tile & 1;
+        {
+            u32x4* d = reinterpret_cast<u32x4*>(&s_tile[stage][0][0][0]);
 #pragma unroll
-            for (int s = 0; s < E; ++s) L[s] = dst[s * WAVE + lane];
-            merge_into_list<E>(L, b);
-#pragma unroll
-            for (int s = 0; s < E; ++s) dst[s * WAVE + lane] = L[s];
-            nt = key_dist(list_at<E>(L, kp - 1));
+            for (int u = 0; u < PF; ++u) {
+                const int ch = threadIdx.x + u * 64 * WV;
+                if (ch < CHUNKS) d[ch] = pf[u];
+            }
         }
-        if (lane == 0) s_cnt[wave][q] = 0;
-        // the query's threshold sits in one accumulator slot of one lane half
-        const int qt = q / 32, mrow = q % 32;
-        const int rr = 4 * (mrow / 8) + (mrow % 4), hh = (mrow / 4) & 1;
+        __syncthreads();                 // stage visible; the other stage's readers finished a tile ago
+        if (tile + 1 < ntiles) {
+            const u32x4* g = reinterpret_cast<const u32x4*>(Bc + static_cast<size_t>(tile + 1) * 32 * kpad);
 #pragma unroll
-        for (int t = 0; t < QT; ++t)
+            for (int u = 0; u < PF; ++u) {
+                const int ch = threadIdx.x + u * 64 * WV;
+                if (ch < CHUNKS) pf[u] = g[ch];
+            }
+        }
+        frag bfr[KS];
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if (t == qt && r == rr && half == hh) tauv[t][r] = nt;
-    };
-
-    issue(0, 0);
-    int stage = 0;
-    for (int c0 = 0; c0 < n; c0 += TW, stage ^= 1) {
-        __builtin_amdgcn_s_waitcnt(0);   // this wavefront's loads of the current stage have landed
-        __syncthreads();                 // ... and every other wavefront's; the other stage is free
-        if (c0 + TW < n) issue(stage ^ 1, c0 + TW);
-        f32x16 acc[NSUB][QT];
+        for (int s = 0; s < KS; ++s) bfr[s] = s_tile[stage][s][half][lane & 31];
+        f32x16 acc;
         const f32x16 zero = {};
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
+        for (int s = 0; s < KS; ++s) acc = Tr::mma(qa[s], bfr[s], s == 0 ? zero : acc);
+
+        const int cand = tile * 32 + (lane & 31);
+        const bool valid = cand < n;
+        uint32_t flush = 0;
 #pragma unroll
-            for (int sub = 0; sub < NSUB; ++sub) {
-                const frag b = s_tile[stage][sub][s][half][lane & 31];
-#pragma unroll
-                for (int qt = 0; qt < QT; ++qt) acc[sub][qt] = Tr::mma(qa[qt][s], b, s == 0 ? zero : acc[sub][qt]);
+        for (int r = 0; r < 16; ++r) {
+            const float sc = acc[r];
+            const uint64_t mask = __ballot(valid && sc <= tauv[r]);
+            if (mask) {
+                const int qa_ = acc_row(r, 0), qb_ = acc_row(r, 1);
+                const uint32_t ma = static_cast<uint32_t>(mask), mb = static_cast<uint32_t>(mask >> 32);
+                const int ca = ma ? s_cnt[wave][qa_] : 0;
+                const int cb = mb ? s_cnt[wave][qb_] : 0;
+                const uint32_t hm = half ? mb : ma;
+                const int l31 = lane & 31;
+                if ((hm >> l31) & 1u) {
+                    const int pos = (half ? cb : ca) + __popc(hm & ((1u << l31) - 1u));
+                    s_buf[wave][half ? qb_ : qa_][pos] = make_key(sc, static_cast<uint32_t>(cand));
+                }
+                const int na = ca + __popc(ma), nb = cb + __popc(mb);
+                if (lane == 0 && ma) s_cnt[wave][qa_] = na;
+                if (lane == 32 && mb) s_cnt[wave][qb_] = nb;
+                if (ma) nonempty |= 1u << qa_;
+                if (mb) nonempty |= 1u << qb_;
+                if (na > FLUSH_AT) flush |= 1u << qa_;
+                if (nb > FLUSH_AT) flush |= 1u << qb_;
             }
         }
+        if (flush) {
+            wave_lds_sync();
+            while (flush) {
+                const int q = __builtin_ctz(flush);
+                flush &= flush - 1;
+                nonempty &= ~(1u << q);
+                const int qg = q0 + q;
+                float nt = __uint_as_float(0x7F800000u);
+                if (qg < n)
+                    nt = merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][q][0],
+                                             s_cnt[wave][q], kp);
+                if (lane == 0) s_cnt[wave][q] = 0;
+                // the query's threshold sits in one accumulator slot of one lane half
+                const int rr = 4 * (q / 8) + (q % 4), hh = (q / 4) & 1;
 #pragma unroll
-        for (int sub = 0; sub < NSUB; ++sub) {
-            const int cand = c0 + sub * 32 + (lane & 31);
-            const bool valid = cand < n;
-            uint64_t flush = 0;
-#pragma unroll
-            for (int qt = 0; qt < QT; ++qt) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const float sc = acc[sub][qt][r];
-                    const uint64_t mask = __ballot(valid && sc <= tauv[qt][r]);
-                    if (mask) {
-                        const int qa_ = qt * 32 + acc_row(r, 0), qb_ = qt * 32 + acc_row(r, 1);
-                        const uint32_t ma = static_cast<uint32_t>(mask), mb = static_cast<uint32_t>(mask >> 32);
-                        const int ca = ma ? s_cnt[wave][qa_] : 0;
-                        const int cb = mb ? s_cnt[wave][qb_] : 0;
-                        const uint32_t hm = half ? mb : ma;
-                        const int l31 = lane & 31;
-                        if ((hm >> l31) & 1u) {
-                            const int pos = (half ? cb : ca) + __popc(hm & ((1u << l31) - 1u));
-                            s_buf[wave][half ? qb_ : qa_][pos] = make_key(sc, static_cast<uint32_t>(cand));
-                        }
-                        const int na = ca + __popc(ma), nb = cb + __popc(mb);
-                        if (lane == 0 && ma) s_cnt[wave][qa_] = na;
-                        if (lane == 32 && mb) s_cnt[wave][qb_] = nb;
-                        if (ma) nonempty |= 1ull << qa_;
-                        if (mb) nonempty |= 1ull << qb_;
-                        if (na > SEL_BUF / 2) flush |= 1ull << qa_;
-                        if (nb > SEL_BUF / 2) flush |= 1ull << qb_;
-                    }
-                }
-            }
-            if (flush) {
+                for (int r = 0; r < 16; ++r)
+                    if (r == rr && half == hh) tauv[r] = nt;
                 wave_lds_sync();
-                while (flush) {
-                    const int q = __builtin_ctzll(flush);
-                    flush &= flush - 1;
-                    merge_query(q);
-                    nonempty &= ~(1ull << q);
-                    wave_lds_sync();
-                }
             }
         }
     }
     wave_lds_sync();
     while (nonempty) {
-        const int q = __builtin_ctzll(nonempty);
+        const int q = __builtin_ctz(nonempty);
         nonempty &= nonempty - 1;
-        merge_query(q);
+        const int qg = q0 + q;
+        if (qg < n)
+            merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][q][0], s_cnt[wave][q], kp);
         wave_lds_sync();
     }
     // certificate lower bound for the candidates left out of each list
     const double R = static_cast<double>(__uint_as_float(*rmax_bits));
-    for (int q = lane; q < NQ; q += WAVE) {
-        const int qg = q0 + q;
-        if (qg >= n) continue;
-        const float sl = key_dist(lists[static_cast<size_t>(qg) * CAP + (kp - 1)]);
-        const double yi2 = static_cast<double>(ynorm2[qg]);
-        const double yi = sqrt(yi2);
-        const double Ei = em.gamma * (R + 1.05 * yi) * (R + 1.05 * yi) + em.norm * R * R + em.cross * yi * R + 1e-30;
-        const double t = static_cast<double>(sl) + yi2 - Ei;
-        double D = t > 0.0 ? sqrt(t) : 0.0;
-        D -= em.center * (yi + R);
-        D = D > 0.0 ? D : 0.0;
-        lb_out[qg] = static_cast<float>(D * D * (1.0 - 1.0 / 1048576.0));
+    if (lane < NQ) {
+        const int qg = q0 + lane;
+        if (qg < n) {
+            const float sl = key_dist(lists[static_cast<size_t>(qg) * CAP + (kp - 1)]);
+            const double yi2 = static_cast<double>(ynorm2[qg]);
+            const double yi = sqrt(yi2);
+            const double Ei =
+                em.gamma * (R + 1.05 * yi) * (R + 1.05 * yi) + em.norm * R * R + em.cross * yi * R + 1e-30;
+            const double t = static_cast<double>(sl) + yi2 - Ei;
+            double D = t > 0.0 ? sqrt(t) : 0.0;
+            D -= em.center * (yi + R);
+            D = D > 0.0 ? D : 0.0;
+            lb_out[qg] = static_cast<float>(D * D * (1.0 - 1.0 / 1048576.0));
+        }
     }
 }
 
@@ -400,31 +399,29 @@ hipError_t launch_prep(const float* X, int n, int m, int split, int kpad, double
     return hipGetLastError();
 }
 
-template <class Tr, int KS, int QT, int TW>
+template <class Tr, int KS, int WV>
 static hipError_t launch_sel(const void* Aq, const void* Bc, int n, int kp, const float* ynorm2, const unsigned* rmax,
                              ErrModel em, uint64_t* lists, int cap, float* lb, hipStream_t st)
 {
     using elem = typename Tr::elem;
-    const int rows_per_block = SEL_WAVES * 32 * QT;
-    const dim3 grid((n + rows_per_block - 1) / rows_per_block), block(256);
+    const int rows_per_block = WV * 32;
+    const dim3 grid((n + rows_per_block - 1) / rows_per_block), block(64 * WV);
     const elem* A = static_cast<const elem*>(Aq);
     const elem* B = static_cast<const elem*>(Bc);
     // the lists buffer holds n * cap keys; only capacities 128 and 256 exist
     if (kp > cap) return hipErrorInvalidValue;
     if (cap == 128)
-        hipLaunchKernelGGL((k_select_mfma<Tr, KS, QT, TW, 2>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em, lists,
-                           lb);
+        hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em, lists, lb);
     else if (cap == 256)
-        hipLaunchKernelGGL((k_select_mfma<Tr, KS, QT, TW, 4>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em, lists,
-                           lb);
+        hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em, lists, lb);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 // Instantiated contraction lengths (in MFMA K-steps); the operand K is padded
-// with zeros up to the next one. QT (query tiles per wavefront) and TW
-// (candidates per LDS stage) are chosen so that registers and LDS fit.
+// with zeros up to the next one. WV (wavefronts per workgroup) is 8 where the
+// two LDS stages and the query buffers fit in LDS, else 4.
 static const int kBf16Steps[] = {2, 3, 4, 5, 6, 7, 8, 10, 13, 16, 20, 25, 32};
 static const int kF32Steps[] = {2, 4, 6, 8, 10, 12, 16, 24, 32, 48, 64, 96, 128};
 
@@ -440,8 +437,8 @@ int mfma_pick_ksteps(int split, int needed)
     return -1;
 }
 
-#define KVB_SEL_CASE(TR, K, QT, TW) \
-    case K: return launch_sel<TR, K, QT, TW>(Aq, Bc, n, kp, ynorm2, rmax, em, lists, cap, lb, st);
+#define KVB_SEL_CASE(TR, K, WV) \
+    case K: return launch_sel<TR, K, WV>(Aq, Bc, n, kp, ynorm2, rmax, em, lists, cap, lb, st);
 
 hipError_t launch_select_mfma(int split, const void* Aq, const void* Bc, int n, int kpad, int kp, const float* ynorm2,
                               const unsigned* rmax, ErrModel em, uint64_t* lists, int cap, float* lb, hipStream_t st)
@@ -449,36 +446,36 @@ hipError_t launch_select_mfma(int split, const void* Aq, const void* Bc, int n, 
     const int ks = kpad / mfma_kstep(split);
     if (split == 0) {
         switch (ks) {
-            KVB_SEL_CASE(TraitsF32, 2, 2, 64)
-            KVB_SEL_CASE(TraitsF32, 4, 2, 64)
-            KVB_SEL_CASE(TraitsF32, 6, 2, 64)
-            KVB_SEL_CASE(TraitsF32, 8, 2, 32)
-            KVB_SEL_CASE(TraitsF32, 10, 2, 32)
-            KVB_SEL_CASE(TraitsF32, 12, 2, 32)
-            KVB_SEL_CASE(TraitsF32, 16, 2, 32)
-            KVB_SEL_CASE(TraitsF32, 24, 2, 32)
-            KVB_SEL_CASE(TraitsF32, 32, 2, 32)
-            KVB_SEL_CASE(TraitsF32, 48, 1, 64)
-            KVB_SEL_CASE(TraitsF32, 64, 1, 64)
-            KVB_SEL_CASE(TraitsF32, 96, 1, 32)
-            KVB_SEL_CASE(TraitsF32, 128, 1, 32)
+            KVB_SEL_CASE(TraitsF32, 2, 8)
+            KVB_SEL_CASE(TraitsF32, 4, 8)
+            KVB_SEL_CASE(TraitsF32, 6, 8)
+            KVB_SEL_CASE(TraitsF32, 8, 8)
+            KVB_SEL_CASE(TraitsF32, 10, 8)
+            KVB_SEL_CASE(TraitsF32, 12, 8)
+            KVB_SEL_CASE(TraitsF32, 16, 8)
+            KVB_SEL_CASE(TraitsF32, 24, 8)
+            KVB_SEL_CASE(TraitsF32, 32, 8)
+            KVB_SEL_CASE(TraitsF32, 48, 8)
+            KVB_SEL_CASE(TraitsF32, 64, 4)
+            KVB_SEL_CASE(TraitsF32, 96, 4)
+            KVB_SEL_CASE(TraitsF32, 128, 4)
         default: return hipErrorInvalidValue;
         }
     }
     switch (ks) {
-        KVB_SEL_CASE(TraitsBF16, 2, 2, 32)
-        KVB_SEL_CASE(TraitsBF16, 3, 2, 32)
-        KVB_SEL_CASE(TraitsBF16, 4, 2, 32)
-        KVB_SEL_CASE(TraitsBF16, 5, 2, 32)
-        KVB_SEL_CASE(TraitsBF16, 6, 2, 32)
-        KVB_SEL_CASE(TraitsBF16, 7, 2, 32)
-        KVB_SEL_CASE(TraitsBF16, 8, 2, 32)
-        KVB_SEL_CASE(TraitsBF16, 10, 1, 64)
-        KVB_SEL_CASE(TraitsBF16, 13, 1, 64)
-        KVB_SEL_CASE(TraitsBF16, 16, 1, 64)
-        KVB_SEL_CASE(TraitsBF16, 20, 1, 32)
-        KVB_SEL_CASE(TraitsBF16, 25, 1, 32)
-        KVB_SEL_CASE(TraitsBF16, 32, 1, 32)
+        KVB_SEL_CASE(TraitsBF16, 2, 8)
+        KVB_SEL_CASE(TraitsBF16, 3, 8)
+        KVB_SEL_CASE(TraitsBF16, 4, 8)
+        KVB_SEL_CASE(TraitsBF16, 5, 8)
+        KVB_SEL_CASE(TraitsBF16, 6, 8)
+        KVB_SEL_CASE(TraitsBF16, 7, 8)
+        KVB_SEL_CASE(TraitsBF16, 8, 8)
+        KVB_SEL_CASE(TraitsBF16, 10, 8)
+        KVB_SEL_CASE(TraitsBF16, 13, 8)
+        KVB_SEL_CASE(TraitsBF16, 16, 8)
+        KVB_SEL_CASE(TraitsBF16, 20, 8)
+        KVB_SEL_CASE(TraitsBF16, 25, 8)
+        KVB_SEL_CASE(TraitsBF16, 32, 4)
     default: return hipErrorInvalidValue;
     }
 }
