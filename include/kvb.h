@@ -189,6 +189,84 @@ int kvb_assemble_csr(kvb_ctx ctx, const int32_t* idx, const float* d2, const flo
                      int64_t n, int32_t k, double e, double alpha, double d, int32_t out_kind,
                      int64_t* rowptr, int32_t* col, float* val, double* P, double* D);
 
+/*
+ * ---- learned partitioner (k-NN over routed candidate buckets) ----
+ * A small MLP m -> h1 -> h2 -> n_buckets (ReLU, BF16 weights and activations,
+ * FP32 accumulation) is trained on the GPU to predict, for a sample, which
+ * buckets of a balanced partition its exact k nearest neighbours fall in
+ * (the neighbour-histogram targets of Neural LSH, Dong et al., ICLR 2020).
+ * kvb_knn(mode = KVB_KNN_LEARNED) then stores every sample in its top-1
+ * bucket, sends every query to its top-n_probe buckets and searches only
+ * those buckets' candidates with the matrix-core distance tiles. Results are
+ * exact within the probed buckets (exact re-rank and FP64 boundary decision)
+ * but carry no global certificate: rows are flagged KVB_ROW_UNCERTIFIED, and
+ * recall against an exact search is the caller's measure of quality. A row
+ * whose probed buckets hold fewer than k - 1 other samples takes the exact
+ * fallback. One partitioner lives in a context; it is freed by kvb_destroy.
+ * All array arguments are device pointers; *_host arguments are host memory.
+ */
+
+/* Create the partitioner's parameters from a seed: weights ~ N(0, 2/fan_in)
+ * (Box-Muller over a SplitMix64 counter stream), zero biases, zero Adam
+ * state. 1 <= m <= 1024; h1, h2, n_buckets multiples of 32 in [32, 4096];
+ * 1 <= n_probe <= min(32, n_buckets). Errors: KVB_E_INVALID, KVB_E_NOMEM. */
+int kvb_part_init(kvb_ctx ctx, int32_t m, int32_t h1, int32_t h2, int32_t n_buckets, int32_t n_probe,
+                  uint64_t seed);
+
+/* Teacher partition of the ns samples Xs [ns, m] float32: `levels` rounds of
+ * median splits; in round l every current node is projected on its own
+ * seeded random direction (components uniform in [-1, 1), SplitMix64 at
+ * counter l << 40 | node << 20 | c), samples are ordered by (float32 of the
+ * float64 projection, index), and the lower floor(size/2) form child 2v, the
+ * rest child 2v + 1. labels [ns] int32 out, in [0, 2^levels).
+ * 1 <= levels <= 12; 2^levels <= ns < 2^31. */
+int kvb_part_teacher(kvb_ctx ctx, const float* Xs, int64_t ns, int32_t m, int32_t levels, uint64_t seed,
+                     int32_t* labels);
+
+/* Train the MLP with Adam (beta1 0.9, beta2 0.999, eps 1e-8, learning rate
+ * lr) on soft targets: for training row i the target over buckets is the
+ * histogram of labels[idx_s[i, r]], r = 0..ks-1 (its exact k-NN rows, as
+ * written by kvb_knn), divided by ks; the loss is the batch-mean softmax
+ * cross-entropy. Each epoch visits floor(ns / batch) batches of `batch` rows
+ * (multiple of 32) in the order of a seeded affine permutation
+ * t -> (a t + c) mod ns. loss_host [epochs] (or NULL) receives each epoch's
+ * mean loss. Synchronises the context stream. Requires m == the partitioner's m. */
+int kvb_part_train(kvb_ctx ctx, const float* Xs, int64_t ns, int32_t m, const int32_t* labels,
+                   const int32_t* idx_s, int32_t ks, int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                   float* loss_host);
+
+/* Routing of X [n, m]: home [n] (or NULL) = first argmax of the logits (the
+ * storage bucket), probe [n, n_probe] = the n_probe largest logits in
+ * descending order, ties to the smaller bucket id (probe[i, 0] == home[i]). */
+int kvb_part_route(kvb_ctx ctx, const float* X, int64_t n, int32_t* home, int32_t* probe);
+
+/* Save / load the partitioner (dimensions, weights, Adam state) to / from a
+ * file (host path). Errors: KVB_E_IO. */
+int kvb_part_save(kvb_ctx ctx, const char* path);
+int kvb_part_load(kvb_ctx ctx, const char* path);
+
+/* Test hooks. kvb_mlp_forward: logits [B, n_buckets] float32 of X [B, m].
+ * kvb_mlp_backward: for X [B, m] and nbr_labels [B, ks] (bucket label of
+ * each neighbour of each row), the batch-mean soft-target cross-entropy
+ * (loss_host, may be NULL) and the gradient of every parameter in grads
+ * [num_params] float32 (order W1, b1, W2, b2, W3, b3, weights row-major
+ * [out, in]). Casts to BF16: the input rows, the weights, the ReLU outputs,
+ * and the back-propagated logit and hidden gradients before each product.
+ * B a multiple of 32 in [32, 65536]. Parameters are not updated. */
+int kvb_mlp_forward(kvb_ctx ctx, const float* X, int64_t B, float* logits);
+int kvb_mlp_backward(kvb_ctx ctx, const float* X, int64_t B, const int32_t* nbr_labels, int32_t ks,
+                     float* loss_host, float* grads);
+
+/* Number of parameters of the current partitioner (floats in grads), or < 0. */
+int64_t kvb_part_num_params(kvb_ctx ctx);
+
+/* Copy the FP32 master parameters (order of grads) to params [num_params]. */
+int kvb_part_get_params(kvb_ctx ctx, float* params);
+
+/* Replace the parameters by params [num_params] (order of grads) and reset
+ * the Adam state. */
+int kvb_part_set_params(kvb_ctx ctx, const float* params);
+
 /* Library identification string (static storage). */
 const char* kvb_version(void);
 
@@ -204,7 +282,9 @@ const char* kvb_version(void);
 #define KVB_PROF_QPASS 7         /* q pass */
 #define KVB_PROF_ASSEMBLE 8      /* Kt, D, output kind, per-row column sort, CSR write */
 #define KVB_PROF_KNN_PREP 9      /* centring and operand layout for the matrix-core distance tiles */
-#define KVB_PROF_SLOTS 10
+#define KVB_PROF_ROUTE 10        /* learned mode: MLP logits and top-n_probe routing */
+#define KVB_PROF_BUCKETS 11      /* learned mode: bucket sort, candidate operand gather, work lists */
+#define KVB_PROF_SLOTS 12
 
 /* Turn event timing on (on != 0) or off; either way the totals restart at 0. */
 int kvb_profile_enable(kvb_ctx ctx, int32_t on);

@@ -1,6 +1,8 @@
 // C ABI of libkvb.so: contexts, argument validation, scratch management and
 // the launch sequence of each entry point. The numerical work of every entry
-// point runs in the kernels of knn_kernels.hip and pass_kernels.hip.
+// point runs in the kernels of knn_kernels.hip, knn_mfma.hip and
+// pass_kernels.hip; the learned partitioner's entry points are in
+// learned_api.hip.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -10,163 +12,17 @@
 #include <string>
 #include <vector>
 
-#include "kvb_kernels.h"
+#include "kvb_ctx.h"
 
 namespace {
 const char* const kProfNames[KVB_PROF_SLOTS] = {
     "knn_select", "knn_refine", "knn_fallback", "adhoc_bandwidth", "chi_tuning", "density",
     "grid_scale", "q_pass", "assemble", "knn_prep",
-};
-struct ProfPair {
-    int slot;
-    hipEvent_t a, b;
+    "route", "bucket_build",
 };
 }  // namespace
 
-struct kvb_ctx_s {
-    hipStream_t stream = nullptr;
-    int device = 0;
-    std::string err;
-    void* scratch = nullptr;
-    size_t scratch_bytes = 0;
-    size_t scratch_limit = 0;
-    int64_t force_fallback = 0;
-    int bf16_split = 3;
-    kvb::TuneResult* tune_dev = nullptr;
-    kvb::TuneResult* tune_host = nullptr;   // pinned
-    int* fb_count_dev = nullptr;            // fallback rows of the last kvb_knn
-    int* fb_count_host = nullptr;           // pinned
-    // instrumentation: HIP events around each kernel launch on the context stream
-    bool prof_on = false;
-    std::vector<hipEvent_t> ev_pool;
-    std::vector<ProfPair> ev_pending;
-    double prof_ms[KVB_PROF_SLOTS] = {};
-    int64_t prof_count[KVB_PROF_SLOTS] = {};
-};
-
-namespace {
-
-int fail(kvb_ctx ctx, int code, const char* fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    if (ctx) ctx->err = buf;
-    return code;
-}
-
-#define KVB_HIP(ctx, call)                                                                     \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return fail((ctx), KVB_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
-    } while (0)
-
-#define KVB_REQUIRE(ctx, cond, ...)                                                            \
-    do {                                                                                       \
-        if (!(cond)) return fail((ctx), KVB_E_INVALID, __VA_ARGS__);                           \
-    } while (0)
-
-template <typename T>
-bool aligned(const T* p)
-{
-    return p != nullptr && (reinterpret_cast<uintptr_t>(p) % alignof(T)) == 0;
-}
-
-// Bump allocator over the context scratch buffer; every region is 256-byte aligned.
-struct Carve {
-    char* base;
-    size_t off = 0;
-    explicit Carve(void* b) : base(static_cast<char*>(b)) {}
-    template <typename T>
-    T* take(size_t count)
-    {
-        off = (off + 255) & ~size_t(255);
-        T* p = reinterpret_cast<T*>(base + off);
-        off += count * sizeof(T);
-        return p;
-    }
-};
-
-size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
-
-int ensure_scratch(kvb_ctx ctx, size_t bytes)
-{
-    if (bytes <= ctx->scratch_bytes) return KVB_OK;
-    if (ctx->scratch_limit && bytes > ctx->scratch_limit)
-        return fail(ctx, KVB_E_NOMEM, "scratch of %zu bytes exceeds the limit of %zu bytes", bytes,
-                    ctx->scratch_limit);
-    KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->scratch) {
-        KVB_HIP(ctx, hipFree(ctx->scratch));
-        ctx->scratch = nullptr;
-        ctx->scratch_bytes = 0;
-    }
-    void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(ctx, KVB_E_NOMEM, "hipMalloc of %zu scratch bytes failed", bytes);
-    }
-    ctx->scratch = p;
-    ctx->scratch_bytes = bytes;
-    return KVB_OK;
-}
-
-int check_ctx(kvb_ctx ctx) { return ctx ? KVB_OK : KVB_E_INVALID; }
-
-hipEvent_t pool_event(kvb_ctx ctx)
-{
-    if (!ctx->ev_pool.empty()) {
-        hipEvent_t e = ctx->ev_pool.back();
-        ctx->ev_pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-// Brackets one launch sequence with events when instrumentation is on.
-struct Prof {
-    kvb_ctx ctx;
-    int slot;
-    hipEvent_t a = nullptr;
-    Prof(kvb_ctx c, int s) : ctx(c), slot(s)
-    {
-        if (ctx->prof_on && (a = pool_event(ctx)) != nullptr) (void)hipEventRecord(a, ctx->stream);
-    }
-    ~Prof()
-    {
-        if (!a) return;
-        hipEvent_t b = pool_event(ctx);
-        if (!b) {
-            ctx->ev_pool.push_back(a);
-            return;
-        }
-        (void)hipEventRecord(b, ctx->stream);
-        ctx->ev_pending.push_back({slot, a, b});
-    }
-};
-
-int prof_collect(kvb_ctx ctx)
-{
-    if (ctx->ev_pending.empty()) return KVB_OK;
-    KVB_HIP(ctx, hipEventSynchronize(ctx->ev_pending.back().b));
-    for (const ProfPair& p : ctx->ev_pending) {
-        float ms = 0.f;
-        KVB_HIP(ctx, hipEventElapsedTime(&ms, p.a, p.b));
-        ctx->prof_ms[p.slot] += ms;
-        ctx->prof_count[p.slot] += 1;
-        ctx->ev_pool.push_back(p.a);
-        ctx->ev_pool.push_back(p.b);
-    }
-    ctx->ev_pending.clear();
-    return KVB_OK;
-}
-
-}  // namespace
+using namespace kvbh;
 
 extern "C" {
 
@@ -209,6 +65,8 @@ void kvb_destroy(kvb_ctx ctx)
     if (ctx->tune_host) (void)hipHostFree(ctx->tune_host);
     if (ctx->fb_count_dev) (void)hipFree(ctx->fb_count_dev);
     if (ctx->fb_count_host) (void)hipHostFree(ctx->fb_count_host);
+    if (ctx->loss_dev) (void)hipFree(ctx->loss_dev);
+    part_free(ctx);
     delete ctx;
 }
 
@@ -251,10 +109,10 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                 "unknown k-NN mode %d", mode);
     if (k + margin > 256) return fail(ctx, KVB_E_UNSUPPORTED, "k + margin = %d exceeds 256", k + margin);
     if (m > 1024) return fail(ctx, KVB_E_UNSUPPORTED, "m = %d exceeds 1024", m);
-    if (mode == KVB_KNN_LEARNED) return fail(ctx, KVB_E_UNSUPPORTED, "k-NN mode %d is not available", mode);
 
     const int nn = static_cast<int>(n);
     const int kp = static_cast<int>(std::min<int64_t>(k + margin, n));
+    if (mode == KVB_KNN_LEARNED) return learned_knn(ctx, X, nn, m, k, kp, idx, d2, row_flags);
     const bool direct = (mode == KVB_KNN_F32 && m <= 8);
     const int split = mode == KVB_KNN_F32 ? 0 : ctx->bf16_split;
     const int cap = kp <= 128 ? 128 : 256;   // list capacities of the matrix-core select kernels
@@ -304,7 +162,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
             Prof pr(ctx, KVB_PROF_KNN_PREP);
             KVB_HIP(ctx, hipMemsetAsync(rmax, 0, sizeof(unsigned), ctx->stream));
             KVB_HIP(ctx, kvb::launch_prep(X, nn, m, split, kpad, colpart, colblocks, mu, Aq, Bc, ynorm2, rmax,
-                                          ctx->stream));
+                                          nullptr, ctx->stream));
         }
         // error model of the selection score (derivation in knn_mfma.hip)
         const double u = std::ldexp(1.0, -24);
@@ -320,7 +178,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
         {
             Prof pr(ctx, KVB_PROF_KNN_SELECT);
             KVB_HIP(ctx, kvb::launch_select_mfma(split, Aq, Bc, nn, kpad, kp, ynorm2, rmax, em, keys, cap, slast,
-                                                 ctx->stream));
+                                                 nullptr, 0, ctx->stream));
         }
         kstride = cap;
     }

@@ -265,12 +265,13 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
         const float hi_edge = a * (1.f + dl) / (1.f - dl);
         // positions: sure-in (below lo_edge), band, sure-out (above hi_edge)
         uint64_t band_m[E];
-        int c_lo = 0, nband = 0, band_beyond = 0;
+        int c_lo = 0, nband = 0, band_beyond = 0, nvalid = 0;
 #pragma unroll
         for (int s = 0; s < E; ++s) {
             const int t = s * WAVE + lane;
             const float dv = key_dist(v[s]);
             const bool valid = v[s] != KEY_INF;
+            nvalid += __popcll(__ballot(valid));
             const bool in_lo = valid && dv < lo_edge;
             const bool in_band = valid && !in_lo && dv <= hi_edge;
             c_lo += __popcll(__ballot(in_lo));
@@ -341,12 +342,19 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
             }
         }
         kept_max = wave_max_f32(kept_max);
-        // certificate: every candidate the select step dropped has a true
-        // squared distance >= slast * lb_scale; it must exceed the largest kept
-        const float lb = slast[i] * lb_scale;
-        const float ub = kept_max * (1.f + dl) * (1.f + 1e-6f);
-        certified = lb > ub;
+        if (slast) {
+            // certificate: every candidate the select step dropped has a true
+            // squared distance >= slast * lb_scale; it must exceed the largest kept
+            const float lb = slast[i] * lb_scale;
+            const float ub = kept_max * (1.f + dl) * (1.f + 1e-6f);
+            certified = lb > ub;
+        } else {
+            // no bound on the dropped candidates (learned routing): the row is
+            // only completed by the exact scan when too few candidates were found
+            certified = nvalid >= kk;
+        }
     }
+    if (!slast) flags |= KVB_ROW_UNCERTIFIED;
     if (force_period > 0 && (i % force_period) == 0) certified = false;
     if (!certified) {
         flags |= KVB_ROW_FALLBACK;

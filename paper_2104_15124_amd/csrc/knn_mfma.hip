@@ -87,16 +87,20 @@ __device__ __forceinline__ size_t bpos(int i, int c, int kpad, int kstep, int ve
 // One wavefront per row: y = x - mu (float32), the operand terms, |y|^2
 // (float64, kept as float32 for the certificate) and the running max |y|.
 // split: 0 = float32 operands, 1 = one BF16 term, 3 = hi/lo pairs, 6 = hi/mid/lo pairs.
-// Rows n..npad-1 pad the last 32-row tile with zeros.
+// Rows n..npad-1 pad the last 32-row tile with zeros. With brow non-null the
+// candidate operand row of sample i is written at row brow[i] instead of i
+// (the bucket order of the learned partitioner; npad == n).
 __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, int n, int npad, int m,
                                                    const double* __restrict__ mu, int split, int kpad,
                                                    void* __restrict__ Aq, void* __restrict__ Bc,
-                                                   float* __restrict__ ynorm2, unsigned* __restrict__ rmax_bits)
+                                                   float* __restrict__ ynorm2, unsigned* __restrict__ rmax_bits,
+                                                   const int* __restrict__ brow)
 {
     const int lane = lane_id();
     const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (i >= npad) return;
     const bool real = i < n;
+    const int ib = (brow && real) ? brow[i] : i;   // candidate operand row
     const float* x = X + static_cast<size_t>(real ? i : 0) * m;
     double nrm = 0.0;
     if (split == 0) {
@@ -107,12 +111,12 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
             const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
             nrm += static_cast<double>(y) * static_cast<double>(y);
             if (real) A[c] = -2.0f * y;
-            B[bpos(i, c, kpad, KS, VE)] = y;
+            B[bpos(ib, c, kpad, KS, VE)] = y;
         }
         nrm = wave_sum_f64(nrm);
         for (int c = m + lane; c < kpad; c += WAVE) {
             if (real) A[c] = (c == m) ? 1.0f : 0.0f;
-            B[bpos(i, c, kpad, KS, VE)] = (c == m) ? static_cast<float>(nrm) : 0.0f;
+            B[bpos(ib, c, kpad, KS, VE)] = (c == m) ? static_cast<float>(nrm) : 0.0f;
         }
     } else {
         constexpr int KS = 16, VE = 8;
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
             }
             for (int t = 0; t < P; ++t) {
                 if (real) A[t * m + c] = a[t];
-                B[bpos(i, t * m + c, kpad, KS, VE)] = b[t];
+                B[bpos(ib, t * m + c, kpad, KS, VE)] = b[t];
             }
         }
         nrm = wave_sum_f64(nrm);
@@ -164,7 +168,7 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
         for (int c = P * m + lane; c < kpad; c += WAVE) {
             const int t = c - P * m;
             if (real) A[c] = t < 3 ? one : static_cast<uint16_t>(0);
-            B[bpos(i, c, kpad, KS, VE)] = t == 0 ? n1 : t == 1 ? n2 : t == 2 ? n3 : static_cast<uint16_t>(0);
+            B[bpos(ib, c, kpad, KS, VE)] = t == 0 ? n1 : t == 1 ? n2 : t == 2 ? n3 : static_cast<uint16_t>(0);
         }
     }
     if (real && lane == 0) {
@@ -220,12 +224,21 @@ __device__ __noinline__ float merge_query_list(uint64_t* __restrict__ dst, const
 // WV wavefronts per workgroup share every candidate stage; each wavefront owns
 // 32 queries. Per-query LDS buffers hold BUF keys and are merged once they
 // pass BUF - 32 (a 32-candidate tile adds at most 32 per query).
-template <class Tr, int KS, int WV, int E>
+//
+// LEARNED = true: bucketed search of the learned partitioner. Workgroup w takes
+// work item (bucket b, first query entry t0): its queries are entries
+// t0 .. min(t0 + 32 WV, qptr[b + 1]) - 1 of qids, its candidates the tiles
+// tptr[b] .. tptr[b + 1] - 1 of the bucket-ordered candidate operand, whose
+// rows map to sample ids through cid (-1 for padding). Lists of queries are
+// created on the first probe pass and merged into on later ones (the list's
+// kp-th score is the starting threshold); no certificate is computed.
+template <class Tr, int KS, int WV, int E, bool LEARNED>
 __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem* __restrict__ Aq,
                                                           const typename Tr::elem* __restrict__ Bc, int n, int kp,
                                                           const float* __restrict__ ynorm2,
                                                           const unsigned* __restrict__ rmax_bits, ErrModel em,
-                                                          uint64_t* __restrict__ lists, float* __restrict__ lb_out)
+                                                          uint64_t* __restrict__ lists, float* __restrict__ lb_out,
+                                                          BucketArgs ba)
 {
     using elem = typename Tr::elem;
     using frag = typename Tr::frag;
@@ -247,44 +260,74 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int half = lane >> 5;
-    const int q0 = (blockIdx.x * WV + wave) * NQ;
+    __shared__ int s_qid[WV][NQ];
+
+    // query ids of this wavefront (-1: none) and the candidate tile range
+    int q0 = 0, tbeg = 0, tend = 0;
+    if constexpr (LEARNED) {
+        const int w = blockIdx.x;
+        if (w >= *ba.n_work) return;   // whole workgroup
+        const int2 wk = ba.work[w];
+        const int qend = ba.qptr[wk.x + 1];
+        q0 = wk.y + wave * NQ;
+        tbeg = ba.tptr[wk.x];
+        tend = ba.tptr[wk.x + 1];
+        if (lane < NQ) s_qid[wave][lane] = q0 + lane < qend ? ba.qids[q0 + lane] : -1;
+    } else {
+        q0 = (blockIdx.x * WV + wave) * NQ;
+        tend = (n + 31) / 32;
+        if (lane < NQ) s_qid[wave][lane] = q0 + lane < n ? q0 + lane : -1;
+    }
+    wave_lds_sync();
 
     frag qa[KS];
     {
-        const int row = min(q0 + (lane & 31), n - 1);
+        int row = s_qid[wave][lane & 31];
+        if (row < 0) row = max(s_qid[wave][0], 0);
         const elem* src = Aq + static_cast<size_t>(row) * kpad + half * Tr::VEC;
 #pragma unroll
         for (int s = 0; s < KS; ++s) qa[s] = Tr::load(src + s * Tr::KSTEP);
     }
     float tauv[16];
+    if (LEARNED && !ba.first) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) tauv[r] = __uint_as_float(0x7F800000u);
-    if (lane < NQ) s_cnt[wave][lane] = 0;
-    for (int q = 0; q < NQ; ++q) {
-        const int qg = q0 + q;
-        if (qg < n)
-            for (int t = lane; t < CAP; t += WAVE) lists[static_cast<size_t>(qg) * CAP + t] = KEY_INF;
+        for (int r = 0; r < 16; ++r) {
+            const int qid = s_qid[wave][acc_row(r, half)];
+            tauv[r] = qid >= 0 ? key_dist(lists[static_cast<size_t>(qid) * CAP + (kp - 1)]) : -__uint_as_float(0x7F800000u);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            tauv[r] = (!LEARNED || s_qid[wave][acc_row(r, half)] >= 0) ? __uint_as_float(0x7F800000u)
+                                                                      : -__uint_as_float(0x7F800000u);
+        for (int q = 0; q < NQ; ++q) {
+            const int qg = s_qid[wave][q];
+            if (qg >= 0)
+                for (int t = lane; t < CAP; t += WAVE) lists[static_cast<size_t>(qg) * CAP + t] = KEY_INF;
+        }
     }
+    if (lane < NQ) s_cnt[wave][lane] = 0;
     wave_lds_sync();
 
     // a tile of the tile-major candidate operand is one contiguous block, laid
     // out exactly like an LDS stage: it moves as 16-byte pieces
-    const int ntiles = (n + 31) / 32;
     // the query fragments have landed before the loop, so the only vector
     // loads in flight inside it are the next tile's prefetch
     __builtin_amdgcn_s_waitcnt(0);
     u32x4 pf[PF];
-    {
-        const u32x4* g = reinterpret_cast<const u32x4*>(Bc);
+    int cid_pf = -1;
+    if (tbeg < tend) {
+        const u32x4* g = reinterpret_cast<const u32x4*>(Bc + static_cast<size_t>(tbeg) * 32 * kpad);
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int ch = threadIdx.x + u * 64 * WV;
             if (ch < CHUNKS) pf[u] = g[ch];
         }
+        if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(tbeg) * 32 + (lane & 31)];
     }
     uint32_t nonempty = 0;   // queries with buffered entries (wave-uniform)
-    for (int tile = 0; tile < ntiles; ++tile) {
-        const int stage = tile & 1;
+    for (int tile = tbeg; tile < tend; ++tile) {
+        const int stage = (tile - tbeg) & 1;
         {
             u32x4* d = reinterpret_cast<u32x4*>(&s_tile[stage][0][0][0]);
 #pragma unroll
@@ -293,14 +336,16 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
                 if (ch < CHUNKS) d[ch] = pf[u];
             }
         }
+        const int cid_cur = cid_pf;
         __syncthreads();                 // stage visible; the other stage's readers finished a tile ago
-        if (tile + 1 < ntiles) {
+        if (tile + 1 < tend) {
             const u32x4* g = reinterpret_cast<const u32x4*>(Bc + static_cast<size_t>(tile + 1) * 32 * kpad);
 #pragma unroll
             for (int u = 0; u < PF; ++u) {
                 const int ch = threadIdx.x + u * 64 * WV;
                 if (ch < CHUNKS) pf[u] = g[ch];
             }
+            if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(tile + 1) * 32 + (lane & 31)];
         }
         frag bfr[KS];
 #pragma unroll
@@ -310,8 +355,8 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
 #pragma unroll
         for (int s = 0; s < KS; ++s) acc = Tr::mma(qa[s], bfr[s], s == 0 ? zero : acc);
 
-        const int cand = tile * 32 + (lane & 31);
-        const bool valid = cand < n;
+        const int cand = LEARNED ? cid_cur : tile * 32 + (lane & 31);
+        const bool valid = LEARNED ? cand >= 0 : cand < n;
         uint32_t flush = 0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -343,9 +388,9 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
                 const int q = __builtin_ctz(flush);
                 flush &= flush - 1;
                 nonempty &= ~(1u << q);
-                const int qg = q0 + q;
-                float nt = __uint_as_float(0x7F800000u);
-                if (qg < n)
+                const int qg = s_qid[wave][q];
+                float nt = -__uint_as_float(0x7F800000u);
+                if (qg >= 0)
                     nt = merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][q][0],
                                              s_cnt[wave][q], kp);
                 if (lane == 0) s_cnt[wave][q] = 0;
@@ -362,11 +407,12 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
     while (nonempty) {
         const int q = __builtin_ctz(nonempty);
         nonempty &= nonempty - 1;
-        const int qg = q0 + q;
-        if (qg < n)
+        const int qg = s_qid[wave][q];
+        if (qg >= 0)
             merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][q][0], s_cnt[wave][q], kp);
         wave_lds_sync();
     }
+    if constexpr (LEARNED) return;
     // certificate lower bound for the candidates left out of each list
     const double R = static_cast<double>(__uint_as_float(*rmax_bits));
     if (lane < NQ) {
@@ -388,34 +434,50 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_prep(const float* X, int n, int m, int split, int kpad, double* colpart, int colblocks,
-                       double* mu, void* Aq, void* Bc, float* ynorm2, unsigned* rmax_bits, hipStream_t st)
+                       double* mu, void* Aq, void* Bc, float* ynorm2, unsigned* rmax_bits, const int* brow,
+                       hipStream_t st)
 {
     const int rpb = (n + colblocks - 1) / colblocks;
-    const int npad = (n + 31) / 32 * 32;
+    const int npad = brow ? n : (n + 31) / 32 * 32;
     hipLaunchKernelGGL(k_colsum_partial, dim3(colblocks), dim3(256), 0, st, X, n, m, rpb, colpart);
     hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(256), 0, st, colpart, colblocks, m, n, mu);
     hipLaunchKernelGGL(k_prep_rows, dim3((npad + 3) / 4), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq, Bc,
-                       ynorm2, rmax_bits);
+                       ynorm2, rmax_bits, brow);
     return hipGetLastError();
 }
 
 template <class Tr, int KS, int WV>
 static hipError_t launch_sel(const void* Aq, const void* Bc, int n, int kp, const float* ynorm2, const unsigned* rmax,
-                             ErrModel em, uint64_t* lists, int cap, float* lb, hipStream_t st)
+                             ErrModel em, uint64_t* lists, int cap, float* lb, const BucketArgs* ba, int max_work,
+                             hipStream_t st)
 {
     using elem = typename Tr::elem;
     const int rows_per_block = WV * 32;
-    const dim3 grid((n + rows_per_block - 1) / rows_per_block), block(64 * WV);
+    const dim3 block(64 * WV);
     const elem* A = static_cast<const elem*>(Aq);
     const elem* B = static_cast<const elem*>(Bc);
     // the lists buffer holds n * cap keys; only capacities 128 and 256 exist
     if (kp > cap) return hipErrorInvalidValue;
+    if (cap != 128 && cap != 256) return hipErrorInvalidValue;
+    if (ba) {
+        if (max_work <= 0) return hipSuccess;
+        const dim3 grid(max_work);
+        if (cap == 128)
+            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2, true>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
+                               lists, lb, *ba);
+        else
+            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4, true>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
+                               lists, lb, *ba);
+        return hipGetLastError();
+    }
+    const dim3 grid((n + rows_per_block - 1) / rows_per_block);
+    const BucketArgs none = {};
     if (cap == 128)
-        hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em, lists, lb);
-    else if (cap == 256)
-        hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em, lists, lb);
+        hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2, false>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
+                           lists, lb, none);
     else
-        return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4, false>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
+                           lists, lb, none);
     return hipGetLastError();
 }
 
@@ -438,10 +500,18 @@ int mfma_pick_ksteps(int split, int needed)
 }
 
 #define KVB_SEL_CASE(TR, K, WV) \
-    case K: return launch_sel<TR, K, WV>(Aq, Bc, n, kp, ynorm2, rmax, em, lists, cap, lb, st);
+    case K: return launch_sel<TR, K, WV>(Aq, Bc, n, kp, ynorm2, rmax, em, lists, cap, lb, ba, max_work, st);
+
+int select_mfma_queries_per_block(int split, int kpad)
+{
+    const int ks = kpad / mfma_kstep(split);
+    const bool four = split == 0 ? ks >= 64 : ks >= 32;
+    return (four ? 4 : 8) * 32;
+}
 
 hipError_t launch_select_mfma(int split, const void* Aq, const void* Bc, int n, int kpad, int kp, const float* ynorm2,
-                              const unsigned* rmax, ErrModel em, uint64_t* lists, int cap, float* lb, hipStream_t st)
+                              const unsigned* rmax, ErrModel em, uint64_t* lists, int cap, float* lb,
+                              const BucketArgs* ba, int max_work, hipStream_t st)
 {
     const int ks = kpad / mfma_kstep(split);
     if (split == 0) {

@@ -16,6 +16,18 @@ struct ErrModel {
     double center;  // relative rounding of the centred coordinates
 };
 
+// Work description of the bucketed (learned-partitioner) selection; see
+// k_select_mfma in knn_mfma.hip.
+struct BucketArgs {
+    const int2* work;    // (bucket, first query entry) per workgroup
+    const int* n_work;   // number of valid work items
+    const int* qids;     // query sample ids grouped by bucket
+    const int* qptr;     // [nb + 1] query entry offsets per bucket
+    const int* tptr;     // [nb + 1] candidate tile offsets per bucket
+    const int* cid;      // [32 * tiles] sample id of each candidate operand row, -1 for padding
+    int first;           // 1: create the query lists, 0: merge into them
+};
+
 struct TuneResult {
     double chi[256];
     double e_star;
@@ -34,11 +46,16 @@ hipError_t launch_fallback(const float* X, int n, int m, int k, const int* fb_co
                            int32_t* idx, float* d2, hipStream_t st);
 
 hipError_t launch_prep(const float* X, int n, int m, int split, int kpad, double* colpart, int colblocks,
-                       double* mu, void* Aq, void* Bc, float* ynorm2, unsigned* rmax_bits, hipStream_t st);
+                       double* mu, void* Aq, void* Bc, float* ynorm2, unsigned* rmax_bits, const int* brow,
+                       hipStream_t st);
 int mfma_kstep(int split);
 int mfma_pick_ksteps(int split, int needed);
+// ba == nullptr: exact all-pairs selection over n rows; otherwise the bucketed
+// selection with max_work workgroups (the kernel skips those beyond *ba->n_work).
 hipError_t launch_select_mfma(int split, const void* Aq, const void* Bc, int n, int kpad, int kp, const float* ynorm2,
-                              const unsigned* rmax, ErrModel em, uint64_t* lists, int cap, float* lb, hipStream_t st);
+                              const unsigned* rmax, ErrModel em, uint64_t* lists, int cap, float* lb,
+                              const BucketArgs* ba, int max_work, hipStream_t st);
+int select_mfma_queries_per_block(int split, int kpad);
 
 // passes
 hipError_t launch_adhoc_bandwidth(const float* d2, int n, int k, int k0, float* b, hipStream_t st);
@@ -55,5 +72,39 @@ hipError_t launch_qpass(const int32_t* idx, const float* d2, int n, int k, const
 hipError_t launch_assemble(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
                            const double* qa, int out_kind, int64_t* rowptr, int32_t* col, float* val,
                            double* P, double* D, hipStream_t st);
+
+// learned partitioner: MLP (mlp_kernels.hip)
+hipError_t launch_gemm_nt(const uint16_t* A, int lda, const uint16_t* B, int ldb, int M, int N, int K,
+                          const float* bias, int relu, const float* mask_ref, int ldm, float* Cf, int ldcf,
+                          uint16_t* Cb, int ldcb, hipStream_t st);
+hipError_t launch_transpose_bf16(const uint16_t* src, int rows, int cols, uint16_t* dst, hipStream_t st);
+hipError_t launch_cast_rows_bf16(const float* src, int cols, const int32_t* idx, int valid, int rows, int ldd,
+                                 uint16_t* dst, hipStream_t st);
+hipError_t launch_cast_bf16(const float* src, int64_t cnt, uint16_t* dst, hipStream_t st);
+hipError_t launch_colsum(const float* src, int rows, int cols, float* out, hipStream_t st);
+hipError_t launch_softmax_xent(const float* Z, int B, int NB, const int32_t* lab, int ks, float* dZ, uint16_t* dZb,
+                               double* row_loss, double* loss_out, int add, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, int64_t cnt, float lr, float b1, float b2,
+                       float eps, float c1, float c2, uint16_t* pb, hipStream_t st);
+hipError_t launch_route_topp(const float* Z, int rows, int NB, int P, int32_t* home, int32_t* probe, hipStream_t st);
+hipError_t launch_fill_normal(float* p, int64_t cnt, uint64_t seed, uint64_t offset, float scale, hipStream_t st);
+
+// learned partitioner: teacher, batches, bucket layout (learned_kernels.hip)
+hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,
+                          int32_t* vout, int cnt, int end_bit, hipStream_t st);
+hipError_t sort_keys_u64(void* tmp, size_t& tmp_bytes, const uint64_t* kin, uint64_t* kout, int64_t cnt,
+                         int end_bit, hipStream_t st);
+hipError_t launch_teacher_keys(const float* X, int ns, int m, const int32_t* node, int level, uint64_t seed,
+                               uint64_t* keys, int32_t* vals, hipStream_t st);
+hipError_t launch_teacher_split(const uint64_t* skeys, const int32_t* svals, int ns, int nodes, int32_t* start,
+                                int32_t* node_out, hipStream_t st);
+hipError_t launch_batch_gather(int64_t ns, uint64_t a, uint64_t c, int64_t t0, int B, const int32_t* idx_s, int ks,
+                               const int32_t* labels, int32_t* bidx, int32_t* nbrlab, hipStream_t st);
+hipError_t launch_member_keys(const int32_t* home, int n, uint64_t* keys, hipStream_t st);
+hipError_t launch_query_keys(const int32_t* probe, int n, int P, uint64_t* keys, hipStream_t st);
+hipError_t launch_bucket_layout(const uint64_t* skeys, int n, int nb, int32_t* mstart, int32_t* tptr,
+                                int32_t* cid, int64_t cid_rows, int32_t* brow, hipStream_t st);
+hipError_t launch_work_layout(const uint64_t* qkeys, int n, int nb, int P, int qpb, int max_work, int32_t* qptr,
+                              int2* work, int32_t* n_work, int32_t* qids, hipStream_t st);
 
 }  // namespace kvb

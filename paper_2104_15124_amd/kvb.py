@@ -32,9 +32,12 @@ MODES = {"f32": KNN_F32, "bf16": KNN_BF16, "learned": KNN_LEARNED}
 
 EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb_knn",
            "kvb_knn_fallback_rows", "kvb_bandwidth", "kvb_grid_scale", "kvb_tune_eps",
-           "kvb_assemble_csr", "kvb_version", "kvb_profile_enable", "kvb_profile_read",
+           "kvb_assemble_csr", "kvb_part_init", "kvb_part_teacher", "kvb_part_train",
+           "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
+           "kvb_mlp_backward", "kvb_part_num_params", "kvb_part_get_params",
+           "kvb_part_set_params", "kvb_version", "kvb_profile_enable", "kvb_profile_read",
            "kvb_profile_name")
-PROF_SLOTS = 10
+PROF_SLOTS = 12
 
 
 class KvbError(RuntimeError):
@@ -70,6 +73,19 @@ def load_library(path: str = LIB_PATH):
                                _vp, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
     L.kvb_assemble_csr.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _f64, _f64, _f64, _i32,
                                    _vp, _vp, _vp, _vp, _vp]
+    _u64, _f32 = ctypes.c_uint64, ctypes.c_float
+    L.kvb_part_init.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32, _u64]
+    L.kvb_part_teacher.argtypes = [_vp, _vp, _i64, _i32, _i32, _u64, _vp]
+    L.kvb_part_train.argtypes = [_vp, _vp, _i64, _i32, _vp, _vp, _i32, _i32, _i32, _f32, _u64, _vp]
+    L.kvb_part_route.argtypes = [_vp, _vp, _i64, _vp, _vp]
+    L.kvb_part_save.argtypes = [_vp, ctypes.c_char_p]
+    L.kvb_part_load.argtypes = [_vp, ctypes.c_char_p]
+    L.kvb_mlp_forward.argtypes = [_vp, _vp, _i64, _vp]
+    L.kvb_mlp_backward.argtypes = [_vp, _vp, _i64, _vp, _i32, _vp, _vp]
+    L.kvb_part_num_params.argtypes = [_vp]
+    L.kvb_part_num_params.restype = _i64
+    L.kvb_part_get_params.argtypes = [_vp, _vp]
+    L.kvb_part_set_params.argtypes = [_vp, _vp]
     L.kvb_version.restype = ctypes.c_char_p
     L.kvb_profile_enable.argtypes = [_vp, _i32]
     L.kvb_profile_read.argtypes = [_vp, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
@@ -77,7 +93,9 @@ def load_library(path: str = LIB_PATH):
     L.kvb_profile_name.restype = ctypes.c_char_p
     for name in ("kvb_create", "kvb_set_option", "kvb_knn", "kvb_knn_fallback_rows", "kvb_bandwidth",
                  "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_profile_enable",
-                 "kvb_profile_read"):
+                 "kvb_profile_read", "kvb_part_init", "kvb_part_teacher", "kvb_part_train",
+                 "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
+                 "kvb_mlp_backward", "kvb_part_get_params", "kvb_part_set_params"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -285,3 +303,119 @@ def build_kernel_matrix(X: torch.Tensor, k: int, k0: int, d: float, alpha: float
     tb = tune_eps(idx, d2, rho, e_min * s, e_max * s, G, ctx)
     rowptr, col, val, P, D = assemble_csr(idx, d2, rho, tb.e_star, alpha, d, out_kind, ctx)
     return KernelMatrix(idx, d2, flags, b, ta, rho, psi, s, tb, rowptr, col, val, P, D)
+
+
+# ------------------------------------------------------------------ learned partitioner
+def part_init(m: int, h1: int = 256, h2: int = 256, n_buckets: int = 1024, n_probe: int = 4, seed: int = 0,
+              ctx: Context | None = None):
+    """Fresh partitioner parameters in the context (He-normal weights, zero biases)."""
+    ctx = ctx or context()
+    ctx.check(ctx.lib.kvb_part_init(ctx.h, m, h1, h2, n_buckets, n_probe, int(seed)))
+
+
+def part_teacher(Xs: torch.Tensor, levels: int = 10, seed: int = 0, ctx: Context | None = None) -> torch.Tensor:
+    """Balanced teacher partition of Xs: labels [ns] int32 in [0, 2^levels)."""
+    ctx = ctx or context()
+    Xs = _dev(Xs, torch.float32, "Xs")
+    ns, m = Xs.shape
+    labels = torch.empty(ns, dtype=torch.int32, device=Xs.device)
+    ctx.check(ctx.lib.kvb_part_teacher(ctx.h, _ptr(Xs), ns, m, levels, int(seed), _ptr(labels)))
+    return labels
+
+
+def part_train(Xs: torch.Tensor, labels: torch.Tensor, idx_s: torch.Tensor, epochs: int = 10, batch: int = 512,
+               lr: float = 1e-3, seed: int = 0, ctx: Context | None = None) -> np.ndarray:
+    """Adam training on neighbour-histogram targets; returns the per-epoch mean losses."""
+    ctx = ctx or context()
+    Xs = _dev(Xs, torch.float32, "Xs")
+    labels = _dev(labels, torch.int32, "labels")
+    idx_s = _dev(idx_s, torch.int32, "idx_s")
+    ns, m = Xs.shape
+    ks = idx_s.shape[1]
+    loss = np.zeros(epochs, dtype=np.float32)
+    ctx.check(ctx.lib.kvb_part_train(ctx.h, _ptr(Xs), ns, m, _ptr(labels), _ptr(idx_s), ks, epochs, batch,
+                                     float(lr), int(seed), loss.ctypes.data_as(_vp)))
+    return loss
+
+
+def part_route(X: torch.Tensor, n_probe: int, ctx: Context | None = None):
+    """Returns (home [n] int32, probe [n, n_probe] int32)."""
+    ctx = ctx or context()
+    X = _dev(X, torch.float32, "X")
+    n = X.shape[0]
+    home = torch.empty(n, dtype=torch.int32, device=X.device)
+    probe = torch.empty((n, n_probe), dtype=torch.int32, device=X.device)
+    ctx.check(ctx.lib.kvb_part_route(ctx.h, _ptr(X), n, _ptr(home), _ptr(probe)))
+    return home, probe
+
+
+def part_save(path: str, ctx: Context | None = None):
+    ctx = ctx or context()
+    ctx.check(ctx.lib.kvb_part_save(ctx.h, os.fsencode(path)))
+
+
+def part_load(path: str, ctx: Context | None = None):
+    ctx = ctx or context()
+    ctx.check(ctx.lib.kvb_part_load(ctx.h, os.fsencode(path)))
+
+
+def part_num_params(ctx: Context | None = None) -> int:
+    ctx = ctx or context()
+    return int(ctx.check(int(ctx.lib.kvb_part_num_params(ctx.h))))
+
+
+def part_get_params(ctx: Context | None = None) -> torch.Tensor:
+    ctx = ctx or context()
+    p = torch.empty(part_num_params(ctx), dtype=torch.float32, device=torch.device("cuda", ctx.device.index))
+    ctx.check(ctx.lib.kvb_part_get_params(ctx.h, _ptr(p)))
+    return p
+
+
+def part_set_params(params: torch.Tensor, ctx: Context | None = None):
+    ctx = ctx or context()
+    params = _dev(params, torch.float32, "params")
+    if params.numel() != part_num_params(ctx):
+        raise KvbError(E_INVALID, "params has the wrong number of elements")
+    ctx.check(ctx.lib.kvb_part_set_params(ctx.h, _ptr(params)))
+
+
+def mlp_forward(X: torch.Tensor, n_buckets: int, ctx: Context | None = None) -> torch.Tensor:
+    ctx = ctx or context()
+    X = _dev(X, torch.float32, "X")
+    B = X.shape[0]
+    logits = torch.empty((B, n_buckets), dtype=torch.float32, device=X.device)
+    ctx.check(ctx.lib.kvb_mlp_forward(ctx.h, _ptr(X), B, _ptr(logits)))
+    return logits
+
+
+def mlp_backward(X: torch.Tensor, nbr_labels: torch.Tensor, ctx: Context | None = None):
+    """Returns (mean loss, flat gradient [num_params] float32) without updating."""
+    ctx = ctx or context()
+    X = _dev(X, torch.float32, "X")
+    nbr_labels = _dev(nbr_labels, torch.int32, "nbr_labels")
+    B = X.shape[0]
+    grads = torch.empty(part_num_params(ctx), dtype=torch.float32, device=X.device)
+    loss = ctypes.c_float()
+    ctx.check(ctx.lib.kvb_mlp_backward(ctx.h, _ptr(X), B, _ptr(nbr_labels), nbr_labels.shape[1],
+                                       ctypes.byref(loss), _ptr(grads)))
+    return float(loss.value), grads
+
+
+def train_partitioner(X: torch.Tensor, k: int, n_train: int = 200_000, levels: int = 10, h1: int = 256,
+                      h2: int = 256, n_probe: int = 4, epochs: int = 10, batch: int = 512, lr: float = 1e-3,
+                      seed: int = 0, exact_mode: str = "bf16", ctx: Context | None = None) -> np.ndarray:
+    """Neural-LSH style training on a seeded subsample of X: exact k-NN of the
+    subsample (k neighbours, self included), teacher partition into
+    2^levels buckets, then Adam on the neighbour-histogram targets. Returns the
+    per-epoch losses; the trained partitioner stays in the context."""
+    ctx = ctx or context()
+    n, m = X.shape
+    ns = min(n, n_train)
+    g = torch.Generator(device="cpu").manual_seed(int(seed))
+    sel = torch.randperm(n, generator=g)[:ns].to(X.device)
+    Xs = X.index_select(0, sel).contiguous()
+    mode = exact_mode if m > 8 else "f32"
+    idx_s, _, _ = knn(Xs, k, mode, 32, ctx)
+    labels = part_teacher(Xs, levels, seed, ctx)
+    part_init(m, h1, h2, 1 << levels, n_probe, seed, ctx)
+    return part_train(Xs, labels, idx_s, epochs, batch, lr, seed, ctx)
