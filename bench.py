@@ -34,9 +34,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="torus_n100k")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mode", default="", choices=["", "f32", "bf16", "learned"],
+                    help="k-NN mode override (the stress workload runs in all three)")
     ap.add_argument("--n", type=int, default=0,
                     help="sample count override (same recipe, for profiling runs; not a bench line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--train-epochs", type=int, default=10, help="learned mode: partitioner training epochs")
+    ap.add_argument("--recall-rows", type=int, default=1024,
+                    help="learned mode: rows whose recall is judged by the exact float64 row search")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -63,14 +68,31 @@ def main() -> int:
     from paper_2104_15124_amd import kvb
 
     w = workloads.WORKLOADS[args.workload]
+    import dataclasses
     if args.n:
-        import dataclasses
         w = dataclasses.replace(w, n=args.n)
+    if args.mode:
+        w = dataclasses.replace(w, mode=args.mode)
     log(f"bench: workload {w.name} n={w.n} m={w.m} k={w.k} mode={w.mode} margin={w.margin}")
     X = workloads.make(w.name, seed=args.seed, n=w.n)
     torch.cuda.set_device(0)
     Xd = torch.from_numpy(X).cuda()
     ctx = kvb.context()
+
+    learned = None
+    if w.mode == "learned":
+        # partitioner training: timed separately, not part of a step
+        n_train = min(w.n, 200_000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = kvb.train_partitioner(Xd, w.k, n_train=n_train, levels=10, h1=256, h2=256, n_probe=4,
+                                       epochs=args.train_epochs, batch=512, lr=2e-3, seed=args.seed, ctx=ctx)
+        torch.cuda.synchronize()
+        learned = {"train_s": round(time.perf_counter() - t0, 3), "train_rows": n_train,
+                   "epochs": args.train_epochs, "loss_first": round(float(losses[0]), 4),
+                   "loss_last": round(float(losses[-1]), 4), "mlp": [w.m, 256, 256, 1024], "n_probe": 4}
+        log(f"bench: partitioner trained on {n_train} rows in {learned['train_s']} s, "
+            f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
 
     def step():
         return kvb.build_kernel_matrix(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
@@ -102,6 +124,24 @@ def main() -> int:
     sel_ms, sel_cnt = prof["knn_select"]
     sel_avg_s = sel_ms / sel_cnt / 1e3
     pairs = float(w.n) * float(w.n)
+    if learned is not None:
+        # pairs the routed search evaluates: each query against its probed buckets;
+        # the selection kernel runs once per probe slot, so per launch a quarter
+        home, probe = kvb.part_route(Xd, 4, ctx)
+        sizes = torch.bincount(home.long(), minlength=1024).double()
+        pairs = float(sizes[probe.long()].sum()) / (sel_cnt / args.steps)
+        learned["candidate_share"] = round(float(sizes[probe.long()].sum()) / float(w.n) ** 2, 5)
+        learned["largest_bucket"] = int(sizes.max())
+        g = torch.Generator().manual_seed(args.seed + 1)
+        rows = torch.randperm(w.n, generator=g)[: args.recall_rows].to(torch.int32).cuda()
+        ex_idx, _ = kvb.knn_exact_rows(Xd, w.k, rows, ctx)
+        got = r.idx.index_select(0, rows.long())
+        ex, gt = ex_idx[:, 1:].cpu().numpy(), got[:, 1:].cpu().numpy()
+        hits = sum(len(np.intersect1d(a, b)) for a, b in zip(gt, ex))
+        learned["recall"] = round(hits / float(ex.size), 5)
+        learned["recall_rows"] = int(rows.numel())
+        log(f"  learned: recall {learned['recall']} on {rows.numel()} rows, candidate share "
+            f"{learned['candidate_share']}, largest bucket {learned['largest_bucket']}")
     if w.mode == "f32" and w.m <= 8:
         ops_per_pair = 2 * w.m + 1      # m subtractions, m multiply(-add)s, 1 threshold compare
         achieved = pairs * ops_per_pair / sel_avg_s / 1e12
@@ -111,12 +151,13 @@ def main() -> int:
                     "work": f"{ops_per_pair} VALU lane-ops per candidate pair, n^2 pairs per launch"}
     else:
         flops_per_pair = 2 * w.m        # the algorithmic contraction y_i . y_j
-        peak = 2500.0 if w.mode == "bf16" else 157.3
+        peak = 157.3 if w.mode == "f32" else 2500.0
         achieved = pairs * flops_per_pair / sel_avg_s / 1e12
         roofline = {"kernel": "knn_select", "bound": "mfma", "achieved": round(achieved, 3),
                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                     "traffic": None, "avg_ms": round(sel_avg_s * 1e3, 4),
-                    "work": f"{flops_per_pair} algorithmic flops per candidate pair (2m), n^2 pairs per launch"}
+                    "work": f"{flops_per_pair} algorithmic flops per candidate pair (2m), "
+                            + ("routed query-candidate pairs per probe pass" if learned else "n^2 pairs per launch")}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -142,7 +183,8 @@ def main() -> int:
                    f"({c1 - c0:.2f} s); the O(nk) passes are not included"}
 
     out = {
-        "metric": "kernel-matrix rows/s (kNN+VB kernel->CSR) at exact kNN sets",
+        "metric": "kernel-matrix rows/s (kNN+VB kernel->CSR) at " + ("learned-routed kNN (recall reported)"
+                                                                    if learned else "exact kNN sets"),
         "value": round(value, 1),
         "unit": "rows/s",
         "n_gpus": 1,
@@ -152,11 +194,11 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if w.mode == "bf16" else "f32",
+        "dtype": "f32" if w.mode == "f32" else "bf16",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "m": w.m, "k": w.k, "k0": w.k0, "d": w.d,
                    "mode": w.mode, "margin": w.margin, "grid": [w.e_min, w.e_max, w.G],
-                   "alpha": w.alpha, "beta": w.beta, "fallback_rows": fb},
+                   "alpha": w.alpha, "beta": w.beta, "fallback_rows": fb, "learned": learned},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

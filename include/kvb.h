@@ -124,10 +124,22 @@ int kvb_set_option(kvb_ctx ctx, int32_t key, int64_t value);
  * within a row, entries are ordered by their compensated FP32 distance.
  * Requires n < 2^31 and m <= 1024. Asynchronous: rows that needed the exact
  * fallback are marked in row_flags and counted by kvb_knn_fallback_rows.
- * Modes other than KVB_KNN_F32 that this build lacks return KVB_E_UNSUPPORTED.
+ * KVB_KNN_LEARNED without a partitioner in ctx returns KVB_E_NOT_TRAINED.
  */
 int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k,
             int32_t mode, int32_t margin, int32_t* idx, float* d2, int32_t* row_flags);
+
+/*
+ * Exact k-NN of selected rows against all n samples, by float64 distances
+ * and a radix selection (the same scan as the exact fallback of kvb_knn):
+ * the judge of recall for KVB_KNN_LEARNED on a sample of rows.
+ *   rows     [nrows] int32 device array of row ids (0 <= rows[t] < n).
+ *   idx, d2  [nrows, k] out, row t for sample rows[t], in kvb_knn's layout
+ *            (self first, then (d2, index) order; d2 rounded to float32).
+ * An id outside [0, n) yields a row of -1 / NaN. Asynchronous.
+ */
+int kvb_knn_exact_rows(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, const int32_t* rows,
+                       int64_t nrows, int32_t* idx, float* d2);
 
 /* Number of rows of the last kvb_knn call on ctx that took the exact fallback
  * scan. Synchronises the context stream. Returns KVB_W_FALLBACK if > 0. */

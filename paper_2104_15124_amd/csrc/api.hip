@@ -206,6 +206,23 @@ int kvb_knn_fallback_rows(kvb_ctx ctx, int64_t* count_host)
     return *count_host > 0 ? KVB_W_FALLBACK : KVB_OK;
 }
 
+int kvb_knn_exact_rows(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, const int32_t* rows,
+                       int64_t nrows, int32_t* idx, float* d2)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
+    KVB_REQUIRE(ctx, m >= 1 && m <= 1024, "m must be in [1, 1024], got %d", m);
+    KVB_REQUIRE(ctx, k >= 1 && k <= n && k <= 256, "k must be in [1, min(n, 256)], got %d", k);
+    KVB_REQUIRE(ctx, nrows >= 0 && nrows < (int64_t(1) << 31), "nrows must be in [0, 2^31)");
+    if (nrows == 0) return KVB_OK;
+    KVB_REQUIRE(ctx, aligned(X) && aligned(rows) && aligned(idx) && aligned(d2),
+                "X, rows, idx and d2 must be non-null device pointers");
+    Prof pr(ctx, KVB_PROF_KNN_FALLBACK);
+    KVB_HIP(ctx, kvb::launch_exact_rows(X, static_cast<int>(n), m, k, rows, static_cast<int>(nrows), idx, d2,
+                                        ctx->stream));
+    return KVB_OK;
+}
+
 int kvb_bandwidth(kvb_ctx ctx, const int32_t* idx, const float* d2, int64_t n, int32_t k, int32_t mode, int32_t k0,
                   const float* b, double e, double d, double beta, float* rho, float* psi)
 {

@@ -373,9 +373,12 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
 // with d < V plus the smallest-index j with d == V, ranked by (d, j).
 constexpr int FB_THREADS = 256;
 
+// The row count is *fb_count, or `count` when fb_count is null. Results go to
+// row i of idx_out / d2_out, or with `compact` to row t (the list position);
+// in compact mode a listed id outside [0, n) yields a row of -1 / NaN.
 __global__ __launch_bounds__(FB_THREADS) void k_fallback(const float* __restrict__ X, int n, int m, int k,
-                                                         const int* __restrict__ fb_count,
-                                                         const int* __restrict__ fb_list,
+                                                         const int* __restrict__ fb_count, int count,
+                                                         const int* __restrict__ fb_list, int compact,
                                                          int32_t* __restrict__ idx_out,
                                                          float* __restrict__ d2_out)
 {
@@ -387,12 +390,27 @@ __global__ __launch_bounds__(FB_THREADS) void k_fallback(const float* __restrict
     __shared__ int s_cnt_lt, s_cnt_eq;
     __shared__ int wsum_lt[FB_THREADS / WAVE], wsum_eq[FB_THREADS / WAVE];
     const int tid = threadIdx.x;
-    const int total = *fb_count;
+    const int total = fb_count ? *fb_count : count;
     const int kk = k - 1;
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const int i = fb_list[t];
+        const size_t orow = compact ? static_cast<size_t>(t) : static_cast<size_t>(i);
+        if (i < 0 || i >= n) {
+            if (compact)
+                for (int r = tid; r < k; r += FB_THREADS) {
+                    idx_out[orow * k + r] = -1;
+                    d2_out[orow * k + r] = __uint_as_float(0x7FC00000u);
+                }
+            continue;
+        }
         const float* xi = X + static_cast<size_t>(i) * m;
-        if (kk == 0) continue;
+        if (kk == 0) {
+            if (tid == 0) {
+                idx_out[orow * k] = i;
+                d2_out[orow * k] = 0.f;
+            }
+            continue;
+        }
         if (tid == 0) {
             s_prefix = 0ull;
             s_remaining = kk;
@@ -482,12 +500,12 @@ __global__ __launch_bounds__(FB_THREADS) void k_fallback(const float* __restrict
             const int j = cj[tid];
             int rank = 0;
             for (int u = 0; u < kk; ++u) rank += (cd[u] < d) || (cd[u] == d && cj[u] < j);
-            idx_out[static_cast<size_t>(i) * k + 1 + rank] = j;
-            d2_out[static_cast<size_t>(i) * k + 1 + rank] = static_cast<float>(d);
+            idx_out[orow * k + 1 + rank] = j;
+            d2_out[orow * k + 1 + rank] = static_cast<float>(d);
         }
         if (tid == 0) {
-            idx_out[static_cast<size_t>(i) * k] = i;
-            d2_out[static_cast<size_t>(i) * k] = 0.f;
+            idx_out[orow * k] = i;
+            d2_out[orow * k] = 0.f;
         }
         __syncthreads();
     }
@@ -553,7 +571,18 @@ hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstrid
 hipError_t launch_fallback(const float* X, int n, int m, int k, const int* fb_count, const int* fb_list,
                            int32_t* idx, float* d2, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fallback, dim3(512), dim3(FB_THREADS), 0, st, X, n, m, k, fb_count, fb_list, idx, d2);
+    hipLaunchKernelGGL(k_fallback, dim3(512), dim3(FB_THREADS), 0, st, X, n, m, k, fb_count, 0, fb_list, 0, idx,
+                       d2);
+    return hipGetLastError();
+}
+
+hipError_t launch_exact_rows(const float* X, int n, int m, int k, const int* rows, int nrows, int32_t* idx, float* d2,
+                             hipStream_t st)
+{
+    if (nrows <= 0) return hipSuccess;
+    const int grid = nrows < 1024 ? nrows : 1024;
+    hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(FB_THREADS), 0, st, X, n, m, k, nullptr, nrows, rows, 1, idx,
+                       d2);
     return hipGetLastError();
 }
 

@@ -44,6 +44,8 @@ hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstrid
                          int* fb_count, int* fb_list, int force_period, hipStream_t st);
 hipError_t launch_fallback(const float* X, int n, int m, int k, const int* fb_count, const int* fb_list,
                            int32_t* idx, float* d2, hipStream_t st);
+hipError_t launch_exact_rows(const float* X, int n, int m, int k, const int* rows, int nrows, int32_t* idx, float* d2,
+                             hipStream_t st);
 
 hipError_t launch_prep(const float* X, int n, int m, int split, int kpad, double* colpart, int colblocks,
                        double* mu, void* Aq, void* Bc, float* ynorm2, unsigned* rmax_bits, const int* brow,

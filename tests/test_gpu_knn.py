@@ -228,3 +228,23 @@ def test_knn_nonlinear5_n1m_sampled_rows(gpu_lib):
     ri, rd = knn_reference(X, w.k, rows=rows)
     check_knn_rows(gi[rows], gd[rows], ri, rd, w.k, rows)
     assert nfb <= w.n // 100
+
+
+EXACT_ROWS_CASES = [("n3000_m3_k32", 3000, 3, 32, 1), ("n2000_m64_k64", 2000, 64, 64, 2), ("n500_m7_k1", 500, 7, 1, 3)]
+
+
+@pytest.mark.parametrize("name,n,m,k,seed", EXACT_ROWS_CASES, ids=[c[0] for c in EXACT_ROWS_CASES])
+def test_knn_exact_rows(gpu_lib, name, n, m, k, seed):
+    say(f"[knn-exact-rows] {name}")
+    X = workloads.gaussian_iid(n, m, seed=seed)
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(n, size=min(n, 300), replace=False).astype(np.int32)
+    gi, gd = gpu_lib.knn_exact_rows(torch.from_numpy(X).cuda(), k, torch.from_numpy(rows).cuda())
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    ri, rd = knn_reference(X, k, rows)
+    check_knn_rows(gi, gd, ri, rd, k, rows)
+    # an id outside [0, n) gives a row of -1
+    bad = torch.tensor([0, n, -1], dtype=torch.int32, device="cuda")
+    bi, bd = gpu_lib.knn_exact_rows(torch.from_numpy(X).cuda(), k, bad)
+    bi = bi.cpu().numpy()
+    assert bi[0, 0] == 0 and (bi[1] == -1).all() and (bi[2] == -1).all()
