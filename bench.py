@@ -123,13 +123,13 @@ def main() -> int:
     # roofline of the dominant kernel: the k-NN distance tiles + selection
     sel_ms, sel_cnt = prof["knn_select"]
     sel_avg_s = sel_ms / sel_cnt / 1e3
-    pairs = float(w.n) * float(w.n)
+    # candidate pairs the distance tiles scored in the last step (all probe
+    # passes of the learned search; the pairs the spatial scan did not skip)
+    pairs = kvb.knn_pairs(ctx)
+    log(f"  knn pairs scored {pairs:.4g} ({pairs / (float(w.n) ** 2):.4%} of n^2)")
     if learned is not None:
-        # pairs the routed search evaluates: each query against its probed buckets;
-        # the selection kernel runs once per probe slot, so per launch a quarter
         home, probe = kvb.part_route(Xd, 4, ctx)
         sizes = torch.bincount(home.long(), minlength=1024).double()
-        pairs = float(sizes[probe.long()].sum()) / (sel_cnt / args.steps)
         learned["candidate_share"] = round(float(sizes[probe.long()].sum()) / float(w.n) ** 2, 5)
         learned["largest_bucket"] = int(sizes.max())
         g = torch.Generator().manual_seed(args.seed + 1)
@@ -148,7 +148,8 @@ def main() -> int:
         roofline = {"kernel": "knn_select", "bound": "alu", "achieved": round(achieved, 3),
                     "peak": round(ALU_PEAK_TOPS, 3), "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
                     "traffic": None, "avg_ms": round(sel_avg_s * 1e3, 4),
-                    "work": f"{ops_per_pair} VALU lane-ops per candidate pair, n^2 pairs per launch"}
+                    "work": f"{ops_per_pair} VALU lane-ops per scored candidate pair, {pairs:.4g} pairs per launch "
+                            f"(the pairs the bounding-box scan did not skip)"}
     else:
         flops_per_pair = 2 * w.m        # the algorithmic contraction y_i . y_j
         peak = 157.3 if w.mode == "f32" else 2500.0
@@ -156,8 +157,8 @@ def main() -> int:
         roofline = {"kernel": "knn_select", "bound": "mfma", "achieved": round(achieved, 3),
                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                     "traffic": None, "avg_ms": round(sel_avg_s * 1e3, 4),
-                    "work": f"{flops_per_pair} algorithmic flops per candidate pair (2m), "
-                            + ("routed query-candidate pairs per probe pass" if learned else "n^2 pairs per launch")}
+                    "work": f"{flops_per_pair} algorithmic flops per scored candidate pair (2m), {pairs:.4g} pairs "
+                            + ("(routed query-candidate pairs, all probe passes)" if learned else "(n^2)")}
 
     cpu = None
     if not args.no_cpu_baseline:

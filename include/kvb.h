@@ -129,6 +129,13 @@ int kvb_set_option(kvb_ctx ctx, int32_t key, int64_t value);
 int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k,
             int32_t mode, int32_t margin, int32_t* idx, float* d2, int32_t* row_flags);
 
+/* Number of candidate pairs (query row, candidate sample) whose score the
+ * distance tiles of the last kvb_knn call on ctx computed: n^2 for the
+ * all-pairs matrix-core scan, fewer where the direct scan skipped tiles by
+ * their bounding boxes or the learned routing limited the candidates.
+ * Synchronises the context stream. */
+int kvb_knn_pairs(kvb_ctx ctx, double* pairs_host);
+
 /*
  * Exact k-NN of selected rows against all n samples, by float64 distances
  * and a radix selection (the same scan as the exact fallback of kvb_knn):

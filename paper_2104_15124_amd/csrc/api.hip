@@ -42,6 +42,9 @@ int kvb_create(kvb_ctx* out, void* hip_stream)
         hipHostMalloc(reinterpret_cast<void**>(&ctx->tune_host), sizeof(kvb::TuneResult), hipHostMallocDefault) !=
             hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&ctx->fb_count_dev), sizeof(int)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&ctx->pairs_dev), sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&ctx->pairs_host), sizeof(unsigned long long),
+                      hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&ctx->fb_count_host), sizeof(int), hipHostMallocDefault) !=
             hipSuccess) {
         kvb_destroy(ctx);
@@ -66,6 +69,8 @@ void kvb_destroy(kvb_ctx ctx)
     if (ctx->fb_count_dev) (void)hipFree(ctx->fb_count_dev);
     if (ctx->fb_count_host) (void)hipHostFree(ctx->fb_count_host);
     if (ctx->loss_dev) (void)hipFree(ctx->loss_dev);
+    if (ctx->pairs_dev) (void)hipFree(ctx->pairs_dev);
+    if (ctx->pairs_host) (void)hipHostFree(ctx->pairs_host);
     part_free(ctx);
     delete ctx;
 }
@@ -130,7 +135,16 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
     const size_t esz = split == 0 ? sizeof(float) : sizeof(uint16_t);
     size_t need = round256(size_t(nn) * (direct ? kp : cap) * sizeof(uint64_t)) +
                   round256(size_t(nn) * sizeof(float)) + round256(size_t(nn) * sizeof(int)) + 2048;
-    if (!direct)
+    size_t sort_bytes = 0;
+    if (direct)
+        KVB_HIP(ctx, kvb::sort_pairs_u64(nullptr, sort_bytes, nullptr, nullptr, nullptr, nullptr, nn, 64, ctx->stream));
+    const int ntiles = kvb::spatial_tiles(nn), nsb = kvb::spatial_superblocks(nn);
+    if (direct)
+        need += round256(size_t(nn) * m * sizeof(float)) + 2 * round256(size_t(nn) * sizeof(int32_t)) +
+                2 * round256(size_t(nn) * sizeof(uint64_t)) + round256(size_t(ntiles) * 2 * m * sizeof(float)) +
+                round256(size_t(nsb) * 2 * m * sizeof(float)) +
+                round256(size_t(kvb::spatial_bbox_blocks(nn)) * 2 * m * sizeof(float)) + round256(sort_bytes);
+    else
         need += 2 * round256(size_t(nn + 31) / 32 * 32 * kpad * esz) + round256(size_t(nn) * sizeof(float)) +
                 round256(size_t(m) * sizeof(double)) + round256(size_t(colblocks) * m * sizeof(double)) + 256;
     int rc = ensure_scratch(ctx, need);
@@ -141,11 +155,29 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
     int* fb_list = cv.take<int>(nn);
 
     KVB_HIP(ctx, hipMemsetAsync(ctx->fb_count_dev, 0, sizeof(int), ctx->stream));
+    KVB_HIP(ctx, hipMemsetAsync(ctx->pairs_dev, 0, sizeof(unsigned long long), ctx->stream));
     float lb_scale = 1.0f;
     int kstride = kp;
     if (direct) {
+        float* Xs = cv.take<float>(size_t(nn) * m);
+        int32_t* perm = cv.take<int32_t>(nn);
+        int32_t* vals = cv.take<int32_t>(nn);
+        uint64_t* code = cv.take<uint64_t>(nn);
+        uint64_t* scode = cv.take<uint64_t>(nn);
+        float* tbox = cv.take<float>(size_t(ntiles) * 2 * m);
+        float* sbox = cv.take<float>(size_t(nsb) * 2 * m);
+        float* bbox = cv.take<float>(size_t(kvb::spatial_bbox_blocks(nn)) * 2 * m);
+        void* sort_tmp = cv.take<char>(sort_bytes);
+        {
+            Prof pr(ctx, KVB_PROF_KNN_PREP);
+            KVB_HIP(ctx, kvb::launch_spatial_codes(X, nn, m, bbox, code, vals, ctx->stream));
+            size_t sb = sort_bytes;
+            KVB_HIP(ctx, kvb::sort_pairs_u64(sort_tmp, sb, code, scode, vals, perm, nn, 64, ctx->stream));
+            KVB_HIP(ctx, kvb::launch_spatial_layout(X, nn, m, perm, Xs, tbox, sbox, ctx->stream));
+        }
         Prof pr(ctx, KVB_PROF_KNN_SELECT);
-        KVB_HIP(ctx, kvb::launch_select_direct(X, nn, m, kp, keys, slast, ctx->stream));
+        KVB_HIP(ctx, kvb::launch_select_direct(Xs, perm, tbox, sbox, nn, m, kp, keys, slast, ctx->pairs_dev,
+                                               ctx->stream));
         // the direct tiles compute each squared distance with at most (m + 2)
         // float32 roundings; (m + 4) 2^-23 bounds their relative error with a
         // factor-2 margin
@@ -178,7 +210,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
         {
             Prof pr(ctx, KVB_PROF_KNN_SELECT);
             KVB_HIP(ctx, kvb::launch_select_mfma(split, Aq, Bc, nn, kpad, kp, ynorm2, rmax, em, keys, cap, slast,
-                                                 nullptr, 0, ctx->stream));
+                                                 nullptr, 0, ctx->pairs_dev, ctx->stream));
         }
         kstride = cap;
     }
@@ -204,6 +236,17 @@ int kvb_knn_fallback_rows(kvb_ctx ctx, int64_t* count_host)
     KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     *count_host = *ctx->fb_count_host;
     return *count_host > 0 ? KVB_W_FALLBACK : KVB_OK;
+}
+
+int kvb_knn_pairs(kvb_ctx ctx, double* pairs_host)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, pairs_host != nullptr, "pairs_host must be non-null");
+    KVB_HIP(ctx, hipMemcpyAsync(ctx->pairs_host, ctx->pairs_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *pairs_host = static_cast<double>(*ctx->pairs_host);
+    return KVB_OK;
 }
 
 int kvb_knn_exact_rows(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, const int32_t* rows,

@@ -16,6 +16,8 @@
 //            dropped candidate can be nearer than the k-th kept one;
 //   fallback rows without a certificate are recomputed by an exact float64
 //            radix selection over all n samples.
+#include <algorithm>
+
 #include "kvb_device.h"
 #include "kvb_kernels.h"
 
@@ -23,27 +25,131 @@ namespace kvb {
 
 // -------------------------------------------------------------------- select
 // Direct-difference distance tiles for small m (VALU: m subtractions and m
-// multiply-adds per pair; the query coordinates are wave-uniform and live in
-// scalar registers). Candidates passing the current threshold of a row are
-// appended to a 64-entry LDS buffer; a full buffer is merged into the row's
-// register list by a bitonic network, which also tightens the threshold.
+// multiply-adds per pair; the query coordinates are wave-uniform).
+//
+// The samples are visited in a spatial order: sorted along a Morton (Z-order)
+// curve of their coordinates, cut into tiles of 64 consecutive samples (one
+// candidate per lane) and superblocks of 16 tiles, each with its axis-aligned
+// bounding box. A wavefront owns R consecutive sorted rows. It first scores
+// its own tile and the nearest tiles along the curve, which sets tight
+// thresholds, then tests every superblock box (64 per instruction, one per
+// lane) and, inside the superblocks within reach, every tile box (16 lanes),
+// and scores only the tiles whose box lies within the largest current
+// threshold of its rows. A skipped candidate is therefore at least as far as
+// a threshold that only decreases afterwards, which keeps the certificate of
+// the refine step valid: the box bound is computed in float32 with at most
+// (m + 2) roundings, inside the relative margin the refine step allows for
+// the selection scores.
+//
+// Candidates passing the current threshold of a row are appended to a
+// 64-entry LDS buffer; a full buffer is merged into the row's register list by
+// a bitonic network, which also tightens the threshold. Keys carry the
+// sample's original index, so ties order as in I(x, k).
+struct SpatialView {
+    const float* Xs;      // [n, m] coordinates in curve order
+    const int* perm;      // [n] original index of each curve position
+    const float* tbox;    // [tiles, 2, m]: lower corner, then upper corner
+    const float* sbox;    // [superblocks, 2, m]
+};
+
+constexpr int TILE = 64;
+constexpr int SB_TILES = 16;
+
+template <int M>
+__device__ __forceinline__ float box_gap2(const float* __restrict__ b, const float (&glo)[M], const float (&ghi)[M])
+{
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        const float g = fmaxf(fmaxf(b[c] - ghi[c], glo[c] - b[M + c]), 0.f);
+        s = fmaf(g, g, s);
+    }
+    return s;
+}
+
+constexpr int SEED_TILES = 2;   // curve neighbours on each side scored before any box test
+
+template <int M>
+__device__ __forceinline__ void load_tile(const SpatialView& sv, int n, int t, int lane, float (&x)[M], uint32_t& jo)
+{
+    const int jp = min(t * TILE + lane, n - 1);
+#pragma unroll
+    for (int c = 0; c < M; ++c) x[c] = sv.Xs[static_cast<size_t>(jp) * M + c];
+    jo = static_cast<uint32_t>(sv.perm[jp]);
+}
+
+// Score one tile of 64 candidates against the wavefront's R rows and append
+// the keys that pass each row's threshold (see k_select_direct).
 template <int M, int R, int E>
-__global__ __launch_bounds__(256) void k_select_direct(const float* __restrict__ X, int n, int kp,
+__device__ __forceinline__ void score_tile(const float (&q)[R][M], const float (&x)[M], uint32_t jo, bool valid, int n,
+                                           int t, int kp, int rows_here, int lane, uint64_t* buf, uint64_t (&L)[R][E],
+                                           float (&tau)[R], int (&bc)[R], float& taumax, unsigned long long& pairs)
+{
+    pairs += static_cast<unsigned long long>(min(TILE, n - t * TILE)) * rows_here;
+    bool merged = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float tt = q[r][0] - x[0];
+        float d = tt * tt;
+#pragma unroll
+        for (int c = 1; c < M; ++c) {
+            tt = q[r][c] - x[c];
+            d = fmaf(tt, tt, d);
+        }
+        uint64_t mask = __ballot(valid && d <= tau[r]);
+        if (mask) {
+            int cnt = __popcll(mask);
+            if (bc[r] + cnt > WAVE) {
+                wave_lds_sync();
+                uint64_t b = lane < bc[r] ? buf[r * WAVE + lane] : KEY_INF;
+                merge_into_list<E>(L[r], b);
+                bc[r] = 0;
+                tau[r] = key_dist(list_at<E>(L[r], kp - 1));
+                merged = true;
+                mask = __ballot(valid && d <= tau[r]);
+                cnt = __popcll(mask);
+                wave_lds_sync();
+            }
+            if ((mask >> lane) & 1ull) buf[r * WAVE + bc[r] + mbcnt64(mask)] = make_key(d, jo);
+            bc[r] += cnt;
+        }
+    }
+    if (merged) {
+        taumax = tau[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) taumax = fmaxf(taumax, tau[r]);
+    }
+}
+
+template <int M, int R, int E>
+__global__ __launch_bounds__(256) void k_select_direct(SpatialView sv, int n, int kp,
                                                        uint64_t* __restrict__ keys_out,
-                                                       float* __restrict__ slast_out)
+                                                       float* __restrict__ slast_out,
+                                                       unsigned long long* __restrict__ pair_count)
 {
     __shared__ uint64_t sbuf[4][R][WAVE];
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int row0 = (blockIdx.x * 4 + wave) * R;
+    const int row0 = (blockIdx.x * 4 + wave) * R;   // curve position of the first row
     if (row0 >= n) return;
 
     float q[R][M];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = min(row0 + r, n - 1);
+        const int p = min(row0 + r, n - 1);
 #pragma unroll
-        for (int c = 0; c < M; ++c) q[r][c] = X[static_cast<size_t>(i) * M + c];
+        for (int c = 0; c < M; ++c) q[r][c] = sv.Xs[static_cast<size_t>(p) * M + c];
+    }
+    float glo[M], ghi[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        glo[c] = q[0][c];
+        ghi[c] = q[0][c];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            glo[c] = fminf(glo[c], q[r][c]);
+            ghi[c] = fmaxf(ghi[c], q[r][c]);
+        }
     }
     uint64_t L[R][E];
     float tau[R];
@@ -55,39 +161,66 @@ __global__ __launch_bounds__(256) void k_select_direct(const float* __restrict__
         tau[r] = __uint_as_float(0x7F800000u);
         bc[r] = 0;
     }
+    float taumax = __uint_as_float(0x7F800000u);
     uint64_t* buf = &sbuf[wave][0][0];
+    const int rows_here = min(R, n - row0);
+    unsigned long long pairs = 0;
 
-    for (int j0 = 0; j0 < n; j0 += WAVE) {
-        const int j = j0 + lane;
-        const bool valid = j < n;
-        const int jj = valid ? j : n - 1;
-        float x[M];
+    const int ntiles = (n + TILE - 1) / TILE;
+    const int nsb = (ntiles + SB_TILES - 1) / SB_TILES;
+    const int own_t = row0 / TILE;
+    // seed: the own tile and its curve neighbours, unconditionally
+    const int a0 = max(0, own_t - SEED_TILES), a1 = min(ntiles - 1, own_t + SEED_TILES);
+    float xc[M];
+    uint32_t jc_o = 0;
+    load_tile<M>(sv, n, a0, lane, xc, jc_o);
+    for (int t = a0; t <= a1; ++t) {
+        float xn[M];
+        uint32_t jn_o = 0;
+        if (t < a1) load_tile<M>(sv, n, t + 1, lane, xn, jn_o);
+        score_tile<M, R, E>(q, xc, jc_o, t * TILE + lane < n, n, t, kp, rows_here, lane, buf, L, tau, bc, taumax, pairs);
+        if (t < a1) {
 #pragma unroll
-        for (int c = 0; c < M; ++c) x[c] = X[static_cast<size_t>(jj) * M + c];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            float t = q[r][0] - x[0];
-            float d = t * t;
-#pragma unroll
-            for (int c = 1; c < M; ++c) {
-                t = q[r][c] - x[c];
-                d = fmaf(t, t, d);
-            }
-            uint64_t mask = __ballot(valid && d <= tau[r]);
-            if (mask) {
-                int cnt = __popcll(mask);
-                if (bc[r] + cnt > WAVE) {
-                    wave_lds_sync();
-                    uint64_t b = lane < bc[r] ? buf[r * WAVE + lane] : KEY_INF;
-                    merge_into_list<E>(L[r], b);
-                    bc[r] = 0;
-                    tau[r] = key_dist(list_at<E>(L[r], kp - 1));
-                    mask = __ballot(valid && d <= tau[r]);
-                    cnt = __popcll(mask);
-                    wave_lds_sync();
+            for (int c = 0; c < M; ++c) xc[c] = xn[c];
+            jc_o = jn_o;
+        }
+    }
+    // then every superblock within reach (boxes tested 64 at a time, one per
+    // lane), and inside it every tile within reach (16 lanes)
+    for (int sb0 = 0; sb0 < nsb; sb0 += WAVE) {
+        const int sbl = sb0 + lane;
+        bool near = false;
+        if (sbl < nsb) near = box_gap2<M>(sv.sbox + static_cast<size_t>(sbl) * 2 * M, glo, ghi) <= taumax;
+        uint64_t sbm = __ballot(near);
+        while (sbm) {
+            const int sb = sb0 + __builtin_ctzll(sbm);
+            sbm &= sbm - 1;
+            const int tl = sb * SB_TILES + lane;
+            bool tnear = false;
+            if (lane < SB_TILES && tl < ntiles && (tl < a0 || tl > a1))
+                tnear = box_gap2<M>(sv.tbox + static_cast<size_t>(tl) * 2 * M, glo, ghi) <= taumax;
+            uint64_t tm = __ballot(tnear);
+            if (!tm) continue;
+            int t = sb * SB_TILES + __builtin_ctzll(tm);
+            tm &= tm - 1;
+            load_tile<M>(sv, n, t, lane, xc, jc_o);
+            while (t >= 0) {
+                int tn = -1;
+                float xn[M];
+                uint32_t jn_o = 0;
+                if (tm) {
+                    tn = sb * SB_TILES + __builtin_ctzll(tm);
+                    tm &= tm - 1;
+                    load_tile<M>(sv, n, tn, lane, xn, jn_o);
                 }
-                if ((mask >> lane) & 1ull) buf[r * WAVE + bc[r] + mbcnt64(mask)] = make_key(d, j);
-                bc[r] += cnt;
+                score_tile<M, R, E>(q, xc, jc_o, t * TILE + lane < n, n, t, kp, rows_here, lane, buf, L, tau, bc,
+                                    taumax, pairs);
+                if (tn >= 0) {
+#pragma unroll
+                    for (int c = 0; c < M; ++c) xc[c] = xn[c];
+                    jc_o = jn_o;
+                }
+                t = tn;
             }
         }
     }
@@ -98,8 +231,8 @@ __global__ __launch_bounds__(256) void k_select_direct(const float* __restrict__
             uint64_t b = lane < bc[r] ? buf[r * WAVE + lane] : KEY_INF;
             merge_into_list<E>(L[r], b);
         }
-        const int i = row0 + r;
-        if (i < n) {
+        if (row0 + r < n) {
+            const int i = sv.perm[row0 + r];
             uint64_t* dst = keys_out + static_cast<size_t>(i) * kp;
 #pragma unroll
             for (int s = 0; s < E; ++s) {
@@ -109,89 +242,112 @@ __global__ __launch_bounds__(256) void k_select_direct(const float* __restrict__
             const float sl = key_dist(list_at<E>(L[r], kp - 1));
             if (lane == 0) slast_out[i] = sl;
         }
+    }
+    if (pair_count && lane == 0) atomicAdd(pair_count, pairs);
+}
+
+// ---- spatial order of the direct path
+// Bounding box of the samples: per-block partial minima / maxima, then one block.
+__global__ __launch_bounds__(256) void k_bbox_partial(const float* __restrict__ X, int n, int m, int rows_per_block,
+                                                      float* __restrict__ part)
+{
+    __shared__ float sl[256], sh[256];
+    const int r0 = blockIdx.x * rows_per_block, r1 = min(n, r0 + rows_per_block);
+    for (int c = 0; c < m; ++c) {
+        float lo = __uint_as_float(0x7F800000u), hi = -__uint_as_float(0x7F800000u);
+        for (int r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+            const float v = X[static_cast<size_t>(r) * m + c];
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+        sl[threadIdx.x] = lo;
+        sh[threadIdx.x] = hi;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) {
+                sl[threadIdx.x] = fminf(sl[threadIdx.x], sl[threadIdx.x + o]);
+                sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + o]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            part[static_cast<size_t>(blockIdx.x) * 2 * m + c] = sl[0];
+            part[static_cast<size_t>(blockIdx.x) * 2 * m + m + c] = sh[0];
+        }
+        __syncthreads();
     }
 }
 
-// Generic-dimension variant (any m): the query row is read with wave-uniform
-// loads, each lane gathers its candidate's coordinates.
-template <int R, int E>
-__global__ __launch_bounds__(256) void k_select_direct_any(const float* __restrict__ X, int n, int m,
-                                                           int kp, uint64_t* __restrict__ keys_out,
-                                                           float* __restrict__ slast_out)
+// Morton code of every sample: each coordinate quantised to b = min(31, 63 / m) bits
+// over the bounding box (the box partials are reduced here, redundantly per
+// thread: at most 1024 partials of 2m values), bits interleaved from the most
+// significant. value = sample index, so a stable sort breaks ties by index.
+__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ X, int n, int m,
+                                                const float* __restrict__ part, int nparts,
+                                                uint64_t* __restrict__ code, int32_t* __restrict__ vals)
 {
-    __shared__ uint64_t sbuf[4][R][WAVE];
-    const int lane = lane_id();
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int row0 = (blockIdx.x * 4 + wave) * R;
-    if (row0 >= n) return;
-    const float* qrow[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) qrow[r] = X + static_cast<size_t>(min(row0 + r, n - 1)) * m;
-    uint64_t L[R][E];
-    float tau[R];
-    int bc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-#pragma unroll
-        for (int s = 0; s < E; ++s) L[r][s] = KEY_INF;
-        tau[r] = __uint_as_float(0x7F800000u);
-        bc[r] = 0;
+    __shared__ float s_lo[8], s_scale[8];
+    const int bits = min(31, 63 / m);
+    if (threadIdx.x < m) {
+        const int c = threadIdx.x;
+        float lo = __uint_as_float(0x7F800000u), hi = -__uint_as_float(0x7F800000u);
+        for (int b = 0; b < nparts; ++b) {
+            lo = fminf(lo, part[static_cast<size_t>(b) * 2 * m + c]);
+            hi = fmaxf(hi, part[static_cast<size_t>(b) * 2 * m + m + c]);
+        }
+        const float ext = hi - lo;
+        s_lo[c] = lo;
+        s_scale[c] = ext > 0.f ? static_cast<float>(1ull << bits) / ext : 0.f;
     }
-    uint64_t* buf = &sbuf[wave][0][0];
-    for (int j0 = 0; j0 < n; j0 += WAVE) {
-        const int j = j0 + lane;
-        const bool valid = j < n;
-        const float* xj = X + static_cast<size_t>(valid ? j : n - 1) * m;
-        float d[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) d[r] = 0.f;
-        for (int c = 0; c < m; ++c) {
-            const float xc = xj[c];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const float t = qrow[r][c] - xc;
-                d[r] = fmaf(t, t, d[r]);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            uint64_t mask = __ballot(valid && d[r] <= tau[r]);
-            if (mask) {
-                int cnt = __popcll(mask);
-                if (bc[r] + cnt > WAVE) {
-                    wave_lds_sync();
-                    uint64_t b = lane < bc[r] ? buf[r * WAVE + lane] : KEY_INF;
-                    merge_into_list<E>(L[r], b);
-                    bc[r] = 0;
-                    tau[r] = key_dist(list_at<E>(L[r], kp - 1));
-                    mask = __ballot(valid && d[r] <= tau[r]);
-                    cnt = __popcll(mask);
-                    wave_lds_sync();
-                }
-                if ((mask >> lane) & 1ull) buf[r * WAVE + bc[r] + mbcnt64(mask)] = make_key(d[r], j);
-                bc[r] += cnt;
-            }
-        }
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t qc[8];
+    const uint32_t qmax = static_cast<uint32_t>((1ull << bits) - 1);
+    for (int c = 0; c < m; ++c) {
+        const float t = (X[static_cast<size_t>(i) * m + c] - s_lo[c]) * s_scale[c];
+        const float tc = fminf(fmaxf(t, 0.f), static_cast<float>(qmax));
+        qc[c] = min(static_cast<uint32_t>(tc), qmax);
     }
-    wave_lds_sync();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (bc[r] > 0) {
-            uint64_t b = lane < bc[r] ? buf[r * WAVE + lane] : KEY_INF;
-            merge_into_list<E>(L[r], b);
-        }
-        const int i = row0 + r;
-        if (i < n) {
-            uint64_t* dst = keys_out + static_cast<size_t>(i) * kp;
-#pragma unroll
-            for (int s = 0; s < E; ++s) {
-                const int t = s * WAVE + lane;
-                if (t < kp) dst[t] = L[r][s];
-            }
-            const float sl = key_dist(list_at<E>(L[r], kp - 1));
-            if (lane == 0) slast_out[i] = sl;
+    uint64_t z = 0;
+    for (int b = bits - 1; b >= 0; --b)
+        for (int c = 0; c < m; ++c) z = (z << 1) | ((qc[c] >> b) & 1u);
+    code[i] = z;
+    vals[i] = i;
+}
+
+__global__ __launch_bounds__(256) void k_gather_rows(const float* __restrict__ X, int n, int m,
+                                                     const int32_t* __restrict__ perm, float* __restrict__ Xs)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(n) * m) return;
+    const int p = static_cast<int>(t / m), c = static_cast<int>(t % m);
+    Xs[t] = X[static_cast<size_t>(perm[p]) * m + c];
+}
+
+// Box of `span` consecutive rows starting at row `first` of each group g
+// (rows beyond n are ignored); used for tiles over Xs and for superblocks over
+// tile boxes (span 16, rows = boxes, with `boxes` set).
+__global__ __launch_bounds__(256) void k_group_boxes(const float* __restrict__ src, int rows, int m, int span,
+                                                     int groups, int boxes, float* __restrict__ out)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(groups) * m) return;
+    const int g = static_cast<int>(t / m), c = static_cast<int>(t % m);
+    const int r0 = g * span, r1 = min(rows, r0 + span);
+    float lo = __uint_as_float(0x7F800000u), hi = -__uint_as_float(0x7F800000u);
+    for (int r = r0; r < r1; ++r) {
+        if (boxes) {
+            lo = fminf(lo, src[static_cast<size_t>(r) * 2 * m + c]);
+            hi = fmaxf(hi, src[static_cast<size_t>(r) * 2 * m + m + c]);
+        } else {
+            const float v = src[static_cast<size_t>(r) * m + c];
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
         }
     }
+    out[static_cast<size_t>(g) * 2 * m + c] = lo;
+    out[static_cast<size_t>(g) * 2 * m + m + c] = hi;
 }
 
 // -------------------------------------------------------------------- refine
@@ -512,43 +668,64 @@ __global__ __launch_bounds__(FB_THREADS) void k_fallback(const float* __restrict
 }
 
 // -------------------------------------------------------------------- launchers
+int spatial_bbox_blocks(int n) { return std::max(1, std::min(1024, (n + 4095) / 4096)); }
+int spatial_tiles(int n) { return (n + TILE - 1) / TILE; }
+int spatial_superblocks(int n) { return (spatial_tiles(n) + SB_TILES - 1) / SB_TILES; }
+
+hipError_t launch_spatial_codes(const float* X, int n, int m, float* bbox_part, uint64_t* code, int32_t* vals,
+                                hipStream_t st)
+{
+    if (m < 1 || m > 8) return hipErrorInvalidValue;
+    const int nb = spatial_bbox_blocks(n);
+    const int rpb = (n + nb - 1) / nb;
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(256), 0, st, X, n, m, rpb, bbox_part);
+    hipLaunchKernelGGL(k_morton, dim3((n + 255) / 256), dim3(256), 0, st, X, n, m, bbox_part, nb, code, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_spatial_layout(const float* X, int n, int m, const int32_t* perm, float* Xs, float* tbox,
+                                 float* sbox, hipStream_t st)
+{
+    const int64_t tot = static_cast<int64_t>(n) * m;
+    hipLaunchKernelGGL(k_gather_rows, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st, X, n, m, perm,
+                       Xs);
+    const int nt = spatial_tiles(n), ns = spatial_superblocks(n);
+    hipLaunchKernelGGL(k_group_boxes, dim3((nt * m + 255) / 256), dim3(256), 0, st, Xs, n, m, TILE, nt, 0, tbox);
+    hipLaunchKernelGGL(k_group_boxes, dim3((ns * m + 255) / 256), dim3(256), 0, st, tbox, nt, m, SB_TILES, ns, 1,
+                       sbox);
+    return hipGetLastError();
+}
+
 template <int M, int R>
-static hipError_t launch_select_m(const float* X, int n, int kp, uint64_t* keys, float* slast, hipStream_t st)
+static hipError_t launch_select_m(const SpatialView& sv, int n, int kp, uint64_t* keys, float* slast,
+                                  unsigned long long* pairs, hipStream_t st)
 {
     const int rows_per_block = 4 * R;
     const dim3 grid((n + rows_per_block - 1) / rows_per_block), block(256);
     if (kp <= 64)
-        hipLaunchKernelGGL((k_select_direct<M, R, 1>), grid, block, 0, st, X, n, kp, keys, slast);
+        hipLaunchKernelGGL((k_select_direct<M, R, 1>), grid, block, 0, st, sv, n, kp, keys, slast, pairs);
     else if (kp <= 128)
-        hipLaunchKernelGGL((k_select_direct<M, R, 2>), grid, block, 0, st, X, n, kp, keys, slast);
+        hipLaunchKernelGGL((k_select_direct<M, R, 2>), grid, block, 0, st, sv, n, kp, keys, slast, pairs);
     else
-        hipLaunchKernelGGL((k_select_direct<M, R, 4>), grid, block, 0, st, X, n, kp, keys, slast);
+        hipLaunchKernelGGL((k_select_direct<M, R, 4>), grid, block, 0, st, sv, n, kp, keys, slast, pairs);
     return hipGetLastError();
 }
 
-hipError_t launch_select_direct(const float* X, int n, int m, int kp, uint64_t* keys, float* slast,
-                                hipStream_t st)
+hipError_t launch_select_direct(const float* Xs, const int32_t* perm, const float* tbox, const float* sbox, int n,
+                                int m, int kp, uint64_t* keys, float* slast, unsigned long long* pairs, hipStream_t st)
 {
+    const SpatialView sv = {Xs, perm, tbox, sbox};
     switch (m) {
-    case 1: return launch_select_m<1, 8>(X, n, kp, keys, slast, st);
-    case 2: return launch_select_m<2, 8>(X, n, kp, keys, slast, st);
-    case 3: return launch_select_m<3, 8>(X, n, kp, keys, slast, st);
-    case 4: return launch_select_m<4, 8>(X, n, kp, keys, slast, st);
-    case 5: return launch_select_m<5, 4>(X, n, kp, keys, slast, st);
-    case 6: return launch_select_m<6, 4>(X, n, kp, keys, slast, st);
-    case 7: return launch_select_m<7, 4>(X, n, kp, keys, slast, st);
-    case 8: return launch_select_m<8, 4>(X, n, kp, keys, slast, st);
-    default: break;
+    case 1: return launch_select_m<1, 8>(sv, n, kp, keys, slast, pairs, st);
+    case 2: return launch_select_m<2, 8>(sv, n, kp, keys, slast, pairs, st);
+    case 3: return launch_select_m<3, 8>(sv, n, kp, keys, slast, pairs, st);
+    case 4: return launch_select_m<4, 8>(sv, n, kp, keys, slast, pairs, st);
+    case 5: return launch_select_m<5, 4>(sv, n, kp, keys, slast, pairs, st);
+    case 6: return launch_select_m<6, 4>(sv, n, kp, keys, slast, pairs, st);
+    case 7: return launch_select_m<7, 4>(sv, n, kp, keys, slast, pairs, st);
+    case 8: return launch_select_m<8, 4>(sv, n, kp, keys, slast, pairs, st);
+    default: return hipErrorInvalidValue;
     }
-    constexpr int R = 4;
-    const dim3 grid((n + 4 * R - 1) / (4 * R)), block(256);
-    if (kp <= 64)
-        hipLaunchKernelGGL((k_select_direct_any<R, 1>), grid, block, 0, st, X, n, m, kp, keys, slast);
-    else if (kp <= 128)
-        hipLaunchKernelGGL((k_select_direct_any<R, 2>), grid, block, 0, st, X, n, m, kp, keys, slast);
-    else
-        hipLaunchKernelGGL((k_select_direct_any<R, 4>), grid, block, 0, st, X, n, m, kp, keys, slast);
-    return hipGetLastError();
 }
 
 hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,

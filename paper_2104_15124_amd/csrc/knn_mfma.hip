@@ -238,7 +238,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
                                                           const float* __restrict__ ynorm2,
                                                           const unsigned* __restrict__ rmax_bits, ErrModel em,
                                                           uint64_t* __restrict__ lists, float* __restrict__ lb_out,
-                                                          BucketArgs ba)
+                                                          BucketArgs ba, unsigned long long* __restrict__ pair_count)
 {
     using elem = typename Tr::elem;
     using frag = typename Tr::frag;
@@ -308,6 +308,8 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
     }
     if (lane < NQ) s_cnt[wave][lane] = 0;
     wave_lds_sync();
+    const int nq_valid = __popcll(__ballot(lane < NQ && s_qid[wave][lane] >= 0));
+    unsigned long long pairs = 0;
 
     // a tile of the tile-major candidate operand is one contiguous block, laid
     // out exactly like an LDS stage: it moves as 16-byte pieces
@@ -357,6 +359,8 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
 
         const int cand = LEARNED ? cid_cur : tile * 32 + (lane & 31);
         const bool valid = LEARNED ? cand >= 0 : cand < n;
+        pairs += static_cast<unsigned long long>(nq_valid) *
+                 static_cast<unsigned long long>(__popcll(__ballot(valid) & 0xFFFFFFFFull));
         uint32_t flush = 0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -412,6 +416,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
             merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][q][0], s_cnt[wave][q], kp);
         wave_lds_sync();
     }
+    if (pair_count && lane == 0) atomicAdd(pair_count, pairs);
     if constexpr (LEARNED) return;
     // certificate lower bound for the candidates left out of each list
     const double R = static_cast<double>(__uint_as_float(*rmax_bits));
@@ -449,7 +454,7 @@ hipError_t launch_prep(const float* X, int n, int m, int split, int kpad, double
 template <class Tr, int KS, int WV>
 static hipError_t launch_sel(const void* Aq, const void* Bc, int n, int kp, const float* ynorm2, const unsigned* rmax,
                              ErrModel em, uint64_t* lists, int cap, float* lb, const BucketArgs* ba, int max_work,
-                             hipStream_t st)
+                             unsigned long long* pairs, hipStream_t st)
 {
     using elem = typename Tr::elem;
     const int rows_per_block = WV * 32;
@@ -464,20 +469,20 @@ static hipError_t launch_sel(const void* Aq, const void* Bc, int n, int kp, cons
         const dim3 grid(max_work);
         if (cap == 128)
             hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2, true>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
-                               lists, lb, *ba);
+                               lists, lb, *ba, pairs);
         else
             hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4, true>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
-                               lists, lb, *ba);
+                               lists, lb, *ba, pairs);
         return hipGetLastError();
     }
     const dim3 grid((n + rows_per_block - 1) / rows_per_block);
     const BucketArgs none = {};
     if (cap == 128)
         hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2, false>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
-                           lists, lb, none);
+                           lists, lb, none, pairs);
     else
         hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4, false>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
-                           lists, lb, none);
+                           lists, lb, none, pairs);
     return hipGetLastError();
 }
 
@@ -500,7 +505,7 @@ int mfma_pick_ksteps(int split, int needed)
 }
 
 #define KVB_SEL_CASE(TR, K, WV) \
-    case K: return launch_sel<TR, K, WV>(Aq, Bc, n, kp, ynorm2, rmax, em, lists, cap, lb, ba, max_work, st);
+    case K: return launch_sel<TR, K, WV>(Aq, Bc, n, kp, ynorm2, rmax, em, lists, cap, lb, ba, max_work, pairs, st);
 
 int select_mfma_queries_per_block(int split, int kpad)
 {
@@ -511,7 +516,7 @@ int select_mfma_queries_per_block(int split, int kpad)
 
 hipError_t launch_select_mfma(int split, const void* Aq, const void* Bc, int n, int kpad, int kp, const float* ynorm2,
                               const unsigned* rmax, ErrModel em, uint64_t* lists, int cap, float* lb,
-                              const BucketArgs* ba, int max_work, hipStream_t st)
+                              const BucketArgs* ba, int max_work, unsigned long long* pairs, hipStream_t st)
 {
     const int ks = kpad / mfma_kstep(split);
     if (split == 0) {

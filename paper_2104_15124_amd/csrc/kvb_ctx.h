@@ -54,6 +54,8 @@ struct kvb_ctx_s {
     kvb::TuneResult* tune_host = nullptr;   // pinned
     int* fb_count_dev = nullptr;            // fallback rows of the last kvb_knn
     int* fb_count_host = nullptr;           // pinned
+    unsigned long long* pairs_dev = nullptr;   // candidate pairs scored by the last kvb_knn
+    unsigned long long* pairs_host = nullptr;  // pinned
     double* loss_dev = nullptr;             // per-epoch losses of kvb_part_train (device)
     int loss_cap = 0;
     kvbh::PartState part;

@@ -41,13 +41,49 @@ __device__ __forceinline__ uint32_t key_idx(uint64_t k) { return static_cast<uin
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Value of lane (lane ^ j) for j in {1, 2, 4, 8, 16, 32}, without the LDS
+// crossbar: DPP quad permutations (j = 1, 2), row shifts (j = 4), a row
+// rotation (j = 8), and the gfx950 row-swap permutes (j = 16, 32). Any other
+// j falls back to ds_bpermute. Calls with a constant j fold to one path.
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int j)
+{
+    const int lane = __lane_id();
+    switch (j) {
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);    // quad_perm [1,0,3,2]
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);    // quad_perm [2,3,0,1]
+    case 4: {
+        const uint32_t up = __builtin_amdgcn_mov_dpp(v, 0x104, 0xF, 0xF, true);   // row_shl:4, lane + 4
+        const uint32_t dn = __builtin_amdgcn_mov_dpp(v, 0x114, 0xF, 0xF, true);   // row_shr:4, lane - 4
+        return (lane & 4) ? dn : up;
+    }
+    case 8: return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);   // row_ror:8
+    case 16: {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    }
+    case 32: {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? r[0] : r[1];
+    }
+    default: return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), j, WAVE));
+    }
+}
+
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask)
 {
-    int lo = static_cast<int>(static_cast<uint32_t>(v));
-    int hi = static_cast<int>(static_cast<uint32_t>(v >> 32));
-    lo = __shfl_xor(lo, mask, WAVE);
-    hi = __shfl_xor(hi, mask, WAVE);
-    return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+    const uint32_t lo = xor_lane(static_cast<uint32_t>(v), mask);
+    const uint32_t hi = xor_lane(static_cast<uint32_t>(v >> 32), mask);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ float shfl_xor_f32(float v, int mask)
+{
+    return __uint_as_float(xor_lane(__float_as_uint(v), mask));
+}
+
+__device__ __forceinline__ double shfl_xor_f64(double v, int mask)
+{
+    return __longlong_as_double(static_cast<long long>(shfl_xor_u64(static_cast<uint64_t>(__double_as_longlong(v)), mask)));
 }
 
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
@@ -88,21 +124,21 @@ __device__ __forceinline__ void wave_lds_sync()
 // ---------------------------------------------------------------- bitonic networks
 // Compare-exchange with partner distance j < 64 (partner in another lane) in a
 // bitonic stage of block size kb (ascending where element index & kb == 0).
-template <int E>
+template <int E, bool DESC = false>
 __device__ __forceinline__ void cx_lanes(uint64_t (&v)[E], int kb, int j, int lane)
 {
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         uint64_t o = shfl_xor_u64(v[s], j);
         int i = s * WAVE + lane;
-        bool up = (i & kb) == 0;
+        bool up = ((i & kb) == 0) != DESC;
         bool lower = (lane & j) == 0;
         v[s] = (up == lower) ? umin64(v[s], o) : umax64(v[s], o);
     }
 }
 
 // Compare-exchange with partner distance js*64 (partner in another slot, same lane).
-template <int E>
+template <int E, bool DESC = false>
 __device__ __forceinline__ void cx_slots(uint64_t (&v)[E], int kb, int js, int lane)
 {
 #pragma unroll
@@ -110,7 +146,7 @@ __device__ __forceinline__ void cx_slots(uint64_t (&v)[E], int kb, int js, int l
         int p = s ^ js;
         if (p > s) {
             int i = s * WAVE + lane;
-            bool up = (i & kb) == 0;
+            bool up = ((i & kb) == 0) != DESC;
             uint64_t a = v[s], b = v[p];
             bool sw = up ? (a > b) : (a < b);
             v[s] = sw ? b : a;
@@ -119,8 +155,9 @@ __device__ __forceinline__ void cx_slots(uint64_t (&v)[E], int kb, int js, int l
     }
 }
 
-// Full ascending sort of the 64*E keys held by the wavefront.
-template <int E>
+// Full sort of the 64*E keys held by the wavefront (ascending, or descending
+// with DESC).
+template <int E, bool DESC = false>
 __device__ __forceinline__ void bitonic_sort(uint64_t (&v)[E])
 {
     const int lane = lane_id();
@@ -128,10 +165,12 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&v)[E])
     for (int kb = 2; kb <= WAVE * E; kb <<= 1) {
 #pragma unroll
         for (int j = kb >> 1; j > 0; j >>= 1) {
+            // the last stage's direction flag (i & 2N) is 0 for every i, so
+            // DESC reverses the whole order
             if (j >= WAVE)
-                cx_slots<E>(v, kb, j / WAVE, lane);
+                cx_slots<E, DESC>(v, kb, j / WAVE, lane);
             else
-                cx_lanes<E>(v, kb, j, lane);
+                cx_lanes<E, DESC>(v, kb, j, lane);
         }
     }
 }
@@ -159,9 +198,8 @@ template <int E>
 __device__ __forceinline__ void merge_into_list(uint64_t (&L)[E], uint64_t b)
 {
     uint64_t B[1] = {b};
-    bitonic_sort<1>(B);
-    uint64_t rev = shfl_u64(B[0], WAVE - 1 - lane_id());
-    L[E - 1] = umin64(L[E - 1], rev);
+    bitonic_sort<1, true>(B);            // descending: B[lane] is the reversed ascending order
+    L[E - 1] = umin64(L[E - 1], B[0]);
     bitonic_merge_asc<E>(L);
 }
 
@@ -181,14 +219,14 @@ __device__ __forceinline__ uint64_t list_at(const uint64_t (&L)[E], int t)
 __device__ __forceinline__ double wave_sum_f64(double v)
 {
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += shfl_xor_f64(v, o);
     return v;
 }
 
 __device__ __forceinline__ float wave_max_f32(float v)
 {
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmaxf(v, shfl_xor_f32(v, o));
     return v;
 }
 

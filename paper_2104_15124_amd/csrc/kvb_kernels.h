@@ -37,8 +37,16 @@ struct TuneResult {
 };
 
 // k-NN
-hipError_t launch_select_direct(const float* X, int n, int m, int kp, uint64_t* keys, float* slast,
+// direct path (m <= 8): spatial order (Morton codes -> sort -> rows, tile and superblock boxes), then the scan
+int spatial_bbox_blocks(int n);
+int spatial_tiles(int n);
+int spatial_superblocks(int n);
+hipError_t launch_spatial_codes(const float* X, int n, int m, float* bbox_part, uint64_t* code, int32_t* vals,
                                 hipStream_t st);
+hipError_t launch_spatial_layout(const float* X, int n, int m, const int32_t* perm, float* Xs, float* tbox,
+                                 float* sbox, hipStream_t st);
+hipError_t launch_select_direct(const float* Xs, const int32_t* perm, const float* tbox, const float* sbox, int n,
+                                int m, int kp, uint64_t* keys, float* slast, unsigned long long* pairs, hipStream_t st);
 hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,
                          const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags,
                          int* fb_count, int* fb_list, int force_period, hipStream_t st);
@@ -56,7 +64,7 @@ int mfma_pick_ksteps(int split, int needed);
 // selection with max_work workgroups (the kernel skips those beyond *ba->n_work).
 hipError_t launch_select_mfma(int split, const void* Aq, const void* Bc, int n, int kpad, int kp, const float* ynorm2,
                               const unsigned* rmax, ErrModel em, uint64_t* lists, int cap, float* lb,
-                              const BucketArgs* ba, int max_work, hipStream_t st);
+                              const BucketArgs* ba, int max_work, unsigned long long* pairs, hipStream_t st);
 int select_mfma_queries_per_block(int split, int kpad);
 
 // passes

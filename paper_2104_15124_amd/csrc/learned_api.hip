@@ -337,6 +337,7 @@ int learned_knn(kvb_ctx ctx, const float* X, int n, int m, int k, int kp, int32_
     hipStream_t st = ctx->stream;
 
     KVB_HIP(ctx, hipMemsetAsync(ctx->fb_count_dev, 0, sizeof(int), st));
+    KVB_HIP(ctx, hipMemsetAsync(ctx->pairs_dev, 0, sizeof(unsigned long long), st));
     {
         Prof pr(ctx, KVB_PROF_ROUTE);
         for (int off = 0; off < n; off += CH) {
@@ -375,7 +376,7 @@ int learned_knn(kvb_ctx ctx, const float* X, int n, int m, int k, int kp, int32_
             ba.cid = cid;
             ba.first = s == 0 ? 1 : 0;
             KVB_HIP(ctx, kvb::launch_select_mfma(split, Aq, Bp, n, kpad, kp, ynorm2, rmax, em, lists, cap, nullptr,
-                                                 &ba, max_work, st));
+                                                 &ba, max_work, ctx->pairs_dev, st));
         }
     }
     {

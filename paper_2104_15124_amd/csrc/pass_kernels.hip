@@ -72,8 +72,8 @@ __device__ __forceinline__ double grid_log(double lo, double hi, int G, int g)
 {
     return lo + (static_cast<double>(g) * (hi - lo)) / static_cast<double>(G - 1);
 }
-constexpr int CHI_MIN_ENTRIES_PER_BLOCK = 16384;
-constexpr int CHI_MAX_BLOCKS = 2048;
+constexpr int CHI_MIN_ENTRIES_PER_BLOCK = 4096;
+constexpr int CHI_MAX_BLOCKS = 4096;
 
 __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __restrict__ idx,
                                                            const float* __restrict__ d2,
@@ -127,32 +127,39 @@ __global__ __launch_bounds__(1024) void k_chi_finish(const double* __restrict__ 
                                                     double log_emin, double log_emax, TuneResult* __restrict__ out)
 {
     __shared__ double chi[256];
-    __shared__ double part4[4][256];
-    const int g = threadIdx.x & 255;
-    const int grp = threadIdx.x >> 8;   // 4 fixed groups of block partials
-    if (g < G) {
-        const int per = (nblocks + 3) / 4;
-        const int b0 = grp * per, b1 = min(nblocks, b0 + per);
-        double s = 0.0;
-        for (int b = b0; b < b1; ++b) s += partial[static_cast<size_t>(b) * G + g];
-        part4[grp][g] = s;
+    __shared__ double slope[256];
+    __shared__ double part[1024];
+    // S fixed slices of the block partials per grid point, each summed in block
+    // order, then the slices in slice order
+    const int Gr = (G + 63) / 64 * 64;
+    const int S = 1024 / Gr;
+    const int g = threadIdx.x % Gr, sl = threadIdx.x / Gr;
+    if (sl < S && g < G) {
+        double a = 0.0;
+        for (int b = sl; b < nblocks; b += S) a += partial[static_cast<size_t>(b) * G + g];
+        part[sl * Gr + g] = a;
     }
     __syncthreads();
-    if (grp == 0 && g < G) {
-        const double s = ((part4[0][g] + part4[1][g]) + part4[2][g]) + part4[3][g];
-        chi[g] = s;
-        out->chi[g] = s;
+    if (threadIdx.x < G) {
+        double a = 0.0;
+        for (int t = 0; t < S; ++t) a += part[t * Gr + threadIdx.x];
+        chi[threadIdx.x] = a;
+        out->chi[threadIdx.x] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x + 1 < G) {
+        const int t = threadIdx.x;
+        const double el = exp(grid_log(log_emin, log_emax, G, t));
+        const double er = exp(grid_log(log_emin, log_emax, G, t + 1));
+        slope[t] = (log(chi[t + 1]) - log(chi[t])) / (log(er) - log(el));
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int best = 0;
         double best_s = -1.0 / 0.0;
         for (int t = 0; t + 1 < G; ++t) {
-            const double el = exp(grid_log(log_emin, log_emax, G, t));
-            const double er = exp(grid_log(log_emin, log_emax, G, t + 1));
-            const double sl = (log(chi[t + 1]) - log(chi[t])) / (log(er) - log(el));
-            if (sl > best_s) {
-                best_s = sl;
+            if (slope[t] > best_s) {
+                best_s = slope[t];
                 best = t;
             }
         }
@@ -186,16 +193,29 @@ __global__ __launch_bounds__(256) void k_logsum_partial(const float* __restrict_
     }
 }
 
-__global__ void k_logsum_finish(const double* __restrict__ partial, int nblocks, int n, double* __restrict__ out)
+__global__ __launch_bounds__(256) void k_logsum_finish(const double* __restrict__ partial, int nblocks, int n,
+                                                      double* __restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double sa[256], sc[256];
     double a = 0.0, c = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
         a += partial[2 * b];
         c += partial[2 * b + 1];
     }
-    const double l2 = 2.0 * (a - c) / static_cast<double>(n) / log(2.0);
-    out[0] = ldexp(1.0, static_cast<int>(round(l2)));
+    sa[threadIdx.x] = a;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sa[threadIdx.x] += sa[threadIdx.x + o];
+            sc[threadIdx.x] += sc[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double l2 = 2.0 * (sa[0] - sc[0]) / static_cast<double>(n) / log(2.0);
+        out[0] = ldexp(1.0, static_cast<int>(round(l2)));
+    }
 }
 
 // ------------------------------------------------------------------ normalisation
@@ -256,7 +276,7 @@ __global__ __launch_bounds__(256) void k_assemble(const int32_t* __restrict__ id
     double Ds = acc.s, Dc = acc.c;
 #pragma unroll
     for (int o = WAVE / 2; o > 0; o >>= 1) {
-        const double os = __shfl_xor(Ds, o, WAVE), oc = __shfl_xor(Dc, o, WAVE);
+        const double os = shfl_xor_f64(Ds, o), oc = shfl_xor_f64(Dc, o);
         const double t = Ds + os;
         Dc += oc + ((fabs(Ds) >= fabs(os)) ? ((Ds - t) + os) : ((os - t) + Ds));
         Ds = t;
@@ -357,7 +377,7 @@ hipError_t launch_grid_scale(const float* ref, const float* rho, int n, double* 
 {
     const int nb = logsum_num_blocks(n);
     hipLaunchKernelGGL(k_logsum_partial, dim3(nb), dim3(256), 0, st, ref, rho, n, partial);
-    hipLaunchKernelGGL(k_logsum_finish, dim3(1), dim3(64), 0, st, partial, nb, n, out);
+    hipLaunchKernelGGL(k_logsum_finish, dim3(1), dim3(256), 0, st, partial, nb, n, out);
     return hipGetLastError();
 }
 

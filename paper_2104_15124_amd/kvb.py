@@ -31,12 +31,11 @@ OPT_FORCE_FALLBACK, OPT_SCRATCH_LIMIT, OPT_BF16_SPLIT = 1, 2, 3
 MODES = {"f32": KNN_F32, "bf16": KNN_BF16, "learned": KNN_LEARNED}
 
 EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb_knn",
-           "kvb_knn_fallback_rows", "kvb_knn_exact_rows", "kvb_bandwidth", "kvb_grid_scale", "kvb_tune_eps",
-           "kvb_assemble_csr", "kvb_part_init", "kvb_part_teacher", "kvb_part_train",
-           "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
-           "kvb_mlp_backward", "kvb_part_num_params", "kvb_part_get_params",
-           "kvb_part_set_params", "kvb_version", "kvb_profile_enable", "kvb_profile_read",
-           "kvb_profile_name")
+           "kvb_knn_fallback_rows", "kvb_knn_pairs", "kvb_knn_exact_rows", "kvb_bandwidth",
+           "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_part_init", "kvb_part_teacher",
+           "kvb_part_train", "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
+           "kvb_mlp_backward", "kvb_part_num_params", "kvb_part_get_params", "kvb_part_set_params",
+           "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name")
 PROF_SLOTS = 12
 
 
@@ -67,6 +66,7 @@ def load_library(path: str = LIB_PATH):
     L.kvb_set_option.argtypes = [_vp, _i32, _i64]
     L.kvb_knn.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp]
     L.kvb_knn_fallback_rows.argtypes = [_vp, ctypes.POINTER(_i64)]
+    L.kvb_knn_pairs.argtypes = [_vp, ctypes.POINTER(_f64)]
     L.kvb_knn_exact_rows.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _i64, _vp, _vp]
     L.kvb_bandwidth.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _vp, _f64, _f64, _f64, _vp, _vp]
     L.kvb_grid_scale.argtypes = [_vp, _vp, _vp, _i64, ctypes.POINTER(_f64)]
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
     L.kvb_profile_name.argtypes = [_i32]
     L.kvb_profile_name.restype = ctypes.c_char_p
     for name in ("kvb_create", "kvb_set_option", "kvb_knn", "kvb_knn_fallback_rows", "kvb_knn_exact_rows",
+                 "kvb_knn_pairs",
                  "kvb_bandwidth",
                  "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_profile_enable",
                  "kvb_profile_read", "kvb_part_init", "kvb_part_teacher", "kvb_part_train",
@@ -195,6 +196,14 @@ def knn_fallback_rows(ctx: Context | None = None) -> int:
     c = _i64()
     ctx.check(ctx.lib.kvb_knn_fallback_rows(ctx.h, ctypes.byref(c)))
     return int(c.value)
+
+
+def knn_pairs(ctx: Context | None = None) -> float:
+    """Candidate pairs scored by the last knn call on the context."""
+    ctx = ctx or context()
+    p = _f64()
+    ctx.check(ctx.lib.kvb_knn_pairs(ctx.h, ctypes.byref(p)))
+    return float(p.value)
 
 
 def knn_exact_rows(X: torch.Tensor, k: int, rows: torch.Tensor, ctx: Context | None = None):
