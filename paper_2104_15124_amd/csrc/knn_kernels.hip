@@ -368,12 +368,97 @@ __device__ __forceinline__ double dist2_f64(const float* __restrict__ a, const f
     return s;
 }
 
+// Squared distances of a row's candidates computed cooperatively: groups of
+// LPC lanes share one candidate (coalesced reads of its row, float4 where the
+// rows are 16-byte aligned), accumulate in float64 (differences of float32
+// values and their squares are exact or nearly so in float64) and reduce
+// inside the group; the result reaches the lane that owns the candidate's key.
+// d[s] receives the distance of key slot s of this lane (unchanged where the
+// key is KEY_INF or the row itself).
+template <int E, int LPC>
+__device__ __forceinline__ void group_distances(const float* __restrict__ X, int m, int i, int kp, bool vec4,
+                                                const uint64_t (&v)[E], double (&d)[E])
+{
+    constexpr int CPW = WAVE / LPC;   // candidates per pass
+    // pieces of the row per lane: float4 pieces (m <= 16 LPC) or floats (m <= 16 LPC)
+    constexpr int QMAX = 16;
+    const int lane = lane_id();
+    const int g = lane / LPC, gl = lane % LPC;
+    const float* xi = X + static_cast<size_t>(i) * m;
+    float4 q4[4];
+    float q1[QMAX];
+    const int nit = vec4 ? (m + 4 * LPC - 1) / (4 * LPC) : (m + LPC - 1) / LPC;
+#pragma unroll
+    for (int it = 0; it < QMAX; ++it) {
+        q1[it] = 0.f;
+        if (!vec4 && it < nit) {
+            const int c = gl + LPC * it;
+            if (c < m) q1[it] = xi[c];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        q4[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (vec4 && it < nit) {
+            const int c = 4 * (gl + LPC * it);
+            if (c < m) q4[it] = *reinterpret_cast<const float4*>(xi + c);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int cj = (v[s] != KEY_INF) ? static_cast<int>(key_idx(v[s])) : -1;
+        for (int t0 = s * WAVE; t0 < min(kp, (s + 1) * WAVE); t0 += CPW) {
+            const int owner = (t0 % WAVE) + g;                 // lane holding this group's candidate
+            const int j = __shfl(cj, owner, WAVE);
+            double acc = 0.0;
+            if (j >= 0 && j != i && t0 + g < kp) {
+                const float* xj = X + static_cast<size_t>(j) * m;
+                if (vec4) {
+#pragma unroll
+                    for (int it = 0; it < 4; ++it) {
+                        const int c = 4 * (gl + LPC * it);
+                        if (it < nit && c < m) {
+                            const float4 b = *reinterpret_cast<const float4*>(xj + c);
+                            const double e0 = static_cast<double>(q4[it].x) - b.x;
+                            const double e1 = static_cast<double>(q4[it].y) - b.y;
+                            const double e2 = static_cast<double>(q4[it].z) - b.z;
+                            const double e3 = static_cast<double>(q4[it].w) - b.w;
+                            acc = fma(e0, e0, acc);
+                            acc = fma(e1, e1, acc);
+                            acc = fma(e2, e2, acc);
+                            acc = fma(e3, e3, acc);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int it = 0; it < QMAX; ++it) {
+                        const int c = gl + LPC * it;
+                        if (it < nit && c < m) {
+                            const double e0 = static_cast<double>(q1[it]) - xj[c];
+                            acc = fma(e0, e0, acc);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 1; o < LPC; o <<= 1) acc += shfl_xor_f64(acc, o);
+            // the group leader's sum goes to the owner lane
+            const int src = (lane - (t0 % WAVE)) * LPC;
+            const double got = __shfl(acc, src >= 0 && src < WAVE ? src : 0, WAVE);
+            if (lane >= t0 % WAVE && lane < t0 % WAVE + CPW) d[s] = got;
+        }
+    }
+}
+
 // One wavefront per row. keys: [n, kstride] candidate keys from a select
 // kernel (the first kp of each row are used), slast: per row, a bound on the
 // candidates the select step dropped, turned into a lower bound on their true
 // squared distance by lb_scale (direct tiles: the kp-th score times
 // 1/(1 + select error); matrix-core tiles: the bound itself, lb_scale = 1).
-template <int E>
+// slast == nullptr: no bound (learned routing). LPC == 0: each lane computes
+// its own candidates' distances (compensated float32, short rows); LPC > 0:
+// groups of LPC lanes per candidate (group_distances, long rows).
+template <int E, int LPC>
 __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int n, int m, int k, int kp,
                                                 int kstride, const uint64_t* __restrict__ keys,
                                                 const float* __restrict__ slast, float lb_scale,
@@ -386,20 +471,41 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
     const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (i >= n) return;
     const float* xi = X + static_cast<size_t>(i) * m;
-    // compensated float32 distances of the candidates, self removed
+    // candidate distances, self removed
     uint64_t v[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         const int t = s * WAVE + lane;
-        uint64_t key = t < kp ? keys[static_cast<size_t>(i) * kstride + t] : KEY_INF;
-        if (key != KEY_INF) {
-            const uint32_t j = key_idx(key);
-            if (static_cast<int>(j) == i)
-                key = KEY_INF;
-            else
-                key = make_key(comp_dist2(xi, X + static_cast<size_t>(j) * m, m), j);
+        v[s] = t < kp ? keys[static_cast<size_t>(i) * kstride + t] : KEY_INF;
+    }
+    if constexpr (LPC == 0) {
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            uint64_t key = v[s];
+            if (key != KEY_INF) {
+                const uint32_t j = key_idx(key);
+                if (static_cast<int>(j) == i)
+                    key = KEY_INF;
+                else
+                    key = make_key(comp_dist2(xi, X + static_cast<size_t>(j) * m, m), j);
+            }
+            v[s] = key;
         }
-        v[s] = key;
+    } else {
+        double dd[E];
+#pragma unroll
+        for (int s = 0; s < E; ++s) dd[s] = 0.0;
+        const bool vec4 = (m % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+        group_distances<E, LPC>(X, m, i, kp, vec4, v, dd);
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            uint64_t key = v[s];
+            if (key != KEY_INF) {
+                const uint32_t j = key_idx(key);
+                key = static_cast<int>(j) == i ? KEY_INF : make_key(static_cast<float>(dd[s]), j);
+            }
+            v[s] = key;
+        }
     }
     bitonic_sort<E>(v);
 
@@ -728,20 +834,43 @@ hipError_t launch_select_direct(const float* Xs, const int32_t* perm, const floa
     }
 }
 
+template <int LPC>
+static void launch_refine_l(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,
+                            const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags, int* fb_count,
+                            int* fb_list, int force_period, hipStream_t st)
+{
+    const dim3 grid((n + 3) / 4), block(256);
+    if (kp <= 64)
+        hipLaunchKernelGGL((k_refine<1, LPC>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
+                           d2, flags, fb_count, fb_list, force_period);
+    else if (kp <= 128)
+        hipLaunchKernelGGL((k_refine<2, LPC>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
+                           d2, flags, fb_count, fb_list, force_period);
+    else
+        hipLaunchKernelGGL((k_refine<4, LPC>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
+                           d2, flags, fb_count, fb_list, force_period);
+}
+
 hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,
                          const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags,
                          int* fb_count, int* fb_list, int force_period, hipStream_t st)
 {
-    const dim3 grid((n + 3) / 4), block(256);
-    if (kp <= 64)
-        hipLaunchKernelGGL((k_refine<1>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
-                           d2, flags, fb_count, fb_list, force_period);
-    else if (kp <= 128)
-        hipLaunchKernelGGL((k_refine<2>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
-                           d2, flags, fb_count, fb_list, force_period);
+    // rows of up to 24 floats stay with one lane per candidate; longer rows are
+    // read by groups of lanes (each lane covers at most 4 float4 pieces)
+    if (m <= 24)
+        launch_refine_l<0>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
+                           force_period, st);
+    else if (m <= 64)
+        launch_refine_l<16>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
+                            force_period, st);
+    else if (m <= 128)
+        launch_refine_l<32>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
+                            force_period, st);
+    else if (m <= 1024)
+        launch_refine_l<64>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
+                            force_period, st);
     else
-        hipLaunchKernelGGL((k_refine<4>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
-                           d2, flags, fb_count, fb_list, force_period);
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -172,6 +172,9 @@ MFMA_CASES = [
     ("bf16x1_nl5_m64", "nonlinear5", 1200, 64, 32, 32, "bf16", 1, 30),
     ("bf16x3_tiny_n33", "gauss", 33, 20, 9, 4, "bf16", 3, 31),
     ("bf16x3_k1", "gauss", 100, 16, 1, 0, "bf16", 3, 32),
+    # rows of odd length (no float4 reads in the re-rank)
+    ("f32_gauss_m37", "gauss", 1300, 37, 24, 16, "f32", 3, 33),
+    ("bf16x3_gauss_m150", "gauss", 900, 150, 16, 16, "bf16", 3, 34),
 ]
 
 
