@@ -27,6 +27,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from the committed counter runs (profiles/traffic.txt),
+    or None when there are none for this kernel or its sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#") or f[0] != workload or f[1] != kernel:
+            continue
+        h = hashlib.sha256()
+        for src in f[2].split("+"):
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != f[3]:
+            log(f"  traffic: the counters in profiles/{f[6]} predate changes to {f[2]}; not reported")
+            return None
+        return int(f[4]) + int(f[5])
+    return None
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,7 +169,7 @@ def main() -> int:
         achieved = pairs * ops_per_pair / sel_avg_s / 1e12
         roofline = {"kernel": "knn_select", "bound": "alu", "achieved": round(achieved, 3),
                     "peak": round(ALU_PEAK_TOPS, 3), "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
-                    "traffic": None, "avg_ms": round(sel_avg_s * 1e3, 4),
+                    "traffic": measured_traffic(w.name, "knn_select") if not args.n else None, "avg_ms": round(sel_avg_s * 1e3, 4),
                     "work": f"{ops_per_pair} VALU lane-ops per scored candidate pair, {pairs:.4g} pairs per launch "
                             f"(the pairs the bounding-box scan did not skip)"}
     else:
@@ -156,7 +178,7 @@ def main() -> int:
         achieved = pairs * flops_per_pair / sel_avg_s / 1e12
         roofline = {"kernel": "knn_select", "bound": "mfma", "achieved": round(achieved, 3),
                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                    "traffic": None, "avg_ms": round(sel_avg_s * 1e3, 4),
+                    "traffic": measured_traffic(w.name, "knn_select") if not (args.n or args.mode) else None, "avg_ms": round(sel_avg_s * 1e3, 4),
                     "work": f"{flops_per_pair} algorithmic flops per scored candidate pair (2m), {pairs:.4g} pairs "
                             + ("(routed query-candidate pairs, all probe passes)" if learned else "(n^2)")}
 

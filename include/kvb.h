@@ -89,6 +89,8 @@ extern "C" {
 #define KVB_OPT_SCRATCH_LIMIT 2  /* value: maximum scratch bytes; 0 = unlimited */
 #define KVB_OPT_BF16_SPLIT 3     /* BF16 terms per coordinate product in KVB_KNN_BF16 mode: 1 (x_hi only),
                                     3 (hi/lo pairs, default) or 6 (hi/mid/lo pairs) */
+#define KVB_OPT_N_PROBE 4        /* learned mode: buckets each query searches (1..min(32, n_buckets)); needs a
+                                    partitioner in the context; saved with it */
 
 typedef struct kvb_ctx_s* kvb_ctx;
 

@@ -89,6 +89,12 @@ int kvb_set_option(kvb_ctx ctx, int32_t key, int64_t value)
         KVB_REQUIRE(ctx, value >= 0, "KVB_OPT_SCRATCH_LIMIT must be >= 0");
         ctx->scratch_limit = static_cast<size_t>(value);
         return KVB_OK;
+    case KVB_OPT_N_PROBE:
+        if (!ctx->part.ready) return fail(ctx, KVB_E_NOT_TRAINED, "KVB_OPT_N_PROBE needs a partitioner");
+        KVB_REQUIRE(ctx, value >= 1 && value <= 32 && value <= ctx->part.nb,
+                    "KVB_OPT_N_PROBE must be in [1, min(32, n_buckets)]");
+        ctx->part.np = static_cast<int>(value);
+        return KVB_OK;
     case KVB_OPT_BF16_SPLIT:
         KVB_REQUIRE(ctx, value == 1 || value == 3 || value == 6, "KVB_OPT_BF16_SPLIT must be 1, 3 or 6");
         ctx->bf16_split = static_cast<int>(value);
