@@ -116,9 +116,13 @@ def main() -> int:
         log(f"bench: partitioner trained on {n_train} rows in {learned['train_s']} s, "
             f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
 
+    prev = [None]
+
     def step():
-        return kvb.build_kernel_matrix(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
-                                       mode=w.mode, margin=w.margin, ctx=ctx)
+        # outputs preallocated: each step reuses the previous step's device arrays
+        prev[0] = kvb.build(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
+                            mode=w.mode, margin=w.margin, ctx=ctx, out=prev[0])
+        return prev[0]
 
     for _ in range(args.warmup):
         step()

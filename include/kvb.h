@@ -211,6 +211,31 @@ int kvb_assemble_csr(kvb_ctx ctx, const int32_t* idx, const float* d2, const flo
                      int64_t* rowptr, int32_t* col, float* val, double* P, double* D);
 
 /*
+ * The whole build in one call, in the order of the paper's pipeline (Section 4
+ * with the tuning of Section 2.3): k-NN (as kvb_knn) -> ad-hoc bandwidth b ->
+ * e tuning on the density kernel over [e_min, e_max] -> density psi and
+ * rho = 2 psi^beta -> grid scale s (as kvb_grid_scale with ref = b) -> e tuning
+ * on the operator kernel over [s e_min, s e_max] -> q, Kt, D and the CSR of
+ * out_kind (as kvb_assemble_csr). Intermediate results stay on the device and
+ * the call synchronises once, at the end; results equal those of the separate
+ * calls bit for bit.
+ *   idx, d2, row_flags   as kvb_knn (row_flags may be NULL).
+ *   b, rho [n] float32 out; psi [n] float32 out or NULL.
+ *   rowptr, col, val, P, D   as kvb_assemble_csr (P, D may be NULL).
+ *   chi_a_host, chi_b_host   [G] host out or NULL: the tuning sums of both stages.
+ *   info_host [8] host out: e_A, dim_A, s, e_B, dim_B, g*_A, g*_B, rows that
+ *                took the exact k-NN fallback.
+ * Returns KVB_W_GRID_EDGE if either optimum lies at the edge of its grid,
+ * else KVB_W_FALLBACK if some rows took the fallback, else KVB_OK; errors as
+ * the separate calls.
+ */
+int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_t mode, int32_t margin, int32_t k0,
+              double d, double alpha, double beta, double e_min, double e_max, int32_t G, int32_t out_kind,
+              int32_t* idx, float* d2, int32_t* row_flags, float* b, float* rho, float* psi, int64_t* rowptr,
+              int32_t* col, float* val, double* P, double* D, double* chi_a_host, double* chi_b_host,
+              double* info_host);
+
+/*
  * ---- learned partitioner (k-NN over routed candidate buckets) ----
  * A small MLP m -> h1 -> h2 -> n_buckets (ReLU, BF16 weights and activations,
  * FP32 accumulation) is trained on the GPU to predict, for a sample, which

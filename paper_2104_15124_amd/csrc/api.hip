@@ -41,6 +41,9 @@ int kvb_create(kvb_ctx* out, void* hip_stream)
     if (hipMalloc(reinterpret_cast<void**>(&ctx->tune_dev), sizeof(kvb::TuneResult)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&ctx->tune_host), sizeof(kvb::TuneResult), hipHostMallocDefault) !=
             hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&ctx->build_dev), sizeof(BuildDev)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&ctx->build_host), sizeof(BuildDev), hipHostMallocDefault) !=
+            hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&ctx->fb_count_dev), sizeof(int)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&ctx->pairs_dev), sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&ctx->pairs_host), sizeof(unsigned long long),
@@ -68,6 +71,8 @@ void kvb_destroy(kvb_ctx ctx)
     if (ctx->tune_host) (void)hipHostFree(ctx->tune_host);
     if (ctx->fb_count_dev) (void)hipFree(ctx->fb_count_dev);
     if (ctx->fb_count_host) (void)hipHostFree(ctx->fb_count_host);
+    if (ctx->build_dev) (void)hipFree(ctx->build_dev);
+    if (ctx->build_host) (void)hipHostFree(ctx->build_host);
     if (ctx->loss_dev) (void)hipFree(ctx->loss_dev);
     if (ctx->pairs_dev) (void)hipFree(ctx->pairs_dev);
     if (ctx->pairs_host) (void)hipHostFree(ctx->pairs_host);
@@ -143,7 +148,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                   round256(size_t(nn) * sizeof(float)) + round256(size_t(nn) * sizeof(int)) + 2048;
     size_t sort_bytes = 0;
     if (direct)
-        KVB_HIP(ctx, kvb::sort_pairs_u64(nullptr, sort_bytes, nullptr, nullptr, nullptr, nullptr, nn, 64, ctx->stream));
+        KVB_HIP(ctx, kvb::sort_pairs_u32(nullptr, sort_bytes, nullptr, nullptr, nullptr, nullptr, nn, 32, ctx->stream));
     const int ntiles = kvb::spatial_tiles(nn), nsb = kvb::spatial_superblocks(nn);
     if (direct)
         need += round256(size_t(nn) * m * sizeof(float)) + 2 * round256(size_t(nn) * sizeof(int32_t)) +
@@ -168,8 +173,8 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
         float* Xs = cv.take<float>(size_t(nn) * m);
         int32_t* perm = cv.take<int32_t>(nn);
         int32_t* vals = cv.take<int32_t>(nn);
-        uint64_t* code = cv.take<uint64_t>(nn);
-        uint64_t* scode = cv.take<uint64_t>(nn);
+        uint32_t* code = cv.take<uint32_t>(nn);
+        uint32_t* scode = cv.take<uint32_t>(nn);
         float* tbox = cv.take<float>(size_t(ntiles) * 2 * m);
         float* sbox = cv.take<float>(size_t(nsb) * 2 * m);
         float* bbox = cv.take<float>(size_t(kvb::spatial_bbox_blocks(nn)) * 2 * m);
@@ -178,7 +183,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
             Prof pr(ctx, KVB_PROF_KNN_PREP);
             KVB_HIP(ctx, kvb::launch_spatial_codes(X, nn, m, bbox, code, vals, ctx->stream));
             size_t sb = sort_bytes;
-            KVB_HIP(ctx, kvb::sort_pairs_u64(sort_tmp, sb, code, scode, vals, perm, nn, 64, ctx->stream));
+            KVB_HIP(ctx, kvb::sort_pairs_u32(sort_tmp, sb, code, scode, vals, perm, nn, 32, ctx->stream));
             KVB_HIP(ctx, kvb::launch_spatial_layout(X, nn, m, perm, Xs, tbox, sbox, ctx->stream));
         }
         Prof pr(ctx, KVB_PROF_KNN_SELECT);
@@ -295,7 +300,7 @@ int kvb_bandwidth(kvb_ctx ctx, const int32_t* idx, const float* d2, int64_t n, i
     KVB_REQUIRE(ctx, d > 0 && std::isfinite(d), "d must be finite and > 0");
     KVB_REQUIRE(ctx, std::isfinite(beta), "beta must be finite");
     Prof pr(ctx, KVB_PROF_DENSITY);
-    KVB_HIP(ctx, kvb::launch_density(idx, d2, nn, k, b, e, d, beta, rho, psi, ctx->stream));
+    KVB_HIP(ctx, kvb::launch_density(idx, d2, nn, k, b, e, nullptr, d, beta, rho, psi, ctx->stream));
     return KVB_OK;
 }
 
@@ -342,7 +347,7 @@ int kvb_tune_eps(kvb_ctx ctx, const int32_t* idx, const float* d2, const float* 
     double* part = cv.take<double>(size_t(nb) * G);
     {
         Prof pr(ctx, KVB_PROF_CHI);
-        KVB_HIP(ctx, kvb::launch_chi(idx, d2, rho, nnz, k, G, std::log(e_min), std::log(e_max), part,
+        KVB_HIP(ctx, kvb::launch_chi(idx, d2, rho, nnz, k, G, e_min, e_max, nullptr, part,
                                      ctx->tune_dev, ctx->stream));
     }
     KVB_HIP(ctx, hipMemcpyAsync(ctx->tune_host, ctx->tune_dev, sizeof(kvb::TuneResult), hipMemcpyDeviceToHost,
@@ -376,14 +381,99 @@ int kvb_assemble_csr(kvb_ctx ctx, const int32_t* idx, const float* d2, const flo
     double* Dtmp = cv.take<double>(nn);
     {
         Prof pr(ctx, KVB_PROF_QPASS);
-        KVB_HIP(ctx, kvb::launch_qpass(idx, d2, nn, k, rho, e, alpha, d, qa, ctx->stream));
+        KVB_HIP(ctx, kvb::launch_qpass(idx, d2, nn, k, rho, e, nullptr, alpha, d, qa, ctx->stream));
     }
     {
         Prof pr(ctx, KVB_PROF_ASSEMBLE);
-        KVB_HIP(ctx, kvb::launch_assemble(idx, d2, nn, k, rho, e, qa, out_kind, rowptr, col, val, P,
+        KVB_HIP(ctx, kvb::launch_assemble(idx, d2, nn, k, rho, e, nullptr, qa, out_kind, rowptr, col, val, P,
                                           D ? D : Dtmp, ctx->stream));
     }
     return KVB_OK;
+}
+
+int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_t mode, int32_t margin, int32_t k0,
+              double d, double alpha, double beta, double e_min, double e_max, int32_t G, int32_t out_kind,
+              int32_t* idx, float* d2, int32_t* row_flags, float* b, float* rho, float* psi, int64_t* rowptr,
+              int32_t* col, float* val, double* P, double* D, double* chi_a_host, double* chi_b_host,
+              double* info_host)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, k0 >= 1 && k0 < k, "k0 must be in [1, k), got k0=%d k=%d", k0, k);
+    KVB_REQUIRE(ctx, k <= 256, "k must be <= 256, got %d", k);
+    KVB_REQUIRE(ctx, G >= 3 && G <= 256, "G must be in [3, 256], got %d", G);
+    KVB_REQUIRE(ctx, e_min > 0 && e_max > e_min && std::isfinite(e_max), "need 0 < e_min < e_max < inf");
+    KVB_REQUIRE(ctx, d > 0 && std::isfinite(d) && std::isfinite(alpha) && std::isfinite(beta),
+                "d must be finite and > 0, alpha and beta finite");
+    KVB_REQUIRE(ctx, out_kind >= KVB_OUT_MARKOV && out_kind <= KVB_OUT_SYMMETRIC, "unknown out_kind %d", out_kind);
+    KVB_REQUIRE(ctx, aligned(b) && aligned(rho) && (psi == nullptr || aligned(psi)),
+                "b and rho must be non-null float32 device pointers");
+    KVB_REQUIRE(ctx, aligned(rowptr) && aligned(col) && aligned(val), "rowptr, col, val must be non-null");
+    KVB_REQUIRE(ctx, (P == nullptr || aligned(P)) && (D == nullptr || aligned(D)), "P and D must be aligned");
+    KVB_REQUIRE(ctx, info_host != nullptr, "info_host must be non-null");
+    int rc = kvb_knn(ctx, X, n, m, k, mode, margin, idx, d2, row_flags);
+    if (rc < 0) return rc;
+    const int nn = static_cast<int>(n);
+    const int64_t nnz = n * k;
+    const int nb = kvb::chi_num_blocks(nnz);
+    const int lb = kvb::logsum_num_blocks(nn);
+    rc = ensure_scratch(ctx, round256(size_t(nb) * G * sizeof(double)) + round256(size_t(2 * lb) * sizeof(double)) +
+                                 2 * round256(size_t(nn) * sizeof(double)) + 1024);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    double* part = cv.take<double>(size_t(nb) * G);
+    double* lpart = cv.take<double>(2 * lb);
+    double* qa = cv.take<double>(nn);
+    double* Dtmp = cv.take<double>(nn);
+    BuildDev* bd = ctx->build_dev;
+    hipStream_t st = ctx->stream;
+    {
+        Prof pr(ctx, KVB_PROF_ADHOC);
+        KVB_HIP(ctx, kvb::launch_adhoc_bandwidth(d2, nn, k, k0, b, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_CHI);
+        KVB_HIP(ctx, kvb::launch_chi(idx, d2, b, nnz, k, G, e_min, e_max, nullptr, part, &bd->a, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_DENSITY);
+        KVB_HIP(ctx, kvb::launch_density(idx, d2, nn, k, b, 0.0, &bd->a.e_star, d, beta, rho, psi, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_GRID_SCALE);
+        KVB_HIP(ctx, kvb::launch_grid_scale(b, rho, nn, lpart, &bd->scale, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_CHI);
+        KVB_HIP(ctx, kvb::launch_chi(idx, d2, rho, nnz, k, G, e_min, e_max, &bd->scale, part, &bd->b, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_QPASS);
+        KVB_HIP(ctx, kvb::launch_qpass(idx, d2, nn, k, rho, 0.0, &bd->b.e_star, alpha, d, qa, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_ASSEMBLE);
+        KVB_HIP(ctx, kvb::launch_assemble(idx, d2, nn, k, rho, 0.0, &bd->b.e_star, qa, out_kind, rowptr, col, val, P,
+                                          D ? D : Dtmp, st));
+    }
+    KVB_HIP(ctx, hipMemcpyAsync(ctx->build_host, bd, sizeof(BuildDev), hipMemcpyDeviceToHost, st));
+    KVB_HIP(ctx, hipMemcpyAsync(ctx->fb_count_host, ctx->fb_count_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    KVB_HIP(ctx, hipStreamSynchronize(st));
+    const BuildDev& h = *ctx->build_host;
+    if (chi_a_host) std::memcpy(chi_a_host, h.a.chi, sizeof(double) * G);
+    if (chi_b_host) std::memcpy(chi_b_host, h.b.chi, sizeof(double) * G);
+    info_host[0] = h.a.e_star;
+    info_host[1] = h.a.dim;
+    info_host[2] = h.scale;
+    info_host[3] = h.b.e_star;
+    info_host[4] = h.b.dim;
+    info_host[5] = h.a.g_star;
+    info_host[6] = h.b.g_star;
+    info_host[7] = *ctx->fb_count_host;
+    if (!(std::isfinite(h.scale) && h.scale > 0))
+        return fail(ctx, KVB_E_INVALID, "grid scale is not finite: bandwidths must be positive and finite");
+    const bool edge = h.a.g_star == 0 || h.a.g_star == G - 2 || h.b.g_star == 0 || h.b.g_star == G - 2;
+    if (edge) return KVB_W_GRID_EDGE;
+    return *ctx->fb_count_host > 0 ? KVB_W_FALLBACK : KVB_OK;
 }
 
 const char* kvb_version(void) { return "kvb 0.1 (gfx950)"; }

@@ -69,6 +69,28 @@ __device__ __forceinline__ float box_gap2(const float* __restrict__ b, const flo
 
 constexpr int SEED_TILES = 2;   // curve neighbours on each side scored before any box test
 
+// Upper bound on the kp-th smallest of the wavefront's NS x 64 non-negative
+// values (+inf marks none): bisection on the float bit pattern down to bit
+// 18 (a relative resolution of 2^-5), by ballot counts; +inf when fewer
+// than kp values are finite.
+template <int NS>
+__device__ __forceinline__ float seed_threshold(const float (&d)[NS], int kp)
+{
+    int total = 0;
+#pragma unroll
+    for (int u = 0; u < NS; ++u) total += __popcll(__ballot(d[u] < __uint_as_float(0x7F800000u)));
+    if (total < kp) return __uint_as_float(0x7F800000u);
+    uint32_t P = 0;
+    for (int b = 30; b >= 18; --b) {
+        const uint32_t cand = P | (1u << b);
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < NS; ++u) cnt += __popcll(__ballot(__float_as_uint(d[u]) < cand));
+        if (cnt < kp) P = cand;
+    }
+    return __uint_as_float(P | ((1u << 18) - 1u));
+}
+
 template <int M>
 __device__ __forceinline__ void load_tile(const SpatialView& sv, int n, int t, int lane, float (&x)[M], uint32_t& jo)
 {
@@ -169,22 +191,45 @@ __global__ __launch_bounds__(256) void k_select_direct(SpatialView sv, int n, in
     const int ntiles = (n + TILE - 1) / TILE;
     const int nsb = (ntiles + SB_TILES - 1) / SB_TILES;
     const int own_t = row0 / TILE;
-    // seed: the own tile and its curve neighbours, unconditionally
+    // seed: the own tile and its curve neighbours, unconditionally. Each row's
+    // first threshold is a coarse upper bound of the kp-th smallest seed
+    // distance (valid for the whole scan: the kp-th smallest of a subset is at
+    // least the kp-th smallest overall), so the seeds append little more than kp.
+    constexpr int NS = 2 * SEED_TILES + 1;
     const int a0 = max(0, own_t - SEED_TILES), a1 = min(ntiles - 1, own_t + SEED_TILES);
+    float xs[NS][M];
+    uint32_t js[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) load_tile<M>(sv, n, min(a0 + u, a1), lane, xs[u], js[u]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float ds[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            float tt = q[r][0] - xs[u][0];
+            float d = tt * tt;
+#pragma unroll
+            for (int c = 1; c < M; ++c) {
+                tt = q[r][c] - xs[u][c];
+                d = fmaf(tt, tt, d);
+            }
+            const bool ok = (a0 + u <= a1) && ((a0 + u) * TILE + lane < n);
+            ds[u] = ok ? d : __uint_as_float(0x7F800000u);
+        }
+        tau[r] = seed_threshold<NS>(ds, kp);
+    }
+    taumax = tau[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r) taumax = fmaxf(taumax, tau[r]);
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int t = a0 + u;
+        if (t <= a1)
+            score_tile<M, R, E>(q, xs[u], js[u], t * TILE + lane < n, n, t, kp, rows_here, lane, buf, L, tau, bc,
+                                taumax, pairs);
+    }
     float xc[M];
     uint32_t jc_o = 0;
-    load_tile<M>(sv, n, a0, lane, xc, jc_o);
-    for (int t = a0; t <= a1; ++t) {
-        float xn[M];
-        uint32_t jn_o = 0;
-        if (t < a1) load_tile<M>(sv, n, t + 1, lane, xn, jn_o);
-        score_tile<M, R, E>(q, xc, jc_o, t * TILE + lane < n, n, t, kp, rows_here, lane, buf, L, tau, bc, taumax, pairs);
-        if (t < a1) {
-#pragma unroll
-            for (int c = 0; c < M; ++c) xc[c] = xn[c];
-            jc_o = jn_o;
-        }
-    }
     // then every superblock within reach (boxes tested 64 at a time, one per
     // lane), and inside it every tile within reach (16 lanes)
     for (int sb0 = 0; sb0 < nsb; sb0 += WAVE) {
@@ -278,16 +323,16 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const float* __restrict__ 
     }
 }
 
-// Morton code of every sample: each coordinate quantised to b = min(31, 63 / m) bits
+// Morton code of every sample: each coordinate quantised to b = min(31, 32 / m) bits
 // over the bounding box (the box partials are reduced here, redundantly per
 // thread: at most 1024 partials of 2m values), bits interleaved from the most
 // significant. value = sample index, so a stable sort breaks ties by index.
 __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ X, int n, int m,
                                                 const float* __restrict__ part, int nparts,
-                                                uint64_t* __restrict__ code, int32_t* __restrict__ vals)
+                                                uint32_t* __restrict__ code, int32_t* __restrict__ vals)
 {
     __shared__ float s_lo[8], s_scale[8];
-    const int bits = min(31, 63 / m);
+    const int bits = min(31, 32 / m);
     if (threadIdx.x < m) {
         const int c = threadIdx.x;
         float lo = __uint_as_float(0x7F800000u), hi = -__uint_as_float(0x7F800000u);
@@ -309,7 +354,7 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ X, int
         const float tc = fminf(fmaxf(t, 0.f), static_cast<float>(qmax));
         qc[c] = min(static_cast<uint32_t>(tc), qmax);
     }
-    uint64_t z = 0;
+    uint32_t z = 0;
     for (int b = bits - 1; b >= 0; --b)
         for (int c = 0; c < m; ++c) z = (z << 1) | ((qc[c] >> b) & 1u);
     code[i] = z;
@@ -778,7 +823,7 @@ int spatial_bbox_blocks(int n) { return std::max(1, std::min(1024, (n + 4095) / 
 int spatial_tiles(int n) { return (n + TILE - 1) / TILE; }
 int spatial_superblocks(int n) { return (spatial_tiles(n) + SB_TILES - 1) / SB_TILES; }
 
-hipError_t launch_spatial_codes(const float* X, int n, int m, float* bbox_part, uint64_t* code, int32_t* vals,
+hipError_t launch_spatial_codes(const float* X, int n, int m, float* bbox_part, uint32_t* code, int32_t* vals,
                                 hipStream_t st)
 {
     if (m < 1 || m > 8) return hipErrorInvalidValue;

@@ -39,6 +39,14 @@ struct PartState {
     int64_t nparams() const { return int64_t(h1) * m + h1 + int64_t(h2) * h1 + h2 + int64_t(nb) * h2 + nb; }
 };
 
+// Tuning results of both stages and the grid scale, kept on the device
+// between the steps of kvb_build.
+struct BuildDev {
+    kvb::TuneResult a, b;
+    double scale;
+    double pad;
+};
+
 }  // namespace kvbh
 
 struct kvb_ctx_s {
@@ -52,6 +60,8 @@ struct kvb_ctx_s {
     int bf16_split = 3;
     kvb::TuneResult* tune_dev = nullptr;
     kvb::TuneResult* tune_host = nullptr;   // pinned
+    kvbh::BuildDev* build_dev = nullptr;    // device-resident tuning results of kvb_build
+    kvbh::BuildDev* build_host = nullptr;   // pinned
     int* fb_count_dev = nullptr;            // fallback rows of the last kvb_knn
     int* fb_count_host = nullptr;           // pinned
     unsigned long long* pairs_dev = nullptr;   // candidate pairs scored by the last kvb_knn

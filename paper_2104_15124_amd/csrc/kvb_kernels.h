@@ -41,7 +41,7 @@ struct TuneResult {
 int spatial_bbox_blocks(int n);
 int spatial_tiles(int n);
 int spatial_superblocks(int n);
-hipError_t launch_spatial_codes(const float* X, int n, int m, float* bbox_part, uint64_t* code, int32_t* vals,
+hipError_t launch_spatial_codes(const float* X, int n, int m, float* bbox_part, uint32_t* code, int32_t* vals,
                                 hipStream_t st);
 hipError_t launch_spatial_layout(const float* X, int n, int m, const int32_t* perm, float* Xs, float* tbox,
                                  float* sbox, hipStream_t st);
@@ -69,19 +69,21 @@ int select_mfma_queries_per_block(int split, int kpad);
 
 // passes
 hipError_t launch_adhoc_bandwidth(const float* d2, int n, int k, int k0, float* b, hipStream_t st);
-hipError_t launch_density(const int32_t* idx, const float* d2, int n, int k, const float* b, double e, double d,
-                          double beta, float* rho, float* psi, hipStream_t st);
+hipError_t launch_density(const int32_t* idx, const float* d2, int n, int k, const float* b, double e,
+                          const double* e_dev, double d, double beta, float* rho, float* psi, hipStream_t st);
 int chi_num_blocks(int64_t nnz);
-hipError_t launch_chi(const int32_t* idx, const float* d2, const float* rho, int64_t nnz, int k, int G,
-                      double log_emin, double log_emax, double* partial, TuneResult* out, hipStream_t st);
+// grid e_g = exp(ln(e_min s) + g (ln(e_max s) - ln(e_min s)) / (G - 1)), s = *scale_dev or 1
+hipError_t launch_chi(const int32_t* idx, const float* d2, const float* rho, int64_t nnz, int k, int G, double e_min,
+                      double e_max, const double* scale_dev, double* partial, TuneResult* out, hipStream_t st);
 int logsum_num_blocks(int n);
 hipError_t launch_grid_scale(const float* ref, const float* rho, int n, double* partial, double* out,
                              hipStream_t st);
+// e_dev non-null: e is read from device memory (e.g. a TuneResult's e_star)
 hipError_t launch_qpass(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
-                        double alpha, double d, double* qa, hipStream_t st);
+                        const double* e_dev, double alpha, double d, double* qa, hipStream_t st);
 hipError_t launch_assemble(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
-                           const double* qa, int out_kind, int64_t* rowptr, int32_t* col, float* val,
-                           double* P, double* D, hipStream_t st);
+                           const double* e_dev, const double* qa, int out_kind, int64_t* rowptr, int32_t* col,
+                           float* val, double* P, double* D, hipStream_t st);
 
 // learned partitioner: MLP (mlp_kernels.hip)
 hipError_t launch_gemm_nt(const uint16_t* A, int lda, const uint16_t* B, int ldb, int M, int N, int K,
@@ -101,6 +103,8 @@ hipError_t launch_fill_normal(float* p, int64_t cnt, uint64_t seed, uint64_t off
 
 // learned partitioner: teacher, batches, bucket layout (learned_kernels.hip)
 hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,
+                          int32_t* vout, int cnt, int end_bit, hipStream_t st);
+hipError_t sort_pairs_u32(void* tmp, size_t& tmp_bytes, const uint32_t* kin, uint32_t* kout, const int32_t* vin,
                           int32_t* vout, int cnt, int end_bit, hipStream_t st);
 hipError_t sort_keys_u64(void* tmp, size_t& tmp_bytes, const uint64_t* kin, uint64_t* kout, int64_t cnt,
                          int end_bit, hipStream_t st);

@@ -252,6 +252,13 @@ hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const uint64_t* kin, uin
                                      static_cast<unsigned>(end_bit), st);
 }
 
+hipError_t sort_pairs_u32(void* tmp, size_t& tmp_bytes, const uint32_t* kin, uint32_t* kout, const int32_t* vin,
+                          int32_t* vout, int cnt, int end_bit, hipStream_t st)
+{
+    return rocprim::radix_sort_pairs(tmp, tmp_bytes, kin, kout, vin, vout, static_cast<size_t>(cnt), 0,
+                                     static_cast<unsigned>(end_bit), st);
+}
+
 hipError_t sort_keys_u64(void* tmp, size_t& tmp_bytes, const uint64_t* kin, uint64_t* kout, int64_t cnt,
                          int end_bit, hipStream_t st)
 {

@@ -24,33 +24,41 @@ __global__ __launch_bounds__(256) void k_adhoc_bandwidth(const float* __restrict
     b[i] = static_cast<float>(sqrt(s));
 }
 
-// Row sum of exp(-d2/(e rho_i rho_j)) with a float64 argument and exponential,
-// reduced over the wavefront in a fixed order.
-__device__ __forceinline__ double row_kernel_sum(const int32_t* __restrict__ irow, const float* __restrict__ drow,
-                                                 int k, const float* __restrict__ rho, double inv_e_rhoi,
-                                                 int lane)
+// Row sums of exp(-d2/(e rho_i rho_j)) with a float64 argument and exponential:
+// four rows per wavefront, 16 lanes per row (entries strided by 16), the
+// group's partial sums reduced in a fixed butterfly order. Every lane of the
+// group returns the row's sum.
+constexpr int RL = 16;   // lanes per row in the row-sum passes
+
+__device__ __forceinline__ double row_kernel_sum16(const int32_t* __restrict__ irow, const float* __restrict__ drow,
+                                                   int k, const float* __restrict__ rho, double inv_e_rhoi, int gl)
 {
     double s = 0.0;
-    for (int r = lane; r < k; r += WAVE) {
+    for (int r = gl; r < k; r += RL) {
         const double x = static_cast<double>(drow[r]) * inv_e_rhoi / static_cast<double>(rho[irow[r]]);
         s += exp(-x);
     }
-    return wave_sum_f64(s);
+#pragma unroll
+    for (int o = 1; o < RL; o <<= 1) s += shfl_xor_f64(s, o);
+    return s;
 }
 
 // psi_i = sum_r K_ir / (n (pi e b_i^2)^{d/2}), rho_i = 2 psi_i^beta
 // (Section 2.1 density eqs.; Algorithm 1 caption)
 __global__ __launch_bounds__(256) void k_density(const int32_t* __restrict__ idx, const float* __restrict__ d2,
-                                                 int n, int k, const float* __restrict__ b, double e, double d,
-                                                 double beta, float* __restrict__ rho, float* __restrict__ psi)
+                                                 int n, int k, const float* __restrict__ b, double e,
+                                                 const double* __restrict__ e_dev, double d, double beta,
+                                                 float* __restrict__ rho, float* __restrict__ psi)
 {
+    if (e_dev) e = *e_dev;
     const int lane = lane_id();
-    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (i >= n) return;
+    const int i = (blockIdx.x * 256 + threadIdx.x) / RL;
+    const int gl = lane % RL;
+    if (i >= n) return;   // whole lane groups
     const double bi = static_cast<double>(b[i]);
-    const double s = row_kernel_sum(idx + static_cast<size_t>(i) * k, d2 + static_cast<size_t>(i) * k, k, b,
-                                    1.0 / (e * bi), lane);
-    if (lane == 0) {
+    const double s = row_kernel_sum16(idx + static_cast<size_t>(i) * k, d2 + static_cast<size_t>(i) * k, k, b,
+                                      1.0 / (e * bi), gl);
+    if (gl == 0) {
         const double pi = 3.14159265358979323846;
         const double w = static_cast<double>(n) * pow(pi * e * bi * bi, 0.5 * d);
         const double p = s / w;
@@ -61,62 +69,66 @@ __global__ __launch_bounds__(256) void k_density(const int32_t* __restrict__ idx
 
 // ------------------------------------------------------------------ tuning sums
 // Block partials of chi[g] = sum over entries of exp(-x / e_g), x = d2/(rho_i rho_j).
-// Each wavefront takes 64 consecutive entries at a time: lane t forms x for
-// entry t, the 64 values go through LDS, then lane g accumulates exp2(x c_g)
-// over them for grid point g (c_g = -log2(e)/e_g), in float32 per 64-entry
-// chunk and float64 across chunks.
+// Each thread forms x for its entries and accumulates exp2(x c_g) for a group
+// of 64 grid points in registers (c_g = -log2(e)/e_g, float32 per thread over
+// its few entries; hardware exp2, whose flush of results below 2^-126 is far
+// below the sum's rounding since every row contributes exp(0) = 1); the
+// per-thread sums are then reduced in float64 in a fixed order.
 constexpr int CHI_BLOCK = 256;
+constexpr int CHI_GROUP = 64;   // grid points per register group
 
 // ln e_g = ln e_min + g (ln e_max - ln e_min) / (G - 1)
 __device__ __forceinline__ double grid_log(double lo, double hi, int G, int g)
 {
     return lo + (static_cast<double>(g) * (hi - lo)) / static_cast<double>(G - 1);
 }
-constexpr int CHI_MIN_ENTRIES_PER_BLOCK = 4096;
-constexpr int CHI_MAX_BLOCKS = 4096;
+constexpr int CHI_MIN_ENTRIES_PER_BLOCK = 8192;
+constexpr int CHI_MAX_BLOCKS = 1024;
 
 __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __restrict__ idx,
                                                            const float* __restrict__ d2,
                                                            const float* __restrict__ rho, int64_t nnz, int k,
-                                                           int G, double log_emin, double log_emax,
-                                                           int64_t per_block, double* __restrict__ partial)
+                                                           int G, double e_min, double e_max,
+                                                           const double* __restrict__ scale_dev, int64_t per_block,
+                                                           double* __restrict__ partial)
 {
-    __shared__ float sx[CHI_BLOCK / WAVE][WAVE];
-    __shared__ double sred[CHI_BLOCK / WAVE][256];
+    const double sc = scale_dev ? *scale_dev : 1.0;
+    const double log_emin = log(e_min * sc), log_emax = log(e_max * sc);
+    __shared__ float s_c[256 + CHI_GROUP];
+    __shared__ double sred[CHI_BLOCK / WAVE][CHI_GROUP];
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int64_t base = static_cast<int64_t>(blockIdx.x) * per_block;
     const int64_t end = min(base + per_block, nnz);
-    const int ngb = (G + WAVE - 1) / WAVE;
-    for (int gb = 0; gb < ngb; ++gb) {
-        const int g = gb * WAVE + lane;
-        const double eg = exp(grid_log(log_emin, log_emax, G, min(g, G - 1)));
-        const float cg = static_cast<float>(-1.4426950408889634 / eg);
-        double acc = 0.0;
-        for (int64_t p0 = base + wave * WAVE; p0 < end; p0 += CHI_BLOCK) {
-            const int64_t p = p0 + lane;
-            float x = __uint_as_float(0x7F800000u);  // +inf -> exp2(-inf) = 0 for padding
-            if (p < end) {
-                const int64_t i = p / k;
-                const float di = d2[p];
-                const float ri = rho[i], rj = rho[idx[p]];
-                x = static_cast<float>(static_cast<double>(di) / (static_cast<double>(ri) * static_cast<double>(rj)));
-            }
-            sx[wave][lane] = x;
-            wave_lds_sync();
-            float part = 0.f;
-#pragma unroll 8
-            for (int t = 0; t < WAVE; ++t) part += exp2f(sx[wave][t] * cg);
-            acc += static_cast<double>(part);
-            wave_lds_sync();
-        }
-        sred[wave][gb * WAVE + lane] = acc;
-    }
+    for (int g = threadIdx.x; g < 256 + CHI_GROUP; g += CHI_BLOCK)
+        s_c[g] = g < G ? static_cast<float>(-1.4426950408889634 / exp(grid_log(log_emin, log_emax, G, g))) : 0.f;
     __syncthreads();
-    if (threadIdx.x < G) {
-        double s = 0.0;
-        for (int w = 0; w < CHI_BLOCK / WAVE; ++w) s += sred[w][threadIdx.x];
-        partial[static_cast<size_t>(blockIdx.x) * G + threadIdx.x] = s;
+    for (int g0 = 0; g0 < G; g0 += CHI_GROUP) {
+        const float* cg = s_c + g0;   // wave-uniform LDS reads (broadcast)
+        float acc[CHI_GROUP];
+#pragma unroll
+        for (int t = 0; t < CHI_GROUP; ++t) acc[t] = 0.f;
+        for (int64_t p = base + threadIdx.x; p < end; p += CHI_BLOCK) {
+            const int64_t i = p / k;
+            const float x =
+                static_cast<float>(static_cast<double>(d2[p]) /
+                                   (static_cast<double>(rho[i]) * static_cast<double>(rho[idx[p]])));
+#pragma unroll
+            for (int t = 0; t < CHI_GROUP; ++t) acc[t] += __builtin_amdgcn_exp2f(x * cg[t]);
+        }
+        // fixed-order reduction: butterfly inside the wavefront, then the 4 wavefronts
+#pragma unroll
+        for (int t = 0; t < CHI_GROUP; ++t) {
+            const double v = wave_sum_f64(static_cast<double>(acc[t]));
+            if (lane == 0) sred[wave][t] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < CHI_GROUP && g0 + threadIdx.x < G) {
+            double s = 0.0;
+            for (int w = 0; w < CHI_BLOCK / WAVE; ++w) s += sred[w][threadIdx.x];
+            partial[static_cast<size_t>(blockIdx.x) * G + g0 + threadIdx.x] = s;
+        }
+        __syncthreads();
     }
 }
 
@@ -124,8 +136,11 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
 // (Section 2.3): slope_g = (ln chi_{g+1} - ln chi_g) / (ln e_{g+1} - ln e_g),
 // g* = first argmax, e* = e_{g*}, dimension estimate 2 slope_{g*}.
 __global__ __launch_bounds__(1024) void k_chi_finish(const double* __restrict__ partial, int nblocks, int G,
-                                                    double log_emin, double log_emax, TuneResult* __restrict__ out)
+                                                    double e_min, double e_max, const double* __restrict__ scale_dev,
+                                                    TuneResult* __restrict__ out)
 {
+    const double sc = scale_dev ? *scale_dev : 1.0;
+    const double log_emin = log(e_min * sc), log_emax = log(e_max * sc);
     __shared__ double chi[256];
     __shared__ double slope[256];
     __shared__ double part[1024];
@@ -221,16 +236,19 @@ __global__ __launch_bounds__(256) void k_logsum_finish(const double* __restrict_
 // ------------------------------------------------------------------ normalisation
 // q_i = P_i^{-d} sum_r K_ir, P_i = rho_i/2; stores qa_i = q_i^{-alpha} (Section 2.2)
 __global__ __launch_bounds__(256) void k_qpass(const int32_t* __restrict__ idx, const float* __restrict__ d2, int n,
-                                               int k, const float* __restrict__ rho, double e, double alpha,
-                                               double d, double* __restrict__ qa)
+                                               int k, const float* __restrict__ rho, double e,
+                                               const double* __restrict__ e_dev, double alpha, double d,
+                                               double* __restrict__ qa)
 {
+    if (e_dev) e = *e_dev;
     const int lane = lane_id();
-    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (i >= n) return;
+    const int i = (blockIdx.x * 256 + threadIdx.x) / RL;
+    const int gl = lane % RL;
+    if (i >= n) return;   // whole lane groups
     const double ri = static_cast<double>(rho[i]);
-    const double s = row_kernel_sum(idx + static_cast<size_t>(i) * k, d2 + static_cast<size_t>(i) * k, k, rho,
-                                    1.0 / (e * ri), lane);
-    if (lane == 0) {
+    const double s = row_kernel_sum16(idx + static_cast<size_t>(i) * k, d2 + static_cast<size_t>(i) * k, k, rho,
+                                      1.0 / (e * ri), gl);
+    if (gl == 0) {
         const double P = 0.5 * ri;
         const double q = pow(P, -d) * s;
         qa[i] = pow(q, -alpha);
@@ -243,11 +261,13 @@ __global__ __launch_bounds__(256) void k_qpass(const int32_t* __restrict__ idx, 
 template <int E>
 __global__ __launch_bounds__(256) void k_assemble(const int32_t* __restrict__ idx, const float* __restrict__ d2,
                                                   int n, int k, const float* __restrict__ rho, double e,
-                                                  const double* __restrict__ qa, int out_kind,
+                                                  const double* __restrict__ e_dev, const double* __restrict__ qa,
+                                                  int out_kind,
                                                   int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
                                                   float* __restrict__ val, double* __restrict__ Pout,
                                                   double* __restrict__ Dout)
 {
+    if (e_dev) e = *e_dev;
     const int lane = lane_id();
     const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (i >= n) return;
@@ -321,8 +341,10 @@ __global__ __launch_bounds__(256) void k_assemble(const int32_t* __restrict__ id
 // Lhat_ir = (Kt_ir / (S_i S_j) - [j == i] / P_i^2) / e, S = P sqrt(D)
 __global__ __launch_bounds__(256) void k_symmetric_finish(int64_t nnz, int k, const int32_t* __restrict__ col,
                                                           const float* __restrict__ rho, const double* __restrict__ D,
-                                                          double e, float* __restrict__ val)
+                                                          double e, const double* __restrict__ e_dev,
+                                                          float* __restrict__ val)
 {
+    if (e_dev) e = *e_dev;
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= nnz) return;
     const int64_t i = p / k;
@@ -340,10 +362,11 @@ hipError_t launch_adhoc_bandwidth(const float* d2, int n, int k, int k0, float* 
     return hipGetLastError();
 }
 
-hipError_t launch_density(const int32_t* idx, const float* d2, int n, int k, const float* b, double e, double d,
-                          double beta, float* rho, float* psi, hipStream_t st)
+hipError_t launch_density(const int32_t* idx, const float* d2, int n, int k, const float* b, double e,
+                          const double* e_dev, double d, double beta, float* rho, float* psi, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_density, dim3((n + 3) / 4), dim3(256), 0, st, idx, d2, n, k, b, e, d, beta, rho, psi);
+    hipLaunchKernelGGL(k_density, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, idx, d2, n, k, b, e, e_dev,
+                       d, beta, rho, psi);
     return hipGetLastError();
 }
 
@@ -360,13 +383,13 @@ int chi_num_blocks(int64_t nnz)
     return static_cast<int>((nnz + per - 1) / per);
 }
 
-hipError_t launch_chi(const int32_t* idx, const float* d2, const float* rho, int64_t nnz, int k, int G,
-                      double log_emin, double log_emax, double* partial, TuneResult* out, hipStream_t st)
+hipError_t launch_chi(const int32_t* idx, const float* d2, const float* rho, int64_t nnz, int k, int G, double e_min,
+                      double e_max, const double* scale_dev, double* partial, TuneResult* out, hipStream_t st)
 {
     const int nb = chi_num_blocks(nnz);
-    hipLaunchKernelGGL(k_chi_partial, dim3(nb), dim3(CHI_BLOCK), 0, st, idx, d2, rho, nnz, k, G, log_emin, log_emax,
-                       chi_per_block(nnz), partial);
-    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, log_emin, log_emax, out);
+    hipLaunchKernelGGL(k_chi_partial, dim3(nb), dim3(CHI_BLOCK), 0, st, idx, d2, rho, nnz, k, G, e_min, e_max,
+                       scale_dev, chi_per_block(nnz), partial);
+    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, out);
     return hipGetLastError();
 }
 
@@ -382,30 +405,31 @@ hipError_t launch_grid_scale(const float* ref, const float* rho, int n, double* 
 }
 
 hipError_t launch_qpass(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
-                        double alpha, double d, double* qa, hipStream_t st)
+                        const double* e_dev, double alpha, double d, double* qa, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_qpass, dim3((n + 3) / 4), dim3(256), 0, st, idx, d2, n, k, rho, e, alpha, d, qa);
+    hipLaunchKernelGGL(k_qpass, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, idx, d2, n, k, rho, e, e_dev,
+                       alpha, d, qa);
     return hipGetLastError();
 }
 
 hipError_t launch_assemble(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
-                           const double* qa, int out_kind, int64_t* rowptr, int32_t* col, float* val,
+                           const double* e_dev, const double* qa, int out_kind, int64_t* rowptr, int32_t* col, float* val,
                            double* P, double* D, hipStream_t st)
 {
     const dim3 grid((n + 3) / 4), block(256);
     if (k <= 64)
-        hipLaunchKernelGGL((k_assemble<1>), grid, block, 0, st, idx, d2, n, k, rho, e, qa, out_kind, rowptr, col,
+        hipLaunchKernelGGL((k_assemble<1>), grid, block, 0, st, idx, d2, n, k, rho, e, e_dev, qa, out_kind, rowptr, col,
                            val, P, D);
     else if (k <= 128)
-        hipLaunchKernelGGL((k_assemble<2>), grid, block, 0, st, idx, d2, n, k, rho, e, qa, out_kind, rowptr, col,
+        hipLaunchKernelGGL((k_assemble<2>), grid, block, 0, st, idx, d2, n, k, rho, e, e_dev, qa, out_kind, rowptr, col,
                            val, P, D);
     else
-        hipLaunchKernelGGL((k_assemble<4>), grid, block, 0, st, idx, d2, n, k, rho, e, qa, out_kind, rowptr, col,
+        hipLaunchKernelGGL((k_assemble<4>), grid, block, 0, st, idx, d2, n, k, rho, e, e_dev, qa, out_kind, rowptr, col,
                            val, P, D);
     if (out_kind == KVB_OUT_SYMMETRIC) {
         const int64_t nnz = static_cast<int64_t>(n) * k;
         hipLaunchKernelGGL(k_symmetric_finish, dim3(static_cast<unsigned>((nnz + 255) / 256)), dim3(256), 0, st,
-                           nnz, k, col, rho, D, e, val);
+                           nnz, k, col, rho, D, e, e_dev, val);
     }
     return hipGetLastError();
 }

@@ -32,7 +32,7 @@ MODES = {"f32": KNN_F32, "bf16": KNN_BF16, "learned": KNN_LEARNED}
 
 EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb_knn",
            "kvb_knn_fallback_rows", "kvb_knn_pairs", "kvb_knn_exact_rows", "kvb_bandwidth",
-           "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_part_init", "kvb_part_teacher",
+           "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_build", "kvb_part_init", "kvb_part_teacher",
            "kvb_part_train", "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
            "kvb_mlp_backward", "kvb_part_num_params", "kvb_part_get_params", "kvb_part_set_params",
            "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name")
@@ -74,6 +74,8 @@ def load_library(path: str = LIB_PATH):
                                _vp, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
     L.kvb_assemble_csr.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _f64, _f64, _f64, _i32,
                                    _vp, _vp, _vp, _vp, _vp]
+    L.kvb_build.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64, _i32, _i32,
+                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     _u64, _f32 = ctypes.c_uint64, ctypes.c_float
     L.kvb_part_init.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32, _u64]
     L.kvb_part_teacher.argtypes = [_vp, _vp, _i64, _i32, _i32, _u64, _vp]
@@ -96,7 +98,7 @@ def load_library(path: str = LIB_PATH):
                  "kvb_knn_pairs",
                  "kvb_bandwidth",
                  "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_profile_enable",
-                 "kvb_profile_read", "kvb_part_init", "kvb_part_teacher", "kvb_part_train",
+                 "kvb_profile_read", "kvb_build", "kvb_part_init", "kvb_part_teacher", "kvb_part_train",
                  "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
                  "kvb_mlp_backward", "kvb_part_get_params", "kvb_part_set_params"):
         getattr(L, name).restype = ctypes.c_int
@@ -310,6 +312,44 @@ class KernelMatrix:
     val: torch.Tensor
     P: torch.Tensor
     D: torch.Tensor
+
+
+def build(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float, e_min: float = 1e-3,
+          e_max: float = 1e1, G: int = 64, mode: str = "f32", margin: int = 32, out_kind: int = OUT_MARKOV,
+          ctx: Context | None = None, out: KernelMatrix | None = None) -> KernelMatrix:
+    """The whole build in one library call (kvb_build): the same steps and results
+    as build_kernel_matrix, with the intermediate values kept on the device.
+    `out` (a previous result of the same n and k) lends its device arrays."""
+    ctx = ctx or context()
+    X = _dev(X, torch.float32, "X")
+    n, m = X.shape
+    dev = X.device
+    if out is not None and out.idx.shape == (n, k) and out.idx.device == dev:
+        idx, d2, flags, b, rho, psi = out.idx, out.d2, out.flags, out.b, out.rho, out.psi
+        rowptr, col, val, P, D = out.rowptr, out.col, out.val, out.P, out.D
+    else:
+        idx = torch.empty((n, k), dtype=torch.int32, device=dev)
+        d2 = torch.empty((n, k), dtype=torch.float32, device=dev)
+        flags = torch.empty(n, dtype=torch.int32, device=dev)
+        b = torch.empty(n, dtype=torch.float32, device=dev)
+        rho = torch.empty(n, dtype=torch.float32, device=dev)
+        psi = torch.empty(n, dtype=torch.float32, device=dev)
+        rowptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(n * k, dtype=torch.int32, device=dev)
+        val = torch.empty(n * k, dtype=torch.float32, device=dev)
+        P = torch.empty(n, dtype=torch.float64, device=dev)
+        D = torch.empty(n, dtype=torch.float64, device=dev)
+    chi_a = np.zeros(G, dtype=np.float64)
+    chi_b = np.zeros(G, dtype=np.float64)
+    info = np.zeros(8, dtype=np.float64)
+    ctx.check(ctx.lib.kvb_build(ctx.h, _ptr(X), n, m, k, MODES[mode], margin, k0, d, alpha, beta, e_min, e_max, G,
+                                out_kind, _ptr(idx), _ptr(d2), _ptr(flags), _ptr(b), _ptr(rho), _ptr(psi),
+                                _ptr(rowptr), _ptr(col), _ptr(val), _ptr(P), _ptr(D), chi_a.ctypes.data_as(_vp),
+                                chi_b.ctypes.data_as(_vp), info.ctypes.data_as(_vp)))
+    ga, gb = int(info[5]), int(info[6])
+    ta = Tuning(chi_a, float(info[0]), float(info[1]), ga in (0, G - 2))
+    tb = Tuning(chi_b, float(info[3]), float(info[4]), gb in (0, G - 2))
+    return KernelMatrix(idx, d2, flags, b, ta, rho, psi, float(info[2]), tb, rowptr, col, val, P, D)
 
 
 def build_kernel_matrix(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float,

@@ -142,3 +142,23 @@ def test_pass_argument_errors(gpu_lib):
     with pytest.raises(kvb.KvbError) as e:
         kvb.assemble_csr(idx, d2, rho, -1.0, -0.5, 2.0)
     assert e.value.code == kvb.E_INVALID
+
+
+@pytest.mark.parametrize("out_kind", [0, 1, 2])
+def test_single_call_build_matches_separate_calls(gpu_lib, out_kind):
+    """kvb_build keeps every intermediate on the device; its results must equal
+    the separate entry points' bit for bit."""
+    kvb = gpu_lib
+    w = workloads.WORKLOADS["sphere2_n2000"]
+    X = workloads.make("sphere2_n2000", seed=3)
+    Xd = torch.from_numpy(X).cuda()
+    a = kvb.build_kernel_matrix(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
+                                mode="f32", margin=w.margin, out_kind=out_kind)
+    b = kvb.build(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
+                  mode="f32", margin=w.margin, out_kind=out_kind)
+    torch.cuda.synchronize()
+    for name in ("idx", "d2", "b", "rho", "psi", "rowptr", "col", "val", "P", "D"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+    assert a.scale_b == b.scale_b
+    for ta, tb in ((a.tune_a, b.tune_a), (a.tune_b, b.tune_b)):
+        assert (ta.chi == tb.chi).all() and ta.e_star == tb.e_star and ta.dim == tb.dim and ta.edge == tb.edge
