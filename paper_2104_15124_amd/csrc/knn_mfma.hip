@@ -221,9 +221,25 @@ __device__ __noinline__ float merge_query_list(uint64_t* __restrict__ dst, const
     return key_dist(list_at<E>(L, kp - 1));
 }
 
+// Sort query q's list in place (whole wavefront) and return its kp-th score.
+template <int E>
+__device__ __noinline__ float sort_query_list(uint64_t* __restrict__ dst, int kp)
+{
+    const int lane = lane_id();
+    uint64_t L[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) L[s] = dst[s * WAVE + lane];
+    bitonic_sort<E>(L);
+#pragma unroll
+    for (int s = 0; s < E; ++s) dst[s * WAVE + lane] = L[s];
+    return key_dist(list_at<E>(L, kp - 1));
+}
+
 // WV wavefronts per workgroup share every candidate stage; each wavefront owns
-// 32 queries. Per-query LDS buffers hold BUF keys and are merged once they
-// pass BUF - 32 (a 32-candidate tile adds at most 32 per query).
+// 32 queries. The first ceil(kp / 32) tiles of a scan that starts from empty
+// lists are written into the lists directly and sorted once; afterwards keys
+// at or below a query's threshold collect in its LDS buffer of BUF keys, which
+// is merged into the list whenever the next tile's keys would not fit.
 //
 // LEARNED = true: bucketed search of the learned partitioner. Workgroup w takes
 // work item (bucket b, first query entry t0): its queries are entries
@@ -246,7 +262,6 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
     constexpr int kpad = KS * Tr::KSTEP;        // padded contraction length
     constexpr int NQ = 32;                      // queries per wavefront
     constexpr int BUF = WV == 8 ? 48 : 64;      // per-query LDS buffer entries
-    constexpr int FLUSH_AT = BUF - 32;
     // two candidate stages, fragment-major: [stage][k-step][half][row] so that
     // lane l reads consecutive fragments (no bank conflicts). The next tile is
     // prefetched into registers while the current one is consumed.
@@ -328,6 +343,12 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
         if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(tbeg) * 32 + (lane & 31)];
     }
     uint32_t nonempty = 0;   // queries with buffered entries (wave-uniform)
+    // lists that start empty are filled by the first tiles without merging
+    bool filling = !LEARNED || ba.first;
+    const int fill_tiles = (kp + 31) / 32;
+    int qrow[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) qrow[r] = s_qid[wave][acc_row(r, half)];
     for (int tile = tbeg; tile < tend; ++tile) {
         const int stage = (tile - tbeg) & 1;
         {
@@ -361,16 +382,69 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
         const bool valid = LEARNED ? cand >= 0 : cand < n;
         pairs += static_cast<unsigned long long>(nq_valid) *
                  static_cast<unsigned long long>(__popcll(__ballot(valid) & 0xFFFFFFFFull));
-        uint32_t flush = 0;
+        if (filling) {
+            // the first ceil(kp / 32) tiles go straight into the (empty) lists
+            const int slot = (tile - tbeg) * 32 + (lane & 31);
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (qrow[r] >= 0)
+                    lists[static_cast<size_t>(qrow[r]) * CAP + slot] =
+                        valid ? make_key(acc[r], static_cast<uint32_t>(cand)) : KEY_INF;
+            if (tile - tbeg + 1 == fill_tiles || tile + 1 == tend) {
+                filling = false;
+                // the lists' stores complete before other lanes read them
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                for (int q = 0; q < NQ; ++q) {
+                    const int qg = s_qid[wave][q];
+                    if (qg < 0) continue;
+                    const float nt = sort_query_list<E>(lists + static_cast<size_t>(qg) * CAP, kp);
+                    const int rr = 4 * (q / 8) + (q % 4), hh = (q / 4) & 1;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        if (r == rr && half == hh) tauv[r] = nt;
+                }
+            }
+            continue;
+        }
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const float sc = acc[r];
-            const uint64_t mask = __ballot(valid && sc <= tauv[r]);
+            uint64_t mask = __ballot(valid && sc <= tauv[r]);
             if (mask) {
                 const int qa_ = acc_row(r, 0), qb_ = acc_row(r, 1);
-                const uint32_t ma = static_cast<uint32_t>(mask), mb = static_cast<uint32_t>(mask >> 32);
-                const int ca = ma ? s_cnt[wave][qa_] : 0;
-                const int cb = mb ? s_cnt[wave][qb_] : 0;
+                uint32_t ma = static_cast<uint32_t>(mask), mb = static_cast<uint32_t>(mask >> 32);
+                int ca = ma ? s_cnt[wave][qa_] : 0;
+                int cb = mb ? s_cnt[wave][qb_] : 0;
+                const bool fa = ca + __popc(ma) > BUF, fb = cb + __popc(mb) > BUF;
+                if (fa || fb) {
+                    // a full buffer is merged before this tile's keys are added,
+                    // so every merge takes nearly BUF keys
+                    wave_lds_sync();
+                    if (fa) {
+                        const int qg = s_qid[wave][qa_];
+                        float nt = -__uint_as_float(0x7F800000u);
+                        if (qg >= 0)
+                            nt = merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][qa_][0], ca,
+                                                     kp);
+                        if (half == 0) tauv[r] = nt;
+                        ca = 0;
+                    }
+                    if (fb) {
+                        const int qg = s_qid[wave][qb_];
+                        float nt = -__uint_as_float(0x7F800000u);
+                        if (qg >= 0)
+                            nt = merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][qb_][0], cb,
+                                                     kp);
+                        if (half == 1) tauv[r] = nt;
+                        cb = 0;
+                    }
+                    wave_lds_sync();
+                    mask = __ballot(valid && sc <= tauv[r]);
+                    ma = static_cast<uint32_t>(mask);
+                    mb = static_cast<uint32_t>(mask >> 32);
+                }
                 const uint32_t hm = half ? mb : ma;
                 const int l31 = lane & 31;
                 if ((hm >> l31) & 1u) {
@@ -378,32 +452,12 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
                     s_buf[wave][half ? qb_ : qa_][pos] = make_key(sc, static_cast<uint32_t>(cand));
                 }
                 const int na = ca + __popc(ma), nb = cb + __popc(mb);
-                if (lane == 0 && ma) s_cnt[wave][qa_] = na;
-                if (lane == 32 && mb) s_cnt[wave][qb_] = nb;
-                if (ma) nonempty |= 1u << qa_;
-                if (mb) nonempty |= 1u << qb_;
-                if (na > FLUSH_AT) flush |= 1u << qa_;
-                if (nb > FLUSH_AT) flush |= 1u << qb_;
-            }
-        }
-        if (flush) {
-            wave_lds_sync();
-            while (flush) {
-                const int q = __builtin_ctz(flush);
-                flush &= flush - 1;
-                nonempty &= ~(1u << q);
-                const int qg = s_qid[wave][q];
-                float nt = -__uint_as_float(0x7F800000u);
-                if (qg >= 0)
-                    nt = merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][q][0],
-                                             s_cnt[wave][q], kp);
-                if (lane == 0) s_cnt[wave][q] = 0;
-                // the query's threshold sits in one accumulator slot of one lane half
-                const int rr = 4 * (q / 8) + (q % 4), hh = (q / 4) & 1;
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    if (r == rr && half == hh) tauv[r] = nt;
-                wave_lds_sync();
+                if (lane == 0 && (ma || fa)) s_cnt[wave][qa_] = na;
+                if (lane == 32 && (mb || fb)) s_cnt[wave][qb_] = nb;
+                if (na) nonempty |= 1u << qa_;
+                else if (fa) nonempty &= ~(1u << qa_);
+                if (nb) nonempty |= 1u << qb_;
+                else if (fb) nonempty &= ~(1u << qb_);
             }
         }
     }
