@@ -370,13 +370,34 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
             }
             if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(tile + 1) * 32 + (lane & 31)];
         }
-        frag bfr[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) bfr[s] = s_tile[stage][s][half][lane & 31];
+        // all fragment reads are issued before the products (up to 16 at a
+        // time), and even / odd K-steps go to two accumulators, so the chain of
+        // dependent MFMAs is half as long and does not wait on each LDS read
         f32x16 acc;
-        const f32x16 zero = {};
+        {
+            constexpr int BATCH = KS <= 16 ? KS : 4;
+            const f32x16 zero = {};
+            f32x16 acc0 = zero, acc1 = zero;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) acc = Tr::mma(qa[s], bfr[s], s == 0 ? zero : acc);
+            for (int s0 = 0; s0 < KS; s0 += BATCH) {
+                frag bfr[BATCH];
+#pragma unroll
+                for (int u = 0; u < BATCH; ++u)
+                    if (s0 + u < KS) bfr[u] = s_tile[stage][s0 + u][half][lane & 31];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < BATCH; ++u) {
+                    const int s = s0 + u;
+                    if (s < KS) {
+                        if (s % 2 == 0)
+                            acc0 = Tr::mma(qa[s], bfr[u], acc0);
+                        else
+                            acc1 = Tr::mma(qa[s], bfr[u], acc1);
+                    }
+                }
+            }
+            acc = KS > 1 ? acc0 + acc1 : acc0;
+        }
 
         const int cand = LEARNED ? cid_cur : tile * 32 + (lane & 31);
         const bool valid = LEARNED ? cand >= 0 : cand < n;
