@@ -61,6 +61,9 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=0,
                     help="sample count override (same recipe, for profiling runs; not a bench line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--curve-order", type=int, default=1, choices=[0, 1],
+                    help="exact matrix-core modes: 1 scans candidates in curve order with projected-box pruning, "
+                         "0 scans every tile")
     ap.add_argument("--train-epochs", type=int, default=10, help="learned mode: partitioner training epochs")
     ap.add_argument("--n-probe", type=int, default=8,
                     help="learned mode: buckets each query searches (the configured top-4 gives recall "
@@ -103,6 +106,7 @@ def main() -> int:
     torch.cuda.set_device(0)
     Xd = torch.from_numpy(X).cuda()
     ctx = kvb.context()
+    ctx.set_option(kvb.OPT_CURVE_ORDER, args.curve_order)
 
     learned = None
     if w.mode == "learned":
@@ -228,6 +232,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "m": w.m, "k": w.k, "k0": w.k0, "d": w.d,
                    "mode": w.mode, "margin": w.margin, "grid": [w.e_min, w.e_max, w.G],
+                   "curve_order": bool(args.curve_order) and w.mode != "learned" and not (w.mode == "f32" and w.m <= 8),
                    "alpha": w.alpha, "beta": w.beta, "fallback_rows": fb, "learned": learned},
         "roofline": roofline,
         "cpu_baseline": cpu,

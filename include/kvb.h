@@ -91,6 +91,10 @@ extern "C" {
                                     3 (hi/lo pairs, default) or 6 (hi/mid/lo pairs) */
 #define KVB_OPT_N_PROBE 4        /* learned mode: buckets each query searches (1..min(32, n_buckets)); needs a
                                     partitioner in the context; saved with it */
+#define KVB_OPT_CURVE_ORDER 5    /* matrix-core exact modes, m <= 256: 1 (default) scans candidates in the Morton
+                                    order of the principal projections and skips tiles whose projected boxes
+                                    lie beyond every query's threshold; 0 scans every tile in sample order.
+                                    Either way the result is the same exact k-NN */
 
 typedef struct kvb_ctx_s* kvb_ctx;
 

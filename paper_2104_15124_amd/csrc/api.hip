@@ -100,6 +100,10 @@ int kvb_set_option(kvb_ctx ctx, int32_t key, int64_t value)
                     "KVB_OPT_N_PROBE must be in [1, min(32, n_buckets)]");
         ctx->part.np = static_cast<int>(value);
         return KVB_OK;
+    case KVB_OPT_CURVE_ORDER:
+        KVB_REQUIRE(ctx, value == 0 || value == 1, "KVB_OPT_CURVE_ORDER must be 0 or 1");
+        ctx->curve_order = static_cast<int>(value);
+        return KVB_OK;
     case KVB_OPT_BF16_SPLIT:
         KVB_REQUIRE(ctx, value == 1 || value == 3 || value == 6, "KVB_OPT_BF16_SPLIT must be 1, 3 or 6");
         ctx->bf16_split = static_cast<int>(value);
@@ -158,6 +162,23 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
     else
         need += 2 * round256(size_t(nn + 31) / 32 * 32 * kpad * esz) + round256(size_t(nn) * sizeof(float)) +
                 round256(size_t(m) * sizeof(double)) + round256(size_t(colblocks) * m * sizeof(double)) + 256;
+    // curve order of the principal projections (matrix-core modes)
+    const bool curve = !direct && ctx->curve_order && m <= 256;
+    const int npad32 = (nn + 31) / 32 * 32, ctiles = npad32 / 32;
+    const int csb = (ctiles + kvb::SB_TILES_MFMA - 1) / kvb::SB_TILES_MFMA;
+    const size_t ntri = size_t(m) * (m + 1) / 2;
+    size_t csort = 0;
+    if (curve) {
+        csort = kvb::curve_sort_bytes(nn);
+        need += round256(size_t(kvb::cov_partials()) * ntri * sizeof(double)) +
+                round256(size_t(m) * m * sizeof(double)) + round256((size_t(m) * kvb::PR_DIMS + 1) * sizeof(float)) +
+                round256(size_t(nn) * kvb::PR_DIMS * sizeof(float)) +
+                round256(size_t(kvb::project_blocks(nn)) * 2 * kvb::PCODE_DIMS * sizeof(float)) +
+                2 * round256(size_t(nn) * sizeof(uint32_t)) + 3 * round256(size_t(nn) * sizeof(int32_t)) +
+                round256(size_t(npad32) * sizeof(int32_t)) + round256(size_t(npad32) * kvb::PR_DIMS * sizeof(float)) +
+                round256(size_t(ctiles) * 2 * kvb::PR_DIMS * sizeof(float)) +
+                round256(size_t(csb) * 2 * kvb::PR_DIMS * sizeof(float)) + round256(csort) + 512;
+    }
     int rc = ensure_scratch(ctx, need);
     if (rc) return rc;
     Carve cv(ctx->scratch);
@@ -201,11 +222,50 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
         double* mu = cv.take<double>(m);
         double* colpart = cv.take<double>(size_t(colblocks) * m);
         unsigned* rmax = cv.take<unsigned>(1);
+        kvb::CurveArgs crv = {};
         {
             Prof pr(ctx, KVB_PROF_KNN_PREP);
             KVB_HIP(ctx, hipMemsetAsync(rmax, 0, sizeof(unsigned), ctx->stream));
-            KVB_HIP(ctx, kvb::launch_prep(X, nn, m, split, kpad, colpart, colblocks, mu, Aq, Bc, ynorm2, rmax,
-                                          nullptr, ctx->stream));
+            if (curve) {
+                double* covpart = cv.take<double>(size_t(kvb::cov_partials()) * ntri);
+                double* C = cv.take<double>(size_t(m) * m);
+                float* P = cv.take<float>(size_t(m) * kvb::PR_DIMS + 1);
+                float* z = cv.take<float>(size_t(nn) * kvb::PR_DIMS);
+                float* zpart = cv.take<float>(size_t(kvb::project_blocks(nn)) * 2 * kvb::PCODE_DIMS);
+                uint32_t* code = cv.take<uint32_t>(nn);
+                uint32_t* scode = cv.take<uint32_t>(nn);
+                int32_t* vals = cv.take<int32_t>(nn);
+                int32_t* perm = cv.take<int32_t>(nn);
+                int32_t* pos = cv.take<int32_t>(nn);
+                int32_t* cid = cv.take<int32_t>(npad32);
+                float* zs = cv.take<float>(size_t(npad32) * kvb::PR_DIMS);
+                float* tbox = cv.take<float>(size_t(ctiles) * 2 * kvb::PR_DIMS);
+                float* sbox = cv.take<float>(size_t(csb) * 2 * kvb::PR_DIMS);
+                void* sort_tmp = cv.take<char>(csort);
+                KVB_HIP(ctx, kvb::launch_colmean(X, nn, m, colpart, colblocks, mu, ctx->stream));
+                KVB_HIP(ctx, kvb::launch_principal_basis(X, nn, m, mu, covpart, C, P, ctx->stream));
+                KVB_HIP(ctx, kvb::launch_curve_order(X, nn, m, mu, P, z, zpart, code, scode, vals, perm, sort_tmp,
+                                                     csort, pos, cid, zs, tbox, sbox, ctx->stream));
+                // the padding rows of the last tile hold zeros (their keys are never taken)
+                const size_t tile_bytes = size_t(32) * kpad * esz;
+                KVB_HIP(ctx, hipMemsetAsync(static_cast<char*>(Bc) + size_t(ctiles - 1) * tile_bytes, 0, tile_bytes,
+                                            ctx->stream));
+                KVB_HIP(ctx, kvb::launch_prep_rows(X, nn, m, mu, split, kpad, Aq, Bc, ynorm2, rmax, pos, pos,
+                                                   ctx->stream));
+                const double u = std::ldexp(1.0, -24);
+                crv.perm = cid;
+                crv.zs = zs;
+                crv.tbox = tbox;
+                crv.sbox = sbox;
+                crv.pscale = P + size_t(m) * kvb::PR_DIMS;
+                // a float32 dot product of m terms errs by at most m u |y| |p| (|p| <= 1 + m u)
+                crv.zcoef = static_cast<float>((m + 2) * u * 1.01);
+                // |y_i - y_j| - |x_i - x_j| <= u (|x_i - mu| + |x_j - mu|) for y = fl(x - mu)
+                crv.ycoef = static_cast<float>(2.1 * u);
+            } else {
+                KVB_HIP(ctx, kvb::launch_prep(X, nn, m, split, kpad, colpart, colblocks, mu, Aq, Bc, ynorm2, rmax,
+                                              nullptr, nullptr, ctx->stream));
+            }
         }
         // error model of the selection score (derivation in knn_mfma.hip)
         const double u = std::ldexp(1.0, -24);
@@ -221,7 +281,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
         {
             Prof pr(ctx, KVB_PROF_KNN_SELECT);
             KVB_HIP(ctx, kvb::launch_select_mfma(split, Aq, Bc, nn, kpad, kp, ynorm2, rmax, em, keys, cap, slast,
-                                                 nullptr, 0, ctx->pairs_dev, ctx->stream));
+                                                 nullptr, 0, curve ? &crv : nullptr, ctx->pairs_dev, ctx->stream));
         }
         kstride = cap;
     }

@@ -94,18 +94,19 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
                                                    const double* __restrict__ mu, int split, int kpad,
                                                    void* __restrict__ Aq, void* __restrict__ Bc,
                                                    float* __restrict__ ynorm2, unsigned* __restrict__ rmax_bits,
-                                                   const int* __restrict__ brow)
+                                                   const int* __restrict__ brow, const int* __restrict__ arow)
 {
     const int lane = lane_id();
     const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (i >= npad) return;
     const bool real = i < n;
     const int ib = (brow && real) ? brow[i] : i;   // candidate operand row
+    const int ia = (arow && real) ? arow[i] : i;   // query operand row
     const float* x = X + static_cast<size_t>(real ? i : 0) * m;
     double nrm = 0.0;
     if (split == 0) {
         constexpr int KS = 2, VE = 1;
-        float* A = static_cast<float*>(Aq) + static_cast<size_t>(i) * kpad;
+        float* A = static_cast<float*>(Aq) + static_cast<size_t>(ia) * kpad;
         float* B = static_cast<float*>(Bc);
         for (int c = lane; c < m; c += WAVE) {
             const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
         }
     } else {
         constexpr int KS = 16, VE = 8;
-        uint16_t* A = static_cast<uint16_t*>(Aq) + static_cast<size_t>(i) * kpad;
+        uint16_t* A = static_cast<uint16_t*>(Aq) + static_cast<size_t>(ia) * kpad;
         uint16_t* B = static_cast<uint16_t*>(Bc);
         for (int c = lane; c < m; c += WAVE) {
             const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
@@ -221,6 +222,63 @@ __device__ __noinline__ float merge_query_list(uint64_t* __restrict__ dst, const
     return key_dist(list_at<E>(L, kp - 1));
 }
 
+// Lower bound on the squared distance between any query of a workgroup (box
+// qlo..qhi of its projected coordinates) and any sample in the projected box
+// b ([lower corner, upper corner]), from the box gaps g_c. The computed
+// projections differ from the exact P^T y by at most zerr per coordinate,
+// |v| >= pscale |P^T v| for every v (the float32 basis is orthonormal only up
+// to rounding; pscale is computed from its Gram matrix), and |y_i - y_j|
+// exceeds |x_i - x_j| by at most yerr; every float32 step below is taken
+// towards a smaller bound.
+struct BoxBound {
+    float zerr, pscale, yerr;
+};
+
+__device__ __forceinline__ float box_bound(const float* __restrict__ b, const float (&qlo)[PR_DIMS],
+                                           const float (&qhi)[PR_DIMS], const BoxBound& bb)
+{
+    float g2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < PR_DIMS; ++c) {
+        const float g = fmaxf(fmaxf(b[c] - qhi[c], qlo[c] - b[PR_DIMS + c]), 0.f);
+        const float gg = fmaxf(g * (1.f - 2.4e-7f) - 2.f * bb.zerr, 0.f);
+        g2 = fmaf(gg, gg, g2);
+    }
+    const float d = sqrtf(g2 * (1.f - 2e-6f)) * bb.pscale - bb.yerr;
+    return d > 0.f ? d * d * (1.f - 2e-6f) : 0.f;
+}
+
+// Next tile of a curve-order scan (own tile, then alternately right and
+// left), skipping tiles and entered superblocks whose bound exceeds thr; -1
+// when the scan is done. The same in every wavefront of the workgroup.
+__device__ __forceinline__ int curve_next(int& cur_r, int& cur_l, bool& go_right, int own_t, int tend, float thr,
+                                          const float (&qlo)[PR_DIMS], const float (&qhi)[PR_DIMS],
+                                          const CurveArgs& crv, const BoxBound& bb)
+{
+    while (cur_r < tend || cur_l >= 0) {
+        int t;
+        if ((go_right && cur_r < tend) || cur_l < 0) {
+            t = cur_r++;
+            go_right = false;
+            if (t % SB_TILES_MFMA == 0 && t != own_t &&
+                box_bound(crv.sbox + static_cast<size_t>(t / SB_TILES_MFMA) * 2 * PR_DIMS, qlo, qhi, bb) > thr) {
+                cur_r = t + SB_TILES_MFMA;
+                continue;
+            }
+        } else {
+            t = cur_l--;
+            go_right = true;
+            if (t % SB_TILES_MFMA == SB_TILES_MFMA - 1 &&
+                box_bound(crv.sbox + static_cast<size_t>(t / SB_TILES_MFMA) * 2 * PR_DIMS, qlo, qhi, bb) > thr) {
+                cur_l = t - SB_TILES_MFMA;
+                continue;
+            }
+        }
+        if (t == own_t || box_bound(crv.tbox + static_cast<size_t>(t) * 2 * PR_DIMS, qlo, qhi, bb) <= thr) return t;
+    }
+    return -1;
+}
+
 // Sort query q's list in place (whole wavefront) and return its kp-th score.
 template <int E>
 __device__ __noinline__ float sort_query_list(uint64_t* __restrict__ dst, int kp)
@@ -241,21 +299,39 @@ __device__ __noinline__ float sort_query_list(uint64_t* __restrict__ dst, int kp
 // at or below a query's threshold collect in its LDS buffer of BUF keys, which
 // is merged into the list whenever the next tile's keys would not fit.
 //
-// LEARNED = true: bucketed search of the learned partitioner. Workgroup w takes
-// work item (bucket b, first query entry t0): its queries are entries
+// MODE 0: queries and candidates in sample order, every tile scanned.
+//
+// MODE 1 (learned): bucketed search of the learned partitioner. Workgroup w
+// takes work item (bucket b, first query entry t0): its queries are entries
 // t0 .. min(t0 + 32 WV, qptr[b + 1]) - 1 of qids, its candidates the tiles
 // tptr[b] .. tptr[b + 1] - 1 of the bucket-ordered candidate operand, whose
 // rows map to sample ids through cid (-1 for padding). Lists of queries are
 // created on the first probe pass and merged into on later ones (the list's
 // kp-th score is the starting threshold); no certificate is computed.
-template <class Tr, int KS, int WV, int E, bool LEARNED>
+//
+// MODE 2 (curve order): operands are laid out in the Morton order of the
+// samples' principal projections (spatial_mfma.hip); curve position p holds
+// sample crv.perm[p]. A workgroup's queries are consecutive positions; it scans
+// tiles outward from its own along the curve and skips every tile (or, where
+// the scan enters one, every superblock of SB_TILES_MFMA tiles) whose
+// projected box is farther from the workgroup's query box than the largest
+// distance threshold of its queries (the bound and its rounding margins are
+// derived with the pruning test below). The thresholds are exchanged between
+// the wavefronts through a double-buffered LDS array at each stage barrier, so
+// all wavefronts take the same skipping decisions. The certificate epilogue
+// is that of MODE 0: a skipped candidate lies beyond the threshold at the
+// time of the skip, hence beyond every later one.
+template <class Tr, int KS, int WV, int E, int MODE>
 __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem* __restrict__ Aq,
                                                           const typename Tr::elem* __restrict__ Bc, int n, int kp,
                                                           const float* __restrict__ ynorm2,
                                                           const unsigned* __restrict__ rmax_bits, ErrModel em,
                                                           uint64_t* __restrict__ lists, float* __restrict__ lb_out,
-                                                          BucketArgs ba, unsigned long long* __restrict__ pair_count)
+                                                          BucketArgs ba, CurveArgs crv,
+                                                          unsigned long long* __restrict__ pair_count)
 {
+    constexpr bool LEARNED = MODE == 1;
+    constexpr bool CURVE = MODE == 2;
     using elem = typename Tr::elem;
     using frag = typename Tr::frag;
     constexpr int CAP = WAVE * E;
@@ -288,6 +364,10 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
         tbeg = ba.tptr[wk.x];
         tend = ba.tptr[wk.x + 1];
         if (lane < NQ) s_qid[wave][lane] = q0 + lane < qend ? ba.qids[q0 + lane] : -1;
+    } else if constexpr (CURVE) {
+        q0 = (blockIdx.x * WV + wave) * NQ;
+        tend = (n + 31) / 32;
+        if (lane < NQ) s_qid[wave][lane] = q0 + lane < n ? crv.perm[q0 + lane] : -1;
     } else {
         q0 = (blockIdx.x * WV + wave) * NQ;
         tend = (n + 31) / 32;
@@ -297,7 +377,8 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
 
     frag qa[KS];
     {
-        int row = s_qid[wave][lane & 31];
+        // query operand row: curve position (MODE 2) or sample id
+        int row = CURVE ? min(q0 + (lane & 31), n - 1) : s_qid[wave][lane & 31];
         if (row < 0) row = max(s_qid[wave][0], 0);
         const elem* src = Aq + static_cast<size_t>(row) * kpad + half * Tr::VEC;
 #pragma unroll
@@ -330,27 +411,89 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
     // out exactly like an LDS stage: it moves as 16-byte pieces
     // the query fragments have landed before the loop, so the only vector
     // loads in flight inside it are the next tile's prefetch
+    int qrow[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) qrow[r] = s_qid[wave][acc_row(r, half)];
+
+    // MODE 2: the workgroup's query box in projected space, the squared norms
+    // of the queries (thresholds are kept as scores s = |y_j|^2 - 2 y_i.y_j, the
+    // distance threshold is s + |y_i|^2) and the scan cursor
+    __shared__ float s_qbox[WV][2][PR_DIMS];
+    __shared__ float s_thr[2][WV];
+    float qlo[PR_DIMS], qhi[PR_DIMS], yq[16];
+    int cur_r = 0, cur_l = -1, own_t = 0;
+    bool go_right = true;
+    BoxBound bb = {0.f, 1.f, 0.f};
+    if constexpr (CURVE) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) yq[r] = qrow[r] >= 0 ? ynorm2[qrow[r]] : 0.f;
+#pragma unroll
+        for (int c = 0; c < PR_DIMS; ++c) {
+            const bool ok = lane < NQ && q0 + lane < n;
+            const float v = ok ? crv.zs[static_cast<size_t>(q0 + lane) * PR_DIMS + c] : 0.f;
+            float lo = ok ? v : __uint_as_float(0x7F800000u), hi = ok ? v : -__uint_as_float(0x7F800000u);
+#pragma unroll
+            for (int o = WAVE / 2; o > 0; o >>= 1) {
+                lo = fminf(lo, shfl_xor_f32(lo, o));
+                hi = fmaxf(hi, shfl_xor_f32(hi, o));
+            }
+            if (lane == 0) {
+                s_qbox[wave][0][c] = lo;
+                s_qbox[wave][1][c] = hi;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < PR_DIMS; ++c) {
+            qlo[c] = s_qbox[0][0][c];
+            qhi[c] = s_qbox[0][1][c];
+#pragma unroll
+            for (int w = 1; w < WV; ++w) {
+                qlo[c] = fminf(qlo[c], s_qbox[w][0][c]);
+                qhi[c] = fmaxf(qhi[c], s_qbox[w][1][c]);
+            }
+        }
+        own_t = min(tend - 1, (blockIdx.x * WV * NQ + WV * NQ / 2) / 32);
+        const float R = __uint_as_float(*rmax_bits);
+        bb.zerr = crv.zcoef * R;
+        bb.pscale = *crv.pscale;
+        bb.yerr = crv.ycoef * R;
+        cur_r = own_t;
+        cur_l = own_t - 1;
+    }
     __builtin_amdgcn_s_waitcnt(0);
     u32x4 pf[PF];
     int cid_pf = -1;
-    if (tbeg < tend) {
-        const u32x4* g = reinterpret_cast<const u32x4*>(Bc + static_cast<size_t>(tbeg) * 32 * kpad);
+    int tile = -1;
+    if (tbeg < tend)
+        tile = CURVE ? curve_next(cur_r, cur_l, go_right, own_t, tend, __uint_as_float(0x7F800000u), qlo, qhi, crv, bb)
+                     : tbeg;
+    if (tile >= 0) {
+        const u32x4* g = reinterpret_cast<const u32x4*>(Bc + static_cast<size_t>(tile) * 32 * kpad);
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int ch = threadIdx.x + u * 64 * WV;
             if (ch < CHUNKS) pf[u] = g[ch];
         }
-        if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(tbeg) * 32 + (lane & 31)];
+        if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(tile) * 32 + (lane & 31)];
+        if constexpr (CURVE) cid_pf = crv.perm[static_cast<size_t>(tile) * 32 + (lane & 31)];
     }
     uint32_t nonempty = 0;   // queries with buffered entries (wave-uniform)
     // lists that start empty are filled by the first tiles without merging
     bool filling = !LEARNED || ba.first;
     const int fill_tiles = (kp + 31) / 32;
-    int qrow[16];
+    for (int it = 0; tile >= 0; ++it) {
+        const int stage = it & 1;
+        if constexpr (CURVE) {
+            // this wavefront's largest distance threshold, an upper bound of
+            // s + |y_i|^2 over its queries
+            float t = -__uint_as_float(0x7F800000u);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) qrow[r] = s_qid[wave][acc_row(r, half)];
-    for (int tile = tbeg; tile < tend; ++tile) {
-        const int stage = (tile - tbeg) & 1;
+            for (int r = 0; r < 16; ++r)
+                if (qrow[r] >= 0) t = fmaxf(t, fmaxf(tauv[r] + yq[r], 0.f) * (1.f + 4.8e-7f));
+            t = wave_max_f32(t);
+            if (lane == 0) s_thr[stage][wave] = t;
+        }
         {
             u32x4* d = reinterpret_cast<u32x4*>(&s_tile[stage][0][0][0]);
 #pragma unroll
@@ -361,14 +504,26 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
         }
         const int cid_cur = cid_pf;
         __syncthreads();                 // stage visible; the other stage's readers finished a tile ago
-        if (tile + 1 < tend) {
-            const u32x4* g = reinterpret_cast<const u32x4*>(Bc + static_cast<size_t>(tile + 1) * 32 * kpad);
+        float thr = __uint_as_float(0x7F800000u);
+        if constexpr (CURVE) {
+            thr = s_thr[stage][0];
+#pragma unroll
+            for (int w = 1; w < WV; ++w) thr = fmaxf(thr, s_thr[stage][w]);
+        }
+        int next;
+        if constexpr (CURVE)
+            next = curve_next(cur_r, cur_l, go_right, own_t, tend, thr, qlo, qhi, crv, bb);
+        else
+            next = tile + 1 < tend ? tile + 1 : -1;
+        if (next >= 0) {
+            const u32x4* g = reinterpret_cast<const u32x4*>(Bc + static_cast<size_t>(next) * 32 * kpad);
 #pragma unroll
             for (int u = 0; u < PF; ++u) {
                 const int ch = threadIdx.x + u * 64 * WV;
                 if (ch < CHUNKS) pf[u] = g[ch];
             }
-            if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(tile + 1) * 32 + (lane & 31)];
+            if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(next) * 32 + (lane & 31)];
+            if constexpr (CURVE) cid_pf = crv.perm[static_cast<size_t>(next) * 32 + (lane & 31)];
         }
         // all fragment reads are issued before the products (up to 16 at a
         // time), and even / odd K-steps go to two accumulators, so the chain of
@@ -399,19 +554,19 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
             acc = KS > 1 ? acc0 + acc1 : acc0;
         }
 
-        const int cand = LEARNED ? cid_cur : tile * 32 + (lane & 31);
-        const bool valid = LEARNED ? cand >= 0 : cand < n;
+        const int cand = MODE != 0 ? cid_cur : tile * 32 + (lane & 31);
+        const bool valid = MODE != 0 ? cand >= 0 : cand < n;
         pairs += static_cast<unsigned long long>(nq_valid) *
                  static_cast<unsigned long long>(__popcll(__ballot(valid) & 0xFFFFFFFFull));
         if (filling) {
             // the first ceil(kp / 32) tiles go straight into the (empty) lists
-            const int slot = (tile - tbeg) * 32 + (lane & 31);
+            const int slot = it * 32 + (lane & 31);
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (qrow[r] >= 0)
                     lists[static_cast<size_t>(qrow[r]) * CAP + slot] =
                         valid ? make_key(acc[r], static_cast<uint32_t>(cand)) : KEY_INF;
-            if (tile - tbeg + 1 == fill_tiles || tile + 1 == tend) {
+            if (it + 1 == fill_tiles || next < 0) {
                 filling = false;
                 // the lists' stores complete before other lanes read them
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -427,6 +582,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
                         if (r == rr && half == hh) tauv[r] = nt;
                 }
             }
+            tile = next;
             continue;
         }
 #pragma unroll
@@ -481,6 +637,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
                 else if (fb) nonempty &= ~(1u << qb_);
             }
         }
+        tile = next;
     }
     wave_lds_sync();
     while (nonempty) {
@@ -496,8 +653,8 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
     // certificate lower bound for the candidates left out of each list
     const double R = static_cast<double>(__uint_as_float(*rmax_bits));
     if (lane < NQ) {
-        const int qg = q0 + lane;
-        if (qg < n) {
+        const int qg = s_qid[wave][lane];
+        if (qg >= 0) {
             const float sl = key_dist(lists[static_cast<size_t>(qg) * CAP + (kp - 1)]);
             const double yi2 = static_cast<double>(ynorm2[qg]);
             const double yi = sqrt(yi2);
@@ -513,23 +670,41 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_prep(const float* X, int n, int m, int split, int kpad, double* colpart, int colblocks,
-                       double* mu, void* Aq, void* Bc, float* ynorm2, unsigned* rmax_bits, const int* brow,
-                       hipStream_t st)
+hipError_t launch_colmean(const float* X, int n, int m, double* colpart, int colblocks, double* mu, hipStream_t st)
 {
     const int rpb = (n + colblocks - 1) / colblocks;
+    hipLaunchKernelGGL(k_colsum_partial, dim3(colblocks), dim3(256), 0, st, X, n, m, rpb, colpart);
+    hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(256), 0, st, colpart, colblocks, m, n, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_rows(const float* X, int n, int m, const double* mu, int split, int kpad, void* Aq, void* Bc,
+                            float* ynorm2, unsigned* rmax_bits, const int* brow, const int* arow, hipStream_t st)
+{
+    const int npad = brow ? n : (n + 31) / 32 * 32;
+    hipLaunchKernelGGL(k_prep_rows, dim3((npad + 3) / 4), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq, Bc,
+                       ynorm2, rmax_bits, brow, arow);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const float* X, int n, int m, int split, int kpad, double* colpart, int colblocks,
+                       double* mu, void* Aq, void* Bc, float* ynorm2, unsigned* rmax_bits, const int* brow,
+                       const int* arow, hipStream_t st)
+{
+    const int rpb = (n + colblocks - 1) / colblocks;
+    // with a row map the padding rows of the last tile are filled separately
     const int npad = brow ? n : (n + 31) / 32 * 32;
     hipLaunchKernelGGL(k_colsum_partial, dim3(colblocks), dim3(256), 0, st, X, n, m, rpb, colpart);
     hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(256), 0, st, colpart, colblocks, m, n, mu);
     hipLaunchKernelGGL(k_prep_rows, dim3((npad + 3) / 4), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq, Bc,
-                       ynorm2, rmax_bits, brow);
+                       ynorm2, rmax_bits, brow, arow);
     return hipGetLastError();
 }
 
 template <class Tr, int KS, int WV>
 static hipError_t launch_sel(const void* Aq, const void* Bc, int n, int kp, const float* ynorm2, const unsigned* rmax,
                              ErrModel em, uint64_t* lists, int cap, float* lb, const BucketArgs* ba, int max_work,
-                             unsigned long long* pairs, hipStream_t st)
+                             const CurveArgs* crv, unsigned long long* pairs, hipStream_t st)
 {
     using elem = typename Tr::elem;
     const int rows_per_block = WV * 32;
@@ -539,25 +714,35 @@ static hipError_t launch_sel(const void* Aq, const void* Bc, int n, int kp, cons
     // the lists buffer holds n * cap keys; only capacities 128 and 256 exist
     if (kp > cap) return hipErrorInvalidValue;
     if (cap != 128 && cap != 256) return hipErrorInvalidValue;
+    const BucketArgs nb = {};
+    const CurveArgs nc = {};
     if (ba) {
         if (max_work <= 0) return hipSuccess;
         const dim3 grid(max_work);
         if (cap == 128)
-            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2, true>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
-                               lists, lb, *ba, pairs);
+            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2, 1>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
+                               lists, lb, *ba, nc, pairs);
         else
-            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4, true>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
-                               lists, lb, *ba, pairs);
+            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4, 1>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
+                               lists, lb, *ba, nc, pairs);
         return hipGetLastError();
     }
     const dim3 grid((n + rows_per_block - 1) / rows_per_block);
-    const BucketArgs none = {};
+    if (crv) {
+        if (cap == 128)
+            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2, 2>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
+                               lists, lb, nb, *crv, pairs);
+        else
+            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4, 2>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
+                               lists, lb, nb, *crv, pairs);
+        return hipGetLastError();
+    }
     if (cap == 128)
-        hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2, false>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
-                           lists, lb, none, pairs);
+        hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2, 0>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em, lists,
+                           lb, nb, nc, pairs);
     else
-        hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4, false>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
-                           lists, lb, none, pairs);
+        hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4, 0>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em, lists,
+                           lb, nb, nc, pairs);
     return hipGetLastError();
 }
 
@@ -580,7 +765,7 @@ int mfma_pick_ksteps(int split, int needed)
 }
 
 #define KVB_SEL_CASE(TR, K, WV) \
-    case K: return launch_sel<TR, K, WV>(Aq, Bc, n, kp, ynorm2, rmax, em, lists, cap, lb, ba, max_work, pairs, st);
+    case K: return launch_sel<TR, K, WV>(Aq, Bc, n, kp, ynorm2, rmax, em, lists, cap, lb, ba, max_work, crv, pairs, st);
 
 int select_mfma_queries_per_block(int split, int kpad)
 {
@@ -591,7 +776,8 @@ int select_mfma_queries_per_block(int split, int kpad)
 
 hipError_t launch_select_mfma(int split, const void* Aq, const void* Bc, int n, int kpad, int kp, const float* ynorm2,
                               const unsigned* rmax, ErrModel em, uint64_t* lists, int cap, float* lb,
-                              const BucketArgs* ba, int max_work, unsigned long long* pairs, hipStream_t st)
+                              const BucketArgs* ba, int max_work, const CurveArgs* crv, unsigned long long* pairs,
+                              hipStream_t st)
 {
     const int ks = kpad / mfma_kstep(split);
     if (split == 0) {

@@ -58,6 +58,7 @@ struct kvb_ctx_s {
     size_t scratch_limit = 0;
     int64_t force_fallback = 0;
     int bf16_split = 3;
+    int curve_order = 1;
     kvb::TuneResult* tune_dev = nullptr;
     kvb::TuneResult* tune_host = nullptr;   // pinned
     kvbh::BuildDev* build_dev = nullptr;    // device-resident tuning results of kvb_build

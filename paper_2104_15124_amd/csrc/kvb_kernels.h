@@ -28,6 +28,23 @@ struct BucketArgs {
     int first;           // 1: create the query lists, 0: merge into them
 };
 
+// Projected dimensions of the curve order (MODE 2 of the matrix-core select):
+// boxes use PR_DIMS principal coordinates, the Morton code the first
+// PCODE_DIMS of them; superblocks group SB_TILES_MFMA tiles of 32 samples.
+constexpr int PR_DIMS = 8;
+constexpr int PCODE_DIMS = 4;
+constexpr int SB_TILES_MFMA = 16;
+
+struct CurveArgs {
+    const int* perm;    // [tiles * 32] sample id at each curve position, -1 for padding
+    const float* zs;    // [n, PR_DIMS] projected coordinates in curve order
+    const float* tbox;  // [tiles, 2, PR_DIMS] boxes of 32-sample tiles
+    const float* sbox;  // [superblocks, 2, PR_DIMS]
+    const float* pscale;// |v| >= *pscale |P^T v| for every v (set with the basis)
+    float zcoef;        // computed projected coordinates are within zcoef R of P^T y (R = max |y|)
+    float ycoef;        // |y_i - y_j| exceeds |x_i - x_j| by at most ycoef R
+};
+
 struct TuneResult {
     double chi[256];
     double e_star;
@@ -57,14 +74,30 @@ hipError_t launch_exact_rows(const float* X, int n, int m, int k, const int* row
 
 hipError_t launch_prep(const float* X, int n, int m, int split, int kpad, double* colpart, int colblocks,
                        double* mu, void* Aq, void* Bc, float* ynorm2, unsigned* rmax_bits, const int* brow,
-                       hipStream_t st);
+                       const int* arow, hipStream_t st);
+hipError_t launch_colmean(const float* X, int n, int m, double* colpart, int colblocks, double* mu, hipStream_t st);
+hipError_t launch_prep_rows(const float* X, int n, int m, const double* mu, int split, int kpad, void* Aq, void* Bc,
+                            float* ynorm2, unsigned* rmax_bits, const int* brow, const int* arow, hipStream_t st);
 int mfma_kstep(int split);
 int mfma_pick_ksteps(int split, int needed);
 // ba == nullptr: exact all-pairs selection over n rows; otherwise the bucketed
 // selection with max_work workgroups (the kernel skips those beyond *ba->n_work).
 hipError_t launch_select_mfma(int split, const void* Aq, const void* Bc, int n, int kpad, int kp, const float* ynorm2,
                               const unsigned* rmax, ErrModel em, uint64_t* lists, int cap, float* lb,
-                              const BucketArgs* ba, int max_work, unsigned long long* pairs, hipStream_t st);
+                              const BucketArgs* ba, int max_work, const CurveArgs* crv, unsigned long long* pairs,
+                              hipStream_t st);
+// curve order of the samples for MODE 2 (spatial_mfma.hip)
+int cov_partials();
+int cov_chunks(int m);
+int project_blocks(int n);
+size_t curve_sort_bytes(int n);
+// P [m * PR_DIMS + 1]: the basis, then the scale factor of CurveArgs::pscale
+hipError_t launch_principal_basis(const float* X, int n, int m, const double* mu, double* part, double* C, float* P,
+                                  hipStream_t st);
+hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, const float* P, float* z, float* zpart,
+                              uint32_t* code, uint32_t* scode, int32_t* vals, int32_t* perm, void* sort_tmp,
+                              size_t sort_bytes, int32_t* pos, int32_t* cid, float* zs, float* tbox, float* sbox,
+                              hipStream_t st);
 int select_mfma_queries_per_block(int split, int kpad);
 
 // passes

@@ -361,7 +361,7 @@ int learned_knn(kvb_ctx ctx, const float* X, int n, int m, int k, int kp, int32_
     {
         Prof pr(ctx, KVB_PROF_KNN_PREP);
         KVB_HIP(ctx, hipMemsetAsync(rmax, 0, sizeof(unsigned), st));
-        KVB_HIP(ctx, kvb::launch_prep(X, n, m, split, kpad, colpart, colblocks, mu, Aq, Bp, ynorm2, rmax, brow, st));
+        KVB_HIP(ctx, kvb::launch_prep(X, n, m, split, kpad, colpart, colblocks, mu, Aq, Bp, ynorm2, rmax, brow, nullptr, st));
     }
     {
         Prof pr(ctx, KVB_PROF_KNN_SELECT);
@@ -376,7 +376,7 @@ int learned_knn(kvb_ctx ctx, const float* X, int n, int m, int k, int kp, int32_
             ba.cid = cid;
             ba.first = s == 0 ? 1 : 0;
             KVB_HIP(ctx, kvb::launch_select_mfma(split, Aq, Bp, n, kpad, kp, ynorm2, rmax, em, lists, cap, nullptr,
-                                                 &ba, max_work, ctx->pairs_dev, st));
+                                                 &ba, max_work, nullptr, ctx->pairs_dev, st));
         }
     }
     {

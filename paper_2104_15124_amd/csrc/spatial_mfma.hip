@@ -1,0 +1,340 @@
+// Spatial order and distance bounds for the matrix-core k-NN scan.
+//
+// Samples of a low intrinsic dimension (the manifold setting of Section 2)
+// concentrate near a few principal directions. An orthonormal basis P of the
+// top PR principal directions of the centred samples y is found by subspace
+// iteration on their covariance; the projections z = P^T y order the samples
+// along a Morton curve of their first PCODE coordinates. Query blocks and
+// candidate tiles of consecutive curve positions are then compact in z, and
+// because an orthonormal projection never lengthens a vector,
+//   |y_i - y_j|^2 >= |z_i - z_j|^2 >= (gap between the boxes of their z)^2,
+// a candidate tile whose box lies farther from a query block's box than all
+// of the block's current thresholds holds no neighbour of any of its queries
+// and is skipped (selection kernel, knn_mfma.hip). The bound is made rigorous
+// for the rounding of P, of z and of the box gaps by the margins set there.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "kvb_device.h"
+#include "kvb_kernels.h"
+
+namespace kvb {
+
+constexpr int COV_ROWS = 32;      // rows staged per step
+constexpr int COV_ENTRIES = 2048; // covariance entries per block (8 per thread)
+constexpr int COV_SAMPLE = 32768; // rows sampled for the covariance
+
+__device__ __forceinline__ void tri_index(int e, int m, int& a, int& b)
+{
+    // e-th entry of the upper triangle (a <= b), row by row
+    a = 0;
+    int rem = e;
+    while (rem >= m - a) {
+        rem -= m - a;
+        ++a;
+    }
+    b = a + rem;
+}
+
+// Partial sums of y y^T over the sampled rows (every `stride`-th row), y = x - mu,
+// for the entries chunk blockIdx.y of the upper triangle.
+__global__ __launch_bounds__(256) void k_cov_partial(const float* __restrict__ X, int n, int m,
+                                                     const double* __restrict__ mu, int stride, int rows_per_block,
+                                                     double* __restrict__ part)
+{
+    __shared__ float sy[COV_ROWS][256 + 1];
+    const int ntri = m * (m + 1) / 2;
+    const int e0 = blockIdx.y * COV_ENTRIES;
+    int ea[8], eb[8];
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int e = e0 + threadIdx.x + 256 * u;
+        acc[u] = 0.0;
+        ea[u] = -1;
+        eb[u] = 0;
+        if (e < ntri) tri_index(e, m, ea[u], eb[u]);
+    }
+    const int s_begin = blockIdx.x * rows_per_block;
+    const int nsample = (n + stride - 1) / stride;
+    const int s_end = min(nsample, s_begin + rows_per_block);
+    for (int s0 = s_begin; s0 < s_end; s0 += COV_ROWS) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < COV_ROWS * m; t += 256) {
+            const int r = t / m, c = t % m;
+            const int srow = s0 + r;
+            sy[r][c] = srow < s_end
+                           ? static_cast<float>(static_cast<double>(X[static_cast<size_t>(srow) * stride * m + c]) - mu[c])
+                           : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (ea[u] < 0) continue;
+            double a = 0.0;
+            for (int r = 0; r < COV_ROWS; ++r)
+                a += static_cast<double>(sy[r][ea[u]]) * static_cast<double>(sy[r][eb[u]]);
+            acc[u] += a;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int e = e0 + threadIdx.x + 256 * u;
+        if (e < ntri) part[static_cast<size_t>(blockIdx.x) * ntri + e] = acc[u];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cov_reduce(const double* __restrict__ part, int nparts, int m,
+                                                    double* __restrict__ C)
+{
+    const int ntri = m * (m + 1) / 2;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= ntri) return;
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += part[static_cast<size_t>(b) * ntri + e];
+    int a, b;
+    tri_index(e, m, a, b);
+    C[static_cast<size_t>(a) * m + b] = s;
+    C[static_cast<size_t>(b) * m + a] = s;
+}
+
+// Subspace iteration for the top PR eigenvectors of the covariance C (one
+// block): V <- orthonormalise(C V) from a fixed full-rank starting basis. The
+// product uses the whole block; modified Gram-Schmidt runs in the first
+// wavefront (float64, wavefront reductions in a fixed order). Columns of
+// negligible norm (a covariance of rank below PR) are set to zero, so the
+// nonzero columns of P stay orthonormal.
+__global__ __launch_bounds__(256) void k_subspace(const double* __restrict__ C, int m, int iters,
+                                                  float* __restrict__ P)
+{
+    __shared__ double V[256 * PR_DIMS];
+    __shared__ double W[256 * PR_DIMS];
+    for (int t = threadIdx.x; t < m * PR_DIMS; t += 256) {
+        const int a = t / PR_DIMS, j = t % PR_DIMS;
+        W[t] = (a % PR_DIMS == j ? 1.0 : 0.0) + 1e-3 * static_cast<double>((a * 7 + j * 13) % 17) / 17.0;
+    }
+    __syncthreads();
+    double trace = 0.0;
+    for (int a = 0; a < m; ++a) trace += C[static_cast<size_t>(a) * m + a];
+    const double tiny = 1e-24 * (trace > 0.0 ? trace * trace : 1.0);
+    for (int it = 0; it <= iters; ++it) {
+        if (it > 0) {
+            for (int t = threadIdx.x; t < m * PR_DIMS; t += 256) {
+                const int a = t / PR_DIMS, j = t % PR_DIMS;
+                double s = 0.0;
+                for (int b = 0; b < m; ++b) s += C[static_cast<size_t>(a) * m + b] * V[b * PR_DIMS + j];
+                W[t] = s;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x < WAVE) {
+            const int lane = threadIdx.x;
+            // Gram-Schmidt twice keeps the columns orthonormal to rounding level
+            for (int pass = 0; pass < 2; ++pass)
+            for (int j = 0; j < PR_DIMS; ++j) {
+                for (int l = 0; l < j; ++l) {
+                    double d = 0.0;
+                    for (int a = lane; a < m; a += WAVE) d += W[a * PR_DIMS + j] * W[a * PR_DIMS + l];
+                    d = wave_sum_f64(d);
+                    for (int a = lane; a < m; a += WAVE) W[a * PR_DIMS + j] -= d * W[a * PR_DIMS + l];
+                }
+                double nn = 0.0;
+                for (int a = lane; a < m; a += WAVE) nn += W[a * PR_DIMS + j] * W[a * PR_DIMS + j];
+                nn = wave_sum_f64(nn);
+                const double inv = (pass == 1 || nn > (it == 0 ? 1e-24 : tiny)) && nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+                for (int a = lane; a < m; a += WAVE) W[a * PR_DIMS + j] *= inv;
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < m * PR_DIMS; t += 256) V[t] = W[t];
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < m * PR_DIMS; t += 256) P[t] = static_cast<float>(V[t]);
+    __syncthreads();
+    // |P^T v|^2 <= lambda_max(P P^T) |v|^2 = lambda_max(P^T P) |v|^2, and the
+    // largest eigenvalue of the Gram matrix G = P^T P of the float32 basis is at
+    // most its largest absolute row sum: pscale = 1 / sqrt(that), rounded down
+    if (threadIdx.x == 0) {
+        double rmax = 0.0;
+        for (int j = 0; j < PR_DIMS; ++j) {
+            double row = 0.0;
+            for (int l = 0; l < PR_DIMS; ++l) {
+                double g = 0.0;
+                for (int a = 0; a < m; ++a)
+                    g += static_cast<double>(P[a * PR_DIMS + j]) * static_cast<double>(P[a * PR_DIMS + l]);
+                row += fabs(g);
+            }
+            rmax = fmax(rmax, row);
+        }
+        P[m * PR_DIMS] = rmax > 0.0 ? static_cast<float>((1.0 - 1e-6) / sqrt(rmax * (1.0 + 1e-9))) : 1.f;
+    }
+}
+
+// z_i = P^T y_i (float32, y = x - mu as in the operands), one thread per row;
+// per-block minima / maxima of the first PCODE coordinates for the code range.
+__global__ __launch_bounds__(256) void k_project(const float* __restrict__ X, int n, int m,
+                                                 const double* __restrict__ mu, const float* __restrict__ P,
+                                                 float* __restrict__ z, float* __restrict__ zpart)
+{
+    __shared__ float slo[PCODE_DIMS][256], shi[PCODE_DIMS][256];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    float zc[PR_DIMS];
+#pragma unroll
+    for (int c = 0; c < PR_DIMS; ++c) zc[c] = 0.f;
+    if (i < n) {
+        const float* x = X + static_cast<size_t>(i) * m;
+        for (int k = 0; k < m; ++k) {
+            const float y = static_cast<float>(static_cast<double>(x[k]) - mu[k]);
+#pragma unroll
+            for (int c = 0; c < PR_DIMS; ++c) zc[c] = fmaf(y, P[k * PR_DIMS + c], zc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < PR_DIMS; ++c) z[static_cast<size_t>(i) * PR_DIMS + c] = zc[c];
+    }
+#pragma unroll
+    for (int c = 0; c < PCODE_DIMS; ++c) {
+        slo[c][threadIdx.x] = i < n ? zc[c] : __uint_as_float(0x7F800000u);
+        shi[c][threadIdx.x] = i < n ? zc[c] : -__uint_as_float(0x7F800000u);
+    }
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+#pragma unroll
+            for (int c = 0; c < PCODE_DIMS; ++c) {
+                slo[c][threadIdx.x] = fminf(slo[c][threadIdx.x], slo[c][threadIdx.x + o]);
+                shi[c][threadIdx.x] = fmaxf(shi[c][threadIdx.x], shi[c][threadIdx.x + o]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < PCODE_DIMS) {
+        zpart[static_cast<size_t>(blockIdx.x) * 2 * PCODE_DIMS + threadIdx.x] = slo[threadIdx.x][0];
+        zpart[static_cast<size_t>(blockIdx.x) * 2 * PCODE_DIMS + PCODE_DIMS + threadIdx.x] = shi[threadIdx.x][0];
+    }
+}
+
+// Morton code of the first PCODE projected coordinates, 8 bits each, over the
+// range of the block partials; value = sample index (stable sort: ties by index).
+__global__ __launch_bounds__(256) void k_zcodes(const float* __restrict__ z, int n, const float* __restrict__ zpart,
+                                                int nparts, uint32_t* __restrict__ code, int32_t* __restrict__ vals)
+{
+    __shared__ float s_lo[PCODE_DIMS], s_scale[PCODE_DIMS];
+    if (threadIdx.x < PCODE_DIMS) {
+        const int c = threadIdx.x;
+        float lo = __uint_as_float(0x7F800000u), hi = -__uint_as_float(0x7F800000u);
+        for (int b = 0; b < nparts; ++b) {
+            lo = fminf(lo, zpart[static_cast<size_t>(b) * 2 * PCODE_DIMS + c]);
+            hi = fmaxf(hi, zpart[static_cast<size_t>(b) * 2 * PCODE_DIMS + PCODE_DIMS + c]);
+        }
+        s_lo[c] = lo;
+        s_scale[c] = hi > lo ? 256.f / (hi - lo) : 0.f;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    uint32_t q[PCODE_DIMS];
+#pragma unroll
+    for (int c = 0; c < PCODE_DIMS; ++c) {
+        const float t = (z[static_cast<size_t>(i) * PR_DIMS + c] - s_lo[c]) * s_scale[c];
+        q[c] = min(static_cast<uint32_t>(fminf(fmaxf(t, 0.f), 255.f)), 255u);
+    }
+    uint32_t zc = 0;
+    for (int b = 7; b >= 0; --b)
+#pragma unroll
+        for (int c = 0; c < PCODE_DIMS; ++c) zc = (zc << 1) | ((q[c] >> b) & 1u);
+    code[i] = zc;
+    vals[i] = i;
+}
+
+// pos[perm[p]] = p; cid[p] = perm[p] for p < n, -1 on the padding up to 32 tiles;
+// zs[p] = z[perm[p]].
+__global__ __launch_bounds__(256) void k_curve_maps(const int32_t* __restrict__ perm, int n, int npad,
+                                                    const float* __restrict__ z, int32_t* __restrict__ pos,
+                                                    int32_t* __restrict__ cid, float* __restrict__ zs)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npad) return;
+    if (p < n) {
+        const int i = perm[p];
+        pos[i] = p;
+        cid[p] = i;
+#pragma unroll
+        for (int c = 0; c < PR_DIMS; ++c) zs[static_cast<size_t>(p) * PR_DIMS + c] = z[static_cast<size_t>(i) * PR_DIMS + c];
+    } else {
+        cid[p] = -1;
+    }
+}
+
+// Boxes of groups of `span` consecutive rows (rows beyond `rows` ignored): over
+// projected rows (boxes = 0) or over boxes (boxes = 1). Layout [group][2][PR].
+__global__ __launch_bounds__(256) void k_zboxes(const float* __restrict__ src, int rows, int span, int groups,
+                                                int boxes, float* __restrict__ out)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= groups * PR_DIMS) return;
+    const int g = t / PR_DIMS, c = t % PR_DIMS;
+    const int r0 = g * span, r1 = min(rows, r0 + span);
+    float lo = __uint_as_float(0x7F800000u), hi = -__uint_as_float(0x7F800000u);
+    for (int r = r0; r < r1; ++r) {
+        if (boxes) {
+            lo = fminf(lo, src[static_cast<size_t>(r) * 2 * PR_DIMS + c]);
+            hi = fmaxf(hi, src[static_cast<size_t>(r) * 2 * PR_DIMS + PR_DIMS + c]);
+        } else {
+            const float v = src[static_cast<size_t>(r) * PR_DIMS + c];
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+    }
+    out[static_cast<size_t>(g) * 2 * PR_DIMS + c] = lo;
+    out[static_cast<size_t>(g) * 2 * PR_DIMS + PR_DIMS + c] = hi;
+}
+
+// ------------------------------------------------------------------ launchers
+int cov_partials() { return 32; }
+int cov_chunks(int m) { return (m * (m + 1) / 2 + COV_ENTRIES - 1) / COV_ENTRIES; }
+int project_blocks(int n) { return (n + 255) / 256; }
+
+hipError_t launch_principal_basis(const float* X, int n, int m, const double* mu, double* part, double* C, float* P,
+                                  hipStream_t st)
+{
+    if (m < 1 || m > 256) return hipErrorInvalidValue;
+    const int stride = n > COV_SAMPLE ? n / COV_SAMPLE : 1;
+    const int nsample = (n + stride - 1) / stride;
+    const int nb = cov_partials();
+    const int rpb = (nsample + nb - 1) / nb;
+    hipLaunchKernelGGL(k_cov_partial, dim3(nb, cov_chunks(m)), dim3(256), 0, st, X, n, m, mu, stride, rpb, part);
+    const int ntri = m * (m + 1) / 2;
+    hipLaunchKernelGGL(k_cov_reduce, dim3((ntri + 255) / 256), dim3(256), 0, st, part, nb, m, C);
+    hipLaunchKernelGGL(k_subspace, dim3(1), dim3(256), 0, st, C, m, 20, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, const float* P, float* z, float* zpart,
+                              uint32_t* code, uint32_t* scode, int32_t* vals, int32_t* perm, void* sort_tmp,
+                              size_t sort_bytes, int32_t* pos, int32_t* cid, float* zs, float* tbox, float* sbox,
+                              hipStream_t st)
+{
+    const int nb = project_blocks(n);
+    hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, st, X, n, m, mu, P, z, zpart);
+    hipLaunchKernelGGL(k_zcodes, dim3(nb), dim3(256), 0, st, z, n, zpart, nb, code, vals);
+    size_t tb = sort_bytes;
+    hipError_t e = rocprim::radix_sort_pairs(sort_tmp, tb, code, scode, vals, perm, static_cast<size_t>(n), 0u,
+                                             8u * PCODE_DIMS, st);
+    if (e != hipSuccess) return e;
+    const int ntiles = (n + 31) / 32, npad = ntiles * 32;
+    hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, perm, n, npad, z, pos, cid, zs);
+    const int nsb = (ntiles + SB_TILES_MFMA - 1) / SB_TILES_MFMA;
+    hipLaunchKernelGGL(k_zboxes, dim3((ntiles * PR_DIMS + 255) / 256), dim3(256), 0, st, zs, n, 32, ntiles, 0, tbox);
+    hipLaunchKernelGGL(k_zboxes, dim3((nsb * PR_DIMS + 255) / 256), dim3(256), 0, st, tbox, ntiles, SB_TILES_MFMA, nsb,
+                       1, sbox);
+    return hipGetLastError();
+}
+
+size_t curve_sort_bytes(int n)
+{
+    size_t b = 0;
+    (void)rocprim::radix_sort_pairs(nullptr, b, static_cast<const uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr),
+                                    static_cast<const int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
+                                    static_cast<size_t>(n), 0u, 8u * PCODE_DIMS, nullptr);
+    return b;
+}
+
+}  // namespace kvb

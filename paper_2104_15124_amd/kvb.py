@@ -27,7 +27,7 @@ KNN_F32, KNN_BF16, KNN_LEARNED = 0, 1, 2
 BW_ADHOC, BW_DENSITY = 0, 1
 OUT_MARKOV, OUT_GENERATOR, OUT_SYMMETRIC = 0, 1, 2
 ROW_RECHECK, ROW_FALLBACK, ROW_UNCERTIFIED = 1, 2, 4
-OPT_FORCE_FALLBACK, OPT_SCRATCH_LIMIT, OPT_BF16_SPLIT, OPT_N_PROBE = 1, 2, 3, 4
+OPT_FORCE_FALLBACK, OPT_SCRATCH_LIMIT, OPT_BF16_SPLIT, OPT_N_PROBE, OPT_CURVE_ORDER = 1, 2, 3, 4, 5
 MODES = {"f32": KNN_F32, "bf16": KNN_BF16, "learned": KNN_LEARNED}
 
 EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb_knn",

@@ -223,8 +223,11 @@ def test_knn_nonlinear5_n1m_sampled_rows(gpu_lib):
     ctx = kvb.Context()
     gi, gd, fl = run_knn(gpu_lib, X, w.k, w.margin, mode="bf16", ctx=ctx)
     nfb = kvb.knn_fallback_rows(ctx)
+    pairs = kvb.knn_pairs(ctx)
     ctx.close()
-    say(f"[knn-mfma] {w.name}: fallback rows {nfb}")
+    say(f"[knn-mfma] {w.name}: fallback rows {nfb}, candidate pairs {pairs:.4g} of {float(w.n) ** 2:.4g}")
+    # five intrinsic dimensions: the curve-ordered scan skips tiles
+    assert pairs < 0.5 * float(w.n) ** 2
     assert (gi[:, 0] == np.arange(w.n)).all()
     assert (np.diff(gd, axis=1) >= 0).all()
     rows = np.random.default_rng(7).choice(w.n, 256, replace=False)
@@ -251,3 +254,60 @@ def test_knn_exact_rows(gpu_lib, name, n, m, k, seed):
     bi, bd = gpu_lib.knn_exact_rows(torch.from_numpy(X).cuda(), k, bad)
     bi = bi.cpu().numpy()
     assert bi[0, 0] == 0 and (bi[1] == -1).all() and (bi[2] == -1).all()
+
+
+# ------------------------------------------------ curve order and box pruning
+CURVE_CASES = [
+    # (name, kind, n, m, k, margin, mode, split, seed)
+    ("nl5_m64_bf16", "nonlinear5", 20000, 64, 64, 32, "bf16", 3, 41),
+    ("s3_m128_f32", "sphere3", 12000, 128, 32, 16, "f32", 3, 42),
+    ("gmm_m16_bf16x6", "gmm", 15001, 16, 64, 32, "bf16", 6, 43),
+    ("gauss_m24_f32", "gauss", 5000, 24, 16, 8, "f32", 3, 44),
+    ("s3_m8_bf16", "sphere3", 9000, 8, 48, 16, "bf16", 3, 45),
+]
+
+
+@pytest.mark.parametrize("name,kind,n,m,k,margin,mode,split,seed", CURVE_CASES, ids=[c[0] for c in CURVE_CASES])
+def test_knn_curve_order_matches_plain_scan(gpu_lib, name, kind, n, m, k, margin, mode, split, seed):
+    """The curve-ordered scan with projected-box pruning returns the same exact
+    neighbour lists as the scan of every tile; on samples of low intrinsic
+    dimension it evaluates fewer candidate pairs."""
+    from paper_2104_15124_amd import kvb
+    say(f"[knn-curve] {name}: n={n} m={m} k={k} margin={margin} mode={mode} split={split}")
+    X = _gen(kind, n, m, seed)
+    out = {}
+    for curve in (1, 0):
+        ctx = kvb.Context()
+        ctx.set_option(kvb.OPT_BF16_SPLIT, split)
+        ctx.set_option(kvb.OPT_CURVE_ORDER, curve)
+        gi, gd, fl = run_knn(gpu_lib, X, k, margin, mode=mode, ctx=ctx)
+        out[curve] = (gi, gd, kvb.knn_pairs(ctx), kvb.knn_fallback_rows(ctx))
+        ctx.close()
+    (ci, cd, cpairs, cfb), (pi, pd, ppairs, pfb) = out[1], out[0]
+    say(f"[knn-curve] {name}: pairs curve {cpairs:.4g} plain {ppairs:.4g}, fallback rows {cfb} / {pfb}")
+    np.testing.assert_array_equal(cd, pd)
+    # indices may differ only among neighbours at exactly equal distances
+    for r in np.nonzero((ci != pi).any(axis=1))[0]:
+        for p in np.nonzero(ci[r] != pi[r])[0]:
+            assert (cd[r] == cd[r][p]).sum() > 1 or cd[r][p] == cd[r][-1], f"row {r} position {p}"
+    rows = np.random.default_rng(seed).choice(n, 200, replace=False)
+    ri, rd = knn_reference(X, k, rows=rows)
+    check_knn_rows(ci[rows], cd[rows], ri, rd, k, rows)
+    assert ppairs == float(n) * n
+    assert cpairs <= ppairs
+
+
+def test_knn_curve_rank_deficient_and_small(gpu_lib):
+    """Covariance of rank below the projection dimension (zero basis columns),
+    a single tile, and n not a multiple of the tile height."""
+    from paper_2104_15124_amd import kvb
+    say("[knn-curve] rank-deficient and small cases")
+    rng = np.random.default_rng(5)
+    for n, m, k, r in ((31, 12, 7, 2), (97, 40, 20, 1), (2500, 32, 32, 3), (777, 10, 64, 10)):
+        B = rng.standard_normal((r, m)).astype(np.float32)
+        X = np.ascontiguousarray((rng.standard_normal((n, r)).astype(np.float32) @ B).astype(np.float32))
+        for mode in ("f32", "bf16"):
+            say(f"[knn-curve] n={n} m={m} k={k} rank={r} mode={mode}")
+            gi, gd, fl = run_knn(gpu_lib, X, k, 8, mode=mode)
+            ri, rd = knn_reference(X, k)
+            check_knn_rows(gi, gd, ri, rd, k, np.arange(n))
