@@ -149,7 +149,8 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
     const int colblocks = std::max(1, std::min(1024, (nn + 4095) / 4096));
     const size_t esz = split == 0 ? sizeof(float) : sizeof(uint16_t);
     size_t need = round256(size_t(nn) * (direct ? kp : cap) * sizeof(uint64_t)) +
-                  round256(size_t(nn) * sizeof(float)) + round256(size_t(nn) * sizeof(int)) + 2048;
+                  round256(size_t(nn) * sizeof(float)) + round256(size_t(nn) * sizeof(int)) + fallback_bytes(nn) +
+                  2048;
     size_t sort_bytes = 0;
     if (direct)
         KVB_HIP(ctx, kvb::sort_pairs_u32(nullptr, sort_bytes, nullptr, nullptr, nullptr, nullptr, nn, 32, ctx->stream));
@@ -185,6 +186,8 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
     uint64_t* keys = cv.take<uint64_t>(size_t(nn) * (direct ? kp : cap));
     float* slast = cv.take<float>(nn);
     int* fb_list = cv.take<int>(nn);
+    float* fb_bound = nullptr;
+    const kvb::FallbackWork fw = take_fallback(cv, nn, &fb_bound);
 
     KVB_HIP(ctx, hipMemsetAsync(ctx->fb_count_dev, 0, sizeof(int), ctx->stream));
     KVB_HIP(ctx, hipMemsetAsync(ctx->pairs_dev, 0, sizeof(unsigned long long), ctx->stream));
@@ -288,12 +291,12 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
     {
         Prof pr(ctx, KVB_PROF_KNN_REFINE);
         KVB_HIP(ctx, kvb::launch_refine(X, nn, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, row_flags,
-                                        ctx->fb_count_dev, fb_list, static_cast<int>(ctx->force_fallback),
+                                        ctx->fb_count_dev, fb_list, fb_bound, static_cast<int>(ctx->force_fallback),
                                         ctx->stream));
     }
     {
         Prof pr(ctx, KVB_PROF_KNN_FALLBACK);
-        KVB_HIP(ctx, kvb::launch_fallback(X, nn, m, k, ctx->fb_count_dev, fb_list, idx, d2, ctx->stream));
+        KVB_HIP(ctx, kvb::launch_fallback(X, nn, m, k, ctx->fb_count_dev, fb_list, fw, idx, d2, ctx->stream));
     }
     return KVB_OK;
 }

@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
                                                 int32_t* __restrict__ idx_out, float* __restrict__ d2_out,
                                                 int32_t* __restrict__ flags_out,
                                                 int* __restrict__ fb_count, int* __restrict__ fb_list,
-                                                int force_period)
+                                                float* __restrict__ fb_bound, int force_period)
 {
     const int lane = lane_id();
     const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -563,6 +563,7 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
     }
     int flags = 0;
     bool certified = true;
+    float bound = __uint_as_float(0x7F800000u);   // upper bound on the true (k-1)-th distance
     if (kk > 0) {
         // relative error bound of the compensated distances (a few units in
         // the last place), doubled for the band test
@@ -620,6 +621,7 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
         }
         // write the k-1 neighbours and find the largest kept distance
         float kept_max = 0.f;
+        int nkept = 0;
         const int need = kk - c_lo;
 #pragma unroll
         for (int s = 0; s < E; ++s) {
@@ -647,8 +649,11 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
                 drow[1 + pos] = outd;
                 kept_max = fmaxf(kept_max, dv);
             }
+            nkept += __popcll(__ballot(pos >= 0));
         }
         kept_max = wave_max_f32(kept_max);
+        // the kept candidates are k-1 samples within this distance of row i
+        if (nkept == kk) bound = kept_max * (1.f + dl) * (1.f + 1e-6f);
         if (slast) {
             // certificate: every candidate the select step dropped has a true
             // squared distance >= slast * lb_scale; it must exceed the largest kept
@@ -668,17 +673,117 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
         if (lane == 0) {
             const int slot = atomicAdd(fb_count, 1);
             fb_list[slot] = i;
+            fb_bound[slot] = bound;
         }
     }
     if (flags_out && lane == 0) flags_out[i] = flags;
 }
 
 // -------------------------------------------------------------------- fallback
-// Exact float64 selection for the listed rows: an 8-pass radix select on the
-// bits of the float64 squared distance (non-negative doubles order like their
-// bit patterns) finds the (k-1)-th smallest value V; the neighbours are all j
-// with d < V plus the smallest-index j with d == V, ranked by (d, j).
+// Exact float64 selection for the listed rows, ranked by (d, j).
+//
+// Bounded pass (rows with a finite bound B >= their true (k-1)-th distance,
+// the first FB_MAX_ROWS listed): every block takes chunks of FB_CHUNK samples
+// and, row after row (the chunk stays in cache), appends the samples j != i
+// with d(i, j) <= B to the row's buffer of FB_CAP entries. All of the row's
+// k-1 nearest are among them, so when the buffer holds between k-1 and FB_CAP
+// entries the row is finished by ranking the buffer.
+//
+// Full scan (every other row): an 8-pass radix select on the bits of the
+// float64 squared distance (non-negative doubles order like their bit
+// patterns) finds the (k-1)-th smallest value V; the neighbours are all j with
+// d < V plus the smallest-index j with d == V.
+//
+// Both compute d in the order of dist2_f64, so they agree on every value and tie.
 constexpr int FB_THREADS = 256;
+constexpr int FB_CHUNK = 1024;
+
+// m <= FB_LDS_M: blocks stage FB_STAGE consecutive samples in LDS (coalesced,
+// row stride m + 1 against bank conflicts) and every wavefront takes listed
+// rows in turn, one staged sample per lane; the summation order is that of
+// dist2_f64.
+constexpr int FB_STAGE = 64;
+constexpr int FB_LDS_M = 256;
+
+__global__ __launch_bounds__(FB_THREADS) void k_fb_collect_lds(const float* __restrict__ X, int n, int m,
+                                                               const int* __restrict__ fb_count,
+                                                               const int* __restrict__ fb_list,
+                                                               const float* __restrict__ fb_bound, int rows_cap,
+                                                               int* __restrict__ cnt, double* __restrict__ bd,
+                                                               int* __restrict__ bj)
+{
+    __shared__ float xc[FB_STAGE * (FB_LDS_M + 1)];
+    const int total = min(*fb_count, rows_cap);
+    if (total == 0) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x / WAVE;
+    const int ld = m + 1;
+    for (int c0 = blockIdx.x * FB_STAGE; c0 < n; c0 += gridDim.x * FB_STAGE) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < FB_STAGE * m; e += FB_THREADS) {
+            const int r = e / m, c = e - r * m;
+            xc[r * ld + c] = c0 + r < n ? X[static_cast<size_t>(c0) * m + e] : 0.f;
+        }
+        __syncthreads();
+        const int j = c0 + lane;
+        const float* xj = xc + lane * ld;
+        for (int t = wave; t < total; t += FB_THREADS / WAVE) {
+            const float B = fb_bound[t];
+            if (!(B < __uint_as_float(0x7F800000u))) continue;
+            const int i = fb_list[t];
+            if (j >= n || j == i) continue;
+            const float* xi = X + static_cast<size_t>(i) * m;
+            double d = 0.0;
+            for (int c = 0; c < m; ++c) {
+                const double u = static_cast<double>(xi[c]) - static_cast<double>(xj[c]);
+                d = fma(u, u, d);
+            }
+            if (d <= static_cast<double>(B)) {
+                const int slot = atomicAdd(&cnt[t], 1);
+                if (slot < FB_CAP) {
+                    bd[static_cast<size_t>(t) * FB_CAP + slot] = d;
+                    bj[static_cast<size_t>(t) * FB_CAP + slot] = j;
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(FB_THREADS) void k_fb_collect(const float* __restrict__ X, int n, int m,
+                                                           const int* __restrict__ fb_count,
+                                                           const int* __restrict__ fb_list,
+                                                           const float* __restrict__ fb_bound, int rows_cap,
+                                                           int* __restrict__ cnt, double* __restrict__ bd,
+                                                           int* __restrict__ bj)
+{
+    __shared__ float xs[1024];
+    const int total = min(*fb_count, rows_cap);
+    for (int c0 = blockIdx.x * FB_CHUNK; c0 < n && total > 0; c0 += gridDim.x * FB_CHUNK) {
+        for (int t = 0; t < total; ++t) {
+            const float B = fb_bound[t];
+            if (!(B < __uint_as_float(0x7F800000u))) continue;
+            const int i = fb_list[t];
+            __syncthreads();
+            for (int c = threadIdx.x; c < m; c += FB_THREADS) xs[c] = X[static_cast<size_t>(i) * m + c];
+            __syncthreads();
+            const double Bd = static_cast<double>(B);
+#pragma unroll
+            for (int u = 0; u < FB_CHUNK / FB_THREADS; ++u) {
+                const int j = c0 + u * FB_THREADS + threadIdx.x;
+                if (j < n && j != i) {
+                    const double d = dist2_f64(xs, X + static_cast<size_t>(j) * m, m);
+                    if (d <= Bd) {
+                        const int slot = atomicAdd(&cnt[t], 1);
+                        if (slot < FB_CAP) {
+                            bd[static_cast<size_t>(t) * FB_CAP + slot] = d;
+                            bj[static_cast<size_t>(t) * FB_CAP + slot] = j;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
 
 // The row count is *fb_count, or `count` when fb_count is null. Results go to
 // row i of idx_out / d2_out, or with `compact` to row t (the list position);
@@ -686,9 +791,13 @@ constexpr int FB_THREADS = 256;
 __global__ __launch_bounds__(FB_THREADS) void k_fallback(const float* __restrict__ X, int n, int m, int k,
                                                          const int* __restrict__ fb_count, int count,
                                                          const int* __restrict__ fb_list, int compact,
+                                                         int rows_cap, const int* __restrict__ cnt,
+                                                         const double* __restrict__ bd, const int* __restrict__ bj,
                                                          int32_t* __restrict__ idx_out,
                                                          float* __restrict__ d2_out)
 {
+    __shared__ double s_bd[FB_CAP];
+    __shared__ int s_bj[FB_CAP];
     __shared__ unsigned int hist[256];
     __shared__ unsigned long long s_prefix;
     __shared__ int s_remaining;
@@ -716,6 +825,31 @@ __global__ __launch_bounds__(FB_THREADS) void k_fallback(const float* __restrict
                 idx_out[orow * k] = i;
                 d2_out[orow * k] = 0.f;
             }
+            continue;
+        }
+        const int c = (cnt && t < rows_cap) ? cnt[t] : -1;
+        if (c >= kk && c <= FB_CAP) {
+            // bounded pass: rank the buffer by (d, j)
+            for (int e = tid; e < c; e += FB_THREADS) {
+                s_bd[e] = bd[static_cast<size_t>(t) * FB_CAP + e];
+                s_bj[e] = bj[static_cast<size_t>(t) * FB_CAP + e];
+            }
+            __syncthreads();
+            for (int e = tid; e < c; e += FB_THREADS) {
+                const double d = s_bd[e];
+                const int j = s_bj[e];
+                int rank = 0;
+                for (int u = 0; u < c; ++u) rank += (s_bd[u] < d) || (s_bd[u] == d && s_bj[u] < j);
+                if (rank < kk) {
+                    idx_out[orow * k + 1 + rank] = j;
+                    d2_out[orow * k + 1 + rank] = static_cast<float>(d);
+                }
+            }
+            if (tid == 0) {
+                idx_out[orow * k] = i;
+                d2_out[orow * k] = 0.f;
+            }
+            __syncthreads();
             continue;
         }
         if (tid == 0) {
@@ -882,48 +1016,63 @@ hipError_t launch_select_direct(const float* Xs, const int32_t* perm, const floa
 template <int LPC>
 static void launch_refine_l(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,
                             const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags, int* fb_count,
-                            int* fb_list, int force_period, hipStream_t st)
+                            int* fb_list, float* fb_bound, int force_period, hipStream_t st)
 {
     const dim3 grid((n + 3) / 4), block(256);
     if (kp <= 64)
         hipLaunchKernelGGL((k_refine<1, LPC>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
-                           d2, flags, fb_count, fb_list, force_period);
+                           d2, flags, fb_count, fb_list, fb_bound, force_period);
     else if (kp <= 128)
         hipLaunchKernelGGL((k_refine<2, LPC>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
-                           d2, flags, fb_count, fb_list, force_period);
+                           d2, flags, fb_count, fb_list, fb_bound, force_period);
     else
         hipLaunchKernelGGL((k_refine<4, LPC>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
-                           d2, flags, fb_count, fb_list, force_period);
+                           d2, flags, fb_count, fb_list, fb_bound, force_period);
 }
 
 hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,
                          const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags,
-                         int* fb_count, int* fb_list, int force_period, hipStream_t st)
+                         int* fb_count, int* fb_list, float* fb_bound, int force_period, hipStream_t st)
 {
     // rows of up to 24 floats stay with one lane per candidate; longer rows are
     // read by groups of lanes (each lane covers at most 4 float4 pieces)
     if (m <= 24)
         launch_refine_l<0>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                           force_period, st);
+                           fb_bound, force_period, st);
     else if (m <= 64)
         launch_refine_l<16>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                            force_period, st);
+                            fb_bound, force_period, st);
     else if (m <= 128)
         launch_refine_l<32>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                            force_period, st);
+                            fb_bound, force_period, st);
     else if (m <= 1024)
         launch_refine_l<64>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                            force_period, st);
+                            fb_bound, force_period, st);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
+int fallback_rows_cap(int n) { return n < FB_MAX_ROWS ? n : FB_MAX_ROWS; }
+
 hipError_t launch_fallback(const float* X, int n, int m, int k, const int* fb_count, const int* fb_list,
-                           int32_t* idx, float* d2, hipStream_t st)
+                           const FallbackWork& fw, int32_t* idx, float* d2, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fallback, dim3(512), dim3(FB_THREADS), 0, st, X, n, m, k, fb_count, 0, fb_list, 0, idx,
-                       d2);
+    if (m > 1024) return hipErrorInvalidValue;
+    const int cap = fallback_rows_cap(n);
+    hipError_t e = hipMemsetAsync(fw.cnt, 0, static_cast<size_t>(cap) * sizeof(int), st);
+    if (e != hipSuccess) return e;
+    if (m <= FB_LDS_M) {
+        const int stages = (n + FB_STAGE - 1) / FB_STAGE;
+        hipLaunchKernelGGL(k_fb_collect_lds, dim3(stages < 2048 ? stages : 2048), dim3(FB_THREADS), 0, st, X, n, m,
+                           fb_count, fb_list, fw.bound, cap, fw.cnt, fw.bd, fw.bj);
+    } else {
+        const int chunks = (n + FB_CHUNK - 1) / FB_CHUNK;
+        hipLaunchKernelGGL(k_fb_collect, dim3(chunks < 2048 ? chunks : 2048), dim3(FB_THREADS), 0, st, X, n, m,
+                           fb_count, fb_list, fw.bound, cap, fw.cnt, fw.bd, fw.bj);
+    }
+    hipLaunchKernelGGL(k_fallback, dim3(512), dim3(FB_THREADS), 0, st, X, n, m, k, fb_count, 0, fb_list, 0, cap,
+                       fw.cnt, fw.bd, fw.bj, idx, d2);
     return hipGetLastError();
 }
 
@@ -932,8 +1081,8 @@ hipError_t launch_exact_rows(const float* X, int n, int m, int k, const int* row
 {
     if (nrows <= 0) return hipSuccess;
     const int grid = nrows < 1024 ? nrows : 1024;
-    hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(FB_THREADS), 0, st, X, n, m, k, nullptr, nrows, rows, 1, idx,
-                       d2);
+    hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(FB_THREADS), 0, st, X, n, m, k, nullptr, nrows, rows, 1, 0,
+                       nullptr, nullptr, nullptr, idx, d2);
     return hipGetLastError();
 }
 

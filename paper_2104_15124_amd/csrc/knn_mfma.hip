@@ -234,8 +234,8 @@ struct BoxBound {
     float zerr, pscale, yerr;
 };
 
-__device__ __forceinline__ float box_bound(const float* __restrict__ b, const float (&qlo)[PR_DIMS],
-                                           const float (&qhi)[PR_DIMS], const BoxBound& bb)
+__device__ __forceinline__ float box_bound(const float* __restrict__ b, const float* __restrict__ qlo,
+                                           const float* __restrict__ qhi, const BoxBound& bb)
 {
     float g2 = 0.f;
 #pragma unroll
@@ -248,36 +248,86 @@ __device__ __forceinline__ float box_bound(const float* __restrict__ b, const fl
     return d > 0.f ? d * d * (1.f - 2e-6f) : 0.f;
 }
 
-// Next tile of a curve-order scan (own tile, then alternately right and
-// left), skipping tiles and entered superblocks whose bound exceeds thr; -1
-// when the scan is done. The same in every wavefront of the workgroup.
-__device__ __forceinline__ int curve_next(int& cur_r, int& cur_l, bool& go_right, int own_t, int tend, float thr,
-                                          const float (&qlo)[PR_DIMS], const float (&qhi)[PR_DIMS],
-                                          const CurveArgs& crv, const BoxBound& bb)
-{
-    while (cur_r < tend || cur_l >= 0) {
-        int t;
-        if ((go_right && cur_r < tend) || cur_l < 0) {
-            t = cur_r++;
-            go_right = false;
-            if (t % SB_TILES_MFMA == 0 && t != own_t &&
-                box_bound(crv.sbox + static_cast<size_t>(t / SB_TILES_MFMA) * 2 * PR_DIMS, qlo, qhi, bb) > thr) {
-                cur_r = t + SB_TILES_MFMA;
-                continue;
+// Curve-order scan (own tile, then alternately right and left) over windows
+// of 64 tiles: one load per window gives every lane the bounds of its tile to
+// the workgroup's box (bw) and to its wavefront's box (ww), so picking the
+// next tile is a ballot against the current threshold with no memory access.
+// The scan state is the same in every wavefront of the workgroup.
+struct CurveScan {
+    int cur_r, cur_l;   // next candidate tile on each side
+    int rbase, lbase;   // window origins: lane l is tile rbase + l / lbase - l
+    bool go_right;
+    float rbw, rww, lbw, lww;
+
+    __device__ __forceinline__ void window(int base, int dir, int own_t, int tend, const CurveArgs& crv,
+                                           const float* qlo, const float* qhi, const float* wlo, const float* whi,
+                                           const BoxBound& bb, float& bw, float& ww)
+    {
+        const int t = base + dir * lane_id();
+        bw = __uint_as_float(0x7F800000u);
+        ww = bw;
+        if (t == own_t) {
+            bw = -bw;
+            ww = -ww;
+        } else if (t >= 0 && t < tend) {
+            float b[2 * PR_DIMS];
+            const float4* src = reinterpret_cast<const float4*>(crv.tbox + static_cast<size_t>(t) * 2 * PR_DIMS);
+#pragma unroll
+            for (int v = 0; v < PR_DIMS / 2; ++v) {
+                const float4 q = src[v];
+                b[4 * v] = q.x;
+                b[4 * v + 1] = q.y;
+                b[4 * v + 2] = q.z;
+                b[4 * v + 3] = q.w;
             }
-        } else {
-            t = cur_l--;
-            go_right = true;
-            if (t % SB_TILES_MFMA == SB_TILES_MFMA - 1 &&
-                box_bound(crv.sbox + static_cast<size_t>(t / SB_TILES_MFMA) * 2 * PR_DIMS, qlo, qhi, bb) > thr) {
-                cur_l = t - SB_TILES_MFMA;
-                continue;
+            bw = box_bound(b, qlo, qhi, bb);
+            ww = box_bound(b, wlo, whi, bb);
+        }
+    }
+
+    // next tile whose workgroup bound is <= thr, or -1; wb: its wavefront bound
+    __device__ __forceinline__ int next(float thr, int own_t, int tend, const CurveArgs& crv, const float* qlo,
+                                        const float* qhi, const float* wlo, const float* whi, const BoxBound& bb,
+                                        float& wb)
+    {
+        while (cur_r < tend || cur_l >= 0) {
+            if ((go_right && cur_r < tend) || cur_l < 0) {
+                go_right = false;
+                while (cur_r < tend) {
+                    if (cur_r >= rbase + WAVE) {
+                        rbase = cur_r;
+                        window(rbase, 1, own_t, tend, crv, qlo, qhi, wlo, whi, bb, rbw, rww);
+                    }
+                    const uint64_t mask = __ballot(rbw <= thr) & (~0ull << (cur_r - rbase));
+                    if (mask) {
+                        const int l = __builtin_ctzll(mask);
+                        wb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rww), l));
+                        cur_r = rbase + l + 1;
+                        return rbase + l;
+                    }
+                    cur_r = rbase + WAVE;
+                }
+            } else {
+                go_right = true;
+                while (cur_l >= 0) {
+                    if (cur_l <= lbase - WAVE || cur_l > lbase) {
+                        lbase = cur_l;
+                        window(lbase, -1, own_t, tend, crv, qlo, qhi, wlo, whi, bb, lbw, lww);
+                    }
+                    const uint64_t mask = __ballot(lbw <= thr) & (~0ull << (lbase - cur_l));
+                    if (mask) {
+                        const int l = __builtin_ctzll(mask);
+                        wb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lww), l));
+                        cur_l = lbase - l - 1;
+                        return lbase - l;
+                    }
+                    cur_l = lbase - WAVE;
+                }
             }
         }
-        if (t == own_t || box_bound(crv.tbox + static_cast<size_t>(t) * 2 * PR_DIMS, qlo, qhi, bb) <= thr) return t;
+        return -1;
     }
-    return -1;
-}
+};
 
 // Sort query q's list in place (whole wavefront) and return its kp-th score.
 template <int E>
@@ -415,14 +465,19 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
 #pragma unroll
     for (int r = 0; r < 16; ++r) qrow[r] = s_qid[wave][acc_row(r, half)];
 
-    // MODE 2: the workgroup's query box in projected space, the squared norms
-    // of the queries (thresholds are kept as scores s = |y_j|^2 - 2 y_i.y_j, the
-    // distance threshold is s + |y_i|^2) and the scan cursor
-    __shared__ float s_qbox[WV][2][PR_DIMS];
+    // MODE 2: the query boxes in projected space (s_qbox[w]: wavefront w's,
+    // s_qbox[WV]: the workgroup's), the squared norms of the queries
+    // (thresholds are kept as scores s = |y_j|^2 - 2 y_i.y_j, the distance
+    // threshold is s + |y_i|^2) and the scan cursor
+    __shared__ float s_qbox[WV + 1][2][PR_DIMS];
     __shared__ float s_thr[2][WV];
-    float qlo[PR_DIMS], qhi[PR_DIMS], yq[16];
-    int cur_r = 0, cur_l = -1, own_t = 0;
-    bool go_right = true;
+    const float* qlo = &s_qbox[WV][0][0];
+    const float* qhi = &s_qbox[WV][1][0];
+    const float* wlo = &s_qbox[wave][0][0];
+    const float* whi = &s_qbox[wave][1][0];
+    float yq[16];
+    CurveScan scan = {0, -1, -2 * WAVE, 0, true, 0.f, 0.f, 0.f, 0.f};
+    int own_t = 0;
     BoxBound bb = {0.f, 1.f, 0.f};
     if constexpr (CURVE) {
 #pragma unroll
@@ -443,30 +498,33 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int c = 0; c < PR_DIMS; ++c) {
-            qlo[c] = s_qbox[0][0][c];
-            qhi[c] = s_qbox[0][1][c];
-#pragma unroll
+        if (threadIdx.x < PR_DIMS) {
+            const int c = threadIdx.x;
+            float lo = s_qbox[0][0][c], hi = s_qbox[0][1][c];
             for (int w = 1; w < WV; ++w) {
-                qlo[c] = fminf(qlo[c], s_qbox[w][0][c]);
-                qhi[c] = fmaxf(qhi[c], s_qbox[w][1][c]);
+                lo = fminf(lo, s_qbox[w][0][c]);
+                hi = fmaxf(hi, s_qbox[w][1][c]);
             }
+            s_qbox[WV][0][c] = lo;
+            s_qbox[WV][1][c] = hi;
         }
+        __syncthreads();
         own_t = min(tend - 1, (blockIdx.x * WV * NQ + WV * NQ / 2) / 32);
         const float R = __uint_as_float(*rmax_bits);
         bb.zerr = crv.zcoef * R;
         bb.pscale = *crv.pscale;
         bb.yerr = crv.ycoef * R;
-        cur_r = own_t;
-        cur_l = own_t - 1;
+        scan.cur_r = own_t;
+        scan.cur_l = own_t - 1;
+        scan.lbase = -2 * WAVE;
     }
     __builtin_amdgcn_s_waitcnt(0);
     u32x4 pf[PF];
     int cid_pf = -1;
     int tile = -1;
+    float wb_pf = 0.f;   // MODE 2: bound of the prefetched tile to this wavefront's box
     if (tbeg < tend)
-        tile = CURVE ? curve_next(cur_r, cur_l, go_right, own_t, tend, __uint_as_float(0x7F800000u), qlo, qhi, crv, bb)
+        tile = CURVE ? scan.next(__uint_as_float(0x7F800000u), own_t, tend, crv, qlo, qhi, wlo, whi, bb, wb_pf)
                      : tbeg;
     if (tile >= 0) {
         const u32x4* g = reinterpret_cast<const u32x4*>(Bc + static_cast<size_t>(tile) * 32 * kpad);
@@ -484,6 +542,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
     const int fill_tiles = (kp + 31) / 32;
     for (int it = 0; tile >= 0; ++it) {
         const int stage = it & 1;
+        float wthr = 0.f;
         if constexpr (CURVE) {
             // this wavefront's largest distance threshold, an upper bound of
             // s + |y_i|^2 over its queries
@@ -491,8 +550,8 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 if (qrow[r] >= 0) t = fmaxf(t, fmaxf(tauv[r] + yq[r], 0.f) * (1.f + 4.8e-7f));
-            t = wave_max_f32(t);
-            if (lane == 0) s_thr[stage][wave] = t;
+            wthr = wave_max_f32(t);
+            if (lane == 0) s_thr[stage][wave] = wthr;
         }
         {
             u32x4* d = reinterpret_cast<u32x4*>(&s_tile[stage][0][0][0]);
@@ -503,6 +562,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
             }
         }
         const int cid_cur = cid_pf;
+        const float wb_cur = wb_pf;
         __syncthreads();                 // stage visible; the other stage's readers finished a tile ago
         float thr = __uint_as_float(0x7F800000u);
         if constexpr (CURVE) {
@@ -512,7 +572,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
         }
         int next;
         if constexpr (CURVE)
-            next = curve_next(cur_r, cur_l, go_right, own_t, tend, thr, qlo, qhi, crv, bb);
+            next = scan.next(thr, own_t, tend, crv, qlo, qhi, wlo, whi, bb, wb_pf);
         else
             next = tile + 1 < tend ? tile + 1 : -1;
         if (next >= 0) {
@@ -524,6 +584,14 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
             }
             if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(next) * 32 + (lane & 31)];
             if constexpr (CURVE) cid_pf = crv.perm[static_cast<size_t>(next) * 32 + (lane & 31)];
+        }
+        // MODE 2, after the fill: a tile the workgroup scans may still lie
+        // beyond this wavefront's own box and thresholds
+        if constexpr (CURVE) {
+            if (!filling && wb_cur > wthr) {
+                tile = next;
+                continue;
+            }
         }
         // all fragment reads are issued before the products (up to 16 at a
         // time), and even / odd K-steps go to two accumulators, so the chain of

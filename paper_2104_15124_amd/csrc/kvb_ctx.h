@@ -132,6 +132,26 @@ struct Carve {
 
 inline size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// scratch of the exact fallback: per-row bounds and the bounded pass buffers
+inline size_t fallback_bytes(int n)
+{
+    const size_t cap = static_cast<size_t>(kvb::fallback_rows_cap(n));
+    return round256(size_t(n) * sizeof(float)) + round256(cap * sizeof(int)) +
+           round256(cap * kvb::FB_CAP * sizeof(double)) + round256(cap * kvb::FB_CAP * sizeof(int)) + 1024;
+}
+
+inline kvb::FallbackWork take_fallback(Carve& cv, int n, float** bound)
+{
+    const size_t cap = static_cast<size_t>(kvb::fallback_rows_cap(n));
+    kvb::FallbackWork fw;
+    *bound = cv.take<float>(n);
+    fw.bound = *bound;
+    fw.cnt = cv.take<int>(cap);
+    fw.bd = cv.take<double>(cap * kvb::FB_CAP);
+    fw.bj = cv.take<int>(cap * kvb::FB_CAP);
+    return fw;
+}
+
 inline int ensure_scratch(kvb_ctx ctx, size_t bytes)
 {
     if (bytes <= ctx->scratch_bytes) return KVB_OK;

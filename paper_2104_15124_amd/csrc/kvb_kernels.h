@@ -66,9 +66,21 @@ hipError_t launch_select_direct(const float* Xs, const int32_t* perm, const floa
                                 int m, int kp, uint64_t* keys, float* slast, unsigned long long* pairs, hipStream_t st);
 hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,
                          const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags,
-                         int* fb_count, int* fb_list, int force_period, hipStream_t st);
+                         int* fb_count, int* fb_list, float* fb_bound, int force_period, hipStream_t st);
+
+// Buffers of the exact fallback's bounded pass (k_fb_collect): rows_cap =
+// fallback_rows_cap(n) listed rows with FB_CAP entries each.
+constexpr int FB_CAP = 1024;
+constexpr int FB_MAX_ROWS = 2048;
+struct FallbackWork {
+    const float* bound;  // [n] per listed row: bound on its true (k-1)-th distance (+inf: none)
+    int* cnt;            // [rows_cap]
+    double* bd;          // [rows_cap * FB_CAP] distances
+    int* bj;             // [rows_cap * FB_CAP] sample ids
+};
+int fallback_rows_cap(int n);
 hipError_t launch_fallback(const float* X, int n, int m, int k, const int* fb_count, const int* fb_list,
-                           int32_t* idx, float* d2, hipStream_t st);
+                           const FallbackWork& fw, int32_t* idx, float* d2, hipStream_t st);
 hipError_t launch_exact_rows(const float* X, int n, int m, int k, const int* rows, int nrows, int32_t* idx, float* d2,
                              hipStream_t st);
 

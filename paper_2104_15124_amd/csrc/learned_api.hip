@@ -307,11 +307,13 @@ int learned_knn(kvb_ctx ctx, const float* X, int n, int m, int k, int kp, int32_
                   round256(size_t(NB) * 4) + round256(size_t(NB + 1) * 4) + round256(size_t(max_tiles) * 32 * 4) +
                   round256(size_t(n) * 4) + round256(size_t(NP) * (NB + 1) * 4) +
                   round256(size_t(NP) * max_work * 8) + round256(size_t(NP) * 4) + round256(size_t(n) * NP * 4) +
-                  round256(tmp_bytes) + acts_bytes(P, CH, 0, false) + 4096;
+                  round256(tmp_bytes) + acts_bytes(P, CH, 0, false) + fallback_bytes(n) + 4096;
     KVB_TRY(ensure_scratch(ctx, need));
     Carve cv(ctx->scratch);
     uint64_t* lists = cv.take<uint64_t>(size_t(n) * cap);
     int* fb_list = cv.take<int>(n);
+    float* fb_bound = nullptr;
+    const kvb::FallbackWork fw = take_fallback(cv, n, &fb_bound);
     void* Aq = cv.take<char>(size_t(n) * kpad * esz);
     void* Bp = cv.take<char>(size_t(max_tiles) * 32 * kpad * esz);
     float* ynorm2 = cv.take<float>(n);
@@ -382,11 +384,12 @@ int learned_knn(kvb_ctx ctx, const float* X, int n, int m, int k, int kp, int32_
     {
         Prof pr(ctx, KVB_PROF_KNN_REFINE);
         KVB_HIP(ctx, kvb::launch_refine(X, n, m, k, kp, cap, lists, nullptr, 1.0f, idx, d2, row_flags,
-                                        ctx->fb_count_dev, fb_list, static_cast<int>(ctx->force_fallback), st));
+                                        ctx->fb_count_dev, fb_list, fb_bound, static_cast<int>(ctx->force_fallback),
+                                        st));
     }
     {
         Prof pr(ctx, KVB_PROF_KNN_FALLBACK);
-        KVB_HIP(ctx, kvb::launch_fallback(X, n, m, k, ctx->fb_count_dev, fb_list, idx, d2, st));
+        KVB_HIP(ctx, kvb::launch_fallback(X, n, m, k, ctx->fb_count_dev, fb_list, fw, idx, d2, st));
     }
     return KVB_OK;
 }

@@ -103,6 +103,26 @@ def test_knn_forced_fallback_matches(gpu_lib):
     ctx.close()
 
 
+@pytest.mark.parametrize("mode,m", [("f32", 3), ("bf16", 64), ("f32", 200)])
+def test_knn_forced_fallback_duplicates(gpu_lib, mode, m):
+    """Every row through the exact fallback: 1500 copies of one point (their
+    bounded-pass buffers overflow, so they take the full scan) among 700
+    distinct points (finished by the bounded pass); ties ranked by index."""
+    from paper_2104_15124_amd import kvb
+    say(f"[knn] forced fallback with 1500 duplicates, mode={mode} m={m}")
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal((2200, m)).astype(np.float32)
+    X[rng.permutation(2200)[:1500]] = X[0]
+    ctx = kvb.Context()
+    ctx.set_option(kvb.OPT_FORCE_FALLBACK, 1)
+    gi, gd, fl = run_knn(gpu_lib, X, 24, 16, mode=mode, ctx=ctx)
+    assert kvb.knn_fallback_rows(ctx) == 2200
+    ctx.close()
+    ri, rd = oracle.knn(X, 24)
+    np.testing.assert_array_equal(gi, ri)
+    np.testing.assert_array_equal(gd, rd.astype(np.float32))
+
+
 def test_knn_sphere_n2000_k32(gpu_lib):
     say("[knn] sphere2 n=2000 k=32 (full oracle)")
     X = workloads.make("sphere2_n2000", seed=0)
