@@ -248,6 +248,19 @@ __device__ __forceinline__ float box_bound(const float* __restrict__ b, const fl
     return d > 0.f ? d * d * (1.f - 2e-6f) : 0.f;
 }
 
+// Workgroups are dispatched to the 8 XCDs round robin (workgroup b to XCD
+// b mod 8). Renumbering them so that each XCD receives one contiguous range of
+// curve positions makes the workgroups resident on an XCD at one time
+// neighbours along the curve, whose scans read the same candidate tiles
+// through that XCD's L2.
+__device__ __forceinline__ int xcd_block()
+{
+    constexpr int XCDS = 8;
+    const int b = blockIdx.x, g = gridDim.x;
+    const int x = b % XCDS, per = g / XCDS, rem = g % XCDS;
+    return x * per + min(x, rem) + b / XCDS;
+}
+
 // Curve-order scan (own tile, then alternately right and left) over windows
 // of 64 tiles: one load per window gives every lane the bounds of its tile to
 // the workgroup's box (bw) and to its wavefront's box (ww), so picking the
@@ -415,7 +428,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
         tend = ba.tptr[wk.x + 1];
         if (lane < NQ) s_qid[wave][lane] = q0 + lane < qend ? ba.qids[q0 + lane] : -1;
     } else if constexpr (CURVE) {
-        q0 = (blockIdx.x * WV + wave) * NQ;
+        q0 = (xcd_block() * WV + wave) * NQ;
         tend = (n + 31) / 32;
         if (lane < NQ) s_qid[wave][lane] = q0 + lane < n ? crv.perm[q0 + lane] : -1;
     } else {
@@ -509,7 +522,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
             s_qbox[WV][1][c] = hi;
         }
         __syncthreads();
-        own_t = min(tend - 1, (blockIdx.x * WV * NQ + WV * NQ / 2) / 32);
+        own_t = min(tend - 1, (xcd_block() * WV * NQ + WV * NQ / 2) / 32);
         const float R = __uint_as_float(*rmax_bits);
         bb.zerr = crv.zcoef * R;
         bb.pscale = *crv.pscale;
