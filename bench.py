@@ -193,6 +193,34 @@ def main() -> int:
                     "work": f"{flops_per_pair} algorithmic flops per scored candidate pair (2m), {pairs:.4g} pairs "
                             + ("(routed query-candidate pairs, all probe passes)" if learned else "(n^2)")}
 
+    # the O(nk) passes against the HBM roofline: algorithmic bytes per launch
+    # (each stored entry: d2 4 B + idx 4 B + the gathered rho_j / q_j 4 B)
+    nnz = float(w.n) * w.k
+    kp = min(w.k + w.margin, w.n)
+    pass_bytes = {
+        "knn_refine": float(w.n) * kp * (w.m * 4 + 8) + nnz * 8,   # candidate rows + keys, idx/d2 out
+        "adhoc_bandwidth": float(w.n) * (w.k0 * 4 + 4),
+        "chi_tuning": nnz * 12 + float(w.n) * 4,
+        "density": nnz * 12 + float(w.n) * 12,
+        "q_pass": nnz * 12 + float(w.n) * 12,
+        "assemble": nnz * (16 + 8) + float(w.n) * 16,                 # entries in / CSR out, P and D
+    }
+    passes = {}
+    for name, byt in pass_bytes.items():
+        ms, cnt = prof.get(name, (0.0, 0))
+        if not cnt:
+            continue
+        sec = ms / cnt / 1e3
+        gbs = byt / sec / 1e9
+        passes[name] = {"avg_ms": round(sec * 1e3, 4), "bytes": int(byt), "GB/s": round(gbs, 1),
+                        "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if "chi_tuning" in passes:
+        # G exponentials per stored entry; v_exp_f32 issues at a quarter of the lane rate
+        exps = nnz * w.G / (passes["chi_tuning"]["avg_ms"] / 1e3)
+        passes["chi_tuning"]["exp_per_s"] = float(f"{exps:.4g}")
+        passes["chi_tuning"]["exp_frac"] = round(exps / (ALU_PEAK_TOPS * 1e12 / 4), 4)
+    log("  passes: " + ", ".join(f"{k} {v['GB/s']} GB/s ({100 * v['frac']:.1f}% HBM)" for k, v in passes.items()))
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -235,6 +263,7 @@ def main() -> int:
                    "curve_order": bool(args.curve_order) and w.mode != "learned" and not (w.mode == "f32" and w.m <= 8),
                    "alpha": w.alpha, "beta": w.beta, "fallback_rows": fb, "learned": learned},
         "roofline": roofline,
+        "passes": passes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -34,9 +34,10 @@ namespace kvb {
 // its own tile and the nearest tiles along the curve, which sets tight
 // thresholds, then tests every superblock box (64 per instruction, one per
 // lane) and, inside the superblocks within reach, every tile box (16 lanes),
-// and scores only the tiles whose box lies within the largest current
-// threshold of its rows. A skipped candidate is therefore at least as far as
-// a threshold that only decreases afterwards, which keeps the certificate of
+// and scores only the tiles whose box lies within some row's current
+// threshold of that row's point. A candidate skipped for a row is therefore at
+// least as far as that row's threshold, which only decreases afterwards; this
+// keeps the certificate of
 // the refine step valid: the box bound is computed in float32 with at most
 // (m + 2) roundings, inside the relative margin the refine step allows for
 // the selection scores.
@@ -55,19 +56,36 @@ struct SpatialView {
 constexpr int TILE = 64;
 constexpr int SB_TILES = 16;
 
-template <int M>
-__device__ __forceinline__ float box_gap2(const float* __restrict__ b, const float (&glo)[M], const float (&ghi)[M])
+// Whether a box may hold a candidate for any of the wavefront's rows: the
+// squared gap from row r's point to the box against row r's own threshold.
+// (Testing the rows' common bounding box instead lets a wavefront whose rows
+// straddle a jump of the curve scan far too many tiles.)
+template <int M, int R>
+__device__ __forceinline__ bool box_near_rows(const float* __restrict__ b, const float (&q)[R][M],
+                                              const float (&tau)[R])
 {
-    float s = 0.f;
+    float lo[M], hi[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-        const float g = fmaxf(fmaxf(b[c] - ghi[c], glo[c] - b[M + c]), 0.f);
-        s = fmaf(g, g, s);
+        lo[c] = b[c];
+        hi[c] = b[M + c];
     }
-    return s;
+    bool near = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float s = 0.f;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const float g = fmaxf(fmaxf(lo[c] - q[r][c], q[r][c] - hi[c]), 0.f);
+            s = fmaf(g, g, s);
+        }
+        near = near || s <= tau[r];
+    }
+    return near;
 }
 
 constexpr int SEED_TILES = 2;   // curve neighbours on each side scored before any box test
+constexpr int TILE_BATCH = 4;   // tiles of a superblock whose loads are in flight together
 
 // Upper bound on the kp-th smallest of the wavefront's NS x 64 non-negative
 // values (+inf marks none): bisection on the float bit pattern down to bit
@@ -105,10 +123,9 @@ __device__ __forceinline__ void load_tile(const SpatialView& sv, int n, int t, i
 template <int M, int R, int E>
 __device__ __forceinline__ void score_tile(const float (&q)[R][M], const float (&x)[M], uint32_t jo, bool valid, int n,
                                            int t, int kp, int rows_here, int lane, uint64_t* buf, uint64_t (&L)[R][E],
-                                           float (&tau)[R], int (&bc)[R], float& taumax, unsigned long long& pairs)
+                                           float (&tau)[R], int (&bc)[R], unsigned long long& pairs)
 {
     pairs += static_cast<unsigned long long>(min(TILE, n - t * TILE)) * rows_here;
-    bool merged = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         float tt = q[r][0] - x[0];
@@ -127,7 +144,6 @@ __device__ __forceinline__ void score_tile(const float (&q)[R][M], const float (
                 merge_into_list<E>(L[r], b);
                 bc[r] = 0;
                 tau[r] = key_dist(list_at<E>(L[r], kp - 1));
-                merged = true;
                 mask = __ballot(valid && d <= tau[r]);
                 cnt = __popcll(mask);
                 wave_lds_sync();
@@ -135,11 +151,6 @@ __device__ __forceinline__ void score_tile(const float (&q)[R][M], const float (
             if ((mask >> lane) & 1ull) buf[r * WAVE + bc[r] + mbcnt64(mask)] = make_key(d, jo);
             bc[r] += cnt;
         }
-    }
-    if (merged) {
-        taumax = tau[0];
-#pragma unroll
-        for (int r = 1; r < R; ++r) taumax = fmaxf(taumax, tau[r]);
     }
 }
 
@@ -162,17 +173,6 @@ __global__ __launch_bounds__(256) void k_select_direct(SpatialView sv, int n, in
 #pragma unroll
         for (int c = 0; c < M; ++c) q[r][c] = sv.Xs[static_cast<size_t>(p) * M + c];
     }
-    float glo[M], ghi[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        glo[c] = q[0][c];
-        ghi[c] = q[0][c];
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-            glo[c] = fminf(glo[c], q[r][c]);
-            ghi[c] = fmaxf(ghi[c], q[r][c]);
-        }
-    }
     uint64_t L[R][E];
     float tau[R];
     int bc[R];
@@ -183,7 +183,6 @@ __global__ __launch_bounds__(256) void k_select_direct(SpatialView sv, int n, in
         tau[r] = __uint_as_float(0x7F800000u);
         bc[r] = 0;
     }
-    float taumax = __uint_as_float(0x7F800000u);
     uint64_t* buf = &sbuf[wave][0][0];
     const int rows_here = min(R, n - row0);
     unsigned long long pairs = 0;
@@ -218,24 +217,20 @@ __global__ __launch_bounds__(256) void k_select_direct(SpatialView sv, int n, in
         }
         tau[r] = seed_threshold<NS>(ds, kp);
     }
-    taumax = tau[0];
-#pragma unroll
-    for (int r = 1; r < R; ++r) taumax = fmaxf(taumax, tau[r]);
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
         const int t = a0 + u;
         if (t <= a1)
             score_tile<M, R, E>(q, xs[u], js[u], t * TILE + lane < n, n, t, kp, rows_here, lane, buf, L, tau, bc,
-                                taumax, pairs);
+                                pairs);
     }
-    float xc[M];
-    uint32_t jc_o = 0;
-    // then every superblock within reach (boxes tested 64 at a time, one per
-    // lane), and inside it every tile within reach (16 lanes)
+    // then every superblock within reach of some row (boxes tested 64 at a
+    // time, one per lane), inside it every tile within reach (16 lanes), the
+    // tiles' loads issued TILE_BATCH at a time
     for (int sb0 = 0; sb0 < nsb; sb0 += WAVE) {
         const int sbl = sb0 + lane;
         bool near = false;
-        if (sbl < nsb) near = box_gap2<M>(sv.sbox + static_cast<size_t>(sbl) * 2 * M, glo, ghi) <= taumax;
+        if (sbl < nsb) near = box_near_rows<M, R>(sv.sbox + static_cast<size_t>(sbl) * 2 * M, q, tau);
         uint64_t sbm = __ballot(near);
         while (sbm) {
             const int sb = sb0 + __builtin_ctzll(sbm);
@@ -243,29 +238,27 @@ __global__ __launch_bounds__(256) void k_select_direct(SpatialView sv, int n, in
             const int tl = sb * SB_TILES + lane;
             bool tnear = false;
             if (lane < SB_TILES && tl < ntiles && (tl < a0 || tl > a1))
-                tnear = box_gap2<M>(sv.tbox + static_cast<size_t>(tl) * 2 * M, glo, ghi) <= taumax;
+                tnear = box_near_rows<M, R>(sv.tbox + static_cast<size_t>(tl) * 2 * M, q, tau);
             uint64_t tm = __ballot(tnear);
-            if (!tm) continue;
-            int t = sb * SB_TILES + __builtin_ctzll(tm);
-            tm &= tm - 1;
-            load_tile<M>(sv, n, t, lane, xc, jc_o);
-            while (t >= 0) {
-                int tn = -1;
-                float xn[M];
-                uint32_t jn_o = 0;
-                if (tm) {
-                    tn = sb * SB_TILES + __builtin_ctzll(tm);
-                    tm &= tm - 1;
-                    load_tile<M>(sv, n, tn, lane, xn, jn_o);
-                }
-                score_tile<M, R, E>(q, xc, jc_o, t * TILE + lane < n, n, t, kp, rows_here, lane, buf, L, tau, bc,
-                                    taumax, pairs);
-                if (tn >= 0) {
+            while (tm) {
+                int tb[TILE_BATCH];
+                float xb[TILE_BATCH][M];
+                uint32_t jb[TILE_BATCH];
 #pragma unroll
-                    for (int c = 0; c < M; ++c) xc[c] = xn[c];
-                    jc_o = jn_o;
+                for (int u = 0; u < TILE_BATCH; ++u) {
+                    tb[u] = -1;
+                    jb[u] = 0;
+                    if (tm) {
+                        tb[u] = sb * SB_TILES + __builtin_ctzll(tm);
+                        tm &= tm - 1;
+                        load_tile<M>(sv, n, tb[u], lane, xb[u], jb[u]);
+                    }
                 }
-                t = tn;
+#pragma unroll
+                for (int u = 0; u < TILE_BATCH; ++u)
+                    if (tb[u] >= 0)
+                        score_tile<M, R, E>(q, xb[u], jb[u], tb[u] * TILE + lane < n, n, tb[u], kp, rows_here, lane,
+                                            buf, L, tau, bc, pairs);
             }
         }
     }

@@ -384,8 +384,21 @@ __device__ __noinline__ float sort_query_list(uint64_t* __restrict__ dst, int kp
 // all wavefronts take the same skipping decisions. The certificate epilogue
 // is that of MODE 0: a skipped candidate lies beyond the threshold at the
 // time of the skip, hence beyond every later one.
+// Curve scans run as two 4-wavefront workgroups per CU where both fit in LDS
+// (two candidate stages and 40-entry query buffers each): a wavefront's list
+// merge then holds up three others at the tile barrier instead of seven, and
+// the other workgroup keeps the CU busy meanwhile.
+constexpr int CURVE_PAIR_BUF = 40;
+template <class Tr, int KS>
+constexpr bool curve_pair()
+{
+    return 2 * (2 * KS * 64 * static_cast<int>(sizeof(typename Tr::frag)) + 4 * 32 * CURVE_PAIR_BUF * 8 + 2048) <=
+           160 * 1024;
+}
+
 template <class Tr, int KS, int WV, int E, int MODE>
-__global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem* __restrict__ Aq,
+__global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS>()) ? 2 : 1) void k_select_mfma(
+    const typename Tr::elem* __restrict__ Aq,
                                                           const typename Tr::elem* __restrict__ Bc, int n, int kp,
                                                           const float* __restrict__ ynorm2,
                                                           const unsigned* __restrict__ rmax_bits, ErrModel em,
@@ -400,7 +413,8 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
     constexpr int CAP = WAVE * E;
     constexpr int kpad = KS * Tr::KSTEP;        // padded contraction length
     constexpr int NQ = 32;                      // queries per wavefront
-    constexpr int BUF = WV == 8 ? 48 : 64;      // per-query LDS buffer entries
+    // per-query LDS buffer entries (curve scans in pairs of 4-wavefront workgroups: 40)
+    constexpr int BUF = (MODE == 2 && WV == 4 && curve_pair<Tr, KS>()) ? CURVE_PAIR_BUF : WV == 8 ? 48 : 64;
     // two candidate stages, fragment-major: [stage][k-step][half][row] so that
     // lane l reads consecutive fragments (no bank conflicts). The next tile is
     // prefetched into registers while the current one is consumed.
@@ -553,17 +567,21 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
     // lists that start empty are filled by the first tiles without merging
     bool filling = !LEARNED || ba.first;
     const int fill_tiles = (kp + 31) / 32;
+    // MODE 2: this wavefront's largest distance threshold, an upper bound of
+    // s + |y_i|^2 over its queries; recomputed only after thresholds change
+    float wthr = __uint_as_float(0x7F800000u);
+    bool thr_dirty = true;
     for (int it = 0; tile >= 0; ++it) {
         const int stage = it & 1;
-        float wthr = 0.f;
         if constexpr (CURVE) {
-            // this wavefront's largest distance threshold, an upper bound of
-            // s + |y_i|^2 over its queries
-            float t = -__uint_as_float(0x7F800000u);
+            if (thr_dirty) {
+                float t = -__uint_as_float(0x7F800000u);
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if (qrow[r] >= 0) t = fmaxf(t, fmaxf(tauv[r] + yq[r], 0.f) * (1.f + 4.8e-7f));
-            wthr = wave_max_f32(t);
+                for (int r = 0; r < 16; ++r)
+                    if (qrow[r] >= 0) t = fmaxf(t, fmaxf(tauv[r] + yq[r], 0.f) * (1.f + 4.8e-7f));
+                wthr = wave_max_f32(t);
+                thr_dirty = false;
+            }
             if (lane == 0) s_thr[stage][wave] = wthr;
         }
         {
@@ -661,6 +679,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
 #pragma unroll
                     for (int r = 0; r < 16; ++r)
                         if (r == rr && half == hh) tauv[r] = nt;
+                    thr_dirty = true;
                 }
             }
             tile = next;
@@ -687,6 +706,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
                             nt = merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][qa_][0], ca,
                                                      kp);
                         if (half == 0) tauv[r] = nt;
+                        thr_dirty = true;
                         ca = 0;
                     }
                     if (fb) {
@@ -696,6 +716,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
                             nt = merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][qb_][0], cb,
                                                      kp);
                         if (half == 1) tauv[r] = nt;
+                        thr_dirty = true;
                         cb = 0;
                     }
                     wave_lds_sync();
@@ -730,6 +751,7 @@ __global__ __launch_bounds__(64 * WV) void k_select_mfma(const typename Tr::elem
         wave_lds_sync();
     }
     if (pair_count && lane == 0) atomicAdd(pair_count, pairs);
+
     if constexpr (LEARNED) return;
     // certificate lower bound for the candidates left out of each list
     const double R = static_cast<double>(__uint_as_float(*rmax_bits));
@@ -810,11 +832,13 @@ static hipError_t launch_sel(const void* Aq, const void* Bc, int n, int kp, cons
     }
     const dim3 grid((n + rows_per_block - 1) / rows_per_block);
     if (crv) {
+        constexpr int WC = curve_pair<Tr, KS>() ? 4 : WV;
+        const dim3 gridc((n + WC * 32 - 1) / (WC * 32)), blockc(64 * WC);
         if (cap == 128)
-            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 2, 2>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
+            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WC, 2, 2>), gridc, blockc, 0, st, A, B, n, kp, ynorm2, rmax, em,
                                lists, lb, nb, *crv, pairs);
         else
-            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WV, 4, 2>), grid, block, 0, st, A, B, n, kp, ynorm2, rmax, em,
+            hipLaunchKernelGGL((k_select_mfma<Tr, KS, WC, 4, 2>), gridc, blockc, 0, st, A, B, n, kp, ynorm2, rmax, em,
                                lists, lb, nb, *crv, pairs);
         return hipGetLastError();
     }

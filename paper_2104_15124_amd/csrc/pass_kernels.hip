@@ -33,10 +33,29 @@ constexpr int RL = 16;   // lanes per row in the row-sum passes
 __device__ __forceinline__ double row_kernel_sum16(const int32_t* __restrict__ irow, const float* __restrict__ drow,
                                                    int k, const float* __restrict__ rho, double inv_e_rhoi, int gl)
 {
+    // four entries per lane at a time: their loads and gathers are in flight
+    // together; the sum still runs entry by entry
+    constexpr int B = 4;
     double s = 0.0;
-    for (int r = gl; r < k; r += RL) {
-        const double x = static_cast<double>(drow[r]) * inv_e_rhoi / static_cast<double>(rho[irow[r]]);
-        s += exp(-x);
+    for (int r0 = gl; r0 < k; r0 += B * RL) {
+        float dv[B];
+        int jv[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int r = r0 + u * RL;
+            dv[u] = r < k ? drow[r] : 0.f;
+            jv[u] = r < k ? irow[r] : 0;
+        }
+        float rj[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) rj[u] = rho[jv[u]];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (r0 + u * RL < k) {
+                const double x = static_cast<double>(dv[u]) * inv_e_rhoi / static_cast<double>(rj[u]);
+                s += exp(-x);
+            }
+        }
     }
 #pragma unroll
     for (int o = 1; o < RL; o <<= 1) s += shfl_xor_f64(s, o);
@@ -83,6 +102,7 @@ __device__ __forceinline__ double grid_log(double lo, double hi, int G, int g)
     return lo + (static_cast<double>(g) * (hi - lo)) / static_cast<double>(G - 1);
 }
 constexpr int CHI_MIN_ENTRIES_PER_BLOCK = 8192;
+constexpr int CHI_BATCH = 4;
 constexpr int CHI_MAX_BLOCKS = 1024;
 
 __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __restrict__ idx,
@@ -108,13 +128,32 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
         float acc[CHI_GROUP];
 #pragma unroll
         for (int t = 0; t < CHI_GROUP; ++t) acc[t] = 0.f;
-        for (int64_t p = base + threadIdx.x; p < end; p += CHI_BLOCK) {
-            const int64_t i = p / k;
-            const float x =
-                static_cast<float>(static_cast<double>(d2[p]) /
-                                   (static_cast<double>(rho[i]) * static_cast<double>(rho[idx[p]])));
+        // CHI_BATCH entries per thread at a time (their loads and gathers in
+        // flight together); the accumulation order stays entry by entry
+        for (int64_t p0 = base + threadIdx.x; p0 < end; p0 += CHI_BATCH * CHI_BLOCK) {
+            float dv[CHI_BATCH];
+            int jv[CHI_BATCH];
+            int64_t iv[CHI_BATCH];
 #pragma unroll
-            for (int t = 0; t < CHI_GROUP; ++t) acc[t] += __builtin_amdgcn_exp2f(x * cg[t]);
+            for (int u = 0; u < CHI_BATCH; ++u) {
+                const int64_t p = p0 + u * CHI_BLOCK;
+                const bool ok = p < end;
+                dv[u] = ok ? d2[p] : 0.f;
+                jv[u] = ok ? idx[p] : 0;
+                iv[u] = ok ? p / k : 0;
+            }
+            float x[CHI_BATCH];
+#pragma unroll
+            for (int u = 0; u < CHI_BATCH; ++u)
+                x[u] = static_cast<float>(static_cast<double>(dv[u]) /
+                                          (static_cast<double>(rho[iv[u]]) * static_cast<double>(rho[jv[u]])));
+#pragma unroll
+            for (int u = 0; u < CHI_BATCH; ++u) {
+                if (p0 + u * CHI_BLOCK < end) {
+#pragma unroll
+                    for (int t = 0; t < CHI_GROUP; ++t) acc[t] += __builtin_amdgcn_exp2f(x[u] * cg[t]);
+                }
+            }
         }
         // fixed-order reduction: butterfly inside the wavefront, then the 4 wavefronts
 #pragma unroll
