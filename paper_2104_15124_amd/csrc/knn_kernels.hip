@@ -84,8 +84,8 @@ __device__ __forceinline__ bool box_near_rows(const float* __restrict__ b, const
     return near;
 }
 
-constexpr int SEED_TILES = 2;   // curve neighbours on each side scored before any box test
-constexpr int TILE_BATCH = 4;   // tiles of a superblock whose loads are in flight together
+constexpr int SEED_TILES = 3;   // curve neighbours on each side scored before any box test
+constexpr int TILE_BATCH = 2;   // tiles of a superblock whose loads are in flight together
 
 // Upper bound on the kp-th smallest of the wavefront's NS x 64 non-negative
 // values (+inf marks none): bisection on the float bit pattern down to bit
@@ -994,10 +994,10 @@ hipError_t launch_select_direct(const float* Xs, const int32_t* perm, const floa
 {
     const SpatialView sv = {Xs, perm, tbox, sbox};
     switch (m) {
-    case 1: return launch_select_m<1, 8>(sv, n, kp, keys, slast, pairs, st);
-    case 2: return launch_select_m<2, 8>(sv, n, kp, keys, slast, pairs, st);
-    case 3: return launch_select_m<3, 8>(sv, n, kp, keys, slast, pairs, st);
-    case 4: return launch_select_m<4, 8>(sv, n, kp, keys, slast, pairs, st);
+    case 1: return launch_select_m<1, 4>(sv, n, kp, keys, slast, pairs, st);
+    case 2: return launch_select_m<2, 4>(sv, n, kp, keys, slast, pairs, st);
+    case 3: return launch_select_m<3, 4>(sv, n, kp, keys, slast, pairs, st);
+    case 4: return launch_select_m<4, 4>(sv, n, kp, keys, slast, pairs, st);
     case 5: return launch_select_m<5, 4>(sv, n, kp, keys, slast, pairs, st);
     case 6: return launch_select_m<6, 4>(sv, n, kp, keys, slast, pairs, st);
     case 7: return launch_select_m<7, 4>(sv, n, kp, keys, slast, pairs, st);

@@ -90,92 +90,99 @@ __device__ __forceinline__ size_t bpos(int i, int c, int kpad, int kstep, int ve
 // Rows n..npad-1 pad the last 32-row tile with zeros. With brow non-null the
 // candidate operand row of sample i is written at row brow[i] instead of i
 // (the bucket order of the learned partitioner; npad == n).
+static int prep_blocks(int npad) { return std::max(1, std::min(4096, (npad + 3) / 4)); }
+
 __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, int n, int npad, int m,
                                                    const double* __restrict__ mu, int split, int kpad,
                                                    void* __restrict__ Aq, void* __restrict__ Bc,
                                                    float* __restrict__ ynorm2, unsigned* __restrict__ rmax_bits,
                                                    const int* __restrict__ brow, const int* __restrict__ arow)
 {
+    // rows are taken in a grid-stride loop; the largest norm is folded per
+    // wavefront and published with one atomic (an atomic per row serialises
+    // millions of updates of one address)
     const int lane = lane_id();
-    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (i >= npad) return;
-    const bool real = i < n;
-    const int ib = (brow && real) ? brow[i] : i;   // candidate operand row
-    const int ia = (arow && real) ? arow[i] : i;   // query operand row
-    const float* x = X + static_cast<size_t>(real ? i : 0) * m;
-    double nrm = 0.0;
-    if (split == 0) {
-        constexpr int KS = 2, VE = 1;
-        float* A = static_cast<float*>(Aq) + static_cast<size_t>(ia) * kpad;
-        float* B = static_cast<float*>(Bc);
-        for (int c = lane; c < m; c += WAVE) {
-            const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
-            nrm += static_cast<double>(y) * static_cast<double>(y);
-            if (real) A[c] = -2.0f * y;
-            B[bpos(ib, c, kpad, KS, VE)] = y;
-        }
-        nrm = wave_sum_f64(nrm);
-        for (int c = m + lane; c < kpad; c += WAVE) {
-            if (real) A[c] = (c == m) ? 1.0f : 0.0f;
-            B[bpos(ib, c, kpad, KS, VE)] = (c == m) ? static_cast<float>(nrm) : 0.0f;
-        }
-    } else {
-        constexpr int KS = 16, VE = 8;
-        uint16_t* A = static_cast<uint16_t*>(Aq) + static_cast<size_t>(ia) * kpad;
-        uint16_t* B = static_cast<uint16_t*>(Bc);
-        for (int c = lane; c < m; c += WAVE) {
-            const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
-            nrm += static_cast<double>(y) * static_cast<double>(y);
-            const uint16_t hi = f32_to_bf16_rne(y);
-            const float r1 = y - bf16_to_f32(hi);
-            const uint16_t mid = f32_to_bf16_rne(r1);
-            const float r2 = r1 - bf16_to_f32(mid);
-            const uint16_t lo = f32_to_bf16_rne(r2);
-            // -2 t is exact in BF16 (a power-of-two scaling)
-            const uint16_t hi2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(hi));
-            const uint16_t mid2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(mid));
-            const uint16_t lo2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(lo));
-            uint16_t a[6], b[6];
-            int P = 1;
-            if (split == 1) {
-                a[0] = hi2; b[0] = hi;
-            } else if (split == 3) {                     // (hi,hi) (hi,lo) (lo,hi), the second term as lo
-                a[0] = hi2; b[0] = hi;
-                a[1] = hi2; b[1] = mid;
-                a[2] = mid2; b[2] = hi;
-                P = 3;
-            } else {                                     // (hi,hi) (hi,mid) (mid,hi) (hi,lo) (lo,hi) (mid,mid)
-                a[0] = hi2; b[0] = hi;
-                a[1] = hi2; b[1] = mid;
-                a[2] = mid2; b[2] = hi;
-                a[3] = hi2; b[3] = lo;
-                a[4] = lo2; b[4] = hi;
-                a[5] = mid2; b[5] = mid;
-                P = 6;
+    float wmax = 0.f;
+    for (int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); i < npad; i += gridDim.x * 4) {
+        const bool real = i < n;
+        const int ib = (brow && real) ? brow[i] : i;   // candidate operand row
+        const int ia = (arow && real) ? arow[i] : i;   // query operand row
+        const float* x = X + static_cast<size_t>(real ? i : 0) * m;
+        double nrm = 0.0;
+        if (split == 0) {
+            constexpr int KS = 2, VE = 1;
+            float* A = static_cast<float*>(Aq) + static_cast<size_t>(ia) * kpad;
+            float* B = static_cast<float*>(Bc);
+            for (int c = lane; c < m; c += WAVE) {
+                const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
+                nrm += static_cast<double>(y) * static_cast<double>(y);
+                if (real) A[c] = -2.0f * y;
+                B[bpos(ib, c, kpad, KS, VE)] = y;
             }
-            for (int t = 0; t < P; ++t) {
-                if (real) A[t * m + c] = a[t];
-                B[bpos(ib, t * m + c, kpad, KS, VE)] = b[t];
+            nrm = wave_sum_f64(nrm);
+            for (int c = m + lane; c < kpad; c += WAVE) {
+                if (real) A[c] = (c == m) ? 1.0f : 0.0f;
+                B[bpos(ib, c, kpad, KS, VE)] = (c == m) ? static_cast<float>(nrm) : 0.0f;
+            }
+        } else {
+            constexpr int KS = 16, VE = 8;
+            uint16_t* A = static_cast<uint16_t*>(Aq) + static_cast<size_t>(ia) * kpad;
+            uint16_t* B = static_cast<uint16_t*>(Bc);
+            for (int c = lane; c < m; c += WAVE) {
+                const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
+                nrm += static_cast<double>(y) * static_cast<double>(y);
+                const uint16_t hi = f32_to_bf16_rne(y);
+                const float r1 = y - bf16_to_f32(hi);
+                const uint16_t mid = f32_to_bf16_rne(r1);
+                const float r2 = r1 - bf16_to_f32(mid);
+                const uint16_t lo = f32_to_bf16_rne(r2);
+                // -2 t is exact in BF16 (a power-of-two scaling)
+                const uint16_t hi2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(hi));
+                const uint16_t mid2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(mid));
+                const uint16_t lo2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(lo));
+                uint16_t a[6], b[6];
+                int P = 1;
+                if (split == 1) {
+                    a[0] = hi2; b[0] = hi;
+                } else if (split == 3) {                     // (hi,hi) (hi,lo) (lo,hi), the second term as lo
+                    a[0] = hi2; b[0] = hi;
+                    a[1] = hi2; b[1] = mid;
+                    a[2] = mid2; b[2] = hi;
+                    P = 3;
+                } else {                                     // (hi,hi) (hi,mid) (mid,hi) (hi,lo) (lo,hi) (mid,mid)
+                    a[0] = hi2; b[0] = hi;
+                    a[1] = hi2; b[1] = mid;
+                    a[2] = mid2; b[2] = hi;
+                    a[3] = hi2; b[3] = lo;
+                    a[4] = lo2; b[4] = hi;
+                    a[5] = mid2; b[5] = mid;
+                    P = 6;
+                }
+                for (int t = 0; t < P; ++t) {
+                    if (real) A[t * m + c] = a[t];
+                    B[bpos(ib, t * m + c, kpad, KS, VE)] = b[t];
+                }
+            }
+            nrm = wave_sum_f64(nrm);
+            const int P = split;
+            const uint16_t n1 = f32_to_bf16_rne(static_cast<float>(nrm));
+            const double r1 = nrm - static_cast<double>(bf16_to_f32(n1));
+            const uint16_t n2 = f32_to_bf16_rne(static_cast<float>(r1));
+            const double r2 = r1 - static_cast<double>(bf16_to_f32(n2));
+            const uint16_t n3 = f32_to_bf16_rne(static_cast<float>(r2));
+            const uint16_t one = f32_to_bf16_rne(1.0f);
+            for (int c = P * m + lane; c < kpad; c += WAVE) {
+                const int t = c - P * m;
+                if (real) A[c] = t < 3 ? one : static_cast<uint16_t>(0);
+                B[bpos(ib, c, kpad, KS, VE)] = t == 0 ? n1 : t == 1 ? n2 : t == 2 ? n3 : static_cast<uint16_t>(0);
             }
         }
-        nrm = wave_sum_f64(nrm);
-        const int P = split;
-        const uint16_t n1 = f32_to_bf16_rne(static_cast<float>(nrm));
-        const double r1 = nrm - static_cast<double>(bf16_to_f32(n1));
-        const uint16_t n2 = f32_to_bf16_rne(static_cast<float>(r1));
-        const double r2 = r1 - static_cast<double>(bf16_to_f32(n2));
-        const uint16_t n3 = f32_to_bf16_rne(static_cast<float>(r2));
-        const uint16_t one = f32_to_bf16_rne(1.0f);
-        for (int c = P * m + lane; c < kpad; c += WAVE) {
-            const int t = c - P * m;
-            if (real) A[c] = t < 3 ? one : static_cast<uint16_t>(0);
-            B[bpos(ib, c, kpad, KS, VE)] = t == 0 ? n1 : t == 1 ? n2 : t == 2 ? n3 : static_cast<uint16_t>(0);
+        if (real && lane == 0) {
+            ynorm2[i] = static_cast<float>(nrm);
+            wmax = fmaxf(wmax, static_cast<float>(sqrt(nrm) * (1.0 + 1e-6)));
         }
     }
-    if (real && lane == 0) {
-        ynorm2[i] = static_cast<float>(nrm);
-        atomicMax(rmax_bits, __float_as_uint(static_cast<float>(sqrt(nrm) * (1.0 + 1e-6))));
-    }
+    if (lane == 0 && wmax > 0.f) atomicMax(rmax_bits, __float_as_uint(wmax));
 }
 
 // ------------------------------------------------------------------ select
@@ -785,7 +792,7 @@ hipError_t launch_prep_rows(const float* X, int n, int m, const double* mu, int 
                             float* ynorm2, unsigned* rmax_bits, const int* brow, const int* arow, hipStream_t st)
 {
     const int npad = brow ? n : (n + 31) / 32 * 32;
-    hipLaunchKernelGGL(k_prep_rows, dim3((npad + 3) / 4), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq, Bc,
+    hipLaunchKernelGGL(k_prep_rows, dim3(prep_blocks(npad)), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq, Bc,
                        ynorm2, rmax_bits, brow, arow);
     return hipGetLastError();
 }
@@ -799,7 +806,7 @@ hipError_t launch_prep(const float* X, int n, int m, int split, int kpad, double
     const int npad = brow ? n : (n + 31) / 32 * 32;
     hipLaunchKernelGGL(k_colsum_partial, dim3(colblocks), dim3(256), 0, st, X, n, m, rpb, colpart);
     hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(256), 0, st, colpart, colblocks, m, n, mu);
-    hipLaunchKernelGGL(k_prep_rows, dim3((npad + 3) / 4), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq, Bc,
+    hipLaunchKernelGGL(k_prep_rows, dim3(prep_blocks(npad)), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq, Bc,
                        ynorm2, rmax_bits, brow, arow);
     return hipGetLastError();
 }
