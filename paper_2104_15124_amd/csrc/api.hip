@@ -193,9 +193,11 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
     KVB_HIP(ctx, hipMemsetAsync(ctx->pairs_dev, 0, sizeof(unsigned long long), ctx->stream));
     float lb_scale = 1.0f;
     int kstride = kp;
+    float* Xs = nullptr;        // direct tiles: curve-ordered samples, lists stored in that order
+    int32_t* perm = nullptr;
     if (direct) {
-        float* Xs = cv.take<float>(size_t(nn) * m);
-        int32_t* perm = cv.take<int32_t>(nn);
+        Xs = cv.take<float>(size_t(nn) * m);
+        perm = cv.take<int32_t>(nn);
         int32_t* vals = cv.take<int32_t>(nn);
         uint32_t* code = cv.take<uint32_t>(nn);
         uint32_t* scode = cv.take<uint32_t>(nn);
@@ -292,7 +294,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
         Prof pr(ctx, KVB_PROF_KNN_REFINE);
         KVB_HIP(ctx, kvb::launch_refine(X, nn, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, row_flags,
                                         ctx->fb_count_dev, fb_list, fb_bound, static_cast<int>(ctx->force_fallback),
-                                        ctx->stream));
+                                        Xs, perm, ctx->stream));
     }
     {
         Prof pr(ctx, KVB_PROF_KNN_FALLBACK);

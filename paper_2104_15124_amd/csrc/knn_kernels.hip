@@ -115,7 +115,7 @@ __device__ __forceinline__ void load_tile(const SpatialView& sv, int n, int t, i
     const int jp = min(t * TILE + lane, n - 1);
 #pragma unroll
     for (int c = 0; c < M; ++c) x[c] = sv.Xs[static_cast<size_t>(jp) * M + c];
-    jo = static_cast<uint32_t>(sv.perm[jp]);
+    jo = static_cast<uint32_t>(jp);   // curve position; the refine step maps it to the sample id
 }
 
 // Score one tile of 64 candidates against the wavefront's R rows and append
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void k_select_direct(SpatialView sv, int n, in
             merge_into_list<E>(L[r], b);
         }
         if (row0 + r < n) {
-            const int i = sv.perm[row0 + r];
+            const int i = row0 + r;   // lists are stored by curve position
             uint64_t* dst = keys_out + static_cast<size_t>(i) * kp;
 #pragma unroll
             for (int s = 0; s < E; ++s) {
@@ -495,26 +495,43 @@ __device__ __forceinline__ void group_distances(const float* __restrict__ X, int
 // 1/(1 + select error); matrix-core tiles: the bound itself, lb_scale = 1).
 // slast == nullptr: no bound (learned routing). LPC == 0: each lane computes
 // its own candidates' distances (compensated float32, short rows); LPC > 0:
-// groups of LPC lanes per candidate (group_distances, long rows).
-template <int E, int LPC>
+// groups of LPC lanes per candidate (group_distances, long rows). Lists whose
+// recomputed keys are still in ascending order once row i is taken out (the
+// common case after the direct tiles, whose float32 scores differ from the
+// compensated distances only in the last bits) skip the sorting network.
+//
+// CV (direct tiles): lists and bounds are stored by curve position r, their
+// keys hold curve positions; the candidates are read from the curve-ordered
+// copy Xs (neighbouring rows read neighbouring samples) and the keys are
+// turned into (distance, sample id) through perm before any ordering.
+template <int E, int LPC, bool CV>
 __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int n, int m, int k, int kp,
                                                 int kstride, const uint64_t* __restrict__ keys,
                                                 const float* __restrict__ slast, float lb_scale,
                                                 int32_t* __restrict__ idx_out, float* __restrict__ d2_out,
                                                 int32_t* __restrict__ flags_out,
                                                 int* __restrict__ fb_count, int* __restrict__ fb_list,
-                                                float* __restrict__ fb_bound, int force_period)
+                                                float* __restrict__ fb_bound, int force_period,
+                                                const float* __restrict__ Xs, const int32_t* __restrict__ perm)
 {
     const int lane = lane_id();
-    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (i >= n) return;
-    const float* xi = X + static_cast<size_t>(i) * m;
+    const int r = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // stored row
+    if (r >= n) return;
+    const int i = CV ? perm[r] : r;   // sample id
+    const float* xi = CV ? Xs + static_cast<size_t>(r) * m : X + static_cast<size_t>(i) * m;
     // candidate distances, self removed
     uint64_t v[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         const int t = s * WAVE + lane;
-        v[s] = t < kp ? keys[static_cast<size_t>(i) * kstride + t] : KEY_INF;
+        v[s] = t < kp ? keys[static_cast<size_t>(r) * kstride + t] : KEY_INF;
+    }
+    // list position of row i, if present
+    int ps = -1;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const uint64_t mm = __ballot(v[s] != KEY_INF && static_cast<int>(key_idx(v[s])) == r);
+        if (ps < 0 && mm) ps = s * WAVE + __builtin_ctzll(mm);
     }
     if constexpr (LPC == 0) {
 #pragma unroll
@@ -522,8 +539,10 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
             uint64_t key = v[s];
             if (key != KEY_INF) {
                 const uint32_t j = key_idx(key);
-                if (static_cast<int>(j) == i)
+                if (static_cast<int>(j) == r)
                     key = KEY_INF;
+                else if constexpr (CV)
+                    key = make_key(comp_dist2(xi, Xs + static_cast<size_t>(j) * m, m), static_cast<uint32_t>(perm[j]));
                 else
                     key = make_key(comp_dist2(xi, X + static_cast<size_t>(j) * m, m), j);
             }
@@ -545,7 +564,29 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
             v[s] = key;
         }
     }
-    bitonic_sort<E>(v);
+    {
+        // the keys one position on, with row i (now KEY_INF) moved past the end
+        uint64_t nv[E];
+        bool sorted = true;
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            uint64_t nx = shfl_u64(v[s], (lane + 1) & (WAVE - 1));
+            if (lane == WAVE - 1) nx = (s + 1 < E) ? readlane_u64(v[s + 1 < E ? s + 1 : s], 0) : KEY_INF;
+            nv[s] = (ps >= 0 && s * WAVE + lane >= ps) ? nx : v[s];
+        }
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            uint64_t nx = shfl_u64(nv[s], (lane + 1) & (WAVE - 1));
+            if (lane == WAVE - 1) nx = (s + 1 < E) ? readlane_u64(nv[s + 1 < E ? s + 1 : s], 0) : KEY_INF;
+            sorted = sorted && !__ballot(nv[s] > nx);
+        }
+        if (sorted) {
+#pragma unroll
+            for (int s = 0; s < E; ++s) v[s] = nv[s];
+        } else {
+            bitonic_sort<E>(v);
+        }
+    }
 
     const int kk = k - 1;  // neighbours other than i
     int32_t* orow = idx_out + static_cast<size_t>(i) * k;
@@ -650,7 +691,7 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
         if (slast) {
             // certificate: every candidate the select step dropped has a true
             // squared distance >= slast * lb_scale; it must exceed the largest kept
-            const float lb = slast[i] * lb_scale;
+            const float lb = slast[r] * lb_scale;
             const float ub = kept_max * (1.f + dl) * (1.f + 1e-6f);
             certified = lb > ub;
         } else {
@@ -1006,43 +1047,51 @@ hipError_t launch_select_direct(const float* Xs, const int32_t* perm, const floa
     }
 }
 
-template <int LPC>
+template <int LPC, bool CV>
 static void launch_refine_l(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,
                             const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags, int* fb_count,
-                            int* fb_list, float* fb_bound, int force_period, hipStream_t st)
+                            int* fb_list, float* fb_bound, int force_period, const float* Xs, const int32_t* perm,
+                            hipStream_t st)
 {
     const dim3 grid((n + 3) / 4), block(256);
     if (kp <= 64)
-        hipLaunchKernelGGL((k_refine<1, LPC>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
-                           d2, flags, fb_count, fb_list, fb_bound, force_period);
+        hipLaunchKernelGGL((k_refine<1, LPC, CV>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale,
+                           idx, d2, flags, fb_count, fb_list, fb_bound, force_period, Xs, perm);
     else if (kp <= 128)
-        hipLaunchKernelGGL((k_refine<2, LPC>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
-                           d2, flags, fb_count, fb_list, fb_bound, force_period);
+        hipLaunchKernelGGL((k_refine<2, LPC, CV>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale,
+                           idx, d2, flags, fb_count, fb_list, fb_bound, force_period, Xs, perm);
     else
-        hipLaunchKernelGGL((k_refine<4, LPC>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale, idx,
-                           d2, flags, fb_count, fb_list, fb_bound, force_period);
+        hipLaunchKernelGGL((k_refine<4, LPC, CV>), grid, block, 0, st, X, n, m, k, kp, kstride, keys, slast, lb_scale,
+                           idx, d2, flags, fb_count, fb_list, fb_bound, force_period, Xs, perm);
 }
 
 hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,
                          const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags,
-                         int* fb_count, int* fb_list, float* fb_bound, int force_period, hipStream_t st)
+                         int* fb_count, int* fb_list, float* fb_bound, int force_period, const float* Xs,
+                         const int32_t* perm, hipStream_t st)
 {
-    // rows of up to 24 floats stay with one lane per candidate; longer rows are
-    // read by groups of lanes (each lane covers at most 4 float4 pieces)
-    if (m <= 24)
-        launch_refine_l<0>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                           fb_bound, force_period, st);
-    else if (m <= 64)
-        launch_refine_l<16>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                            fb_bound, force_period, st);
-    else if (m <= 128)
-        launch_refine_l<32>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                            fb_bound, force_period, st);
-    else if (m <= 1024)
-        launch_refine_l<64>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                            fb_bound, force_period, st);
-    else
+    // curve-ordered lists (direct tiles, m <= 8); otherwise rows of up to 24
+    // floats stay with one lane per candidate, longer rows are read by groups
+    // of lanes (each lane covers at most 4 float4 pieces)
+    if (perm) {
+        if (m > 24) return hipErrorInvalidValue;
+        launch_refine_l<0, true>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
+                                 fb_bound, force_period, Xs, perm, st);
+    } else if (m <= 24) {
+        launch_refine_l<0, false>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
+                                  fb_bound, force_period, nullptr, nullptr, st);
+    } else if (m <= 64) {
+        launch_refine_l<16, false>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
+                                   fb_bound, force_period, nullptr, nullptr, st);
+    } else if (m <= 128) {
+        launch_refine_l<32, false>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
+                                   fb_bound, force_period, nullptr, nullptr, st);
+    } else if (m <= 1024) {
+        launch_refine_l<64, false>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
+                                   fb_bound, force_period, nullptr, nullptr, st);
+    } else {
         return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -66,7 +66,8 @@ hipError_t launch_select_direct(const float* Xs, const int32_t* perm, const floa
                                 int m, int kp, uint64_t* keys, float* slast, unsigned long long* pairs, hipStream_t st);
 hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,
                          const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags,
-                         int* fb_count, int* fb_list, float* fb_bound, int force_period, hipStream_t st);
+                         int* fb_count, int* fb_list, float* fb_bound, int force_period, const float* Xs,
+                         const int32_t* perm, hipStream_t st);
 
 // Buffers of the exact fallback's bounded pass (k_fb_collect): rows_cap =
 // fallback_rows_cap(n) listed rows with FB_CAP entries each.

@@ -385,7 +385,7 @@ int learned_knn(kvb_ctx ctx, const float* X, int n, int m, int k, int kp, int32_
         Prof pr(ctx, KVB_PROF_KNN_REFINE);
         KVB_HIP(ctx, kvb::launch_refine(X, n, m, k, kp, cap, lists, nullptr, 1.0f, idx, d2, row_flags,
                                         ctx->fb_count_dev, fb_list, fb_bound, static_cast<int>(ctx->force_fallback),
-                                        st));
+                                        nullptr, nullptr, st));
     }
     {
         Prof pr(ctx, KVB_PROF_KNN_FALLBACK);

@@ -116,6 +116,7 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
     const double log_emin = log(e_min * sc), log_emax = log(e_max * sc);
     __shared__ float s_c[256 + CHI_GROUP];
     __shared__ double sred[CHI_BLOCK / WAVE][CHI_GROUP];
+    __shared__ float s_tr[WAVE][CHI_GROUP + 1];   // one wavefront's partials, transposed
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int64_t base = static_cast<int64_t>(blockIdx.x) * per_block;
@@ -124,7 +125,11 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
         s_c[g] = g < G ? static_cast<float>(-1.4426950408889634 / exp(grid_log(log_emin, log_emax, G, g))) : 0.f;
     __syncthreads();
     for (int g0 = 0; g0 < G; g0 += CHI_GROUP) {
-        const float* cg = s_c + g0;   // wave-uniform LDS reads (broadcast)
+        // the group's coefficients are wave-uniform: held in scalar registers
+        float cg[CHI_GROUP];
+#pragma unroll
+        for (int t = 0; t < CHI_GROUP; ++t)
+            cg[t] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_c[g0 + t])));
         float acc[CHI_GROUP];
 #pragma unroll
         for (int t = 0; t < CHI_GROUP; ++t) acc[t] = 0.f;
@@ -155,13 +160,21 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
                 }
             }
         }
-        // fixed-order reduction: butterfly inside the wavefront, then the 4 wavefronts
+        // fixed-order reduction: the wavefronts in turn store their partials
+        // transposed, lane t sums grid point t over the 64 lanes in float64;
+        // then the wavefronts in order
+#pragma unroll 1
+        for (int w = 0; w < CHI_BLOCK / WAVE; ++w) {
+            if (wave == w) {
 #pragma unroll
-        for (int t = 0; t < CHI_GROUP; ++t) {
-            const double v = wave_sum_f64(static_cast<double>(acc[t]));
-            if (lane == 0) sred[wave][t] = v;
+                for (int t = 0; t < CHI_GROUP; ++t) s_tr[lane][t] = acc[t];
+                wave_lds_sync();
+                double v = 0.0;
+                for (int l = 0; l < WAVE; ++l) v += static_cast<double>(s_tr[l][lane]);
+                sred[w][lane] = v;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         if (threadIdx.x < CHI_GROUP && g0 + threadIdx.x < G) {
             double s = 0.0;
             for (int w = 0; w < CHI_BLOCK / WAVE; ++w) s += sred[w][threadIdx.x];
@@ -190,6 +203,7 @@ __global__ __launch_bounds__(1024) void k_chi_finish(const double* __restrict__ 
     const int g = threadIdx.x % Gr, sl = threadIdx.x / Gr;
     if (sl < S && g < G) {
         double a = 0.0;
+#pragma unroll 8
         for (int b = sl; b < nblocks; b += S) a += partial[static_cast<size_t>(b) * G + g];
         part[sl * Gr + g] = a;
     }
