@@ -268,41 +268,73 @@ __device__ __forceinline__ int xcd_block()
     return x * per + min(x, rem) + b / XCDS;
 }
 
-// Curve-order scan (own tile, then alternately right and left) over windows
-// of 64 tiles: one load per window gives every lane the bounds of its tile to
-// the workgroup's box (bw) and to its wavefront's box (ww), so picking the
-// next tile is a ballot against the current threshold with no memory access.
-// The scan state is the same in every wavefront of the workgroup.
+// Curve-order scan: the own tile, then alternately outward to the right and
+// to the left, skipping what lies beyond the workgroup's current threshold.
+// Picking the next tile is a ballot over a window of 64 tiles whose bounds to
+// the workgroup's box (bw) and to this wavefront's box (ww) one load gave
+// every lane. Before a new tile window is loaded, a window of 64 superblock
+// bounds (SB_TILES_MFMA tiles each, also one load) moves the scan past the
+// superblocks beyond reach, so sparse scans do not load tile windows of
+// tiles that are all far away. The scan state is the same in every wavefront
+// of the workgroup.
 struct CurveScan {
-    int cur_r, cur_l;   // next candidate tile on each side
-    int rbase, lbase;   // window origins: lane l is tile rbase + l / lbase - l
+    int cur_r, cur_l;     // next candidate tile on each side
+    int rt0, lt0;         // tile windows: lane l is tile rt0 + l / lt0 - l
+    int rsb0, lsb0;       // superblock windows: lane l is superblock rsb0 + l / lsb0 - l
     bool go_right;
-    float rbw, rww, lbw, lww;
+    float rbw, rww, lbw, lww;   // tile bounds
+    float rsbw, lsbw;           // superblock bounds (workgroup box)
 
-    __device__ __forceinline__ void window(int base, int dir, int own_t, int tend, const CurveArgs& crv,
-                                           const float* qlo, const float* qhi, const float* wlo, const float* whi,
-                                           const BoxBound& bb, float& bw, float& ww)
+    __device__ __forceinline__ void init(int own_t)
     {
-        const int t = base + dir * lane_id();
-        bw = __uint_as_float(0x7F800000u);
-        ww = bw;
-        if (t == own_t) {
-            bw = -bw;
-            ww = -ww;
-        } else if (t >= 0 && t < tend) {
-            float b[2 * PR_DIMS];
-            const float4* src = reinterpret_cast<const float4*>(crv.tbox + static_cast<size_t>(t) * 2 * PR_DIMS);
+        cur_r = own_t;
+        cur_l = own_t - 1;
+        rt0 = lt0 = rsb0 = lsb0 = -4 * WAVE;
+        go_right = true;
+        rbw = rww = lbw = lww = rsbw = lsbw = 0.f;
+    }
+
+    __device__ __forceinline__ static void load_box(const float* __restrict__ src_f, float (&b)[2 * PR_DIMS])
+    {
+        const float4* src = reinterpret_cast<const float4*>(src_f);
 #pragma unroll
-            for (int v = 0; v < PR_DIMS / 2; ++v) {
-                const float4 q = src[v];
-                b[4 * v] = q.x;
-                b[4 * v + 1] = q.y;
-                b[4 * v + 2] = q.z;
-                b[4 * v + 3] = q.w;
-            }
-            bw = box_bound(b, qlo, qhi, bb);
-            ww = box_bound(b, wlo, whi, bb);
+        for (int v = 0; v < PR_DIMS / 2; ++v) {
+            const float4 q = src[v];
+            b[4 * v] = q.x;
+            b[4 * v + 1] = q.y;
+            b[4 * v + 2] = q.z;
+            b[4 * v + 3] = q.w;
         }
+    }
+
+    // bounds of tile t (NaN: no such tile, never within reach; -inf: own tile)
+    __device__ __forceinline__ static void tile_window(int t, int own_t, int tend, const CurveArgs& crv,
+                                                       const float* qlo, const float* qhi, const float* wlo,
+                                                       const float* whi, const BoxBound& bb, float& bw, float& ww)
+    {
+        bw = __uint_as_float(0x7FC00000u);
+        ww = bw;
+        if (t < 0 || t >= tend) return;
+        if (t == own_t) {
+            bw = -__uint_as_float(0x7F800000u);
+            ww = bw;
+            return;
+        }
+        float b[2 * PR_DIMS];
+        load_box(crv.tbox + static_cast<size_t>(t) * 2 * PR_DIMS, b);
+        bw = box_bound(b, qlo, qhi, bb);
+        ww = box_bound(b, wlo, whi, bb);
+    }
+
+    // bound of superblock sb (NaN: none; -inf: the own tile's)
+    __device__ __forceinline__ static float sb_window(int sb, int own_sb, int nsb, const CurveArgs& crv,
+                                                      const float* qlo, const float* qhi, const BoxBound& bb)
+    {
+        if (sb < 0 || sb >= nsb) return __uint_as_float(0x7FC00000u);
+        if (sb == own_sb) return -__uint_as_float(0x7F800000u);
+        float b[2 * PR_DIMS];
+        load_box(crv.sbox + static_cast<size_t>(sb) * 2 * PR_DIMS, b);
+        return box_bound(b, qlo, qhi, bb);
     }
 
     // next tile whose workgroup bound is <= thr, or -1; wb: its wavefront bound
@@ -310,38 +342,68 @@ struct CurveScan {
                                         const float* qhi, const float* wlo, const float* whi, const BoxBound& bb,
                                         float& wb)
     {
+        constexpr int ST = SB_TILES_MFMA;
+        const int own_sb = own_t / ST, nsb = (tend + ST - 1) / ST;
+        const int lane = lane_id();
         while (cur_r < tend || cur_l >= 0) {
             if ((go_right && cur_r < tend) || cur_l < 0) {
                 go_right = false;
                 while (cur_r < tend) {
-                    if (cur_r >= rbase + WAVE) {
-                        rbase = cur_r;
-                        window(rbase, 1, own_t, tend, crv, qlo, qhi, wlo, whi, bb, rbw, rww);
+                    if (cur_r >= rt0 + WAVE) {
+                        // first superblock within reach at or after cur_r's
+                        const int sb = cur_r / ST;
+                        if (sb >= rsb0 + WAVE || sb < rsb0) {
+                            rsb0 = sb;
+                            rsbw = sb_window(rsb0 + lane, own_sb, nsb, crv, qlo, qhi, bb);
+                        }
+                        const uint64_t ms = __ballot(rsbw <= thr) & (~0ull << (sb - rsb0));
+                        if (!ms) {
+                            cur_r = (rsb0 + WAVE) * ST;
+                            continue;
+                        }
+                        const int nsbr = rsb0 + __builtin_ctzll(ms);
+                        if (nsbr != sb) cur_r = nsbr * ST;
+                        if (cur_r >= tend) break;
+                        rt0 = cur_r;
+                        tile_window(rt0 + lane, own_t, tend, crv, qlo, qhi, wlo, whi, bb, rbw, rww);
                     }
-                    const uint64_t mask = __ballot(rbw <= thr) & (~0ull << (cur_r - rbase));
-                    if (mask) {
-                        const int l = __builtin_ctzll(mask);
+                    const uint64_t m = __ballot(rbw <= thr) & (~0ull << (cur_r - rt0));
+                    if (m) {
+                        const int l = __builtin_ctzll(m);
                         wb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rww), l));
-                        cur_r = rbase + l + 1;
-                        return rbase + l;
+                        cur_r = rt0 + l + 1;
+                        return rt0 + l;
                     }
-                    cur_r = rbase + WAVE;
+                    cur_r = rt0 + WAVE;
                 }
             } else {
                 go_right = true;
                 while (cur_l >= 0) {
-                    if (cur_l <= lbase - WAVE || cur_l > lbase) {
-                        lbase = cur_l;
-                        window(lbase, -1, own_t, tend, crv, qlo, qhi, wlo, whi, bb, lbw, lww);
+                    if (cur_l <= lt0 - WAVE || cur_l > lt0) {
+                        // first superblock within reach at or before cur_l's
+                        const int sb = cur_l / ST;
+                        if (sb > lsb0 || sb <= lsb0 - WAVE) {
+                            lsb0 = sb;
+                            lsbw = sb_window(lsb0 - lane, own_sb, nsb, crv, qlo, qhi, bb);
+                        }
+                        const uint64_t ms = __ballot(lsbw <= thr) & (~0ull << (lsb0 - sb));
+                        if (!ms) {
+                            cur_l = (lsb0 - WAVE + 1) * ST - 1;
+                            continue;
+                        }
+                        const int nsbl = lsb0 - __builtin_ctzll(ms);
+                        if (nsbl != sb) cur_l = nsbl * ST + ST - 1;
+                        lt0 = cur_l;
+                        tile_window(lt0 - lane, own_t, tend, crv, qlo, qhi, wlo, whi, bb, lbw, lww);
                     }
-                    const uint64_t mask = __ballot(lbw <= thr) & (~0ull << (lbase - cur_l));
-                    if (mask) {
-                        const int l = __builtin_ctzll(mask);
+                    const uint64_t m = __ballot(lbw <= thr) & (~0ull << (lt0 - cur_l));
+                    if (m) {
+                        const int l = __builtin_ctzll(m);
                         wb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lww), l));
-                        cur_l = lbase - l - 1;
-                        return lbase - l;
+                        cur_l = lt0 - l - 1;
+                        return lt0 - l;
                     }
-                    cur_l = lbase - WAVE;
+                    cur_l = lt0 - WAVE;
                 }
             }
         }
@@ -509,13 +571,23 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
     const float* qhi = &s_qbox[WV][1][0];
     const float* wlo = &s_qbox[wave][0][0];
     const float* whi = &s_qbox[wave][1][0];
-    float yq[16];
-    CurveScan scan = {0, -1, -2 * WAVE, 0, true, 0.f, 0.f, 0.f, 0.f};
+    // |y_i|^2 of the queries for the distance thresholds: in registers, or in
+    // LDS for short contractions (measured faster there; the long ones are
+    // short of LDS instead)
+    constexpr bool YQ_LDS = KS <= 8;
+    __shared__ float s_yq[WV][NQ];
+    float yq[YQ_LDS ? 1 : 16];
+    CurveScan scan;
+    scan.init(0);
     int own_t = 0;
     BoxBound bb = {0.f, 1.f, 0.f};
     if constexpr (CURVE) {
+        if constexpr (YQ_LDS) {
+            if (lane < NQ) s_yq[wave][lane] = s_qid[wave][lane] >= 0 ? ynorm2[s_qid[wave][lane]] : 0.f;
+        } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) yq[r] = qrow[r] >= 0 ? ynorm2[qrow[r]] : 0.f;
+            for (int r = 0; r < 16; ++r) yq[r] = qrow[r] >= 0 ? ynorm2[qrow[r]] : 0.f;
+        }
 #pragma unroll
         for (int c = 0; c < PR_DIMS; ++c) {
             const bool ok = lane < NQ && q0 + lane < n;
@@ -548,9 +620,7 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
         bb.zerr = crv.zcoef * R;
         bb.pscale = *crv.pscale;
         bb.yerr = crv.ycoef * R;
-        scan.cur_r = own_t;
-        scan.cur_l = own_t - 1;
-        scan.lbase = -2 * WAVE;
+        scan.init(own_t);
     }
     __builtin_amdgcn_s_waitcnt(0);
     u32x4 pf[PF];
@@ -585,7 +655,10 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
                 float t = -__uint_as_float(0x7F800000u);
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
-                    if (qrow[r] >= 0) t = fmaxf(t, fmaxf(tauv[r] + yq[r], 0.f) * (1.f + 4.8e-7f));
+                    if (qrow[r] >= 0) {
+                        const float y2 = YQ_LDS ? s_yq[wave][acc_row(r, half)] : yq[YQ_LDS ? 0 : r];
+                        t = fmaxf(t, fmaxf(tauv[r] + y2, 0.f) * (1.f + 4.8e-7f));
+                    }
                 wthr = wave_max_f32(t);
                 thr_dirty = false;
             }
