@@ -220,15 +220,18 @@ int kvb_assemble_csr(kvb_ctx ctx, const int32_t* idx, const float* d2, const flo
  * e tuning on the density kernel over [e_min, e_max] -> density psi and
  * rho = 2 psi^beta -> grid scale s (as kvb_grid_scale with ref = b) -> e tuning
  * on the operator kernel over [s e_min, s e_max] -> q, Kt, D and the CSR of
- * out_kind (as kvb_assemble_csr). Intermediate results stay on the device and
- * the call synchronises once, at the end; results equal those of the separate
- * calls bit for bit.
+ * out_kind (as kvb_assemble_csr). Intermediate results stay on the device;
+ * results equal those of the separate calls bit for bit. With info_host
+ * non-NULL the call synchronises once, at the end; with info_host NULL it
+ * only enqueues the work on the context's stream and returns KVB_OK (argument
+ * errors are still returned at once), so that consecutive builds run back to
+ * back; kvb_build_info then waits for the last build and reports it.
  *   idx, d2, row_flags   as kvb_knn (row_flags may be NULL).
  *   b, rho [n] float32 out; psi [n] float32 out or NULL.
  *   rowptr, col, val, P, D   as kvb_assemble_csr (P, D may be NULL).
  *   chi_a_host, chi_b_host   [G] host out or NULL: the tuning sums of both stages.
- *   info_host [8] host out: e_A, dim_A, s, e_B, dim_B, g*_A, g*_B, rows that
- *                took the exact k-NN fallback.
+ *   info_host [8] host out or NULL: e_A, dim_A, s, e_B, dim_B, g*_A, g*_B, rows
+ *                that took the exact k-NN fallback.
  * Returns KVB_W_GRID_EDGE if either optimum lies at the edge of its grid,
  * else KVB_W_FALLBACK if some rows took the fallback, else KVB_OK; errors as
  * the separate calls.
@@ -238,6 +241,11 @@ int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int3
               int32_t* idx, float* d2, int32_t* row_flags, float* b, float* rho, float* psi, int64_t* rowptr,
               int32_t* col, float* val, double* P, double* D, double* chi_a_host, double* chi_b_host,
               double* info_host);
+
+/* Wait for the context's stream and report the last kvb_build on it, as that
+ * call reports with non-NULL host arguments (chi_*_host may be NULL; info_host
+ * [8] must not). KVB_E_INVALID if the context has run no build. */
+int kvb_build_info(kvb_ctx ctx, double* chi_a_host, double* chi_b_host, double* info_host);
 
 /*
  * ---- learned partitioner (k-NN over routed candidate buckets) ----

@@ -474,7 +474,6 @@ int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int3
                 "b and rho must be non-null float32 device pointers");
     KVB_REQUIRE(ctx, aligned(rowptr) && aligned(col) && aligned(val), "rowptr, col, val must be non-null");
     KVB_REQUIRE(ctx, (P == nullptr || aligned(P)) && (D == nullptr || aligned(D)), "P and D must be aligned");
-    KVB_REQUIRE(ctx, info_host != nullptr, "info_host must be non-null");
     int rc = kvb_knn(ctx, X, n, m, k, mode, margin, idx, d2, row_flags);
     if (rc < 0) return rc;
     const int nn = static_cast<int>(n);
@@ -520,7 +519,19 @@ int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int3
         KVB_HIP(ctx, kvb::launch_assemble(idx, d2, nn, k, rho, 0.0, &bd->b.e_star, qa, out_kind, rowptr, col, val, P,
                                           D ? D : Dtmp, st));
     }
-    KVB_HIP(ctx, hipMemcpyAsync(ctx->build_host, bd, sizeof(BuildDev), hipMemcpyDeviceToHost, st));
+    ctx->build_G = G;
+    if (!info_host) return KVB_OK;
+    return kvb_build_info(ctx, chi_a_host, chi_b_host, info_host);
+}
+
+int kvb_build_info(kvb_ctx ctx, double* chi_a_host, double* chi_b_host, double* info_host)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, info_host != nullptr, "info_host must be non-null");
+    const int G = ctx->build_G;
+    KVB_REQUIRE(ctx, G > 0, "no build has run on this context");
+    hipStream_t st = ctx->stream;
+    KVB_HIP(ctx, hipMemcpyAsync(ctx->build_host, ctx->build_dev, sizeof(BuildDev), hipMemcpyDeviceToHost, st));
     KVB_HIP(ctx, hipMemcpyAsync(ctx->fb_count_host, ctx->fb_count_dev, sizeof(int), hipMemcpyDeviceToHost, st));
     KVB_HIP(ctx, hipStreamSynchronize(st));
     const BuildDev& h = *ctx->build_host;
@@ -553,6 +564,12 @@ int kvb_profile_enable(kvb_ctx ctx, int32_t on)
         ctx->prof_count[s] = 0;
     }
     ctx->prof_on = on != 0;
+    // events are created up front, not while timed work is being enqueued
+    while (ctx->prof_on && ctx->ev_pool.size() < 512) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) break;
+        ctx->ev_pool.push_back(e);
+    }
     return KVB_OK;
 }
 

@@ -32,8 +32,8 @@ MODES = {"f32": KNN_F32, "bf16": KNN_BF16, "learned": KNN_LEARNED}
 
 EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb_knn",
            "kvb_knn_fallback_rows", "kvb_knn_pairs", "kvb_knn_exact_rows", "kvb_bandwidth",
-           "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_build", "kvb_part_init", "kvb_part_teacher",
-           "kvb_part_train", "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
+           "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_build", "kvb_build_info", "kvb_part_init",
+           "kvb_part_teacher", "kvb_part_train", "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
            "kvb_mlp_backward", "kvb_part_num_params", "kvb_part_get_params", "kvb_part_set_params",
            "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name")
 PROF_SLOTS = 12
@@ -76,6 +76,7 @@ def load_library(path: str = LIB_PATH):
                                    _vp, _vp, _vp, _vp, _vp]
     L.kvb_build.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64, _i32, _i32,
                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.kvb_build_info.argtypes = [_vp, _vp, _vp, _vp]
     _u64, _f32 = ctypes.c_uint64, ctypes.c_float
     L.kvb_part_init.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32, _u64]
     L.kvb_part_teacher.argtypes = [_vp, _vp, _i64, _i32, _i32, _u64, _vp]
@@ -98,7 +99,7 @@ def load_library(path: str = LIB_PATH):
                  "kvb_knn_pairs",
                  "kvb_bandwidth",
                  "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_profile_enable",
-                 "kvb_profile_read", "kvb_build", "kvb_part_init", "kvb_part_teacher", "kvb_part_train",
+                 "kvb_profile_read", "kvb_build", "kvb_build_info", "kvb_part_init", "kvb_part_teacher", "kvb_part_train",
                  "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
                  "kvb_mlp_backward", "kvb_part_get_params", "kvb_part_set_params"):
         getattr(L, name).restype = ctypes.c_int
@@ -316,10 +317,12 @@ class KernelMatrix:
 
 def build(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float, e_min: float = 1e-3,
           e_max: float = 1e1, G: int = 64, mode: str = "f32", margin: int = 32, out_kind: int = OUT_MARKOV,
-          ctx: Context | None = None, out: KernelMatrix | None = None) -> KernelMatrix:
+          ctx: Context | None = None, out: KernelMatrix | None = None, sync: bool = True) -> KernelMatrix:
     """The whole build in one library call (kvb_build): the same steps and results
     as build_kernel_matrix, with the intermediate values kept on the device.
-    `out` (a previous result of the same n and k) lends its device arrays."""
+    `out` (a previous result of the same n and k) lends its device arrays.
+    sync=False only enqueues the work (the tuning results of the returned
+    matrix are then None; build_info(ctx) waits and returns them)."""
     ctx = ctx or context()
     X = _dev(X, torch.float32, "X")
     n, m = X.shape
@@ -342,14 +345,35 @@ def build(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float,
     chi_a = np.zeros(G, dtype=np.float64)
     chi_b = np.zeros(G, dtype=np.float64)
     info = np.zeros(8, dtype=np.float64)
+    host = (chi_a.ctypes.data_as(_vp), chi_b.ctypes.data_as(_vp), info.ctypes.data_as(_vp)) if sync else \
+        (None, None, None)
     ctx.check(ctx.lib.kvb_build(ctx.h, _ptr(X), n, m, k, MODES[mode], margin, k0, d, alpha, beta, e_min, e_max, G,
                                 out_kind, _ptr(idx), _ptr(d2), _ptr(flags), _ptr(b), _ptr(rho), _ptr(psi),
-                                _ptr(rowptr), _ptr(col), _ptr(val), _ptr(P), _ptr(D), chi_a.ctypes.data_as(_vp),
-                                chi_b.ctypes.data_as(_vp), info.ctypes.data_as(_vp)))
+                                _ptr(rowptr), _ptr(col), _ptr(val), _ptr(P), _ptr(D), *host))
+    if not sync:
+        return KernelMatrix(idx, d2, flags, b, None, rho, psi, None, None, rowptr, col, val, P, D)
+    ta, s, tb = _tunings(chi_a, chi_b, info, G)
+    return KernelMatrix(idx, d2, flags, b, ta, rho, psi, s, tb, rowptr, col, val, P, D)
+
+
+def _tunings(chi_a, chi_b, info, G):
     ga, gb = int(info[5]), int(info[6])
     ta = Tuning(chi_a, float(info[0]), float(info[1]), ga in (0, G - 2))
     tb = Tuning(chi_b, float(info[3]), float(info[4]), gb in (0, G - 2))
-    return KernelMatrix(idx, d2, flags, b, ta, rho, psi, float(info[2]), tb, rowptr, col, val, P, D)
+    return ta, float(info[2]), tb
+
+
+def build_info(G: int = 64, ctx: Context | None = None):
+    """Wait for the last build on the context: (tuning A, grid scale, tuning B,
+    rows that took the exact fallback)."""
+    ctx = ctx or context()
+    chi_a = np.zeros(256, dtype=np.float64)   # the library's largest grid
+    chi_b = np.zeros(256, dtype=np.float64)
+    info = np.zeros(8, dtype=np.float64)
+    ctx.check(ctx.lib.kvb_build_info(ctx.h, chi_a.ctypes.data_as(_vp), chi_b.ctypes.data_as(_vp),
+                                     info.ctypes.data_as(_vp)))
+    ta, s, tb = _tunings(chi_a[:G], chi_b[:G], info, G)
+    return ta, s, tb, int(info[7])
 
 
 def build_kernel_matrix(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float,

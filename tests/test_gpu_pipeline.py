@@ -162,3 +162,31 @@ def test_single_call_build_matches_separate_calls(gpu_lib, out_kind):
     assert a.scale_b == b.scale_b
     for ta, tb in ((a.tune_a, b.tune_a), (a.tune_b, b.tune_b)):
         assert (ta.chi == tb.chi).all() and ta.e_star == tb.e_star and ta.dim == tb.dim and ta.edge == tb.edge
+
+
+def test_async_builds_back_to_back(gpu_lib):
+    """Builds enqueued without a host copy (info_host NULL) run back to back on
+    the stream, reuse their outputs, and report through kvb_build_info exactly
+    what a synchronous build reports."""
+    kvb = gpu_lib
+    w = workloads.WORKLOADS["sphere2_n2000"]
+    X = workloads.make("sphere2_n2000", seed=4)
+    Xd = torch.from_numpy(X).cuda()
+    ctx = kvb.Context()
+    with pytest.raises(kvb.KvbError) as e:
+        kvb.build_info(w.G, ctx)      # no build yet
+    assert e.value.code == kvb.E_INVALID
+    ref = kvb.build(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G, mode="f32",
+                    margin=w.margin, ctx=ctx)
+    out = None
+    for _ in range(3):
+        out = kvb.build(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G, mode="f32",
+                        margin=w.margin, ctx=ctx, out=out, sync=False)
+    assert out.tune_a is None
+    ta, s, tb, fb = kvb.build_info(w.G, ctx)
+    for name in ("idx", "d2", "b", "rho", "rowptr", "col", "val", "P", "D"):
+        assert torch.equal(getattr(ref, name), getattr(out, name)), name
+    assert s == ref.scale_b and fb == kvb.knn_fallback_rows(ctx)
+    for x, y in ((ta, ref.tune_a), (tb, ref.tune_b)):
+        assert (x.chi == y.chi).all() and x.e_star == y.e_star and x.dim == y.dim and x.edge == y.edge
+    ctx.close()
