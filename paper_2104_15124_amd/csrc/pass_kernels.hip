@@ -101,7 +101,7 @@ __device__ __forceinline__ double grid_log(double lo, double hi, int G, int g)
 {
     return lo + (static_cast<double>(g) * (hi - lo)) / static_cast<double>(G - 1);
 }
-constexpr int CHI_MIN_ENTRIES_PER_BLOCK = 8192;
+constexpr int CHI_MIN_ENTRIES_PER_BLOCK = 4096;
 constexpr int CHI_BATCH = 4;
 constexpr int CHI_MAX_BLOCKS = 1024;
 
@@ -135,6 +135,11 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
         for (int t = 0; t < CHI_GROUP; ++t) acc[t] = 0.f;
         // CHI_BATCH entries per thread at a time (their loads and gathers in
         // flight together); the accumulation order stays entry by entry
+        // the row of entry p = i k + r is tracked incrementally (no division
+        // per entry): consecutive entries of a thread are CHI_BLOCK apart
+        const int di = CHI_BLOCK / k, dr = CHI_BLOCK % k;
+        int64_t irow = (base + threadIdx.x) / k;
+        int rcol = static_cast<int>((base + threadIdx.x) - irow * k);
         for (int64_t p0 = base + threadIdx.x; p0 < end; p0 += CHI_BATCH * CHI_BLOCK) {
             float dv[CHI_BATCH];
             int jv[CHI_BATCH];
@@ -145,7 +150,13 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
                 const bool ok = p < end;
                 dv[u] = ok ? d2[p] : 0.f;
                 jv[u] = ok ? idx[p] : 0;
-                iv[u] = ok ? p / k : 0;
+                iv[u] = ok ? irow : 0;
+                irow += di;
+                rcol += dr;
+                if (rcol >= k) {
+                    rcol -= k;
+                    ++irow;
+                }
             }
             float x[CHI_BATCH];
 #pragma unroll
