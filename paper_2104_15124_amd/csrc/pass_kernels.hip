@@ -24,7 +24,9 @@ __global__ __launch_bounds__(256) void k_adhoc_bandwidth(const float* __restrict
     b[i] = static_cast<float>(sqrt(s));
 }
 
-// Row sums of exp(-d2/(e rho_i rho_j)) with a float64 argument and exponential:
+// Row sums of exp(-d2/(e rho_i rho_j)): the argument in float64, the kernel
+// value in float32 (its relative error, about x 2^-24 at argument x, stays far
+// inside the 1e-5 entry tolerance where the terms matter), the sum in float64;
 // four rows per wavefront, 16 lanes per row (entries strided by 16), the
 // group's partial sums reduced in a fixed butterfly order. Every lane of the
 // group returns the row's sum.
@@ -53,7 +55,7 @@ __device__ __forceinline__ double row_kernel_sum16(const int32_t* __restrict__ i
         for (int u = 0; u < B; ++u) {
             if (r0 + u * RL < k) {
                 const double x = static_cast<double>(dv[u]) * inv_e_rhoi / static_cast<double>(rj[u]);
-                s += exp(-x);
+                s += static_cast<double>(expf(-static_cast<float>(x)));
             }
         }
     }
@@ -319,7 +321,8 @@ __global__ __launch_bounds__(256) void k_qpass(const int32_t* __restrict__ idx, 
     }
 }
 
-// Kt_ir = K_ir qa_i qa_j, D_i = sum_r Kt_ir (compensated), then the requested
+// Kt_ir = K_ir qa_i qa_j (K_ir in float32 as in the row sums), D_i = sum_r Kt_ir
+// (float64, compensated), then the requested
 // output kind, the row sorted by column. For KVB_OUT_SYMMETRIC this pass
 // stores Kt and the finishing pass divides by S_i S_j.
 template <int E>
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(256) void k_assemble(const int32_t* __restrict__ id
         if (r < k) {
             const int j = irow[r];
             const double x = static_cast<double>(drow[r]) * inv / static_cast<double>(rho[j]);
-            kt[s] = exp(-x) * qai * qa[j];
+            kt[s] = static_cast<double>(expf(-static_cast<float>(x))) * qai * qa[j];
             cj[s] = j;
             acc.add(kt[s]);
         }
