@@ -426,7 +426,7 @@ __device__ __noinline__ float sort_query_list(uint64_t* __restrict__ dst, int kp
 }
 
 // WV wavefronts per workgroup share every candidate stage; each wavefront owns
-// 32 queries. The first ceil(kp / 32) tiles of a scan that starts from empty
+// 32 queries. The first CAP / 32 tiles of a scan that starts from empty
 // lists are written into the lists directly and sorted once; afterwards keys
 // at or below a query's threshold collect in its LDS buffer of BUF keys, which
 // is merged into the list whenever the next tile's keys would not fit.
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
     uint32_t nonempty = 0;   // queries with buffered entries (wave-uniform)
     // lists that start empty are filled by the first tiles without merging
     bool filling = !LEARNED || ba.first;
-    const int fill_tiles = (kp + 31) / 32;
+    const int fill_tiles = CAP / 32;   // the whole list capacity: a tighter first threshold
     // MODE 2: this wavefront's largest distance threshold, an upper bound of
     // s + |y_i|^2 over its queries; recomputed only after thresholds change
     float wthr = __uint_as_float(0x7F800000u);
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
         pairs += static_cast<unsigned long long>(nq_valid) *
                  static_cast<unsigned long long>(__popcll(__ballot(valid) & 0xFFFFFFFFull));
         if (filling) {
-            // the first ceil(kp / 32) tiles go straight into the (empty) lists
+            // the first CAP / 32 tiles go straight into the (empty) lists
             const int slot = it * 32 + (lane & 31);
 #pragma unroll
             for (int r = 0; r < 16; ++r)
