@@ -174,11 +174,12 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
         need += round256(size_t(kvb::cov_partials()) * ntri * sizeof(double)) +
                 round256(size_t(m) * m * sizeof(double)) + round256((size_t(m) * kvb::PR_DIMS + 1) * sizeof(float)) +
                 round256(size_t(nn) * kvb::PR_DIMS * sizeof(float)) +
-                round256(size_t(kvb::project_blocks(nn)) * 2 * kvb::PCODE_DIMS * sizeof(float)) +
+                round256(size_t(kvb::project_blocks(nn) + 1) * 2 * kvb::PCODE_DIMS * sizeof(float)) +
                 2 * round256(size_t(nn) * sizeof(uint32_t)) + 3 * round256(size_t(nn) * sizeof(int32_t)) +
                 round256(size_t(npad32) * sizeof(int32_t)) + round256(size_t(npad32) * kvb::PR_DIMS * sizeof(float)) +
                 round256(size_t(ctiles) * 2 * kvb::PR_DIMS * sizeof(float)) +
-                round256(size_t(csb) * 2 * kvb::PR_DIMS * sizeof(float)) + round256(csort) + 512;
+                round256(size_t(csb) * 2 * kvb::PR_DIMS * sizeof(float)) + round256(csort) +
+                round256(size_t(nn) * m * sizeof(float)) + 512;
     }
     int rc = ensure_scratch(ctx, need);
     if (rc) return rc;
@@ -193,7 +194,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
     KVB_HIP(ctx, hipMemsetAsync(ctx->pairs_dev, 0, sizeof(unsigned long long), ctx->stream));
     float lb_scale = 1.0f;
     int kstride = kp;
-    float* Xs = nullptr;        // direct tiles: curve-ordered samples, lists stored in that order
+    float* Xs = nullptr;        // curve-ordered samples (lists are then stored in that order)
     int32_t* perm = nullptr;
     if (direct) {
         Xs = cv.take<float>(size_t(nn) * m);
@@ -236,11 +237,11 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                 double* C = cv.take<double>(size_t(m) * m);
                 float* P = cv.take<float>(size_t(m) * kvb::PR_DIMS + 1);
                 float* z = cv.take<float>(size_t(nn) * kvb::PR_DIMS);
-                float* zpart = cv.take<float>(size_t(kvb::project_blocks(nn)) * 2 * kvb::PCODE_DIMS);
+                float* zpart = cv.take<float>(size_t(kvb::project_blocks(nn) + 1) * 2 * kvb::PCODE_DIMS);
                 uint32_t* code = cv.take<uint32_t>(nn);
                 uint32_t* scode = cv.take<uint32_t>(nn);
                 int32_t* vals = cv.take<int32_t>(nn);
-                int32_t* perm = cv.take<int32_t>(nn);
+                int32_t* order = cv.take<int32_t>(nn);
                 int32_t* pos = cv.take<int32_t>(nn);
                 int32_t* cid = cv.take<int32_t>(npad32);
                 float* zs = cv.take<float>(size_t(npad32) * kvb::PR_DIMS);
@@ -249,8 +250,12 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                 void* sort_tmp = cv.take<char>(csort);
                 KVB_HIP(ctx, kvb::launch_colmean(X, nn, m, colpart, colblocks, mu, ctx->stream));
                 KVB_HIP(ctx, kvb::launch_principal_basis(X, nn, m, mu, covpart, C, P, ctx->stream));
-                KVB_HIP(ctx, kvb::launch_curve_order(X, nn, m, mu, P, z, zpart, code, scode, vals, perm, sort_tmp,
+                KVB_HIP(ctx, kvb::launch_curve_order(X, nn, m, mu, P, z, zpart, code, scode, vals, order, sort_tmp,
                                                      csort, pos, cid, zs, tbox, sbox, ctx->stream));
+                // curve-ordered copy of the samples for the refine step
+                Xs = cv.take<float>(size_t(nn) * m);
+                KVB_HIP(ctx, kvb::launch_gather_rows(X, nn, m, cid, Xs, ctx->stream));
+                perm = cid;
                 // the padding rows of the last tile hold zeros (their keys are never taken)
                 const size_t tile_bytes = size_t(32) * kpad * esz;
                 KVB_HIP(ctx, hipMemsetAsync(static_cast<char*>(Bc) + size_t(ctiles - 1) * tile_bytes, 0, tile_bytes,

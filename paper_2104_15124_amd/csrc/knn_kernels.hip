@@ -500,7 +500,7 @@ __device__ __forceinline__ void group_distances(const float* __restrict__ X, int
 // common case after the direct tiles, whose float32 scores differ from the
 // compensated distances only in the last bits) skip the sorting network.
 //
-// CV (direct tiles): lists and bounds are stored by curve position r, their
+// CV (curve-ordered scans): lists and bounds are stored by curve position r, their
 // keys hold curve positions; the candidates are read from the curve-ordered
 // copy Xs (neighbouring rows read neighbouring samples) and the keys are
 // turned into (distance, sample id) through perm before any ordering.
@@ -552,14 +552,17 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
         double dd[E];
 #pragma unroll
         for (int s = 0; s < E; ++s) dd[s] = 0.0;
-        const bool vec4 = (m % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
-        group_distances<E, LPC>(X, m, i, kp, vec4, v, dd);
+        const float* Xr = CV ? Xs : X;   // the rows the keys refer to
+        const bool vec4 = (m % 4 == 0) && ((reinterpret_cast<uintptr_t>(Xr) & 15) == 0);
+        group_distances<E, LPC>(Xr, m, r, kp, vec4, v, dd);
 #pragma unroll
         for (int s = 0; s < E; ++s) {
             uint64_t key = v[s];
             if (key != KEY_INF) {
                 const uint32_t j = key_idx(key);
-                key = static_cast<int>(j) == i ? KEY_INF : make_key(static_cast<float>(dd[s]), j);
+                key = static_cast<int>(j) == r
+                          ? KEY_INF
+                          : make_key(static_cast<float>(dd[s]), CV ? static_cast<uint32_t>(perm[j]) : j);
             }
             v[s] = key;
         }
@@ -1070,28 +1073,36 @@ hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstrid
                          int* fb_count, int* fb_list, float* fb_bound, int force_period, const float* Xs,
                          const int32_t* perm, hipStream_t st)
 {
-    // curve-ordered lists (direct tiles, m <= 8); otherwise rows of up to 24
-    // floats stay with one lane per candidate, longer rows are read by groups
-    // of lanes (each lane covers at most 4 float4 pieces)
-    if (perm) {
-        if (m > 24) return hipErrorInvalidValue;
-        launch_refine_l<0, true>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                                 fb_bound, force_period, Xs, perm, st);
-    } else if (m <= 24) {
-        launch_refine_l<0, false>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                                  fb_bound, force_period, nullptr, nullptr, st);
-    } else if (m <= 64) {
-        launch_refine_l<16, false>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                                   fb_bound, force_period, nullptr, nullptr, st);
-    } else if (m <= 128) {
-        launch_refine_l<32, false>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                                   fb_bound, force_period, nullptr, nullptr, st);
-    } else if (m <= 1024) {
-        launch_refine_l<64, false>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count, fb_list,
-                                   fb_bound, force_period, nullptr, nullptr, st);
-    } else {
+    // rows of up to 24 floats stay with one lane per candidate; longer rows are
+    // read by groups of lanes (each lane covers at most 4 float4 pieces)
+#define KVB_REFINE(LPC)                                                                                              \
+    do {                                                                                                              \
+        if (perm)                                                                                                     \
+            launch_refine_l<LPC, true>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count,     \
+                                       fb_list, fb_bound, force_period, Xs, perm, st);                                \
+        else                                                                                                          \
+            launch_refine_l<LPC, false>(X, n, m, k, kp, kstride, keys, slast, lb_scale, idx, d2, flags, fb_count,    \
+                                        fb_list, fb_bound, force_period, nullptr, nullptr, st);                       \
+    } while (0)
+    if (m <= 24)
+        KVB_REFINE(0);
+    else if (m <= 64)
+        KVB_REFINE(16);
+    else if (m <= 128)
+        KVB_REFINE(32);
+    else if (m <= 1024)
+        KVB_REFINE(64);
+    else
         return hipErrorInvalidValue;
-    }
+#undef KVB_REFINE
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const float* X, int n, int m, const int32_t* perm, float* Xs, hipStream_t st)
+{
+    const int64_t tot = static_cast<int64_t>(n) * m;
+    hipLaunchKernelGGL(k_gather_rows, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st, X, n, m, perm,
+                       Xs);
     return hipGetLastError();
 }
 

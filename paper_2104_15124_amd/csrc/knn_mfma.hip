@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
             }
         }
         if (real && lane == 0) {
-            ynorm2[i] = static_cast<float>(nrm);
+            ynorm2[ia] = static_cast<float>(nrm);   // by query operand row
             wmax = fmaxf(wmax, static_cast<float>(sqrt(nrm) * (1.0 + 1e-6)));
         }
     }
@@ -443,7 +443,10 @@ __device__ __noinline__ float sort_query_list(uint64_t* __restrict__ dst, int kp
 //
 // MODE 2 (curve order): operands are laid out in the Morton order of the
 // samples' principal projections (spatial_mfma.hip); curve position p holds
-// sample crv.perm[p]. A workgroup's queries are consecutive positions; it scans
+// sample crv.perm[p]. Queries, candidate keys, lists and bounds all refer to
+// curve positions (the refine step maps them to sample ids while it reads the
+// candidates from a curve-ordered copy of the samples). A workgroup's queries
+// are consecutive positions; it scans
 // tiles outward from its own along the curve and skips every tile (or, where
 // the scan enters one, every superblock of SB_TILES_MFMA tiles) whose
 // projected box is farther from the workgroup's query box than the largest
@@ -513,7 +516,7 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
     } else if constexpr (CURVE) {
         q0 = (xcd_block() * WV + wave) * NQ;
         tend = (n + 31) / 32;
-        if (lane < NQ) s_qid[wave][lane] = q0 + lane < n ? crv.perm[q0 + lane] : -1;
+        if (lane < NQ) s_qid[wave][lane] = q0 + lane < n ? q0 + lane : -1;   // curve positions
     } else {
         q0 = (blockIdx.x * WV + wave) * NQ;
         tend = (n + 31) / 32;
@@ -638,7 +641,7 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
             if (ch < CHUNKS) pf[u] = g[ch];
         }
         if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(tile) * 32 + (lane & 31)];
-        if constexpr (CURVE) cid_pf = crv.perm[static_cast<size_t>(tile) * 32 + (lane & 31)];
+        if constexpr (CURVE) cid_pf = tile * 32 + (lane & 31) < n ? tile * 32 + (lane & 31) : -1;
     }
     uint32_t nonempty = 0;   // queries with buffered entries (wave-uniform)
     // lists that start empty are filled by the first tiles without merging
@@ -694,7 +697,7 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
                 if (ch < CHUNKS) pf[u] = g[ch];
             }
             if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(next) * 32 + (lane & 31)];
-            if constexpr (CURVE) cid_pf = crv.perm[static_cast<size_t>(next) * 32 + (lane & 31)];
+            if constexpr (CURVE) cid_pf = next * 32 + (lane & 31) < n ? next * 32 + (lane & 31) : -1;
         }
         // MODE 2, after the fill: a tile the workgroup scans may still lie
         // beyond this wavefront's own box and thresholds

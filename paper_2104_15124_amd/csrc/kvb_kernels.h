@@ -80,6 +80,8 @@ struct FallbackWork {
     int* bj;             // [rows_cap * FB_CAP] sample ids
 };
 int fallback_rows_cap(int n);
+// Xs[p] = X[perm[p]] (rows of m floats, p < n)
+hipError_t launch_gather_rows(const float* X, int n, int m, const int32_t* perm, float* Xs, hipStream_t st);
 hipError_t launch_fallback(const float* X, int n, int m, int k, const int* fb_count, const int* fb_list,
                            const FallbackWork& fw, int32_t* idx, float* d2, hipStream_t st);
 hipError_t launch_exact_rows(const float* X, int n, int m, int k, const int* rows, int nrows, int32_t* idx, float* d2,
@@ -107,6 +109,7 @@ size_t curve_sort_bytes(int n);
 // P [m * PR_DIMS + 1]: the basis, then the scale factor of CurveArgs::pscale
 hipError_t launch_principal_basis(const float* X, int n, int m, const double* mu, double* part, double* C, float* P,
                                   hipStream_t st);
+// zpart [(project_blocks(n) + 1) * 2 * PCODE_DIMS]: block partials, then the reduced range
 hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, const float* P, float* z, float* zpart,
                               uint32_t* code, uint32_t* scode, int32_t* vals, int32_t* perm, void* sort_tmp,
                               size_t sort_bytes, int32_t* pos, int32_t* cid, float* zs, float* tbox, float* sbox,

@@ -211,19 +211,53 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ X, in
     }
 }
 
-// Morton code of the first PCODE projected coordinates, 8 bits each, over the
-// range of the block partials; value = sample index (stable sort: ties by index).
-__global__ __launch_bounds__(256) void k_zcodes(const float* __restrict__ z, int n, const float* __restrict__ zpart,
-                                                int nparts, uint32_t* __restrict__ code, int32_t* __restrict__ vals)
+// Range of the first PCODE projected coordinates from the block partials (one
+// block): zr = [lo, hi] per coordinate.
+__global__ __launch_bounds__(256) void k_zrange(const float* __restrict__ zpart, int nparts, float* __restrict__ zr)
+{
+    __shared__ float slo[PCODE_DIMS][256], shi[PCODE_DIMS][256];
+    float lo[PCODE_DIMS], hi[PCODE_DIMS];
+#pragma unroll
+    for (int c = 0; c < PCODE_DIMS; ++c) {
+        lo[c] = __uint_as_float(0x7F800000u);
+        hi[c] = -__uint_as_float(0x7F800000u);
+    }
+    for (int b = threadIdx.x; b < nparts; b += 256)
+#pragma unroll
+        for (int c = 0; c < PCODE_DIMS; ++c) {
+            lo[c] = fminf(lo[c], zpart[static_cast<size_t>(b) * 2 * PCODE_DIMS + c]);
+            hi[c] = fmaxf(hi[c], zpart[static_cast<size_t>(b) * 2 * PCODE_DIMS + PCODE_DIMS + c]);
+        }
+#pragma unroll
+    for (int c = 0; c < PCODE_DIMS; ++c) {
+        slo[c][threadIdx.x] = lo[c];
+        shi[c][threadIdx.x] = hi[c];
+    }
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+#pragma unroll
+            for (int c = 0; c < PCODE_DIMS; ++c) {
+                slo[c][threadIdx.x] = fminf(slo[c][threadIdx.x], slo[c][threadIdx.x + o]);
+                shi[c][threadIdx.x] = fmaxf(shi[c][threadIdx.x], shi[c][threadIdx.x + o]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < PCODE_DIMS) {
+        zr[threadIdx.x] = slo[threadIdx.x][0];
+        zr[PCODE_DIMS + threadIdx.x] = shi[threadIdx.x][0];
+    }
+}
+
+// Morton code of the first PCODE projected coordinates, 8 bits each, over
+// their range zr; value = sample index (stable sort: ties by index).
+__global__ __launch_bounds__(256) void k_zcodes(const float* __restrict__ z, int n, const float* __restrict__ zr,
+                                                uint32_t* __restrict__ code, int32_t* __restrict__ vals)
 {
     __shared__ float s_lo[PCODE_DIMS], s_scale[PCODE_DIMS];
     if (threadIdx.x < PCODE_DIMS) {
         const int c = threadIdx.x;
-        float lo = __uint_as_float(0x7F800000u), hi = -__uint_as_float(0x7F800000u);
-        for (int b = 0; b < nparts; ++b) {
-            lo = fminf(lo, zpart[static_cast<size_t>(b) * 2 * PCODE_DIMS + c]);
-            hi = fmaxf(hi, zpart[static_cast<size_t>(b) * 2 * PCODE_DIMS + PCODE_DIMS + c]);
-        }
+        const float lo = zr[c], hi = zr[PCODE_DIMS + c];
         s_lo[c] = lo;
         s_scale[c] = hi > lo ? 256.f / (hi - lo) : 0.f;
     }
@@ -314,7 +348,9 @@ hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, co
 {
     const int nb = project_blocks(n);
     hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, st, X, n, m, mu, P, z, zpart);
-    hipLaunchKernelGGL(k_zcodes, dim3(nb), dim3(256), 0, st, z, n, zpart, nb, code, vals);
+    float* zr = zpart + static_cast<size_t>(nb) * 2 * PCODE_DIMS;   // one more partial's room
+    hipLaunchKernelGGL(k_zrange, dim3(1), dim3(256), 0, st, zpart, nb, zr);
+    hipLaunchKernelGGL(k_zcodes, dim3(nb), dim3(256), 0, st, z, n, zr, code, vals);
     size_t tb = sort_bytes;
     hipError_t e = rocprim::radix_sort_pairs(sort_tmp, tb, code, scode, vals, perm, static_cast<size_t>(n), 0u,
                                              8u * PCODE_DIMS, st);
