@@ -152,8 +152,10 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                   round256(size_t(nn) * sizeof(float)) + round256(size_t(nn) * sizeof(int)) + fallback_bytes(nn) +
                   2048;
     size_t sort_bytes = 0;
+    const int code_bits = direct ? m * kvb::spatial_code_bits(nn, m) : 32;
     if (direct)
-        KVB_HIP(ctx, kvb::sort_pairs_u32(nullptr, sort_bytes, nullptr, nullptr, nullptr, nullptr, nn, 32, ctx->stream));
+        KVB_HIP(ctx, kvb::sort_pairs_u32(nullptr, sort_bytes, nullptr, nullptr, nullptr, nullptr, nn, code_bits,
+                                         ctx->stream));
     const int ntiles = kvb::spatial_tiles(nn), nsb = kvb::spatial_superblocks(nn);
     if (direct)
         need += round256(size_t(nn) * m * sizeof(float)) + 2 * round256(size_t(nn) * sizeof(int32_t)) +
@@ -210,7 +212,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
             Prof pr(ctx, KVB_PROF_KNN_PREP);
             KVB_HIP(ctx, kvb::launch_spatial_codes(X, nn, m, bbox, code, vals, ctx->stream));
             size_t sb = sort_bytes;
-            KVB_HIP(ctx, kvb::sort_pairs_u32(sort_tmp, sb, code, scode, vals, perm, nn, 32, ctx->stream));
+            KVB_HIP(ctx, kvb::sort_pairs_u32(sort_tmp, sb, code, scode, vals, perm, nn, code_bits, ctx->stream));
             KVB_HIP(ctx, kvb::launch_spatial_layout(X, nn, m, perm, Xs, tbox, sbox, ctx->stream));
         }
         Prof pr(ctx, KVB_PROF_KNN_SELECT);

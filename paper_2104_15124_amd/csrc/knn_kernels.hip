@@ -320,12 +320,11 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const float* __restrict__ 
 // over the bounding box (the box partials are reduced here, redundantly per
 // thread: at most 1024 partials of 2m values), bits interleaved from the most
 // significant. value = sample index, so a stable sort breaks ties by index.
-__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ X, int n, int m,
+__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ X, int n, int m, int bits,
                                                 const float* __restrict__ part, int nparts,
                                                 uint32_t* __restrict__ code, int32_t* __restrict__ vals)
 {
     __shared__ float s_lo[8], s_scale[8];
-    const int bits = min(31, 32 / m);
     if (threadIdx.x < m) {
         const int c = threadIdx.x;
         float lo = __uint_as_float(0x7F800000u), hi = -__uint_as_float(0x7F800000u);
@@ -994,14 +993,25 @@ int spatial_bbox_blocks(int n) { return std::max(1, std::min(1024, (n + 4095) / 
 int spatial_tiles(int n) { return (n + TILE - 1) / TILE; }
 int spatial_superblocks(int n) { return (spatial_tiles(n) + SB_TILES - 1) / SB_TILES; }
 
+// Bits per coordinate of the Morton code: enough cells for a few samples each
+// (the tiles stay compact; finer codes only lengthen the sort), at most 32 in all.
+int spatial_code_bits(int n, int m)
+{
+    int lg = 0;
+    while ((1ll << lg) < static_cast<long long>(n)) ++lg;
+    const int want = std::max(8, (lg + m - 1) / m + 2);
+    return std::min(std::min(31, 32 / m), want);
+}
+
 hipError_t launch_spatial_codes(const float* X, int n, int m, float* bbox_part, uint32_t* code, int32_t* vals,
                                 hipStream_t st)
 {
     if (m < 1 || m > 8) return hipErrorInvalidValue;
+    const int bits = spatial_code_bits(n, m);
     const int nb = spatial_bbox_blocks(n);
     const int rpb = (n + nb - 1) / nb;
     hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(256), 0, st, X, n, m, rpb, bbox_part);
-    hipLaunchKernelGGL(k_morton, dim3((n + 255) / 256), dim3(256), 0, st, X, n, m, bbox_part, nb, code, vals);
+    hipLaunchKernelGGL(k_morton, dim3((n + 255) / 256), dim3(256), 0, st, X, n, m, bits, bbox_part, nb, code, vals);
     return hipGetLastError();
 }
 

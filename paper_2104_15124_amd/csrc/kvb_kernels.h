@@ -58,6 +58,7 @@ struct TuneResult {
 int spatial_bbox_blocks(int n);
 int spatial_tiles(int n);
 int spatial_superblocks(int n);
+int spatial_code_bits(int n, int m);   // the code has m * spatial_code_bits(n, m) bits
 hipError_t launch_spatial_codes(const float* X, int n, int m, float* bbox_part, uint32_t* code, int32_t* vals,
                                 hipStream_t st);
 hipError_t launch_spatial_layout(const float* X, int n, int m, const int32_t* perm, float* Xs, float* tbox,
