@@ -216,7 +216,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
             KVB_HIP(ctx, kvb::launch_spatial_layout(X, nn, m, perm, Xs, tbox, sbox, ctx->stream));
         }
         Prof pr(ctx, KVB_PROF_KNN_SELECT);
-        KVB_HIP(ctx, kvb::launch_select_direct(Xs, perm, tbox, sbox, nn, m, kp, keys, slast, ctx->pairs_dev,
+        KVB_HIP(ctx, kvb::launch_select_direct(Xs, tbox, sbox, nn, m, kp, keys, slast, ctx->pairs_dev,
                                                ctx->stream));
         // the direct tiles compute each squared distance with at most (m + 2)
         // float32 roundings; (m + 4) 2^-23 bounds their relative error with a

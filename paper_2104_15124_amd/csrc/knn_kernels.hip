@@ -44,11 +44,11 @@ namespace kvb {
 //
 // Candidates passing the current threshold of a row are appended to a
 // 64-entry LDS buffer; a full buffer is merged into the row's register list by
-// a bitonic network, which also tightens the threshold. Keys carry the
-// sample's original index, so ties order as in I(x, k).
+// a bitonic network, which also tightens the threshold. Keys carry curve
+// positions; the re-rank maps them to original indices and breaks ties on
+// those, so ties order as in I(x, k).
 struct SpatialView {
     const float* Xs;      // [n, m] coordinates in curve order
-    const int* perm;      // [n] original index of each curve position
     const float* tbox;    // [tiles, 2, m]: lower corner, then upper corner
     const float* sbox;    // [superblocks, 2, m]
 };
@@ -1043,10 +1043,10 @@ static hipError_t launch_select_m(const SpatialView& sv, int n, int kp, uint64_t
     return hipGetLastError();
 }
 
-hipError_t launch_select_direct(const float* Xs, const int32_t* perm, const float* tbox, const float* sbox, int n,
-                                int m, int kp, uint64_t* keys, float* slast, unsigned long long* pairs, hipStream_t st)
+hipError_t launch_select_direct(const float* Xs, const float* tbox, const float* sbox, int n, int m, int kp,
+                                uint64_t* keys, float* slast, unsigned long long* pairs, hipStream_t st)
 {
-    const SpatialView sv = {Xs, perm, tbox, sbox};
+    const SpatialView sv = {Xs, tbox, sbox};
     switch (m) {
     case 1: return launch_select_m<1, 4>(sv, n, kp, keys, slast, pairs, st);
     case 2: return launch_select_m<2, 4>(sv, n, kp, keys, slast, pairs, st);

@@ -63,8 +63,9 @@ hipError_t launch_spatial_codes(const float* X, int n, int m, float* bbox_part, 
                                 hipStream_t st);
 hipError_t launch_spatial_layout(const float* X, int n, int m, const int32_t* perm, float* Xs, float* tbox,
                                  float* sbox, hipStream_t st);
-hipError_t launch_select_direct(const float* Xs, const int32_t* perm, const float* tbox, const float* sbox, int n,
-                                int m, int kp, uint64_t* keys, float* slast, unsigned long long* pairs, hipStream_t st);
+// lists [n, kp] and bounds [n] stored by curve position; keys hold curve positions
+hipError_t launch_select_direct(const float* Xs, const float* tbox, const float* sbox, int n, int m, int kp,
+                                uint64_t* keys, float* slast, unsigned long long* pairs, hipStream_t st);
 hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstride, const uint64_t* keys,
                          const float* slast, float lb_scale, int32_t* idx, float* d2, int32_t* flags,
                          int* fb_count, int* fb_list, float* fb_bound, int force_period, const float* Xs,
