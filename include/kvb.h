@@ -214,6 +214,50 @@ int kvb_assemble_csr(kvb_ctx ctx, const int32_t* idx, const float* d2, const flo
                      int64_t n, int32_t k, double e, double alpha, double d, int32_t out_kind,
                      int64_t* rowptr, int32_t* col, float* val, double* P, double* D);
 
+/* ---- the union pattern E u E^T ----
+ * The paper's kernel matrix is symmetric: its brute-force construction sets
+ * K_ij and K_ji together (Section 4, Algorithm 1). A directed k-NN pattern is
+ * not; its union with its transpose is. These calls build that pattern and run
+ * the density, tuning and normalisation passes over any CSR pattern (row sums
+ * then run over the stored row, whatever its length).
+ *
+ * kvb_union_pattern: row i of the output holds every j with j in row i of idx
+ * or i in row j of idx, once, columns ascending; ud2 carries the squared
+ * distance of the pair, taken from row i of d2 where (i, j) is stored there,
+ * else from row j.
+ *   idx [n k] int32, d2 [n k] float32 in: a k-NN pattern as written by kvb_knn
+ *     (each row k distinct columns in [0, n)); 1 <= k <= 256.
+ *   rowptr [n+1] int64 out (rowptr[0] = 0, rowptr[n] = nnz);
+ *   col [cap] int32 out, ud2 [cap] float32 out: the first nnz entries are written.
+ *     cap = n (2k - 1) always suffices; nnz <= cap is required.
+ *   nnz_host: host out (required).
+ * The result is deterministic. Scratch grows by about 36 bytes per directed entry.
+ * Synchronises the context stream (once, to size the transpose). KVB_E_INVALID
+ * for a repeated column or a column outside [0, n) in a row of idx, or for
+ * cap < nnz (the outputs are then unspecified, *nnz_host is set).
+ */
+int kvb_union_pattern(kvb_ctx ctx, const int32_t* idx, const float* d2, int64_t n, int32_t k,
+                      int64_t* rowptr, int32_t* col, float* ud2, int64_t cap, int64_t* nnz_host);
+
+/*
+ * The passes of kvb_bandwidth (KVB_BW_DENSITY), kvb_tune_eps and
+ * kvb_assemble_csr over a CSR pattern with nnz entries: rowptr [n+1] int64
+ * (rowptr[0] = 0, non-decreasing, rowptr[n] = nnz), col [nnz] int32 in
+ * [0, n), ud2 [nnz] float32 squared distances. Same formulas, with r running
+ * over the stored entries of row i. kvb_normalize_csr writes val [nnz] float32
+ * in pattern order (it does not reorder columns); P, D as kvb_assemble_csr.
+ * Each call checks the pattern's shape on the device and synchronises once to
+ * read the check; KVB_E_INVALID if it fails (nothing else is written then).
+ */
+int kvb_density_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* ud2, int64_t n,
+                    int64_t nnz, const float* b, double e, double d, double beta, float* rho, float* psi);
+int kvb_tune_eps_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* ud2, const float* rho,
+                     int64_t n, int64_t nnz, double e_min, double e_max, int32_t G,
+                     double* chi_host, double* e_star_host, double* dim_host);
+int kvb_normalize_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* ud2, const float* rho,
+                      int64_t n, int64_t nnz, double e, double alpha, double d, int32_t out_kind,
+                      float* val, double* P, double* D);
+
 /*
  * The whole build in one call, in the order of the paper's pipeline (Section 4
  * with the tuning of Section 2.3): k-NN (as kvb_knn) -> ad-hoc bandwidth b ->
@@ -342,7 +386,8 @@ const char* kvb_version(void);
 #define KVB_PROF_KNN_PREP 9      /* centring and operand layout for the matrix-core distance tiles */
 #define KVB_PROF_ROUTE 10        /* learned mode: MLP logits and top-n_probe routing */
 #define KVB_PROF_BUCKETS 11      /* learned mode: bucket sort, candidate operand gather, work lists */
-#define KVB_PROF_SLOTS 12
+#define KVB_PROF_UNION 12        /* union pattern: row sort, transpose count, scan, sort, merge */
+#define KVB_PROF_SLOTS 13
 
 /* Turn event timing on (on != 0) or off; either way the totals restart at 0. */
 int kvb_profile_enable(kvb_ctx ctx, int32_t on);

@@ -18,7 +18,7 @@ namespace {
 const char* const kProfNames[KVB_PROF_SLOTS] = {
     "knn_select", "knn_refine", "knn_fallback", "adhoc_bandwidth", "chi_tuning", "density",
     "grid_scale", "q_pass", "assemble", "knn_prep",
-    "route", "bucket_build",
+    "route", "bucket_build", "union_pattern",
 };
 }  // namespace
 
@@ -49,7 +49,9 @@ int kvb_create(kvb_ctx* out, void* hip_stream)
         hipHostMalloc(reinterpret_cast<void**>(&ctx->pairs_host), sizeof(unsigned long long),
                       hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&ctx->fb_count_host), sizeof(int), hipHostMallocDefault) !=
-            hipSuccess) {
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&ctx->union_host), 2 * sizeof(unsigned long long),
+                      hipHostMallocDefault) != hipSuccess) {
         kvb_destroy(ctx);
         return KVB_E_NOMEM;
     }
@@ -76,6 +78,7 @@ void kvb_destroy(kvb_ctx ctx)
     if (ctx->loss_dev) (void)hipFree(ctx->loss_dev);
     if (ctx->pairs_dev) (void)hipFree(ctx->pairs_dev);
     if (ctx->pairs_host) (void)hipHostFree(ctx->pairs_host);
+    if (ctx->union_host) (void)hipHostFree(ctx->union_host);
     part_free(ctx);
     delete ctx;
 }
@@ -459,6 +462,151 @@ int kvb_assemble_csr(kvb_ctx ctx, const int32_t* idx, const float* d2, const flo
         Prof pr(ctx, KVB_PROF_ASSEMBLE);
         KVB_HIP(ctx, kvb::launch_assemble(idx, d2, nn, k, rho, e, nullptr, qa, out_kind, rowptr, col, val, P,
                                           D ? D : Dtmp, ctx->stream));
+    }
+    return KVB_OK;
+}
+
+// ------------------------------------------------------------------ union pattern and CSR passes
+int kvb_union_pattern(kvb_ctx ctx, const int32_t* idx, const float* d2, int64_t n, int32_t k, int64_t* rowptr,
+                      int32_t* col, float* ud2, int64_t cap, int64_t* nnz_host)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
+    KVB_REQUIRE(ctx, k >= 1 && k <= 256 && k <= n, "k must be in [1, min(256, n)], got %d", k);
+    KVB_REQUIRE(ctx, aligned(idx) && aligned(d2), "idx and d2 must be non-null device pointers");
+    KVB_REQUIRE(ctx, aligned(rowptr) && aligned(col) && aligned(ud2), "rowptr, col, ud2 must be non-null");
+    KVB_REQUIRE(ctx, nnz_host != nullptr, "nnz_host must be non-null");
+    KVB_REQUIRE(ctx, cap >= 0, "cap must be >= 0");
+    const int nn = static_cast<int>(n);
+    const int64_t nk = n * k;
+    const size_t scan_bytes = kvb::union_scan_bytes(nn);
+    const size_t sort_bytes = kvb::union_sort_bytes(nk);
+    const size_t need = 2 * round256(size_t(nk) * 4) + 2 * round256(size_t(nk) * 8) + 3 * round256(size_t(nk) * 4) +
+                        round256((size_t(nn) + 1) * 4) + round256((size_t(nn) + 1) * 8) + round256(16) +
+                        round256(scan_bytes) + round256(sort_bytes) + 2048;
+    int rc = ensure_scratch(ctx, need);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    int32_t* scol = cv.take<int32_t>(nk);
+    float* sd2 = cv.take<float>(nk);
+    uint64_t* rkey = cv.take<uint64_t>(nk);
+    uint64_t* skey = cv.take<uint64_t>(nk);
+    float* rd2 = cv.take<float>(nk);
+    float* srd2 = cv.take<float>(nk);
+    int32_t* rcol = cv.take<int32_t>(nk);
+    int* cnt = cv.take<int>(size_t(nn) + 1);
+    int64_t* revptr = cv.take<int64_t>(size_t(nn) + 1);
+    unsigned long long* stats = cv.take<unsigned long long>(2);
+    void* scan_tmp = cv.take<char>(scan_bytes);
+    void* sort_tmp = cv.take<char>(sort_bytes);
+    Prof pr(ctx, KVB_PROF_UNION);
+    KVB_HIP(ctx, kvb::launch_union_count(idx, d2, nn, k, scol, sd2, cnt, stats, rkey, rd2, ctx->stream));
+    KVB_HIP(ctx, hipMemcpyAsync(ctx->union_host, stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const int64_t total = static_cast<int64_t>(ctx->union_host[0]);
+    if (ctx->union_host[1])
+        return fail(ctx, KVB_E_INVALID, "idx: a row holds a column outside [0, n) or the same column twice");
+    *nnz_host = nk + total;
+    if (cap < nk + total)
+        return fail(ctx, KVB_E_INVALID, "cap %lld is below the union's %lld entries", static_cast<long long>(cap),
+                    static_cast<long long>(nk + total));
+    KVB_HIP(ctx, kvb::launch_union_scan(scan_tmp, scan_bytes, cnt, nn, k, revptr, rowptr, ctx->stream));
+    KVB_HIP(ctx, kvb::launch_union_place(sort_tmp, sort_bytes, rkey, skey, rd2, srd2, total, scol, sd2, nn, k, revptr,
+                                         rowptr, rcol, col, ud2, ctx->stream));
+    return KVB_OK;
+}
+
+// shape check of a caller's CSR pattern (synchronises)
+static int check_pattern(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, int64_t n, int64_t nnz)
+{
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
+    KVB_REQUIRE(ctx, nnz >= 1, "nnz must be >= 1");
+    KVB_REQUIRE(ctx, aligned(rowptr) && aligned(col), "rowptr and col must be non-null device pointers");
+    int rc = ensure_scratch(ctx, 512);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    unsigned long long* bad = cv.take<unsigned long long>(1);
+    KVB_HIP(ctx, kvb::launch_check_csr(rowptr, col, static_cast<int>(n), nnz, bad, ctx->stream));
+    KVB_HIP(ctx, hipMemcpyAsync(ctx->union_host, bad, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
+    KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->union_host[0] & 1)
+        return fail(ctx, KVB_E_INVALID, "rowptr must start at 0, never decrease and end at nnz");
+    if (ctx->union_host[0] & 2) return fail(ctx, KVB_E_INVALID, "col: a column lies outside [0, n)");
+    return KVB_OK;
+}
+
+int kvb_density_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* ud2, int64_t n, int64_t nnz,
+                    const float* b, double e, double d, double beta, float* rho, float* psi)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, aligned(ud2) && aligned(b) && aligned(rho), "ud2, b, rho must be non-null device pointers");
+    KVB_REQUIRE(ctx, psi == nullptr || aligned(psi), "psi must be aligned");
+    KVB_REQUIRE(ctx, e > 0 && std::isfinite(e), "e must be finite and > 0");
+    KVB_REQUIRE(ctx, d > 0 && std::isfinite(d), "d must be finite and > 0");
+    KVB_REQUIRE(ctx, std::isfinite(beta), "beta must be finite");
+    KVB_TRY(check_pattern(ctx, rowptr, col, n, nnz));
+    Prof pr(ctx, KVB_PROF_DENSITY);
+    KVB_HIP(ctx, kvb::launch_density_csr(rowptr, col, ud2, static_cast<int>(n), b, e, nullptr, d, beta, rho, psi,
+                                         ctx->stream));
+    return KVB_OK;
+}
+
+int kvb_tune_eps_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* ud2, const float* rho,
+                     int64_t n, int64_t nnz, double e_min, double e_max, int32_t G, double* chi_host,
+                     double* e_star_host, double* dim_host)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, G >= 3 && G <= 256, "G must be in [3, 256], got %d", G);
+    KVB_REQUIRE(ctx, e_min > 0 && e_max > e_min && std::isfinite(e_max), "need 0 < e_min < e_max < inf");
+    KVB_REQUIRE(ctx, aligned(ud2) && aligned(rho), "ud2 and rho must be non-null device pointers");
+    KVB_REQUIRE(ctx, e_star_host != nullptr, "e_star_host must be non-null");
+    KVB_TRY(check_pattern(ctx, rowptr, col, n, nnz));
+    const int nb = kvb::chi_num_blocks(nnz);
+    int rc = ensure_scratch(ctx, round256(size_t(nb) * G * sizeof(double)) + 256);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    double* part = cv.take<double>(size_t(nb) * G);
+    {
+        Prof pr(ctx, KVB_PROF_CHI);
+        KVB_HIP(ctx, kvb::launch_chi_csr(rowptr, col, ud2, static_cast<int>(n), nnz, rho, G, e_min, e_max, nullptr,
+                                         part, ctx->tune_dev, ctx->stream));
+    }
+    KVB_HIP(ctx, hipMemcpyAsync(ctx->tune_host, ctx->tune_dev, sizeof(kvb::TuneResult), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const kvb::TuneResult& t = *ctx->tune_host;
+    if (chi_host) std::memcpy(chi_host, t.chi, sizeof(double) * G);
+    *e_star_host = t.e_star;
+    if (dim_host) *dim_host = t.dim;
+    return (t.g_star == 0 || t.g_star == G - 2) ? KVB_W_GRID_EDGE : KVB_OK;
+}
+
+int kvb_normalize_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* ud2, const float* rho,
+                      int64_t n, int64_t nnz, double e, double alpha, double d, int32_t out_kind, float* val,
+                      double* P, double* D)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, e > 0 && std::isfinite(e), "e must be finite and > 0");
+    KVB_REQUIRE(ctx, std::isfinite(alpha) && std::isfinite(d) && d > 0, "alpha must be finite and d > 0");
+    KVB_REQUIRE(ctx, out_kind >= KVB_OUT_MARKOV && out_kind <= KVB_OUT_SYMMETRIC, "unknown out_kind %d", out_kind);
+    KVB_REQUIRE(ctx, aligned(ud2) && aligned(rho) && aligned(val), "ud2, rho, val must be non-null device pointers");
+    KVB_REQUIRE(ctx, (P == nullptr || aligned(P)) && (D == nullptr || aligned(D)), "P and D must be aligned");
+    KVB_TRY(check_pattern(ctx, rowptr, col, n, nnz));
+    const int nn = static_cast<int>(n);
+    int rc = ensure_scratch(ctx, 2 * round256(size_t(nn) * sizeof(double)) + 256);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    double* qa = cv.take<double>(nn);
+    double* Dtmp = cv.take<double>(nn);
+    {
+        Prof pr(ctx, KVB_PROF_QPASS);
+        KVB_HIP(ctx, kvb::launch_qpass_csr(rowptr, col, ud2, nn, rho, e, nullptr, alpha, d, qa, ctx->stream));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_ASSEMBLE);
+        KVB_HIP(ctx, kvb::launch_assemble_rows(rowptr, col, ud2, nn, rho, e, nullptr, qa, out_kind, val, P,
+                                               D ? D : Dtmp, ctx->stream));
     }
     return KVB_OK;
 }

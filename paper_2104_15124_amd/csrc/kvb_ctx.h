@@ -68,6 +68,7 @@ struct kvb_ctx_s {
     int* fb_count_host = nullptr;           // pinned
     unsigned long long* pairs_dev = nullptr;   // candidate pairs scored by the last kvb_knn
     unsigned long long* pairs_host = nullptr;  // pinned
+    unsigned long long* union_host = nullptr;  // pinned [2]: reverse entries / check flags, invalid-input flag
     double* loss_dev = nullptr;             // per-epoch losses of kvb_part_train (device)
     int loss_cap = 0;
     kvbh::PartState part;

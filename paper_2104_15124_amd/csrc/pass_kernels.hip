@@ -6,7 +6,9 @@
 //
 // One wavefront owns one row for the row-wise passes (k <= 256 entries, lanes
 // strided over them), so row sums reduce inside the wavefront in a fixed
-// butterfly order and no atomics are needed.
+// butterfly order and no atomics are needed. The same passes also run over a
+// general CSR pattern (rows of any length, given by rowptr), such as the union
+// pattern E u E^T.
 #include "kvb_device.h"
 #include "kvb_kernels.h"
 
@@ -66,8 +68,19 @@ __device__ __forceinline__ double row_kernel_sum16(const int32_t* __restrict__ i
 
 // psi_i = sum_r K_ir / (n (pi e b_i^2)^{d/2}), rho_i = 2 psi_i^beta
 // (Section 2.1 density eqs.; Algorithm 1 caption)
+// Row i spans entries [rowptr_i, rowptr_{i+1}), or [i k, (i + 1) k) when rowptr is null.
+__device__ __forceinline__ int64_t row_begin(const int64_t* __restrict__ rowptr, int i, int k)
+{
+    return rowptr ? rowptr[i] : static_cast<int64_t>(i) * k;
+}
+__device__ __forceinline__ int row_length(const int64_t* __restrict__ rowptr, int i, int k)
+{
+    return rowptr ? static_cast<int>(rowptr[i + 1] - rowptr[i]) : k;
+}
+
 __global__ __launch_bounds__(256) void k_density(const int32_t* __restrict__ idx, const float* __restrict__ d2,
-                                                 int n, int k, const float* __restrict__ b, double e,
+                                                 const int64_t* __restrict__ rowptr, int n, int k,
+                                                 const float* __restrict__ b, double e,
                                                  const double* __restrict__ e_dev, double d, double beta,
                                                  float* __restrict__ rho, float* __restrict__ psi)
 {
@@ -77,8 +90,8 @@ __global__ __launch_bounds__(256) void k_density(const int32_t* __restrict__ idx
     const int gl = lane % RL;
     if (i >= n) return;   // whole lane groups
     const double bi = static_cast<double>(b[i]);
-    const double s = row_kernel_sum16(idx + static_cast<size_t>(i) * k, d2 + static_cast<size_t>(i) * k, k, b,
-                                      1.0 / (e * bi), gl);
+    const int64_t rb = row_begin(rowptr, i, k);
+    const double s = row_kernel_sum16(idx + rb, d2 + rb, row_length(rowptr, i, k), b, 1.0 / (e * bi), gl);
     if (gl == 0) {
         const double pi = 3.14159265358979323846;
         const double w = static_cast<double>(n) * pow(pi * e * bi * bi, 0.5 * d);
@@ -107,8 +120,11 @@ constexpr int CHI_MIN_ENTRIES_PER_BLOCK = 4096;
 constexpr int CHI_BATCH = 4;
 constexpr int CHI_MAX_BLOCKS = 1024;
 
+// CSR: rows given by rowptr [n + 1] (k unused); otherwise k entries per row.
+template <bool CSR>
 __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __restrict__ idx,
                                                            const float* __restrict__ d2,
+                                                           const int64_t* __restrict__ rowptr, int n,
                                                            const float* __restrict__ rho, int64_t nnz, int k,
                                                            int G, double e_min, double e_max,
                                                            const double* __restrict__ scale_dev, int64_t per_block,
@@ -139,9 +155,26 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
         // flight together); the accumulation order stays entry by entry
         // the row of entry p = i k + r is tracked incrementally (no division
         // per entry): consecutive entries of a thread are CHI_BLOCK apart
-        const int di = CHI_BLOCK / k, dr = CHI_BLOCK % k;
-        int64_t irow = (base + threadIdx.x) / k;
-        int rcol = static_cast<int>((base + threadIdx.x) - irow * k);
+        const int di = CSR ? 0 : CHI_BLOCK / k, dr = CSR ? 0 : CHI_BLOCK % k;
+        int64_t irow, rend = 0;
+        int rcol = 0;
+        if (CSR) {
+            // the row holding the thread's first entry: last i with rowptr_i <= p
+            const int64_t p = min(base + threadIdx.x, nnz - 1);
+            int lo = 0, hi = n;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (rowptr[mid] <= p)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            irow = lo;
+            rend = rowptr[lo + 1];
+        } else {
+            irow = (base + threadIdx.x) / k;
+            rcol = static_cast<int>((base + threadIdx.x) - irow * k);
+        }
         for (int64_t p0 = base + threadIdx.x; p0 < end; p0 += CHI_BATCH * CHI_BLOCK) {
             float dv[CHI_BATCH];
             int jv[CHI_BATCH];
@@ -152,12 +185,23 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
                 const bool ok = p < end;
                 dv[u] = ok ? d2[p] : 0.f;
                 jv[u] = ok ? idx[p] : 0;
-                iv[u] = ok ? irow : 0;
-                irow += di;
-                rcol += dr;
-                if (rcol >= k) {
-                    rcol -= k;
-                    ++irow;
+                if (CSR) {
+                    // p < nnz = rowptr_n, so the walk stops at a row below n
+                    if (ok) {
+                        while (p >= rend) {
+                            ++irow;
+                            rend = rowptr[irow + 1];
+                        }
+                    }
+                    iv[u] = ok ? irow : 0;
+                } else {
+                    iv[u] = ok ? irow : 0;
+                    irow += di;
+                    rcol += dr;
+                    if (rcol >= k) {
+                        rcol -= k;
+                        ++irow;
+                    }
                 }
             }
             float x[CHI_BATCH];
@@ -301,8 +345,9 @@ __global__ __launch_bounds__(256) void k_logsum_finish(const double* __restrict_
 
 // ------------------------------------------------------------------ normalisation
 // q_i = P_i^{-d} sum_r K_ir, P_i = rho_i/2; stores qa_i = q_i^{-alpha} (Section 2.2)
-__global__ __launch_bounds__(256) void k_qpass(const int32_t* __restrict__ idx, const float* __restrict__ d2, int n,
-                                               int k, const float* __restrict__ rho, double e,
+__global__ __launch_bounds__(256) void k_qpass(const int32_t* __restrict__ idx, const float* __restrict__ d2,
+                                               const int64_t* __restrict__ rowptr, int n, int k,
+                                               const float* __restrict__ rho, double e,
                                                const double* __restrict__ e_dev, double alpha, double d,
                                                double* __restrict__ qa)
 {
@@ -312,8 +357,8 @@ __global__ __launch_bounds__(256) void k_qpass(const int32_t* __restrict__ idx, 
     const int gl = lane % RL;
     if (i >= n) return;   // whole lane groups
     const double ri = static_cast<double>(rho[i]);
-    const double s = row_kernel_sum16(idx + static_cast<size_t>(i) * k, d2 + static_cast<size_t>(i) * k, k, rho,
-                                      1.0 / (e * ri), gl);
+    const int64_t rb = row_begin(rowptr, i, k);
+    const double s = row_kernel_sum16(idx + rb, d2 + rb, row_length(rowptr, i, k), rho, 1.0 / (e * ri), gl);
     if (gl == 0) {
         const double P = 0.5 * ri;
         const double q = pow(P, -d) * s;
@@ -422,6 +467,84 @@ __global__ __launch_bounds__(256) void k_symmetric_finish(int64_t nnz, int k, co
     val[p] = static_cast<float>(w);
 }
 
+// The normalisation over a CSR pattern whose rows are already ordered by
+// column: one wavefront per row of any length. Kt_ir is formed as in
+// k_assemble (lanes strided over the row, compensated float64 sum, the same
+// butterfly), then formed again, identically, for the output value, which is
+// written in place. For KVB_OUT_SYMMETRIC the value is Kt and
+// k_symmetric_rows finishes it.
+__global__ __launch_bounds__(256) void k_assemble_rows(const int64_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ col, const float* __restrict__ d2,
+                                                       int n, const float* __restrict__ rho, double e,
+                                                       const double* __restrict__ e_dev,
+                                                       const double* __restrict__ qa, int out_kind,
+                                                       float* __restrict__ val, double* __restrict__ Pout,
+                                                       double* __restrict__ Dout)
+{
+    if (e_dev) e = *e_dev;
+    const int lane = lane_id();
+    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i >= n) return;
+    const int64_t rb = rowptr[i], re = rowptr[i + 1];
+    const double ri = static_cast<double>(rho[i]);
+    const double inv = 1.0 / (e * ri);
+    const double qai = qa[i];
+    Comp64 acc;
+    for (int64_t p = rb + lane; p < re; p += WAVE) {
+        const int j = col[p];
+        const double x = static_cast<double>(d2[p]) * inv / static_cast<double>(rho[j]);
+        acc.add(static_cast<double>(expf(-static_cast<float>(x))) * qai * qa[j]);
+    }
+    double Ds = acc.s, Dc = acc.c;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const double os = shfl_xor_f64(Ds, o), oc = shfl_xor_f64(Dc, o);
+        const double t = Ds + os;
+        Dc += oc + ((fabs(Ds) >= fabs(os)) ? ((Ds - t) + os) : ((os - t) + Ds));
+        Ds = t;
+    }
+    const double Di = Ds + Dc;
+    const double Pi = 0.5 * ri;
+    for (int64_t p = rb + lane; p < re; p += WAVE) {
+        const int j = col[p];
+        const double x = static_cast<double>(d2[p]) * inv / static_cast<double>(rho[j]);
+        const double kt = static_cast<double>(expf(-static_cast<float>(x))) * qai * qa[j];
+        double w;
+        if (out_kind == KVB_OUT_MARKOV)
+            w = kt / Di;
+        else if (out_kind == KVB_OUT_GENERATOR)
+            w = (kt / Di - (j == i ? 1.0 : 0.0)) / (e * Pi * Pi);
+        else
+            w = kt;
+        val[p] = static_cast<float>(w);
+    }
+    if (lane == 0) {
+        if (Pout) Pout[i] = Pi;
+        Dout[i] = Di;
+    }
+}
+
+// Lhat_ir = (Kt_ir / (S_i S_j) - [j == i] / P_i^2) / e over a CSR pattern
+__global__ __launch_bounds__(256) void k_symmetric_rows(const int64_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col, int n,
+                                                        const float* __restrict__ rho, const double* __restrict__ D,
+                                                        double e, const double* __restrict__ e_dev,
+                                                        float* __restrict__ val)
+{
+    if (e_dev) e = *e_dev;
+    const int lane = lane_id();
+    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i >= n) return;
+    const double Pi = 0.5 * static_cast<double>(rho[i]);
+    const double Si = Pi * sqrt(D[i]);
+    for (int64_t p = rowptr[i] + lane; p < rowptr[i + 1]; p += WAVE) {
+        const int j = col[p];
+        const double Pj = 0.5 * static_cast<double>(rho[j]);
+        const double Sj = Pj * sqrt(D[j]);
+        val[p] = static_cast<float>((static_cast<double>(val[p]) / (Si * Sj) - (j == i ? 1.0 / (Pi * Pi) : 0.0)) / e);
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 hipError_t launch_adhoc_bandwidth(const float* d2, int n, int k, int k0, float* b, hipStream_t st)
 {
@@ -432,8 +555,8 @@ hipError_t launch_adhoc_bandwidth(const float* d2, int n, int k, int k0, float* 
 hipError_t launch_density(const int32_t* idx, const float* d2, int n, int k, const float* b, double e,
                           const double* e_dev, double d, double beta, float* rho, float* psi, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_density, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, idx, d2, n, k, b, e, e_dev,
-                       d, beta, rho, psi);
+    hipLaunchKernelGGL(k_density, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, idx, d2, nullptr, n, k, b,
+                       e, e_dev, d, beta, rho, psi);
     return hipGetLastError();
 }
 
@@ -454,8 +577,8 @@ hipError_t launch_chi(const int32_t* idx, const float* d2, const float* rho, int
                       double e_max, const double* scale_dev, double* partial, TuneResult* out, hipStream_t st)
 {
     const int nb = chi_num_blocks(nnz);
-    hipLaunchKernelGGL(k_chi_partial, dim3(nb), dim3(CHI_BLOCK), 0, st, idx, d2, rho, nnz, k, G, e_min, e_max,
-                       scale_dev, chi_per_block(nnz), partial);
+    hipLaunchKernelGGL(k_chi_partial<false>, dim3(nb), dim3(CHI_BLOCK), 0, st, idx, d2, nullptr, 0, rho, nnz, k, G,
+                       e_min, e_max, scale_dev, chi_per_block(nnz), partial);
     hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, out);
     return hipGetLastError();
 }
@@ -474,8 +597,8 @@ hipError_t launch_grid_scale(const float* ref, const float* rho, int n, double* 
 hipError_t launch_qpass(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
                         const double* e_dev, double alpha, double d, double* qa, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_qpass, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, idx, d2, n, k, rho, e, e_dev,
-                       alpha, d, qa);
+    hipLaunchKernelGGL(k_qpass, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, idx, d2, nullptr, n, k, rho,
+                       e, e_dev, alpha, d, qa);
     return hipGetLastError();
 }
 
@@ -498,6 +621,47 @@ hipError_t launch_assemble(const int32_t* idx, const float* d2, int n, int k, co
         hipLaunchKernelGGL(k_symmetric_finish, dim3(static_cast<unsigned>((nnz + 255) / 256)), dim3(256), 0, st,
                            nnz, k, col, rho, D, e, e_dev, val);
     }
+    return hipGetLastError();
+}
+
+// ---- the same passes over a CSR pattern
+hipError_t launch_density_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, const float* b,
+                              double e, const double* e_dev, double d, double beta, float* rho, float* psi,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(k_density, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, col, d2, rowptr, n, 0, b,
+                       e, e_dev, d, beta, rho, psi);
+    return hipGetLastError();
+}
+
+hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, int64_t nnz,
+                          const float* rho, int G, double e_min, double e_max, const double* scale_dev,
+                          double* partial, TuneResult* out, hipStream_t st)
+{
+    const int nb = chi_num_blocks(nnz);
+    hipLaunchKernelGGL(k_chi_partial<true>, dim3(nb), dim3(CHI_BLOCK), 0, st, col, d2, rowptr, n, rho, nnz, 0, G,
+                       e_min, e_max, scale_dev, chi_per_block(nnz), partial);
+    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_qpass_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, const float* rho,
+                            double e, const double* e_dev, double alpha, double d, double* qa, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_qpass, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, col, d2, rowptr, n, 0, rho,
+                       e, e_dev, alpha, d, qa);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_rows(const int64_t* rowptr, const int32_t* col, const float* d2, int n, const float* rho,
+                                double e, const double* e_dev, const double* qa, int out_kind, float* val, double* P,
+                                double* D, hipStream_t st)
+{
+    const dim3 grid((n + 3) / 4), block(256);
+    hipLaunchKernelGGL(k_assemble_rows, grid, block, 0, st, rowptr, col, d2, n, rho, e, e_dev, qa, out_kind, val, P,
+                       D);
+    if (out_kind == KVB_OUT_SYMMETRIC)
+        hipLaunchKernelGGL(k_symmetric_rows, grid, block, 0, st, rowptr, col, n, rho, D, e, e_dev, val);
     return hipGetLastError();
 }
 

@@ -35,8 +35,9 @@ EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb
            "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_build", "kvb_build_info", "kvb_part_init",
            "kvb_part_teacher", "kvb_part_train", "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
            "kvb_mlp_backward", "kvb_part_num_params", "kvb_part_get_params", "kvb_part_set_params",
-           "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name")
-PROF_SLOTS = 12
+           "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name",
+           "kvb_union_pattern", "kvb_density_csr", "kvb_tune_eps_csr", "kvb_normalize_csr")
+PROF_SLOTS = 13
 
 
 class KvbError(RuntimeError):
@@ -77,6 +78,11 @@ def load_library(path: str = LIB_PATH):
     L.kvb_build.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64, _i32, _i32,
                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.kvb_build_info.argtypes = [_vp, _vp, _vp, _vp]
+    L.kvb_union_pattern.argtypes = [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64)]
+    L.kvb_density_csr.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _vp, _f64, _f64, _f64, _vp, _vp]
+    L.kvb_tune_eps_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _i32, _vp,
+                                   ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
+    L.kvb_normalize_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _f64, _i32, _vp, _vp, _vp]
     _u64, _f32 = ctypes.c_uint64, ctypes.c_float
     L.kvb_part_init.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32, _u64]
     L.kvb_part_teacher.argtypes = [_vp, _vp, _i64, _i32, _i32, _u64, _vp]
@@ -391,6 +397,113 @@ def build_kernel_matrix(X: torch.Tensor, k: int, k0: int, d: float, alpha: float
     tb = tune_eps(idx, d2, rho, e_min * s, e_max * s, G, ctx)
     rowptr, col, val, P, D = assemble_csr(idx, d2, rho, tb.e_star, alpha, d, out_kind, ctx)
     return KernelMatrix(idx, d2, flags, b, ta, rho, psi, s, tb, rowptr, col, val, P, D)
+
+
+# ------------------------------------------------------------------ union pattern E u E^T
+@dataclass
+class CsrPattern:
+    """A CSR pattern with the squared distance of each stored entry (device)."""
+    rowptr: torch.Tensor   # int64 [n+1]
+    col: torch.Tensor      # int32 [nnz]
+    d2: torch.Tensor       # float32 [nnz]
+
+    @property
+    def n(self) -> int:
+        return self.rowptr.numel() - 1
+
+    @property
+    def nnz(self) -> int:
+        return self.col.numel()
+
+
+def union_pattern(idx: torch.Tensor, d2: torch.Tensor, ctx: Context | None = None) -> CsrPattern:
+    """E u E^T of a k-NN pattern: row i holds every j with j in N(i) or i in N(j),
+    columns ascending (kvb_union_pattern)."""
+    ctx = ctx or context()
+    idx = _dev(idx, torch.int32, "idx")
+    d2 = _dev(d2, torch.float32, "d2")
+    n, k = d2.shape
+    cap = n * (2 * k - 1)
+    rowptr = torch.empty(n + 1, dtype=torch.int64, device=d2.device)
+    col = torch.empty(cap, dtype=torch.int32, device=d2.device)
+    ud2 = torch.empty(cap, dtype=torch.float32, device=d2.device)
+    nnz = _i64()
+    ctx.check(ctx.lib.kvb_union_pattern(ctx.h, _ptr(idx), _ptr(d2), n, k, _ptr(rowptr), _ptr(col), _ptr(ud2), cap,
+                                        ctypes.byref(nnz)))
+    return CsrPattern(rowptr, col[:nnz.value], ud2[:nnz.value])
+
+
+def density_csr(pat: CsrPattern, b: torch.Tensor, e: float, d: float, beta: float, ctx: Context | None = None):
+    """(rho, psi) over a CSR pattern (kvb_density_csr)."""
+    ctx = ctx or context()
+    b = _dev(b, torch.float32, "b")
+    rho = torch.empty(pat.n, dtype=torch.float32, device=b.device)
+    psi = torch.empty(pat.n, dtype=torch.float32, device=b.device)
+    ctx.check(ctx.lib.kvb_density_csr(ctx.h, _ptr(pat.rowptr), _ptr(pat.col), _ptr(pat.d2), pat.n, pat.nnz, _ptr(b),
+                                      e, d, beta, _ptr(rho), _ptr(psi)))
+    return rho, psi
+
+
+def tune_eps_csr(pat: CsrPattern, rho: torch.Tensor, e_min: float, e_max: float, G: int,
+                 ctx: Context | None = None) -> Tuning:
+    ctx = ctx or context()
+    rho = _dev(rho, torch.float32, "rho")
+    chi = np.zeros(G, dtype=np.float64)
+    es, dm = _f64(), _f64()
+    rc = ctx.check(ctx.lib.kvb_tune_eps_csr(ctx.h, _ptr(pat.rowptr), _ptr(pat.col), _ptr(pat.d2), _ptr(rho), pat.n,
+                                            pat.nnz, e_min, e_max, G, chi.ctypes.data_as(_vp), ctypes.byref(es),
+                                            ctypes.byref(dm)))
+    return Tuning(chi, float(es.value), float(dm.value), rc == W_GRID_EDGE)
+
+
+def normalize_csr(pat: CsrPattern, rho: torch.Tensor, e: float, alpha: float, d: float, out_kind: int = OUT_MARKOV,
+                  ctx: Context | None = None):
+    """Values in pattern order plus P, D (kvb_normalize_csr)."""
+    ctx = ctx or context()
+    rho = _dev(rho, torch.float32, "rho")
+    val = torch.empty(pat.nnz, dtype=torch.float32, device=rho.device)
+    P = torch.empty(pat.n, dtype=torch.float64, device=rho.device)
+    D = torch.empty(pat.n, dtype=torch.float64, device=rho.device)
+    ctx.check(ctx.lib.kvb_normalize_csr(ctx.h, _ptr(pat.rowptr), _ptr(pat.col), _ptr(pat.d2), _ptr(rho), pat.n,
+                                        pat.nnz, e, alpha, d, out_kind, _ptr(val), _ptr(P), _ptr(D)))
+    return val, P, D
+
+
+@dataclass
+class UnionMatrix:
+    idx: torch.Tensor
+    d2: torch.Tensor
+    pattern: CsrPattern
+    b: torch.Tensor
+    tune_a: Tuning
+    rho: torch.Tensor
+    psi: torch.Tensor
+    scale_b: float
+    tune_b: Tuning
+    val: torch.Tensor
+    P: torch.Tensor
+    D: torch.Tensor
+
+
+def build_union_matrix(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float,
+                       e_min: float = 1e-3, e_max: float = 1e1, G: int = 64, mode: str = "f32", margin: int = 32,
+                       out_kind: int = OUT_MARKOV, ctx: Context | None = None, knn_result=None) -> UnionMatrix:
+    """The build of build_kernel_matrix on the symmetric pattern E u E^T: the
+    ad-hoc bandwidth from the k nearest neighbours, every later row sum over
+    the union row. knn_result = (idx, d2) skips the search."""
+    ctx = ctx or context()
+    if knn_result is None:
+        idx, d2, _ = knn(X, k, mode, margin, ctx)
+    else:
+        idx, d2 = knn_result
+    b = bandwidth_adhoc(d2, k0, ctx)
+    pat = union_pattern(idx, d2, ctx)
+    ta = tune_eps_csr(pat, b, e_min, e_max, G, ctx)
+    rho, psi = density_csr(pat, b, ta.e_star, d, beta, ctx)
+    s = grid_scale(b, rho, ctx)
+    tb = tune_eps_csr(pat, rho, e_min * s, e_max * s, G, ctx)
+    val, P, D = normalize_csr(pat, rho, tb.e_star, alpha, d, out_kind, ctx)
+    return UnionMatrix(idx, d2, pat, b, ta, rho, psi, s, tb, val, P, D)
 
 
 # ------------------------------------------------------------------ learned partitioner

@@ -139,6 +139,69 @@ def test_scale_invariance_of_operator(sphere_run):
             np.testing.assert_allclose(v1, v0, rtol=1e-11, atol=1e-12 * abs(v0).max())
 
 
+# ------------------------------------------------------------------ union pattern E u E^T
+def union_by_sets(idx, d2):
+    """E u E^T from its definition, with Python sets: (i, j) is stored when j
+    is in row i of idx or i is in row j (Algorithm 1 stores K_ij and K_ji
+    together); the distance of the pair is symmetric."""
+    n, k = idx.shape
+    rows = [dict() for _ in range(n)]
+    for i in range(n):
+        for r in range(k):
+            j = int(idx[i, r])
+            rows[i][j] = d2[i, r]
+            rows[j][i] = d2[i, r]
+    return rows
+
+
+def test_union_pattern_hand_example():
+    """Points 0, 1, 2, 10 on a line, k = 2 (self + nearest, ties to the lower
+    index): N = [0,1], [1,0], [2,1], [3,2]. The transpose adds (1,2) and (2,3)."""
+    X = np.array([[0.0], [1.0], [2.0], [10.0]], dtype=np.float32)
+    idx, d2 = oracle.knn(X, 2)
+    assert idx.tolist() == [[0, 1], [1, 0], [2, 1], [3, 2]]
+    pat = spectral.union_pattern(idx, d2)
+    assert pat.rowptr.tolist() == [0, 2, 5, 8, 10]
+    assert pat.col.tolist() == [0, 1, 0, 1, 2, 1, 2, 3, 2, 3]
+    assert pat.dist2.tolist() == [0, 1, 1, 0, 1, 1, 0, 64, 64, 0]
+
+
+@pytest.mark.parametrize("case", ["random", "hub", "complete", "self_only"])
+def test_union_pattern_matches_set_definition(case):
+    rng = np.random.default_rng(11)
+    if case == "random":
+        X = rng.standard_normal((300, 3)).astype(np.float32)
+        idx, d2 = oracle.knn(X, 9)
+    elif case == "hub":
+        # every row lists the same few low indices: their union rows hold all n
+        n, k = 200, 6
+        idx = np.empty((n, k), dtype=np.int32)
+        for i in range(n):
+            others = [j for j in range(k + 1) if j != i][:k - 1]
+            idx[i] = [i] + others
+        d2 = np.array([[0.001 * (i + j + 1) * (i != j) for j in row] for i, row in enumerate(idx)])
+    elif case == "complete":
+        X = rng.standard_normal((12, 2)).astype(np.float32)
+        idx, d2 = oracle.knn(X, 12)
+    else:
+        X = rng.standard_normal((50, 4)).astype(np.float32)
+        idx, d2 = oracle.knn(X, 1)
+    pat = spectral.union_pattern(idx, d2)
+    rows = union_by_sets(idx, d2)
+    n = len(idx)
+    assert pat.rowptr[0] == 0 and pat.rowptr[-1] == len(pat.col)
+    for i in range(n):
+        cols = pat.col[pat.rowptr[i]:pat.rowptr[i + 1]]
+        assert cols.tolist() == sorted(rows[i]), i
+        assert pat.dist2[pat.rowptr[i]:pat.rowptr[i + 1]].tolist() == [rows[i][j] for j in sorted(rows[i])]
+    if case == "complete":
+        assert len(pat.col) == n * n
+    if case == "self_only":
+        assert pat.col.tolist() == list(range(n))
+    if case == "hub":
+        assert pat.rowptr[1] - pat.rowptr[0] == n
+
+
 def test_union_symmetric_conjugate_similar_to_generator():
     X = workloads.sphere2(800, seed=4)
     A, info = spectral.union_operator(X, 24, 8, 2.0, -0.5, -0.5)
