@@ -64,6 +64,8 @@ def main() -> int:
     ap.add_argument("--curve-order", type=int, default=1, choices=[0, 1],
                     help="exact matrix-core modes: 1 scans candidates in curve order with projected-box pruning, "
                          "0 scans every tile")
+    ap.add_argument("--pattern", default="knn", choices=["knn", "union"],
+                    help="matrix pattern: the directed k-NN rows, or their union with the transpose (symmetric)")
     ap.add_argument("--train-epochs", type=int, default=10, help="learned mode: partitioner training epochs")
     ap.add_argument("--n-probe", type=int, default=8,
                     help="learned mode: buckets each query searches (the configured top-4 gives recall "
@@ -130,7 +132,7 @@ def main() -> int:
         # the build is only enqueued (steps run back to back on the stream) and
         # its tuning results are read once, after the timed region
         prev[0] = kvb.build(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
-                            mode=w.mode, margin=w.margin, ctx=ctx, out=prev[0], sync=False)
+                            mode=w.mode, margin=w.margin, ctx=ctx, out=prev[0], sync=False, pattern=args.pattern)
         return prev[0]
 
     for _ in range(args.warmup):
@@ -197,16 +199,23 @@ def main() -> int:
 
     # the O(nk) passes against the HBM roofline: algorithmic bytes per launch
     # (each stored entry: d2 4 B + idx 4 B + the gathered rho_j / q_j 4 B)
-    nnz = float(w.n) * w.k
+    nk = float(w.n) * w.k
     kp = min(w.k + w.margin, w.n)
+    union = args.pattern == "union"
+    nnz = float(r.rowptr[-1].item()) if union else nk
+    rows8 = float(w.n) * 8 if union else 0.0                       # rowptr reads of the CSR passes
     pass_bytes = {
-        "knn_refine": float(w.n) * kp * (w.m * 4 + 8) + nnz * 8,   # candidate rows + keys, idx/d2 out
+        "knn_refine": float(w.n) * kp * (w.m * 4 + 8) + nk * 8,    # candidate rows + keys, idx/d2 out
         "adhoc_bandwidth": float(w.n) * (w.k0 * 4 + 4),
-        "chi_tuning": nnz * 12 + float(w.n) * 4,
-        "density": nnz * 12 + float(w.n) * 12,
-        "q_pass": nnz * 12 + float(w.n) * 12,
-        "assemble": nnz * (16 + 8) + float(w.n) * 16,                 # entries in / CSR out, P and D
+        "chi_tuning": nnz * 12 + float(w.n) * 4 + rows8,
+        "density": nnz * 12 + float(w.n) * 12 + rows8,
+        "q_pass": nnz * 12 + float(w.n) * 12 + rows8,
+        # entries in / CSR out (the union pattern's columns are already written), P and D
+        "assemble": nnz * (16 + (4 if union else 8)) + float(w.n) * 16 + rows8,
     }
+    if union:
+        # the directed rows in, the union's columns, distances and row pointers out
+        pass_bytes["union_pattern"] = nk * 8 + nnz * 8 + float(w.n + 1) * 8
     passes = {}
     for name, byt in pass_bytes.items():
         ms, cnt = prof.get(name, (0.0, 0))
@@ -229,7 +238,12 @@ def main() -> int:
         if w.n <= 200_000:
             log("bench: timing the FP64 oracle on the host cores (whole workload, one run)")
             c0 = time.perf_counter()
-            oracle.pipeline(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G)
+            if union:
+                from oracle import spectral
+                spectral.union_operator(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
+                                        out_kind=oracle.MARKOV)
+            else:
+                oracle.pipeline(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G)
             c1 = time.perf_counter()
             cpu = {"value": round(w.n / (c1 - c0), 2), "unit": "rows/s", "cores": oracle.num_threads(),
                    "kind": "oracle", "sample": f"whole workload ({w.n} rows), one run, {c1 - c0:.2f} s"}
@@ -248,7 +262,8 @@ def main() -> int:
 
     out = {
         "metric": "kernel-matrix rows/s (kNN+VB kernel->CSR) at " + ("learned-routed kNN (recall reported)"
-                                                                    if learned else "exact kNN sets"),
+                                                                    if learned else "exact kNN sets")
+                  + (", union pattern E u E^T" if union else ""),
         "value": round(value, 1),
         "unit": "rows/s",
         "n_gpus": 1,
@@ -263,7 +278,8 @@ def main() -> int:
         "config": {"workload": w.name, "n": w.n, "m": w.m, "k": w.k, "k0": w.k0, "d": w.d,
                    "mode": w.mode, "margin": w.margin, "grid": [w.e_min, w.e_max, w.G],
                    "curve_order": bool(args.curve_order) and w.mode != "learned" and not (w.mode == "f32" and w.m <= 8),
-                   "alpha": w.alpha, "beta": w.beta, "fallback_rows": fb, "learned": learned},
+                   "alpha": w.alpha, "beta": w.beta, "fallback_rows": fb, "learned": learned,
+                   "pattern": args.pattern, "nnz": int(nnz)},
         "roofline": roofline,
         "passes": passes,
         "cpu_baseline": cpu,

@@ -95,6 +95,10 @@ extern "C" {
                                     order of the principal projections and skips tiles whose projected boxes
                                     lie beyond every query's threshold; 0 scans every tile in sample order.
                                     Either way the result is the same exact k-NN */
+#define KVB_OPT_PATTERN 6        /* pattern of kvb_build's matrix: KVB_PATTERN_KNN (default) or KVB_PATTERN_UNION */
+#define KVB_PATTERN_KNN 0        /* the directed k-NN pattern, k entries per row */
+#define KVB_PATTERN_UNION 1      /* E u E^T (as kvb_union_pattern); col and val must then hold n (2k - 1)
+                                    entries and rowptr[n] gives the stored count */
 
 typedef struct kvb_ctx_s* kvb_ctx;
 
@@ -231,7 +235,7 @@ int kvb_assemble_csr(kvb_ctx ctx, const int32_t* idx, const float* d2, const flo
  *   col [cap] int32 out, ud2 [cap] float32 out: the first nnz entries are written.
  *     cap = n (2k - 1) always suffices; nnz <= cap is required.
  *   nnz_host: host out (required).
- * The result is deterministic. Scratch grows by about 36 bytes per directed entry.
+ * The result is deterministic. Scratch grows by about 17 bytes per directed entry.
  * Synchronises the context stream (once, to size the transpose). KVB_E_INVALID
  * for a repeated column or a column outside [0, n) in a row of idx, or for
  * cap < nnz (the outputs are then unspecified, *nnz_host is set).
@@ -272,7 +276,11 @@ int kvb_normalize_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, co
  * back; kvb_build_info then waits for the last build and reports it.
  *   idx, d2, row_flags   as kvb_knn (row_flags may be NULL).
  *   b, rho [n] float32 out; psi [n] float32 out or NULL.
- *   rowptr, col, val, P, D   as kvb_assemble_csr (P, D may be NULL).
+ *   rowptr, col, val, P, D   as kvb_assemble_csr (P, D may be NULL); with
+ *                KVB_OPT_PATTERN = KVB_PATTERN_UNION the pattern is E u E^T and
+ *                every pass after the ad-hoc bandwidth runs over it, as
+ *                kvb_union_pattern, kvb_tune_eps_csr, kvb_density_csr and
+ *                kvb_normalize_csr would (col, val: n (2k - 1) entries).
  *   chi_a_host, chi_b_host   [G] host out or NULL: the tuning sums of both stages.
  *   info_host [8] host out or NULL: e_A, dim_A, s, e_B, dim_B, g*_A, g*_B, rows
  *                that took the exact k-NN fallback.

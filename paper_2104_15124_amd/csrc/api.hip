@@ -103,6 +103,11 @@ int kvb_set_option(kvb_ctx ctx, int32_t key, int64_t value)
                     "KVB_OPT_N_PROBE must be in [1, min(32, n_buckets)]");
         ctx->part.np = static_cast<int>(value);
         return KVB_OK;
+    case KVB_OPT_PATTERN:
+        KVB_REQUIRE(ctx, value == KVB_PATTERN_KNN || value == KVB_PATTERN_UNION,
+                    "KVB_OPT_PATTERN must be KVB_PATTERN_KNN or KVB_PATTERN_UNION");
+        ctx->pattern = static_cast<int>(value);
+        return KVB_OK;
     case KVB_OPT_CURVE_ORDER:
         KVB_REQUIRE(ctx, value == 0 || value == 1, "KVB_OPT_CURVE_ORDER must be 0 or 1");
         ctx->curve_order = static_cast<int>(value);
@@ -467,6 +472,31 @@ int kvb_assemble_csr(kvb_ctx ctx, const int32_t* idx, const float* d2, const flo
 }
 
 // ------------------------------------------------------------------ union pattern and CSR passes
+// scratch of the transpose-merge: about 17 bytes per directed entry
+static size_t union_work_bytes(int n, int64_t nk)
+{
+    return 2 * round256(size_t(nk) * 4) + round256(size_t(nk)) + round256(size_t(nk) * 8) +
+           round256((size_t(n) + 1) * 4) + round256((size_t(n) + 1) * 8) + 3 * round256(16) +
+           round256(size_t(n) * 4) + round256(kvb::union_scan_bytes(n)) + 2048;
+}
+
+static kvb::UnionWork take_union_work(Carve& cv, int n, int64_t nk)
+{
+    kvb::UnionWork w;
+    w.scol = cv.take<int32_t>(nk);
+    w.sd2 = cv.take<float>(nk);
+    w.flag = cv.take<uint8_t>(nk);
+    w.rkey = cv.take<uint64_t>(nk);
+    w.cnt = cv.take<int>(size_t(n) + 1);
+    w.revptr = cv.take<int64_t>(size_t(n) + 1);
+    w.bad = cv.take<unsigned long long>(1);
+    w.long_count = cv.take<int>(1);
+    w.long_rows = cv.take<int>(n);
+    w.scan_bytes = kvb::union_scan_bytes(n);
+    w.scan_tmp = cv.take<char>(w.scan_bytes);
+    return w;
+}
+
 int kvb_union_pattern(kvb_ctx ctx, const int32_t* idx, const float* d2, int64_t n, int32_t k, int64_t* rowptr,
                       int32_t* col, float* ud2, int64_t cap, int64_t* nnz_host)
 {
@@ -479,29 +509,14 @@ int kvb_union_pattern(kvb_ctx ctx, const int32_t* idx, const float* d2, int64_t 
     KVB_REQUIRE(ctx, cap >= 0, "cap must be >= 0");
     const int nn = static_cast<int>(n);
     const int64_t nk = n * k;
-    const size_t scan_bytes = kvb::union_scan_bytes(nn);
-    const size_t sort_bytes = kvb::union_sort_bytes(nk);
-    const size_t need = 2 * round256(size_t(nk) * 4) + 2 * round256(size_t(nk) * 8) + 3 * round256(size_t(nk) * 4) +
-                        round256((size_t(nn) + 1) * 4) + round256((size_t(nn) + 1) * 8) + round256(16) +
-                        round256(scan_bytes) + round256(sort_bytes) + 2048;
-    int rc = ensure_scratch(ctx, need);
+    int rc = ensure_scratch(ctx, union_work_bytes(nn, nk));
     if (rc) return rc;
     Carve cv(ctx->scratch);
-    int32_t* scol = cv.take<int32_t>(nk);
-    float* sd2 = cv.take<float>(nk);
-    uint64_t* rkey = cv.take<uint64_t>(nk);
-    uint64_t* skey = cv.take<uint64_t>(nk);
-    float* rd2 = cv.take<float>(nk);
-    float* srd2 = cv.take<float>(nk);
-    int32_t* rcol = cv.take<int32_t>(nk);
-    int* cnt = cv.take<int>(size_t(nn) + 1);
-    int64_t* revptr = cv.take<int64_t>(size_t(nn) + 1);
-    unsigned long long* stats = cv.take<unsigned long long>(2);
-    void* scan_tmp = cv.take<char>(scan_bytes);
-    void* sort_tmp = cv.take<char>(sort_bytes);
+    const kvb::UnionWork w = take_union_work(cv, nn, nk);
     Prof pr(ctx, KVB_PROF_UNION);
-    KVB_HIP(ctx, kvb::launch_union_count(idx, d2, nn, k, scol, sd2, cnt, stats, rkey, rd2, ctx->stream));
-    KVB_HIP(ctx, hipMemcpyAsync(ctx->union_host, stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+    KVB_HIP(ctx, kvb::launch_union_count(idx, d2, nn, k, w, ctx->stream));
+    KVB_HIP(ctx, hipMemcpyAsync(ctx->union_host, w.revptr + nn, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    KVB_HIP(ctx, hipMemcpyAsync(ctx->union_host + 1, w.bad, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                 ctx->stream));
     KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const int64_t total = static_cast<int64_t>(ctx->union_host[0]);
@@ -511,9 +526,7 @@ int kvb_union_pattern(kvb_ctx ctx, const int32_t* idx, const float* d2, int64_t 
     if (cap < nk + total)
         return fail(ctx, KVB_E_INVALID, "cap %lld is below the union's %lld entries", static_cast<long long>(cap),
                     static_cast<long long>(nk + total));
-    KVB_HIP(ctx, kvb::launch_union_scan(scan_tmp, scan_bytes, cnt, nn, k, revptr, rowptr, ctx->stream));
-    KVB_HIP(ctx, kvb::launch_union_place(sort_tmp, sort_bytes, rkey, skey, rd2, srd2, total, scol, sd2, nn, k, revptr,
-                                         rowptr, rcol, col, ud2, ctx->stream));
+    KVB_HIP(ctx, kvb::launch_union_place(nn, k, w, rowptr, col, ud2, ctx->stream));
     return KVB_OK;
 }
 
@@ -569,8 +582,8 @@ int kvb_tune_eps_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, con
     double* part = cv.take<double>(size_t(nb) * G);
     {
         Prof pr(ctx, KVB_PROF_CHI);
-        KVB_HIP(ctx, kvb::launch_chi_csr(rowptr, col, ud2, static_cast<int>(n), nnz, rho, G, e_min, e_max, nullptr,
-                                         part, ctx->tune_dev, ctx->stream));
+        KVB_HIP(ctx, kvb::launch_chi_csr(rowptr, col, ud2, static_cast<int>(n), nnz, nnz, rho, G, e_min, e_max,
+                                         nullptr, part, ctx->tune_dev, ctx->stream));
     }
     KVB_HIP(ctx, hipMemcpyAsync(ctx->tune_host, ctx->tune_dev, sizeof(kvb::TuneResult), hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -611,6 +624,72 @@ int kvb_normalize_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, co
     return KVB_OK;
 }
 
+// The passes of kvb_build after the k-NN, over E u E^T: enqueued only (the
+// pattern's size stays on the device; the transpose sort runs over all n k
+// slots with the unused ones holding a sentinel key).
+static int build_union(kvb_ctx ctx, int64_t n, int32_t k, int32_t k0, double d, double alpha, double beta,
+                       double e_min, double e_max, int32_t G, int32_t out_kind, const int32_t* idx, const float* d2,
+                       float* b, float* rho, float* psi, int64_t* rowptr, int32_t* col, float* val, double* P,
+                       double* D)
+{
+    const int nn = static_cast<int>(n);
+    const int64_t nk = n * k;
+    const int64_t cap = n * (2 * int64_t(k) - 1);
+    const int nb = kvb::chi_csr_blocks(nk, cap);
+    const int lb = kvb::logsum_num_blocks(nn);
+    const size_t need = union_work_bytes(nn, nk) + round256(size_t(cap) * 4) +
+                        round256(size_t(nb) * G * sizeof(double)) + round256(size_t(2 * lb) * sizeof(double)) +
+                        2 * round256(size_t(nn) * sizeof(double)) + 2048;
+    int rc = ensure_scratch(ctx, need);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    const kvb::UnionWork uw = take_union_work(cv, nn, nk);
+    float* ud2 = cv.take<float>(cap);
+    double* part = cv.take<double>(size_t(nb) * G);
+    double* lpart = cv.take<double>(2 * lb);
+    double* qa = cv.take<double>(nn);
+    double* Dtmp = cv.take<double>(nn);
+    BuildDev* bd = ctx->build_dev;
+    hipStream_t st = ctx->stream;
+    {
+        Prof pr(ctx, KVB_PROF_ADHOC);
+        KVB_HIP(ctx, kvb::launch_adhoc_bandwidth(d2, nn, k, k0, b, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_UNION);
+        KVB_HIP(ctx, kvb::launch_union_count(idx, d2, nn, k, uw, st));
+        KVB_HIP(ctx, kvb::launch_union_place(nn, k, uw, rowptr, col, ud2, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_CHI);
+        KVB_HIP(ctx, kvb::launch_chi_csr(rowptr, col, ud2, nn, nk, cap, b, G, e_min, e_max, nullptr, part, &bd->a,
+                                         st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_DENSITY);
+        KVB_HIP(ctx, kvb::launch_density_csr(rowptr, col, ud2, nn, b, 0.0, &bd->a.e_star, d, beta, rho, psi, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_GRID_SCALE);
+        KVB_HIP(ctx, kvb::launch_grid_scale(b, rho, nn, lpart, &bd->scale, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_CHI);
+        KVB_HIP(ctx, kvb::launch_chi_csr(rowptr, col, ud2, nn, nk, cap, rho, G, e_min, e_max, &bd->scale, part,
+                                         &bd->b, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_QPASS);
+        KVB_HIP(ctx, kvb::launch_qpass_csr(rowptr, col, ud2, nn, rho, 0.0, &bd->b.e_star, alpha, d, qa, st));
+    }
+    {
+        Prof pr(ctx, KVB_PROF_ASSEMBLE);
+        KVB_HIP(ctx, kvb::launch_assemble_rows(rowptr, col, ud2, nn, rho, 0.0, &bd->b.e_star, qa, out_kind, val, P,
+                                               D ? D : Dtmp, st));
+    }
+    return KVB_OK;
+}
+
 int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_t mode, int32_t margin, int32_t k0,
               double d, double alpha, double beta, double e_min, double e_max, int32_t G, int32_t out_kind,
               int32_t* idx, float* d2, int32_t* row_flags, float* b, float* rho, float* psi, int64_t* rowptr,
@@ -631,6 +710,14 @@ int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int3
     KVB_REQUIRE(ctx, (P == nullptr || aligned(P)) && (D == nullptr || aligned(D)), "P and D must be aligned");
     int rc = kvb_knn(ctx, X, n, m, k, mode, margin, idx, d2, row_flags);
     if (rc < 0) return rc;
+    if (ctx->pattern == KVB_PATTERN_UNION) {
+        rc = build_union(ctx, n, k, k0, d, alpha, beta, e_min, e_max, G, out_kind, idx, d2, b, rho, psi, rowptr, col,
+                         val, P, D);
+        if (rc < 0) return rc;
+        ctx->build_G = G;
+        if (!info_host) return KVB_OK;
+        return kvb_build_info(ctx, chi_a_host, chi_b_host, info_host);
+    }
     const int nn = static_cast<int>(n);
     const int64_t nnz = n * k;
     const int nb = kvb::chi_num_blocks(nnz);

@@ -59,6 +59,7 @@ struct kvb_ctx_s {
     int64_t force_fallback = 0;
     int bf16_split = 3;
     int curve_order = 1;
+    int pattern = KVB_PATTERN_KNN;   // pattern of kvb_build's matrix
     int build_G = 0;   // grid size of the last kvb_build (0: none yet)
     kvb::TuneResult* tune_dev = nullptr;
     kvb::TuneResult* tune_host = nullptr;   // pinned

@@ -173,27 +173,37 @@ hipError_t launch_work_layout(const uint64_t* qkeys, int n, int nb, int P, int q
                               int2* work, int32_t* n_work, int32_t* qids, hipStream_t st);
 
 // ---- union pattern E u E^T and the passes over a CSR pattern
-int union_key_bits(int n);
+// scratch of the transpose-merge (arrays of n k entries unless noted)
+struct UnionWork {
+    int32_t* scol;              // directed rows sorted by column
+    float* sd2;
+    uint8_t* flag;              // entry contributes a reverse entry
+    uint64_t* rkey;             // reverse entries (at most n k), by row segment
+    int* cnt;                   // [n + 1]
+    int64_t* revptr;            // [n + 1]
+    unsigned long long* bad;    // [1] invalid-input flag
+    int* long_count;            // [1]
+    int* long_rows;             // [n]
+    void* scan_tmp;
+    size_t scan_bytes;
+};
 size_t union_scan_bytes(int n);
-size_t union_sort_bytes(int64_t cap);
-// sorted directed rows (scol, sd2 [n k]), reverse-entry counts cnt [n + 1],
-// stats [2] (reverse entries; invalid-input flag), appended pairs rkey/rd2 [n k]
-hipError_t launch_union_count(const int32_t* idx, const float* d2, int n, int k, int32_t* scol, float* sd2, int* cnt,
-                              unsigned long long* stats, uint64_t* rkey, float* rd2, hipStream_t st);
-hipError_t launch_union_scan(void* tmp, size_t tmp_bytes, const int* cnt, int n, int k, int64_t* revptr,
-                             int64_t* rowptr, hipStream_t st);
-hipError_t launch_union_place(void* tmp, size_t tmp_bytes, const uint64_t* rkey, uint64_t* skey, const float* rd2,
-                              float* srd2, int64_t total, const int32_t* scol, const float* sd2, int n, int k,
-                              const int64_t* revptr, const int64_t* rowptr, int32_t* rcol, int32_t* col, float* ud2,
+// steps 1-3: sorted rows, flags, counts, revptr (revptr[n] = reverse entries)
+hipError_t launch_union_count(const int32_t* idx, const float* d2, int n, int k, const UnionWork& w, hipStream_t st);
+// steps 4-6 into rowptr [n + 1], col and ud2 [n k + revptr[n]]
+hipError_t launch_union_place(int n, int k, const UnionWork& w, int64_t* rowptr, int32_t* col, float* ud2,
                               hipStream_t st);
 hipError_t launch_check_csr(const int64_t* rowptr, const int32_t* col, int n, int64_t nnz, unsigned long long* bad,
                             hipStream_t st);
 hipError_t launch_density_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, const float* b,
                               double e, const double* e_dev, double d, double beta, float* rho, float* psi,
                               hipStream_t st);
-hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, int64_t nnz,
-                          const float* rho, int G, double e_min, double e_max, const double* scale_dev,
-                          double* partial, TuneResult* out, hipStream_t st);
+// nnz_cap: an upper bound of rowptr[n] (the kernel reads the count from
+// rowptr[n]); nnz_hint: the expected count, which sets the block partition
+int chi_csr_blocks(int64_t nnz_hint, int64_t nnz_cap);
+hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, int64_t nnz_hint,
+                          int64_t nnz_cap, const float* rho, int G, double e_min, double e_max,
+                          const double* scale_dev, double* partial, TuneResult* out, hipStream_t st);
 hipError_t launch_qpass_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, const float* rho,
                             double e, const double* e_dev, double alpha, double d, double* qa, hipStream_t st);
 hipError_t launch_assemble_rows(const int64_t* rowptr, const int32_t* col, const float* d2, int n, const float* rho,

@@ -137,6 +137,7 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
     __shared__ float s_tr[WAVE][CHI_GROUP + 1];   // one wavefront's partials, transposed
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
+    if (CSR) nnz = rowptr[n];   // the launch is sized for an upper bound
     const int64_t base = static_cast<int64_t>(blockIdx.x) * per_block;
     const int64_t end = min(base + per_block, nnz);
     for (int g = threadIdx.x; g < 256 + CHI_GROUP; g += CHI_BLOCK)
@@ -470,8 +471,8 @@ __global__ __launch_bounds__(256) void k_symmetric_finish(int64_t nnz, int k, co
 // The normalisation over a CSR pattern whose rows are already ordered by
 // column: one wavefront per row of any length. Kt_ir is formed as in
 // k_assemble (lanes strided over the row, compensated float64 sum, the same
-// butterfly), then formed again, identically, for the output value, which is
-// written in place. For KVB_OUT_SYMMETRIC the value is Kt and
+// butterfly); the output value, written in place, takes Kt_ir from registers
+// for a row's first 128 entries and forms it again, identically, beyond. For KVB_OUT_SYMMETRIC the value is Kt and
 // k_symmetric_rows finishes it.
 __global__ __launch_bounds__(256) void k_assemble_rows(const int64_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ col, const float* __restrict__ d2,
@@ -489,11 +490,19 @@ __global__ __launch_bounds__(256) void k_assemble_rows(const int64_t* __restrict
     const double ri = static_cast<double>(rho[i]);
     const double inv = 1.0 / (e * ri);
     const double qai = qa[i];
+    // the row's first KEEP * 64 values stay in registers for the second sweep
+    constexpr int KEEP = 2;
+    double kv[KEEP];
     Comp64 acc;
-    for (int64_t p = rb + lane; p < re; p += WAVE) {
+    int s = 0;
+    for (int64_t p = rb + lane; p < re; p += WAVE, ++s) {
         const int j = col[p];
         const double x = static_cast<double>(d2[p]) * inv / static_cast<double>(rho[j]);
-        acc.add(static_cast<double>(expf(-static_cast<float>(x))) * qai * qa[j]);
+        const double kt = static_cast<double>(expf(-static_cast<float>(x))) * qai * qa[j];
+#pragma unroll
+        for (int u = 0; u < KEEP; ++u)
+            if (s == u) kv[u] = kt;
+        acc.add(kt);
     }
     double Ds = acc.s, Dc = acc.c;
 #pragma unroll
@@ -505,10 +514,17 @@ __global__ __launch_bounds__(256) void k_assemble_rows(const int64_t* __restrict
     }
     const double Di = Ds + Dc;
     const double Pi = 0.5 * ri;
-    for (int64_t p = rb + lane; p < re; p += WAVE) {
+    s = 0;
+    for (int64_t p = rb + lane; p < re; p += WAVE, ++s) {
         const int j = col[p];
-        const double x = static_cast<double>(d2[p]) * inv / static_cast<double>(rho[j]);
-        const double kt = static_cast<double>(expf(-static_cast<float>(x))) * qai * qa[j];
+        double kt = 0.0;
+#pragma unroll
+        for (int u = 0; u < KEEP; ++u)
+            if (s == u) kt = kv[u];
+        if (s >= KEEP) {
+            const double x = static_cast<double>(d2[p]) * inv / static_cast<double>(rho[j]);
+            kt = static_cast<double>(expf(-static_cast<float>(x))) * qai * qa[j];
+        }
         double w;
         if (out_kind == KVB_OUT_MARKOV)
             w = kt / Di;
@@ -634,13 +650,20 @@ hipError_t launch_density_csr(const int64_t* rowptr, const int32_t* col, const f
     return hipGetLastError();
 }
 
-hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, int64_t nnz,
-                          const float* rho, int G, double e_min, double e_max, const double* scale_dev,
-                          double* partial, TuneResult* out, hipStream_t st)
+int chi_csr_blocks(int64_t nnz_hint, int64_t nnz_cap)
 {
-    const int nb = chi_num_blocks(nnz);
-    hipLaunchKernelGGL(k_chi_partial<true>, dim3(nb), dim3(CHI_BLOCK), 0, st, col, d2, rowptr, n, rho, nnz, 0, G,
-                       e_min, e_max, scale_dev, chi_per_block(nnz), partial);
+    const int64_t per = chi_per_block(nnz_hint);
+    return static_cast<int>((nnz_cap + per - 1) / per);
+}
+
+hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, int64_t nnz_hint,
+                          int64_t nnz_cap, const float* rho, int G, double e_min, double e_max,
+                          const double* scale_dev, double* partial, TuneResult* out, hipStream_t st)
+{
+    // blocks sized for the expected count; enough of them for the largest
+    const int nb = chi_csr_blocks(nnz_hint, nnz_cap);
+    hipLaunchKernelGGL(k_chi_partial<true>, dim3(nb), dim3(CHI_BLOCK), 0, st, col, d2, rowptr, n, rho, nnz_cap, 0, G,
+                       e_min, e_max, scale_dev, chi_per_block(nnz_hint), partial);
     hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, out);
     return hipGetLastError();
 }

@@ -6,30 +6,34 @@
 // union pattern stores, in row i, every j with j in N(i) or i in N(j), each
 // once, columns ascending, with the squared distance of the pair.
 //
-// The transpose-merge runs in five data-parallel steps, none of which depends
+// The transpose-merge runs in data-parallel steps whose result does not depend
 // on the order in which atomics land:
 //   1. each directed row is sorted by column (one wavefront per row);
 //   2. every entry (i, j), j != i, looks i up in the sorted row j by binary
 //      search; when it is absent, (j, i) is an entry that only the transpose
-//      contributes: row j's count is incremented and the pair is appended to
-//      a list (the append order is arbitrary);
+//      contributes ("reverse entry"): the entry is flagged and row j's count
+//      incremented;
 //   3. an exclusive scan of the counts gives each row's reverse segment and
 //      rowptr_i = i k + (reverse entries of rows before i);
-//   4. a radix sort of the appended pairs by (row, column) puts each row's
-//      reverse entries in its segment, columns ascending;
-//   5. every entry's place in its merged row is its rank in its own sorted
+//   4. the flagged entries are dropped into their rows' segments (slot order
+//      arbitrary) as keys i << 32 | bits of d2;
+//   5. each segment is sorted (a wavefront in registers up to 256 entries;
+//      longer segments, which only hubs of the k-NN graph have, by a
+//      workgroup in global memory), so it no longer depends on the slots;
+//   6. every entry's place in its merged row is its rank in its own sorted
 //      list plus the number of entries of the other list with a smaller
 //      column (a binary search); the two lists are disjoint, so the places
 //      are distinct.
-// The HBM traffic is a few passes over the n k entries plus the sort of the
-// reverse entries; the binary searches gather from rows that stay in L2.
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
-
+// No step needs the number of reverse entries on the host, so the whole
+// construction can be enqueued without a round trip.
 #include "kvb_device.h"
 #include "kvb_kernels.h"
 
+#include <rocprim/device/device_scan.hpp>
+
 namespace kvb {
+
+constexpr int SEG_SHORT = 4 * WAVE;   // reverse segments sorted in registers
 
 // 1. directed row i sorted by column: key = column << 32 | bits of d2
 template <int E>
@@ -74,32 +78,45 @@ __device__ __forceinline__ int64_t count_less(const int32_t* __restrict__ a, int
     return lo;
 }
 
-// 2. entries that only the transpose contributes: (j, i) with j in N(i), i not in N(j).
-// stats[0] counts them; stats[1] becomes non-zero if a row holds a column
+// the same over keys whose high word is the column
+__device__ __forceinline__ int64_t count_less_key(const uint64_t* __restrict__ a, int64_t len, int32_t v)
+{
+    int64_t lo = 0, hi = len;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (static_cast<int32_t>(a[mid] >> 32) < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// 2. flag[p] = 1 for entries (i, j) whose transpose (j, i) row j does not
+// store; cnt[j] counts them. bad becomes non-zero if a row holds a column
 // outside [0, n) or the same column twice (such entries are skipped, so no
 // access leaves the arrays).
-__global__ __launch_bounds__(256) void k_union_count(const int32_t* __restrict__ scol, const float* __restrict__ sd2,
-                                                     int n, int k, int bits, int* __restrict__ cnt,
-                                                     unsigned long long* __restrict__ stats,
-                                                     uint64_t* __restrict__ rkey, float* __restrict__ rd2)
+__global__ __launch_bounds__(256) void k_union_count(const int32_t* __restrict__ scol, int n, int k,
+                                                     int* __restrict__ cnt, uint8_t* __restrict__ flag,
+                                                     unsigned long long* __restrict__ bad)
 {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= static_cast<int64_t>(n) * k) return;
     const int i = static_cast<int>(p / k);
     const int r = static_cast<int>(p - static_cast<int64_t>(i) * k);
     const int j = scol[p];
+    uint8_t f = 0;
     if (j < 0 || j >= n || (r > 0 && scol[p - 1] == j)) {
-        atomicOr(stats + 1, 1ull);
-        return;
+        atomicOr(bad, 1ull);
+    } else if (j != i) {
+        const int32_t* rj = scol + static_cast<size_t>(j) * k;
+        const int64_t at = count_less(rj, k, i);
+        if (!(at < k && rj[at] == i)) {   // row j does not store (j, i) itself
+            atomicAdd(cnt + j, 1);
+            f = 1;
+        }
     }
-    if (j == i) return;
-    const int32_t* rj = scol + static_cast<size_t>(j) * k;
-    const int64_t at = count_less(rj, k, i);
-    if (at < k && rj[at] == i) return;   // mutual: row j stores (j, i) itself
-    atomicAdd(cnt + j, 1);
-    const unsigned long long slot = atomicAdd(stats, 1ull);
-    rkey[slot] = (static_cast<uint64_t>(j) << bits) | static_cast<uint64_t>(i);
-    rd2[slot] = sd2[p];
+    flag[p] = f;
 }
 
 // 3. rowptr_i = i k + revptr_i (revptr: exclusive scan of the counts, n + 1 entries)
@@ -110,12 +127,138 @@ __global__ __launch_bounds__(256) void k_union_rowptr(const int64_t* __restrict_
     if (i <= n) rowptr[i] = static_cast<int64_t>(i) * k + revptr[i];
 }
 
-// 5a. a directed entry's place: its rank r in the sorted row plus the reverse
+// 4. the flagged entries into their rows' reverse segments (fill: zeroed counts)
+__global__ __launch_bounds__(256) void k_union_fill(const int32_t* __restrict__ scol, const float* __restrict__ sd2,
+                                                    const uint8_t* __restrict__ flag, int n, int k,
+                                                    const int64_t* __restrict__ revptr, int* __restrict__ fill,
+                                                    uint64_t* __restrict__ rkey)
+{
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= static_cast<int64_t>(n) * k || !flag[p]) return;
+    const int i = static_cast<int>(p / k);
+    const int j = scol[p];
+    const int64_t slot = revptr[j] + atomicAdd(fill + j, 1);
+    rkey[slot] = (static_cast<uint64_t>(static_cast<uint32_t>(i)) << 32) | __float_as_uint(sd2[p]);
+}
+
+// a reverse entry's place in row j: its rank t in the sorted segment plus the
+// directed entries of row j with a smaller column
+__device__ __forceinline__ void place_reverse(uint64_t key, int64_t t, int j, int k, const int32_t* __restrict__ scol,
+                                             const int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                             float* __restrict__ ud2)
+{
+    const int32_t c = static_cast<int32_t>(key >> 32);
+    const int64_t at = rowptr[j] + t + count_less(scol + static_cast<size_t>(j) * k, k, c);
+    col[at] = c;
+    ud2[at] = __uint_as_float(static_cast<uint32_t>(key));
+}
+
+// 5a + 6. segments of up to 256 entries: one wavefront per row sorts the
+// segment in registers, writes it back sorted (the directed entries' places
+// need it) and places its entries. Longer segments are listed for 5b.
+template <int E>
+__device__ __forceinline__ void sort_place_segment(uint64_t* __restrict__ seg, int L, int j, int k,
+                                                   const int32_t* __restrict__ scol,
+                                                   const int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                   float* __restrict__ ud2)
+{
+    const int lane = lane_id();
+    uint64_t key[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int t = s * WAVE + lane;
+        key[s] = t < L ? seg[t] : ~0ull;
+    }
+    bitonic_sort<E>(key);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int t = s * WAVE + lane;
+        if (t < L) {
+            seg[t] = key[s];
+            place_reverse(key[s], t, j, k, scol, rowptr, col, ud2);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_union_segments(uint64_t* __restrict__ rkey, int n, int k,
+                                                        const int64_t* __restrict__ revptr,
+                                                        const int32_t* __restrict__ scol,
+                                                        const int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                        float* __restrict__ ud2, int* __restrict__ long_count,
+                                                        int* __restrict__ long_rows)
+{
+    const int j = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (j >= n) return;
+    const int64_t b = revptr[j];
+    const int64_t L = revptr[j + 1] - b;
+    if (L == 0) return;
+    if (L <= WAVE)
+        sort_place_segment<1>(rkey + b, static_cast<int>(L), j, k, scol, rowptr, col, ud2);
+    else if (L <= SEG_SHORT)
+        sort_place_segment<4>(rkey + b, static_cast<int>(L), j, k, scol, rowptr, col, ud2);
+    else if (lane_id() == 0)
+        long_rows[atomicAdd(long_count, 1)] = j;
+}
+
+// 5b + 6. a workgroup per listed row sorts its segment in global memory with
+// a bitonic network in which every comparator puts the smaller key first
+// (each merge stage starts by comparing mirrored positions), so positions at
+// or past L act as +inf and need not exist; then it places the entries.
+// The barriers order the workgroup's global accesses (one compute unit).
+__global__ __launch_bounds__(256) void k_union_long_segments(uint64_t* __restrict__ rkey,
+                                                             const int64_t* __restrict__ revptr, int k,
+                                                             const int32_t* __restrict__ scol,
+                                                             const int64_t* __restrict__ rowptr,
+                                                             int32_t* __restrict__ col, float* __restrict__ ud2,
+                                                             const int* __restrict__ long_count,
+                                                             const int* __restrict__ long_rows)
+{
+    const int count = *long_count;
+    for (int q = blockIdx.x; q < count; q += gridDim.x) {
+        const int j = long_rows[q];
+        const int64_t b = revptr[j];
+        const int64_t L = revptr[j + 1] - b;
+        uint64_t* seg = rkey + b;
+        int64_t P = 1;
+        while (P < L) P <<= 1;
+        for (int64_t kb = 2; kb <= P; kb <<= 1) {
+            for (int64_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const int64_t h = kb >> 1, blk = t / h, off = t - blk * h;
+                const int64_t a = blk * kb + off, c = blk * kb + kb - 1 - off;
+                if (c < L) {
+                    const uint64_t x = seg[a], y = seg[c];
+                    if (x > y) {
+                        seg[a] = y;
+                        seg[c] = x;
+                    }
+                }
+            }
+            __syncthreads();
+            for (int64_t jj = kb >> 2; jj > 0; jj >>= 1) {
+                for (int64_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                    const int64_t a = (t / jj) * 2 * jj + (t % jj), c = a + jj;
+                    if (c < L) {
+                        const uint64_t x = seg[a], y = seg[c];
+                        if (x > y) {
+                            seg[a] = y;
+                            seg[c] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int64_t t = threadIdx.x; t < L; t += blockDim.x) place_reverse(seg[t], t, j, k, scol, rowptr, col, ud2);
+        __syncthreads();
+    }
+}
+
+// 6. a directed entry's place: its rank r in the sorted row plus the reverse
 // entries of the row with a smaller column
 __global__ __launch_bounds__(256) void k_union_place_direct(const int32_t* __restrict__ scol,
                                                             const float* __restrict__ sd2, int n, int k,
                                                             const int64_t* __restrict__ revptr,
-                                                            const int32_t* __restrict__ rcol,
+                                                            const uint64_t* __restrict__ rkey,
                                                             const int64_t* __restrict__ rowptr,
                                                             int32_t* __restrict__ col, float* __restrict__ ud2)
 {
@@ -125,36 +268,9 @@ __global__ __launch_bounds__(256) void k_union_place_direct(const int32_t* __res
     const int r = static_cast<int>(p - static_cast<int64_t>(i) * k);
     const int32_t c = scol[p];
     const int64_t rb = revptr[i];
-    const int64_t at = rowptr[i] + r + count_less(rcol + rb, revptr[i + 1] - rb, c);
+    const int64_t at = rowptr[i] + r + count_less_key(rkey + rb, revptr[i + 1] - rb, c);
     col[at] = c;
     ud2[at] = sd2[p];
-}
-
-// 5b. a reverse entry's place: its rank in the row's reverse segment plus the
-// directed entries of the row with a smaller column. The sorted keys are
-// row << bits | column; rcol receives the columns for 5a.
-__global__ __launch_bounds__(256) void k_union_split_keys(const uint64_t* __restrict__ skey, int64_t total, int bits,
-                                                          int32_t* __restrict__ rcol)
-{
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t < total) rcol[t] = static_cast<int32_t>(skey[t] & ((1ull << bits) - 1));
-}
-
-__global__ __launch_bounds__(256) void k_union_place_reverse(const uint64_t* __restrict__ skey,
-                                                             const float* __restrict__ srd2, int64_t total, int bits,
-                                                             const int32_t* __restrict__ scol, int k,
-                                                             const int64_t* __restrict__ revptr,
-                                                             const int64_t* __restrict__ rowptr,
-                                                             int32_t* __restrict__ col, float* __restrict__ ud2)
-{
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    const uint64_t key = skey[t];
-    const int j = static_cast<int>(key >> bits);
-    const int32_t c = static_cast<int32_t>(key & ((1ull << bits) - 1));
-    const int64_t at = rowptr[j] + (t - revptr[j]) + count_less(scol + static_cast<size_t>(j) * k, k, c);
-    col[at] = c;
-    ud2[at] = srd2[t];
 }
 
 // Shape of a caller's CSR pattern: bad |= 1 unless rowptr_0 = 0, rowptr_n = nnz
@@ -180,33 +296,7 @@ __global__ __launch_bounds__(256) void k_check_csr(const int64_t* __restrict__ r
 // ------------------------------------------------------------------ launchers
 static unsigned grid_of(int64_t cnt) { return static_cast<unsigned>((cnt + 255) / 256); }
 
-int union_key_bits(int n)
-{
-    int b = 1;
-    while ((int64_t(1) << b) < n) ++b;
-    return b;
-}
-
-hipError_t launch_union_count(const int32_t* idx, const float* d2, int n, int k, int32_t* scol, float* sd2, int* cnt,
-                              unsigned long long* stats, uint64_t* rkey, float* rd2, hipStream_t st)
-{
-    const dim3 rows((n + 3) / 4), block(256);
-    if (k <= 64)
-        hipLaunchKernelGGL((k_union_sort_rows<1>), rows, block, 0, st, idx, d2, n, k, scol, sd2);
-    else if (k <= 128)
-        hipLaunchKernelGGL((k_union_sort_rows<2>), rows, block, 0, st, idx, d2, n, k, scol, sd2);
-    else
-        hipLaunchKernelGGL((k_union_sort_rows<4>), rows, block, 0, st, idx, d2, n, k, scol, sd2);
-    // n + 1 counts: the last stays zero, so the scan's last entry is the total
-    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int) * (static_cast<size_t>(n) + 1), st);
-    if (e != hipSuccess) return e;
-    e = hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), st);
-    if (e != hipSuccess) return e;
-    const int64_t nk = static_cast<int64_t>(n) * k;
-    hipLaunchKernelGGL(k_union_count, dim3(grid_of(nk)), block, 0, st, scol, sd2, n, k, union_key_bits(n), cnt, stats,
-                       rkey, rd2);
-    return hipGetLastError();
-}
+constexpr int LONG_SEGMENT_BLOCKS = 256;
 
 size_t union_scan_bytes(int n)
 {
@@ -216,43 +306,46 @@ size_t union_scan_bytes(int n)
     return b;
 }
 
-size_t union_sort_bytes(int64_t cap)
+hipError_t launch_union_count(const int32_t* idx, const float* d2, int n, int k, const UnionWork& w, hipStream_t st)
 {
-    size_t b = 0;
-    (void)rocprim::radix_sort_pairs(nullptr, b, static_cast<const uint64_t*>(nullptr), static_cast<uint64_t*>(nullptr),
-                                    static_cast<const float*>(nullptr), static_cast<float*>(nullptr),
-                                    static_cast<size_t>(cap), 0u, 64u, nullptr);
-    return b;
-}
-
-// cnt must hold n + 1 entries, the last zero: its scan is the total
-hipError_t launch_union_scan(void* tmp, size_t tmp_bytes, const int* cnt, int n, int k, int64_t* revptr,
-                             int64_t* rowptr, hipStream_t st)
-{
-    hipError_t e = rocprim::exclusive_scan(tmp, tmp_bytes, cnt, revptr, int64_t(0), static_cast<size_t>(n) + 1,
-                                           rocprim::plus<int64_t>(), st);
+    const dim3 rows((n + 3) / 4), block(256);
+    if (k <= 64)
+        hipLaunchKernelGGL((k_union_sort_rows<1>), rows, block, 0, st, idx, d2, n, k, w.scol, w.sd2);
+    else if (k <= 128)
+        hipLaunchKernelGGL((k_union_sort_rows<2>), rows, block, 0, st, idx, d2, n, k, w.scol, w.sd2);
+    else
+        hipLaunchKernelGGL((k_union_sort_rows<4>), rows, block, 0, st, idx, d2, n, k, w.scol, w.sd2);
+    // n + 1 counts: the last stays zero, so the scan's last entry is the total
+    hipError_t e = hipMemsetAsync(w.cnt, 0, sizeof(int) * (static_cast<size_t>(n) + 1), st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_union_rowptr, dim3(grid_of(int64_t(n) + 1)), dim3(256), 0, st, revptr, n, k, rowptr);
+    e = hipMemsetAsync(w.bad, 0, sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+    const int64_t nk = static_cast<int64_t>(n) * k;
+    hipLaunchKernelGGL(k_union_count, dim3(grid_of(nk)), block, 0, st, w.scol, n, k, w.cnt, w.flag, w.bad);
+    size_t scan_bytes = w.scan_bytes;
+    e = rocprim::exclusive_scan(w.scan_tmp, scan_bytes, w.cnt, w.revptr, int64_t(0), static_cast<size_t>(n) + 1,
+                                rocprim::plus<int64_t>(), st);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
-hipError_t launch_union_place(void* tmp, size_t tmp_bytes, const uint64_t* rkey, uint64_t* skey, const float* rd2,
-                              float* srd2, int64_t total, const int32_t* scol, const float* sd2, int n, int k,
-                              const int64_t* revptr, const int64_t* rowptr, int32_t* rcol, int32_t* col, float* ud2,
+hipError_t launch_union_place(int n, int k, const UnionWork& w, int64_t* rowptr, int32_t* col, float* ud2,
                               hipStream_t st)
 {
-    const int bits = union_key_bits(n);
-    if (total > 0) {
-        hipError_t e = rocprim::radix_sort_pairs(tmp, tmp_bytes, rkey, skey, rd2, srd2, static_cast<size_t>(total),
-                                                 0u, static_cast<unsigned>(2 * bits), st);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_union_split_keys, dim3(grid_of(total)), dim3(256), 0, st, skey, total, bits, rcol);
-        hipLaunchKernelGGL(k_union_place_reverse, dim3(grid_of(total)), dim3(256), 0, st, skey, srd2, total, bits,
-                           scol, k, revptr, rowptr, col, ud2);
-    }
     const int64_t nk = static_cast<int64_t>(n) * k;
-    hipLaunchKernelGGL(k_union_place_direct, dim3(grid_of(nk)), dim3(256), 0, st, scol, sd2, n, k, revptr, rcol,
-                       rowptr, col, ud2);
+    hipLaunchKernelGGL(k_union_rowptr, dim3(grid_of(int64_t(n) + 1)), dim3(256), 0, st, w.revptr, n, k, rowptr);
+    hipError_t e = hipMemsetAsync(w.cnt, 0, sizeof(int) * (static_cast<size_t>(n) + 1), st);   // fill counts
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(w.long_count, 0, sizeof(int), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_union_fill, dim3(grid_of(nk)), dim3(256), 0, st, w.scol, w.sd2, w.flag, n, k, w.revptr, w.cnt,
+                       w.rkey);
+    hipLaunchKernelGGL(k_union_segments, dim3((n + 3) / 4), dim3(256), 0, st, w.rkey, n, k, w.revptr, w.scol, rowptr,
+                       col, ud2, w.long_count, w.long_rows);
+    hipLaunchKernelGGL(k_union_long_segments, dim3(LONG_SEGMENT_BLOCKS), dim3(256), 0, st, w.rkey, w.revptr, k, w.scol,
+                       rowptr, col, ud2, w.long_count, w.long_rows);
+    hipLaunchKernelGGL(k_union_place_direct, dim3(grid_of(nk)), dim3(256), 0, st, w.scol, w.sd2, n, k, w.revptr,
+                       w.rkey, rowptr, col, ud2);
     return hipGetLastError();
 }
 

@@ -27,7 +27,8 @@ KNN_F32, KNN_BF16, KNN_LEARNED = 0, 1, 2
 BW_ADHOC, BW_DENSITY = 0, 1
 OUT_MARKOV, OUT_GENERATOR, OUT_SYMMETRIC = 0, 1, 2
 ROW_RECHECK, ROW_FALLBACK, ROW_UNCERTIFIED = 1, 2, 4
-OPT_FORCE_FALLBACK, OPT_SCRATCH_LIMIT, OPT_BF16_SPLIT, OPT_N_PROBE, OPT_CURVE_ORDER = 1, 2, 3, 4, 5
+OPT_FORCE_FALLBACK, OPT_SCRATCH_LIMIT, OPT_BF16_SPLIT, OPT_N_PROBE, OPT_CURVE_ORDER, OPT_PATTERN = 1, 2, 3, 4, 5, 6
+PATTERNS = {"knn": 0, "union": 1}
 MODES = {"f32": KNN_F32, "bf16": KNN_BF16, "learned": KNN_LEARNED}
 
 EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb_knn",
@@ -323,17 +324,23 @@ class KernelMatrix:
 
 def build(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float, e_min: float = 1e-3,
           e_max: float = 1e1, G: int = 64, mode: str = "f32", margin: int = 32, out_kind: int = OUT_MARKOV,
-          ctx: Context | None = None, out: KernelMatrix | None = None, sync: bool = True) -> KernelMatrix:
+          ctx: Context | None = None, out: KernelMatrix | None = None, sync: bool = True,
+          pattern: str = "knn") -> KernelMatrix:
     """The whole build in one library call (kvb_build): the same steps and results
-    as build_kernel_matrix, with the intermediate values kept on the device.
-    `out` (a previous result of the same n and k) lends its device arrays.
-    sync=False only enqueues the work (the tuning results of the returned
-    matrix are then None; build_info(ctx) waits and returns them)."""
+    as build_kernel_matrix (pattern "knn") or build_union_matrix (pattern
+    "union", the symmetric E u E^T), with the intermediate values kept on the
+    device. `out` (a previous result of the same n, k and pattern) lends its
+    device arrays. sync=False only enqueues the work (the tuning results of the
+    returned matrix are then None; build_info(ctx) waits and returns them; with
+    the union pattern col and val then keep their capacity n (2k - 1) and
+    rowptr[n] is the stored count)."""
     ctx = ctx or context()
     X = _dev(X, torch.float32, "X")
     n, m = X.shape
     dev = X.device
-    if out is not None and out.idx.shape == (n, k) and out.idx.device == dev:
+    cap = n * k if pattern == "knn" else n * (2 * k - 1)
+    ctx.check(ctx.lib.kvb_set_option(ctx.h, OPT_PATTERN, PATTERNS[pattern]))
+    if out is not None and out.idx.shape == (n, k) and out.idx.device == dev and out.col.numel() == cap:
         idx, d2, flags, b, rho, psi = out.idx, out.d2, out.flags, out.b, out.rho, out.psi
         rowptr, col, val, P, D = out.rowptr, out.col, out.val, out.P, out.D
     else:
@@ -344,8 +351,8 @@ def build(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float,
         rho = torch.empty(n, dtype=torch.float32, device=dev)
         psi = torch.empty(n, dtype=torch.float32, device=dev)
         rowptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
-        col = torch.empty(n * k, dtype=torch.int32, device=dev)
-        val = torch.empty(n * k, dtype=torch.float32, device=dev)
+        col = torch.empty(cap, dtype=torch.int32, device=dev)
+        val = torch.empty(cap, dtype=torch.float32, device=dev)
         P = torch.empty(n, dtype=torch.float64, device=dev)
         D = torch.empty(n, dtype=torch.float64, device=dev)
     chi_a = np.zeros(G, dtype=np.float64)
@@ -359,6 +366,9 @@ def build(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float,
     if not sync:
         return KernelMatrix(idx, d2, flags, b, None, rho, psi, None, None, rowptr, col, val, P, D)
     ta, s, tb = _tunings(chi_a, chi_b, info, G)
+    if pattern != "knn":
+        nnz = int(rowptr[n].item())
+        col, val = col[:nnz], val[:nnz]
     return KernelMatrix(idx, d2, flags, b, ta, rho, psi, s, tb, rowptr, col, val, P, D)
 
 

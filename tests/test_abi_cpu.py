@@ -66,7 +66,9 @@ def test_header_constants_match_binding():
              "KVB_OUT_SYMMETRIC": kvb.OUT_SYMMETRIC, "KVB_ROW_RECHECK": kvb.ROW_RECHECK,
              "KVB_ROW_FALLBACK": kvb.ROW_FALLBACK, "KVB_OPT_FORCE_FALLBACK": kvb.OPT_FORCE_FALLBACK,
              "KVB_OPT_SCRATCH_LIMIT": kvb.OPT_SCRATCH_LIMIT, "KVB_OPT_BF16_SPLIT": kvb.OPT_BF16_SPLIT,
-             "KVB_OPT_N_PROBE": kvb.OPT_N_PROBE, "KVB_OPT_CURVE_ORDER": kvb.OPT_CURVE_ORDER, "KVB_ROW_UNCERTIFIED": kvb.ROW_UNCERTIFIED,
+             "KVB_OPT_N_PROBE": kvb.OPT_N_PROBE, "KVB_OPT_CURVE_ORDER": kvb.OPT_CURVE_ORDER,
+             "KVB_OPT_PATTERN": kvb.OPT_PATTERN, "KVB_PATTERN_KNN": kvb.PATTERNS["knn"],
+             "KVB_PATTERN_UNION": kvb.PATTERNS["union"], "KVB_ROW_UNCERTIFIED": kvb.ROW_UNCERTIFIED,
              "KVB_E_NOT_TRAINED": kvb.E_NOT_TRAINED, "KVB_E_IO": kvb.E_IO,
              "KVB_PROF_SLOTS": kvb.PROF_SLOTS}
     for k, v in pairs.items():

@@ -131,6 +131,44 @@ def hub_pattern(n, k):
     return idx, d2
 
 
+def test_union_reverse_segment_lengths(gpu_lib):
+    """Reverse segments of 1-64, 65-256 and over 256 entries (the three sort
+    paths) in one pattern: rows 0, 1, 2 are listed by 50, 200 and 1000 other
+    rows that they do not list themselves."""
+    n, k = 3000, 8
+    idx = np.empty((n, k), dtype=np.int32)
+    for i in range(n):
+        row = [i]
+        hub = 0 if 100 <= i < 150 else 1 if 200 <= i < 400 else 2 if 1000 <= i < 2000 else -1
+        if hub >= 0:
+            row.append(hub)
+        j = i + 3
+        while len(row) < k:
+            c = j % n
+            if c not in row and c > 2:
+                row.append(c)
+            j += 1
+        idx[i] = row
+    d2 = (np.arange(n * k).reshape(n, k) % 97 * 0.01).astype(np.float32)
+    d2[:, 0] = 0
+    say("[union] reverse segments of 50, 200 and 1000 entries")
+    gpat = gpu_lib.union_pattern(torch.from_numpy(idx).cuda(), torch.from_numpy(d2).cuda())
+    # the distance of a pair stored in both directions differs here, so only
+    # the pattern is compared, and the distances of the hub rows' reverse entries
+    rpat = spectral.union_pattern(idx, d2.astype(np.float64))
+    np.testing.assert_array_equal(gpat.rowptr.cpu().numpy(), rpat.rowptr)
+    np.testing.assert_array_equal(gpat.col.cpu().numpy(), rpat.col)
+    lens = np.diff(rpat.rowptr)[:3]
+    assert lens.tolist() == [k + 50, k + 200, k + 1000]
+    gd = gpat.d2.cpu().numpy()
+    for h in range(3):
+        for t in range(rpat.rowptr[h], rpat.rowptr[h + 1]):
+            c = rpat.col[t]
+            if c not in idx[h]:   # a reverse entry: its distance comes from row c
+                r = int(np.nonzero(idx[c] == h)[0][0])
+                assert gd[t] == d2[c, r], (h, c)
+
+
 def test_union_hub_rows_and_csr_passes(gpu_lib):
     """Rows far longer than k (in-degree n) through the pattern build and all
     three CSR passes, against the oracle's passes on the same pattern."""
@@ -236,3 +274,47 @@ def test_union_deterministic(gpu_lib):
         assert torch.equal(getattr(a.pattern, f), getattr(b.pattern, f)), f
     for f in ("rho", "psi", "val", "P", "D"):
         assert torch.equal(getattr(a, f), getattr(b, f)), f
+
+
+@pytest.mark.parametrize("out_kind", [0, 1, 2])
+def test_single_call_union_build_matches_separate_calls(gpu_lib, out_kind):
+    """kvb_build with the union pattern enqueues the same passes without a host
+    round trip (its transpose sort runs over all n k slots); only the block
+    partition of the tuning sums differs, so those agree to rounding and every
+    other result bit for bit."""
+    kvb = gpu_lib
+    w = workloads.WORKLOADS["torus_n100k"]
+    X = torch.from_numpy(workloads.torus(20000, seed=3)).cuda()
+    say(f"[union] single call, kind {out_kind}")
+    a = kvb.build_union_matrix(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G, out_kind=out_kind)
+    b = kvb.build(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G, out_kind=out_kind,
+                  pattern="union")
+    assert torch.equal(a.pattern.rowptr, b.rowptr)
+    assert torch.equal(a.pattern.col, b.col)
+    np.testing.assert_allclose(b.tune_a.chi, a.tune_a.chi, rtol=1e-12)
+    np.testing.assert_allclose(b.tune_b.chi, a.tune_b.chi, rtol=1e-12)
+    assert a.tune_a.e_star == b.tune_a.e_star and a.tune_b.e_star == b.tune_b.e_star
+    assert a.scale_b == b.scale_b
+    for f in ("b", "rho", "psi", "val", "P", "D"):
+        assert torch.equal(getattr(a, f), getattr(b, f)), f
+
+
+def test_union_async_builds_back_to_back(gpu_lib):
+    """Enqueued union builds (no host round trip) into the same arrays give the
+    synchronous result; the directed build on the same context is unchanged."""
+    kvb = gpu_lib
+    w = workloads.WORKLOADS["torus_n100k"]
+    X = torch.from_numpy(workloads.torus(30000, seed=4)).cuda()
+    ref = kvb.build(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G, pattern="union")
+    out = kvb.build(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G, pattern="union", sync=False)
+    for _ in range(3):
+        out = kvb.build(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G, pattern="union",
+                        sync=False, out=out)
+    ta, s, tb, fb = kvb.build_info(w.G)
+    nnz = int(out.rowptr[-1].item())
+    assert nnz == ref.col.numel()
+    assert torch.equal(out.col[:nnz], ref.col) and torch.equal(out.val[:nnz], ref.val)
+    assert ta.e_star == ref.tune_a.e_star and tb.e_star == ref.tune_b.e_star
+    d = kvb.build(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G)
+    assert d.col.numel() == X.shape[0] * w.k
+    assert torch.equal(d.rowptr, torch.arange(X.shape[0] + 1, device="cuda", dtype=torch.int64) * w.k)
