@@ -14,7 +14,8 @@ Conventions (the readings of the paper this oracle takes):
   * e denotes the paper's epsilon^2; one kernel exp(-D2/(e rho_i rho_j)) serves
     both stages, with rho = b (density) and rho = 2 psi^beta (operator).
   * Row i of the k-NN pattern is i itself followed by the k-1 nearest j != i in
-    (D2, j) order; all k entries are kept (no threshold truncation).
+    (D2, j) order; all k entries are kept unless a pattern is truncated
+    explicitly (``truncate``: Algorithm 1's sparsity tolerance).
   * The tuning grid is e_g = e_min (e_max/e_min)^{g/(G-1)}; the slope is the
     forward difference of ln chi over ln e; the optimum is its first maximum.
   * The operator-stage grid is rescaled by a power of two,
@@ -69,6 +70,9 @@ def lib():
     L.oracle_normalize.restype = ctypes.c_int
     L.oracle_sort_rows_by_col.argtypes = [_c_i64, _c_i32, _i32p, _f64p]
     L.oracle_sort_rows_by_col.restype = ctypes.c_int
+    L.oracle_truncate.argtypes = [_i64p, _i32p, _f64p, _f64p, _c_i64, _c_f64, _c_f64, _i64p, _i32p, _f64p,
+                                  ctypes.POINTER(_c_i64)]
+    L.oracle_truncate.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -187,6 +191,20 @@ def normalize(pat: Pattern, rho: np.ndarray, e: float, alpha: float, d: float,
     return val, q, P, D
 
 
+def truncate(pat: Pattern, rho: np.ndarray, e: float, delta: float) -> Pattern:
+    """The entries of `pat` whose kernel value exp(-D2/(e rho_i rho_j)) exceeds
+    delta (Section 4, Algorithm 1's sparsity tolerance), in their order."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    n = pat.n
+    rowptr = np.empty(n + 1, dtype=np.int64)
+    col = np.empty(len(pat.col), dtype=np.int32)
+    d2 = np.empty(len(pat.col), dtype=np.float64)
+    nnz = _c_i64()
+    _check(lib().oracle_truncate(pat.rowptr, pat.col, pat.dist2, rho, n, e, delta, rowptr, col, d2,
+                                 ctypes.byref(nnz)), "truncate")
+    return Pattern(rowptr, col[:nnz.value].copy(), d2[:nnz.value].copy())
+
+
 def sort_rows_by_col(col: np.ndarray, val: np.ndarray, k: int):
     col = np.ascontiguousarray(col, dtype=np.int32).copy()
     val = np.ascontiguousarray(val, dtype=np.float64).copy()
@@ -233,3 +251,21 @@ def pipeline(X: np.ndarray, k: int, k0: int, d: float, alpha: float, beta: float
     col, val = sort_rows_by_col(pat.col, val, k)
     return Result(idx, d2, b, ta, psi, rho, s, tb, q, P, D,
                   np.arange(n + 1, dtype=np.int64) * k, col, val)
+
+
+def truncated_build(base: Pattern, d2_knn: np.ndarray, k0: int, d: float, alpha: float, beta: float,
+                    delta: float, e_min: float = 1e-3, e_max: float = 1e1, G: int = 64, out_kind: int = MARKOV):
+    """The build with the sparsity tolerance delta_tol of Section 4: the tuning
+    sums run over the whole stored pattern `base`; the density kernel matrix
+    (at e_A) and the operator kernel matrix (at e_B) keep only their entries
+    above delta, and every row sum of the density, q and D runs over the kept
+    entries. The ad-hoc bandwidth comes from the k-NN distances d2_knn."""
+    b = adhoc_bandwidth(d2_knn, k0)
+    ta = chi(base, b, e_min, e_max, G)
+    pa = truncate(base, b, ta.e_star, delta)
+    psi, rho = density(pa, b, ta.e_star, d, beta)
+    s = grid_scale(b, rho)
+    tb = chi(base, rho, e_min * s, e_max * s, G)
+    pb = truncate(base, rho, tb.e_star, delta)
+    val, q, P, D = normalize(pb, rho, tb.e_star, alpha, d, out_kind)
+    return dict(b=b, ta=ta, pa=pa, psi=psi, rho=rho, s=s, tb=tb, pb=pb, val=val, q=q, P=P, D=D)

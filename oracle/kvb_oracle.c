@@ -29,9 +29,12 @@
  * uses rho = 2 psi^beta, which turns 4 epsilon^2 (psi_i psi_j)^beta into
  * e rho_i rho_j.
  *
+ *   truncate     keep K_ij > delta_tol only (Section 4, Algorithm 1)
+ *
  * The passes after the neighbour search take a general CSR pattern
- * (rowptr, col, dist2) so that the same code serves both the directed k-NN
- * pattern and the symmetrised union pattern used by the spectral checks.
+ * (rowptr, col, dist2) so that the same code serves the directed k-NN
+ * pattern, the symmetrised union pattern used by the spectral checks and
+ * their threshold-truncated forms.
  *
  * Summations run in a fixed sequential order so results are reproducible.
  * OpenMP parallelises only over independent rows.
@@ -312,6 +315,44 @@ int oracle_normalize(const int64_t* rowptr, const int32_t* col, const double* di
     if (P_out) memcpy(P_out, P, sizeof(double) * (size_t)n);
     if (D_out) memcpy(D_out, D, sizeof(double) * (size_t)n);
     free(q); free(P); free(D);
+    return ORC_OK;
+}
+
+/*
+ * Threshold truncation (Section 4: Algorithm 1 and the k-d tree algorithm
+ * store an entry only when its kernel value exceeds the sparsity tolerance
+ * delta_tol). Entry (i, j) of the pattern is kept when
+ * exp(-D2_ij / (e rho_i rho_j)) > delta, 0 < delta < 1. The test is taken on
+ * the exponent, x < -ln(delta), with x formed as (D2 * (1 / (e rho_i))) / rho_j
+ * in double precision: the equivalent strict inequality without the rounding
+ * of exp, and the same operations as the library's kernel, so that both sides
+ * take every keep/drop decision identically. Kept entries keep their order;
+ * rowptr_out (length n + 1) and the kept columns and distances are written.
+ * *nnz_out receives rowptr_out[n].
+ */
+int oracle_truncate(const int64_t* rowptr, const int32_t* col, const double* dist2, const double* rho, int64_t n,
+                    double e, double delta, int64_t* rowptr_out, int32_t* col_out, double* dist2_out,
+                    int64_t* nnz_out)
+{
+    if (!rowptr || !col || !dist2 || !rho || !rowptr_out || !col_out || !dist2_out || n < 1 || !(e > 0.0) ||
+        !(delta > 0.0 && delta < 1.0))
+        return ORC_EINVAL;
+    const double L = -log(delta);
+    int64_t out = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        rowptr_out[i] = out;
+        const double inv = 1.0 / (e * rho[i]);
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            const double x = dist2[p] * inv / rho[col[p]];
+            if (x < L) {
+                col_out[out] = col[p];
+                dist2_out[out] = dist2[p];
+                ++out;
+            }
+        }
+    }
+    rowptr_out[n] = out;
+    if (nnz_out) *nnz_out = out;
     return ORC_OK;
 }
 

@@ -202,6 +202,81 @@ def test_union_pattern_matches_set_definition(case):
         assert pat.rowptr[1] - pat.rowptr[0] == n
 
 
+# ------------------------------------------------------------------ threshold truncation
+def test_truncation_polygon_closed_form():
+    """Section 4 (Algorithm 1 keeps K_ij > delta_tol). On the regular n-gon
+    every row is the same circulant: with e rho^2 fixed, the kept entries are
+    exactly the chords with 4 sin^2(pi r / n) < -e rho^2 ln(delta)."""
+    n, k = 101, 9
+    X, idx, d2, chords = polygon_setup(n, k)
+    pat = oracle.Pattern.from_knn(idx, d2)
+    rho = np.full(n, 0.7)
+    e = 0.05
+    x = chords / (e * rho[0] ** 2)                  # exponents of the chords r = 1..4
+    for keep in range(0, len(chords) + 1):
+        # a threshold halfway between consecutive exponents: no rounding question
+        lo = x[keep - 1] if keep > 0 else 0.0
+        hi = x[keep] if keep < len(x) else x[-1] * 2
+        delta = math.exp(-0.5 * (lo + hi))
+        t = oracle.truncate(pat, rho, e, delta)
+        per_row = 1 + 2 * keep
+        assert (np.diff(t.rowptr) == per_row).all(), (keep, np.unique(np.diff(t.rowptr)))
+        for i in (0, 37, n - 1):
+            got = sorted(t.col[t.rowptr[i]:t.rowptr[i + 1]].tolist())
+            want = sorted({(i + s) % n for s in range(-keep, keep + 1)})
+            assert got == want
+        kept_d2 = np.sort(t.dist2[t.rowptr[5]:t.rowptr[6]])
+        np.testing.assert_array_equal(kept_d2, np.sort(d2[5, :per_row]))
+
+
+def test_truncation_matches_definition_and_limits():
+    """Kept set = {(i, j) : exp(-D2/(e rho_i rho_j)) > delta} on random samples
+    (checked with numpy's exp where the exponent is not within 1e-9 of the
+    threshold); a tiny delta keeps everything; delta near 1 keeps the diagonal."""
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((400, 3)).astype(np.float32)
+    idx, d2 = oracle.knn(X, 16)
+    pat = oracle.Pattern.from_knn(idx, d2)
+    rho = 0.5 + rng.random(400)
+    e = 0.3
+    delta = 0.05
+    t = oracle.truncate(pat, rho, e, delta)
+    rows = np.repeat(np.arange(400), 16)
+    K = np.exp(-pat.dist2 / (e * rho[rows] * rho[pat.col]))
+    xs = pat.dist2 / (e * rho[rows] * rho[pat.col])
+    assert np.abs(xs + math.log(delta)).min() > 1e-9
+    want = K > delta
+    kept = np.zeros(len(pat.col), dtype=bool)
+    for i in range(400):
+        cols = set(t.col[t.rowptr[i]:t.rowptr[i + 1]].tolist())
+        kept[i * 16:(i + 1) * 16] = [c in cols for c in pat.col[i * 16:(i + 1) * 16]]
+    np.testing.assert_array_equal(kept, want)
+    # order within a row is kept
+    for i in (0, 199):
+        np.testing.assert_array_equal(t.col[t.rowptr[i]:t.rowptr[i + 1]], pat.col[i * 16:(i + 1) * 16][want[i * 16:(i + 1) * 16]])
+    full = oracle.truncate(pat, rho, e, 1e-300)
+    np.testing.assert_array_equal(full.col, pat.col)
+    diag = oracle.truncate(pat, rho, e, 1 - 1e-12)
+    assert diag.col.tolist() == list(range(400))
+
+
+def test_truncated_markov_rows_and_invariants():
+    """The truncated build stays a Markov matrix with detailed balance on
+    mutual kept pairs (Section 2.2), and delta -> 0 gives the untruncated build."""
+    X = workloads.sphere2(600, seed=2)
+    idx, d2 = oracle.knn(X, 24)
+    base = oracle.Pattern.from_knn(idx, d2)
+    r = oracle.truncated_build(base, d2, 8, 2.0, -0.5, -0.5, 1e-2)
+    pb = r["pb"]
+    assert len(pb.col) < len(base.col)
+    rs = np.add.reduceat(r["val"], pb.rowptr[:-1])
+    np.testing.assert_allclose(rs, 1.0, atol=1e-13)
+    full = oracle.pipeline(X, 24, 8, 2.0, -0.5, -0.5)
+    r0 = oracle.truncated_build(base, d2, 8, 2.0, -0.5, -0.5, 1e-300)
+    np.testing.assert_allclose(r0["rho"], full.rho, rtol=1e-15)
+    assert r0["tb"].e_star == full.tune_b.e_star
+
+
 def test_union_symmetric_conjugate_similar_to_generator():
     X = workloads.sphere2(800, seed=4)
     A, info = spectral.union_operator(X, 24, 8, 2.0, -0.5, -0.5)
