@@ -263,6 +263,26 @@ int kvb_normalize_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, co
                       float* val, double* P, double* D);
 
 /*
+ * Threshold truncation (Section 4: Algorithm 1 stores an entry only when its
+ * kernel value exceeds the sparsity tolerance delta_tol). Entry (i, j) of the
+ * CSR pattern (rowptr, col, d2: as kvb_density_csr) is kept when
+ * exp(-d2 / (e rho_i rho_j)) > delta, 0 < delta < 1; the test is taken on the
+ * exponent, x < -ln(delta) with x = (d2 (1 / (e rho_i))) / rho_j in FP64 and
+ * ln on the host, so that a reference making the same operations takes every
+ * decision identically. Kept entries keep their order.
+ *   rho [n] float32 in; e > 0.
+ *   rowptr_out [n+1] int64 out; col_out [nnz] int32 out, d2_out [nnz] float32
+ *   out (capacity nnz always suffices; rowptr_out[n] entries are written).
+ *   nnz_host: host out or NULL.
+ * Checks the input pattern's shape as kvb_density_csr does (one
+ * synchronisation); with nnz_host non-NULL it synchronises again to report
+ * the count.
+ */
+int kvb_truncate_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* d2, const float* rho,
+                     int64_t n, int64_t nnz, double e, double delta, int64_t* rowptr_out, int32_t* col_out,
+                     float* d2_out, int64_t* nnz_host);
+
+/*
  * The whole build in one call, in the order of the paper's pipeline (Section 4
  * with the tuning of Section 2.3): k-NN (as kvb_knn) -> ad-hoc bandwidth b ->
  * e tuning on the density kernel over [e_min, e_max] -> density psi and
@@ -395,7 +415,8 @@ const char* kvb_version(void);
 #define KVB_PROF_ROUTE 10        /* learned mode: MLP logits and top-n_probe routing */
 #define KVB_PROF_BUCKETS 11      /* learned mode: bucket sort, candidate operand gather, work lists */
 #define KVB_PROF_UNION 12        /* union pattern: row sort, transpose count, scan, sort, merge */
-#define KVB_PROF_SLOTS 13
+#define KVB_PROF_TRUNCATE 13     /* threshold truncation: count, scan, ordered fill */
+#define KVB_PROF_SLOTS 14
 
 /* Turn event timing on (on != 0) or off; either way the totals restart at 0. */
 int kvb_profile_enable(kvb_ctx ctx, int32_t on);

@@ -18,7 +18,7 @@ namespace {
 const char* const kProfNames[KVB_PROF_SLOTS] = {
     "knn_select", "knn_refine", "knn_fallback", "adhoc_bandwidth", "chi_tuning", "density",
     "grid_scale", "q_pass", "assemble", "knn_prep",
-    "route", "bucket_build", "union_pattern",
+    "route", "bucket_build", "union_pattern", "truncate",
 };
 }  // namespace
 
@@ -546,6 +546,38 @@ static int check_pattern(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col,
     if (ctx->union_host[0] & 1)
         return fail(ctx, KVB_E_INVALID, "rowptr must start at 0, never decrease and end at nnz");
     if (ctx->union_host[0] & 2) return fail(ctx, KVB_E_INVALID, "col: a column lies outside [0, n)");
+    return KVB_OK;
+}
+
+int kvb_truncate_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* d2, const float* rho,
+                     int64_t n, int64_t nnz, double e, double delta, int64_t* rowptr_out, int32_t* col_out,
+                     float* d2_out, int64_t* nnz_host)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, e > 0 && std::isfinite(e), "e must be finite and > 0");
+    KVB_REQUIRE(ctx, delta > 0 && delta < 1, "delta must lie in (0, 1)");
+    KVB_REQUIRE(ctx, aligned(d2) && aligned(rho), "d2 and rho must be non-null device pointers");
+    KVB_REQUIRE(ctx, aligned(rowptr_out) && aligned(col_out) && aligned(d2_out),
+                "rowptr_out, col_out, d2_out must be non-null device pointers");
+    KVB_TRY(check_pattern(ctx, rowptr, col, n, nnz));
+    const int nn = static_cast<int>(n);
+    const size_t scan_bytes = kvb::union_scan_bytes(nn);
+    int rc = ensure_scratch(ctx, round256((size_t(nn) + 1) * sizeof(int)) + round256(scan_bytes) + 512);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    int* cnt = cv.take<int>(size_t(nn) + 1);
+    void* scan_tmp = cv.take<char>(scan_bytes);
+    {
+        Prof pr(ctx, KVB_PROF_TRUNCATE);
+        KVB_HIP(ctx, kvb::launch_truncate(rowptr, col, d2, rho, nn, e, nullptr, -std::log(delta), cnt, scan_tmp,
+                                          scan_bytes, rowptr_out, col_out, d2_out, ctx->stream));
+    }
+    if (nnz_host) {
+        KVB_HIP(ctx, hipMemcpyAsync(ctx->union_host, rowptr_out + nn, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        KVB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        *nnz_host = static_cast<int64_t>(ctx->union_host[0]);
+    }
     return KVB_OK;
 }
 

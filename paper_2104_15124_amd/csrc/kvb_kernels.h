@@ -193,6 +193,11 @@ hipError_t launch_union_count(const int32_t* idx, const float* d2, int n, int k,
 // steps 4-6 into rowptr [n + 1], col and ud2 [n k + revptr[n]]
 hipError_t launch_union_place(int n, int k, const UnionWork& w, int64_t* rowptr, int32_t* col, float* ud2,
                               hipStream_t st);
+// threshold truncation: keep x = d2 / (e rho_i rho_j) < L (L = -ln delta); cnt [n + 1]
+// and scan_tmp (union_scan_bytes(n)) are scratch; col_out, d2_out need rowptr[n] entries
+hipError_t launch_truncate(const int64_t* rowptr, const int32_t* col, const float* d2, const float* rho, int n,
+                           double e, const double* e_dev, double L, int* cnt, void* scan_tmp, size_t scan_bytes,
+                           int64_t* rowptr_out, int32_t* col_out, float* d2_out, hipStream_t st);
 hipError_t launch_check_csr(const int64_t* rowptr, const int32_t* col, int n, int64_t nnz, unsigned long long* bad,
                             hipStream_t st);
 hipError_t launch_density_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, const float* b,

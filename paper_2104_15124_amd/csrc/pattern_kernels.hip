@@ -1,4 +1,6 @@
-// The union pattern E u E^T of a directed k-NN pattern (gfx950).
+// Pattern transforms (gfx950): the union E u E^T of a directed k-NN pattern,
+// the threshold truncation of any CSR pattern, and the shape check of a
+// caller's CSR pattern.
 //
 // The paper's kernel matrix is symmetric: its brute-force construction sets
 // K_ij and K_ji together (Section 4, Algorithm 1). A k-NN row i stores the k
@@ -293,6 +295,65 @@ __global__ __launch_bounds__(256) void k_check_csr(const int64_t* __restrict__ r
     if (f) atomicOr(bad, f);
 }
 
+// ------------------------------------------------------------------ threshold truncation
+// Section 4: Algorithm 1 stores an entry only when its kernel value exceeds the
+// sparsity tolerance delta. Entry (i, j) is kept when x < L, L = -ln(delta)
+// (formed on the host), x = (d2 * (1 / (e rho_i))) / rho_j in float64: the
+// exponent form of exp(-x) > delta, free of the rounding of exp. One wavefront
+// per row; the fill keeps the row's order (ballot and prefix count).
+__device__ __forceinline__ bool trunc_keep(const float* __restrict__ d2, const int32_t* __restrict__ col,
+                                           const float* __restrict__ rho, int64_t p, double inv, double L)
+{
+    const double x = static_cast<double>(d2[p]) * inv / static_cast<double>(rho[col[p]]);
+    return x < L;
+}
+
+__global__ __launch_bounds__(256) void k_trunc_count(const int64_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col, const float* __restrict__ d2,
+                                                     const float* __restrict__ rho, int n, double e,
+                                                     const double* __restrict__ e_dev, double L,
+                                                     int* __restrict__ cnt)
+{
+    if (e_dev) e = *e_dev;
+    const int lane = lane_id();
+    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i >= n) return;
+    const double inv = 1.0 / (e * static_cast<double>(rho[i]));
+    int c = 0;
+    for (int64_t p = rowptr[i] + lane; p < rowptr[i + 1]; p += WAVE) c += trunc_keep(d2, col, rho, p, inv, L);
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) cnt[i] = c;
+    if (i == n - 1 && lane == 0) cnt[n] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_trunc_fill(const int64_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col, const float* __restrict__ d2,
+                                                    const float* __restrict__ rho, int n, double e,
+                                                    const double* __restrict__ e_dev, double L,
+                                                    const int64_t* __restrict__ rowptr_out,
+                                                    int32_t* __restrict__ col_out, float* __restrict__ d2_out)
+{
+    if (e_dev) e = *e_dev;
+    const int lane = lane_id();
+    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i >= n) return;
+    const double inv = 1.0 / (e * static_cast<double>(rho[i]));
+    int64_t out = rowptr_out[i];
+    const uint64_t below = (1ull << lane) - 1;
+    for (int64_t p0 = rowptr[i]; p0 < rowptr[i + 1]; p0 += WAVE) {
+        const int64_t p = p0 + lane;
+        const bool keep = p < rowptr[i + 1] && trunc_keep(d2, col, rho, p, inv, L);
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int64_t at = out + __popcll(m & below);
+            col_out[at] = col[p];
+            d2_out[at] = d2[p];
+        }
+        out += __popcll(m);
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 static unsigned grid_of(int64_t cnt) { return static_cast<unsigned>((cnt + 255) / 256); }
 
@@ -346,6 +407,20 @@ hipError_t launch_union_place(int n, int k, const UnionWork& w, int64_t* rowptr,
                        rowptr, col, ud2, w.long_count, w.long_rows);
     hipLaunchKernelGGL(k_union_place_direct, dim3(grid_of(nk)), dim3(256), 0, st, w.scol, w.sd2, n, k, w.revptr,
                        w.rkey, rowptr, col, ud2);
+    return hipGetLastError();
+}
+
+hipError_t launch_truncate(const int64_t* rowptr, const int32_t* col, const float* d2, const float* rho, int n,
+                           double e, const double* e_dev, double L, int* cnt, void* scan_tmp, size_t scan_bytes,
+                           int64_t* rowptr_out, int32_t* col_out, float* d2_out, hipStream_t st)
+{
+    const dim3 rows((n + 3) / 4), block(256);
+    hipLaunchKernelGGL(k_trunc_count, rows, block, 0, st, rowptr, col, d2, rho, n, e, e_dev, L, cnt);
+    hipError_t err = rocprim::exclusive_scan(scan_tmp, scan_bytes, cnt, rowptr_out, int64_t(0),
+                                             static_cast<size_t>(n) + 1, rocprim::plus<int64_t>(), st);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_trunc_fill, rows, block, 0, st, rowptr, col, d2, rho, n, e, e_dev, L, rowptr_out, col_out,
+                       d2_out);
     return hipGetLastError();
 }
 

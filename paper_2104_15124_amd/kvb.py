@@ -37,8 +37,9 @@ EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb
            "kvb_part_teacher", "kvb_part_train", "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
            "kvb_mlp_backward", "kvb_part_num_params", "kvb_part_get_params", "kvb_part_set_params",
            "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name",
-           "kvb_union_pattern", "kvb_density_csr", "kvb_tune_eps_csr", "kvb_normalize_csr")
-PROF_SLOTS = 13
+           "kvb_union_pattern", "kvb_density_csr", "kvb_tune_eps_csr", "kvb_normalize_csr",
+           "kvb_truncate_csr")
+PROF_SLOTS = 14
 
 
 class KvbError(RuntimeError):
@@ -83,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     L.kvb_density_csr.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _vp, _f64, _f64, _f64, _vp, _vp]
     L.kvb_tune_eps_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _i32, _vp,
                                    ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
+    L.kvb_truncate_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _vp, _vp, _vp,
+                                   ctypes.POINTER(_i64)]
     L.kvb_normalize_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _f64, _i32, _vp, _vp, _vp]
     _u64, _f32 = ctypes.c_uint64, ctypes.c_float
     L.kvb_part_init.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32, _u64]
@@ -443,6 +446,28 @@ def union_pattern(idx: torch.Tensor, d2: torch.Tensor, ctx: Context | None = Non
     return CsrPattern(rowptr, col[:nnz.value], ud2[:nnz.value])
 
 
+def knn_pattern(idx: torch.Tensor, d2: torch.Tensor) -> CsrPattern:
+    """The directed k-NN pattern as CSR (views of idx and d2; rows in distance order)."""
+    n, k = idx.shape
+    rowptr = torch.arange(n + 1, dtype=torch.int64, device=idx.device) * k
+    return CsrPattern(rowptr, _dev(idx, torch.int32, "idx").reshape(-1), _dev(d2, torch.float32, "d2").reshape(-1))
+
+
+def truncate_csr(pat: CsrPattern, rho: torch.Tensor, e: float, delta: float, ctx: Context | None = None) -> CsrPattern:
+    """The entries of `pat` whose kernel value exp(-d2/(e rho_i rho_j)) exceeds
+    delta, in their order (kvb_truncate_csr)."""
+    ctx = ctx or context()
+    rho = _dev(rho, torch.float32, "rho")
+    dev = rho.device
+    rowptr = torch.empty(pat.n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(pat.nnz, dtype=torch.int32, device=dev)
+    d2 = torch.empty(pat.nnz, dtype=torch.float32, device=dev)
+    nnz = _i64()
+    ctx.check(ctx.lib.kvb_truncate_csr(ctx.h, _ptr(pat.rowptr), _ptr(pat.col), _ptr(pat.d2), _ptr(rho), pat.n,
+                                       pat.nnz, e, delta, _ptr(rowptr), _ptr(col), _ptr(d2), ctypes.byref(nnz)))
+    return CsrPattern(rowptr, col[:nnz.value], d2[:nnz.value])
+
+
 def density_csr(pat: CsrPattern, b: torch.Tensor, e: float, d: float, beta: float, ctx: Context | None = None):
     """(rho, psi) over a CSR pattern (kvb_density_csr)."""
     ctx = ctx or context()
@@ -514,6 +539,50 @@ def build_union_matrix(X: torch.Tensor, k: int, k0: int, d: float, alpha: float,
     tb = tune_eps_csr(pat, rho, e_min * s, e_max * s, G, ctx)
     val, P, D = normalize_csr(pat, rho, tb.e_star, alpha, d, out_kind, ctx)
     return UnionMatrix(idx, d2, pat, b, ta, rho, psi, s, tb, val, P, D)
+
+
+@dataclass
+class TruncatedMatrix:
+    idx: torch.Tensor
+    d2: torch.Tensor
+    base: CsrPattern
+    b: torch.Tensor
+    tune_a: Tuning
+    density_pattern: CsrPattern
+    rho: torch.Tensor
+    psi: torch.Tensor
+    scale_b: float
+    tune_b: Tuning
+    pattern: CsrPattern
+    val: torch.Tensor
+    P: torch.Tensor
+    D: torch.Tensor
+
+
+def build_truncated_matrix(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float, delta: float,
+                           e_min: float = 1e-3, e_max: float = 1e1, G: int = 64, mode: str = "f32",
+                           margin: int = 32, out_kind: int = OUT_MARKOV, pattern: str = "knn",
+                           ctx: Context | None = None, knn_result=None) -> TruncatedMatrix:
+    """The build with the sparsity tolerance delta_tol of Section 4 on the k-NN
+    pattern (rows in distance order) or its union E u E^T (columns ascending):
+    the tuning sums run over the whole pattern; the density kernel matrix (at
+    e_A) and the operator kernel matrix (at e_B) keep only entries above delta,
+    and the density, q and D row sums run over the kept entries."""
+    ctx = ctx or context()
+    if knn_result is None:
+        idx, d2, _ = knn(X, k, mode, margin, ctx)
+    else:
+        idx, d2 = knn_result
+    b = bandwidth_adhoc(d2, k0, ctx)
+    base = knn_pattern(idx, d2) if pattern == "knn" else union_pattern(idx, d2, ctx)
+    ta = tune_eps_csr(base, b, e_min, e_max, G, ctx)
+    pa = truncate_csr(base, b, ta.e_star, delta, ctx)
+    rho, psi = density_csr(pa, b, ta.e_star, d, beta, ctx)
+    s = grid_scale(b, rho, ctx)
+    tb = tune_eps_csr(base, rho, e_min * s, e_max * s, G, ctx)
+    pb = truncate_csr(base, rho, tb.e_star, delta, ctx)
+    val, P, D = normalize_csr(pb, rho, tb.e_star, alpha, d, out_kind, ctx)
+    return TruncatedMatrix(idx, d2, base, b, ta, pa, rho, psi, s, tb, pb, val, P, D)
 
 
 # ------------------------------------------------------------------ learned partitioner
