@@ -66,6 +66,8 @@ def main() -> int:
                          "0 scans every tile")
     ap.add_argument("--pattern", default="knn", choices=["knn", "union"],
                     help="matrix pattern: the directed k-NN rows, or their union with the transpose (symmetric)")
+    ap.add_argument("--delta", type=float, default=0.0,
+                    help="sparsity tolerance: keep only kernel entries above it (0 keeps every entry)")
     ap.add_argument("--train-epochs", type=int, default=10, help="learned mode: partitioner training epochs")
     ap.add_argument("--n-probe", type=int, default=8,
                     help="learned mode: buckets each query searches (the configured top-4 gives recall "
@@ -132,7 +134,8 @@ def main() -> int:
         # the build is only enqueued (steps run back to back on the stream) and
         # its tuning results are read once, after the timed region
         prev[0] = kvb.build(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
-                            mode=w.mode, margin=w.margin, ctx=ctx, out=prev[0], sync=False, pattern=args.pattern)
+                            mode=w.mode, margin=w.margin, ctx=ctx, out=prev[0], sync=False, pattern=args.pattern,
+                            delta=args.delta)
         return prev[0]
 
     for _ in range(args.warmup):
@@ -202,8 +205,9 @@ def main() -> int:
     nk = float(w.n) * w.k
     kp = min(w.k + w.margin, w.n)
     union = args.pattern == "union"
-    nnz = float(r.rowptr[-1].item()) if union else nk
-    rows8 = float(w.n) * 8 if union else 0.0                       # rowptr reads of the CSR passes
+    csr = union or args.delta > 0
+    nnz = float(r.rowptr[-1].item()) if csr else nk
+    rows8 = float(w.n) * 8 if csr else 0.0                         # rowptr reads of the CSR passes
     pass_bytes = {
         "knn_refine": float(w.n) * kp * (w.m * 4 + 8) + nk * 8,    # candidate rows + keys, idx/d2 out
         "adhoc_bandwidth": float(w.n) * (w.k0 * 4 + 4),
@@ -211,11 +215,16 @@ def main() -> int:
         "density": nnz * 12 + float(w.n) * 12 + rows8,
         "q_pass": nnz * 12 + float(w.n) * 12 + rows8,
         # entries in / CSR out (the union pattern's columns are already written), P and D
-        "assemble": nnz * (16 + (4 if union else 8)) + float(w.n) * 16 + rows8,
+        "assemble": nnz * (16 + (4 if csr else 8)) + float(w.n) * 16 + rows8,
     }
     if union:
         # the directed rows in, the union's columns, distances and row pointers out
         pass_bytes["union_pattern"] = nk * 8 + nnz * 8 + float(w.n + 1) * 8
+    if args.delta > 0:
+        # two truncations of the base pattern: its entries read (col, d2, the
+        # gathered rho_j) twice, the kept entries written
+        base = float(nk) if not union else float(kvb.union_pattern(r.idx, r.d2, ctx).nnz)
+        pass_bytes["truncate"] = 2 * base * 12 + 2 * nnz * 8 + float(w.n) * 32
     passes = {}
     for name, byt in pass_bytes.items():
         ms, cnt = prof.get(name, (0.0, 0))
@@ -238,7 +247,13 @@ def main() -> int:
         if w.n <= 200_000:
             log("bench: timing the FP64 oracle on the host cores (whole workload, one run)")
             c0 = time.perf_counter()
-            if union:
+            if args.delta > 0:
+                from oracle import spectral
+                idx_o, d2_o = oracle.knn(X, w.k)
+                base_o = spectral.union_pattern(idx_o, d2_o) if union else oracle.Pattern.from_knn(idx_o, d2_o)
+                oracle.truncated_build(base_o, d2_o, w.k0, float(w.d), w.alpha, w.beta, args.delta, w.e_min,
+                                       w.e_max, w.G)
+            elif union:
                 from oracle import spectral
                 spectral.union_operator(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
                                         out_kind=oracle.MARKOV)
@@ -263,7 +278,8 @@ def main() -> int:
     out = {
         "metric": "kernel-matrix rows/s (kNN+VB kernel->CSR) at " + ("learned-routed kNN (recall reported)"
                                                                     if learned else "exact kNN sets")
-                  + (", union pattern E u E^T" if union else ""),
+                  + (", union pattern E u E^T" if union else "")
+                  + (f", entries above {args.delta:g}" if args.delta > 0 else ""),
         "value": round(value, 1),
         "unit": "rows/s",
         "n_gpus": 1,
@@ -279,7 +295,7 @@ def main() -> int:
                    "mode": w.mode, "margin": w.margin, "grid": [w.e_min, w.e_max, w.G],
                    "curve_order": bool(args.curve_order) and w.mode != "learned" and not (w.mode == "f32" and w.m <= 8),
                    "alpha": w.alpha, "beta": w.beta, "fallback_rows": fb, "learned": learned,
-                   "pattern": args.pattern, "nnz": int(nnz)},
+                   "pattern": args.pattern, "delta": args.delta, "nnz": int(nnz)},
         "roofline": roofline,
         "passes": passes,
         "cpu_baseline": cpu,

@@ -283,6 +283,17 @@ int kvb_truncate_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, con
                      float* d2_out, int64_t* nnz_host);
 
 /*
+ * Sparsity tolerance of kvb_build (Section 4: Algorithm 1 stores an entry only
+ * when its kernel value exceeds delta_tol), 0 <= delta < 1; 0 (the default)
+ * keeps every entry. With delta > 0 kvb_build truncates the density kernel
+ * matrix at e_A and the operator kernel matrix at e_B as kvb_truncate_csr
+ * does; the tuning sums still run over the whole pattern, and the density, q
+ * and D row sums over the kept entries. Its CSR rows then hold the kept
+ * entries, columns ascending; rowptr[n] gives their count.
+ */
+int kvb_set_tolerance(kvb_ctx ctx, double delta);
+
+/*
  * The whole build in one call, in the order of the paper's pipeline (Section 4
  * with the tuning of Section 2.3): k-NN (as kvb_knn) -> ad-hoc bandwidth b ->
  * e tuning on the density kernel over [e_min, e_max] -> density psi and

@@ -497,6 +497,14 @@ static kvb::UnionWork take_union_work(Carve& cv, int n, int64_t nk)
     return w;
 }
 
+int kvb_set_tolerance(kvb_ctx ctx, double delta)
+{
+    if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, delta >= 0.0 && delta < 1.0, "delta must lie in [0, 1)");
+    ctx->delta = delta;
+    return KVB_OK;
+}
+
 int kvb_union_pattern(kvb_ctx ctx, const int32_t* idx, const float* d2, int64_t n, int32_t k, int64_t* rowptr,
                       int32_t* col, float* ud2, int64_t cap, int64_t* nnz_host)
 {
@@ -656,50 +664,80 @@ int kvb_normalize_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, co
     return KVB_OK;
 }
 
-// The passes of kvb_build after the k-NN, over E u E^T: enqueued only (the
-// pattern's size stays on the device; the transpose sort runs over all n k
-// slots with the unused ones holding a sentinel key).
-static int build_union(kvb_ctx ctx, int64_t n, int32_t k, int32_t k0, double d, double alpha, double beta,
-                       double e_min, double e_max, int32_t G, int32_t out_kind, const int32_t* idx, const float* d2,
-                       float* b, float* rho, float* psi, int64_t* rowptr, int32_t* col, float* val, double* P,
-                       double* D)
+// The passes of kvb_build after the k-NN over a CSR pattern: the union E u E^T
+// (KVB_PATTERN_UNION) or the directed rows sorted by column, truncated at the
+// context's sparsity tolerance when it is set. Enqueued only: the patterns'
+// sizes stay on the device (the tuning sums are partitioned for n k entries
+// and launched for the largest possible pattern, reading the true count from
+// rowptr[n]).
+static int build_csr(kvb_ctx ctx, int64_t n, int32_t k, int32_t k0, double d, double alpha, double beta,
+                     double e_min, double e_max, int32_t G, int32_t out_kind, const int32_t* idx, const float* d2,
+                     float* b, float* rho, float* psi, int64_t* rowptr, int32_t* col, float* val, double* P, double* D)
 {
     const int nn = static_cast<int>(n);
     const int64_t nk = n * k;
-    const int64_t cap = n * (2 * int64_t(k) - 1);
+    const bool uni = ctx->pattern == KVB_PATTERN_UNION;
+    const bool trunc = ctx->delta > 0.0;
+    const int64_t cap = uni ? n * (2 * int64_t(k) - 1) : nk;
     const int nb = kvb::chi_csr_blocks(nk, cap);
     const int lb = kvb::logsum_num_blocks(nn);
-    const size_t need = union_work_bytes(nn, nk) + round256(size_t(cap) * 4) +
-                        round256(size_t(nb) * G * sizeof(double)) + round256(size_t(2 * lb) * sizeof(double)) +
-                        2 * round256(size_t(nn) * sizeof(double)) + 2048;
+    const size_t scan_bytes = kvb::union_scan_bytes(nn);
+    const size_t pat_bytes = round256((size_t(nn) + 1) * 8) + round256(size_t(cap) * 4) * 2;
+    const size_t need = union_work_bytes(nn, nk) + pat_bytes * 3 + round256((size_t(nn) + 1) * 4) +
+                        round256(scan_bytes) + round256(size_t(nb) * G * sizeof(double)) +
+                        round256(size_t(2 * lb) * sizeof(double)) + 2 * round256(size_t(nn) * sizeof(double)) + 4096;
     int rc = ensure_scratch(ctx, need);
     if (rc) return rc;
     Carve cv(ctx->scratch);
     const kvb::UnionWork uw = take_union_work(cv, nn, nk);
-    float* ud2 = cv.take<float>(cap);
+    // base pattern: the caller's rowptr/col when it is also the operator pattern
+    int64_t* brow = trunc ? cv.take<int64_t>(size_t(nn) + 1) : rowptr;
+    int32_t* bcol = trunc ? cv.take<int32_t>(cap) : col;
+    float* bd2 = cv.take<float>(cap);
+    int64_t* arow = cv.take<int64_t>(size_t(nn) + 1);   // density pattern (truncated)
+    int32_t* acol = cv.take<int32_t>(cap);
+    float* ad2 = cv.take<float>(cap);
+    float* od2 = cv.take<float>(cap);                    // operator pattern distances (truncated)
+    int* tcnt = cv.take<int>(size_t(nn) + 1);
+    void* tscan = cv.take<char>(scan_bytes);
     double* part = cv.take<double>(size_t(nb) * G);
     double* lpart = cv.take<double>(2 * lb);
     double* qa = cv.take<double>(nn);
     double* Dtmp = cv.take<double>(nn);
     BuildDev* bd = ctx->build_dev;
     hipStream_t st = ctx->stream;
+    const double L = trunc ? -std::log(ctx->delta) : 0.0;
     {
         Prof pr(ctx, KVB_PROF_ADHOC);
         KVB_HIP(ctx, kvb::launch_adhoc_bandwidth(d2, nn, k, k0, b, st));
     }
     {
         Prof pr(ctx, KVB_PROF_UNION);
-        KVB_HIP(ctx, kvb::launch_union_count(idx, d2, nn, k, uw, st));
-        KVB_HIP(ctx, kvb::launch_union_place(nn, k, uw, rowptr, col, ud2, st));
+        if (uni) {
+            KVB_HIP(ctx, kvb::launch_union_count(idx, d2, nn, k, uw, st));
+            KVB_HIP(ctx, kvb::launch_union_place(nn, k, uw, brow, bcol, bd2, st));
+        } else {
+            KVB_HIP(ctx, kvb::launch_sorted_rows(idx, d2, nn, k, brow, bcol, bd2, st));
+        }
     }
     {
         Prof pr(ctx, KVB_PROF_CHI);
-        KVB_HIP(ctx, kvb::launch_chi_csr(rowptr, col, ud2, nn, nk, cap, b, G, e_min, e_max, nullptr, part, &bd->a,
-                                         st));
+        KVB_HIP(ctx, kvb::launch_chi_csr(brow, bcol, bd2, nn, nk, cap, b, G, e_min, e_max, nullptr, part, &bd->a, st));
+    }
+    const int64_t* drow = brow;
+    const int32_t* dcol = bcol;
+    const float* dd2 = bd2;
+    if (trunc) {
+        Prof pr(ctx, KVB_PROF_TRUNCATE);
+        KVB_HIP(ctx, kvb::launch_truncate(brow, bcol, bd2, b, nn, 0.0, &bd->a.e_star, L, tcnt, tscan, scan_bytes, arow,
+                                          acol, ad2, st));
+        drow = arow;
+        dcol = acol;
+        dd2 = ad2;
     }
     {
         Prof pr(ctx, KVB_PROF_DENSITY);
-        KVB_HIP(ctx, kvb::launch_density_csr(rowptr, col, ud2, nn, b, 0.0, &bd->a.e_star, d, beta, rho, psi, st));
+        KVB_HIP(ctx, kvb::launch_density_csr(drow, dcol, dd2, nn, b, 0.0, &bd->a.e_star, d, beta, rho, psi, st));
     }
     {
         Prof pr(ctx, KVB_PROF_GRID_SCALE);
@@ -707,16 +745,23 @@ static int build_union(kvb_ctx ctx, int64_t n, int32_t k, int32_t k0, double d, 
     }
     {
         Prof pr(ctx, KVB_PROF_CHI);
-        KVB_HIP(ctx, kvb::launch_chi_csr(rowptr, col, ud2, nn, nk, cap, rho, G, e_min, e_max, &bd->scale, part,
-                                         &bd->b, st));
+        KVB_HIP(ctx, kvb::launch_chi_csr(brow, bcol, bd2, nn, nk, cap, rho, G, e_min, e_max, &bd->scale, part, &bd->b,
+                                         st));
+    }
+    const float* od = bd2;
+    if (trunc) {
+        Prof pr(ctx, KVB_PROF_TRUNCATE);
+        KVB_HIP(ctx, kvb::launch_truncate(brow, bcol, bd2, rho, nn, 0.0, &bd->b.e_star, L, tcnt, tscan, scan_bytes,
+                                          rowptr, col, od2, st));
+        od = od2;
     }
     {
         Prof pr(ctx, KVB_PROF_QPASS);
-        KVB_HIP(ctx, kvb::launch_qpass_csr(rowptr, col, ud2, nn, rho, 0.0, &bd->b.e_star, alpha, d, qa, st));
+        KVB_HIP(ctx, kvb::launch_qpass_csr(rowptr, col, od, nn, rho, 0.0, &bd->b.e_star, alpha, d, qa, st));
     }
     {
         Prof pr(ctx, KVB_PROF_ASSEMBLE);
-        KVB_HIP(ctx, kvb::launch_assemble_rows(rowptr, col, ud2, nn, rho, 0.0, &bd->b.e_star, qa, out_kind, val, P,
+        KVB_HIP(ctx, kvb::launch_assemble_rows(rowptr, col, od, nn, rho, 0.0, &bd->b.e_star, qa, out_kind, val, P,
                                                D ? D : Dtmp, st));
     }
     return KVB_OK;
@@ -742,9 +787,9 @@ int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int3
     KVB_REQUIRE(ctx, (P == nullptr || aligned(P)) && (D == nullptr || aligned(D)), "P and D must be aligned");
     int rc = kvb_knn(ctx, X, n, m, k, mode, margin, idx, d2, row_flags);
     if (rc < 0) return rc;
-    if (ctx->pattern == KVB_PATTERN_UNION) {
-        rc = build_union(ctx, n, k, k0, d, alpha, beta, e_min, e_max, G, out_kind, idx, d2, b, rho, psi, rowptr, col,
-                         val, P, D);
+    if (ctx->pattern == KVB_PATTERN_UNION || ctx->delta > 0.0) {
+        rc = build_csr(ctx, n, k, k0, d, alpha, beta, e_min, e_max, G, out_kind, idx, d2, b, rho, psi, rowptr, col,
+                       val, P, D);
         if (rc < 0) return rc;
         ctx->build_G = G;
         if (!info_host) return KVB_OK;

@@ -60,6 +60,7 @@ struct kvb_ctx_s {
     int bf16_split = 3;
     int curve_order = 1;
     int pattern = KVB_PATTERN_KNN;   // pattern of kvb_build's matrix
+    double delta = 0.0;              // sparsity tolerance of kvb_build (0: keep every entry)
     int build_G = 0;   // grid size of the last kvb_build (0: none yet)
     kvb::TuneResult* tune_dev = nullptr;
     kvb::TuneResult* tune_host = nullptr;   // pinned

@@ -193,6 +193,9 @@ hipError_t launch_union_count(const int32_t* idx, const float* d2, int n, int k,
 // steps 4-6 into rowptr [n + 1], col and ud2 [n k + revptr[n]]
 hipError_t launch_union_place(int n, int k, const UnionWork& w, int64_t* rowptr, int32_t* col, float* ud2,
                               hipStream_t st);
+// the directed k-NN rows sorted by column as CSR (rowptr_i = i k)
+hipError_t launch_sorted_rows(const int32_t* idx, const float* d2, int n, int k, int64_t* rowptr, int32_t* col,
+                              float* sd2, hipStream_t st);
 // threshold truncation: keep x = d2 / (e rho_i rho_j) < L (L = -ln delta); cnt [n + 1]
 // and scan_tmp (union_scan_bytes(n)) are scratch; col_out, d2_out need rowptr[n] entries
 hipError_t launch_truncate(const int64_t* rowptr, const int32_t* col, const float* d2, const float* rho, int n,

@@ -410,6 +410,26 @@ hipError_t launch_union_place(int n, int k, const UnionWork& w, int64_t* rowptr,
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_rows_of_k(int n, int k, int64_t* __restrict__ rowptr)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) rowptr[i] = static_cast<int64_t>(i) * k;
+}
+
+hipError_t launch_sorted_rows(const int32_t* idx, const float* d2, int n, int k, int64_t* rowptr, int32_t* col,
+                              float* sd2, hipStream_t st)
+{
+    const dim3 rows((n + 3) / 4), block(256);
+    if (k <= 64)
+        hipLaunchKernelGGL((k_union_sort_rows<1>), rows, block, 0, st, idx, d2, n, k, col, sd2);
+    else if (k <= 128)
+        hipLaunchKernelGGL((k_union_sort_rows<2>), rows, block, 0, st, idx, d2, n, k, col, sd2);
+    else
+        hipLaunchKernelGGL((k_union_sort_rows<4>), rows, block, 0, st, idx, d2, n, k, col, sd2);
+    hipLaunchKernelGGL(k_rows_of_k, dim3(grid_of(int64_t(n) + 1)), block, 0, st, n, k, rowptr);
+    return hipGetLastError();
+}
+
 hipError_t launch_truncate(const int64_t* rowptr, const int32_t* col, const float* d2, const float* rho, int n,
                            double e, const double* e_dev, double L, int* cnt, void* scan_tmp, size_t scan_bytes,
                            int64_t* rowptr_out, int32_t* col_out, float* d2_out, hipStream_t st)

@@ -38,7 +38,7 @@ EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb
            "kvb_mlp_backward", "kvb_part_num_params", "kvb_part_get_params", "kvb_part_set_params",
            "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name",
            "kvb_union_pattern", "kvb_density_csr", "kvb_tune_eps_csr", "kvb_normalize_csr",
-           "kvb_truncate_csr")
+           "kvb_truncate_csr", "kvb_set_tolerance")
 PROF_SLOTS = 14
 
 
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
     L.kvb_density_csr.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _vp, _f64, _f64, _f64, _vp, _vp]
     L.kvb_tune_eps_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _i32, _vp,
                                    ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
+    L.kvb_set_tolerance.argtypes = [_vp, _f64]
     L.kvb_truncate_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _vp, _vp, _vp,
                                    ctypes.POINTER(_i64)]
     L.kvb_normalize_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _f64, _i32, _vp, _vp, _vp]
@@ -328,21 +329,24 @@ class KernelMatrix:
 def build(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float, e_min: float = 1e-3,
           e_max: float = 1e1, G: int = 64, mode: str = "f32", margin: int = 32, out_kind: int = OUT_MARKOV,
           ctx: Context | None = None, out: KernelMatrix | None = None, sync: bool = True,
-          pattern: str = "knn") -> KernelMatrix:
+          pattern: str = "knn", delta: float = 0.0) -> KernelMatrix:
     """The whole build in one library call (kvb_build): the same steps and results
     as build_kernel_matrix (pattern "knn") or build_union_matrix (pattern
     "union", the symmetric E u E^T), with the intermediate values kept on the
-    device. `out` (a previous result of the same n, k and pattern) lends its
-    device arrays. sync=False only enqueues the work (the tuning results of the
-    returned matrix are then None; build_info(ctx) waits and returns them; with
-    the union pattern col and val then keep their capacity n (2k - 1) and
-    rowptr[n] is the stored count)."""
+    device; delta > 0 applies the sparsity tolerance of Section 4 as
+    build_truncated_matrix does (rows then in column order). `out` (a previous
+    result of the same n, k and pattern) lends its device arrays. sync=False
+    only enqueues the work (the tuning results of the returned matrix are then
+    None; build_info(ctx) waits and returns them; with the union pattern or a
+    tolerance col and val then keep their capacity and rowptr[n] is the stored
+    count)."""
     ctx = ctx or context()
     X = _dev(X, torch.float32, "X")
     n, m = X.shape
     dev = X.device
     cap = n * k if pattern == "knn" else n * (2 * k - 1)
     ctx.check(ctx.lib.kvb_set_option(ctx.h, OPT_PATTERN, PATTERNS[pattern]))
+    ctx.check(ctx.lib.kvb_set_tolerance(ctx.h, float(delta)))
     if out is not None and out.idx.shape == (n, k) and out.idx.device == dev and out.col.numel() == cap:
         idx, d2, flags, b, rho, psi = out.idx, out.d2, out.flags, out.b, out.rho, out.psi
         rowptr, col, val, P, D = out.rowptr, out.col, out.val, out.P, out.D
@@ -369,7 +373,7 @@ def build(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float,
     if not sync:
         return KernelMatrix(idx, d2, flags, b, None, rho, psi, None, None, rowptr, col, val, P, D)
     ta, s, tb = _tunings(chi_a, chi_b, info, G)
-    if pattern != "knn":
+    if pattern != "knn" or delta > 0:
         nnz = int(rowptr[n].item())
         col, val = col[:nnz], val[:nnz]
     return KernelMatrix(idx, d2, flags, b, ta, rho, psi, s, tb, rowptr, col, val, P, D)

@@ -160,3 +160,42 @@ def test_truncated_build_torus_n100k(gpu_lib):
     rowmax = np.maximum.reduceat(val_r, pb.rowptr[:-1])[rows]
     check_entries(f64(g.val), val_r, x, rowmax, "torus truncated entries")
     say(f"[truncate] torus: kept {len(pb.col)} of {len(base.col)}")
+
+
+@pytest.mark.parametrize("pattern", ["knn", "union"])
+def test_single_call_truncated_build(gpu_lib, pattern):
+    """kvb_build with a sparsity tolerance enqueues the truncated build without
+    a host round trip. On the union pattern it matches the separate calls bit
+    for bit (the tuning sums to rounding); on the k-NN pattern its rows are in
+    column order, so the kept sets agree and the values to rounding."""
+    kvb = gpu_lib
+    w = workloads.WORKLOADS["torus_n100k"]
+    X = torch.from_numpy(workloads.torus(20000, seed=6)).cuda()
+    delta = 1e-2
+    say(f"[truncate] single call, pattern {pattern}")
+    a = kvb.build_truncated_matrix(X, w.k, w.k0, float(w.d), w.alpha, w.beta, delta, w.e_min, w.e_max, w.G,
+                                   pattern=pattern)
+    b = kvb.build(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G, pattern=pattern, delta=delta)
+    assert a.tune_a.e_star == b.tune_a.e_star and a.tune_b.e_star == b.tune_b.e_star
+    # the k-NN rows are summed in another order here, so rho and the
+    # operator-stage sums agree to rounding only
+    np.testing.assert_allclose(b.tune_b.chi, a.tune_b.chi, rtol=1e-12 if pattern == "union" else 1e-6)
+    if pattern == "union":
+        assert torch.equal(a.pattern.rowptr, b.rowptr)
+        assert torch.equal(a.pattern.col, b.col)
+        for f in ("rho", "psi", "val", "P", "D"):
+            assert torch.equal(getattr(a, f), getattr(b, f)), f
+    else:
+        # the row sums run in another order, so rho may move an entry that
+        # sits exactly at the threshold; such rows are counted, not compared
+        n = X.shape[0]
+        ra, rb = a.pattern.rowptr.cpu().numpy(), b.rowptr.cpu().numpy()
+        same = np.diff(ra) == np.diff(rb)
+        assert (~same).sum() <= 3
+        ca, va = a.pattern.col.cpu().numpy(), a.val.cpu().numpy().astype(np.float64)
+        cb, vb = b.col.cpu().numpy(), b.val.cpu().numpy().astype(np.float64)
+        for i in np.nonzero(same)[0][::97]:
+            oa = np.argsort(ca[ra[i]:ra[i + 1]])
+            np.testing.assert_array_equal(ca[ra[i]:ra[i + 1]][oa], cb[rb[i]:rb[i + 1]])
+            np.testing.assert_allclose(va[ra[i]:ra[i + 1]][oa], vb[rb[i]:rb[i + 1]], rtol=1e-6)
+        torch.testing.assert_close(a.rho, b.rho, rtol=1e-6, atol=0)
