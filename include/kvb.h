@@ -58,6 +58,7 @@ extern "C" {
 #define KVB_OK 0
 #define KVB_W_GRID_EDGE 1    /* tuning optimum on the first or last slope of the grid */
 #define KVB_W_FALLBACK 2     /* kvb_knn_fallback_rows: some rows needed the exact fallback scan */
+#define KVB_W_NOT_CONVERGED 3 /* kvb_eigsh: some Ritz residual above the tolerance (results still returned) */
 #define KVB_E_INVALID (-1)   /* an argument is out of range or a pointer is null/misaligned */
 #define KVB_E_NOMEM (-2)     /* scratch allocation failed or exceeds KVB_OPT_SCRATCH_LIMIT */
 #define KVB_E_HIP (-3)       /* a HIP runtime call failed (message carries its error string) */
@@ -281,6 +282,30 @@ int kvb_normalize_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, co
 int kvb_truncate_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* d2, const float* rho,
                      int64_t n, int64_t nnz, double e, double delta, int64_t* rowptr_out, int32_t* col_out,
                      float* d2_out, int64_t* nnz_host);
+
+/*
+ * Leading eigenpairs of a symmetric CSR matrix (the paper's spectral use of
+ * the kernel matrix: the eigenpairs of the symmetric conjugate Lhat of
+ * Section 2.2, e.g. KVB_OUT_SYMMETRIC on KVB_PATTERN_UNION, approximate the
+ * Kolmogorov operator's; Sections 2.2, 4 and 5). Lanczos with full
+ * reorthogonalisation (two passes of classical Gram-Schmidt per step), ncv
+ * steps from a seeded start vector, no restart; the Ritz pairs of the
+ * tridiagonal projection (cyclic Jacobi on the host, FP64) are returned for
+ * the nev largest eigenvalues (for Lhat, those nearest zero), descending.
+ *   rowptr, col, val: the matrix (as kvb_density_csr, val float32); it must be
+ *     symmetric (not checked; a non-symmetric input gives meaningless but
+ *     finite results).
+ *   1 <= nev <= ncv <= min(1024, n); tol > 0; seed: the start vector's seed.
+ *   evals_host [nev] host out; resid_host [nev] host out or NULL: the Ritz
+ *     residual norms |beta_{ncv-1} s_{ncv-1,i}|.
+ *   evecs [nev * n] float64 device out or NULL: unit Ritz vectors, one per row.
+ * Returns KVB_W_NOT_CONVERGED if a residual exceeds tol * max|Ritz value|.
+ * Scratch: (ncv + 1) n doubles. Synchronises the context stream (three times
+ * per step).
+ */
+int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* val, int64_t n, int64_t nnz,
+              int32_t nev, int32_t ncv, double tol, uint64_t seed, double* evals_host, double* resid_host,
+              double* evecs);
 
 /*
  * Sparsity tolerance of kvb_build (Section 4: Algorithm 1 stores an entry only

@@ -538,8 +538,10 @@ int kvb_union_pattern(kvb_ctx ctx, const int32_t* idx, const float* d2, int64_t 
     return KVB_OK;
 }
 
+}  // extern "C"
+
 // shape check of a caller's CSR pattern (synchronises)
-static int check_pattern(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, int64_t n, int64_t nnz)
+int kvbh::check_pattern(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, int64_t n, int64_t nnz)
 {
     KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
     KVB_REQUIRE(ctx, nnz >= 1, "nnz must be >= 1");
@@ -556,6 +558,9 @@ static int check_pattern(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col,
     if (ctx->union_host[0] & 2) return fail(ctx, KVB_E_INVALID, "col: a column lies outside [0, n)");
     return KVB_OK;
 }
+
+extern "C" {
+
 
 int kvb_truncate_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* d2, const float* rho,
                      int64_t n, int64_t nnz, double e, double delta, int64_t* rowptr_out, int32_t* col_out,

@@ -1,0 +1,372 @@
+// Leading eigenpairs of a symmetric CSR matrix (gfx950): Lanczos with full
+// reorthogonalisation.
+//
+// The paper's use of the kernel matrix is spectral: the eigenpairs of the
+// symmetric conjugate Lhat = e^{-1}(S^{-1} Kt S^{-1} - P^{-2}) (Section 2.2)
+// approximate those of the Kolmogorov operator (Sections 2.2 and 5), and a
+// sparse eigensolver is the most expensive step after the matrix itself
+// (Section 4). Lhat is negative semi-definite; the wanted eigenvalues are the
+// ones nearest zero, the top of its spectrum.
+//
+// Lanczos (Lanczos 1950; Golub and Van Loan, Section 10.1) builds an
+// orthonormal basis v_0..v_{m-1} of the Krylov space of a seeded start vector
+// with A v_j = beta_{j-1} v_{j-1} + alpha_j v_j + beta_j v_{j+1}. Rounding
+// destroys the orthogonality as Ritz values converge, so every new vector is
+// orthogonalised against all previous ones, twice (classical Gram-Schmidt
+// repeated). The eigenpairs of the m x m tridiagonal T = tridiag(beta, alpha,
+// beta) are the Ritz pairs; a Ritz vector is V s, its residual norm
+// |beta_{m-1} s_{m-1}|. The small eigenproblem is solved on the host for the
+// wanted pairs only: eigenvalues by bisection on the Sturm count, eigenvectors
+// by inverse iteration (Golub and Van Loan, Sections 8.4 and 8.2).
+//
+// On the device: the matrix-vector product (one wavefront per row, FP64
+// accumulation of float32 entries), the projections V^T w (blocks of rows,
+// per-block partial sums reduced in a fixed order), w -= V h, norms and Ritz
+// vectors. Every reduction has a fixed order, so results are reproducible.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "kvb_ctx.h"
+#include "kvb_device.h"
+
+namespace kvb {
+
+constexpr int EIG_RPT = 2;                  // rows per thread of the projection kernel
+constexpr int EIG_ROWS = 256 * EIG_RPT;     // rows per block
+
+// y = A x, one wavefront per row, lanes strided over the row, butterfly sum
+__global__ __launch_bounds__(256) void k_spmv(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                              const float* __restrict__ val, const double* __restrict__ x, int n,
+                                              double* __restrict__ y)
+{
+    const int lane = lane_id();
+    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t p = rowptr[i] + lane; p < rowptr[i + 1]; p += WAVE)
+        s += static_cast<double>(val[p]) * x[col[p]];
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) s += shfl_xor_f64(s, o);
+    if (lane == 0) y[i] = s;
+}
+
+// partial[c][blk] = sum over the block's rows of V[c][r] w[r], c < ncol
+__global__ __launch_bounds__(256) void k_project_partial(const double* __restrict__ V, int64_t ldv, int ncol,
+                                                         const double* __restrict__ w, int n,
+                                                         double* __restrict__ partial, int nblk)
+{
+    __shared__ double red[4];
+    const int r0 = blockIdx.x * EIG_ROWS;
+    double wr[EIG_RPT];
+#pragma unroll
+    for (int t = 0; t < EIG_RPT; ++t) {
+        const int r = r0 + t * 256 + threadIdx.x;
+        wr[t] = r < n ? w[r] : 0.0;
+    }
+    for (int c = 0; c < ncol; ++c) {
+        const double* vc = V + static_cast<size_t>(c) * ldv;
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < EIG_RPT; ++t) {
+            const int r = r0 + t * 256 + threadIdx.x;
+            if (r < n) s += vc[r] * wr[t];
+        }
+        s = wave_sum_f64(s);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) partial[static_cast<size_t>(c) * nblk + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
+    }
+}
+
+// h[c] = sum of the block partials in block order
+__global__ __launch_bounds__(256) void k_project_finish(const double* __restrict__ partial, int ncol, int nblk,
+                                                        double* __restrict__ h)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[static_cast<size_t>(c) * nblk + b];
+    h[c] = s;
+}
+
+// w[r] -= sum_c V[c][r] h[c]
+__global__ __launch_bounds__(256) void k_subtract_span(const double* __restrict__ V, int64_t ldv, int ncol,
+                                                       const double* __restrict__ h, int n, double* __restrict__ w)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < ncol; ++c) s += V[static_cast<size_t>(c) * ldv + r] * h[c];
+    w[r] -= s;
+}
+
+// out[r] = x[r] * scale
+__global__ __launch_bounds__(256) void k_scale(const double* __restrict__ x, double scale, int n,
+                                               double* __restrict__ out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) out[r] = x[r] * scale;
+}
+
+// the seeded start vector: SplitMix64 (Steele, Lea and Flood 2014) of
+// seed + r mapped to [-1, 1)
+__global__ __launch_bounds__(256) void k_start_vector(uint64_t seed, int n, double* __restrict__ v)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (static_cast<uint64_t>(r) + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    v[r] = static_cast<double>(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// Y[i][r] = sum_c V[c][r] S[c][i] (Ritz vectors), S column-major [m][nev] as S[c * nev + i]
+__global__ __launch_bounds__(256) void k_ritz(const double* __restrict__ V, int64_t ldv, int m,
+                                              const double* __restrict__ S, int nev, int n, double* __restrict__ Y)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    for (int i = 0; i < nev; ++i) {
+        double s = 0.0;
+        for (int c = 0; c < m; ++c) s += V[static_cast<size_t>(c) * ldv + r] * S[static_cast<size_t>(c) * nev + i];
+        Y[static_cast<size_t>(i) * n + r] = s;
+    }
+}
+
+}  // namespace kvb
+
+namespace {
+
+using namespace kvbh;
+
+// Number of eigenvalues of the symmetric tridiagonal T = tridiag(b, a, b)
+// below x: the negative pivots of the LDL^T factorisation of T - x I
+// (Sylvester's law of inertia; the Sturm sequence count).
+int count_below(const std::vector<double>& a, const std::vector<double>& b, int m, double x, double tiny)
+{
+    int c = 0;
+    double q = a[0] - x;
+    if (q == 0.0) q = -tiny;
+    c += q < 0.0;
+    for (int i = 1; i < m; ++i) {
+        q = a[i] - x - b[i - 1] * b[i - 1] / q;
+        if (q == 0.0) q = -tiny;
+        c += q < 0.0;
+    }
+    return c;
+}
+
+// Solve (T - theta I) y = rhs in place: Gaussian elimination with partial
+// pivoting on the tridiagonal band (row swaps fill one extra superdiagonal).
+void shifted_solve(const std::vector<double>& a, const std::vector<double>& b, int m, double theta, double tiny,
+                   std::vector<double>& y)
+{
+    std::vector<double> lo(m, 0.0), d(m), up(m, 0.0), up2(m, 0.0);
+    std::vector<char> swapped(m, 0);
+    for (int i = 0; i < m; ++i) d[i] = a[i] - theta;
+    for (int i = 0; i + 1 < m; ++i) {
+        lo[i] = b[i];
+        up[i] = b[i];
+    }
+    for (int i = 0; i + 1 < m; ++i) {
+        if (std::fabs(d[i]) >= std::fabs(lo[i])) {
+            if (d[i] == 0.0) d[i] = tiny;
+            const double f = lo[i] / d[i];
+            lo[i] = f;
+            d[i + 1] -= f * up[i];
+        } else {
+            // rows i and i + 1 trade places; row i + 1's entries move up
+            const double f = d[i] / lo[i];
+            d[i] = lo[i];
+            lo[i] = f;
+            const double u = up[i];
+            up[i] = d[i + 1];
+            d[i + 1] = u - f * d[i + 1];
+            if (i + 2 < m) {
+                up2[i] = up[i + 1];
+                up[i + 1] = -f * up[i + 1];
+            }
+            swapped[i] = 1;
+        }
+    }
+    if (d[m - 1] == 0.0) d[m - 1] = tiny;
+    for (int i = 0; i + 1 < m; ++i) {
+        if (swapped[i]) {
+            const double t = y[i];
+            y[i] = y[i + 1];
+            y[i + 1] = t - lo[i] * y[i + 1];
+        } else {
+            y[i + 1] -= lo[i] * y[i];
+        }
+    }
+    y[m - 1] /= d[m - 1];
+    if (m > 1) y[m - 2] = (y[m - 2] - up[m - 2] * y[m - 1]) / d[m - 2];
+    for (int i = m - 3; i >= 0; --i) y[i] = (y[i] - up[i] * y[i + 1] - up2[i] * y[i + 2]) / d[i];
+}
+
+// The nev largest eigenpairs of T (descending): each eigenvalue by bisection
+// on the Sturm count to the resolution of double precision, its eigenvector
+// by inverse iteration (three solves with T - theta I), orthogonalised against
+// the vectors of nearby eigenvalues already found.
+void top_eigenpairs(const std::vector<double>& a, const std::vector<double>& b, int m, int nev,
+                    std::vector<double>& theta, std::vector<double>& Y)
+{
+    double lo = a[0], hi = a[0], norm = 0.0;
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+        norm = std::max(norm, std::fabs(a[i]) + r);
+    }
+    const double tiny = 1e-300 + 2.2e-16 * norm;
+    theta.assign(nev, 0.0);
+    Y.assign(size_t(nev) * m, 0.0);
+    for (int q = 0; q < nev; ++q) {
+        const int idx = m - 1 - q;   // ascending rank of the wanted eigenvalue
+        double l = lo, h = hi;
+        for (int it = 0; it < 2000 && h - l > 4.4e-16 * std::max(std::fabs(l), std::fabs(h)) + 1e-300; ++it) {
+            const double mid = 0.5 * (l + h);
+            if (mid <= l || mid >= h) break;
+            if (count_below(a, b, m, mid, tiny) > idx)
+                h = mid;
+            else
+                l = mid;
+        }
+        theta[q] = 0.5 * (l + h);
+        std::vector<double> y(m);
+        for (int i = 0; i < m; ++i) y[i] = 1.0 + 0.01 * std::sin(1.0 + 7.0 * i + 3.0 * q);
+        for (int it = 0; it < 3; ++it) {
+            shifted_solve(a, b, m, theta[q], tiny, y);
+            for (int p = 0; p < q; ++p) {
+                if (std::fabs(theta[p] - theta[q]) > 1e-3 * norm) continue;
+                double dot = 0.0;
+                for (int i = 0; i < m; ++i) dot += Y[size_t(p) * m + i] * y[i];
+                for (int i = 0; i < m; ++i) y[i] -= dot * Y[size_t(p) * m + i];
+            }
+            double nrm = 0.0;
+            for (int i = 0; i < m; ++i) nrm += y[i] * y[i];
+            nrm = std::sqrt(nrm);
+            for (int i = 0; i < m; ++i) y[i] /= nrm;
+        }
+        for (int i = 0; i < m; ++i) Y[size_t(q) * m + i] = y[i];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* val, int64_t n, int64_t nnz,
+              int32_t nev, int32_t ncv, double tol, uint64_t seed, double* evals_host, double* resid_host,
+              double* evecs)
+{
+    if (!ctx) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
+    KVB_REQUIRE(ctx, nev >= 1 && ncv >= nev && ncv <= 1024 && ncv <= n, "need 1 <= nev <= ncv <= min(1024, n)");
+    KVB_REQUIRE(ctx, tol > 0 && std::isfinite(tol), "tol must be finite and > 0");
+    KVB_REQUIRE(ctx, aligned(val), "val must be a non-null float32 device pointer");
+    KVB_REQUIRE(ctx, evals_host != nullptr, "evals_host must be non-null");
+    KVB_REQUIRE(ctx, evecs == nullptr || aligned(evecs), "evecs must be aligned");
+    KVB_TRY(check_pattern(ctx, rowptr, col, n, nnz));
+    const int nn = static_cast<int>(n);
+    const int nblk = (nn + kvb::EIG_ROWS - 1) / kvb::EIG_ROWS;
+    const int64_t ldv = (n + 63) / 64 * 64;
+    const size_t need = round256(size_t(ncv + 1) * ldv * sizeof(double)) + round256(size_t(ldv) * sizeof(double)) +
+                        round256(size_t(ncv + 1) * nblk * sizeof(double)) + 2 * round256(size_t(ncv + 1) * sizeof(double)) +
+                        round256(size_t(ncv) * nev * sizeof(double)) + 2048;
+    int rc = ensure_scratch(ctx, need);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    double* V = cv.take<double>(size_t(ncv + 1) * ldv);
+    double* w = cv.take<double>(ldv);
+    double* part = cv.take<double>(size_t(ncv + 1) * nblk);
+    double* h = cv.take<double>(ncv + 1);
+    double* hsum = cv.take<double>(ncv + 1);
+    double* S = cv.take<double>(size_t(ncv) * nev);
+    hipStream_t st = ctx->stream;
+    const dim3 blk(256), rows_grid((nn + 255) / 256), spmv_grid((nn + 3) / 4);
+    std::vector<double> hh(ncv + 1);
+
+    // hd = V[:, :ncol]^T x on the device
+    auto project = [&](const double* x, int ncol, double* hd) -> hipError_t {
+        hipLaunchKernelGGL(kvb::k_project_partial, dim3(nblk), blk, 0, st, V, ldv, ncol, x, nn, part, nblk);
+        hipLaunchKernelGGL(kvb::k_project_finish, dim3((ncol + 255) / 256), blk, 0, st, part, ncol, nblk, hd);
+        return hipGetLastError();
+    };
+    // ||x|| via the projection kernel with x itself as the only column
+    auto norm = [&](double* x, double* out) -> int {
+        hipLaunchKernelGGL(kvb::k_project_partial, dim3(nblk), blk, 0, st, x, ldv, 1, x, nn, part, nblk);
+        hipLaunchKernelGGL(kvb::k_project_finish, dim3(1), blk, 0, st, part, 1, nblk, h);
+        KVB_HIP(ctx, hipGetLastError());
+        KVB_HIP(ctx, hipMemcpyAsync(out, h, sizeof(double), hipMemcpyDeviceToHost, st));
+        KVB_HIP(ctx, hipStreamSynchronize(st));
+        *out = std::sqrt(*out);
+        return KVB_OK;
+    };
+
+    std::vector<double> alpha, beta;
+    hipLaunchKernelGGL(kvb::k_start_vector, rows_grid, blk, 0, st, seed, nn, w);
+    double b0 = 0.0;
+    KVB_TRY(norm(w, &b0));
+    KVB_REQUIRE(ctx, b0 > 0, "start vector vanished");
+    hipLaunchKernelGGL(kvb::k_scale, rows_grid, blk, 0, st, w, 1.0 / b0, nn, V);
+    int m = 0;
+    for (int j = 0; j < ncv; ++j) {
+        double* vj = V + size_t(j) * ldv;
+        hipLaunchKernelGGL(kvb::k_spmv, spmv_grid, blk, 0, st, rowptr, col, val, vj, nn, w);
+        // two passes of classical Gram-Schmidt against v_0..v_j; alpha_j is
+        // the first pass's coefficient on v_j plus the second's correction
+        double a = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+            KVB_HIP(ctx, project(w, j + 1, hsum));
+            hipLaunchKernelGGL(kvb::k_subtract_span, rows_grid, blk, 0, st, V, ldv, j + 1, hsum, nn, w);
+            KVB_HIP(ctx, hipMemcpyAsync(hh.data(), hsum + j, sizeof(double), hipMemcpyDeviceToHost, st));
+            KVB_HIP(ctx, hipStreamSynchronize(st));
+            a += hh[0];
+        }
+        double bj = 0.0;
+        KVB_TRY(norm(w, &bj));
+        alpha.push_back(a);
+        m = j + 1;
+        if (j + 1 == ncv) {
+            beta.push_back(bj);
+            break;
+        }
+        if (!(bj > 1e-300)) {   // invariant subspace found: the Ritz pairs are exact
+            beta.push_back(0.0);
+            break;
+        }
+        beta.push_back(bj);
+        hipLaunchKernelGGL(kvb::k_scale, rows_grid, blk, 0, st, w, 1.0 / bj, nn, V + size_t(j + 1) * ldv);
+    }
+    KVB_REQUIRE(ctx, nev <= m, "the Krylov space closed after %d steps, below nev = %d", m, nev);
+    // Ritz pairs of T
+    std::vector<double> theta, Yt;
+    top_eigenpairs(alpha, beta, m, nev, theta, Yt);
+    double scale = 0.0;
+    for (int i = 0; i < m; ++i)
+        scale = std::max(scale, std::fabs(alpha[i]) + (i > 0 ? std::fabs(beta[i - 1]) : 0.0) +
+                                    (i + 1 < m ? std::fabs(beta[i]) : 0.0));
+    bool converged = true;
+    std::vector<double> Ssel(size_t(m) * nev);
+    for (int q = 0; q < nev; ++q) {
+        evals_host[q] = theta[q];
+        const double res = std::fabs(beta[m - 1] * Yt[size_t(q) * m + m - 1]);
+        if (resid_host) resid_host[q] = res;
+        if (res > tol * scale) converged = false;
+        for (int c = 0; c < m; ++c) Ssel[size_t(c) * nev + q] = Yt[size_t(q) * m + c];
+    }
+    if (evecs) {
+        KVB_HIP(ctx, hipMemcpyAsync(S, Ssel.data(), sizeof(double) * Ssel.size(), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(kvb::k_ritz, rows_grid, blk, 0, st, V, ldv, m, S, nev, nn, evecs);
+        KVB_HIP(ctx, hipGetLastError());
+        KVB_HIP(ctx, hipStreamSynchronize(st));
+    }
+    return converged ? KVB_OK : KVB_W_NOT_CONVERGED;
+}
+
+}  // extern "C"

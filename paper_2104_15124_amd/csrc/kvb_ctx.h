@@ -84,6 +84,10 @@ struct kvb_ctx_s {
 
 namespace kvbh {
 
+// shape check of a caller's CSR pattern: rowptr[0] = 0, non-decreasing,
+// rowptr[n] = nnz, columns in [0, n) (one synchronisation)
+int check_pattern(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, int64_t n, int64_t nnz);
+
 inline int fail(kvb_ctx ctx, int code, const char* fmt, ...)
 {
     char buf[512];

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libkvb.so")
 # status / enum values mirrored from include/kvb.h
 OK, W_GRID_EDGE, W_FALLBACK = 0, 1, 2
 E_INVALID, E_NOMEM, E_HIP, E_UNSUPPORTED, E_NOT_TRAINED, E_IO = -1, -2, -3, -4, -5, -6
+W_NOT_CONVERGED = 3
 KNN_F32, KNN_BF16, KNN_LEARNED = 0, 1, 2
 BW_ADHOC, BW_DENSITY = 0, 1
 OUT_MARKOV, OUT_GENERATOR, OUT_SYMMETRIC = 0, 1, 2
@@ -38,7 +39,7 @@ EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb
            "kvb_mlp_backward", "kvb_part_num_params", "kvb_part_get_params", "kvb_part_set_params",
            "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name",
            "kvb_union_pattern", "kvb_density_csr", "kvb_tune_eps_csr", "kvb_normalize_csr",
-           "kvb_truncate_csr", "kvb_set_tolerance")
+           "kvb_truncate_csr", "kvb_set_tolerance", "kvb_eigsh")
 PROF_SLOTS = 14
 
 
@@ -85,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     L.kvb_tune_eps_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _i32, _vp,
                                    ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
     L.kvb_set_tolerance.argtypes = [_vp, _f64]
+    L.kvb_eigsh.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _i32, _f64, ctypes.c_uint64, _vp, _vp, _vp]
     L.kvb_truncate_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _vp, _vp, _vp,
                                    ctypes.POINTER(_i64)]
     L.kvb_normalize_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _f64, _i32, _vp, _vp, _vp]
@@ -543,6 +545,31 @@ def build_union_matrix(X: torch.Tensor, k: int, k0: int, d: float, alpha: float,
     tb = tune_eps_csr(pat, rho, e_min * s, e_max * s, G, ctx)
     val, P, D = normalize_csr(pat, rho, tb.e_star, alpha, d, out_kind, ctx)
     return UnionMatrix(idx, d2, pat, b, ta, rho, psi, s, tb, val, P, D)
+
+
+@dataclass
+class Eigs:
+    values: np.ndarray          # [nev], descending
+    residuals: np.ndarray       # [nev] Ritz residual norms
+    vectors: torch.Tensor | None  # [nev, n] float64, unit rows
+    converged: bool
+
+
+def eigsh(rowptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, nev: int = 8, ncv: int = 128,
+          tol: float = 1e-8, seed: int = 0, vectors: bool = True, ctx: Context | None = None) -> Eigs:
+    """The nev largest eigenpairs of a symmetric CSR matrix (kvb_eigsh); for the
+    symmetric conjugate Lhat these are the eigenvalues nearest zero."""
+    ctx = ctx or context()
+    rowptr = _dev(rowptr, torch.int64, "rowptr")
+    col = _dev(col, torch.int32, "col")
+    val = _dev(val, torch.float32, "val")
+    n = rowptr.numel() - 1
+    ev = np.zeros(nev, dtype=np.float64)
+    rs = np.zeros(nev, dtype=np.float64)
+    vec = torch.empty((nev, n), dtype=torch.float64, device=val.device) if vectors else None
+    rc = ctx.check(ctx.lib.kvb_eigsh(ctx.h, _ptr(rowptr), _ptr(col), _ptr(val), n, col.numel(), nev, ncv, tol,
+                                     seed, ev.ctypes.data_as(_vp), rs.ctypes.data_as(_vp), _ptr(vec)))
+    return Eigs(ev, rs, vec, rc != W_NOT_CONVERGED)
 
 
 @dataclass

@@ -70,6 +70,7 @@ def test_header_constants_match_binding():
              "KVB_OPT_PATTERN": kvb.OPT_PATTERN, "KVB_PATTERN_KNN": kvb.PATTERNS["knn"],
              "KVB_PATTERN_UNION": kvb.PATTERNS["union"], "KVB_ROW_UNCERTIFIED": kvb.ROW_UNCERTIFIED,
              "KVB_E_NOT_TRAINED": kvb.E_NOT_TRAINED, "KVB_E_IO": kvb.E_IO,
+             "KVB_W_NOT_CONVERGED": kvb.W_NOT_CONVERGED,
              "KVB_PROF_SLOTS": kvb.PROF_SLOTS}
     for k, v in pairs.items():
         assert consts[k] == v, k
