@@ -68,6 +68,10 @@ def main() -> int:
                     help="matrix pattern: the directed k-NN rows, or their union with the transpose (symmetric)")
     ap.add_argument("--delta", type=float, default=0.0,
                     help="sparsity tolerance: keep only kernel entries above it (0 keeps every entry)")
+    ap.add_argument("--eigs", type=int, default=0,
+                    help="after the timed builds, the NEV leading eigenpairs of the symmetric conjugate on the union "
+                         "pattern (sets --pattern union and the symmetric output), timed once")
+    ap.add_argument("--ncv", type=int, default=1024, help="Lanczos steps of --eigs")
     ap.add_argument("--train-epochs", type=int, default=10, help="learned mode: partitioner training epochs")
     ap.add_argument("--n-probe", type=int, default=8,
                     help="learned mode: buckets each query searches (the configured top-4 gives recall "
@@ -77,6 +81,8 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.eigs:
+        args.pattern = "union"
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -135,7 +141,7 @@ def main() -> int:
         # its tuning results are read once, after the timed region
         prev[0] = kvb.build(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
                             mode=w.mode, margin=w.margin, ctx=ctx, out=prev[0], sync=False, pattern=args.pattern,
-                            delta=args.delta)
+                            delta=args.delta, out_kind=kvb.OUT_SYMMETRIC if args.eigs else kvb.OUT_MARKOV)
         return prev[0]
 
     for _ in range(args.warmup):
@@ -241,6 +247,26 @@ def main() -> int:
         passes["chi_tuning"]["exp_frac"] = round(exps / (ALU_PEAK_TOPS * 1e12 / 4), 4)
     log("  passes: " + ", ".join(f"{k} {v['GB/s']} GB/s ({100 * v['frac']:.1f}% HBM)" for k, v in passes.items()))
 
+    eigs = None
+    if args.eigs:
+        nnz_i = int(r.rowptr[-1].item())
+        col, val = r.col[:nnz_i], r.val[:nnz_i]
+        kvb.eigsh(r.rowptr, col, val, nev=args.eigs, ncv=max(args.eigs, 16), ctx=ctx)    # warm-up
+        torch.cuda.synchronize()
+        e0 = time.perf_counter()
+        ev = kvb.eigsh(r.rowptr, col, val, nev=args.eigs, ncv=args.ncv, tol=1e-8, seed=args.seed, ctx=ctx)
+        e1 = time.perf_counter()
+        # per Lanczos step: one sparse product (12 B per entry + the vectors),
+        # two projections and two subtractions over the basis (j n 8 B each, j
+        # the step), one norm: the basis sweeps dominate
+        basis_bytes = 4.0 * 8 * w.n * args.ncv * (args.ncv + 1) / 2
+        eigs = {"nev": args.eigs, "ncv": args.ncv, "ms": round((e1 - e0) * 1e3, 2),
+                "values": [round(float(x), 6) for x in ev.values],
+                "max_residual": float(f"{ev.residuals.max():.4g}"), "converged": ev.converged,
+                "basis_GB/s": round(basis_bytes / (e1 - e0) / 1e9, 1)}
+        log(f"  eigsh: {args.eigs} pairs, {args.ncv} Lanczos steps in {eigs['ms']} ms, values {eigs['values']}, "
+            f"max residual {eigs['max_residual']}")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -300,6 +326,8 @@ def main() -> int:
         "passes": passes,
         "cpu_baseline": cpu,
     }
+    if eigs is not None:
+        out["eigsh"] = eigs
     print(json.dumps(out), flush=True)
     return 0
 

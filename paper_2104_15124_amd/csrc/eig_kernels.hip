@@ -20,9 +20,8 @@
 // by inverse iteration (Golub and Van Loan, Sections 8.4 and 8.2).
 //
 // On the device: the matrix-vector product (one wavefront per row, FP64
-// accumulation of float32 entries), the projections V^T w (blocks of rows,
-// per-block partial sums reduced in a fixed order), w -= V h, norms and Ritz
-// vectors. Every reduction has a fixed order, so results are reproducible.
+// accumulation of float32 entries), the projections V^T w (one workgroup per
+// basis vector), w -= V h (one thread per row), norms and Ritz vectors. Every reduction has a fixed order, so results are reproducible.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -32,9 +31,6 @@
 #include "kvb_device.h"
 
 namespace kvb {
-
-constexpr int EIG_RPT = 2;                  // rows per thread of the projection kernel
-constexpr int EIG_ROWS = 256 * EIG_RPT;     // rows per block
 
 // y = A x, one wavefront per row, lanes strided over the row, butterfly sum
 __global__ __launch_bounds__(256) void k_spmv(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -52,44 +48,20 @@ __global__ __launch_bounds__(256) void k_spmv(const int64_t* __restrict__ rowptr
     if (lane == 0) y[i] = s;
 }
 
-// partial[c][blk] = sum over the block's rows of V[c][r] w[r], c < ncol
-__global__ __launch_bounds__(256) void k_project_partial(const double* __restrict__ V, int64_t ldv, int ncol,
-                                                         const double* __restrict__ w, int n,
-                                                         double* __restrict__ partial, int nblk)
+// h[c] = V[c] . w, one workgroup per column: the threads stride over the
+// rows, then a fixed-order reduction (wavefront butterflies, then the four
+// wavefronts in order)
+__global__ __launch_bounds__(256) void k_project(const double* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ w, int n, double* __restrict__ h)
 {
     __shared__ double red[4];
-    const int r0 = blockIdx.x * EIG_ROWS;
-    double wr[EIG_RPT];
-#pragma unroll
-    for (int t = 0; t < EIG_RPT; ++t) {
-        const int r = r0 + t * 256 + threadIdx.x;
-        wr[t] = r < n ? w[r] : 0.0;
-    }
-    for (int c = 0; c < ncol; ++c) {
-        const double* vc = V + static_cast<size_t>(c) * ldv;
-        double s = 0.0;
-#pragma unroll
-        for (int t = 0; t < EIG_RPT; ++t) {
-            const int r = r0 + t * 256 + threadIdx.x;
-            if (r < n) s += vc[r] * wr[t];
-        }
-        s = wave_sum_f64(s);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) partial[static_cast<size_t>(c) * nblk + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-        __syncthreads();
-    }
-}
-
-// h[c] = sum of the block partials in block order
-__global__ __launch_bounds__(256) void k_project_finish(const double* __restrict__ partial, int ncol, int nblk,
-                                                        double* __restrict__ h)
-{
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncol) return;
+    const double* vc = V + static_cast<size_t>(blockIdx.x) * ldv;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[static_cast<size_t>(c) * nblk + b];
-    h[c] = s;
+    for (int r = threadIdx.x; r < n; r += 256) s += vc[r] * w[r];
+    s = wave_sum_f64(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) h[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // w[r] -= sum_c V[c][r] h[c]
@@ -273,17 +245,15 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
     KVB_REQUIRE(ctx, evecs == nullptr || aligned(evecs), "evecs must be aligned");
     KVB_TRY(check_pattern(ctx, rowptr, col, n, nnz));
     const int nn = static_cast<int>(n);
-    const int nblk = (nn + kvb::EIG_ROWS - 1) / kvb::EIG_ROWS;
     const int64_t ldv = (n + 63) / 64 * 64;
     const size_t need = round256(size_t(ncv + 1) * ldv * sizeof(double)) + round256(size_t(ldv) * sizeof(double)) +
-                        round256(size_t(ncv + 1) * nblk * sizeof(double)) + 2 * round256(size_t(ncv + 1) * sizeof(double)) +
+                        2 * round256(size_t(ncv + 1) * sizeof(double)) +
                         round256(size_t(ncv) * nev * sizeof(double)) + 2048;
     int rc = ensure_scratch(ctx, need);
     if (rc) return rc;
     Carve cv(ctx->scratch);
     double* V = cv.take<double>(size_t(ncv + 1) * ldv);
     double* w = cv.take<double>(ldv);
-    double* part = cv.take<double>(size_t(ncv + 1) * nblk);
     double* h = cv.take<double>(ncv + 1);
     double* hsum = cv.take<double>(ncv + 1);
     double* S = cv.take<double>(size_t(ncv) * nev);
@@ -293,14 +263,12 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
 
     // hd = V[:, :ncol]^T x on the device
     auto project = [&](const double* x, int ncol, double* hd) -> hipError_t {
-        hipLaunchKernelGGL(kvb::k_project_partial, dim3(nblk), blk, 0, st, V, ldv, ncol, x, nn, part, nblk);
-        hipLaunchKernelGGL(kvb::k_project_finish, dim3((ncol + 255) / 256), blk, 0, st, part, ncol, nblk, hd);
+        hipLaunchKernelGGL(kvb::k_project, dim3(ncol), blk, 0, st, V, ldv, x, nn, hd);
         return hipGetLastError();
     };
-    // ||x|| via the projection kernel with x itself as the only column
+    // ||x||
     auto norm = [&](double* x, double* out) -> int {
-        hipLaunchKernelGGL(kvb::k_project_partial, dim3(nblk), blk, 0, st, x, ldv, 1, x, nn, part, nblk);
-        hipLaunchKernelGGL(kvb::k_project_finish, dim3(1), blk, 0, st, part, 1, nblk, h);
+        hipLaunchKernelGGL(kvb::k_project, dim3(1), blk, 0, st, x, ldv, x, nn, h);
         KVB_HIP(ctx, hipGetLastError());
         KVB_HIP(ctx, hipMemcpyAsync(out, h, sizeof(double), hipMemcpyDeviceToHost, st));
         KVB_HIP(ctx, hipStreamSynchronize(st));
