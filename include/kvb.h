@@ -308,6 +308,26 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
               double* evecs);
 
 /*
+ * Spectral solution of the Kolmogorov problem L f = g (Section 3.1): the
+ * least-squares solution in the span of the leading eigenvectors of L with
+ * nonzero eigenvalue, f = Q Lambda^{-1} g~, g~ = Q^T S^2 g / n, where the
+ * columns phi_j of Q satisfy <phi_i, phi_j>_S = phi_i^T S^2 phi_j / n =
+ * delta_ij. With unit eigenvectors y_j of the symmetric conjugate Lhat (as
+ * kvb_eigsh returns them) phi_j = sqrt(n) S^{-1} y_j, so
+ * f = S^{-1} sum_j y_j (y_j . S g) / lambda_j.
+ *   evecs [nvec * n] float64 device (unit rows), evals_host [nvec]: eigenpairs
+ *     of Lhat; the first `skip` pairs (the null pair, eigenvalue 0) are left out.
+ *   P, D [n] float64 device: as kvb_assemble_csr returns them (S = P D^{1/2}).
+ *   g [n] float64 device in; f [n] float64 device out; g_proj [n] float64
+ *   device out or NULL: the projection g_l = Q g~ of g on the span.
+ *   coef_host [nvec - skip] host out or NULL: the coefficients g~_j.
+ * Synchronises the context stream.
+ */
+int kvb_kolmogorov_solve(kvb_ctx ctx, const double* evecs, const double* evals_host, int32_t nvec, int32_t skip,
+                         const double* P, const double* D, const double* g, int64_t n, double* f, double* g_proj,
+                         double* coef_host);
+
+/*
  * Sparsity tolerance of kvb_build (Section 4: Algorithm 1 stores an entry only
  * when its kernel value exceeds delta_tol), 0 <= delta < 1; 0 (the default)
  * keeps every entry. With delta > 0 kvb_build truncates the density kernel

@@ -65,3 +65,24 @@ def leading_eigenvalues(A, count: int) -> np.ndarray:
     (dense symmetric eigensolver; meant for n of a few thousand)."""
     w = np.linalg.eigvalsh(A.toarray())
     return np.sort(w)[::-1][:count]
+
+
+def kolmogorov_solve(A, P: np.ndarray, D: np.ndarray, g: np.ndarray, nvec: int, skip: int = 1):
+    """The least-squares solution of the discrete Kolmogorov problem L f = g in
+    the span of the leading eigenvectors of L (Section 3.1), from the symmetric
+    conjugate A = Lhat (dense symmetric eigensolver): with S = P D^{1/2},
+    the eigenvectors of L are phi_j = S^{-1} phihat_j, phihat_j the eigenvectors
+    of Lhat scaled to phihat^T phihat = n, so that <phi_i, phi_j>_S =
+    phi_i^T S^2 phi_j / n = delta_ij; then g~ = Q^T S^2 g / n, f = Q Lambda^{-1} g~
+    and the projection of g is Q g~. The first `skip` (null) pairs are left out.
+    Returns (f, g projected, g~, eigenvalues used)."""
+    Ad = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+    n = len(Ad)
+    w, Y = np.linalg.eigh(0.5 * (Ad + Ad.T))
+    order = np.argsort(w)[::-1][:nvec]
+    lam = w[order][skip:]
+    S = P * np.sqrt(D)
+    Q = (np.sqrt(n) * Y[:, order][:, skip:]) / S[:, None]
+    gt = Q.T @ (S ** 2 * g) / n
+    f = Q @ (gt / lam)
+    return f, Q @ gt, gt, lam

@@ -109,6 +109,34 @@ __global__ __launch_bounds__(256) void k_ritz(const double* __restrict__ V, int6
     }
 }
 
+// Spectral solution of the Kolmogorov problem (Section 3.1): with unit
+// eigenvectors y_j of Lhat and S = P D^{1/2},
+//   t = S g;  c_j = y_j . t;  f = S^{-1} sum_j y_j c_j / lambda_j;  g_l = S^{-1} sum_j y_j c_j.
+__global__ __launch_bounds__(256) void k_weight(const double* __restrict__ P, const double* __restrict__ D,
+                                                const double* __restrict__ g, int n, double* __restrict__ t)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) t[r] = P[r] * sqrt(D[r]) * g[r];
+}
+
+__global__ __launch_bounds__(256) void k_expand(const double* __restrict__ Y, int nvec, const double* __restrict__ cf,
+                                                const double* __restrict__ cg, const double* __restrict__ P,
+                                                const double* __restrict__ D, int n, double* __restrict__ f,
+                                                double* __restrict__ gl)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double sf = 0.0, sg = 0.0;
+    for (int j = 0; j < nvec; ++j) {
+        const double y = Y[static_cast<size_t>(j) * n + r];
+        sf += y * cf[j];
+        sg += y * cg[j];
+    }
+    const double is = 1.0 / (P[r] * sqrt(D[r]));
+    f[r] = sf * is;
+    if (gl) gl[r] = sg * is;
+}
+
 }  // namespace kvb
 
 namespace {
@@ -335,6 +363,52 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
         KVB_HIP(ctx, hipStreamSynchronize(st));
     }
     return converged ? KVB_OK : KVB_W_NOT_CONVERGED;
+}
+
+int kvb_kolmogorov_solve(kvb_ctx ctx, const double* evecs, const double* evals_host, int32_t nvec, int32_t skip,
+                         const double* P, const double* D, const double* g, int64_t n, double* f, double* g_proj,
+                         double* coef_host)
+{
+    if (!ctx) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
+    KVB_REQUIRE(ctx, nvec >= 1 && skip >= 0 && skip < nvec && nvec <= 1024, "need 0 <= skip < nvec <= 1024");
+    KVB_REQUIRE(ctx, evals_host != nullptr, "evals_host must be non-null");
+    KVB_REQUIRE(ctx, aligned(evecs) && aligned(P) && aligned(D) && aligned(g) && aligned(f),
+                "evecs, P, D, g, f must be non-null float64 device pointers");
+    KVB_REQUIRE(ctx, g_proj == nullptr || aligned(g_proj), "g_proj must be aligned");
+    const int l = nvec - skip;
+    for (int j = skip; j < nvec; ++j)
+        KVB_REQUIRE(ctx, evals_host[j] != 0.0 && std::isfinite(evals_host[j]),
+                    "eigenvalue %d is zero or not finite: skip the null pairs", j);
+    const int nn = static_cast<int>(n);
+    int rc = ensure_scratch(ctx, round256(size_t(nn) * sizeof(double)) + 3 * round256(size_t(l) * sizeof(double)) + 1024);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    double* t = cv.take<double>(nn);
+    double* c = cv.take<double>(l);
+    double* cf = cv.take<double>(l);
+    double* cg = cv.take<double>(l);
+    hipStream_t st = ctx->stream;
+    const double* Y = evecs + size_t(skip) * nn;
+    const dim3 blk(256), rows_grid((nn + 255) / 256);
+    hipLaunchKernelGGL(kvb::k_weight, rows_grid, blk, 0, st, P, D, g, nn, t);
+    hipLaunchKernelGGL(kvb::k_project, dim3(l), blk, 0, st, Y, static_cast<int64_t>(nn), t, nn, c);
+    KVB_HIP(ctx, hipGetLastError());
+    std::vector<double> ch(l), fh(l);
+    KVB_HIP(ctx, hipMemcpyAsync(ch.data(), c, sizeof(double) * l, hipMemcpyDeviceToHost, st));
+    KVB_HIP(ctx, hipStreamSynchronize(st));
+    for (int j = 0; j < l; ++j) fh[j] = ch[j] / evals_host[skip + j];
+    KVB_HIP(ctx, hipMemcpyAsync(cf, fh.data(), sizeof(double) * l, hipMemcpyHostToDevice, st));
+    KVB_HIP(ctx, hipMemcpyAsync(cg, ch.data(), sizeof(double) * l, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(kvb::k_expand, rows_grid, blk, 0, st, Y, l, cf, cg, P, D, nn, f, g_proj);
+    KVB_HIP(ctx, hipGetLastError());
+    KVB_HIP(ctx, hipStreamSynchronize(st));
+    if (coef_host) {
+        // the paper's coefficients g~_j = <phi_j, g>_S with <phi_i, phi_j>_S = delta_ij, phi_j = sqrt(n) S^{-1} y_j
+        const double rn = 1.0 / std::sqrt(static_cast<double>(n));
+        for (int j = 0; j < l; ++j) coef_host[j] = ch[j] * rn;
+    }
+    return KVB_OK;
 }
 
 }  // extern "C"

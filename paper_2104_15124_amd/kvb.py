@@ -39,7 +39,7 @@ EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb
            "kvb_mlp_backward", "kvb_part_num_params", "kvb_part_get_params", "kvb_part_set_params",
            "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name",
            "kvb_union_pattern", "kvb_density_csr", "kvb_tune_eps_csr", "kvb_normalize_csr",
-           "kvb_truncate_csr", "kvb_set_tolerance", "kvb_eigsh")
+           "kvb_truncate_csr", "kvb_set_tolerance", "kvb_eigsh", "kvb_kolmogorov_solve")
 PROF_SLOTS = 14
 
 
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     L.kvb_tune_eps_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _i32, _vp,
                                    ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
     L.kvb_set_tolerance.argtypes = [_vp, _f64]
+    L.kvb_kolmogorov_solve.argtypes = [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp]
     L.kvb_eigsh.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _i32, _f64, ctypes.c_uint64, _vp, _vp, _vp]
     L.kvb_truncate_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _vp, _vp, _vp,
                                    ctypes.POINTER(_i64)]
@@ -570,6 +571,24 @@ def eigsh(rowptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, nev: int =
     rc = ctx.check(ctx.lib.kvb_eigsh(ctx.h, _ptr(rowptr), _ptr(col), _ptr(val), n, col.numel(), nev, ncv, tol,
                                      seed, ev.ctypes.data_as(_vp), rs.ctypes.data_as(_vp), _ptr(vec)))
     return Eigs(ev, rs, vec, rc != W_NOT_CONVERGED)
+
+
+def kolmogorov_solve(eigs: Eigs, P: torch.Tensor, D: torch.Tensor, g: torch.Tensor, skip: int = 1,
+                     ctx: Context | None = None):
+    """Least-squares solution of L f = g in the span of the leading eigenvectors
+    (kvb_kolmogorov_solve): returns (f, g projected on the span, coefficients)."""
+    ctx = ctx or context()
+    g = _dev(g, torch.float64, "g")
+    n = g.numel()
+    f = torch.empty(n, dtype=torch.float64, device=g.device)
+    gl = torch.empty(n, dtype=torch.float64, device=g.device)
+    nvec = len(eigs.values)
+    coef = np.zeros(nvec - skip, dtype=np.float64)
+    ev = np.ascontiguousarray(eigs.values, dtype=np.float64)
+    ctx.check(ctx.lib.kvb_kolmogorov_solve(ctx.h, _ptr(eigs.vectors), ev.ctypes.data_as(_vp), nvec, skip,
+                                           _ptr(_dev(P, torch.float64, "P")), _ptr(_dev(D, torch.float64, "D")),
+                                           _ptr(g), n, _ptr(f), _ptr(gl), coef.ctypes.data_as(_vp)))
+    return f, gl, coef
 
 
 @dataclass

@@ -113,3 +113,29 @@ def test_eigsh_sphere_spectrum_n20000(gpu_lib):
     assert 2.4 < ratio < 3.4, ratio
     say(f"[eigsh] n=20000: {np.round(v, 4).tolist()}, converged {e.converged}, "
         f"max residual {e.residuals.max():.3g}, l=2/l=1 ratio {ratio:.3f}")
+
+
+def test_kolmogorov_solve_matches_oracle(gpu_lib):
+    """Section 3.1 on the GPU (kvb_eigsh then kvb_kolmogorov_solve) against the
+    oracle's dense eigenvectors and the paper's own formula: the 2-sphere,
+    g = x_1, the span of the l = 1 cluster and of the l = 1 and l = 2 clusters."""
+    kvb = gpu_lib
+    w = workloads.WORKLOADS["sphere2_n2000"]
+    X = workloads.make(w.name, seed=0)
+    g_build = build_lhat(kvb, X, w.k, w.k0)
+    A_ref, info = spectral.union_operator(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G)
+    S_ref = info["P"] * np.sqrt(info["D"])
+    g = X[:, 0].astype(np.float64)
+    g = g - (S_ref ** 2 * g).sum() / (S_ref ** 2).sum()
+    e = kvb.eigsh(g_build.rowptr, g_build.col, g_build.val, nev=9, ncv=300, tol=1e-9, seed=4)
+    for nvec in (4, 9):
+        say(f"[kolmogorov] nvec={nvec}")
+        sub = kvb.Eigs(e.values[:nvec], e.residuals[:nvec], e.vectors[:nvec].contiguous(), e.converged)
+        f, gl, coef = kvb.kolmogorov_solve(sub, g_build.P, g_build.D, torch.from_numpy(g).cuda(), skip=1)
+        fr, glr, gtr, lam = spectral.kolmogorov_solve(A_ref, info["P"], info["D"], g, nvec, 1)
+        f, gl = f.cpu().numpy(), gl.cpu().numpy()
+        assert np.linalg.norm(f - fr) < 1e-3 * np.linalg.norm(fr), np.linalg.norm(f - fr) / np.linalg.norm(fr)
+        assert np.linalg.norm(gl - glr) < 1e-3 * np.linalg.norm(glr)
+        # the coefficients within a cluster depend on the basis chosen in it;
+        # their norm over the span does not
+        assert abs(np.linalg.norm(coef) / np.linalg.norm(gtr) - 1) < 1e-3

@@ -139,6 +139,42 @@ def test_scale_invariance_of_operator(sphere_run):
             np.testing.assert_allclose(v1, v0, rtol=1e-11, atol=1e-12 * abs(v0).max())
 
 
+# ------------------------------------------------------------------ spectral Kolmogorov solve
+def test_kolmogorov_solve_full_span_is_exact():
+    """Section 3.1: with every nonzero eigenpair (l = n - 1) the least-squares
+    solution solves L f = g exactly for g S-orthogonal to the constant."""
+    X = workloads.sphere2(300, seed=8)
+    A, info = spectral.union_operator(X, 16, 8, 2.0, -0.5, -0.5)
+    n = len(X)
+    S = info["P"] * np.sqrt(info["D"])
+    g = X[:, 0].astype(np.float64)
+    g = g - (S ** 2 * g).sum() / (S ** 2).sum()            # <g, 1>_S = 0
+    f, gl, gt, lam = spectral.kolmogorov_solve(A, info["P"], info["D"], g, n, 1)
+    L = (A.toarray() / S[:, None]) * S[None, :]               # L = S^{-1} Lhat S
+    np.testing.assert_allclose(L @ f, g, atol=1e-9 * np.abs(g).max())
+    np.testing.assert_allclose(gl, g, atol=1e-9 * np.abs(g).max())
+    assert abs((S ** 2 * f).sum()) < 1e-9 * np.abs(S ** 2 * f).sum()   # f orthogonal to the constant
+
+
+def test_kolmogorov_solve_sphere_coordinate():
+    """Section 5.2: on the uniform 2-sphere L is the Laplacian and x_1 an
+    eigenfunction (eigenvalue -2), so L f = x_1 has the solution f = -x_1 / 2.
+    The null pair and the l = 1 cluster carry it: g lies almost in their span
+    and f = g / lambda with lambda the discrete cluster's eigenvalue (about
+    -1.4 at n = 2000, k = 32, biased low in magnitude by the tuned bandwidth)."""
+    X = workloads.sphere2(2000, seed=0)
+    A, info = spectral.union_operator(X, 32, 8, 2.0, -0.5, -0.5)
+    S = info["P"] * np.sqrt(info["D"])
+    g = X[:, 0].astype(np.float64)
+    g = g - (S ** 2 * g).sum() / (S ** 2).sum()
+    f, gl, gt, lam = spectral.kolmogorov_solve(A, info["P"], info["D"], g, 4, 1)
+    assert np.linalg.norm(gl - g) < 0.12 * np.linalg.norm(g)    # 8% at this size
+    ratio = (f @ g) / (g @ g)
+    assert abs(ratio * lam.mean() - 1) < 0.05, (ratio, lam)
+    assert -0.8 < ratio < -0.45, ratio                           # -1/2 in the limit
+    assert np.linalg.norm(f - ratio * g) < 0.15 * np.linalg.norm(f)
+
+
 # ------------------------------------------------------------------ union pattern E u E^T
 def union_by_sets(idx, d2):
     """E u E^T from its definition, with Python sets: (i, j) is stored when j
