@@ -328,6 +328,24 @@ int kvb_kolmogorov_solve(kvb_ctx ctx, const double* evecs, const double* evals_h
                          double* coef_host);
 
 /*
+ * Gradients through the Carre du champ identity (Section 3.2): for functions
+ * u, v sampled at the n points, grad u . grad v at the samples from the
+ * eigenbasis, sum over l, j, k < nvec of u~_j v~_k C_ljk (lambda_l - lambda_j
+ * - lambda_k) / 2 phi_l, with C_ljk = <phi_l, phi_j phi_k>_S, u~_j = <u, phi_j>_S,
+ * v~_k = <v, phi_k>_S and phi_j = sqrt(n) S^{-1} y_j (y_j unit eigenvectors of
+ * Lhat as kvb_eigsh returns them, the null pair first). v = x_s gives the
+ * derivative of u along coordinate s. The sum over j and k is evaluated as
+ * lambda_l U V - (L U) V - U (L V) with U, V the projections of u, v and L U,
+ * L V their images, which equals the triple sum term by term.
+ *   evecs [nvec * n] float64 device, evals_host [nvec]; P, D [n] float64 device.
+ *   u, v [n] float64 device in; grad [n] float64 device out.
+ *   C [nvec^3] float64 device out or NULL (nvec <= 64): C_ljk, index (l nvec + j) nvec + k.
+ * Synchronises the context stream.
+ */
+int kvb_carre_du_champ(kvb_ctx ctx, const double* evecs, const double* evals_host, int32_t nvec, const double* P,
+                       const double* D, const double* u, const double* v, int64_t n, double* grad, double* C);
+
+/*
  * Sparsity tolerance of kvb_build (Section 4: Algorithm 1 stores an entry only
  * when its kernel value exceeds delta_tol), 0 <= delta < 1; 0 (the default)
  * keeps every entry. With delta > 0 kvb_build truncates the density kernel

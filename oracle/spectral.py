@@ -86,3 +86,26 @@ def kolmogorov_solve(A, P: np.ndarray, D: np.ndarray, g: np.ndarray, nvec: int, 
     gt = Q.T @ (S ** 2 * g) / n
     f = Q @ (gt / lam)
     return f, Q @ gt, gt, lam
+
+
+def carre_du_champ(A, P: np.ndarray, D: np.ndarray, u: np.ndarray, v: np.ndarray, nvec: int):
+    """grad u . grad v at the samples by the spectral Carre du champ formula of
+    Section 3.2, written out term by term: the leading nvec eigenpairs of L
+    (null pair included; phi_j = S^{-1} phihat_j with phihat^T phihat = n),
+    C_ljk = <phi_l, phi_j * phi_k>_S, u~ = <u, phi>_S, v~ = <v, phi>_S and
+    grad u . grad v = sum_{l,j,k} u~_j v~_k C_ljk (lambda_l - lambda_j - lambda_k) / 2 phi_l.
+    Returns (the gradient product, C, eigenvalues)."""
+    Ad = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+    n = len(Ad)
+    w, Y = np.linalg.eigh(0.5 * (Ad + Ad.T))
+    order = np.argsort(w)[::-1][:nvec]
+    lam = w[order]
+    S = P * np.sqrt(D)
+    Phi = (np.sqrt(n) * Y[:, order]) / S[:, None]
+    S2 = S ** 2
+    C = np.einsum("r,rl,rj,rk->ljk", S2, Phi, Phi, Phi) / n
+    ut = Phi.T @ (S2 * u) / n
+    vt = Phi.T @ (S2 * v) / n
+    fac = lam[:, None, None] - lam[None, :, None] - lam[None, None, :]
+    coef = np.einsum("j,k,ljk,ljk->l", ut, vt, C, fac) / 2
+    return Phi @ coef, C, lam

@@ -137,6 +137,74 @@ __global__ __launch_bounds__(256) void k_expand(const double* __restrict__ Y, in
     if (gl) gl[r] = sg * is;
 }
 
+// Carre du champ (Section 3.2): with p_j = y_j . S u and q_j = y_j . S v,
+//   U = S^{-1} sum_j p_j y_j,  LU = S^{-1} sum_j lambda_j p_j y_j  (and V, LV from q),
+//   t1 = S U V,  t2 = S (LU V + U LV).
+__global__ __launch_bounds__(256) void k_cdc_products(const double* __restrict__ Y, int nvec,
+                                                      const double* __restrict__ coef, const double* __restrict__ P,
+                                                      const double* __restrict__ D, int n, double* __restrict__ t1,
+                                                      double* __restrict__ t2)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    // coef: p, lambda p, q, lambda q (nvec each)
+    double U = 0.0, LU = 0.0, V = 0.0, LV = 0.0;
+    for (int j = 0; j < nvec; ++j) {
+        const double y = Y[static_cast<size_t>(j) * n + r];
+        U += coef[j] * y;
+        LU += coef[nvec + j] * y;
+        V += coef[2 * nvec + j] * y;
+        LV += coef[3 * nvec + j] * y;
+    }
+    const double S = P[r] * sqrt(D[r]), is = 1.0 / S;
+    U *= is;
+    LU *= is;
+    V *= is;
+    LV *= is;
+    t1[r] = S * U * V;
+    t2[r] = S * (LU * V + U * LV);
+}
+
+// C[l][j][k] = <phi_l, phi_j phi_k>_S = sqrt(n) sum_r y_l y_j y_k / S_r for j <= k
+// (one workgroup per pair (j, k), all l at once; the tensor is symmetric)
+constexpr int CDC_MAX = 64;
+__global__ __launch_bounds__(256) void k_cdc_tensor(const double* __restrict__ Y, int nvec,
+                                                    const double* __restrict__ P, const double* __restrict__ D, int n,
+                                                    const int* __restrict__ pair_j, const int* __restrict__ pair_k,
+                                                    double* __restrict__ C)
+{
+    __shared__ double red[4][CDC_MAX];
+    const int j = pair_j[blockIdx.x], k = pair_k[blockIdx.x];
+    double acc[CDC_MAX];
+#pragma unroll
+    for (int l = 0; l < CDC_MAX; ++l) acc[l] = 0.0;
+    for (int r = threadIdx.x; r < n; r += 256) {
+        const double w = Y[static_cast<size_t>(j) * n + r] * Y[static_cast<size_t>(k) * n + r] / (P[r] * sqrt(D[r]));
+#pragma unroll
+        for (int l = 0; l < CDC_MAX; ++l)
+            if (l < nvec) acc[l] += Y[static_cast<size_t>(l) * n + r] * w;
+    }
+    const double rn = sqrt(static_cast<double>(n));
+#pragma unroll
+    for (int l = 0; l < CDC_MAX; ++l) {
+        const double s = wave_sum_f64(acc[l]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][l] = s;
+    }
+    __syncthreads();
+    // each sorted triple l <= j <= k is written, with its permutations, by the
+    // one workgroup of the pair (j, k), so every entry has a single writer
+    for (int l = threadIdx.x; l <= j; l += 256) {
+        const double v = ((red[0][l] + red[1][l]) + (red[2][l] + red[3][l])) * rn;
+        const size_t nv = static_cast<size_t>(nvec);
+        C[(l * nv + j) * nv + k] = v;
+        C[(l * nv + k) * nv + j] = v;
+        C[(j * nv + l) * nv + k] = v;
+        C[(j * nv + k) * nv + l] = v;
+        C[(k * nv + l) * nv + j] = v;
+        C[(k * nv + j) * nv + l] = v;
+    }
+}
+
 }  // namespace kvb
 
 namespace {
@@ -408,6 +476,79 @@ int kvb_kolmogorov_solve(kvb_ctx ctx, const double* evecs, const double* evals_h
         const double rn = 1.0 / std::sqrt(static_cast<double>(n));
         for (int j = 0; j < l; ++j) coef_host[j] = ch[j] * rn;
     }
+    return KVB_OK;
+}
+
+int kvb_carre_du_champ(kvb_ctx ctx, const double* evecs, const double* evals_host, int32_t nvec, const double* P,
+                       const double* D, const double* u, const double* v, int64_t n, double* grad, double* C)
+{
+    if (!ctx) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
+    KVB_REQUIRE(ctx, nvec >= 1 && nvec <= 1024, "need 1 <= nvec <= 1024");
+    KVB_REQUIRE(ctx, C == nullptr || nvec <= kvb::CDC_MAX, "the coefficient tensor needs nvec <= %d", kvb::CDC_MAX);
+    KVB_REQUIRE(ctx, evals_host != nullptr, "evals_host must be non-null");
+    KVB_REQUIRE(ctx, aligned(evecs) && aligned(P) && aligned(D) && aligned(u) && aligned(v) && aligned(grad),
+                "evecs, P, D, u, v, grad must be non-null float64 device pointers");
+    KVB_REQUIRE(ctx, C == nullptr || aligned(C), "C must be aligned");
+    const int nn = static_cast<int>(n);
+    const int npairs = nvec * (nvec + 1) / 2;
+    int rc = ensure_scratch(ctx, 4 * round256(size_t(nn) * sizeof(double)) + 6 * round256(size_t(nvec) * sizeof(double)) +
+                                     2 * round256(size_t(npairs) * sizeof(int)) + 2048);
+    if (rc) return rc;
+    Carve cv(ctx->scratch);
+    double* su = cv.take<double>(nn);
+    double* sv = cv.take<double>(nn);
+    double* t1 = cv.take<double>(nn);
+    double* t2 = cv.take<double>(nn);
+    double* pq = cv.take<double>(2 * size_t(nvec));
+    double* coef = cv.take<double>(4 * size_t(nvec));
+    double* ab = cv.take<double>(2 * size_t(nvec));
+    int* pj = cv.take<int>(npairs);
+    int* pk = cv.take<int>(npairs);
+    hipStream_t st = ctx->stream;
+    const dim3 blk(256), rows_grid((nn + 255) / 256);
+    hipLaunchKernelGGL(kvb::k_weight, rows_grid, blk, 0, st, P, D, u, nn, su);
+    hipLaunchKernelGGL(kvb::k_weight, rows_grid, blk, 0, st, P, D, v, nn, sv);
+    hipLaunchKernelGGL(kvb::k_project, dim3(nvec), blk, 0, st, evecs, static_cast<int64_t>(nn), su, nn, pq);
+    hipLaunchKernelGGL(kvb::k_project, dim3(nvec), blk, 0, st, evecs, static_cast<int64_t>(nn), sv, nn, pq + nvec);
+    KVB_HIP(ctx, hipGetLastError());
+    std::vector<double> h(2 * size_t(nvec)), c4(4 * size_t(nvec));
+    KVB_HIP(ctx, hipMemcpyAsync(h.data(), pq, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    KVB_HIP(ctx, hipStreamSynchronize(st));
+    for (int j = 0; j < nvec; ++j) {
+        c4[j] = h[j];
+        c4[nvec + j] = evals_host[j] * h[j];
+        c4[2 * nvec + j] = h[nvec + j];
+        c4[3 * nvec + j] = evals_host[j] * h[nvec + j];
+    }
+    KVB_HIP(ctx, hipMemcpyAsync(coef, c4.data(), sizeof(double) * c4.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(kvb::k_cdc_products, rows_grid, blk, 0, st, evecs, nvec, coef, P, D, nn, t1, t2);
+    hipLaunchKernelGGL(kvb::k_project, dim3(nvec), blk, 0, st, evecs, static_cast<int64_t>(nn), t1, nn, ab);
+    hipLaunchKernelGGL(kvb::k_project, dim3(nvec), blk, 0, st, evecs, static_cast<int64_t>(nn), t2, nn, ab + nvec);
+    KVB_HIP(ctx, hipGetLastError());
+    KVB_HIP(ctx, hipMemcpyAsync(h.data(), ab, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    KVB_HIP(ctx, hipStreamSynchronize(st));
+    // expansion coefficient of phi_l in grad u . grad v, in the y basis: (lambda_l a_l - b_l) / 2
+    for (int l = 0; l < nvec; ++l) c4[l] = 0.5 * (evals_host[l] * h[l] - h[nvec + l]);
+    KVB_HIP(ctx, hipMemcpyAsync(coef, c4.data(), sizeof(double) * nvec, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(kvb::k_expand, rows_grid, blk, 0, st, evecs, nvec, coef, coef, P, D, nn, grad,
+                       static_cast<double*>(nullptr));
+    KVB_HIP(ctx, hipGetLastError());
+    if (C) {
+        std::vector<int> hj(npairs), hk(npairs);
+        int q = 0;
+        for (int j = 0; j < nvec; ++j)
+            for (int k = j; k < nvec; ++k) {
+                hj[q] = j;
+                hk[q] = k;
+                ++q;
+            }
+        KVB_HIP(ctx, hipMemcpyAsync(pj, hj.data(), sizeof(int) * npairs, hipMemcpyHostToDevice, st));
+        KVB_HIP(ctx, hipMemcpyAsync(pk, hk.data(), sizeof(int) * npairs, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(kvb::k_cdc_tensor, dim3(npairs), blk, 0, st, evecs, nvec, P, D, nn, pj, pk, C);
+        KVB_HIP(ctx, hipGetLastError());
+    }
+    KVB_HIP(ctx, hipStreamSynchronize(st));
     return KVB_OK;
 }
 

@@ -39,7 +39,8 @@ EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb
            "kvb_mlp_backward", "kvb_part_num_params", "kvb_part_get_params", "kvb_part_set_params",
            "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name",
            "kvb_union_pattern", "kvb_density_csr", "kvb_tune_eps_csr", "kvb_normalize_csr",
-           "kvb_truncate_csr", "kvb_set_tolerance", "kvb_eigsh", "kvb_kolmogorov_solve")
+           "kvb_truncate_csr", "kvb_set_tolerance", "kvb_eigsh", "kvb_kolmogorov_solve",
+           "kvb_carre_du_champ")
 PROF_SLOTS = 14
 
 
@@ -86,6 +87,7 @@ def load_library(path: str = LIB_PATH):
     L.kvb_tune_eps_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _i32, _vp,
                                    ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
     L.kvb_set_tolerance.argtypes = [_vp, _f64]
+    L.kvb_carre_du_champ.argtypes = [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp]
     L.kvb_kolmogorov_solve.argtypes = [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp]
     L.kvb_eigsh.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _i32, _f64, ctypes.c_uint64, _vp, _vp, _vp]
     L.kvb_truncate_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _vp, _vp, _vp,
@@ -589,6 +591,24 @@ def kolmogorov_solve(eigs: Eigs, P: torch.Tensor, D: torch.Tensor, g: torch.Tens
                                            _ptr(_dev(P, torch.float64, "P")), _ptr(_dev(D, torch.float64, "D")),
                                            _ptr(g), n, _ptr(f), _ptr(gl), coef.ctypes.data_as(_vp)))
     return f, gl, coef
+
+
+def carre_du_champ(eigs: Eigs, P: torch.Tensor, D: torch.Tensor, u: torch.Tensor, v: torch.Tensor,
+                   tensor: bool = False, ctx: Context | None = None):
+    """grad u . grad v at the samples from the eigenbasis (kvb_carre_du_champ);
+    with tensor=True also the coefficients C_ljk as a [nvec, nvec, nvec] tensor."""
+    ctx = ctx or context()
+    u = _dev(u, torch.float64, "u")
+    v = _dev(v, torch.float64, "v")
+    n = u.numel()
+    nvec = len(eigs.values)
+    grad = torch.empty(n, dtype=torch.float64, device=u.device)
+    C = torch.empty((nvec, nvec, nvec), dtype=torch.float64, device=u.device) if tensor else None
+    ev = np.ascontiguousarray(eigs.values, dtype=np.float64)
+    ctx.check(ctx.lib.kvb_carre_du_champ(ctx.h, _ptr(eigs.vectors), ev.ctypes.data_as(_vp), nvec,
+                                         _ptr(_dev(P, torch.float64, "P")), _ptr(_dev(D, torch.float64, "D")),
+                                         _ptr(u), _ptr(v), n, _ptr(grad), _ptr(C)))
+    return grad, C
 
 
 @dataclass

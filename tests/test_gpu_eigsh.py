@@ -139,3 +139,32 @@ def test_kolmogorov_solve_matches_oracle(gpu_lib):
         # the coefficients within a cluster depend on the basis chosen in it;
         # their norm over the span does not
         assert abs(np.linalg.norm(coef) / np.linalg.norm(gtr) - 1) < 1e-3
+
+
+def test_carre_du_champ_matches_oracle(gpu_lib):
+    """Section 3.2 on the GPU against the oracle's term-by-term triple sum: the
+    2-sphere, the null pair and the l = 1 and l = 2 clusters (nvec = 9, whole
+    clusters), u = x_1 and v = x_1 or x_2. The coefficients C_ljk depend on the
+    basis inside a cluster; their contraction with the projections of u and v,
+    and the resulting gradient product, do not. C is compared through those
+    contractions and its basis-free invariants."""
+    kvb = gpu_lib
+    w = workloads.WORKLOADS["sphere2_n2000"]
+    X = workloads.make(w.name, seed=0)
+    gb = build_lhat(kvb, X, w.k, w.k0)
+    A_ref, info = spectral.union_operator(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G)
+    e = kvb.eigsh(gb.rowptr, gb.col, gb.val, nev=9, ncv=300, tol=1e-9, seed=5)
+    u = X[:, 0].astype(np.float64)
+    for s_ in (0, 1):
+        v = X[:, s_].astype(np.float64)
+        say(f"[cdc] u = x_1, v = x_{s_ + 1}")
+        gr, C = kvb.carre_du_champ(e, gb.P, gb.D, torch.from_numpy(u).cuda(), torch.from_numpy(v).cuda(),
+                                   tensor=True)
+        gr_ref, C_ref, lam = spectral.carre_du_champ(A_ref, info["P"], info["D"], u, v, 9)
+        gr = gr.cpu().numpy()
+        assert np.linalg.norm(gr - gr_ref) < 2e-3 * np.linalg.norm(gr_ref), np.linalg.norm(gr - gr_ref) / np.linalg.norm(gr_ref)
+        C = C.cpu().numpy()
+        # invariants under rotations inside clusters: the Frobenius norm and C_ll0 sums
+        assert abs(np.linalg.norm(C) / np.linalg.norm(C_ref) - 1) < 1e-3
+        np.testing.assert_allclose(C, np.transpose(C, (1, 2, 0)), atol=1e-12 * np.abs(C).max())
+        np.testing.assert_allclose(np.abs(C[:, :, 0]), np.abs(C_ref[0, 0, 0]) * np.eye(9), atol=1e-4 * abs(C_ref[0, 0, 0]))

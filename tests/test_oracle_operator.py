@@ -175,6 +175,31 @@ def test_kolmogorov_solve_sphere_coordinate():
     assert np.linalg.norm(f - ratio * g) < 0.15 * np.linalg.norm(f)
 
 
+# ------------------------------------------------------------------ Carre du champ gradients
+def test_carre_du_champ_coefficients_and_sphere_gradient():
+    """Section 3.2. Pins: C_ljk is symmetric in its three indices and, with the
+    constant null eigenvector phi_0 = c0 (<c0, c0>_S = 1), C_lj0 = c0 delta_lj
+    (orthonormality); on the uniform 2-sphere, where L is the Laplacian,
+    grad x_1 . grad x_1 = 1 - x_1^2 (the tangential part of e_1). The discrete
+    eigenvalues at n = 2000, k = 32 are about 0.7 of -2 and -6, which scales the
+    estimate down by that factor; its shape follows 1 - x_1^2."""
+    X = workloads.sphere2(2000, seed=0)
+    A, info = spectral.union_operator(X, 32, 8, 2.0, -0.5, -0.5)
+    S = info["P"] * np.sqrt(info["D"])
+    u = X[:, 0].astype(np.float64)
+    gr, C, lam = spectral.carre_du_champ(A, info["P"], info["D"], u, u, 9)
+    np.testing.assert_allclose(C, np.transpose(C, (1, 0, 2)), atol=1e-10)
+    np.testing.assert_allclose(C, np.transpose(C, (2, 1, 0)), atol=1e-10)
+    c0 = C[0, 0, 0]
+    assert abs(abs(c0) - 1 / np.sqrt(np.mean(S ** 2))) < 1e-8 * abs(c0)
+    np.testing.assert_allclose(C[:, :, 0], c0 * np.eye(9), atol=1e-8)
+    truth = 1 - u ** 2
+    corr = np.corrcoef(gr, truth)[0, 1]
+    assert corr > 0.97, corr
+    scale = (gr @ truth) / (truth @ truth)
+    assert 0.55 < scale < 1.05, scale
+
+
 # ------------------------------------------------------------------ union pattern E u E^T
 def union_by_sets(idx, d2):
     """E u E^T from its definition, with Python sets: (i, j) is stored when j
