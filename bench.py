@@ -266,6 +266,26 @@ def main() -> int:
                 "basis_GB/s": round(basis_bytes / (e1 - e0) / 1e9, 1)}
         log(f"  eigsh: {args.eigs} pairs, {args.ncv} Lanczos steps in {eigs['ms']} ms, values {eigs['values']}, "
             f"max residual {eigs['max_residual']}")
+        # the downstream steps of Sections 3 and 5.3 on this eigenbasis:
+        # Kolmogorov solve for g = x_1 - mean, grad f per coordinate, particle update
+        g = (Xd[:, 0].double() - Xd[:, 0].double().mean()).contiguous()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        f, _, _ = kvb.kolmogorov_solve(ev, r.P, r.D, g, skip=1, ctx=ctx)
+        s1 = time.perf_counter()
+        grad = torch.empty((w.m, w.n), dtype=torch.float64, device="cuda")
+        for c in range(w.m):
+            grad[c], _ = kvb.carre_du_champ(ev, r.P, r.D, f, Xd[:, c].double().contiguous(), ctx=ctx)
+        s2 = time.perf_counter()
+        Xo = torch.empty_like(Xd)
+        ctx.check(ctx.lib.kvb_advect(ctx.h, kvb._ptr(Xd), w.n, w.m, None, kvb._ptr(grad), None, 0.01, 0.0,
+                                     kvb._ptr(Xo)))
+        torch.cuda.synchronize()
+        s3 = time.perf_counter()
+        eigs.update({"solve_ms": round((s1 - s0) * 1e3, 3), "grad_ms": round((s2 - s1) * 1e3, 3),
+                     "advect_ms": round((s3 - s2) * 1e3, 3)})
+        log(f"  Kolmogorov solve {eigs['solve_ms']} ms, grad f ({w.m} coordinates) {eigs['grad_ms']} ms, "
+            f"particle update {eigs['advect_ms']} ms")
 
     cpu = None
     if not args.no_cpu_baseline:

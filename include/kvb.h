@@ -346,6 +346,20 @@ int kvb_carre_du_champ(kvb_ctx ctx, const double* evecs, const double* evals_hos
                        const double* D, const double* u, const double* v, int64_t n, double* grad, double* C);
 
 /*
+ * Particle update of the density-evolution example (Section 5.3, the explicit
+ * step of the sample SDE): x' = x + dt (u - grad f) + sqrt(dt) sigma w, where
+ * grad f comes from kvb_carre_du_champ with v = x_s for each coordinate s and
+ * f from kvb_kolmogorov_solve.
+ *   X, X_out [n, m] float32 device, row-major (may be the same array).
+ *   velocity [n, m] float64 device or NULL (u = 0); noise [n, m] float64 device
+ *   or NULL (no diffusion): standard normal draws w, which the caller supplies.
+ *   grad [m, n] float64 device: component s of grad f at every sample in row s.
+ * Enqueued only.
+ */
+int kvb_advect(kvb_ctx ctx, const float* X, int64_t n, int32_t m, const double* velocity, const double* grad,
+               const double* noise, double dt, double sigma, float* X_out);
+
+/*
  * Sparsity tolerance of kvb_build (Section 4: Algorithm 1 stores an entry only
  * when its kernel value exceeds delta_tol), 0 <= delta < 1; 0 (the default)
  * keeps every entry. With delta > 0 kvb_build truncates the density kernel

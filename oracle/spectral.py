@@ -109,3 +109,21 @@ def carre_du_champ(A, P: np.ndarray, D: np.ndarray, u: np.ndarray, v: np.ndarray
     fac = lam[:, None, None] - lam[None, :, None] - lam[None, None, :]
     coef = np.einsum("j,k,ljk,ljk->l", ut, vt, C, fac) / 2
     return Phi @ coef, C, lam
+
+
+def advection_step(X: np.ndarray, g: np.ndarray, dt: float, nvec: int, k: int, k0: int,
+                   sigma: float = 0.0, noise: np.ndarray | None = None):
+    """One explicit step of the density-evolution example (Section 5.3) with
+    u = 0: the operator with c = 1 on the union pattern (alpha = -d/4,
+    beta = -1/2, d = m), f solving L f = g in the span of the leading nvec - 1
+    nonzero eigenvectors, grad f by the Carre du champ formula with v = x_s,
+    x' = x - dt grad f + sqrt(dt) sigma w. Returns (x', f, grad f [m, n])."""
+    n, m = X.shape
+    A, info = union_operator(X, k, k0, float(m), -m / 4.0, -0.5)
+    f, _, _, _ = kolmogorov_solve(A, info["P"], info["D"], g, nvec, 1)
+    grad = np.array([carre_du_champ(A, info["P"], info["D"], f, X[:, s].astype(np.float64), nvec)[0]
+                     for s in range(m)])
+    Xn = X.astype(np.float64) - dt * grad.T
+    if noise is not None:
+        Xn = Xn + np.sqrt(dt) * sigma * noise
+    return Xn, f, grad

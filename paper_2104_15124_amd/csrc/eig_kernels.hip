@@ -205,6 +205,25 @@ __global__ __launch_bounds__(256) void k_cdc_tensor(const double* __restrict__ Y
     }
 }
 
+// Particle update of the density-evolution example (Section 5.3, explicit
+// step of the sample SDE): x' = x + dt (u - grad f) + sqrt(dt) sigma w, with
+// x, x' [n, m] float32 row-major, u and w [n, m] float64 row-major (or null:
+// zero), grad [m, n] float64 (one gradient component per row).
+__global__ __launch_bounds__(256) void k_advect(const float* __restrict__ X, int n, int m,
+                                                const double* __restrict__ u, const double* __restrict__ grad,
+                                                const double* __restrict__ w, double dt, double sdt,
+                                                float* __restrict__ Xo)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(n) * m) return;
+    const int r = static_cast<int>(t / m), s = static_cast<int>(t - static_cast<int64_t>(r) * m);
+    double v = -grad[static_cast<size_t>(s) * n + r];
+    if (u) v += u[t];
+    double x = static_cast<double>(X[t]) + dt * v;
+    if (w) x += sdt * w[t];
+    Xo[t] = static_cast<float>(x);
+}
+
 }  // namespace kvb
 
 namespace {
@@ -549,6 +568,22 @@ int kvb_carre_du_champ(kvb_ctx ctx, const double* evecs, const double* evals_hos
         KVB_HIP(ctx, hipGetLastError());
     }
     KVB_HIP(ctx, hipStreamSynchronize(st));
+    return KVB_OK;
+}
+
+int kvb_advect(kvb_ctx ctx, const float* X, int64_t n, int32_t m, const double* velocity, const double* grad,
+               const double* noise, double dt, double sigma, float* X_out)
+{
+    if (!ctx) return KVB_E_INVALID;
+    KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31) && m >= 1 && n * m < (int64_t(1) << 40), "bad n or m");
+    KVB_REQUIRE(ctx, std::isfinite(dt) && dt >= 0 && std::isfinite(sigma), "dt must be finite and >= 0, sigma finite");
+    KVB_REQUIRE(ctx, aligned(X) && aligned(grad) && aligned(X_out), "X, grad, X_out must be non-null device pointers");
+    KVB_REQUIRE(ctx, (velocity == nullptr || aligned(velocity)) && (noise == nullptr || aligned(noise)),
+                "velocity and noise must be aligned");
+    const int64_t total = n * m;
+    hipLaunchKernelGGL(kvb::k_advect, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, ctx->stream, X,
+                       static_cast<int>(n), m, velocity, grad, noise, dt, std::sqrt(dt) * sigma, X_out);
+    KVB_HIP(ctx, hipGetLastError());
     return KVB_OK;
 }
 

@@ -40,7 +40,7 @@ EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb
            "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name",
            "kvb_union_pattern", "kvb_density_csr", "kvb_tune_eps_csr", "kvb_normalize_csr",
            "kvb_truncate_csr", "kvb_set_tolerance", "kvb_eigsh", "kvb_kolmogorov_solve",
-           "kvb_carre_du_champ")
+           "kvb_carre_du_champ", "kvb_advect")
 PROF_SLOTS = 14
 
 
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
     L.kvb_tune_eps_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _i32, _vp,
                                    ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
     L.kvb_set_tolerance.argtypes = [_vp, _f64]
+    L.kvb_advect.argtypes = [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _f64, _f64, _vp]
     L.kvb_carre_du_champ.argtypes = [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp]
     L.kvb_kolmogorov_solve.argtypes = [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp]
     L.kvb_eigsh.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _i32, _f64, ctypes.c_uint64, _vp, _vp, _vp]
@@ -609,6 +610,41 @@ def carre_du_champ(eigs: Eigs, P: torch.Tensor, D: torch.Tensor, u: torch.Tensor
                                          _ptr(_dev(P, torch.float64, "P")), _ptr(_dev(D, torch.float64, "D")),
                                          _ptr(u), _ptr(v), n, _ptr(grad), _ptr(C)))
     return grad, C
+
+
+@dataclass
+class AdvectionStep:
+    X: torch.Tensor          # [n, m] float32, the moved samples
+    f: torch.Tensor          # [n] float64, the Kolmogorov solution
+    grad: torch.Tensor       # [m, n] float64, grad f at the samples
+    eigs: Eigs
+
+
+def advection_step(X: torch.Tensor, g: torch.Tensor, dt: float, ell: int | None = None, k: int = 64, k0: int = 8,
+                   sigma: float = 0.0, velocity: torch.Tensor | None = None, noise: torch.Tensor | None = None,
+                   ncv: int = 400, seed: int = 0, ctx: Context | None = None) -> AdvectionStep:
+    """One time step of the density-evolution example (Section 5.3): the
+    kernel matrix of the samples (symmetric conjugate on the union pattern,
+    c = 1: alpha = -d/4, beta = -1/2 with d = m), its leading ell nonzero
+    eigenpairs (default 3 ln n), the Kolmogorov solution of L f = g, grad f
+    through the Carre du champ identity, then the particle update
+    x + dt (u - grad f) + sqrt(dt) sigma w."""
+    ctx = ctx or context()
+    X = _dev(X, torch.float32, "X")
+    n, m = X.shape
+    ell = ell or int(round(3 * np.log(n)))
+    km = build(X, k, k0, float(m), -m / 4.0, -0.5, out_kind=OUT_SYMMETRIC, pattern="union", ctx=ctx)
+    eg = eigsh(km.rowptr, km.col, km.val, nev=ell + 1, ncv=max(ncv, ell + 1), seed=seed, ctx=ctx)
+    f, _, _ = kolmogorov_solve(eg, km.P, km.D, g, skip=1, ctx=ctx)
+    grad = torch.empty((m, n), dtype=torch.float64, device=X.device)
+    for s in range(m):
+        gs, _ = carre_du_champ(eg, km.P, km.D, f, X[:, s].to(torch.float64), ctx=ctx)
+        grad[s] = gs
+    Xo = torch.empty_like(X)
+    u = None if velocity is None else _dev(velocity, torch.float64, "velocity")
+    w = None if noise is None else _dev(noise, torch.float64, "noise")
+    ctx.check(ctx.lib.kvb_advect(ctx.h, _ptr(X), n, m, _ptr(u), _ptr(grad), _ptr(w), dt, sigma, _ptr(Xo)))
+    return AdvectionStep(Xo, f, grad, eg)
 
 
 @dataclass

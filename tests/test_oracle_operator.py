@@ -200,6 +200,22 @@ def test_carre_du_champ_coefficients_and_sphere_gradient():
     assert 0.55 < scale < 1.05, scale
 
 
+# ------------------------------------------------------------------ density evolution
+def test_advection_step_translates_gaussian():
+    """Section 5.3's validation case: samples of N(0, I_2), g = (x - mean x) . r
+    with r = (1, 0), u = 0. Then L f = g (c = 1) has f = -(x_1 - mean) and the
+    effective velocity -grad f = (1, 0); with l = 3 ln n = 23 eigenpairs the
+    discrete velocity is within 10% of it."""
+    X = workloads.gaussian_iid(2000, 2, seed=3)
+    g = X[:, 0].astype(np.float64) - X[:, 0].mean()
+    dt = 0.1
+    Xn, f, grad = spectral.advection_step(X, g, dt, 24, 64, 8)
+    vel = (Xn - X) / dt
+    assert abs(vel[:, 0].mean() - 1) < 0.12, vel[:, 0].mean()
+    assert abs(vel[:, 1].mean()) < 0.05, vel[:, 1].mean()
+    np.testing.assert_allclose(vel, -grad.T, rtol=1e-6, atol=1e-6)
+
+
 # ------------------------------------------------------------------ union pattern E u E^T
 def union_by_sets(idx, d2):
     """E u E^T from its definition, with Python sets: (i, j) is stored when j
