@@ -476,6 +476,7 @@ int kvb_assemble_csr(kvb_ctx ctx, const int32_t* idx, const float* d2, const flo
 static size_t union_work_bytes(int n, int64_t nk)
 {
     return 2 * round256(size_t(nk) * 4) + round256(size_t(nk)) + round256(size_t(nk) * 8) +
+           round256(size_t(n) * 32 * sizeof(uint16_t)) +
            round256((size_t(n) + 1) * 4) + round256((size_t(n) + 1) * 8) + 3 * round256(16) +
            round256(size_t(n) * 4) + round256(kvb::union_scan_bytes(n)) + 2048;
 }
@@ -486,6 +487,7 @@ static kvb::UnionWork take_union_work(Carve& cv, int n, int64_t nk)
     w.scol = cv.take<int32_t>(nk);
     w.sd2 = cv.take<float>(nk);
     w.flag = cv.take<uint8_t>(nk);
+    w.boff = cv.take<uint16_t>(size_t(n) * 32);
     w.rkey = cv.take<uint64_t>(nk);
     w.cnt = cv.take<int>(size_t(n) + 1);
     w.revptr = cv.take<int64_t>(size_t(n) + 1);

@@ -178,6 +178,7 @@ struct UnionWork {
     int32_t* scol;              // directed rows sorted by column
     float* sd2;
     uint8_t* flag;              // entry contributes a reverse entry
+    uint16_t* boff;             // [n, 32] bucket index of the sorted rows
     uint64_t* rkey;             // reverse entries (at most n k), by row segment
     int* cnt;                   // [n + 1]
     int64_t* revptr;            // [n + 1]

@@ -94,11 +94,50 @@ __device__ __forceinline__ int64_t count_less_key(const uint64_t* __restrict__ a
     return lo;
 }
 
+// 1b. a bucket index of each sorted row: the column range [0, n) is cut into
+// UB equal buckets; boff[j][b] (b = 1..UB-1, slot 0 unused) holds the number
+// of row j's columns below bucket b, so a column's candidates in row j lie
+// between two neighbouring entries of the index (about k / UB of them)
+constexpr int UB = 32;
+
+__device__ __forceinline__ int bucket_of(int v, int n) { return static_cast<int>((static_cast<int64_t>(v) * UB) / n); }
+
+__global__ __launch_bounds__(256) void k_union_buckets(const int32_t* __restrict__ scol, int n, int k,
+                                                       uint16_t* __restrict__ boff)
+{
+    const int lane = lane_id();
+    const int j = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (j >= n || lane >= UB) return;
+    // columns v with bucket_of(v) < b are those below ceil(b n / UB)
+    const int64_t bound = (static_cast<int64_t>(lane) * n + UB - 1) / UB;
+    const int32_t* row = scol + static_cast<size_t>(j) * k;
+    int lo = 0, hi = k;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (row[mid] < bound)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    boff[static_cast<size_t>(j) * UB + lane] = static_cast<uint16_t>(lo);
+}
+
+// the entries of sorted row j that can equal v: [first, last)
+__device__ __forceinline__ void bucket_range(const uint16_t* __restrict__ boff, int j, int k, int n, int v, int& first,
+                                             int& last)
+{
+    const int b = bucket_of(v, n);
+    const uint16_t* o = boff + static_cast<size_t>(j) * UB;
+    first = b == 0 ? 0 : o[b];
+    last = b == UB - 1 ? k : o[b + 1];
+}
+
 // 2. flag[p] = 1 for entries (i, j) whose transpose (j, i) row j does not
 // store; cnt[j] counts them. bad becomes non-zero if a row holds a column
 // outside [0, n) or the same column twice (such entries are skipped, so no
 // access leaves the arrays).
-__global__ __launch_bounds__(256) void k_union_count(const int32_t* __restrict__ scol, int n, int k,
+__global__ __launch_bounds__(256) void k_union_count(const int32_t* __restrict__ scol,
+                                                     const uint16_t* __restrict__ boff, int n, int k,
                                                      int* __restrict__ cnt, uint8_t* __restrict__ flag,
                                                      unsigned long long* __restrict__ bad)
 {
@@ -112,8 +151,11 @@ __global__ __launch_bounds__(256) void k_union_count(const int32_t* __restrict__
         atomicOr(bad, 1ull);
     } else if (j != i) {
         const int32_t* rj = scol + static_cast<size_t>(j) * k;
-        const int64_t at = count_less(rj, k, i);
-        if (!(at < k && rj[at] == i)) {   // row j does not store (j, i) itself
+        int first, last;
+        bucket_range(boff, j, k, n, i, first, last);
+        bool found = false;
+        for (int t = first; t < last; ++t) found |= rj[t] == i;
+        if (!found) {   // row j does not store (j, i) itself
             atomicAdd(cnt + j, 1);
             f = 1;
         }
@@ -382,7 +424,8 @@ hipError_t launch_union_count(const int32_t* idx, const float* d2, int n, int k,
     e = hipMemsetAsync(w.bad, 0, sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
     const int64_t nk = static_cast<int64_t>(n) * k;
-    hipLaunchKernelGGL(k_union_count, dim3(grid_of(nk)), block, 0, st, w.scol, n, k, w.cnt, w.flag, w.bad);
+    hipLaunchKernelGGL(k_union_buckets, rows, block, 0, st, w.scol, n, k, w.boff);
+    hipLaunchKernelGGL(k_union_count, dim3(grid_of(nk)), block, 0, st, w.scol, w.boff, n, k, w.cnt, w.flag, w.bad);
     size_t scan_bytes = w.scan_bytes;
     e = rocprim::exclusive_scan(w.scan_tmp, scan_bytes, w.cnt, w.revptr, int64_t(0), static_cast<size_t>(n) + 1,
                                 rocprim::plus<int64_t>(), st);
