@@ -295,7 +295,7 @@ int kvb_truncate_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, con
  *   rowptr, col, val: the matrix (as kvb_density_csr, val float32); it must be
  *     symmetric (not checked; a non-symmetric input gives meaningless but
  *     finite results).
- *   1 <= nev <= ncv <= min(1024, n); tol > 0; seed: the start vector's seed.
+ *   1 <= nev <= ncv <= min(4096, n); tol > 0; seed: the start vector's seed.
  *   evals_host [nev] host out; resid_host [nev] host out or NULL: the Ritz
  *     residual norms |beta_{ncv-1} s_{ncv-1,i}|.
  *   evecs [nev * n] float64 device out or NULL: unit Ritz vectors, one per row.

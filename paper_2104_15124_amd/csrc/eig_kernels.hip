@@ -353,7 +353,7 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
 {
     if (!ctx) return KVB_E_INVALID;
     KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31)");
-    KVB_REQUIRE(ctx, nev >= 1 && ncv >= nev && ncv <= 1024 && ncv <= n, "need 1 <= nev <= ncv <= min(1024, n)");
+    KVB_REQUIRE(ctx, nev >= 1 && ncv >= nev && ncv <= 4096 && ncv <= n, "need 1 <= nev <= ncv <= min(4096, n)");
     KVB_REQUIRE(ctx, tol > 0 && std::isfinite(tol), "tol must be finite and > 0");
     KVB_REQUIRE(ctx, aligned(val), "val must be a non-null float32 device pointer");
     KVB_REQUIRE(ctx, evals_host != nullptr, "evals_host must be non-null");

@@ -96,16 +96,15 @@ def test_eigsh_sphere_spectrum_n20000(gpu_lib):
     n = len(X)
     g = build_lhat(kvb, X, 32, 8)
     say("[eigsh] Lhat of the 2-sphere, n=20000")
-    e = kvb.eigsh(g.rowptr, g.col, g.val, nev=9, ncv=1024, tol=1e-7, seed=2)
+    e = kvb.eigsh(g.rowptr, g.col, g.val, nev=9, ncv=2048, tol=1e-8, seed=2)
     A = sp.csr_matrix((g.val.cpu().numpy().astype(np.float64), g.col.cpu().numpy(), g.rowptr.cpu().numpy()),
                       shape=(n, n))
     S = 0.5 * (A + A.T)
     # ARPACK in shift-invert mode about 0.5 (above the spectrum of Lhat <= 0)
     wa = np.sort(spla.eigsh(S.tocsc(), k=9, sigma=0.5, which="LM", tol=1e-12, v0=np.ones(n))[0])[::-1]
-    # Ritz value errors are of order residual^2 / gap (residuals ~ 1e-2 after
-    # 1024 steps against a spectrum 1.6e4 wide; gaps ~ 1)
-    np.testing.assert_allclose(e.values, wa, rtol=0, atol=5e-3)
+    np.testing.assert_allclose(e.values, wa, rtol=0, atol=1e-6)
     v = e.values
+    assert e.converged, e.residuals      # 2048 steps: residuals below 1e-8 of the spectrum's width
     assert abs(v[0]) < 1e-3 * abs(v[1])
     l1, l2 = v[1:4], v[4:9]
     assert (l1.max() - l1.min()) < 0.5 * (l1.min() - l2.max())     # separated clusters
