@@ -199,3 +199,34 @@ def test_single_call_truncated_build(gpu_lib, pattern):
             np.testing.assert_array_equal(ca[ra[i]:ra[i + 1]][oa], cb[rb[i]:rb[i + 1]])
             np.testing.assert_allclose(va[ra[i]:ra[i + 1]][oa], vb[rb[i]:rb[i + 1]], rtol=1e-6)
         torch.testing.assert_close(a.rho, b.rho, rtol=1e-6, atol=0)
+
+
+def test_truncated_build_gmm_n8m_sampled_rows(gpu_lib):
+    """The largest workload (n = 8e6, k = 64) built in one call with the
+    sparsity tolerance 1e-2: the operator pattern's rows of 48 sampled samples
+    against the keep rule x = (d2 (1 / (e rho_i))) / rho_j < -ln(delta),
+    evaluated in float64 with the same operations on the GPU's rho and e_B,
+    bit for bit; the rows are the k-NN rows in column order."""
+    kvb = gpu_lib
+    w = workloads.WORKLOADS["gmm_n8m"]
+    X = workloads.make(w.name, seed=0)
+    n, k, delta = len(X), w.k, 1e-2
+    say(f"[truncate] gmm_n8m: n={n} k={k} delta={delta}")
+    g = kvb.build(torch.from_numpy(X).cuda(), k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
+                  mode="bf16", margin=w.margin, delta=delta)
+    rho = f64(g.rho)
+    e_b = g.tune_b.e_star
+    L = -np.log(delta)
+    rowptr = g.rowptr.cpu().numpy()
+    rng = np.random.default_rng(13)
+    for i in np.sort(rng.choice(n, 48, replace=False)):
+        order = np.argsort(g.idx[i].cpu().numpy(), kind="stable")
+        cols = g.idx[i].cpu().numpy()[order]
+        dd = g.d2[i].cpu().numpy()[order].astype(np.float64)
+        x = dd * (1.0 / (e_b * rho[i])) / rho[cols]
+        keep = x < L
+        lo, hi = rowptr[i], rowptr[i + 1]
+        assert g.col[lo:hi].cpu().numpy().tolist() == cols[keep].tolist(), i
+    kept = int(rowptr[-1])
+    assert kept == g.col.numel() and 0 < kept < n * k
+    say(f"[truncate] gmm_n8m: kept {kept} of {n * k} entries ({kept / (n * k):.3f})")

@@ -318,3 +318,37 @@ def test_union_async_builds_back_to_back(gpu_lib):
     d = kvb.build(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G)
     assert d.col.numel() == X.shape[0] * w.k
     assert torch.equal(d.rowptr, torch.arange(X.shape[0] + 1, device="cuda", dtype=torch.int64) * w.k)
+
+
+def test_union_pattern_gmm_n8m_sampled_rows(gpu_lib):
+    """The largest workload (n = 8e6, k = 64, matrix-core k-NN, as bench.py
+    times it): the union rows of 48 sampled samples against the set definition
+    (the row's own list plus every row that lists it), bit for bit, with each
+    reverse entry's distance taken from the row that lists it."""
+    kvb = gpu_lib
+    w = workloads.WORKLOADS["gmm_n8m"]
+    X = workloads.make(w.name, seed=0)
+    n, k = len(X), w.k
+    say(f"[union] gmm_n8m: n={n} k={k}")
+    idx_g, d2_g, _ = kvb.knn(torch.from_numpy(X).cuda(), k, mode="bf16", margin=w.margin)
+    pat = kvb.union_pattern(idx_g, d2_g)
+    idx, d2 = idx_g.cpu().numpy(), d2_g.cpu().numpy()
+    rowptr = pat.rowptr.cpu().numpy()
+    rng = np.random.default_rng(12)
+    R = np.sort(rng.choice(n, 48, replace=False)).astype(np.int32)
+    flat = idx.ravel()
+    pos = np.searchsorted(R, flat)
+    hit = np.nonzero((pos < len(R)) & (R[np.minimum(pos, len(R) - 1)] == flat))[0]
+    src_row = hit // k
+    for q, i in enumerate(R):
+        own = dict(zip(idx[i].tolist(), d2[i].tolist()))
+        rev = {int(s): float(d2.ravel()[p]) for s, p in zip(src_row[flat[hit] == i], hit[flat[hit] == i])}
+        want = dict(rev)
+        want.update(own)                                  # a pair the row stores keeps its own distance
+        lo, hi = rowptr[i], rowptr[i + 1]
+        cols = pat.col[lo:hi].cpu().numpy()
+        dd = pat.d2[lo:hi].cpu().numpy()
+        assert cols.tolist() == sorted(want), i
+        assert [float(v) for v in dd] == [want[c] for c in cols.tolist()], i
+    assert rowptr[-1] == pat.nnz and np.all(np.diff(rowptr) >= k)
+    say(f"[union] gmm_n8m: {pat.nnz} entries ({pat.nnz / (n * k):.4f} n k), 48 rows checked")
