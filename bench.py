@@ -213,11 +213,13 @@ def main() -> int:
     union = args.pattern == "union"
     csr = union or args.delta > 0
     nnz = float(r.rowptr[-1].item()) if csr else nk
+    # the tuning sums run over the whole base pattern (before any truncation)
+    base_nnz = nk if not union else (nnz if args.delta <= 0 else float(kvb.union_pattern(r.idx, r.d2, ctx).nnz))
     rows8 = float(w.n) * 8 if csr else 0.0                         # rowptr reads of the CSR passes
     pass_bytes = {
         "knn_refine": float(w.n) * kp * (w.m * 4 + 8) + nk * 8,    # candidate rows + keys, idx/d2 out
         "adhoc_bandwidth": float(w.n) * (w.k0 * 4 + 4),
-        "chi_tuning": nnz * 12 + float(w.n) * 4 + rows8,
+        "chi_tuning": base_nnz * 12 + float(w.n) * 4 + rows8 + (base_nnz * 4 if csr else 0.0),   # + row ids
         "density": nnz * 12 + float(w.n) * 12 + rows8,
         "q_pass": nnz * 12 + float(w.n) * 12 + rows8,
         # entries in / CSR out (the union pattern's columns are already written), P and D
@@ -229,8 +231,7 @@ def main() -> int:
     if args.delta > 0:
         # two truncations of the base pattern: its entries read (col, d2, the
         # gathered rho_j) twice, the kept entries written
-        base = float(nk) if not union else float(kvb.union_pattern(r.idx, r.d2, ctx).nnz)
-        pass_bytes["truncate"] = 2 * base * 12 + 2 * nnz * 8 + float(w.n) * 32
+        pass_bytes["truncate"] = 2 * base_nnz * 12 + 2 * nnz * 8 + float(w.n) * 32
     passes = {}
     for name, byt in pass_bytes.items():
         ms, cnt = prof.get(name, (0.0, 0))
@@ -242,7 +243,7 @@ def main() -> int:
                         "frac": round(gbs / HBM_PEAK_GBS, 4)}
     if "chi_tuning" in passes:
         # G exponentials per stored entry; v_exp_f32 issues at a quarter of the lane rate
-        exps = nnz * w.G / (passes["chi_tuning"]["avg_ms"] / 1e3)
+        exps = base_nnz * w.G / (passes["chi_tuning"]["avg_ms"] / 1e3)
         passes["chi_tuning"]["exp_per_s"] = float(f"{exps:.4g}")
         passes["chi_tuning"]["exp_frac"] = round(exps / (ALU_PEAK_TOPS * 1e12 / 4), 4)
     log("  passes: " + ", ".join(f"{k} {v['GB/s']} GB/s ({100 * v['frac']:.1f}% HBM)" for k, v in passes.items()))

@@ -629,8 +629,8 @@ int kvb_tune_eps_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, con
     double* part = cv.take<double>(size_t(nb) * G);
     {
         Prof pr(ctx, KVB_PROF_CHI);
-        KVB_HIP(ctx, kvb::launch_chi_csr(rowptr, col, ud2, static_cast<int>(n), nnz, nnz, rho, G, e_min, e_max,
-                                         nullptr, part, ctx->tune_dev, ctx->stream));
+        KVB_HIP(ctx, kvb::launch_chi_csr(rowptr, nullptr, col, ud2, static_cast<int>(n), nnz, nnz, rho, G, e_min,
+                                         e_max, nullptr, part, ctx->tune_dev, ctx->stream));
     }
     KVB_HIP(ctx, hipMemcpyAsync(ctx->tune_host, ctx->tune_dev, sizeof(kvb::TuneResult), hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -690,7 +690,8 @@ static int build_csr(kvb_ctx ctx, int64_t n, int32_t k, int32_t k0, double d, do
     const int lb = kvb::logsum_num_blocks(nn);
     const size_t scan_bytes = kvb::union_scan_bytes(nn);
     const size_t pat_bytes = round256((size_t(nn) + 1) * 8) + round256(size_t(cap) * 4) * 2;
-    const size_t need = union_work_bytes(nn, nk) + pat_bytes * 3 + round256((size_t(nn) + 1) * 4) +
+    const size_t need = union_work_bytes(nn, nk) + pat_bytes * 3 + round256(size_t(cap) * 4) +
+                        round256((size_t(nn) + 1) * 4) +
                         round256(scan_bytes) + round256(size_t(nb) * G * sizeof(double)) +
                         round256(size_t(2 * lb) * sizeof(double)) + 2 * round256(size_t(nn) * sizeof(double)) + 4096;
     int rc = ensure_scratch(ctx, need);
@@ -705,6 +706,7 @@ static int build_csr(kvb_ctx ctx, int64_t n, int32_t k, int32_t k0, double d, do
     int32_t* acol = cv.take<int32_t>(cap);
     float* ad2 = cv.take<float>(cap);
     float* od2 = cv.take<float>(cap);                    // operator pattern distances (truncated)
+    int32_t* brid = cv.take<int32_t>(cap);               // row of every base entry
     int* tcnt = cv.take<int>(size_t(nn) + 1);
     void* tscan = cv.take<char>(scan_bytes);
     double* part = cv.take<double>(size_t(nb) * G);
@@ -726,10 +728,12 @@ static int build_csr(kvb_ctx ctx, int64_t n, int32_t k, int32_t k0, double d, do
         } else {
             KVB_HIP(ctx, kvb::launch_sorted_rows(idx, d2, nn, k, brow, bcol, bd2, st));
         }
+        KVB_HIP(ctx, kvb::launch_row_ids(brow, nn, brid, st));   // read by both tuning passes
     }
     {
         Prof pr(ctx, KVB_PROF_CHI);
-        KVB_HIP(ctx, kvb::launch_chi_csr(brow, bcol, bd2, nn, nk, cap, b, G, e_min, e_max, nullptr, part, &bd->a, st));
+        KVB_HIP(ctx, kvb::launch_chi_csr(brow, brid, bcol, bd2, nn, nk, cap, b, G, e_min, e_max, nullptr, part, &bd->a,
+                                         st));
     }
     const int64_t* drow = brow;
     const int32_t* dcol = bcol;
@@ -752,8 +756,8 @@ static int build_csr(kvb_ctx ctx, int64_t n, int32_t k, int32_t k0, double d, do
     }
     {
         Prof pr(ctx, KVB_PROF_CHI);
-        KVB_HIP(ctx, kvb::launch_chi_csr(brow, bcol, bd2, nn, nk, cap, rho, G, e_min, e_max, &bd->scale, part, &bd->b,
-                                         st));
+        KVB_HIP(ctx, kvb::launch_chi_csr(brow, brid, bcol, bd2, nn, nk, cap, rho, G, e_min, e_max, &bd->scale, part,
+                                         &bd->b, st));
     }
     const float* od = bd2;
     if (trunc) {

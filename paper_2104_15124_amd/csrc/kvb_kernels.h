@@ -210,8 +210,10 @@ hipError_t launch_density_csr(const int64_t* rowptr, const int32_t* col, const f
 // nnz_cap: an upper bound of rowptr[n] (the kernel reads the count from
 // rowptr[n]); nnz_hint: the expected count, which sets the block partition
 int chi_csr_blocks(int64_t nnz_hint, int64_t nnz_cap);
-hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, int64_t nnz_hint,
-                          int64_t nnz_cap, const float* rho, int G, double e_min, double e_max,
+// rowid [nnz] (or null: the kernel walks rowptr): each entry's row, from launch_row_ids
+hipError_t launch_row_ids(const int64_t* rowptr, int n, int32_t* rowid, hipStream_t st);
+hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* rowid, const int32_t* col, const float* d2, int n,
+                          int64_t nnz_hint, int64_t nnz_cap, const float* rho, int G, double e_min, double e_max,
                           const double* scale_dev, double* partial, TuneResult* out, hipStream_t st);
 hipError_t launch_qpass_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, const float* rho,
                             double e, const double* e_dev, double alpha, double d, double* qa, hipStream_t st);

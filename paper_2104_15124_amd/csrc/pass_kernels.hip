@@ -120,11 +120,13 @@ constexpr int CHI_MIN_ENTRIES_PER_BLOCK = 4096;
 constexpr int CHI_BATCH = 4;
 constexpr int CHI_MAX_BLOCKS = 1024;
 
-// CSR: rows given by rowptr [n + 1] (k unused); otherwise k entries per row.
+// CSR: rows given by rowptr [n + 1] (k unused) and, when rowid is not null,
+// the row of every entry; otherwise k entries per row.
 template <bool CSR>
 __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __restrict__ idx,
                                                            const float* __restrict__ d2,
-                                                           const int64_t* __restrict__ rowptr, int n,
+                                                           const int64_t* __restrict__ rowptr,
+                                                           const int32_t* __restrict__ rowid, int n,
                                                            const float* __restrict__ rho, int64_t nnz, int k,
                                                            int G, double e_min, double e_max,
                                                            const double* __restrict__ scale_dev, int64_t per_block,
@@ -159,7 +161,9 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
         const int di = CSR ? 0 : CHI_BLOCK / k, dr = CSR ? 0 : CHI_BLOCK % k;
         int64_t irow, rend = 0;
         int rcol = 0;
-        if (CSR) {
+        if (CSR && rowid) {
+            irow = 0;
+        } else if (CSR) {
             // the row holding the thread's first entry: last i with rowptr_i <= p
             const int64_t p = min(base + threadIdx.x, nnz - 1);
             int lo = 0, hi = n;
@@ -186,7 +190,9 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
                 const bool ok = p < end;
                 dv[u] = ok ? d2[p] : 0.f;
                 jv[u] = ok ? idx[p] : 0;
-                if (CSR) {
+                if (CSR && rowid) {
+                    iv[u] = ok ? rowid[p] : 0;
+                } else if (CSR) {
                     // p < nnz = rowptr_n, so the walk stops at a row below n
                     if (ok) {
                         while (p >= rend) {
@@ -593,8 +599,8 @@ hipError_t launch_chi(const int32_t* idx, const float* d2, const float* rho, int
                       double e_max, const double* scale_dev, double* partial, TuneResult* out, hipStream_t st)
 {
     const int nb = chi_num_blocks(nnz);
-    hipLaunchKernelGGL(k_chi_partial<false>, dim3(nb), dim3(CHI_BLOCK), 0, st, idx, d2, nullptr, 0, rho, nnz, k, G,
-                       e_min, e_max, scale_dev, chi_per_block(nnz), partial);
+    hipLaunchKernelGGL(k_chi_partial<false>, dim3(nb), dim3(CHI_BLOCK), 0, st, idx, d2, nullptr, nullptr, 0, rho, nnz,
+                       k, G, e_min, e_max, scale_dev, chi_per_block(nnz), partial);
     hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, out);
     return hipGetLastError();
 }
@@ -656,14 +662,30 @@ int chi_csr_blocks(int64_t nnz_hint, int64_t nnz_cap)
     return static_cast<int>((nnz_cap + per - 1) / per);
 }
 
-hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, int64_t nnz_hint,
-                          int64_t nnz_cap, const float* rho, int G, double e_min, double e_max,
+// rowid [nnz_cap] int32: each entry's row, filled by k_row_ids (every row's
+// entries in [rowptr_i, rowptr_{i+1}))
+__global__ __launch_bounds__(256) void k_row_ids(const int64_t* __restrict__ rowptr, int n, int32_t* __restrict__ rowid)
+{
+    const int lane = lane_id();
+    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i >= n) return;
+    for (int64_t p = rowptr[i] + lane; p < rowptr[i + 1]; p += WAVE) rowid[p] = i;
+}
+
+hipError_t launch_row_ids(const int64_t* rowptr, int n, int32_t* rowid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_row_ids, dim3((n + 3) / 4), dim3(256), 0, st, rowptr, n, rowid);
+    return hipGetLastError();
+}
+
+hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* rowid, const int32_t* col, const float* d2, int n,
+                          int64_t nnz_hint, int64_t nnz_cap, const float* rho, int G, double e_min, double e_max,
                           const double* scale_dev, double* partial, TuneResult* out, hipStream_t st)
 {
     // blocks sized for the expected count; enough of them for the largest
     const int nb = chi_csr_blocks(nnz_hint, nnz_cap);
-    hipLaunchKernelGGL(k_chi_partial<true>, dim3(nb), dim3(CHI_BLOCK), 0, st, col, d2, rowptr, n, rho, nnz_cap, 0, G,
-                       e_min, e_max, scale_dev, chi_per_block(nnz_hint), partial);
+    hipLaunchKernelGGL(k_chi_partial<true>, dim3(nb), dim3(CHI_BLOCK), 0, st, col, d2, rowptr, rowid, n, rho, nnz_cap,
+                       0, G, e_min, e_max, scale_dev, chi_per_block(nnz_hint), partial);
     hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, out);
     return hipGetLastError();
 }
