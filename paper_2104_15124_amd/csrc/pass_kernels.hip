@@ -251,10 +251,14 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
 // Fixed-order reduction of the block partials, then slopes and the optimum
 // (Section 2.3): slope_g = (ln chi_{g+1} - ln chi_g) / (ln e_{g+1} - ln e_g),
 // g* = first argmax, e* = e_{g*}, dimension estimate 2 slope_{g*}.
+// nnz_dev (or null): the pattern's entry count on the device; blocks past it
+// hold zero partials and are skipped (adding zeros would change nothing)
 __global__ __launch_bounds__(1024) void k_chi_finish(const double* __restrict__ partial, int nblocks, int G,
                                                     double e_min, double e_max, const double* __restrict__ scale_dev,
+                                                    const int64_t* __restrict__ nnz_dev, int64_t per_block,
                                                     TuneResult* __restrict__ out)
 {
+    if (nnz_dev) nblocks = static_cast<int>(min(static_cast<int64_t>(nblocks), (*nnz_dev + per_block - 1) / per_block));
     const double sc = scale_dev ? *scale_dev : 1.0;
     const double log_emin = log(e_min * sc), log_emax = log(e_max * sc);
     __shared__ double chi[256];
@@ -601,7 +605,8 @@ hipError_t launch_chi(const int32_t* idx, const float* d2, const float* rho, int
     const int nb = chi_num_blocks(nnz);
     hipLaunchKernelGGL(k_chi_partial<false>, dim3(nb), dim3(CHI_BLOCK), 0, st, idx, d2, nullptr, nullptr, 0, rho, nnz,
                        k, G, e_min, e_max, scale_dev, chi_per_block(nnz), partial);
-    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, out);
+    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, nullptr, 0,
+                       out);
     return hipGetLastError();
 }
 
@@ -686,7 +691,8 @@ hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* rowid, const int
     const int nb = chi_csr_blocks(nnz_hint, nnz_cap);
     hipLaunchKernelGGL(k_chi_partial<true>, dim3(nb), dim3(CHI_BLOCK), 0, st, col, d2, rowptr, rowid, n, rho, nnz_cap,
                        0, G, e_min, e_max, scale_dev, chi_per_block(nnz_hint), partial);
-    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, out);
+    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, rowptr + n, chi_per_block(nnz_hint),
+                       out);
     return hipGetLastError();
 }
 
