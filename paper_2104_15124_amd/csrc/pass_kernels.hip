@@ -251,43 +251,44 @@ __global__ __launch_bounds__(CHI_BLOCK) void k_chi_partial(const int32_t* __rest
 // Fixed-order reduction of the block partials, then slopes and the optimum
 // (Section 2.3): slope_g = (ln chi_{g+1} - ln chi_g) / (ln e_{g+1} - ln e_g),
 // g* = first argmax, e* = e_{g*}, dimension estimate 2 slope_{g*}.
-// nnz_dev (or null): the pattern's entry count on the device; blocks past it
-// hold zero partials and are skipped (adding zeros would change nothing)
-__global__ __launch_bounds__(1024) void k_chi_finish(const double* __restrict__ partial, int nblocks, int G,
-                                                    double e_min, double e_max, const double* __restrict__ scale_dev,
+// chi[g] = the sum of the block partials of grid point g: one workgroup per
+// grid point, thread t summing blocks t, t + 256, ... in order, then a fixed
+// tree over the threads. nnz_dev (or null): the pattern's entry count on the
+// device; blocks past it hold zero partials and are skipped (adding zeros
+// would change nothing).
+__global__ __launch_bounds__(256) void k_chi_reduce(const double* __restrict__ partial, int nblocks, int G,
                                                     const int64_t* __restrict__ nnz_dev, int64_t per_block,
                                                     TuneResult* __restrict__ out)
 {
     if (nnz_dev) nblocks = static_cast<int>(min(static_cast<int64_t>(nblocks), (*nnz_dev + per_block - 1) / per_block));
+    __shared__ double red[256];
+    const int g = blockIdx.x;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) a += partial[static_cast<size_t>(b) * G + g];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out->chi[g] = red[0];
+}
+
+// Slopes and the optimum (Section 2.3): slope_g = (ln chi_{g+1} - ln chi_g) /
+// (ln e_{g+1} - ln e_g), g* = first argmax, e* = e_{g*}, dimension estimate
+// 2 slope_{g*}.
+__global__ __launch_bounds__(256) void k_chi_finish(int G, double e_min, double e_max,
+                                                    const double* __restrict__ scale_dev,
+                                                    TuneResult* __restrict__ out)
+{
     const double sc = scale_dev ? *scale_dev : 1.0;
     const double log_emin = log(e_min * sc), log_emax = log(e_max * sc);
-    __shared__ double chi[256];
     __shared__ double slope[256];
-    __shared__ double part[1024];
-    // S fixed slices of the block partials per grid point, each summed in block
-    // order, then the slices in slice order
-    const int Gr = (G + 63) / 64 * 64;
-    const int S = 1024 / Gr;
-    const int g = threadIdx.x % Gr, sl = threadIdx.x / Gr;
-    if (sl < S && g < G) {
-        double a = 0.0;
-#pragma unroll 8
-        for (int b = sl; b < nblocks; b += S) a += partial[static_cast<size_t>(b) * G + g];
-        part[sl * Gr + g] = a;
-    }
-    __syncthreads();
-    if (threadIdx.x < G) {
-        double a = 0.0;
-        for (int t = 0; t < S; ++t) a += part[t * Gr + threadIdx.x];
-        chi[threadIdx.x] = a;
-        out->chi[threadIdx.x] = a;
-    }
-    __syncthreads();
     if (threadIdx.x + 1 < G) {
         const int t = threadIdx.x;
         const double el = exp(grid_log(log_emin, log_emax, G, t));
         const double er = exp(grid_log(log_emin, log_emax, G, t + 1));
-        slope[t] = (log(chi[t + 1]) - log(chi[t])) / (log(er) - log(el));
+        slope[t] = (log(out->chi[t + 1]) - log(out->chi[t])) / (log(er) - log(el));
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -605,8 +606,8 @@ hipError_t launch_chi(const int32_t* idx, const float* d2, const float* rho, int
     const int nb = chi_num_blocks(nnz);
     hipLaunchKernelGGL(k_chi_partial<false>, dim3(nb), dim3(CHI_BLOCK), 0, st, idx, d2, nullptr, nullptr, 0, rho, nnz,
                        k, G, e_min, e_max, scale_dev, chi_per_block(nnz), partial);
-    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, nullptr, 0,
-                       out);
+    hipLaunchKernelGGL(k_chi_reduce, dim3(G), dim3(256), 0, st, partial, nb, G, nullptr, 0, out);
+    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(256), 0, st, G, e_min, e_max, scale_dev, out);
     return hipGetLastError();
 }
 
@@ -691,8 +692,9 @@ hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* rowid, const int
     const int nb = chi_csr_blocks(nnz_hint, nnz_cap);
     hipLaunchKernelGGL(k_chi_partial<true>, dim3(nb), dim3(CHI_BLOCK), 0, st, col, d2, rowptr, rowid, n, rho, nnz_cap,
                        0, G, e_min, e_max, scale_dev, chi_per_block(nnz_hint), partial);
-    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(1024), 0, st, partial, nb, G, e_min, e_max, scale_dev, rowptr + n, chi_per_block(nnz_hint),
+    hipLaunchKernelGGL(k_chi_reduce, dim3(G), dim3(256), 0, st, partial, nb, G, rowptr + n, chi_per_block(nnz_hint),
                        out);
+    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(256), 0, st, G, e_min, e_max, scale_dev, out);
     return hipGetLastError();
 }
 
