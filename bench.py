@@ -52,8 +52,8 @@ def measured_traffic(workload: str, kernel: str):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="torus_n100k")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", default="", choices=["", "f32", "bf16", "learned"],
