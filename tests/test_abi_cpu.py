@@ -6,6 +6,7 @@ no CPU path by design.
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -74,3 +75,12 @@ def test_header_constants_match_binding():
              "KVB_PROF_SLOTS": kvb.PROF_SLOTS}
     for k, v in pairs.items():
         assert consts[k] == v, k
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus N > 1 exits with a message, before any
+    GPU or library work."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
