@@ -206,3 +206,35 @@ def test_advection_step_matches_oracle(gpu_lib):
     diff = st2.X.cpu().numpy().astype(np.float64) - st.X.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(diff, np.sqrt(dt) * noise, atol=1e-5)
     say(f"[advect] mean velocity {vel.mean(axis=0).round(4).tolist()}")
+
+
+def test_spectral_entry_points_reject_bad_arguments(gpu_lib):
+    """Argument errors come back as KVB_E_INVALID with a message, a short
+    Lanczos run reports KVB_W_NOT_CONVERGED (results still returned), and the
+    context keeps working."""
+    kvb = gpu_lib
+    n = 300
+    T = sp.diags([np.ones(n - 1), -2 * np.ones(n), np.ones(n - 1)], [-1, 0, 1], format="csr")
+    rp, cl, vl = csr_to_gpu(T)
+    with pytest.raises(kvb.KvbError, match="ncv"):
+        kvb.eigsh(rp, cl, vl, nev=10, ncv=5)
+    with pytest.raises(kvb.KvbError, match="ncv"):
+        kvb.eigsh(rp, cl, vl, nev=4, ncv=n + 1)
+    bad = cl.clone()
+    bad[7] = n                                    # a column outside [0, n)
+    with pytest.raises(kvb.KvbError, match="col"):
+        kvb.eigsh(rp, bad, vl, nev=2, ncv=8)
+    e = kvb.eigsh(rp, cl, vl, nev=4, ncv=8, tol=1e-12)
+    assert not e.converged and np.isfinite(e.values).all() and (e.residuals > 0).all()
+    full = kvb.eigsh(rp, cl, vl, nev=4, ncv=n, tol=1e-9)
+    assert full.converged
+    P = torch.ones(n, dtype=torch.float64, device="cuda")
+    D = torch.ones(n, dtype=torch.float64, device="cuda")
+    g = torch.ones(n, dtype=torch.float64, device="cuda")
+    with pytest.raises(kvb.KvbError, match="skip"):
+        kvb.kolmogorov_solve(full, P, D, g, skip=4)
+    zero = kvb.Eigs(np.array([0.0, -1.0]), full.residuals[:2], full.vectors[:2].contiguous(), True)
+    with pytest.raises(kvb.KvbError, match="zero"):
+        kvb.kolmogorov_solve(zero, P, D, g, skip=0)
+    f, gl, coef = kvb.kolmogorov_solve(full, P, D, g, skip=0)
+    assert torch.isfinite(f).all()
