@@ -21,7 +21,7 @@
 //
 // On the device: the matrix-vector product (one wavefront per row, FP64
 // accumulation of float32 entries), the projections V^T w (one workgroup per
-// basis vector), w -= V h (one thread per row), norms and Ritz vectors. Every reduction has a fixed order, so results are reproducible.
+// basis vector and row chunk, then a fixed-order sum over the chunks), w -= V h (one thread per row), norms and Ritz vectors. Every reduction has a fixed order, so results are reproducible.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -64,6 +64,36 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ V, i
     if (threadIdx.x == 0) h[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// part[s * ldp + c] = V[c][rows of chunk s] . w[same rows]: grid (ncol, chunks),
+// so that a few columns still spread over the whole chip; the same fixed-order
+// reduction within each workgroup as k_project
+__global__ __launch_bounds__(256) void k_project_part(const double* __restrict__ V, int64_t ldv,
+                                                      const double* __restrict__ w, int n, int chunk, int ldp,
+                                                      double* __restrict__ part)
+{
+    __shared__ double red[4];
+    const double* vc = V + static_cast<size_t>(blockIdx.x) * ldv;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.y) * chunk;
+    const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
+    double s = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) s += vc[r] * w[r];
+    s = wave_sum_f64(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[static_cast<size_t>(blockIdx.y) * ldp + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// h[c] = sum over chunks s, in order, of part[s * ldp + c]
+__global__ __launch_bounds__(256) void k_project_sum(const double* __restrict__ part, int ncol, int nchunk,
+                                                     int ldp, double* __restrict__ h)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    double s = 0.0;
+    for (int q = 0; q < nchunk; ++q) s += part[static_cast<size_t>(q) * ldp + c];
+    h[c] = s;
+}
+
 // w[r] -= sum_c V[c][r] h[c]
 __global__ __launch_bounds__(256) void k_subtract_span(const double* __restrict__ V, int64_t ldv, int ncol,
                                                        const double* __restrict__ h, int n, double* __restrict__ w)
@@ -71,6 +101,7 @@ __global__ __launch_bounds__(256) void k_subtract_span(const double* __restrict_
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     double s = 0.0;
+#pragma unroll 8
     for (int c = 0; c < ncol; ++c) s += V[static_cast<size_t>(c) * ldv + r] * h[c];
     w[r] -= s;
 }
@@ -228,6 +259,11 @@ __global__ __launch_bounds__(256) void k_advect(const float* __restrict__ X, int
 
 namespace {
 
+// split of the Lanczos projections over rows: chunks of at least 8192 rows,
+// at most 64 chunks
+constexpr int PROJ_MIN_CHUNK = 8192;
+constexpr int PROJ_MAX_CHUNKS = 64;
+
 using namespace kvbh;
 
 // Number of eigenvalues of the symmetric tridiagonal T = tridiag(b, a, b)
@@ -363,7 +399,8 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
     const int64_t ldv = (n + 63) / 64 * 64;
     const size_t need = round256(size_t(ncv + 1) * ldv * sizeof(double)) + round256(size_t(ldv) * sizeof(double)) +
                         2 * round256(size_t(ncv + 1) * sizeof(double)) +
-                        round256(size_t(ncv) * nev * sizeof(double)) + 2048;
+                        round256(size_t(ncv) * nev * sizeof(double)) +
+                        round256(size_t(PROJ_MAX_CHUNKS) * (ncv + 1) * sizeof(double)) + 2048;
     int rc = ensure_scratch(ctx, need);
     if (rc) return rc;
     Carve cv(ctx->scratch);
@@ -372,19 +409,29 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
     double* h = cv.take<double>(ncv + 1);
     double* hsum = cv.take<double>(ncv + 1);
     double* S = cv.take<double>(size_t(ncv) * nev);
+    const int ldp = ncv + 1;
+    double* part = cv.take<double>(size_t(PROJ_MAX_CHUNKS) * ldp);
     hipStream_t st = ctx->stream;
     const dim3 blk(256), rows_grid((nn + 255) / 256), spmv_grid((nn + 3) / 4);
     std::vector<double> hh(ncv + 1);
+    // row chunks of the projections: at least PROJ_MIN_CHUNK rows, a multiple
+    // of 256, at most PROJ_MAX_CHUNKS of them
+    int chunk = std::max(PROJ_MIN_CHUNK, (nn + PROJ_MAX_CHUNKS - 1) / PROJ_MAX_CHUNKS);
+    chunk = (chunk + 255) / 256 * 256;
+    const int nchunk = (nn + chunk - 1) / chunk;
 
-    // hd = V[:, :ncol]^T x on the device
-    auto project = [&](const double* x, int ncol, double* hd) -> hipError_t {
-        hipLaunchKernelGGL(kvb::k_project, dim3(ncol), blk, 0, st, V, ldv, x, nn, hd);
+    // hd[0..ncol) = B[:, :ncol]^T x on the device, B's columns ldv apart
+    auto project_cols = [&](const double* B, const double* x, int ncol, double* hd) -> hipError_t {
+        hipLaunchKernelGGL(kvb::k_project_part, dim3(ncol, nchunk), blk, 0, st, B, ldv, x, nn, chunk, ldp, part);
+        hipLaunchKernelGGL(kvb::k_project_sum, dim3((ncol + 255) / 256), blk, 0, st, part, ncol, nchunk, ldp, hd);
         return hipGetLastError();
+    };
+    auto project = [&](const double* x, int ncol, double* hd) -> hipError_t {
+        return project_cols(V, x, ncol, hd);
     };
     // ||x||
     auto norm = [&](double* x, double* out) -> int {
-        hipLaunchKernelGGL(kvb::k_project, dim3(1), blk, 0, st, x, ldv, x, nn, h);
-        KVB_HIP(ctx, hipGetLastError());
+        KVB_HIP(ctx, project_cols(x, x, 1, h));
         KVB_HIP(ctx, hipMemcpyAsync(out, h, sizeof(double), hipMemcpyDeviceToHost, st));
         KVB_HIP(ctx, hipStreamSynchronize(st));
         *out = std::sqrt(*out);
