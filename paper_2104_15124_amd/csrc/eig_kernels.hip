@@ -114,6 +114,22 @@ __global__ __launch_bounds__(256) void k_scale(const double* __restrict__ x, dou
     if (r < n) out[r] = x[r] * scale;
 }
 
+// ab[0] = h[0] on the first Gram-Schmidt pass, ab[0] += h[0] on the second
+__global__ void k_alpha_add(const double* __restrict__ h, int first, double* __restrict__ ab)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) ab[0] = first ? h[0] : ab[0] + h[0];
+}
+
+// b = sqrt(nrm2[0]); out[r] = x[r] * (1 / b); the first thread stores b
+__global__ __launch_bounds__(256) void k_scale_by_norm(const double* __restrict__ x, const double* __restrict__ nrm2,
+                                                       int n, double* __restrict__ out, double* __restrict__ b)
+{
+    const double bj = sqrt(nrm2[0]);
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0) b[0] = bj;
+    if (r < n) out[r] = x[r] * (1.0 / bj);
+}
+
 // the seeded start vector: SplitMix64 (Steele, Lea and Flood 2014) of
 // seed + r mapped to [-1, 1)
 __global__ __launch_bounds__(256) void k_start_vector(uint64_t seed, int n, double* __restrict__ v)
@@ -361,8 +377,15 @@ void top_eigenpairs(const std::vector<double>& a, const std::vector<double>& b, 
         }
         theta[q] = 0.5 * (l + h);
         std::vector<double> y(m);
-        for (int i = 0; i < m; ++i) y[i] = 1.0 + 0.01 * std::sin(1.0 + 7.0 * i + 3.0 * q);
+        double y0 = 0.0;
+        for (int i = 0; i < m; ++i) {
+            y[i] = 1.0 + 0.01 * std::sin(1.0 + 7.0 * i + 3.0 * q);
+            y0 += y[i] * y[i];
+        }
+        y0 = std::sqrt(y0);
+        for (int i = 0; i < m; ++i) y[i] /= y0;
         for (int it = 0; it < 3; ++it) {
+            const std::vector<double> prev = y;
             shifted_solve(a, b, m, theta[q], tiny, y);
             for (int p = 0; p < q; ++p) {
                 if (std::fabs(theta[p] - theta[q]) > 1e-3 * norm) continue;
@@ -370,8 +393,20 @@ void top_eigenpairs(const std::vector<double>& a, const std::vector<double>& b, 
                 for (int i = 0; i < m; ++i) dot += Y[size_t(p) * m + i] * y[i];
                 for (int i = 0; i < m; ++i) y[i] -= dot * Y[size_t(p) * m + i];
             }
+            // normalise after scaling by the largest entry: a pivot at the
+            // floor (T - theta I exactly singular, as for T = 0) makes the
+            // entries as large as 1/tiny, whose squares would overflow
+            double amax = 0.0;
+            for (int i = 0; i < m; ++i) amax = std::max(amax, std::fabs(y[i]));
+            if (!(amax > 0.0) || !std::isfinite(amax)) {
+                y = prev;   // keep the last unit iterate
+                break;
+            }
             double nrm = 0.0;
-            for (int i = 0; i < m; ++i) nrm += y[i] * y[i];
+            for (int i = 0; i < m; ++i) {
+                y[i] /= amax;
+                nrm += y[i] * y[i];
+            }
             nrm = std::sqrt(nrm);
             for (int i = 0; i < m; ++i) y[i] /= nrm;
         }
@@ -400,7 +435,8 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
     const size_t need = round256(size_t(ncv + 1) * ldv * sizeof(double)) + round256(size_t(ldv) * sizeof(double)) +
                         2 * round256(size_t(ncv + 1) * sizeof(double)) +
                         round256(size_t(ncv) * nev * sizeof(double)) +
-                        round256(size_t(PROJ_MAX_CHUNKS) * (ncv + 1) * sizeof(double)) + 2048;
+                        round256(size_t(PROJ_MAX_CHUNKS) * (ncv + 1) * sizeof(double)) +
+                        round256(2 * size_t(ncv) * sizeof(double)) + 2048;
     int rc = ensure_scratch(ctx, need);
     if (rc) return rc;
     Carve cv(ctx->scratch);
@@ -413,7 +449,7 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
     double* part = cv.take<double>(size_t(PROJ_MAX_CHUNKS) * ldp);
     hipStream_t st = ctx->stream;
     const dim3 blk(256), rows_grid((nn + 255) / 256), spmv_grid((nn + 3) / 4);
-    std::vector<double> hh(ncv + 1);
+    double* ab = cv.take<double>(2 * size_t(ncv));   // alpha_0..alpha_{ncv-1}, then beta_0..beta_{ncv-1}
     // row chunks of the projections: at least PROJ_MIN_CHUNK rows, a multiple
     // of 256, at most PROJ_MAX_CHUNKS of them
     int chunk = std::max(PROJ_MIN_CHUNK, (nn + PROJ_MAX_CHUNKS - 1) / PROJ_MAX_CHUNKS);
@@ -438,29 +474,42 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
         return KVB_OK;
     };
 
-    std::vector<double> alpha, beta;
     hipLaunchKernelGGL(kvb::k_start_vector, rows_grid, blk, 0, st, seed, nn, w);
     double b0 = 0.0;
     KVB_TRY(norm(w, &b0));
     KVB_REQUIRE(ctx, b0 > 0, "start vector vanished");
     hipLaunchKernelGGL(kvb::k_scale, rows_grid, blk, 0, st, w, 1.0 / b0, nn, V);
-    int m = 0;
+    // The steps run without a host round trip: alpha_j and beta_j stay on the
+    // device until the end. A breakdown (beta_j = 0, an invariant subspace)
+    // is found afterwards; the steps after it hold non-finite values that no
+    // Ritz vector uses.
+    double* alpha_d = ab;
+    double* beta_d = ab + ncv;
     for (int j = 0; j < ncv; ++j) {
         double* vj = V + size_t(j) * ldv;
         hipLaunchKernelGGL(kvb::k_spmv, spmv_grid, blk, 0, st, rowptr, col, val, vj, nn, w);
         // two passes of classical Gram-Schmidt against v_0..v_j; alpha_j is
         // the first pass's coefficient on v_j plus the second's correction
-        double a = 0.0;
         for (int pass = 0; pass < 2; ++pass) {
             KVB_HIP(ctx, project(w, j + 1, hsum));
             hipLaunchKernelGGL(kvb::k_subtract_span, rows_grid, blk, 0, st, V, ldv, j + 1, hsum, nn, w);
-            KVB_HIP(ctx, hipMemcpyAsync(hh.data(), hsum + j, sizeof(double), hipMemcpyDeviceToHost, st));
-            KVB_HIP(ctx, hipStreamSynchronize(st));
-            a += hh[0];
+            hipLaunchKernelGGL(kvb::k_alpha_add, dim3(1), dim3(64), 0, st, hsum + j, pass == 0 ? 1 : 0,
+                               alpha_d + j);
         }
-        double bj = 0.0;
-        KVB_TRY(norm(w, &bj));
-        alpha.push_back(a);
+        // beta_j = ||w||, v_{j+1} = w / beta_j (V has room for v_ncv)
+        KVB_HIP(ctx, project_cols(w, w, 1, h));
+        hipLaunchKernelGGL(kvb::k_scale_by_norm, rows_grid, blk, 0, st, w, h, nn, V + size_t(j + 1) * ldv,
+                           beta_d + j);
+        KVB_HIP(ctx, hipGetLastError());
+    }
+    std::vector<double> abh(2 * size_t(ncv));
+    KVB_HIP(ctx, hipMemcpyAsync(abh.data(), ab, sizeof(double) * abh.size(), hipMemcpyDeviceToHost, st));
+    KVB_HIP(ctx, hipStreamSynchronize(st));
+    std::vector<double> alpha, beta;
+    int m = 0;
+    for (int j = 0; j < ncv; ++j) {
+        const double bj = abh[size_t(ncv) + j];
+        alpha.push_back(abh[j]);
         m = j + 1;
         if (j + 1 == ncv) {
             beta.push_back(bj);
@@ -471,7 +520,6 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
             break;
         }
         beta.push_back(bj);
-        hipLaunchKernelGGL(kvb::k_scale, rows_grid, blk, 0, st, w, 1.0 / bj, nn, V + size_t(j + 1) * ldv);
     }
     KVB_REQUIRE(ctx, nev <= m, "the Krylov space closed after %d steps, below nev = %d", m, nev);
     // Ritz pairs of T

@@ -238,3 +238,27 @@ def test_spectral_entry_points_reject_bad_arguments(gpu_lib):
         kvb.kolmogorov_solve(zero, P, D, g, skip=0)
     f, gl, coef = kvb.kolmogorov_solve(full, P, D, g, skip=0)
     assert torch.isfinite(f).all()
+
+
+def test_eigsh_breakdown_on_an_invariant_subspace(gpu_lib):
+    """The zero matrix (zeros stored on the diagonal) maps the start vector to
+    exactly zero, so beta_0 = 0: the Krylov space is the start vector's span,
+    Lanczos stops after one step, and its one Ritz pair (0, v_0) is exact
+    (Golub and Van Loan, Section 10.1: a zero beta_j means the Krylov space is
+    invariant). Asking for more pairs than that space holds is an error, and
+    the context keeps working afterwards."""
+    kvb = gpu_lib
+    n = 64
+    Z = sp.csr_matrix((np.zeros(n), np.arange(n), np.arange(n + 1)), shape=(n, n))
+    rp, cl, vl = csr_to_gpu(Z)
+    e = kvb.eigsh(rp, cl, vl, nev=1, ncv=16, tol=1e-12, seed=9)
+    say("breakdown", f"value {e.values[0]!r}, residual {e.residuals[0]!r}")
+    assert e.converged and e.values[0] == 0.0 and e.residuals[0] == 0.0
+    v = e.vectors[0].cpu().numpy()
+    assert np.isfinite(v).all() and abs(np.linalg.norm(v) - 1.0) < 1e-12
+    with pytest.raises(kvb.KvbError, match="closed"):
+        kvb.eigsh(rp, cl, vl, nev=2, ncv=16, seed=9)
+    T = sp.diags([np.ones(n - 1), -2 * np.ones(n), np.ones(n - 1)], [-1, 0, 1], format="csr")
+    full = kvb.eigsh(*csr_to_gpu(T), nev=3, ncv=n, tol=1e-9, seed=9)
+    exact = -2 + 2 * np.cos(np.pi * np.arange(1, 4) / (n + 1))
+    assert full.converged and np.max(np.abs(full.values - exact)) < 1e-5
