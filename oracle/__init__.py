@@ -54,6 +54,8 @@ def lib():
     L.oracle_num_threads.restype = ctypes.c_int
     L.oracle_knn_rows.argtypes = [_f32p, _c_i64, _c_i32, _c_i32, _c_i64, _c_i64, _i32p, _f64p]
     L.oracle_knn_rows.restype = ctypes.c_int
+    L.oracle_knn_list.argtypes = [_f32p, _c_i64, _c_i32, _c_i32, _i64p, _c_i64, _i32p, _f64p]
+    L.oracle_knn_list.restype = ctypes.c_int
     L.oracle_adhoc_bandwidth.argtypes = [_f64p, _c_i64, _c_i32, _c_i32, _f64p]
     L.oracle_adhoc_bandwidth.restype = ctypes.c_int
     L.oracle_chi.argtypes = [_i64p, _i32p, _f64p, _f64p, _c_i64, _c_f64, _c_f64, _c_i32,
@@ -104,17 +106,14 @@ def knn(X: np.ndarray, k: int, rows: np.ndarray | slice | None = None):
 
 
 def knn_sampled(X: np.ndarray, k: int, rows: np.ndarray):
-    """Exact k-NN of the listed rows (any order) against all samples."""
+    """Exact k-NN of the listed rows (any order) against all samples, one row
+    per thread."""
     X = np.ascontiguousarray(X, dtype=np.float32)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
     out_i = np.empty((len(rows), k), dtype=np.int32)
     out_d = np.empty((len(rows), k), dtype=np.float64)
-    L = lib()
     n, m = X.shape
-    for t, r in enumerate(np.asarray(rows, dtype=np.int64)):
-        ii = np.empty((1, k), dtype=np.int32)
-        dd = np.empty((1, k), dtype=np.float64)
-        _check(L.oracle_knn_rows(X, n, m, k, int(r), int(r) + 1, ii, dd), "knn")
-        out_i[t], out_d[t] = ii[0], dd[0]
+    _check(lib().oracle_knn_list(X, n, m, k, rows, len(rows), out_i, out_d), "knn_list")
     return out_i, out_d
 
 

@@ -78,6 +78,49 @@ static int key_less(double da, int64_t ja, double db, int64_t jb)
 }
 
 /*
+ * Exact k-NN of one row i against all n samples, on the calling thread: i
+ * itself (distance 0), then the k-1 samples j != i first in (D2_ij, j) order,
+ * kept in a bounded insertion list.
+ */
+static int oracle_knn_rows_serial(const float* X, int64_t n, int32_t m, int32_t k, int64_t i, int32_t* idx,
+                                  double* d2)
+{
+    int32_t kk = k - 1;
+    double* bd = (double*)malloc(sizeof(double) * (size_t)(kk > 0 ? kk : 1));
+    int64_t* bj = (int64_t*)malloc(sizeof(int64_t) * (size_t)(kk > 0 ? kk : 1));
+    if (!bd || !bj) {
+        free(bd);
+        free(bj);
+        return ORC_ENOMEM;
+    }
+    const float* xi = X + (size_t)i * (size_t)m;
+    int32_t cnt = 0;
+    for (int64_t j = 0; j < n && kk > 0; ++j) {
+        if (j == i) continue;
+        double s = dist2_f64(xi, X + (size_t)j * (size_t)m, m);
+        if (cnt < kk || key_less(s, j, bd[cnt - 1], bj[cnt - 1])) {
+            int32_t p = (cnt < kk) ? cnt++ : cnt - 1;
+            while (p > 0 && key_less(s, j, bd[p - 1], bj[p - 1])) {
+                bd[p] = bd[p - 1];
+                bj[p] = bj[p - 1];
+                --p;
+            }
+            bd[p] = s;
+            bj[p] = j;
+        }
+    }
+    idx[0] = (int32_t)i;
+    d2[0] = 0.0;
+    for (int32_t r = 0; r < kk; ++r) {
+        idx[1 + r] = (int32_t)bj[r];
+        d2[1 + r] = bd[r];
+    }
+    free(bd);
+    free(bj);
+    return ORC_OK;
+}
+
+/*
  * Exact k-NN self-join over rows [row_begin, row_end) against all n samples.
  * Row i of the output holds i itself (distance 0) and then the k-1 samples
  * j != i that come first in the (D2_ij, j) order. A bounded insertion list
@@ -137,6 +180,27 @@ int oracle_knn_rows(const float* X, int64_t n, int32_t m, int32_t k,
 int oracle_knn(const float* X, int64_t n, int32_t m, int32_t k, int32_t* idx, double* d2)
 {
     return oracle_knn_rows(X, n, m, k, 0, n, idx, d2);
+}
+
+/* Exact k-NN of the listed rows (any order, each in [0, n)) against all n
+ * samples; output row t belongs to sample rows[t]. The same search as
+ * oracle_knn_rows, one list row per thread. */
+int oracle_knn_list(const float* X, int64_t n, int32_t m, int32_t k, const int64_t* rows, int64_t nrows,
+                    int32_t* idx, double* d2)
+{
+    if (!X || !rows || !idx || !d2 || n < 1 || m < 1 || k < 1 || k > n || nrows < 0) return ORC_EINVAL;
+    for (int64_t t = 0; t < nrows; ++t)
+        if (rows[t] < 0 || rows[t] >= n) return ORC_EINVAL;
+    int err = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nrows; ++t) {
+        int rc = oracle_knn_rows_serial(X, n, m, k, rows[t], idx + t * (int64_t)k, d2 + t * (int64_t)k);
+        if (rc != ORC_OK) {
+#pragma omp atomic write
+            err = rc;
+        }
+    }
+    return err;
 }
 
 /* b_i = sqrt(sum_{r=1..k0} d2[i, r]) over the k-NN rows (self at r = 0 is skipped). */
@@ -322,13 +386,10 @@ int oracle_normalize(const int64_t* rowptr, const int32_t* col, const double* di
  * Threshold truncation (Section 4: Algorithm 1 and the k-d tree algorithm
  * store an entry only when its kernel value exceeds the sparsity tolerance
  * delta_tol). Entry (i, j) of the pattern is kept when
- * exp(-D2_ij / (e rho_i rho_j)) > delta, 0 < delta < 1. The test is taken on
- * the exponent, x < -ln(delta), with x formed as (D2 * (1 / (e rho_i))) / rho_j
- * in double precision: the equivalent strict inequality without the rounding
- * of exp, and the same operations as the library's kernel, so that both sides
- * take every keep/drop decision identically. Kept entries keep their order;
- * rowptr_out (length n + 1) and the kept columns and distances are written.
- * *nnz_out receives rowptr_out[n].
+ * K_ij = exp(-D2_ij / (e rho_i rho_j)) > delta, 0 < delta < 1, evaluated as
+ * written, in double precision. Kept entries keep their order; rowptr_out
+ * (length n + 1) and the kept columns and distances are written. *nnz_out
+ * receives rowptr_out[n].
  */
 int oracle_truncate(const int64_t* rowptr, const int32_t* col, const double* dist2, const double* rho, int64_t n,
                     double e, double delta, int64_t* rowptr_out, int32_t* col_out, double* dist2_out,
@@ -337,14 +398,12 @@ int oracle_truncate(const int64_t* rowptr, const int32_t* col, const double* dis
     if (!rowptr || !col || !dist2 || !rho || !rowptr_out || !col_out || !dist2_out || n < 1 || !(e > 0.0) ||
         !(delta > 0.0 && delta < 1.0))
         return ORC_EINVAL;
-    const double L = -log(delta);
     int64_t out = 0;
     for (int64_t i = 0; i < n; ++i) {
         rowptr_out[i] = out;
-        const double inv = 1.0 / (e * rho[i]);
         for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-            const double x = dist2[p] * inv / rho[col[p]];
-            if (x < L) {
+            const double K = exp(-dist2[p] / (e * rho[i] * rho[col[p]]));
+            if (K > delta) {
                 col_out[out] = col[p];
                 dist2_out[out] = dist2[p];
                 ++out;
