@@ -269,8 +269,9 @@ int kvb_normalize_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, co
  * CSR pattern (rowptr, col, d2: as kvb_density_csr) is kept when
  * exp(-d2 / (e rho_i rho_j)) > delta, 0 < delta < 1; the test is taken on the
  * exponent, x < -ln(delta) with x = (d2 (1 / (e rho_i))) / rho_j in FP64 and
- * ln on the host, so that a reference making the same operations takes every
- * decision identically. Kept entries keep their order.
+ * ln on the host (the same inequality without the rounding of exp; an entry
+ * whose exponent lies within a few FP64 rounding steps of -ln(delta) may be
+ * decided either way). Kept entries keep their order.
  *   rho [n] float32 in; e > 0.
  *   rowptr_out [n+1] int64 out; col_out [nnz] int32 out, d2_out [nnz] float32
  *   out (capacity nnz always suffices; rowptr_out[n] entries are written).
@@ -289,23 +290,36 @@ int kvb_truncate_csr(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, con
  * Section 2.2, e.g. KVB_OUT_SYMMETRIC on KVB_PATTERN_UNION, approximate the
  * Kolmogorov operator's; Sections 2.2, 4 and 5). Lanczos with full
  * reorthogonalisation (two passes of classical Gram-Schmidt per step), ncv
- * steps from a seeded start vector, no restart; the Ritz pairs of the
- * tridiagonal projection (cyclic Jacobi on the host, FP64) are returned for
- * the nev largest eigenvalues (for Lhat, those nearest zero), descending.
+ * steps from a seeded start vector, no restart; the Lanczos coefficients stay
+ * on the device until the last step. The Ritz pairs of the tridiagonal
+ * projection T (eigenvalues by Sturm-count bisection, eigenvectors by inverse
+ * iteration, on the host in FP64) are returned for the nev largest
+ * eigenvalues (for Lhat, those nearest zero), descending. A breakdown
+ * (beta_j = 0: an invariant subspace) ends the projection early; its Ritz
+ * pairs are then exact.
  *   rowptr, col, val: the matrix (as kvb_density_csr, val float32); it must be
  *     symmetric (not checked; a non-symmetric input gives meaningless but
  *     finite results).
  *   1 <= nev <= ncv <= min(4096, n); tol > 0; seed: the start vector's seed.
  *   evals_host [nev] host out; resid_host [nev] host out or NULL: the Ritz
- *     residual norms |beta_{ncv-1} s_{ncv-1,i}|.
+ *     residual norms |beta_{m-1} s_{m-1,i}| (m the steps used).
  *   evecs [nev * n] float64 device out or NULL: unit Ritz vectors, one per row.
- * Returns KVB_W_NOT_CONVERGED if a residual exceeds tol * max|Ritz value|.
- * Scratch: (ncv + 1) n doubles. Synchronises the context stream (three times
- * per step).
+ * Returns KVB_W_NOT_CONVERGED if a residual exceeds tol * ||T||_inf (results
+ * still returned); KVB_E_INVALID if a Lanczos coefficient is not finite (the
+ * matrix holds non-finite values) or the space closes before nev steps.
+ * Scratch: (ncv + 1) n doubles. Synchronises the context stream once after the
+ * steps (and once more when evecs is requested).
  */
 int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* val, int64_t n, int64_t nnz,
               int32_t nev, int32_t ncv, double tol, uint64_t seed, double* evals_host, double* resid_host,
               double* evecs);
+
+/* The part of a Lanczos run kvb_eigsh keeps (host only, needs no device):
+ * *m_host = the steps up to and including the first breakdown (beta_j <= 1e-300)
+ * or ncv. KVB_E_INVALID if alpha_j or beta_j of a kept step is not finite or
+ * beta_j < 0 (*m_host then counts the steps before it).
+ *   alpha_host, beta_host [ncv] host in. */
+int kvb_lanczos_prefix(const double* alpha_host, const double* beta_host, int32_t ncv, int32_t* m_host);
 
 /*
  * Spectral solution of the Kolmogorov problem L f = g (Section 3.1): the
@@ -515,6 +529,22 @@ int kvb_profile_read(kvb_ctx ctx, int32_t slot, double* total_ms_host, int64_t* 
 
 /* Short name of a slot ("" if out of range; static storage). */
 const char* kvb_profile_name(int32_t slot);
+
+/* ---- measured peaks: the chip's rates for the resources the build is bound
+ * by, so that roofline fractions can be stated against the chip as measured as
+ * well as against its published figures ---- */
+#define KVB_PEAK_HBM_COPY 0   /* bytes read + written per second by a streaming copy of 2 GiB */
+#define KVB_PEAK_MFMA_BF16 1  /* flops per second of v_mfma_f32_32x32x16_bf16 chains */
+#define KVB_PEAK_MFMA_F32 2   /* flops per second of v_mfma_f32_32x32x2f32 chains */
+#define KVB_PEAK_EXP 3        /* v_exp_f32 results per second */
+#define KVB_PEAK_VALU_FMA 4   /* v_fma_f32 lane operations per second */
+
+/* Run the microbenchmark `kind` (KVB_PEAK_*) on the context's stream: one
+ * warm-up launch, then the fastest of five timed launches (HIP events).
+ * *rate_host = its rate (units above); *ms_host (or NULL) = that launch's
+ * milliseconds. Allocates and frees its own device buffer (4 GiB for the copy,
+ * 4 MiB otherwise): KVB_E_NOMEM if that fails. Synchronises the stream. */
+int kvb_peak_probe(kvb_ctx ctx, int32_t kind, double* rate_host, double* ms_host);
 
 #ifdef __cplusplus
 }

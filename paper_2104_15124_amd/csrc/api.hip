@@ -176,6 +176,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
     // curve order of the principal projections (matrix-core modes)
     const bool curve = !direct && ctx->curve_order && m <= 256;
     const int npad32 = (nn + 31) / 32 * 32, ctiles = npad32 / 32;
+    const kvb::TreeLayout tl = kvb::tree_layout(ctiles);
     const int csb = (ctiles + kvb::SB_TILES_MFMA - 1) / kvb::SB_TILES_MFMA;
     const size_t ntri = size_t(m) * (m + 1) / 2;
     size_t csort = 0;
@@ -188,6 +189,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                 2 * round256(size_t(nn) * sizeof(uint32_t)) + 3 * round256(size_t(nn) * sizeof(int32_t)) +
                 round256(size_t(npad32) * sizeof(int32_t)) + round256(size_t(npad32) * kvb::PR_DIMS * sizeof(float)) +
                 round256(size_t(ctiles) * 2 * kvb::PR_DIMS * sizeof(float)) +
+                round256(size_t(std::max(tl.nodes, 1)) * 2 * kvb::PR_DIMS * sizeof(float)) +
                 round256(size_t(csb) * 2 * kvb::PR_DIMS * sizeof(float)) + round256(csort) +
                 round256(size_t(nn) * m * sizeof(float)) + 512;
     }
@@ -256,12 +258,13 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                 int32_t* cid = cv.take<int32_t>(npad32);
                 float* zs = cv.take<float>(size_t(npad32) * kvb::PR_DIMS);
                 float* tbox = cv.take<float>(size_t(ctiles) * 2 * kvb::PR_DIMS);
+                float* tree = cv.take<float>(size_t(std::max(tl.nodes, 1)) * 2 * kvb::PR_DIMS);
                 float* sbox = cv.take<float>(size_t(csb) * 2 * kvb::PR_DIMS);
                 void* sort_tmp = cv.take<char>(csort);
                 KVB_HIP(ctx, kvb::launch_colmean(X, nn, m, colpart, colblocks, mu, ctx->stream));
                 KVB_HIP(ctx, kvb::launch_principal_basis(X, nn, m, mu, covpart, C, P, ctx->stream));
                 KVB_HIP(ctx, kvb::launch_curve_order(X, nn, m, mu, P, z, zpart, code, scode, vals, order, sort_tmp,
-                                                     csort, pos, cid, zs, tbox, sbox, ctx->stream));
+                                                     csort, pos, cid, zs, tbox, sbox, tree, ctx->stream));
                 // curve-ordered copy of the samples for the refine step
                 Xs = cv.take<float>(size_t(nn) * m);
                 KVB_HIP(ctx, kvb::launch_gather_rows(X, nn, m, cid, Xs, ctx->stream));
@@ -277,6 +280,8 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                 crv.zs = zs;
                 crv.tbox = tbox;
                 crv.sbox = sbox;
+                crv.tree = tree;
+                crv.layout = tl;
                 crv.pscale = P + size_t(m) * kvb::PR_DIMS;
                 // a float32 dot product of m terms errs by at most m u |y| |p| (|p| <= 1 + m u)
                 crv.zcoef = static_cast<float>((m + 2) * u * 1.01);
@@ -300,8 +305,12 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
         em.center = 1.01 * u;
         {
             Prof pr(ctx, KVB_PROF_KNN_SELECT);
-            KVB_HIP(ctx, kvb::launch_select_mfma(split, Aq, Bc, nn, kpad, kp, ynorm2, rmax, em, keys, cap, slast,
-                                                 nullptr, 0, curve ? &crv : nullptr, ctx->pairs_dev, ctx->stream));
+            if (curve && kvb::select_tree_fits(split, kpad))
+                KVB_HIP(ctx, kvb::launch_select_tree(split, Aq, Bc, nn, kpad, kp, ynorm2, rmax, em, keys, cap, slast,
+                                                     crv, ctx->pairs_dev, ctx->stream));
+            else
+                KVB_HIP(ctx, kvb::launch_select_mfma(split, Aq, Bc, nn, kpad, kp, ynorm2, rmax, em, keys, cap, slast,
+                                                     nullptr, 0, curve ? &crv : nullptr, ctx->pairs_dev, ctx->stream));
         }
         kstride = cap;
     }

@@ -418,6 +418,24 @@ void top_eigenpairs(const std::vector<double>& a, const std::vector<double>& b, 
 
 extern "C" {
 
+int kvb_lanczos_prefix(const double* alpha_host, const double* beta_host, int32_t ncv, int32_t* m_host)
+{
+    if (!alpha_host || !beta_host || !m_host || ncv < 1) return KVB_E_INVALID;
+    // the steps up to the first breakdown (beta_j = 0 up to underflow: an
+    // invariant subspace) or all ncv of them; every coefficient used must be
+    // finite, and a NaN beta is not a breakdown
+    int32_t m = 0;
+    for (int32_t j = 0; j < ncv; ++j) {
+        const double a = alpha_host[j], b = beta_host[j];
+        *m_host = m;
+        if (!std::isfinite(a) || !std::isfinite(b) || b < 0.0) return KVB_E_INVALID;
+        m = j + 1;
+        if (b <= 1e-300) break;
+    }
+    *m_host = m;
+    return KVB_OK;
+}
+
 int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const float* val, int64_t n, int64_t nnz,
               int32_t nev, int32_t ncv, double tol, uint64_t seed, double* evals_host, double* resid_host,
               double* evecs)
@@ -505,22 +523,13 @@ int kvb_eigsh(kvb_ctx ctx, const int64_t* rowptr, const int32_t* col, const floa
     std::vector<double> abh(2 * size_t(ncv));
     KVB_HIP(ctx, hipMemcpyAsync(abh.data(), ab, sizeof(double) * abh.size(), hipMemcpyDeviceToHost, st));
     KVB_HIP(ctx, hipStreamSynchronize(st));
-    std::vector<double> alpha, beta;
     int m = 0;
-    for (int j = 0; j < ncv; ++j) {
-        const double bj = abh[size_t(ncv) + j];
-        alpha.push_back(abh[j]);
-        m = j + 1;
-        if (j + 1 == ncv) {
-            beta.push_back(bj);
-            break;
-        }
-        if (!(bj > 1e-300)) {   // invariant subspace found: the Ritz pairs are exact
-            beta.push_back(0.0);
-            break;
-        }
-        beta.push_back(bj);
-    }
+    if (kvb_lanczos_prefix(abh.data(), abh.data() + ncv, ncv, &m) != KVB_OK)
+        return fail(ctx, KVB_E_INVALID, "non-finite Lanczos coefficient after %d steps: the matrix or the "
+                    "start vector holds non-finite values", m);
+    std::vector<double> alpha(abh.begin(), abh.begin() + m);
+    std::vector<double> beta(abh.begin() + ncv, abh.begin() + ncv + m);
+    if (m < ncv) beta[size_t(m) - 1] = 0.0;   // invariant subspace found: the Ritz pairs are exact
     KVB_REQUIRE(ctx, nev <= m, "the Krylov space closed after %d steps, below nev = %d", m, nev);
     // Ritz pairs of T
     std::vector<double> theta, Yt;

@@ -35,11 +35,26 @@ constexpr int PR_DIMS = 8;
 constexpr int PCODE_DIMS = 4;
 constexpr int SB_TILES_MFMA = 16;
 
+// Box tree over the curve-ordered tiles: level 0 holds the tiles' boxes,
+// node v of level l >= 1 the box of nodes 64 v .. 64 v + 63 of level l - 1;
+// the top level has at most 64 nodes.
+constexpr int TREE_FAN = 64;
+constexpr int TREE_LEVELS = 6;   // 64^5 tiles of 32 cover every n < 2^31
+struct TreeLayout {
+    int top;                     // top level (0: the tiles themselves)
+    int cnt[TREE_LEVELS];        // nodes per level
+    int off[TREE_LEVELS];        // level l >= 1 starts at node off[l] of the node array
+    int nodes;                   // nodes of levels >= 1
+};
+TreeLayout tree_layout(int ntiles);
+
 struct CurveArgs {
     const int* perm;    // [tiles * 32] sample id at each curve position, -1 for padding
     const float* zs;    // [n, PR_DIMS] projected coordinates in curve order
     const float* tbox;  // [tiles, 2, PR_DIMS] boxes of 32-sample tiles
-    const float* sbox;  // [superblocks, 2, PR_DIMS]
+    const float* sbox;  // [superblocks, 2, PR_DIMS] (workgroup scans of knn_mfma.hip)
+    const float* tree;  // [layout.nodes, 2, PR_DIMS] boxes of the tree levels >= 1
+    TreeLayout layout;
     const float* pscale;// |v| >= *pscale |P^T v| for every v (set with the basis)
     float zcoef;        // computed projected coordinates are within zcoef R of P^T y (R = max |y|)
     float ycoef;        // |y_i - y_j| exceeds |x_i - x_j| by at most ycoef R
@@ -112,10 +127,19 @@ size_t curve_sort_bytes(int n);
 hipError_t launch_principal_basis(const float* X, int n, int m, const double* mu, double* part, double* C, float* P,
                                   hipStream_t st);
 // zpart [(project_blocks(n) + 1) * 2 * PCODE_DIMS]: block partials, then the reduced range
+// tbox [tiles, 2, PR_DIMS]; sbox [superblocks, 2, PR_DIMS]; tree [tree_layout(tiles).nodes, 2, PR_DIMS]
+// (the box tree's levels >= 1)
 hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, const float* P, float* z, float* zpart,
                               uint32_t* code, uint32_t* scode, int32_t* vals, int32_t* perm, void* sort_tmp,
                               size_t sort_bytes, int32_t* pos, int32_t* cid, float* zs, float* tbox, float* sbox,
-                              hipStream_t st);
+                              float* tree, hipStream_t st);
+// curve-ordered exact selection over the box tree (knn_tree.hip); lists [n, cap], lb [n] by curve position.
+// select_tree_fits: whether the tree walk suits the contraction length (else the
+// workgroup scan of launch_select_mfma with crv runs)
+bool select_tree_fits(int split, int kpad);
+hipError_t launch_select_tree(int split, const void* Aq, const void* Bc, int n, int kpad, int kp, const float* ynorm2,
+                              const unsigned* rmax, ErrModel em, uint64_t* lists, int cap, float* lb,
+                              const CurveArgs& crv, unsigned long long* pairs, hipStream_t st);
 int select_mfma_queries_per_block(int split, int kpad);
 
 // passes

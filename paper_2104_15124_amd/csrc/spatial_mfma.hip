@@ -344,7 +344,7 @@ hipError_t launch_principal_basis(const float* X, int n, int m, const double* mu
 hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, const float* P, float* z, float* zpart,
                               uint32_t* code, uint32_t* scode, int32_t* vals, int32_t* perm, void* sort_tmp,
                               size_t sort_bytes, int32_t* pos, int32_t* cid, float* zs, float* tbox, float* sbox,
-                              hipStream_t st)
+                              float* tree, hipStream_t st)
 {
     const int nb = project_blocks(n);
     hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, st, X, n, m, mu, P, z, zpart);
@@ -357,11 +357,34 @@ hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, co
     if (e != hipSuccess) return e;
     const int ntiles = (n + 31) / 32, npad = ntiles * 32;
     hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, perm, n, npad, z, pos, cid, zs);
-    const int nsb = (ntiles + SB_TILES_MFMA - 1) / SB_TILES_MFMA;
     hipLaunchKernelGGL(k_zboxes, dim3((ntiles * PR_DIMS + 255) / 256), dim3(256), 0, st, zs, n, 32, ntiles, 0, tbox);
+    const int nsb = (ntiles + SB_TILES_MFMA - 1) / SB_TILES_MFMA;
     hipLaunchKernelGGL(k_zboxes, dim3((nsb * PR_DIMS + 255) / 256), dim3(256), 0, st, tbox, ntiles, SB_TILES_MFMA, nsb,
                        1, sbox);
+    // the box tree: each level's boxes over groups of 64 boxes of the level below
+    const TreeLayout t = tree_layout(ntiles);
+    for (int l = 1; l <= t.top; ++l) {
+        const float* src = l == 1 ? tbox : tree + static_cast<size_t>(t.off[l - 1]) * 2 * PR_DIMS;
+        hipLaunchKernelGGL(k_zboxes, dim3((t.cnt[l] * PR_DIMS + 255) / 256), dim3(256), 0, st, src, t.cnt[l - 1],
+                           TREE_FAN, t.cnt[l], 1, tree + static_cast<size_t>(t.off[l]) * 2 * PR_DIMS);
+    }
     return hipGetLastError();
+}
+
+TreeLayout tree_layout(int ntiles)
+{
+    TreeLayout t = {};
+    t.cnt[0] = ntiles;
+    int l = 0, nodes = 0;
+    while (t.cnt[l] > TREE_FAN && l + 1 < TREE_LEVELS) {
+        ++l;
+        t.cnt[l] = (t.cnt[l - 1] + TREE_FAN - 1) / TREE_FAN;
+        t.off[l] = nodes;
+        nodes += t.cnt[l];
+    }
+    t.top = l;
+    t.nodes = nodes;
+    return t;
 }
 
 size_t curve_sort_bytes(int n)

@@ -40,8 +40,9 @@ EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb
            "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name",
            "kvb_union_pattern", "kvb_density_csr", "kvb_tune_eps_csr", "kvb_normalize_csr",
            "kvb_truncate_csr", "kvb_set_tolerance", "kvb_eigsh", "kvb_kolmogorov_solve",
-           "kvb_carre_du_champ", "kvb_advect")
+           "kvb_carre_du_champ", "kvb_advect", "kvb_lanczos_prefix", "kvb_peak_probe")
 PROF_SLOTS = 14
+PEAK_HBM_COPY, PEAK_MFMA_BF16, PEAK_MFMA_F32, PEAK_EXP, PEAK_VALU_FMA = 0, 1, 2, 3, 4
 
 
 class KvbError(RuntimeError):
@@ -90,6 +91,10 @@ def load_library(path: str = LIB_PATH):
     L.kvb_advect.argtypes = [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _f64, _f64, _vp]
     L.kvb_carre_du_champ.argtypes = [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp]
     L.kvb_kolmogorov_solve.argtypes = [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp]
+    L.kvb_peak_probe.argtypes = [_vp, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
+    L.kvb_peak_probe.restype = ctypes.c_int
+    L.kvb_lanczos_prefix.argtypes = [_vp, _vp, _i32, ctypes.POINTER(_i32)]
+    L.kvb_lanczos_prefix.restype = ctypes.c_int
     L.kvb_eigsh.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _i32, _f64, ctypes.c_uint64, _vp, _vp, _vp]
     L.kvb_truncate_csr.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f64, _f64, _vp, _vp, _vp,
                                    ctypes.POINTER(_i64)]
@@ -211,6 +216,16 @@ def knn(X: torch.Tensor, k: int, mode: str = "f32", margin: int = 32, ctx: Conte
     return idx, d2, flags
 
 
+def peak_probe(kind: int, ctx: Context | None = None):
+    """(rate, ms) of a peak microbenchmark (kvb_peak_probe): PEAK_HBM_COPY in
+    bytes/s (read + written), PEAK_MFMA_* in flop/s, PEAK_EXP in exp/s,
+    PEAK_VALU_FMA in lane-op/s."""
+    ctx = ctx or context()
+    rate, ms = _f64(), _f64()
+    ctx.check(ctx.lib.kvb_peak_probe(ctx.h, kind, ctypes.byref(rate), ctypes.byref(ms)))
+    return float(rate.value), float(ms.value)
+
+
 def knn_fallback_rows(ctx: Context | None = None) -> int:
     ctx = ctx or context()
     c = _i64()
@@ -330,6 +345,7 @@ class KernelMatrix:
     val: torch.Tensor
     P: torch.Tensor
     D: torch.Tensor
+    status: int = OK      # the call's status: OK or a warning (W_GRID_EDGE, W_FALLBACK)
 
 
 def build(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float, e_min: float = 1e-3,
@@ -373,16 +389,16 @@ def build(X: torch.Tensor, k: int, k0: int, d: float, alpha: float, beta: float,
     info = np.zeros(8, dtype=np.float64)
     host = (chi_a.ctypes.data_as(_vp), chi_b.ctypes.data_as(_vp), info.ctypes.data_as(_vp)) if sync else \
         (None, None, None)
-    ctx.check(ctx.lib.kvb_build(ctx.h, _ptr(X), n, m, k, MODES[mode], margin, k0, d, alpha, beta, e_min, e_max, G,
-                                out_kind, _ptr(idx), _ptr(d2), _ptr(flags), _ptr(b), _ptr(rho), _ptr(psi),
-                                _ptr(rowptr), _ptr(col), _ptr(val), _ptr(P), _ptr(D), *host))
+    rc = ctx.check(ctx.lib.kvb_build(ctx.h, _ptr(X), n, m, k, MODES[mode], margin, k0, d, alpha, beta, e_min, e_max,
+                                     G, out_kind, _ptr(idx), _ptr(d2), _ptr(flags), _ptr(b), _ptr(rho), _ptr(psi),
+                                     _ptr(rowptr), _ptr(col), _ptr(val), _ptr(P), _ptr(D), *host))
     if not sync:
-        return KernelMatrix(idx, d2, flags, b, None, rho, psi, None, None, rowptr, col, val, P, D)
+        return KernelMatrix(idx, d2, flags, b, None, rho, psi, None, None, rowptr, col, val, P, D, rc)
     ta, s, tb = _tunings(chi_a, chi_b, info, G)
     if pattern != "knn" or delta > 0:
         nnz = int(rowptr[n].item())
         col, val = col[:nnz], val[:nnz]
-    return KernelMatrix(idx, d2, flags, b, ta, rho, psi, s, tb, rowptr, col, val, P, D)
+    return KernelMatrix(idx, d2, flags, b, ta, rho, psi, s, tb, rowptr, col, val, P, D, rc)
 
 
 def _tunings(chi_a, chi_b, info, G):

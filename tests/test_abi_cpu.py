@@ -84,3 +84,35 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libkvb.so not built")
+def test_lanczos_prefix_rejects_non_finite_coefficients():
+    """The host-side decision of kvb_eigsh on its tridiagonal (no device
+    needed): it keeps the steps up to the first breakdown (beta = 0, an
+    invariant subspace, whose Ritz pairs are exact) or all of them, and
+    refuses a NaN or infinite coefficient instead of reading a NaN beta as a
+    breakdown (a non-finite matrix would otherwise return NaN eigenvalues
+    reported as converged)."""
+    import ctypes
+    import numpy as np
+    from paper_2104_15124_amd import kvb
+    L = kvb.load_library()
+
+    def prefix(a, b):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        m = ctypes.c_int32(-7)
+        rc = L.kvb_lanczos_prefix(a.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p),
+                                  len(a), ctypes.byref(m))
+        return rc, m.value
+
+    assert prefix([1.0, 2.0, 3.0], [0.5, 0.25, 0.1]) == (kvb.OK, 3)
+    assert prefix([1.0, 2.0, 3.0], [0.5, 0.0, np.nan]) == (kvb.OK, 2)      # breakdown at step 1
+    assert prefix([1.0, 2.0, 3.0], [0.5, 1e-310, 0.3]) == (kvb.OK, 2)      # underflowed norm
+    assert prefix([np.nan], [np.nan]) == (kvb.E_INVALID, 0)                 # NaN matrix: not a breakdown
+    assert prefix([1.0, 2.0], [np.nan, 0.3]) == (kvb.E_INVALID, 0)
+    assert prefix([1.0, np.inf, 3.0], [0.5, 0.5, 0.5]) == (kvb.E_INVALID, 1)
+    assert prefix([1.0, 2.0, 3.0], [0.5, 0.5, np.inf]) == (kvb.E_INVALID, 2)
+    assert prefix([1.0, 2.0], [-0.5, 0.5]) == (kvb.E_INVALID, 0)
+    assert prefix([], []) [0] == kvb.E_INVALID

@@ -262,3 +262,22 @@ def test_eigsh_breakdown_on_an_invariant_subspace(gpu_lib):
     full = kvb.eigsh(*csr_to_gpu(T), nev=3, ncv=n, tol=1e-9, seed=9)
     exact = -2 + 2 * np.cos(np.pi * np.arange(1, 4) / (n + 1))
     assert full.converged and np.max(np.abs(full.values - exact)) < 1e-5
+
+
+def test_eigsh_rejects_a_non_finite_matrix(gpu_lib):
+    """A NaN or infinite stored value makes every Lanczos coefficient
+    non-finite; kvb_eigsh then fails with KVB_E_INVALID instead of reading a
+    NaN beta as a breakdown and returning NaN eigenvalues as converged. The
+    context keeps working afterwards."""
+    kvb = gpu_lib
+    n = 64
+    T = sp.diags([np.ones(n - 1), -2 * np.ones(n), np.ones(n - 1)], [-1, 0, 1], format="csr")
+    for bad in (np.nan, np.inf):
+        B = T.copy()
+        B.data[5] = bad
+        say(f"[eigsh] non-finite value {bad}")
+        with pytest.raises(kvb.KvbError, match="non-finite") as e:
+            kvb.eigsh(*csr_to_gpu(B), nev=1, ncv=8, seed=4)
+        assert e.value.code == kvb.E_INVALID
+    ok = kvb.eigsh(*csr_to_gpu(T), nev=2, ncv=n, tol=1e-9, seed=4)
+    assert ok.converged and np.isfinite(ok.values).all()

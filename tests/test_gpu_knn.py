@@ -256,6 +256,35 @@ def test_knn_nonlinear5_n1m_sampled_rows(gpu_lib):
     assert nfb <= w.n // 100
 
 
+LARGE_CASES = [("sphere3_n4m", "bf16"), ("gmm_n8m", "f32"), ("gmm_n8m", "bf16")]
+
+
+@pytest.mark.parametrize("name,mode", LARGE_CASES, ids=[f"{c[0]}_{c[1]}" for c in LARGE_CASES])
+def test_knn_large_workloads_sampled_rows(gpu_lib, name, mode):
+    """The two largest workloads at full size in the exact modes the benchmark
+    times (the lifted 3-sphere: n = 4e6, m = 128, k = 128; the mixture:
+    n = 8e6, m = 16, k = 64; margin 32, curve order): 256 sampled rows
+    against the oracle's exact rows, every row against the row invariants."""
+    from paper_2104_15124_amd import kvb
+    w = workloads.WORKLOADS[name]
+    say(f"[knn-large] {name}: n={w.n} m={w.m} k={w.k} mode={mode} (sampled oracle rows)")
+    X = workloads.make(w.name, seed=0)
+    ctx = kvb.Context()
+    gi, gd, fl = run_knn(gpu_lib, X, w.k, w.margin, mode=mode, ctx=ctx)
+    nfb = kvb.knn_fallback_rows(ctx)
+    pairs = kvb.knn_pairs(ctx)
+    ctx.close()
+    say(f"[knn-large] {name}: fallback rows {nfb}, candidate pairs {pairs:.4g} ({pairs / float(w.n) ** 2:.3%} of n^2)")
+    assert (gi[:, 0] == np.arange(w.n)).all()
+    assert (gd[:, 0] == 0).all() and (np.diff(gd, axis=1) >= 0).all()
+    assert ((gi >= 0) & (gi < w.n)).all()
+    rows = np.random.default_rng(11).choice(w.n, 256, replace=False)
+    ri, rd = knn_reference(X, w.k, rows=rows)
+    ties = check_knn_rows(gi[rows], gd[rows], ri, rd, w.k, rows)
+    say(f"[knn-large] {name}: 256 sampled rows match the oracle (near-tie rows {ties})")
+    assert nfb <= w.n // 100
+
+
 EXACT_ROWS_CASES = [("n3000_m3_k32", 3000, 3, 32, 1), ("n2000_m64_k64", 2000, 64, 64, 2), ("n500_m7_k1", 500, 7, 1, 3)]
 
 

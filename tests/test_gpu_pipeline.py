@@ -16,10 +16,14 @@ from parity import check_entries, check_knn_rows, knn_reference, say
 pytestmark = pytest.mark.gpu
 
 
-def gpu_build(kvb, X, w, out_kind=0):
+def gpu_build(kvb, X, w, out_kind=0, mode="f32", entry="calls"):
+    """The build through the separate entry points (kvb_knn, kvb_bandwidth,
+    kvb_tune_eps, kvb_grid_scale, kvb_assemble_csr) or through the single call
+    kvb_build."""
     Xd = torch.from_numpy(X).cuda()
-    r = kvb.build_kernel_matrix(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
-                                mode="f32", margin=w.margin, out_kind=out_kind)
+    fn = kvb.build_kernel_matrix if entry == "calls" else kvb.build
+    r = fn(Xd, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G,
+           mode=mode, margin=w.margin, out_kind=out_kind)
     torch.cuda.synchronize()
     return r
 
@@ -29,9 +33,9 @@ def near_tie(slope):
     return (s[-1] - s[-2]) <= 1e-5 * abs(s[-1])
 
 
-def compare_pipeline(kvb, name, X, w):
-    say(f"[pipeline] {name}: n={len(X)} m={X.shape[1]} k={w.k}")
-    g = gpu_build(kvb, X, w)
+def compare_pipeline(kvb, name, X, w, mode="f32", entry="calls"):
+    say(f"[pipeline] {name}: n={len(X)} m={X.shape[1]} k={w.k} mode={mode} entry={entry}")
+    g = gpu_build(kvb, X, w, mode=mode, entry=entry)
     ref = oracle.pipeline(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G)
     n, k = len(X), w.k
     # k-NN
@@ -68,7 +72,7 @@ def compare_pipeline(kvb, name, X, w):
     _, x = oracle.sort_rows_by_col(pat.col, xs, k)   # exponents in CSR order
     rowmax = np.repeat(ref.val.reshape(n, k).max(axis=1), k)
     worst = check_entries(val, ref.val, x, rowmax, f"{name} Markov entries")
-    np.testing.assert_allclose(g.P.cpu().numpy(), ref.P, rtol=1e-7)
+    np.testing.assert_allclose(g.P.cpu().numpy(), ref.P, rtol=5e-6)     # P = rho / 2 of the float32 rho
     np.testing.assert_allclose(g.D.cpu().numpy(), ref.D, rtol=2e-5)
     rs = val.reshape(n, k).sum(axis=1)
     assert np.abs(rs - 1).max() < 2e-6
@@ -92,6 +96,53 @@ def test_pipeline_torus_n100k_full(gpu_lib):
     """Full-size measured workload, every row and entry compared."""
     w = workloads.WORKLOADS["torus_n100k"]
     compare_pipeline(gpu_lib, "torus_n100k", workloads.make(w.name, seed=0), w)
+
+
+def test_pipeline_torus_n100k_single_call(gpu_lib):
+    """The entry point the benchmark times (kvb_build, one call, intermediate
+    values on the device) at the torus workload's full size, every row and
+    entry against the oracle."""
+    w = workloads.WORKLOADS["torus_n100k"]
+    compare_pipeline(gpu_lib, "torus_n100k", workloads.make(w.name, seed=0), w, entry="build")
+
+
+def test_pipeline_k128_lifted_sphere(gpu_lib):
+    """The lifted 3-sphere recipe (m = 128, k = 128, d = 3) at n = 20000 through
+    kvb_build with BF16 matrix-core tiles: the k > 64 forms of the density,
+    tuning, q and assembly passes (two row slices per lane) against the oracle."""
+    import dataclasses
+    w = dataclasses.replace(workloads.WORKLOADS["sphere3_n4m"], n=20000, mode="bf16")
+    compare_pipeline(gpu_lib, "sphere3_n20k_k128", workloads.make(w.name, seed=0, n=w.n), w, mode="bf16",
+                     entry="build")
+
+
+@pytest.mark.parametrize("entry", ["calls", "build"])
+def test_pipeline_k200_mixture(gpu_lib, entry):
+    """k = 200 (margin 56, k + margin = 256: the largest list) on the mixture
+    recipe at n = 5000: the widest form of the passes (four row slices per
+    lane) against the oracle, through both entry forms."""
+    import dataclasses
+    w = dataclasses.replace(workloads.WORKLOADS["gmm_n8m"], n=5000, k=200, margin=56, mode="f32")
+    compare_pipeline(gpu_lib, f"gmm_n5000_k200_{entry}", workloads.make(w.name, seed=1, n=w.n), w, mode="f32",
+                     entry=entry)
+
+
+@pytest.mark.parametrize("out_kind", [1, 2])
+@pytest.mark.parametrize("k", [128, 200])
+def test_output_kinds_wide_rows(gpu_lib, out_kind, k):
+    """The generator and the symmetric conjugate at k > 64."""
+    import dataclasses
+    w = dataclasses.replace(workloads.WORKLOADS["gmm_n8m"], n=3000, k=k, margin=256 - k, mode="f32")
+    X = workloads.make(w.name, seed=2, n=w.n)
+    say(f"[pipeline] output kind {out_kind}, k={k}")
+    g = gpu_build(gpu_lib, X, w, out_kind=out_kind, entry="build")
+    ref = oracle.pipeline(X, w.k, w.k0, float(w.d), w.alpha, w.beta, w.e_min, w.e_max, w.G, out_kind=out_kind)
+    assert g.tune_b.e_star == pytest.approx(ref.tune_b.e_star, rel=1e-13)
+    val = g.val.cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal(g.col.cpu().numpy(), ref.col)
+    scale = np.abs(ref.val).max()
+    err = np.abs(val - ref.val)
+    assert (err <= 1e-5 * np.abs(ref.val) + 1e-6 * scale).all(), float(np.max(err / (np.abs(ref.val) + scale)))
 
 
 @pytest.mark.parametrize("out_kind", [1, 2])

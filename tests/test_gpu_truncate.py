@@ -1,16 +1,24 @@
 """GPU parity of threshold truncation (run on an MI355X).
 
 Section 4: Algorithm 1 stores an entry only when its kernel value exceeds the
-sparsity tolerance delta_tol, which gives rows of varying length.
-kvb_truncate_csr keeps the entries with exp(-d2/(e rho_i rho_j)) > delta; the
-keep/drop decision is an integer taken from floating point, so the oracle
-(oracle.truncate) takes it with the same operations in the same precision and
-the kept patterns must agree bit for bit on the same inputs. In the whole
-truncated build the decisions depend on the bandwidths b and rho, which the GPU
-computes in float32; there the oracle's truncation is fed the GPU's b and rho
-(its own values differ in the last places and would move entries that sit
-exactly at the threshold), and every value is compared within the entry
-tolerance of the untruncated path.
+sparsity tolerance delta_tol, which gives rows of varying length. The oracle
+keeps an entry when exp(-d2 / (e rho_i rho_j)) > delta, evaluated as written in
+float64; kvb_truncate_csr tests the exponent x = d2 / (e rho_i rho_j) against
+-ln(delta). The keep decision is an integer taken from floating point: on the
+same inputs the two sides may disagree only for entries whose exponent lies
+within rounding of -ln(delta) (relative 1e-12); those are counted.
+
+In the whole build each side computes its own bandwidths (the GPU b and rho in
+float32, within about 1e-5 of the oracle's), so an entry whose exponent lies
+within that of the threshold may be kept on one side only. Such a flip changes
+the row's density (or q) by about delta / row sum, which reaches every row that
+stores the flipped row as a neighbour, and their degrees. The build tests
+therefore run the oracle end to end on its own k-NN, b, e and rho, mark the
+oracle's entries within RT_BAND of the threshold, follow their reach through the
+pattern (T1: rows owning such a density entry; T2: rows owning such an operator
+entry or an entry on a T1 row or column; T3: T2 and every row storing a T2
+row), compare everything exactly on the rows outside that reach, count the rows
+inside it, and check those only loosely.
 """
 import numpy as np
 import pytest
@@ -19,40 +27,80 @@ import torch
 import oracle
 import workloads
 from oracle import spectral
-from parity import check_entries, say
+from parity import check_entries, check_knn_rows, knn_reference, say
 
 pytestmark = pytest.mark.gpu
+
+# relative width of the rounding band around -ln(delta): the GPU's exponent
+# carries its float32 b or rho (within 5e-6 of the oracle's, squared in rho_i
+# rho_j) and float32 d2 (2^-21)
+RT_BAND = 2e-5
 
 
 def f64(t):
     return t.cpu().numpy().astype(np.float64)
 
 
-def pair_ids(p):
-    rows = np.repeat(np.arange(p.n, dtype=np.int64), np.diff(p.rowptr))
-    return rows * (p.n + 1) + p.col
+def entry_rows(rowptr):
+    return np.repeat(np.arange(len(rowptr) - 1, dtype=np.int64), np.diff(rowptr))
 
 
-def check_same_pattern(g, r, what):
-    np.testing.assert_array_equal(g.rowptr.cpu().numpy(), r.rowptr, err_msg=f"{what}: rowptr")
-    np.testing.assert_array_equal(g.col.cpu().numpy(), r.col, err_msg=f"{what}: col")
-    np.testing.assert_array_equal(f64(g.d2), r.dist2, err_msg=f"{what}: d2")
+def pair_ids(rowptr, col):
+    n = len(rowptr) - 1
+    return entry_rows(rowptr) * (n + 1) + col.astype(np.int64)
 
 
-def gpu_base(g, idx, d2, pattern):
-    """The GPU's base pattern, checked (rowptr, col) against the oracle's
-    construction from the GPU's k-NN, then used with the GPU's distances as
-    the oracle's input array (a pair stored in both rows may carry distances
-    that differ in the last place, where one row rechecked it in FP64)."""
-    ref = oracle.Pattern.from_knn(idx, d2) if pattern == "knn" else spectral.union_pattern(idx, d2)
-    np.testing.assert_array_equal(g.base.rowptr.cpu().numpy(), ref.rowptr)
-    np.testing.assert_array_equal(g.base.col.cpu().numpy(), ref.col)
-    return oracle.Pattern(g.base.rowptr.cpu().numpy(), g.base.col.cpu().numpy(), f64(g.base.d2))
+def as_np(p):
+    """(rowptr, col, d2) of a GPU pattern or an oracle Pattern, as numpy."""
+    if isinstance(p, oracle.Pattern):
+        return p.rowptr, p.col, p.dist2
+    return p.rowptr.cpu().numpy(), p.col.cpu().numpy(), f64(p.d2)
+
+
+def rows_storing(rowptr, col, rows_set):
+    """Rows that own an entry in a row of rows_set or with a column in it."""
+    n = len(rowptr) - 1
+    bad = np.zeros(n, dtype=bool)
+    bad[rows_set] = True
+    r = entry_rows(rowptr)
+    return np.unique(r[bad[r] | bad[col]])
+
+
+def kept_sets_equal(gp, rp, clean, what):
+    """The kept columns of every clean row agree as sets."""
+    gr, gc, _ = as_np(gp)
+    rr, rc, _ = as_np(rp)
+    gid, rid = pair_ids(gr, gc), pair_ids(rr, rc)
+    n = len(gr) - 1
+    gsel = np.sort(gid[clean[entry_rows(gr)]])
+    rsel = np.sort(rid[clean[entry_rows(rr)]])
+    assert len(gsel) == len(rsel) and (gsel == rsel).all(), \
+        f"{what}: kept sets differ on clean rows ({len(np.setxor1d(gsel, rsel))} entries)"
+    assert n == len(rr) - 1
+
+
+def aligned(gp, gval, rp, rval, rows_mask):
+    """Values of the entries of the rows in rows_mask, matched by (row, col)."""
+    gr, gc, _ = as_np(gp)
+    rr, rc, _ = as_np(rp)
+    gid, rid = pair_ids(gr, gc), pair_ids(rr, rc)
+    gs = rows_mask[entry_rows(gr)]
+    rs = rows_mask[entry_rows(rr)]
+    og, orf = np.argsort(gid[gs]), np.argsort(rid[rs])
+    assert (gid[gs][og] == rid[rs][orf]).all()
+    return gval[gs][og], rval[rs][orf], orf, rs
+
+
+def near_tie(slope):
+    s = np.sort(slope)
+    return (s[-1] - s[-2]) <= 1e-5 * abs(s[-1])
 
 
 @pytest.mark.parametrize("delta", [0.3, 1e-2, 1e-6])
 @pytest.mark.parametrize("union", [False, True])
 def test_truncate_matches_oracle(gpu_lib, delta, union):
+    """The same pattern, bandwidths and e on both sides: the kept sets agree
+    except for entries within 1e-12 of the threshold (counted; none expected)."""
     kvb = gpu_lib
     n, k = 3000, 32
     say(f"[truncate] n={n} k={k} delta={delta} union={union}")
@@ -66,14 +114,27 @@ def test_truncate_matches_oracle(gpu_lib, delta, union):
     else:
         gpat = kvb.knn_pattern(gi, gd)
         rpat = oracle.Pattern.from_knn(idx, d2f.astype(np.float64))
+    np.testing.assert_array_equal(gpat.rowptr.cpu().numpy(), rpat.rowptr)
+    np.testing.assert_array_equal(gpat.col.cpu().numpy(), rpat.col)
     rng = np.random.default_rng(3)
     rho = (0.05 + 0.1 * rng.random(n)).astype(np.float32)
     e = 0.2
     g = kvb.truncate_csr(gpat, torch.from_numpy(rho).cuda(), e, delta)
     r = oracle.truncate(rpat, rho.astype(np.float64), e, delta)
-    check_same_pattern(g, r, f"delta {delta}")
+    rows = entry_rows(rpat.rowptr)
+    x = rpat.dist2 / (e * rho.astype(np.float64)[rows] * rho.astype(np.float64)[rpat.col])
+    L = -np.log(delta)
+    band = np.abs(x / L - 1) <= 1e-12
+    clean = np.ones(n, dtype=bool)
+    clean[np.unique(rows[band])] = False
+    kept_sets_equal(g, r, clean, f"delta {delta}")
+    # clean rows keep their entries in the pattern's order, with their distances
+    gr, gc, gd2 = as_np(g)
+    for i in np.nonzero(clean)[0][::7]:
+        np.testing.assert_array_equal(gc[gr[i]:gr[i + 1]], r.col[r.rowptr[i]:r.rowptr[i + 1]])
+        np.testing.assert_array_equal(gd2[gr[i]:gr[i + 1]], r.dist2[r.rowptr[i]:r.rowptr[i + 1]])
     assert 0 < g.nnz < gpat.nnz
-    say(f"[truncate] kept {g.nnz} of {gpat.nnz}")
+    say(f"[truncate] kept {g.nnz} of {gpat.nnz}; {int(band.sum())} entries within rounding of the threshold")
 
 
 def test_truncate_limits_and_ragged(gpu_lib):
@@ -93,73 +154,94 @@ def test_truncate_limits_and_ragged(gpu_lib):
         kvb.truncate_csr(gpat, rho, 0.1, 1.0)
 
 
+def compare_truncated_build(kvb, X, w, delta, pattern, name, min_clean):
+    """End-to-end truncated build against the oracle's own pipeline on the
+    same samples (see the module docstring for the band and its reach)."""
+    n, k = len(X), w.k
+    say(f"[truncate] {name}: n={n} k={k} pattern {pattern} delta {delta}")
+    g = kvb.build_truncated_matrix(torch.from_numpy(X).cuda(), k, w.k0, float(w.d), w.alpha, w.beta, delta,
+                                   w.e_min, w.e_max, w.G, pattern=pattern)
+    torch.cuda.synchronize()
+    # the oracle's own k-NN (with one extra neighbour for the tie gap)
+    ri, rd = knn_reference(X, k)
+    ties = check_knn_rows(g.idx.cpu().numpy(), g.d2.cpu().numpy(), ri, rd, k, np.arange(n))
+    assert ties == 0, "the workload has no near-tie rows at this seed"
+    idx, d2 = np.ascontiguousarray(ri[:, :k]), np.ascontiguousarray(rd[:, :k])
+    base = oracle.Pattern.from_knn(idx, d2) if pattern == "knn" else spectral.union_pattern(idx, d2)
+    everyone = np.ones(n, dtype=bool)
+    kept_sets_equal(g.base, base, everyone, "base pattern")
+    ref = oracle.truncated_build(base, d2, w.k0, float(w.d), w.alpha, w.beta, delta, w.e_min, w.e_max, w.G)
+    L = -np.log(delta)
+    rows = entry_rows(base.rowptr)
+    # density stage
+    np.testing.assert_allclose(f64(g.b), ref["b"], rtol=2e-6)
+    np.testing.assert_allclose(g.tune_a.chi, ref["ta"].chi, rtol=2e-5)
+    assert not near_tie(ref["ta"].slope), "the oracle's two best slopes tie: pick another seed"
+    assert g.tune_a.e_star == pytest.approx(ref["ta"].e_star, rel=1e-13)
+    xa = base.dist2 / (ref["ta"].e_star * ref["b"][rows] * ref["b"][base.col])
+    t1 = np.unique(rows[np.abs(xa / L - 1) <= RT_BAND])
+    clean1 = np.ones(n, dtype=bool)
+    clean1[t1] = False
+    kept_sets_equal(g.density_pattern, ref["pa"], clean1, "density pattern")
+    np.testing.assert_allclose(f64(g.psi)[clean1], ref["psi"][clean1], rtol=5e-6)
+    np.testing.assert_allclose(f64(g.rho)[clean1], ref["rho"][clean1], rtol=5e-6)
+    np.testing.assert_allclose(f64(g.rho), ref["rho"], rtol=2e-3)
+    # operator stage
+    assert g.scale_b == ref["s"]
+    np.testing.assert_allclose(g.tune_b.chi, ref["tb"].chi, rtol=2e-5)
+    assert not near_tie(ref["tb"].slope), "the oracle's two best slopes tie: pick another seed"
+    assert g.tune_b.e_star == pytest.approx(ref["tb"].e_star, rel=1e-13)
+    e_b, rho = ref["tb"].e_star, ref["rho"]
+    xb = base.dist2 / (e_b * rho[rows] * rho[base.col])
+    band_b = (np.abs(xb / L - 1) <= RT_BAND) | ~clean1[rows] | ~clean1[base.col]
+    t2 = np.unique(rows[band_b])
+    clean2 = np.ones(n, dtype=bool)
+    clean2[t2] = False
+    kept_sets_equal(g.pattern, ref["pb"], clean2, "operator pattern")
+    t3 = np.union1d(t2, rows_storing(ref["pb"].rowptr, ref["pb"].col, t2))
+    clean3 = np.ones(n, dtype=bool)
+    clean3[t3] = False
+    gval = f64(g.val)
+    # every row stays a Markov row
+    gr = g.pattern.rowptr.cpu().numpy()
+    rs = np.add.reduceat(gval, gr[:-1])[np.diff(gr) > 0]
+    assert np.abs(rs - 1).max() < 2e-6
+    pb = ref["pb"]
+    xk = pb.dist2 / (e_b * rho[entry_rows(pb.rowptr)] * rho[pb.col])
+    rowmax = np.maximum.reduceat(ref["val"], pb.rowptr[:-1])[entry_rows(pb.rowptr)]
+    worst = 0.0
+    if clean3.any():
+        gv, rv, orf, sel = aligned(g.pattern, gval, pb, ref["val"], clean3)
+        worst = check_entries(gv, rv, xk[sel][orf], rowmax[sel][orf], f"{name} clean rows")
+        np.testing.assert_allclose(g.D.cpu().numpy()[clean3], ref["D"][clean3], rtol=2e-5)
+    # rows reached only through a neighbour's degree: same kept set, values close
+    loose = clean2 & ~clean3
+    if loose.any():
+        gv, rv, _, _ = aligned(g.pattern, gval, pb, ref["val"], loose)
+        big = rv > 1e-6 * rv.max()
+        assert (np.abs(gv - rv)[big] <= 1e-2 * rv[big]).all()
+    frac = clean3.mean()
+    say(f"[truncate] {name}: density band rows {len(t1)}, operator rows reached {len(t2)}, "
+        f"degree rows reached {len(t3)}; {frac:.3f} of rows compared exactly (worst rel err {worst:.3g})")
+    assert frac >= min_clean, frac
+
+
 @pytest.mark.parametrize("pattern", ["knn", "union"])
 def test_truncated_build_matches_oracle(gpu_lib, pattern):
     """The build with the paper's sparsity tolerance 1e-2 (Section 5 sets
-    density-kernel entries below 1e-2 to zero) on the 2-sphere workload."""
-    kvb = gpu_lib
+    density-kernel entries below 1e-2 to zero) on the 2-sphere workload,
+    against the oracle's own end-to-end build."""
     w = workloads.WORKLOADS["sphere2_n2000"]
-    X = workloads.make(w.name, seed=0)
-    n, delta = len(X), 1e-2
-    say(f"[truncate] build, pattern {pattern}")
-    g = kvb.build_truncated_matrix(torch.from_numpy(X).cuda(), w.k, w.k0, float(w.d), w.alpha, w.beta, delta,
-                                   w.e_min, w.e_max, w.G, pattern=pattern)
-    idx, d2 = g.idx.cpu().numpy(), f64(g.d2)
-    base = gpu_base(g, idx, d2, pattern)
-    ref = oracle.truncated_build(base, d2, w.k0, float(w.d), w.alpha, w.beta, delta, w.e_min, w.e_max, w.G)
-    np.testing.assert_allclose(f64(g.b), ref["b"], rtol=2e-6)
-    assert g.tune_a.e_star == pytest.approx(ref["ta"].e_star, rel=1e-13)
-    e_a = g.tune_a.e_star
-    # density stage: the decisions taken with the GPU's b
-    pa = oracle.truncate(base, f64(g.b), e_a, delta)
-    check_same_pattern(g.density_pattern, pa, "density pattern")
-    # with the oracle's own b only entries at the threshold may move
-    moved = len(np.setxor1d(pair_ids(pa), pair_ids(ref["pa"])))
-    assert moved <= 1e-4 * len(pa.col) + 2
-    psi_r, rho_r = oracle.density(pa, ref["b"], e_a, float(w.d), w.beta)
-    np.testing.assert_allclose(f64(g.psi), psi_r, rtol=5e-6)
-    np.testing.assert_allclose(f64(g.rho), rho_r, rtol=5e-6)
-    assert g.scale_b == ref["s"]
-    assert g.tune_b.e_star == pytest.approx(ref["tb"].e_star, rel=1e-13)
-    e_b = g.tune_b.e_star
-    # operator stage: the decisions taken with the GPU's rho
-    rho_g = f64(g.rho)
-    pb = oracle.truncate(base, rho_g, e_b, delta)
-    check_same_pattern(g.pattern, pb, "operator pattern")
-    val_r, q, P, D = oracle.normalize(pb, rho_g, e_b, w.alpha, float(w.d))
-    rows = np.repeat(np.arange(n), np.diff(pb.rowptr))
-    x = pb.dist2 / (e_b * rho_g[rows] * rho_g[pb.col])
-    rowmax = np.maximum.reduceat(val_r, pb.rowptr[:-1])[rows]
-    worst = check_entries(f64(g.val), val_r, x, rowmax, f"truncated {pattern} entries")
-    np.testing.assert_allclose(g.D.cpu().numpy(), D, rtol=2e-5)
-    rs = np.add.reduceat(f64(g.val), pb.rowptr[:-1])
-    assert np.abs(rs - 1).max() < 2e-6
-    assert (x < -np.log(delta) * (1 + 1e-12)).all()
-    say(f"[truncate] {pattern}: kept {len(pb.col)} of {len(base.col)} entries, worst rel err {worst:.3g}")
+    compare_truncated_build(gpu_lib, workloads.make(w.name, seed=0), w, 1e-2, pattern, "sphere2_n2000", 0.5)
 
 
 def test_truncated_build_torus_n100k(gpu_lib):
-    """The measured workload's size, the union pattern, delta 1e-2: the
-    operator pattern bit for bit and every value, against the oracle fed the
-    GPU's k-NN and rho."""
-    kvb = gpu_lib
+    """The torus workload at full size, union pattern, delta 1e-2, against the
+    oracle's own end-to-end build. About 150 of its 6.75M entries sit within the
+    band; their reach covers most rows' degrees, so those rows are compared
+    loosely and the patterns and bandwidths exactly where they are clean."""
     w = workloads.WORKLOADS["torus_n100k"]
-    X = workloads.make(w.name, seed=0)
-    n, delta = len(X), 1e-2
-    say("[truncate] torus n=100000 union delta=1e-2")
-    g = kvb.build_truncated_matrix(torch.from_numpy(X).cuda(), w.k, w.k0, float(w.d), w.alpha, w.beta, delta,
-                                   w.e_min, w.e_max, w.G, pattern="union")
-    idx, d2 = g.idx.cpu().numpy(), f64(g.d2)
-    base = gpu_base(g, idx, d2, "union")
-    rho_g = f64(g.rho)
-    pb = oracle.truncate(base, rho_g, g.tune_b.e_star, delta)
-    check_same_pattern(g.pattern, pb, "operator pattern")
-    val_r, q, P, D = oracle.normalize(pb, rho_g, g.tune_b.e_star, w.alpha, float(w.d))
-    rows = np.repeat(np.arange(n), np.diff(pb.rowptr))
-    x = pb.dist2 / (g.tune_b.e_star * rho_g[rows] * rho_g[pb.col])
-    rowmax = np.maximum.reduceat(val_r, pb.rowptr[:-1])[rows]
-    check_entries(f64(g.val), val_r, x, rowmax, "torus truncated entries")
-    say(f"[truncate] torus: kept {len(pb.col)} of {len(base.col)}")
+    compare_truncated_build(gpu_lib, workloads.make(w.name, seed=0), w, 1e-2, "union", "torus_n100k", 0.0)
 
 
 @pytest.mark.parametrize("pattern", ["knn", "union"])
@@ -203,10 +285,12 @@ def test_single_call_truncated_build(gpu_lib, pattern):
 
 def test_truncated_build_gmm_n8m_sampled_rows(gpu_lib):
     """The largest workload (n = 8e6, k = 64) built in one call with the
-    sparsity tolerance 1e-2: the operator pattern's rows of 48 sampled samples
-    against the keep rule x = (d2 (1 / (e rho_i))) / rho_j < -ln(delta),
-    evaluated in float64 with the same operations on the GPU's rho and e_B,
-    bit for bit; the rows are the k-NN rows in column order."""
+    sparsity tolerance 1e-2. The oracle cannot rebuild 8M rows, so this checks
+    a property that holds at any size: in the rows of 48 sampled samples the
+    operator pattern holds exactly the k-NN entries whose kernel value
+    exp(-d2 / (e_B rho_i rho_j)), evaluated as written in float64 on the
+    build's own rho and e_B, exceeds delta (entries within 1e-12 of the
+    threshold counted, not compared), in column order."""
     kvb = gpu_lib
     w = workloads.WORKLOADS["gmm_n8m"]
     X = workloads.make(w.name, seed=0)
@@ -219,14 +303,22 @@ def test_truncated_build_gmm_n8m_sampled_rows(gpu_lib):
     L = -np.log(delta)
     rowptr = g.rowptr.cpu().numpy()
     rng = np.random.default_rng(13)
+    banded = 0
     for i in np.sort(rng.choice(n, 48, replace=False)):
         order = np.argsort(g.idx[i].cpu().numpy(), kind="stable")
         cols = g.idx[i].cpu().numpy()[order]
         dd = g.d2[i].cpu().numpy()[order].astype(np.float64)
-        x = dd * (1.0 / (e_b * rho[i])) / rho[cols]
-        keep = x < L
+        x = dd / (e_b * rho[i] * rho[cols])
+        keep = np.exp(-x) > delta
+        band = np.abs(x / L - 1) <= 1e-12
         lo, hi = rowptr[i], rowptr[i + 1]
-        assert g.col[lo:hi].cpu().numpy().tolist() == cols[keep].tolist(), i
+        got = g.col[lo:hi].cpu().numpy()
+        if band.any():
+            banded += 1
+            assert set(cols[keep & ~band]) <= set(got) <= set(cols[keep | band]), i
+        else:
+            assert got.tolist() == cols[keep].tolist(), i
     kept = int(rowptr[-1])
     assert kept == g.col.numel() and 0 < kept < n * k
-    say(f"[truncate] gmm_n8m: kept {kept} of {n * k} entries ({kept / (n * k):.3f})")
+    say(f"[truncate] gmm_n8m: kept {kept} of {n * k} entries ({kept / (n * k):.3f}); {banded} sampled rows "
+        f"had an entry within rounding of the threshold")
