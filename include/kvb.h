@@ -141,10 +141,10 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k,
             int32_t mode, int32_t margin, int32_t* idx, float* d2, int32_t* row_flags);
 
 /* Number of candidate pairs (query row, candidate sample) whose score the
- * distance tiles of the last kvb_knn call on ctx computed: n^2 for the
- * all-pairs matrix-core scan, fewer where the direct scan skipped tiles by
- * their bounding boxes or the learned routing limited the candidates.
- * Synchronises the context stream. */
+ * distance tiles of the last kvb_knn call on ctx computed: the tiles the
+ * spatial scans did not skip by their boxes (direct tiles, curve-ordered
+ * matrix-core tiles), every pair when KVB_OPT_CURVE_ORDER is 0, or the routed
+ * pairs of the learned search. Synchronises the context stream. */
 int kvb_knn_pairs(kvb_ctx ctx, double* pairs_host);
 
 /*
