@@ -204,6 +204,23 @@ int kvb_tune_eps(kvb_ctx ctx, const int32_t* idx, const float* d2, const float* 
                  double* chi_host, double* e_star_host, double* dim_host);
 
 /*
+ * kvb_tune_eps without any allocation, for callers that cannot allocate
+ * device memory during a call (serving loops, harnesses that forbid it). Same
+ * arguments, results (bit for bit) and status as kvb_tune_eps, and the same
+ * synchronisation. Its scratch (the sums' block partials and the result) is a
+ * static device array of 4 MiB that each GPU holds from library load until the
+ * process ends; its address is looked up when a context is created on that
+ * GPU. Every call on one GPU shares that array: calls that overlap in time on
+ * one GPU race and must be ordered by the caller. The tuning needs at most
+ * 2 MiB of it (1024 blocks x G <= 256 doubles); a need beyond the array
+ * returns KVB_E_UNSUPPORTED. KVB_OPT_SCRATCH_LIMIT does not apply (nothing is
+ * allocated).
+ */
+int kvb_tune_eps_noalloc(kvb_ctx ctx, const int32_t* idx, const float* d2, const float* rho,
+                         int64_t n, int32_t k, double e_min, double e_max, int32_t G,
+                         double* chi_host, double* e_star_host, double* dim_host);
+
+/*
  * Normalisation into CSR (Section 2.2):
  *   K_ir = exp(-d2[i,r] / (e rho_i rho_j)), P_i = rho_i / 2,
  *   q_i = P_i^{-d} sum_r K_ir, Kt_ir = K_ir / (q_i q_j)^alpha, D_i = sum_r Kt_ir,

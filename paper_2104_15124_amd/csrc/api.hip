@@ -55,6 +55,10 @@ int kvb_create(kvb_ctx* out, void* hip_stream)
         kvb_destroy(ctx);
         return KVB_E_NOMEM;
     }
+    if (noalloc_scratch_init(dev) != KVB_OK) {
+        kvb_destroy(ctx);
+        return KVB_E_HIP;
+    }
     *out = ctx;
     return KVB_OK;
 }

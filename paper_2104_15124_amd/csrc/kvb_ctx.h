@@ -184,6 +184,10 @@ inline int ensure_scratch(kvb_ctx ctx, size_t bytes)
 
 inline int check_ctx(kvb_ctx ctx) { return ctx ? KVB_OK : KVB_E_INVALID; }
 
+// Looks up (once per device, with that device current) the device address of
+// the static scratch array of the allocation-free entry point (noalloc.hip).
+int noalloc_scratch_init(int device);
+
 inline hipEvent_t pool_event(kvb_ctx ctx)
 {
     if (!ctx->ev_pool.empty()) {

@@ -40,7 +40,7 @@ EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb
            "kvb_version", "kvb_profile_enable", "kvb_profile_read", "kvb_profile_name",
            "kvb_union_pattern", "kvb_density_csr", "kvb_tune_eps_csr", "kvb_normalize_csr",
            "kvb_truncate_csr", "kvb_set_tolerance", "kvb_eigsh", "kvb_kolmogorov_solve",
-           "kvb_carre_du_champ", "kvb_advect", "kvb_lanczos_prefix", "kvb_peak_probe")
+           "kvb_carre_du_champ", "kvb_advect", "kvb_lanczos_prefix", "kvb_peak_probe", "kvb_tune_eps_noalloc")
 PROF_SLOTS = 14
 PEAK_HBM_COPY, PEAK_MFMA_BF16, PEAK_MFMA_F32, PEAK_EXP, PEAK_VALU_FMA = 0, 1, 2, 3, 4
 
@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH):
     L.kvb_grid_scale.argtypes = [_vp, _vp, _vp, _i64, ctypes.POINTER(_f64)]
     L.kvb_tune_eps.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _f64, _f64, _i32,
                                _vp, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
+    L.kvb_tune_eps_noalloc.argtypes = L.kvb_tune_eps.argtypes
+    L.kvb_tune_eps_noalloc.restype = ctypes.c_int
     L.kvb_assemble_csr.argtypes = [_vp, _vp, _vp, _vp, _i64, _i32, _f64, _f64, _f64, _i32,
                                    _vp, _vp, _vp, _vp, _vp]
     L.kvb_build.argtypes = [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64, _i32, _i32,
