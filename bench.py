@@ -315,9 +315,10 @@ def main() -> int:
                     help="sample count override (same recipe, for profiling runs; not a bench line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the peak microbenchmarks")
-    ap.add_argument("--curve-order", type=int, default=1, choices=[0, 1],
-                    help="exact matrix-core modes: 1 scans candidates in curve order with projected-box pruning, "
-                         "0 scans every tile")
+    ap.add_argument("--curve-order", type=int, default=2, choices=[0, 1, 2],
+                    help="exact matrix-core modes: 1 scans candidates in Morton curve order with projected-box "
+                         "pruning, 2 also halves each 64-tile group of the curve at its medians down to single "
+                         "tiles, 0 scans every tile")
     ap.add_argument("--pattern", default="knn", choices=["knn", "union"],
                     help="matrix pattern: the directed k-NN rows, or their union with the transpose (symmetric)")
     ap.add_argument("--delta", type=float, default=0.0,
@@ -416,7 +417,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "m": w.m, "k": w.k, "k0": w.k0, "d": w.d,
                    "mode": primary, "margin": w.margin, "grid": [w.e_min, w.e_max, w.G],
-                   "curve_order": bool(args.curve_order) and primary != "learned" and not (primary == "f32" and w.m <= 8),
+                   "curve_order": (args.curve_order if primary != "learned" and not (primary == "f32" and w.m <= 8)
+                                   else 0),
                    "alpha": w.alpha, "beta": w.beta, "fallback_rows": main_form["fallback_rows"],
                    "learned": main_form.get("learned"), "pattern": args.pattern, "delta": args.delta,
                    "nnz": main_form["nnz"]},

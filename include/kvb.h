@@ -92,10 +92,13 @@ extern "C" {
                                     3 (hi/lo pairs, default) or 6 (hi/mid/lo pairs) */
 #define KVB_OPT_N_PROBE 4        /* learned mode: buckets each query searches (1..min(32, n_buckets)); needs a
                                     partitioner in the context; saved with it */
-#define KVB_OPT_CURVE_ORDER 5    /* matrix-core exact modes, m <= 256: 1 (default) scans candidates in the Morton
-                                    order of the principal projections and skips tiles whose projected boxes
-                                    lie beyond every query's threshold; 0 scans every tile in sample order.
-                                    Either way the result is the same exact k-NN */
+#define KVB_OPT_CURVE_ORDER 5    /* matrix-core exact modes, m <= 256: 1 scans candidates in the Morton order
+                                    of the principal projections and skips tiles whose projected boxes lie
+                                    beyond every query's threshold; 2 (default) does the same after halving
+                                    every group of 64 consecutive tiles at its median along the widest side of
+                                    its box, recursively down to single tiles (tighter tile boxes: fewer
+                                    scored pairs); 0 scans every tile in sample order. Every value gives the
+                                    same exact k-NN */
 #define KVB_OPT_PATTERN 6        /* pattern of kvb_build's matrix: KVB_PATTERN_KNN (default) or KVB_PATTERN_UNION */
 #define KVB_PATTERN_KNN 0        /* the directed k-NN pattern, k entries per row */
 #define KVB_PATTERN_UNION 1      /* E u E^T (as kvb_union_pattern); col and val must then hold n (2k - 1)

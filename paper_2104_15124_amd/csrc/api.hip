@@ -113,7 +113,7 @@ int kvb_set_option(kvb_ctx ctx, int32_t key, int64_t value)
         ctx->pattern = static_cast<int>(value);
         return KVB_OK;
     case KVB_OPT_CURVE_ORDER:
-        KVB_REQUIRE(ctx, value == 0 || value == 1, "KVB_OPT_CURVE_ORDER must be 0 or 1");
+        KVB_REQUIRE(ctx, value >= 0 && value <= 2, "KVB_OPT_CURVE_ORDER must be 0, 1 or 2");
         ctx->curve_order = static_cast<int>(value);
         return KVB_OK;
     case KVB_OPT_BF16_SPLIT:
@@ -268,7 +268,8 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                 KVB_HIP(ctx, kvb::launch_colmean(X, nn, m, colpart, colblocks, mu, ctx->stream));
                 KVB_HIP(ctx, kvb::launch_principal_basis(X, nn, m, mu, covpart, C, P, ctx->stream));
                 KVB_HIP(ctx, kvb::launch_curve_order(X, nn, m, mu, P, z, zpart, code, scode, vals, order, sort_tmp,
-                                                     csort, pos, cid, zs, tbox, sbox, tree, ctx->stream));
+                                                     csort, pos, cid, zs, tbox, sbox, tree, ctx->curve_order == 2,
+                                                     ctx->stream));
                 // curve-ordered copy of the samples for the refine step
                 Xs = cv.take<float>(size_t(nn) * m);
                 KVB_HIP(ctx, kvb::launch_gather_rows(X, nn, m, cid, Xs, ctx->stream));

@@ -58,7 +58,7 @@ struct kvb_ctx_s {
     size_t scratch_limit = 0;
     int64_t force_fallback = 0;
     int bf16_split = 3;
-    int curve_order = 1;
+    int curve_order = 2;
     int pattern = KVB_PATTERN_KNN;   // pattern of kvb_build's matrix
     double delta = 0.0;              // sparsity tolerance of kvb_build (0: keep every entry)
     int build_G = 0;   // grid size of the last kvb_build (0: none yet)

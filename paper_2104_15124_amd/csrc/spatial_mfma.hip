@@ -4,7 +4,8 @@
 // concentrate near a few principal directions. An orthonormal basis P of the
 // top PR principal directions of the centred samples y is found by subspace
 // iteration on their covariance; the projections z = P^T y order the samples
-// along a Morton curve of their first PCODE coordinates. Query blocks and
+// along a Morton curve of their first PCODE coordinates, optionally refined by
+// median splits inside groups of 64 tiles (k_kd_local). Query blocks and
 // candidate tiles of consecutive curve positions are then compact in z, and
 // because an orthonormal projection never lengthens a vector,
 //   |y_i - y_j|^2 >= |z_i - z_j|^2 >= (gap between the boxes of their z)^2,
@@ -321,6 +322,120 @@ __global__ __launch_bounds__(256) void k_zboxes(const float* __restrict__ src, i
     out[static_cast<size_t>(g) * 2 * PR_DIMS + PR_DIMS + c] = hi;
 }
 
+// Median splits inside each group of KD_GROUP consecutive curve positions (64
+// tiles): the group is halved at its middle position along the widest side of
+// its box in z, each half likewise, down to 32-position tiles. A curve jump
+// inside a group then falls between tiles instead of inside one, and every
+// tile is the leaf of a balanced split of its group, so the tiles' boxes are
+// compact (the first split of a group that straddles two distant regions
+// separates them). Positions beyond n (last group) stay at the group's end.
+// One workgroup per group; the halving is a bitonic sort in LDS of the keys
+// (segment, coordinate on the segment's widest side, local index).
+constexpr int KD_GROUP = 2048;
+constexpr int KD_LEVELS = 6;          // 2048 -> 32
+constexpr int KD_THREADS = 256;
+constexpr int KD_PER = KD_GROUP / KD_THREADS;
+
+__global__ __launch_bounds__(KD_THREADS) void k_kd_local(int32_t* __restrict__ perm, const float* __restrict__ zs,
+                                                         int n)
+{
+    __shared__ uint64_t s_key[KD_GROUP];
+    __shared__ int32_t s_id[KD_GROUP];
+    __shared__ uint32_t s_lo[1 << (KD_LEVELS - 1)][PR_DIMS], s_hi[1 << (KD_LEVELS - 1)][PR_DIMS];
+    __shared__ int s_dim[1 << (KD_LEVELS - 1)];
+    const int tid = threadIdx.x;
+    const int g0 = blockIdx.x * KD_GROUP;
+    const int m = min(KD_GROUP, n - g0);
+    constexpr uint64_t PAD = ~0ull;
+    for (int e = tid; e < KD_GROUP; e += KD_THREADS) {
+        s_id[e] = e < m ? perm[g0 + e] : -1;
+        s_key[e] = e < m ? static_cast<uint64_t>(e) : PAD;   // current order: local index in the low bits
+    }
+    __syncthreads();
+    for (int l = 0; l < KD_LEVELS; ++l) {
+        const int shift = 11 - l;   // position >> shift = segment at this level
+        const int nseg = 1 << l;
+        for (int e = tid; e < nseg * PR_DIMS; e += KD_THREADS) {
+            s_lo[e / PR_DIMS][e % PR_DIMS] = ~0u;
+            s_hi[e / PR_DIMS][e % PR_DIMS] = 0u;
+        }
+        __syncthreads();
+        // boxes: each thread owns KD_PER consecutive positions (one segment)
+        {
+            const int p0 = tid * KD_PER;
+            const int seg = p0 >> shift;
+            uint32_t lo[PR_DIMS], hi[PR_DIMS];
+#pragma unroll
+            for (int c = 0; c < PR_DIMS; ++c) {
+                lo[c] = ~0u;
+                hi[c] = 0u;
+            }
+            bool any = false;
+            for (int j = 0; j < KD_PER; ++j) {
+                const uint64_t k = s_key[p0 + j];
+                if (k == PAD) continue;
+                const int o = static_cast<int>(k & 0xFFFFu);
+                any = true;
+#pragma unroll
+                for (int c = 0; c < PR_DIMS; ++c) {
+                    const uint32_t v = float_order_bits(zs[static_cast<size_t>(g0 + o) * PR_DIMS + c]);
+                    lo[c] = min(lo[c], v);
+                    hi[c] = max(hi[c], v);
+                }
+            }
+            if (any) {
+#pragma unroll
+                for (int c = 0; c < PR_DIMS; ++c) {
+                    atomicMin(&s_lo[seg][c], lo[c]);
+                    atomicMax(&s_hi[seg][c], hi[c]);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < nseg) {
+            int best = 0;
+            float wbest = -1.f;
+            for (int c = 0; c < PR_DIMS; ++c) {
+                const float w = s_hi[tid][c] >= s_lo[tid][c]
+                                    ? order_bits_float(s_hi[tid][c]) - order_bits_float(s_lo[tid][c]) : -1.f;
+                if (w > wbest) {
+                    wbest = w;
+                    best = c;
+                }
+            }
+            s_dim[tid] = best;
+        }
+        __syncthreads();
+        // keys: segment (bits 48..), coordinate on its widest side (16..47), local index (0..15)
+        for (int p = tid; p < KD_GROUP; p += KD_THREADS) {
+            const uint64_t k = s_key[p];
+            if (k == PAD) continue;
+            const int o = static_cast<int>(k & 0xFFFFu);
+            const int seg = p >> shift;
+            const uint32_t v = float_order_bits(zs[static_cast<size_t>(g0 + o) * PR_DIMS + s_dim[seg]]);
+            s_key[p] = (static_cast<uint64_t>(seg) << 48) | (static_cast<uint64_t>(v) << 16) | static_cast<uint64_t>(o);
+        }
+        __syncthreads();
+        // ascending bitonic sort of the group's keys (PAD keys sort last)
+        for (int k = 2; k <= KD_GROUP; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = tid; t < KD_GROUP / 2; t += KD_THREADS) {
+                    const int i = 2 * t - (t & (j - 1));
+                    const int q = i + j;
+                    const uint64_t a = s_key[i], b = s_key[q];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        s_key[i] = b;
+                        s_key[q] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    for (int p = tid; p < m; p += KD_THREADS) perm[g0 + p] = s_id[static_cast<int>(s_key[p] & 0xFFFFu)];
+}
+
 // ------------------------------------------------------------------ launchers
 int cov_partials() { return 32; }
 int cov_chunks(int m) { return (m * (m + 1) / 2 + COV_ENTRIES - 1) / COV_ENTRIES; }
@@ -344,7 +459,7 @@ hipError_t launch_principal_basis(const float* X, int n, int m, const double* mu
 hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, const float* P, float* z, float* zpart,
                               uint32_t* code, uint32_t* scode, int32_t* vals, int32_t* perm, void* sort_tmp,
                               size_t sort_bytes, int32_t* pos, int32_t* cid, float* zs, float* tbox, float* sbox,
-                              float* tree, hipStream_t st)
+                              float* tree, bool median_splits, hipStream_t st)
 {
     const int nb = project_blocks(n);
     hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, st, X, n, m, mu, P, z, zpart);
@@ -357,6 +472,12 @@ hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, co
     if (e != hipSuccess) return e;
     const int ntiles = (n + 31) / 32, npad = ntiles * 32;
     hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, perm, n, npad, z, pos, cid, zs);
+    if (median_splits) {
+        // the median splits inside each 64-tile group of the curve (they read the
+        // curve's coordinates), then the maps of the final order
+        hipLaunchKernelGGL(k_kd_local, dim3((n + KD_GROUP - 1) / KD_GROUP), dim3(KD_THREADS), 0, st, perm, zs, n);
+        hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, perm, n, npad, z, pos, cid, zs);
+    }
     hipLaunchKernelGGL(k_zboxes, dim3((ntiles * PR_DIMS + 255) / 256), dim3(256), 0, st, zs, n, 32, ntiles, 0, tbox);
     const int nsb = (ntiles + SB_TILES_MFMA - 1) / SB_TILES_MFMA;
     hipLaunchKernelGGL(k_zboxes, dim3((nsb * PR_DIMS + 255) / 256), dim3(256), 0, st, tbox, ntiles, SB_TILES_MFMA, nsb,

@@ -318,32 +318,55 @@ CURVE_CASES = [
 
 @pytest.mark.parametrize("name,kind,n,m,k,margin,mode,split,seed", CURVE_CASES, ids=[c[0] for c in CURVE_CASES])
 def test_knn_curve_order_matches_plain_scan(gpu_lib, name, kind, n, m, k, margin, mode, split, seed):
-    """The curve-ordered scan with projected-box pruning returns the same exact
-    neighbour lists as the scan of every tile; on samples of low intrinsic
-    dimension it evaluates fewer candidate pairs."""
+    """The curve-ordered scans with projected-box pruning (Morton order, and
+    Morton order with median splits inside 64-tile groups) return the same
+    exact neighbour lists as the scan of every tile; on samples of low
+    intrinsic dimension they evaluate fewer candidate pairs."""
     from paper_2104_15124_amd import kvb
     say(f"[knn-curve] {name}: n={n} m={m} k={k} margin={margin} mode={mode} split={split}")
     X = _gen(kind, n, m, seed)
     out = {}
-    for curve in (1, 0):
+    for curve in (2, 1, 0):
         ctx = kvb.Context()
         ctx.set_option(kvb.OPT_BF16_SPLIT, split)
         ctx.set_option(kvb.OPT_CURVE_ORDER, curve)
         gi, gd, fl = run_knn(gpu_lib, X, k, margin, mode=mode, ctx=ctx)
         out[curve] = (gi, gd, kvb.knn_pairs(ctx), kvb.knn_fallback_rows(ctx))
         ctx.close()
-    (ci, cd, cpairs, cfb), (pi, pd, ppairs, pfb) = out[1], out[0]
-    say(f"[knn-curve] {name}: pairs curve {cpairs:.4g} plain {ppairs:.4g}, fallback rows {cfb} / {pfb}")
-    np.testing.assert_array_equal(cd, pd)
-    # indices may differ only among neighbours at exactly equal distances
-    for r in np.nonzero((ci != pi).any(axis=1))[0]:
-        for p in np.nonzero(ci[r] != pi[r])[0]:
-            assert (cd[r] == cd[r][p]).sum() > 1 or cd[r][p] == cd[r][-1], f"row {r} position {p}"
+    pi, pd, ppairs, pfb = out[0]
+    assert ppairs == float(n) * n
     rows = np.random.default_rng(seed).choice(n, 200, replace=False)
     ri, rd = knn_reference(X, k, rows=rows)
-    check_knn_rows(ci[rows], cd[rows], ri, rd, k, rows)
-    assert ppairs == float(n) * n
-    assert cpairs <= ppairs
+    for curve in (2, 1):
+        ci, cd, cpairs, cfb = out[curve]
+        say(f"[knn-curve] {name}: order {curve}: pairs {cpairs:.4g} (plain {ppairs:.4g}), "
+            f"fallback rows {cfb} / {pfb}")
+        np.testing.assert_array_equal(cd, pd)
+        # indices may differ only among neighbours at exactly equal distances
+        for r in np.nonzero((ci != pi).any(axis=1))[0]:
+            for p in np.nonzero(ci[r] != pi[r])[0]:
+                assert (cd[r] == cd[r][p]).sum() > 1 or cd[r][p] == cd[r][-1], f"row {r} position {p}"
+        check_knn_rows(ci[rows], cd[rows], ri, rd, k, rows)
+        assert cpairs <= ppairs
+
+
+def test_knn_median_splits_score_fewer_pairs(gpu_lib):
+    """On the 4-dimensional mixture (the 8M workload's recipe at n = 500k) the
+    median splits inside the curve's 64-tile groups give tighter tile boxes:
+    the exact scan scores at most 80% of the Morton order's pairs, with the
+    same neighbour distances."""
+    from paper_2104_15124_amd import kvb
+    X = workloads.make("gmm_n8m", seed=3, n=500_000)
+    out = {}
+    for curve in (1, 2):
+        ctx = kvb.Context()
+        ctx.set_option(kvb.OPT_CURVE_ORDER, curve)
+        gi, gd, fl = run_knn(gpu_lib, X, 64, 32, mode="f32", ctx=ctx)
+        out[curve] = (gd, kvb.knn_pairs(ctx))
+        ctx.close()
+    say(f"[knn-curve] mixture n=500k: pairs Morton {out[1][1]:.4g}, with median splits {out[2][1]:.4g}")
+    np.testing.assert_array_equal(out[1][0], out[2][0])
+    assert out[2][1] <= 0.8 * out[1][1]
 
 
 def test_knn_curve_rank_deficient_and_small(gpu_lib):
