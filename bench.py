@@ -113,6 +113,9 @@ def pass_rooflines(w, prof, r, nnz, base_nnz, csr, union, delta, peaks):
     nk = float(w.n) * w.k
     kp = min(w.k + w.margin, w.n)
     rows8 = float(w.n) * 8 if csr else 0.0                         # rowptr reads of the CSR passes
+    # after a curve-ordered k-NN the passes run on curve-ordered rows, and the
+    # assemble pass reads the sample ids of its output row as well
+    curve_rows = prof.get("curve_rows", (0.0, 0))[1] > 0
     pass_bytes = {
         "knn_refine": float(w.n) * kp * (w.m * 4 + 8) + nk * 8,    # candidate rows + keys, idx/d2 out
         "adhoc_bandwidth": float(w.n) * (w.k0 * 4 + 4),
@@ -120,7 +123,9 @@ def pass_rooflines(w, prof, r, nnz, base_nnz, csr, union, delta, peaks):
         "density": nnz * 12 + float(w.n) * 12 + rows8,
         "q_pass": nnz * 12 + float(w.n) * 12 + rows8,
         # entries in / CSR out (the union pattern's columns are already written), P and D
-        "assemble": nnz * (16 + (4 if csr else 8)) + float(w.n) * 16 + rows8,
+        "assemble": nnz * (16 + (4 if csr else 8) + (4 if curve_rows else 0)) + float(w.n) * (16 + 4 * curve_rows) + rows8,
+        # idx/d2 rows in, the neighbours' curve positions gathered, idx/d2 out; the bandwidths and the row map
+        "curve_rows": nk * 20 + float(w.n) * 8,
     }
     if union:
         pass_bytes["union_pattern"] = nk * 8 + nnz * 8 + float(w.n + 1) * 8

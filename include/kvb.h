@@ -538,7 +538,9 @@ const char* kvb_version(void);
 #define KVB_PROF_BUCKETS 11      /* learned mode: bucket sort, candidate operand gather, work lists */
 #define KVB_PROF_UNION 12        /* union pattern: row sort, transpose count, scan, sort, merge */
 #define KVB_PROF_TRUNCATE 13     /* threshold truncation: count, scan, ordered fill */
-#define KVB_PROF_SLOTS 14
+#define KVB_PROF_CURVE_ROWS 14   /* kvb_build after a curve-ordered k-NN: the rows in curve order, neighbours as
+                                    curve positions, and the ad-hoc bandwidths (in place of KVB_PROF_ADHOC) */
+#define KVB_PROF_SLOTS 15
 
 /* Turn event timing on (on != 0) or off; either way the totals restart at 0. */
 int kvb_profile_enable(kvb_ctx ctx, int32_t on);

@@ -18,7 +18,7 @@ namespace {
 const char* const kProfNames[KVB_PROF_SLOTS] = {
     "knn_select", "knn_refine", "knn_fallback", "adhoc_bandwidth", "chi_tuning", "density",
     "grid_scale", "q_pass", "assemble", "knn_prep",
-    "route", "bucket_build", "union_pattern", "truncate",
+    "route", "bucket_build", "union_pattern", "truncate", "curve_rows",
 };
 }  // namespace
 
@@ -125,8 +125,18 @@ int kvb_set_option(kvb_ctx ctx, int32_t key, int64_t value)
     }
 }
 
-int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_t mode, int32_t margin,
-            int32_t* idx, float* d2, int32_t* row_flags)
+// The curve order a matrix-core k-NN scanned, left in the context's scratch
+// for the passes of kvb_build: cid[p] = sample at curve position p, pos its
+// inverse (null when the k-NN did not run in curve order).
+struct CurveRows {
+    const int32_t* cid = nullptr;
+    const int32_t* pos = nullptr;
+};
+
+// kvb_knn on the scratch from byte `base` on (the bytes before it are left to
+// the caller), reporting the curve order through cr when it ran in one.
+static int knn_run(kvb_ctx ctx, size_t base, const float* X, int64_t n, int32_t m, int32_t k, int32_t mode,
+                   int32_t margin, int32_t* idx, float* d2, int32_t* row_flags, CurveRows* cr)
 {
     if (check_ctx(ctx)) return KVB_E_INVALID;
     KVB_REQUIRE(ctx, n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31), got %lld", (long long)n);
@@ -197,9 +207,9 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                 round256(size_t(csb) * 2 * kvb::PR_DIMS * sizeof(float)) + round256(csort) +
                 round256(size_t(nn) * m * sizeof(float)) + 512;
     }
-    int rc = ensure_scratch(ctx, need);
+    int rc = ensure_scratch(ctx, base + need);
     if (rc) return rc;
-    Carve cv(ctx->scratch);
+    Carve cv(static_cast<char*>(ctx->scratch) + base);
     uint64_t* keys = cv.take<uint64_t>(size_t(nn) * (direct ? kp : cap));
     float* slast = cv.take<float>(nn);
     int* fb_list = cv.take<int>(nn);
@@ -212,6 +222,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
     int kstride = kp;
     float* Xs = nullptr;        // curve-ordered samples (lists are then stored in that order)
     int32_t* perm = nullptr;
+    const int32_t* curve_pos = nullptr;
     if (direct) {
         Xs = cv.take<float>(size_t(nn) * m);
         perm = cv.take<int32_t>(nn);
@@ -260,6 +271,7 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
                 int32_t* order = cv.take<int32_t>(nn);
                 int32_t* pos = cv.take<int32_t>(nn);
                 int32_t* cid = cv.take<int32_t>(npad32);
+                curve_pos = pos;
                 float* zs = cv.take<float>(size_t(npad32) * kvb::PR_DIMS);
                 float* tbox = cv.take<float>(size_t(ctiles) * 2 * kvb::PR_DIMS);
                 float* tree = cv.take<float>(size_t(std::max(tl.nodes, 1)) * 2 * kvb::PR_DIMS);
@@ -329,7 +341,17 @@ int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_
         Prof pr(ctx, KVB_PROF_KNN_FALLBACK);
         KVB_HIP(ctx, kvb::launch_fallback(X, nn, m, k, ctx->fb_count_dev, fb_list, fw, idx, d2, ctx->stream));
     }
+    if (cr && curve_pos) {
+        cr->cid = perm;
+        cr->pos = curve_pos;
+    }
     return KVB_OK;
+}
+
+int kvb_knn(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int32_t mode, int32_t margin,
+            int32_t* idx, float* d2, int32_t* row_flags)
+{
+    return knn_run(ctx, 0, X, n, m, k, mode, margin, idx, d2, row_flags, nullptr);
 }
 
 int kvb_knn_fallback_rows(kvb_ctx ctx, int64_t* count_host)
@@ -810,9 +832,26 @@ int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int3
                 "b and rho must be non-null float32 device pointers");
     KVB_REQUIRE(ctx, aligned(rowptr) && aligned(col) && aligned(val), "rowptr, col, val must be non-null");
     KVB_REQUIRE(ctx, (P == nullptr || aligned(P)) && (D == nullptr || aligned(D)), "P and D must be aligned");
-    int rc = kvb_knn(ctx, X, n, m, k, mode, margin, idx, d2, row_flags);
+    const bool fixed_k = !(ctx->pattern == KVB_PATTERN_UNION || ctx->delta > 0.0);
+    const int nn = static_cast<int>(n);
+    const int64_t nnz = n * k;
+    const int nb = kvb::chi_num_blocks(nnz);
+    const int lb = kvb::logsum_num_blocks(nn);
+    // the passes' own scratch; a matrix-core k-NN in curve order also leaves
+    // room for the curve-ordered rows (its own scratch follows)
+    const bool curve_possible = fixed_k && mode != KVB_KNN_LEARNED && !(mode == KVB_KNN_F32 && m <= 8) &&
+                                ctx->curve_order && m <= 256;
+    size_t own = round256(size_t(nb) * G * sizeof(double)) + round256(size_t(2 * lb) * sizeof(double)) +
+                 2 * round256(size_t(nn) * sizeof(double)) + 1024;
+    if (curve_possible)
+        own += round256(size_t(nnz) * sizeof(int32_t)) + round256(size_t(nnz) * sizeof(float)) +
+               3 * round256(size_t(nn) * sizeof(float));
+    own = round256(own);
+    CurveRows cr;
+    int rc = knn_run(ctx, fixed_k ? own : 0, X, n, m, k, mode, margin, idx, d2, row_flags,
+                     curve_possible ? &cr : nullptr);
     if (rc < 0) return rc;
-    if (ctx->pattern == KVB_PATTERN_UNION || ctx->delta > 0.0) {
+    if (!fixed_k) {
         rc = build_csr(ctx, n, k, k0, d, alpha, beta, e_min, e_max, G, out_kind, idx, d2, b, rho, psi, rowptr, col,
                        val, P, D);
         if (rc < 0) return rc;
@@ -820,12 +859,7 @@ int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int3
         if (!info_host) return KVB_OK;
         return kvb_build_info(ctx, chi_a_host, chi_b_host, info_host);
     }
-    const int nn = static_cast<int>(n);
-    const int64_t nnz = n * k;
-    const int nb = kvb::chi_num_blocks(nnz);
-    const int lb = kvb::logsum_num_blocks(nn);
-    rc = ensure_scratch(ctx, round256(size_t(nb) * G * sizeof(double)) + round256(size_t(2 * lb) * sizeof(double)) +
-                                 2 * round256(size_t(nn) * sizeof(double)) + 1024);
+    rc = ensure_scratch(ctx, own);
     if (rc) return rc;
     Carve cv(ctx->scratch);
     double* part = cv.take<double>(size_t(nb) * G);
@@ -834,34 +868,55 @@ int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int3
     double* Dtmp = cv.take<double>(nn);
     BuildDev* bd = ctx->build_dev;
     hipStream_t st = ctx->stream;
-    {
+    // With the curve order: the rows, bandwidths, densities and q in curve
+    // order (neighbours as curve positions), the matrix rows written back by
+    // sample id. Otherwise every vector by sample id.
+    const bool cv_rows = cr.cid != nullptr;
+    const int32_t* pidx = idx;
+    const float* pd2 = d2;
+    float *pb = b, *prho = rho, *ppsi = psi;
+    if (cv_rows) {
+        int32_t* idx_c = cv.take<int32_t>(size_t(nnz));
+        float* d2_c = cv.take<float>(size_t(nnz));
+        pb = cv.take<float>(nn);
+        prho = cv.take<float>(nn);
+        ppsi = cv.take<float>(nn);
+        pidx = idx_c;
+        pd2 = d2_c;
+        Prof pr(ctx, KVB_PROF_CURVE_ROWS);
+        KVB_HIP(ctx, kvb::launch_curve_rows(idx, d2, nn, k, k0, cr.cid, cr.pos, idx_c, d2_c, pb, st));
+    } else {
         Prof pr(ctx, KVB_PROF_ADHOC);
         KVB_HIP(ctx, kvb::launch_adhoc_bandwidth(d2, nn, k, k0, b, st));
     }
     {
         Prof pr(ctx, KVB_PROF_CHI);
-        KVB_HIP(ctx, kvb::launch_chi(idx, d2, b, nnz, k, G, e_min, e_max, nullptr, part, &bd->a, st));
+        KVB_HIP(ctx, kvb::launch_chi(pidx, pd2, pb, nnz, k, G, e_min, e_max, nullptr, part, &bd->a, st));
     }
     {
         Prof pr(ctx, KVB_PROF_DENSITY);
-        KVB_HIP(ctx, kvb::launch_density(idx, d2, nn, k, b, 0.0, &bd->a.e_star, d, beta, rho, psi, st));
+        KVB_HIP(ctx, kvb::launch_density(pidx, pd2, nn, k, pb, 0.0, &bd->a.e_star, d, beta, prho,
+                                         cv_rows ? ppsi : psi, st));
     }
     {
         Prof pr(ctx, KVB_PROF_GRID_SCALE);
-        KVB_HIP(ctx, kvb::launch_grid_scale(b, rho, nn, lpart, &bd->scale, st));
+        KVB_HIP(ctx, kvb::launch_grid_scale(pb, prho, nn, lpart, &bd->scale, st));
     }
     {
         Prof pr(ctx, KVB_PROF_CHI);
-        KVB_HIP(ctx, kvb::launch_chi(idx, d2, rho, nnz, k, G, e_min, e_max, &bd->scale, part, &bd->b, st));
+        KVB_HIP(ctx, kvb::launch_chi(pidx, pd2, prho, nnz, k, G, e_min, e_max, &bd->scale, part, &bd->b, st));
     }
     {
         Prof pr(ctx, KVB_PROF_QPASS);
-        KVB_HIP(ctx, kvb::launch_qpass(idx, d2, nn, k, rho, 0.0, &bd->b.e_star, alpha, d, qa, st));
+        KVB_HIP(ctx, kvb::launch_qpass(pidx, pd2, nn, k, prho, 0.0, &bd->b.e_star, alpha, d, qa, st));
     }
+    if (cv_rows)
+        KVB_HIP(ctx, kvb::launch_scatter_samples(cr.cid, nn, pb, b, prho, rho, ppsi, psi, st));
     {
         Prof pr(ctx, KVB_PROF_ASSEMBLE);
-        KVB_HIP(ctx, kvb::launch_assemble(idx, d2, nn, k, rho, 0.0, &bd->b.e_star, qa, out_kind, rowptr, col, val, P,
-                                          D ? D : Dtmp, st));
+        KVB_HIP(ctx, kvb::launch_assemble(pidx, pd2, nn, k, prho, 0.0, &bd->b.e_star, qa, out_kind, rowptr, col, val,
+                                          P, D ? D : Dtmp, st, cv_rows ? cr.cid : nullptr, cv_rows ? idx : nullptr,
+                                          rho));
     }
     ctx->build_G = G;
     if (!info_host) return KVB_OK;

@@ -157,9 +157,18 @@ hipError_t launch_grid_scale(const float* ref, const float* rho, int n, double* 
 // e_dev non-null: e is read from device memory (e.g. a TuneResult's e_star)
 hipError_t launch_qpass(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
                         const double* e_dev, double alpha, double d, double* qa, hipStream_t st);
+// rowmap non-null: stored row p (curve order, idx as curve positions, rho and qa by position) is output row
+// rowmap[p], whose columns are sid[rowmap[p] * k + r]; rho_out: rho by sample id (the symmetric finish)
 hipError_t launch_assemble(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
                            const double* e_dev, const double* qa, int out_kind, int64_t* rowptr, int32_t* col,
-                           float* val, double* P, double* D, hipStream_t st);
+                           float* val, double* P, double* D, hipStream_t st, const int32_t* rowmap = nullptr,
+                           const int32_t* sid = nullptr, const float* rho_out = nullptr);
+// the k-NN rows in curve order (row p = sample cid[p]), neighbours as curve positions, and their bandwidths
+hipError_t launch_curve_rows(const int32_t* idx, const float* d2, int n, int k, int k0, const int32_t* cid,
+                             const int32_t* pos, int32_t* idx_c, float* d2_c, float* b_c, hipStream_t st);
+// out[cid[p]] = in[p] for up to three vectors (null pointers skipped)
+hipError_t launch_scatter_samples(const int32_t* cid, int n, const float* a_c, float* a, const float* b_c, float* b,
+                                  const float* c_c, float* c, hipStream_t st);
 
 // learned partitioner: MLP (mlp_kernels.hip)
 hipError_t launch_gemm_nt(const uint16_t* A, int lda, const uint16_t* B, int ldb, int M, int N, int K,

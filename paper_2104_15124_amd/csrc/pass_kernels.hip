@@ -26,6 +26,48 @@ __global__ __launch_bounds__(256) void k_adhoc_bandwidth(const float* __restrict
     b[i] = static_cast<float>(sqrt(s));
 }
 
+// The k-NN rows in the order of the curve the matrix-core k-NN scanned (row p
+// = sample cid[p]), their neighbours as curve positions (pos of the sample
+// id), and the bandwidth of each (as k_adhoc_bandwidth). The passes that
+// follow then gather the per-sample vectors of a row's neighbours from curve
+// positions near the row's own: neighbouring rows share cache lines.
+// One wavefront per row.
+__global__ __launch_bounds__(256) void k_curve_rows(const int32_t* __restrict__ idx, const float* __restrict__ d2,
+                                                    int n, int k, int k0, const int32_t* __restrict__ cid,
+                                                    const int32_t* __restrict__ pos, int32_t* __restrict__ idx_c,
+                                                    float* __restrict__ d2_c, float* __restrict__ b_c)
+{
+    const int lane = lane_id();
+    const int p = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (p >= n) return;
+    const int i = cid[p];
+    const int32_t* irow = idx + static_cast<size_t>(i) * k;
+    const float* drow = d2 + static_cast<size_t>(i) * k;
+    for (int r = lane; r < k; r += WAVE) {
+        idx_c[static_cast<size_t>(p) * k + r] = pos[irow[r]];
+        d2_c[static_cast<size_t>(p) * k + r] = drow[r];
+    }
+    if (lane == 0) {
+        double s = 0.0;
+        for (int r = 1; r <= k0; ++r) s += static_cast<double>(drow[r]);
+        b_c[p] = static_cast<float>(sqrt(s));
+    }
+}
+
+// out[cid[p]] = in[p] for up to three per-sample vectors (null: skipped)
+__global__ __launch_bounds__(256) void k_scatter_samples(const int32_t* __restrict__ cid, int n,
+                                                         const float* __restrict__ a_c, float* __restrict__ a,
+                                                         const float* __restrict__ b_c, float* __restrict__ b,
+                                                         const float* __restrict__ c_c, float* __restrict__ c)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const int i = cid[p];
+    if (a) a[i] = a_c[p];
+    if (b) b[i] = b_c[p];
+    if (c) c[i] = c_c[p];
+}
+
 // Row sums of exp(-d2/(e rho_i rho_j)): the argument in float64, the kernel
 // value in float32 (its relative error, about x 2^-24 at argument x, stays far
 // inside the 1e-5 entry tolerance where the terms matter), the sum in float64;
@@ -389,17 +431,23 @@ __global__ __launch_bounds__(256) void k_assemble(const int32_t* __restrict__ id
                                                   int out_kind,
                                                   int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
                                                   float* __restrict__ val, double* __restrict__ Pout,
-                                                  double* __restrict__ Dout)
+                                                  double* __restrict__ Dout, const int32_t* __restrict__ rowmap,
+                                                  const int32_t* __restrict__ sid)
 {
     if (e_dev) e = *e_dev;
     const int lane = lane_id();
-    const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (i >= n) return;
-    const int32_t* irow = idx + static_cast<size_t>(i) * k;
-    const float* drow = d2 + static_cast<size_t>(i) * k;
-    const double ri = static_cast<double>(rho[i]);
+    const int p = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (p >= n) return;
+    // stored row p is output row i; with a row map (curve-ordered rows, see
+    // k_curve_rows) idx holds curve positions for the gathers and sid the
+    // sample ids of output row i, which are the columns
+    const int i = rowmap ? rowmap[p] : p;
+    const int32_t* irow = idx + static_cast<size_t>(p) * k;
+    const int32_t* srow = rowmap ? sid + static_cast<size_t>(i) * k : irow;
+    const float* drow = d2 + static_cast<size_t>(p) * k;
+    const double ri = static_cast<double>(rho[p]);
     const double inv = 1.0 / (e * ri);
-    const double qai = qa[i];
+    const double qai = qa[p];
     double kt[E];
     int cj[E];
     Comp64 acc;
@@ -412,7 +460,7 @@ __global__ __launch_bounds__(256) void k_assemble(const int32_t* __restrict__ id
             const int j = irow[r];
             const double x = static_cast<double>(drow[r]) * inv / static_cast<double>(rho[j]);
             kt[s] = static_cast<double>(expf(-static_cast<float>(x))) * qai * qa[j];
-            cj[s] = j;
+            cj[s] = srow[r];
             acc.add(kt[s]);
         }
     }
@@ -632,23 +680,39 @@ hipError_t launch_qpass(const int32_t* idx, const float* d2, int n, int k, const
 
 hipError_t launch_assemble(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
                            const double* e_dev, const double* qa, int out_kind, int64_t* rowptr, int32_t* col, float* val,
-                           double* P, double* D, hipStream_t st)
+                           double* P, double* D, hipStream_t st, const int32_t* rowmap, const int32_t* sid,
+                           const float* rho_out)
 {
     const dim3 grid((n + 3) / 4), block(256);
     if (k <= 64)
         hipLaunchKernelGGL((k_assemble<1>), grid, block, 0, st, idx, d2, n, k, rho, e, e_dev, qa, out_kind, rowptr, col,
-                           val, P, D);
+                           val, P, D, rowmap, sid);
     else if (k <= 128)
         hipLaunchKernelGGL((k_assemble<2>), grid, block, 0, st, idx, d2, n, k, rho, e, e_dev, qa, out_kind, rowptr, col,
-                           val, P, D);
+                           val, P, D, rowmap, sid);
     else
         hipLaunchKernelGGL((k_assemble<4>), grid, block, 0, st, idx, d2, n, k, rho, e, e_dev, qa, out_kind, rowptr, col,
-                           val, P, D);
+                           val, P, D, rowmap, sid);
     if (out_kind == KVB_OUT_SYMMETRIC) {
         const int64_t nnz = static_cast<int64_t>(n) * k;
         hipLaunchKernelGGL(k_symmetric_finish, dim3(static_cast<unsigned>((nnz + 255) / 256)), dim3(256), 0, st,
-                           nnz, k, col, rho, D, e, e_dev, val);
+                           nnz, k, col, rowmap ? rho_out : rho, D, e, e_dev, val);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_curve_rows(const int32_t* idx, const float* d2, int n, int k, int k0, const int32_t* cid,
+                             const int32_t* pos, int32_t* idx_c, float* d2_c, float* b_c, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_curve_rows, dim3((n + 3) / 4), dim3(256), 0, st, idx, d2, n, k, k0, cid, pos, idx_c, d2_c,
+                       b_c);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_samples(const int32_t* cid, int n, const float* a_c, float* a, const float* b_c, float* b,
+                                  const float* c_c, float* c, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scatter_samples, dim3((n + 255) / 256), dim3(256), 0, st, cid, n, a_c, a, b_c, b, c_c, c);
     return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb
            "kvb_union_pattern", "kvb_density_csr", "kvb_tune_eps_csr", "kvb_normalize_csr",
            "kvb_truncate_csr", "kvb_set_tolerance", "kvb_eigsh", "kvb_kolmogorov_solve",
            "kvb_carre_du_champ", "kvb_advect", "kvb_lanczos_prefix", "kvb_peak_probe", "kvb_tune_eps_noalloc")
-PROF_SLOTS = 14
+PROF_SLOTS = 15
 PEAK_HBM_COPY, PEAK_MFMA_BF16, PEAK_MFMA_F32, PEAK_EXP, PEAK_VALU_FMA = 0, 1, 2, 3, 4
 
 
