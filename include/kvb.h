@@ -95,7 +95,7 @@ extern "C" {
 #define KVB_OPT_CURVE_ORDER 5    /* matrix-core exact modes, m <= 256: 1 scans candidates in the Morton order
                                     of the principal projections and skips tiles whose projected boxes lie
                                     beyond every query's threshold; 2 (default) does the same after halving
-                                    every group of 64 consecutive tiles at its median along the widest side of
+                                    every group of 256 consecutive tiles at its median along the widest side of
                                     its box, recursively down to single tiles (tighter tile boxes: fewer
                                     scored pairs); 0 scans every tile in sample order. Every value gives the
                                     same exact k-NN */

@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_zboxes(const float* __restrict__ src, i
     out[static_cast<size_t>(g) * 2 * PR_DIMS + PR_DIMS + c] = hi;
 }
 
-// Median splits inside each group of KD_GROUP consecutive curve positions (64
+// Median splits inside each group of KD_GROUP consecutive curve positions (256
 // tiles): the group is halved at its middle position along the widest side of
 // its box in z, each half likewise, down to 32-position tiles. A curve jump
 // inside a group then falls between tiles instead of inside one, and every
@@ -331,9 +331,10 @@ __global__ __launch_bounds__(256) void k_zboxes(const float* __restrict__ src, i
 // separates them). Positions beyond n (last group) stay at the group's end.
 // One workgroup per group; the halving is a bitonic sort in LDS of the keys
 // (segment, coordinate on the segment's widest side, local index).
-constexpr int KD_GROUP = 2048;
-constexpr int KD_LEVELS = 6;          // 2048 -> 32
-constexpr int KD_THREADS = 256;
+constexpr int KD_LOG = 13;
+constexpr int KD_GROUP = 1 << KD_LOG;   // 8192 positions, 256 tiles
+constexpr int KD_LEVELS = KD_LOG - 5;   // halvings down to 32
+constexpr int KD_THREADS = 1024;
 constexpr int KD_PER = KD_GROUP / KD_THREADS;
 
 __global__ __launch_bounds__(KD_THREADS) void k_kd_local(int32_t* __restrict__ perm, const float* __restrict__ zs,
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(KD_THREADS) void k_kd_local(int32_t* __restrict__ p
     }
     __syncthreads();
     for (int l = 0; l < KD_LEVELS; ++l) {
-        const int shift = 11 - l;   // position >> shift = segment at this level
+        const int shift = KD_LOG - l;   // position >> shift = segment at this level
         const int nseg = 1 << l;
         for (int e = tid; e < nseg * PR_DIMS; e += KD_THREADS) {
             s_lo[e / PR_DIMS][e % PR_DIMS] = ~0u;
@@ -473,7 +474,7 @@ hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, co
     const int ntiles = (n + 31) / 32, npad = ntiles * 32;
     hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, perm, n, npad, z, pos, cid, zs);
     if (median_splits) {
-        // the median splits inside each 64-tile group of the curve (they read the
+        // the median splits inside each 256-tile group of the curve (they read the
         // curve's coordinates), then the maps of the final order
         hipLaunchKernelGGL(k_kd_local, dim3((n + KD_GROUP - 1) / KD_GROUP), dim3(KD_THREADS), 0, st, perm, zs, n);
         hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, perm, n, npad, z, pos, cid, zs);
