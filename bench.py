@@ -322,7 +322,7 @@ def main() -> int:
     ap.add_argument("--no-peaks", action="store_true", help="skip the peak microbenchmarks")
     ap.add_argument("--curve-order", type=int, default=2, choices=[0, 1, 2],
                     help="exact matrix-core modes: 1 scans candidates in Morton curve order with projected-box "
-                         "pruning, 2 also halves each 256-tile group of the curve at its medians down to single "
+                         "pruning, 2 also halves each 4096-tile group of the curve at its medians down to single "
                          "tiles, 0 scans every tile")
     ap.add_argument("--pattern", default="knn", choices=["knn", "union"],
                     help="matrix pattern: the directed k-NN rows, or their union with the transpose (symmetric)")

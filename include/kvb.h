@@ -95,10 +95,10 @@ extern "C" {
 #define KVB_OPT_CURVE_ORDER 5    /* matrix-core exact modes, m <= 256: 1 scans candidates in the Morton order
                                     of the principal projections and skips tiles whose projected boxes lie
                                     beyond every query's threshold; 2 (default) does the same after halving
-                                    every group of 256 consecutive tiles at its median along the widest side of
-                                    its box, recursively down to single tiles (tighter tile boxes: fewer
-                                    scored pairs); 0 scans every tile in sample order. Every value gives the
-                                    same exact k-NN */
+                                    every group of 4096 consecutive tiles at its median along the widest side
+                                    of its box, recursively down to single tiles (a k-d order inside each
+                                    group: tighter tile and tree boxes, fewer scored pairs); 0 scans every tile
+                                    in sample order. Every value gives the same exact k-NN */
 #define KVB_OPT_PATTERN 6        /* pattern of kvb_build's matrix: KVB_PATTERN_KNN (default) or KVB_PATTERN_UNION */
 #define KVB_PATTERN_KNN 0        /* the directed k-NN pattern, k entries per row */
 #define KVB_PATTERN_UNION 1      /* E u E^T (as kvb_union_pattern); col and val must then hold n (2k - 1)

@@ -128,7 +128,7 @@ hipError_t launch_principal_basis(const float* X, int n, int m, const double* mu
                                   hipStream_t st);
 // zpart [(project_blocks(n) + 1) * 2 * PCODE_DIMS]: block partials, then the reduced range
 // tbox [tiles, 2, PR_DIMS]; sbox [superblocks, 2, PR_DIMS]; tree [tree_layout(tiles).nodes, 2, PR_DIMS]
-// (the box tree's levels >= 1). median_splits: each group of 256 consecutive tiles of the curve is then
+// (the box tree's levels >= 1). median_splits: each group of 4096 consecutive tiles of the curve is then
 // halved at its median along the widest side of its box, recursively down to single tiles.
 hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, const float* P, float* z, float* zpart,
                               uint32_t* code, uint32_t* scode, int32_t* vals, int32_t* perm, void* sort_tmp,

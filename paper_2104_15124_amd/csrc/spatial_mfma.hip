@@ -437,6 +437,247 @@ __global__ __launch_bounds__(KD_THREADS) void k_kd_local(int32_t* __restrict__ p
     for (int p = tid; p < m; p += KD_THREADS) perm[g0 + p] = s_id[static_cast<int>(s_key[p] & 0xFFFFu)];
 }
 
+// The same halving for the levels above: groups of KG_GROUP consecutive curve
+// positions (4096 tiles) are halved along the widest side of each segment's
+// box down to segments of KD_GROUP positions, which k_kd_local then finishes.
+// One workgroup of 1024 threads per group; the segments' arrangements (local
+// indices into the group's curve order, whose coordinates zs never move) live
+// in two global buffers used in turn. A level: the segments' boxes (LDS
+// atomics on order bits), a histogram of each segment's widest coordinate
+// over KG_BINS bins of its extent, the bin holding the segment's middle rank,
+// then every element placed by prefix sums over the threads (so the result
+// does not depend on the timing of the atomics): the elements of the lower
+// bins first, then those of the middle bin up to the middle position, the rest
+// of that bin after it, the upper bins last. Within a segment the order of a
+// side is that of the previous level.
+constexpr int KG_LOG = 17;
+constexpr int KG_GROUP = 1 << KG_LOG;
+constexpr int KG_LEVELS = KG_LOG - KD_LOG;
+constexpr int KG_THREADS = 1024;
+constexpr int KG_PER = KG_GROUP / KG_THREADS;   // consecutive positions per thread (one segment)
+constexpr int KG_BINS = 1024;
+constexpr int KG_SEGS = 1 << (KG_LEVELS - 1);
+constexpr int KG_WAVES = KG_THREADS / WAVE;
+
+// exclusive prefix sum of v over the workgroup (thread order); *total: the sum
+__device__ __forceinline__ int kg_exclusive_scan(int v, int* s_w, int* total)
+{
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int y = __shfl_up(x, o, WAVE);
+        if (lane >= o) x += y;
+    }
+    if (lane == WAVE - 1) s_w[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < KG_WAVES; ++i) {
+            const int t = s_w[i];
+            s_w[i] = acc;
+            acc += t;
+        }
+        s_w[KG_WAVES] = acc;
+    }
+    __syncthreads();
+    const int r = s_w[w] + x - v;
+    *total = s_w[KG_WAVES];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int kg_bin(float v, float lo, float scale)
+{
+    const int b = static_cast<int>((v - lo) * scale);
+    return b < 0 ? 0 : (b >= KG_BINS ? KG_BINS - 1 : b);
+}
+
+// The arrangement entries of positions [p, p + KG_B) (those below pe) and
+// their coordinate on side d, loaded together so that their latencies overlap.
+constexpr int KG_B = 8;
+__device__ __forceinline__ void kg_load_side(const int32_t* __restrict__ cur, const float* __restrict__ zs, int g0,
+                                             int p, int pe, int d, int (&o)[KG_B], float (&v)[KG_B])
+{
+#pragma unroll
+    for (int u = 0; u < KG_B; ++u) o[u] = p + u < pe ? cur[p + u] : 0;
+#pragma unroll
+    for (int u = 0; u < KG_B; ++u) v[u] = p + u < pe ? zs[static_cast<size_t>(g0 + o[u]) * PR_DIMS + d] : 0.f;
+}
+
+__global__ __launch_bounds__(KG_THREADS) void k_kd_group(const int32_t* __restrict__ perm,
+                                                         const float* __restrict__ zs, int n,
+                                                         int32_t* __restrict__ ord_a, int32_t* __restrict__ ord_b,
+                                                         int32_t* __restrict__ perm_out)
+{
+    __shared__ uint32_t s_lo[KG_SEGS][PR_DIMS], s_hi[KG_SEGS][PR_DIMS];
+    __shared__ int s_dim[KG_SEGS];
+    __shared__ int s_hist[KG_SEGS][KG_BINS];
+    __shared__ int s_bstar[KG_SEGS], s_below[KG_SEGS], s_take[KG_SEGS], s_cmed[KG_SEGS];
+    __shared__ int s_base[KG_SEGS][3];
+    __shared__ int s_w[KG_WAVES + 1];
+    const int tid = threadIdx.x;
+    const int g0 = blockIdx.x * KG_GROUP;
+    const int m = min(KG_GROUP, n - g0);
+    const int p0 = tid * KG_PER;
+    const int pe = min(p0 + KG_PER, m);   // this thread's real positions [p0, pe)
+    int32_t* cur = ord_a + g0;
+    int32_t* nxt = ord_b + g0;
+    for (int p = p0; p < pe; ++p) cur[p] = p;
+    __syncthreads();
+    for (int l = 0; l < KG_LEVELS; ++l) {
+        const int shift = KG_LOG - l;   // position >> shift = segment
+        const int S = 1 << shift, H = S >> 1;
+        const int nseg = 1 << l;
+        const int seg = p0 >> shift;
+        const int s0 = seg << shift;
+        for (int e = tid; e < nseg * PR_DIMS; e += KG_THREADS) {
+            s_lo[e / PR_DIMS][e % PR_DIMS] = ~0u;
+            s_hi[e / PR_DIMS][e % PR_DIMS] = 0u;
+        }
+        for (int e = tid; e < nseg * KG_BINS; e += KG_THREADS) s_hist[e / KG_BINS][e % KG_BINS] = 0;
+        __syncthreads();
+        {
+            uint32_t lo[PR_DIMS], hi[PR_DIMS];
+#pragma unroll
+            for (int c = 0; c < PR_DIMS; ++c) {
+                lo[c] = ~0u;
+                hi[c] = 0u;
+            }
+            for (int p = p0; p < pe; p += KG_B) {
+                int o[KG_B];
+#pragma unroll
+                for (int u = 0; u < KG_B; ++u) o[u] = p + u < pe ? cur[p + u] : cur[p];
+                float4 za[KG_B], zb[KG_B];
+#pragma unroll
+                for (int u = 0; u < KG_B; ++u) {
+                    const float4* z = reinterpret_cast<const float4*>(zs + static_cast<size_t>(g0 + o[u]) * PR_DIMS);
+                    za[u] = z[0];
+                    zb[u] = z[1];
+                }
+#pragma unroll
+                for (int u = 0; u < KG_B; ++u) {
+                    const float zv[PR_DIMS] = {za[u].x, za[u].y, za[u].z, za[u].w, zb[u].x, zb[u].y, zb[u].z, zb[u].w};
+#pragma unroll
+                    for (int c = 0; c < PR_DIMS; ++c) {
+                        const uint32_t v = float_order_bits(zv[c]);
+                        lo[c] = min(lo[c], v);
+                        hi[c] = max(hi[c], v);
+                    }
+                }
+            }
+            if (pe > p0) {
+#pragma unroll
+                for (int c = 0; c < PR_DIMS; ++c) {
+                    atomicMin(&s_lo[seg][c], lo[c]);
+                    atomicMax(&s_hi[seg][c], hi[c]);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < nseg) {
+            int best = 0;
+            float wbest = -1.f;
+            for (int c = 0; c < PR_DIMS; ++c) {
+                const float w = s_hi[tid][c] >= s_lo[tid][c]
+                                    ? order_bits_float(s_hi[tid][c]) - order_bits_float(s_lo[tid][c]) : -1.f;
+                if (w > wbest) {
+                    wbest = w;
+                    best = c;
+                }
+            }
+            s_dim[tid] = best;
+        }
+        __syncthreads();
+        const int d = s_dim[seg];
+        const float lo = order_bits_float(s_lo[seg][d]), hi = order_bits_float(s_hi[seg][d]);
+        const float scale = (pe > p0 && hi > lo) ? static_cast<float>(KG_BINS) / (hi - lo) : 0.f;
+        for (int p = p0; p < pe; p += KG_B) {
+            int o[KG_B];
+            float v[KG_B];
+            kg_load_side(cur, zs, g0, p, pe, d, o, v);
+#pragma unroll
+            for (int u = 0; u < KG_B; ++u)
+                if (p + u < pe) atomicAdd(&s_hist[seg][kg_bin(v[u], lo, scale)], 1);
+        }
+        __syncthreads();
+        if (tid < nseg) {
+            // the first L = min(real, H) positions of the segment take the lower side
+            const int real = max(0, min(S, m - (tid << shift)));
+            const int L = min(real, H);
+            int b = KG_BINS, below = real;   // no split: every element stays on the lower side
+            if (real > H) {
+                int acc = 0;
+                for (b = 0; b < KG_BINS - 1; ++b) {
+                    const int c = s_hist[tid][b];
+                    if (acc + c >= L) break;
+                    acc += c;
+                }
+                below = acc;
+            }
+            s_bstar[tid] = b;
+            s_below[tid] = below;
+            s_take[tid] = L - below;
+            s_cmed[tid] = b < KG_BINS ? s_hist[tid][b] : 0;
+        }
+        __syncthreads();
+        const int bs = s_bstar[seg];
+        int cl = 0, cm = 0, cr = 0;
+        for (int p = p0; p < pe; p += KG_B) {
+            int o[KG_B];
+            float v[KG_B];
+            kg_load_side(cur, zs, g0, p, pe, d, o, v);
+#pragma unroll
+            for (int u = 0; u < KG_B; ++u)
+                if (p + u < pe) {
+                    const int b = kg_bin(v[u], lo, scale);
+                    cl += b < bs;
+                    cm += b == bs;
+                    cr += b > bs;
+                }
+        }
+        int tot;
+        int xl = kg_exclusive_scan(cl, s_w, &tot);
+        int xm = kg_exclusive_scan(cm, s_w, &tot);
+        int xr = kg_exclusive_scan(cr, s_w, &tot);
+        if (p0 == s0) {
+            s_base[seg][0] = xl;
+            s_base[seg][1] = xm;
+            s_base[seg][2] = xr;
+        }
+        __syncthreads();
+        xl -= s_base[seg][0];
+        xm -= s_base[seg][1];
+        xr -= s_base[seg][2];
+        const int below = s_below[seg], take = s_take[seg], cmed = s_cmed[seg];
+        for (int p = p0; p < pe; p += KG_B) {
+            int o[KG_B];
+            float v[KG_B];
+            kg_load_side(cur, zs, g0, p, pe, d, o, v);
+#pragma unroll
+            for (int u = 0; u < KG_B; ++u) {
+                if (p + u >= pe) continue;
+                const int b = kg_bin(v[u], lo, scale);
+                int q;
+                if (b < bs) {
+                    q = s0 + xl++;
+                } else if (b == bs) {
+                    const int r = xm++;
+                    q = r < take ? s0 + below + r : s0 + H + (r - take);
+                } else {
+                    q = s0 + H + (cmed - take) + xr++;
+                }
+                nxt[q] = o[u];
+            }
+        }
+        __syncthreads();
+        int32_t* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    for (int p = p0; p < pe; ++p) perm_out[g0 + p] = perm[g0 + cur[p]];
+}
+
 // ------------------------------------------------------------------ launchers
 int cov_partials() { return 32; }
 int cov_chunks(int m) { return (m * (m + 1) / 2 + COV_ENTRIES - 1) / COV_ENTRIES; }
@@ -474,10 +715,19 @@ hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, co
     const int ntiles = (n + 31) / 32, npad = ntiles * 32;
     hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, perm, n, npad, z, pos, cid, zs);
     if (median_splits) {
-        // the median splits inside each 256-tile group of the curve (they read the
-        // curve's coordinates), then the maps of the final order
-        hipLaunchKernelGGL(k_kd_local, dim3((n + KD_GROUP - 1) / KD_GROUP), dim3(KD_THREADS), 0, st, perm, zs, n);
-        hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, perm, n, npad, z, pos, cid, zs);
+        // the median splits inside each 4096-tile group of the curve down to
+        // 256-tile segments (they read the curve's coordinates; code and scode
+        // hold the arrangements, vals the new order), then inside each of those
+        // down to single tiles, then the maps of the final order
+        int32_t* split_order = vals;
+        hipLaunchKernelGGL(k_kd_group, dim3((n + KG_GROUP - 1) / KG_GROUP), dim3(KG_THREADS), 0, st, perm, zs, n,
+                           reinterpret_cast<int32_t*>(code), reinterpret_cast<int32_t*>(scode), split_order);
+        hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, split_order, n, npad, z, pos, cid,
+                           zs);
+        hipLaunchKernelGGL(k_kd_local, dim3((n + KD_GROUP - 1) / KD_GROUP), dim3(KD_THREADS), 0, st, split_order, zs,
+                           n);
+        hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, split_order, n, npad, z, pos, cid,
+                           zs);
     }
     hipLaunchKernelGGL(k_zboxes, dim3((ntiles * PR_DIMS + 255) / 256), dim3(256), 0, st, zs, n, 32, ntiles, 0, tbox);
     const int nsb = (ntiles + SB_TILES_MFMA - 1) / SB_TILES_MFMA;

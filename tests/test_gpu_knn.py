@@ -319,7 +319,7 @@ CURVE_CASES = [
 @pytest.mark.parametrize("name,kind,n,m,k,margin,mode,split,seed", CURVE_CASES, ids=[c[0] for c in CURVE_CASES])
 def test_knn_curve_order_matches_plain_scan(gpu_lib, name, kind, n, m, k, margin, mode, split, seed):
     """The curve-ordered scans with projected-box pruning (Morton order, and
-    Morton order with median splits inside 64-tile groups) return the same
+    Morton order with median splits inside 4096-tile groups) return the same
     exact neighbour lists as the scan of every tile; on samples of low
     intrinsic dimension they evaluate fewer candidate pairs."""
     from paper_2104_15124_amd import kvb
@@ -352,7 +352,7 @@ def test_knn_curve_order_matches_plain_scan(gpu_lib, name, kind, n, m, k, margin
 
 def test_knn_median_splits_score_fewer_pairs(gpu_lib):
     """On the 4-dimensional mixture (the 8M workload's recipe at n = 500k) the
-    median splits inside the curve's 64-tile groups give tighter tile boxes:
+    median splits inside the curve's 4096-tile groups give tighter tile boxes:
     the exact scan scores at most 80% of the Morton order's pairs, with the
     same neighbour distances."""
     from paper_2104_15124_amd import kvb
