@@ -1,23 +1,24 @@
 // Exact k-NN selection over curve-ordered matrix-core tiles, pruned by a tree
 // of projected boxes (gfx950).
 //
-// The samples are laid out in the Morton order of their principal projections
-// (spatial_mfma.hip), so 32 consecutive curve positions form a compact tile
-// and 64 consecutive tiles (or tree nodes) form a compact node of the level
-// above. One wavefront owns one tile of 32 queries and works alone: no
-// workgroup barrier, no shared candidate stage. Its scan has two phases.
+// The samples are laid out in the Morton order of their principal projections,
+// refined by median splits inside groups of 4096 tiles (spatial_mfma.hip), so
+// 32 consecutive positions form a compact tile and 64 consecutive tiles (or
+// tree nodes) form a compact node of the level above. One wavefront owns one
+// tile of 32 queries and works alone: no workgroup barrier, no shared
+// candidate stage. Its scan has two phases.
 //
 // Fill. The CAP / 32 tiles around its own tile (CAP = the list capacity) are
 // scored and written into the query lists in global scratch, which are then
 // sorted once; each query's threshold is its list's kp-th score.
 //
-// Tree walk. Depth first from the top level: a node's (up to 64) children
-// are bounded at once, one per lane, against the wavefront's own query box
-// (the box of its tile), and a ballot against the wavefront's largest
-// distance threshold keeps those within reach. Children are taken in curve
-// order and re-tested against the current threshold when taken, so the walk
-// tightens as the lists improve; among the pending children the one with the
-// smallest bound is taken first, so the thresholds fall early. Every tile
+// Tree walk. From the top level down: a node's (up to 64) children are
+// bounded at once, one per lane, against the wavefront's own query box (the
+// box of its tile), and a ballot against the wavefront's largest distance
+// threshold keeps those within reach. Among a node's pending children the one
+// with the smallest bound is taken first (so the thresholds fall early), and
+// every child is re-tested against the current threshold when taken, so the
+// walk tightens as the lists improve. Every tile
 // reached is one 32 x 32 matrix-core product of the query fragments
 // (registers) and the candidate fragments (read from the tile-major operand;
 // the next tile's reads are issued before the current tile's products). A
