@@ -38,12 +38,32 @@
 namespace kvb {
 
 // ------------------------------------------------------------------ prep
-// Column sums (float64) over blocks of rows, then the fixed-order mean.
+// Column sums (float64) over blocks of rows, then the fixed-order mean. For
+// m <= 256 the block's threads form T = 256 / m row lanes of m columns: thread
+// (j, c) sums column c over rows r0 + j, r0 + j + T, ... (consecutive threads
+// read consecutive columns of a row), and the T partial sums of a column are
+// added in the order j = 0, 1, ... . Wider rows: one thread per column.
 __global__ __launch_bounds__(256) void k_colsum_partial(const float* __restrict__ X, int n, int m, int rows_per_block,
                                                         double* __restrict__ part)
 {
+    __shared__ double s_part[256];
     const int r0 = blockIdx.x * rows_per_block;
     const int r1 = min(n, r0 + rows_per_block);
+    if (m <= 256) {
+        const int T = 256 / m;
+        const int j = threadIdx.x / m, c = threadIdx.x % m;
+        double s = 0.0;
+        if (j < T)
+            for (int r = r0 + j; r < r1; r += T) s += static_cast<double>(X[static_cast<size_t>(r) * m + c]);
+        s_part[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x < m) {
+            double t = 0.0;
+            for (int q = 0; q < T; ++q) t += s_part[q * m + threadIdx.x];
+            part[static_cast<size_t>(blockIdx.x) * m + threadIdx.x] = t;
+        }
+        return;
+    }
     for (int c = threadIdx.x; c < m; c += blockDim.x) {
         double s = 0.0;
         for (int r = r0; r < r1; ++r) s += static_cast<double>(X[static_cast<size_t>(r) * m + c]);
@@ -51,9 +71,28 @@ __global__ __launch_bounds__(256) void k_colsum_partial(const float* __restrict_
     }
 }
 
+// The block partials of each column added in a fixed order: for m <= 256,
+// thread (j, c) sums the partials j, j + T, ... of column c, and the T sums
+// are added in the order j = 0, 1, ... .
 __global__ __launch_bounds__(256) void k_colsum_finish(const double* __restrict__ part, int nb, int m, int n,
                                                        double* __restrict__ mu)
 {
+    __shared__ double s_part[256];
+    if (m <= 256) {
+        const int T = 256 / m;
+        const int j = threadIdx.x / m, c = threadIdx.x % m;
+        double s = 0.0;
+        if (j < T)
+            for (int b = j; b < nb; b += T) s += part[static_cast<size_t>(b) * m + c];
+        s_part[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x < m) {
+            double t = 0.0;
+            for (int q = 0; q < T; ++q) t += s_part[q * m + threadIdx.x];
+            mu[threadIdx.x] = t / static_cast<double>(n);
+        }
+        return;
+    }
     for (int c = threadIdx.x; c < m; c += blockDim.x) {
         double s = 0.0;
         for (int b = 0; b < nb; ++b) s += part[static_cast<size_t>(b) * m + c];
@@ -178,6 +217,131 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
         }
     }
     if (lane == 0 && wmax > 0.f) atomicMax(rmax_bits, __float_as_uint(wmax));
+}
+
+// k_prep_rows for rows of at most PREP_THREAD_M coordinates, by operand row:
+// thread r prepares operand row r from sample cid[r] (cid null: sample r; a
+// negative entry or r >= n: a padding row of zeros), with the same values as
+// k_prep_rows (|y|^2 summed over the row in column order). Consecutive
+// threads then write consecutive query operand rows and, in the candidate
+// operand, whose k-step blocks hold 32 consecutive rows, consecutive
+// addresses.
+constexpr int PREP_THREAD_M = 64;
+
+__global__ __launch_bounds__(256) void k_prep_rows_thread(const float* __restrict__ X, int n, int npad, int m,
+                                                          const double* __restrict__ mu, int split, int kpad,
+                                                          void* __restrict__ Aq, void* __restrict__ Bc,
+                                                          float* __restrict__ ynorm2, unsigned* __restrict__ rmax_bits,
+                                                          const int* __restrict__ cid)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    float wmax = 0.f;
+    if (r < npad) {
+        const int i = r < n ? (cid ? cid[r] : r) : -1;
+        const bool real = i >= 0;
+        const int ib = r, ia = r;
+        const float* x = X + static_cast<size_t>(real ? i : 0) * m;
+        double nrm = 0.0;
+        if (split == 0) {
+            constexpr int KS = 2, VE = 1;
+            float* A = static_cast<float*>(Aq) + static_cast<size_t>(ia) * kpad;
+            float* B = static_cast<float*>(Bc);
+            const bool vec = (m % 4 == 0) && (kpad % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
+                             ((reinterpret_cast<uintptr_t>(Aq) & 15) == 0);
+            if (vec) {
+                for (int c = 0; c < m; c += 4) {
+                    const float4 xv = real ? *reinterpret_cast<const float4*>(x + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+                    float ys[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        ys[u] = real ? static_cast<float>(static_cast<double>(xs[u]) - mu[c + u]) : 0.0f;
+                        nrm += static_cast<double>(ys[u]) * static_cast<double>(ys[u]);
+                        B[bpos(ib, c + u, kpad, KS, VE)] = ys[u];
+                    }
+                    if (real)
+                        *reinterpret_cast<float4*>(A + c) = make_float4(-2.0f * ys[0], -2.0f * ys[1], -2.0f * ys[2],
+                                                                        -2.0f * ys[3]);
+                }
+                for (int c = m; c < kpad; c += 4) {
+                    float av[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        av[u] = (c + u == m) ? 1.0f : 0.0f;
+                        B[bpos(ib, c + u, kpad, KS, VE)] = (c + u == m) ? static_cast<float>(nrm) : 0.0f;
+                    }
+                    if (real) *reinterpret_cast<float4*>(A + c) = make_float4(av[0], av[1], av[2], av[3]);
+                }
+            } else {
+                for (int c = 0; c < m; ++c) {
+                    const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
+                    nrm += static_cast<double>(y) * static_cast<double>(y);
+                    if (real) A[c] = -2.0f * y;
+                    B[bpos(ib, c, kpad, KS, VE)] = y;
+                }
+                for (int c = m; c < kpad; ++c) {
+                    if (real) A[c] = (c == m) ? 1.0f : 0.0f;
+                    B[bpos(ib, c, kpad, KS, VE)] = (c == m) ? static_cast<float>(nrm) : 0.0f;
+                }
+            }
+        } else {
+            constexpr int KS = 16, VE = 8;
+            uint16_t* A = static_cast<uint16_t*>(Aq) + static_cast<size_t>(ia) * kpad;
+            uint16_t* B = static_cast<uint16_t*>(Bc);
+            for (int c = 0; c < m; ++c) {
+                const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
+                nrm += static_cast<double>(y) * static_cast<double>(y);
+                const uint16_t hi = f32_to_bf16_rne(y);
+                const float r1 = y - bf16_to_f32(hi);
+                const uint16_t mid = f32_to_bf16_rne(r1);
+                const float r2 = r1 - bf16_to_f32(mid);
+                const uint16_t lo = f32_to_bf16_rne(r2);
+                const uint16_t hi2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(hi));
+                const uint16_t mid2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(mid));
+                const uint16_t lo2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(lo));
+                uint16_t a[6], b[6];
+                int P = 1;
+                if (split == 1) {
+                    a[0] = hi2; b[0] = hi;
+                } else if (split == 3) {
+                    a[0] = hi2; b[0] = hi;
+                    a[1] = hi2; b[1] = mid;
+                    a[2] = mid2; b[2] = hi;
+                    P = 3;
+                } else {
+                    a[0] = hi2; b[0] = hi;
+                    a[1] = hi2; b[1] = mid;
+                    a[2] = mid2; b[2] = hi;
+                    a[3] = hi2; b[3] = lo;
+                    a[4] = lo2; b[4] = hi;
+                    a[5] = mid2; b[5] = mid;
+                    P = 6;
+                }
+                for (int t = 0; t < P; ++t) {
+                    if (real) A[t * m + c] = a[t];
+                    B[bpos(ib, t * m + c, kpad, KS, VE)] = b[t];
+                }
+            }
+            const int P = split;
+            const uint16_t n1 = f32_to_bf16_rne(static_cast<float>(nrm));
+            const double r1 = nrm - static_cast<double>(bf16_to_f32(n1));
+            const uint16_t n2 = f32_to_bf16_rne(static_cast<float>(r1));
+            const double r2 = r1 - static_cast<double>(bf16_to_f32(n2));
+            const uint16_t n3 = f32_to_bf16_rne(static_cast<float>(r2));
+            const uint16_t one = f32_to_bf16_rne(1.0f);
+            for (int c = P * m; c < kpad; ++c) {
+                const int t = c - P * m;
+                if (real) A[c] = t < 3 ? one : static_cast<uint16_t>(0);
+                B[bpos(ib, c, kpad, KS, VE)] = t == 0 ? n1 : t == 1 ? n2 : t == 2 ? n3 : static_cast<uint16_t>(0);
+            }
+        }
+        if (real) {
+            ynorm2[ia] = static_cast<float>(nrm);
+            wmax = static_cast<float>(sqrt(nrm) * (1.0 + 1e-6));
+        }
+    }
+    wmax = wave_max_f32(wmax);
+    if (lane_id() == 0 && wmax > 0.f) atomicMax(rmax_bits, __float_as_uint(wmax));
 }
 
 // ------------------------------------------------------------------ select
@@ -763,12 +927,37 @@ hipError_t launch_colmean(const float* X, int n, int m, double* colpart, int col
     return hipGetLastError();
 }
 
+// sample-order operand rows (no row maps): one thread per row for short rows
+static void launch_rows(const float* X, int n, int npad, int m, const double* mu, int split, int kpad, void* Aq,
+                        void* Bc, float* ynorm2, unsigned* rmax_bits, const int* brow, const int* arow, hipStream_t st)
+{
+    if (m <= PREP_THREAD_M && !brow && !arow)
+        hipLaunchKernelGGL(k_prep_rows_thread, dim3((npad + 255) / 256), dim3(256), 0, st, X, n, npad, m, mu, split,
+                           kpad, Aq, Bc, ynorm2, rmax_bits, nullptr);
+    else
+        hipLaunchKernelGGL(k_prep_rows, dim3(prep_blocks(npad)), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq,
+                           Bc, ynorm2, rmax_bits, brow, arow);
+}
+
 hipError_t launch_prep_rows(const float* X, int n, int m, const double* mu, int split, int kpad, void* Aq, void* Bc,
                             float* ynorm2, unsigned* rmax_bits, const int* brow, const int* arow, hipStream_t st)
 {
     const int npad = brow ? n : (n + 31) / 32 * 32;
-    hipLaunchKernelGGL(k_prep_rows, dim3(prep_blocks(npad)), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq, Bc,
-                       ynorm2, rmax_bits, brow, arow);
+    launch_rows(X, n, npad, m, mu, split, kpad, Aq, Bc, ynorm2, rmax_bits, brow, arow, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_rows_curve(const float* X, int n, int m, const double* mu, int split, int kpad, void* Aq,
+                                  void* Bc, float* ynorm2, unsigned* rmax_bits, const int* cid, const int* pos,
+                                  hipStream_t st)
+{
+    const int npad = (n + 31) / 32 * 32;
+    if (m <= PREP_THREAD_M)
+        hipLaunchKernelGGL(k_prep_rows_thread, dim3((npad + 255) / 256), dim3(256), 0, st, X, n, npad, m, mu, split,
+                           kpad, Aq, Bc, ynorm2, rmax_bits, cid);
+    else
+        hipLaunchKernelGGL(k_prep_rows, dim3(prep_blocks(npad)), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq,
+                           Bc, ynorm2, rmax_bits, pos, pos);
     return hipGetLastError();
 }
 
@@ -781,8 +970,7 @@ hipError_t launch_prep(const float* X, int n, int m, int split, int kpad, double
     const int npad = brow ? n : (n + 31) / 32 * 32;
     hipLaunchKernelGGL(k_colsum_partial, dim3(colblocks), dim3(256), 0, st, X, n, m, rpb, colpart);
     hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(256), 0, st, colpart, colblocks, m, n, mu);
-    hipLaunchKernelGGL(k_prep_rows, dim3(prep_blocks(npad)), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq, Bc,
-                       ynorm2, rmax_bits, brow, arow);
+    launch_rows(X, n, npad, m, mu, split, kpad, Aq, Bc, ynorm2, rmax_bits, brow, arow, st);
     return hipGetLastError();
 }
 

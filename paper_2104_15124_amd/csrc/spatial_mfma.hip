@@ -417,14 +417,18 @@ __global__ __launch_bounds__(KD_THREADS) void k_kd_local(int32_t* __restrict__ p
             s_key[p] = (static_cast<uint64_t>(seg) << 48) | (static_cast<uint64_t>(v) << 16) | static_cast<uint64_t>(o);
         }
         __syncthreads();
-        // ascending bitonic sort of the group's keys (PAD keys sort last)
-        for (int k = 2; k <= KD_GROUP; k <<= 1) {
+        // ascending bitonic sort of each segment's keys (a segment's keys share
+        // its high bits, so sorting the segments sorts the group; PAD keys sort
+        // last): the networks of size seg_size, the last merge ascending in
+        // every segment
+        const int seg_size = 1 << shift;
+        for (int k = 2; k <= seg_size; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
                 for (int t = tid; t < KD_GROUP / 2; t += KD_THREADS) {
                     const int i = 2 * t - (t & (j - 1));
                     const int q = i + j;
                     const uint64_t a = s_key[i], b = s_key[q];
-                    const bool up = (i & k) == 0;
+                    const bool up = k == seg_size || (i & k) == 0;
                     if ((a > b) == up) {
                         s_key[i] = b;
                         s_key[q] = a;
@@ -440,69 +444,33 @@ __global__ __launch_bounds__(KD_THREADS) void k_kd_local(int32_t* __restrict__ p
 // The same halving for the levels above: groups of KG_GROUP consecutive curve
 // positions (4096 tiles) are halved along the widest side of each segment's
 // box down to segments of KD_GROUP positions, which k_kd_local then finishes.
-// One workgroup of 1024 threads per group; the segments' arrangements (local
-// indices into the group's curve order, whose coordinates zs never move) live
-// in two global buffers used in turn. A level: the segments' boxes (LDS
-// atomics on order bits), a histogram of each segment's widest coordinate
-// over KG_BINS bins of its extent, the bin holding the segment's middle rank,
-// then every element placed by prefix sums over the threads (so the result
-// does not depend on the timing of the atomics): the elements of the lower
-// bins first, then those of the middle bin up to the middle position, the rest
-// of that bin after it, the upper bins last. Within a segment the order of a
-// side is that of the previous level.
+// One workgroup of 16 wavefronts per group; wavefront w owns the positions
+// [w KG_WPOS, (w + 1) KG_WPOS) of the group, lane l the ones congruent to l
+// mod 64 (loads and stores of consecutive lanes are consecutive), and a
+// wavefront's positions lie in one segment at every level. The segments'
+// arrangements (local indices into the group's curve order, whose coordinates
+// zs never move) live in two global buffers used in turn. A level: the
+// segments' boxes (wavefront reductions, then LDS atomics on order bits), a
+// histogram of each segment's widest coordinate over KG_BINS bins of its
+// extent, the bin holding the segment's middle rank, then every element
+// placed in the order (wavefront, position): the elements of the lower bins
+// first, then those of the middle bin up to the middle position, the rest of
+// that bin after it, the upper bins last; ranks come from ballots, so the
+// result does not depend on the timing of the atomics.
 constexpr int KG_LOG = 17;
 constexpr int KG_GROUP = 1 << KG_LOG;
 constexpr int KG_LEVELS = KG_LOG - KD_LOG;
 constexpr int KG_THREADS = 1024;
-constexpr int KG_PER = KG_GROUP / KG_THREADS;   // consecutive positions per thread (one segment)
+constexpr int KG_WAVES = KG_THREADS / WAVE;
+constexpr int KG_WPOS = KG_GROUP / KG_WAVES;    // 8192 positions per wavefront
 constexpr int KG_BINS = 1024;
 constexpr int KG_SEGS = 1 << (KG_LEVELS - 1);
-constexpr int KG_WAVES = KG_THREADS / WAVE;
-
-// exclusive prefix sum of v over the workgroup (thread order); *total: the sum
-__device__ __forceinline__ int kg_exclusive_scan(int v, int* s_w, int* total)
-{
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        const int y = __shfl_up(x, o, WAVE);
-        if (lane >= o) x += y;
-    }
-    if (lane == WAVE - 1) s_w[w] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int i = 0; i < KG_WAVES; ++i) {
-            const int t = s_w[i];
-            s_w[i] = acc;
-            acc += t;
-        }
-        s_w[KG_WAVES] = acc;
-    }
-    __syncthreads();
-    const int r = s_w[w] + x - v;
-    *total = s_w[KG_WAVES];
-    __syncthreads();
-    return r;
-}
+constexpr int KG_U = 4;                         // positions per lane in flight
 
 __device__ __forceinline__ int kg_bin(float v, float lo, float scale)
 {
     const int b = static_cast<int>((v - lo) * scale);
     return b < 0 ? 0 : (b >= KG_BINS ? KG_BINS - 1 : b);
-}
-
-// The arrangement entries of positions [p, p + KG_B) (those below pe) and
-// their coordinate on side d, loaded together so that their latencies overlap.
-constexpr int KG_B = 8;
-__device__ __forceinline__ void kg_load_side(const int32_t* __restrict__ cur, const float* __restrict__ zs, int g0,
-                                             int p, int pe, int d, int (&o)[KG_B], float (&v)[KG_B])
-{
-#pragma unroll
-    for (int u = 0; u < KG_B; ++u) o[u] = p + u < pe ? cur[p + u] : 0;
-#pragma unroll
-    for (int u = 0; u < KG_B; ++u) v[u] = p + u < pe ? zs[static_cast<size_t>(g0 + o[u]) * PR_DIMS + d] : 0.f;
 }
 
 __global__ __launch_bounds__(KG_THREADS) void k_kd_group(const int32_t* __restrict__ perm,
@@ -514,22 +482,22 @@ __global__ __launch_bounds__(KG_THREADS) void k_kd_group(const int32_t* __restri
     __shared__ int s_dim[KG_SEGS];
     __shared__ int s_hist[KG_SEGS][KG_BINS];
     __shared__ int s_bstar[KG_SEGS], s_below[KG_SEGS], s_take[KG_SEGS], s_cmed[KG_SEGS];
-    __shared__ int s_base[KG_SEGS][3];
-    __shared__ int s_w[KG_WAVES + 1];
+    __shared__ int s_wcnt[KG_WAVES][3];
     const int tid = threadIdx.x;
+    const int lane = tid % WAVE, w = tid / WAVE;
     const int g0 = blockIdx.x * KG_GROUP;
     const int m = min(KG_GROUP, n - g0);
-    const int p0 = tid * KG_PER;
-    const int pe = min(p0 + KG_PER, m);   // this thread's real positions [p0, pe)
+    const int wb = w * KG_WPOS;   // this wavefront's first position
+    const uint64_t below_me = (1ull << lane) - 1ull;
     int32_t* cur = ord_a + g0;
     int32_t* nxt = ord_b + g0;
-    for (int p = p0; p < pe; ++p) cur[p] = p;
+    for (int p = wb + lane; p < min(wb + KG_WPOS, m); p += WAVE) cur[p] = p;
     __syncthreads();
     for (int l = 0; l < KG_LEVELS; ++l) {
         const int shift = KG_LOG - l;   // position >> shift = segment
         const int S = 1 << shift, H = S >> 1;
         const int nseg = 1 << l;
-        const int seg = p0 >> shift;
+        const int seg = wb >> shift;
         const int s0 = seg << shift;
         for (int e = tid; e < nseg * PR_DIMS; e += KG_THREADS) {
             s_lo[e / PR_DIMS][e % PR_DIMS] = ~0u;
@@ -544,29 +512,26 @@ __global__ __launch_bounds__(KG_THREADS) void k_kd_group(const int32_t* __restri
                 lo[c] = ~0u;
                 hi[c] = 0u;
             }
-            for (int p = p0; p < pe; p += KG_B) {
-                int o[KG_B];
+            for (int p = wb + lane; p < min(wb + KG_WPOS, m); p += WAVE) {
+                const float4* z = reinterpret_cast<const float4*>(zs + static_cast<size_t>(g0 + cur[p]) * PR_DIMS);
+                const float4 za = z[0], zb = z[1];
+                const float zv[PR_DIMS] = {za.x, za.y, za.z, za.w, zb.x, zb.y, zb.z, zb.w};
 #pragma unroll
-                for (int u = 0; u < KG_B; ++u) o[u] = p + u < pe ? cur[p + u] : cur[p];
-                float4 za[KG_B], zb[KG_B];
-#pragma unroll
-                for (int u = 0; u < KG_B; ++u) {
-                    const float4* z = reinterpret_cast<const float4*>(zs + static_cast<size_t>(g0 + o[u]) * PR_DIMS);
-                    za[u] = z[0];
-                    zb[u] = z[1];
-                }
-#pragma unroll
-                for (int u = 0; u < KG_B; ++u) {
-                    const float zv[PR_DIMS] = {za[u].x, za[u].y, za[u].z, za[u].w, zb[u].x, zb[u].y, zb[u].z, zb[u].w};
-#pragma unroll
-                    for (int c = 0; c < PR_DIMS; ++c) {
-                        const uint32_t v = float_order_bits(zv[c]);
-                        lo[c] = min(lo[c], v);
-                        hi[c] = max(hi[c], v);
-                    }
+                for (int c = 0; c < PR_DIMS; ++c) {
+                    const uint32_t v = float_order_bits(zv[c]);
+                    lo[c] = min(lo[c], v);
+                    hi[c] = max(hi[c], v);
                 }
             }
-            if (pe > p0) {
+#pragma unroll
+            for (int c = 0; c < PR_DIMS; ++c) {
+#pragma unroll
+                for (int o = 1; o < WAVE; o <<= 1) {
+                    lo[c] = min(lo[c], xor_lane(lo[c], o));
+                    hi[c] = max(hi[c], xor_lane(hi[c], o));
+                }
+            }
+            if (lane == 0 && wb < m) {
 #pragma unroll
                 for (int c = 0; c < PR_DIMS; ++c) {
                     atomicMin(&s_lo[seg][c], lo[c]);
@@ -579,10 +544,10 @@ __global__ __launch_bounds__(KG_THREADS) void k_kd_group(const int32_t* __restri
             int best = 0;
             float wbest = -1.f;
             for (int c = 0; c < PR_DIMS; ++c) {
-                const float w = s_hi[tid][c] >= s_lo[tid][c]
-                                    ? order_bits_float(s_hi[tid][c]) - order_bits_float(s_lo[tid][c]) : -1.f;
-                if (w > wbest) {
-                    wbest = w;
+                const float wd = s_hi[tid][c] >= s_lo[tid][c]
+                                     ? order_bits_float(s_hi[tid][c]) - order_bits_float(s_lo[tid][c]) : -1.f;
+                if (wd > wbest) {
+                    wbest = wd;
                     best = c;
                 }
             }
@@ -591,14 +556,23 @@ __global__ __launch_bounds__(KG_THREADS) void k_kd_group(const int32_t* __restri
         __syncthreads();
         const int d = s_dim[seg];
         const float lo = order_bits_float(s_lo[seg][d]), hi = order_bits_float(s_hi[seg][d]);
-        const float scale = (pe > p0 && hi > lo) ? static_cast<float>(KG_BINS) / (hi - lo) : 0.f;
-        for (int p = p0; p < pe; p += KG_B) {
-            int o[KG_B];
-            float v[KG_B];
-            kg_load_side(cur, zs, g0, p, pe, d, o, v);
+        const float scale = hi > lo ? static_cast<float>(KG_BINS) / (hi - lo) : 0.f;
+        const int pe = min(wb + KG_WPOS, m);
+        // the coordinate on side d of the positions p, p + 64, ... (KG_U of them)
+        auto side = [&](int p, int (&o)[KG_U], float (&v)[KG_U]) {
 #pragma unroll
-            for (int u = 0; u < KG_B; ++u)
-                if (p + u < pe) atomicAdd(&s_hist[seg][kg_bin(v[u], lo, scale)], 1);
+            for (int u = 0; u < KG_U; ++u) o[u] = p + u * WAVE < pe ? cur[p + u * WAVE] : 0;
+#pragma unroll
+            for (int u = 0; u < KG_U; ++u)
+                v[u] = p + u * WAVE < pe ? zs[static_cast<size_t>(g0 + o[u]) * PR_DIMS + d] : 0.f;
+        };
+        for (int p = wb + lane; p < pe; p += KG_U * WAVE) {
+            int o[KG_U];
+            float v[KG_U];
+            side(p, o, v);
+#pragma unroll
+            for (int u = 0; u < KG_U; ++u)
+                if (p + u * WAVE < pe) atomicAdd(&s_hist[seg][kg_bin(v[u], lo, scale)], 1);
         }
         __syncthreads();
         if (tid < nseg) {
@@ -622,52 +596,60 @@ __global__ __launch_bounds__(KG_THREADS) void k_kd_group(const int32_t* __restri
         }
         __syncthreads();
         const int bs = s_bstar[seg];
-        int cl = 0, cm = 0, cr = 0;
-        for (int p = p0; p < pe; p += KG_B) {
-            int o[KG_B];
-            float v[KG_B];
-            kg_load_side(cur, zs, g0, p, pe, d, o, v);
+        // this wavefront's count of each class (wave-uniform)
+        int nl = 0, nm = 0, nr = 0;
+        for (int p = wb + lane; p - lane < pe; p += KG_U * WAVE) {
+            int o[KG_U];
+            float v[KG_U];
+            side(p, o, v);
 #pragma unroll
-            for (int u = 0; u < KG_B; ++u)
-                if (p + u < pe) {
-                    const int b = kg_bin(v[u], lo, scale);
-                    cl += b < bs;
-                    cm += b == bs;
-                    cr += b > bs;
-                }
+            for (int u = 0; u < KG_U; ++u) {
+                const bool in = p + u * WAVE < pe;
+                const int b = kg_bin(v[u], lo, scale);
+                nl += __popcll(__ballot(in && b < bs));
+                nm += __popcll(__ballot(in && b == bs));
+                nr += __popcll(__ballot(in && b > bs));
+            }
         }
-        int tot;
-        int xl = kg_exclusive_scan(cl, s_w, &tot);
-        int xm = kg_exclusive_scan(cm, s_w, &tot);
-        int xr = kg_exclusive_scan(cr, s_w, &tot);
-        if (p0 == s0) {
-            s_base[seg][0] = xl;
-            s_base[seg][1] = xm;
-            s_base[seg][2] = xr;
+        if (lane == 0) {
+            s_wcnt[w][0] = nl;
+            s_wcnt[w][1] = nm;
+            s_wcnt[w][2] = nr;
         }
         __syncthreads();
-        xl -= s_base[seg][0];
-        xm -= s_base[seg][1];
-        xr -= s_base[seg][2];
+        // ranks: the wavefronts of the segment before this one, then this one's running counts
+        int xl = 0, xm = 0, xr = 0;
+        for (int q = s0 / KG_WPOS; q < w; ++q) {
+            xl += s_wcnt[q][0];
+            xm += s_wcnt[q][1];
+            xr += s_wcnt[q][2];
+        }
         const int below = s_below[seg], take = s_take[seg], cmed = s_cmed[seg];
-        for (int p = p0; p < pe; p += KG_B) {
-            int o[KG_B];
-            float v[KG_B];
-            kg_load_side(cur, zs, g0, p, pe, d, o, v);
+        for (int p = wb + lane; p - lane < pe; p += KG_U * WAVE) {
+            int o[KG_U];
+            float v[KG_U];
+            side(p, o, v);
 #pragma unroll
-            for (int u = 0; u < KG_B; ++u) {
-                if (p + u >= pe) continue;
+            for (int u = 0; u < KG_U; ++u) {
+                const bool in = p + u * WAVE < pe;
                 const int b = kg_bin(v[u], lo, scale);
-                int q;
-                if (b < bs) {
-                    q = s0 + xl++;
-                } else if (b == bs) {
-                    const int r = xm++;
-                    q = r < take ? s0 + below + r : s0 + H + (r - take);
-                } else {
-                    q = s0 + H + (cmed - take) + xr++;
+                const uint64_t ml = __ballot(in && b < bs), mm = __ballot(in && b == bs),
+                               mr = __ballot(in && b > bs);
+                if (in) {
+                    int q;
+                    if (b < bs) {
+                        q = s0 + xl + __popcll(ml & below_me);
+                    } else if (b == bs) {
+                        const int r = xm + __popcll(mm & below_me);
+                        q = r < take ? s0 + below + r : s0 + H + (r - take);
+                    } else {
+                        q = s0 + H + (cmed - take) + xr + __popcll(mr & below_me);
+                    }
+                    nxt[q] = o[u];
                 }
-                nxt[q] = o[u];
+                xl += __popcll(ml);
+                xm += __popcll(mm);
+                xr += __popcll(mr);
             }
         }
         __syncthreads();
@@ -675,7 +657,7 @@ __global__ __launch_bounds__(KG_THREADS) void k_kd_group(const int32_t* __restri
         cur = nxt;
         nxt = t;
     }
-    for (int p = p0; p < pe; ++p) perm_out[g0 + p] = perm[g0 + cur[p]];
+    for (int p = wb + lane; p < min(wb + KG_WPOS, m); p += WAVE) perm_out[g0 + p] = perm[g0 + cur[p]];
 }
 
 // ------------------------------------------------------------------ launchers
