@@ -395,6 +395,68 @@ __device__ __forceinline__ float comp_dist2(const float* __restrict__ a, const f
     return acc.s + acc.c;
 }
 
+// comp_dist2 of row a against rows b_s = B + j_s m (where act_s), the terms
+// added in the same order; the coordinates are read 16 at a time (float4
+// pieces when vec4; 8 for four key slots), so that a chunk's loads are in
+// flight together.
+template <int E>
+__device__ __forceinline__ void comp_dist2_rows(const float* __restrict__ a, const float* __restrict__ B, int m,
+                                                const int (&j)[E], const bool (&act)[E], bool vec4, float (&out)[E])
+{
+    constexpr int CH = E >= 4 ? 8 : 16;   // coordinates per chunk
+    CompF32 acc[E];
+    for (int c0 = 0; c0 < m; c0 += CH) {
+        float av[CH], bv[E][CH];
+        if (vec4) {
+#pragma unroll
+            for (int u = 0; u < CH / 4; ++u) {
+                if (c0 + 4 * u < m) {
+                    const float4 q = *reinterpret_cast<const float4*>(a + c0 + 4 * u);
+                    av[4 * u] = q.x;
+                    av[4 * u + 1] = q.y;
+                    av[4 * u + 2] = q.z;
+                    av[4 * u + 3] = q.w;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const float* b = B + static_cast<size_t>(j[s]) * m;
+#pragma unroll
+                for (int u = 0; u < CH / 4; ++u) {
+                    if (act[s] && c0 + 4 * u < m) {
+                        const float4 q = *reinterpret_cast<const float4*>(b + c0 + 4 * u);
+                        bv[s][4 * u] = q.x;
+                        bv[s][4 * u + 1] = q.y;
+                        bv[s][4 * u + 2] = q.z;
+                        bv[s][4 * u + 3] = q.w;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < CH; ++t)
+                if (c0 + t < m) av[t] = a[c0 + t];
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const float* b = B + static_cast<size_t>(j[s]) * m;
+#pragma unroll
+                for (int t = 0; t < CH; ++t)
+                    if (act[s] && c0 + t < m) bv[s][t] = b[c0 + t];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            if (c0 + t < m) {
+#pragma unroll
+                for (int s = 0; s < E; ++s)
+                    if (act[s]) comp_sqdiff_add(acc[s], av[t], bv[s][t]);
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < E; ++s) out[s] = acc[s].s + acc[s].c;
+}
+
 __device__ __forceinline__ double dist2_f64(const float* __restrict__ a, const float* __restrict__ b, int m)
 {
     double s = 0.0;
@@ -533,19 +595,26 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
         if (ps < 0 && mm) ps = s * WAVE + __builtin_ctzll(mm);
     }
     if constexpr (LPC == 0) {
+        int jr[E];
+        bool act[E];
 #pragma unroll
         for (int s = 0; s < E; ++s) {
-            uint64_t key = v[s];
-            if (key != KEY_INF) {
-                const uint32_t j = key_idx(key);
-                if (static_cast<int>(j) == r)
-                    key = KEY_INF;
-                else if constexpr (CV)
-                    key = make_key(comp_dist2(xi, Xs + static_cast<size_t>(j) * m, m), static_cast<uint32_t>(perm[j]));
-                else
-                    key = make_key(comp_dist2(xi, X + static_cast<size_t>(j) * m, m), j);
-            }
-            v[s] = key;
+            act[s] = v[s] != KEY_INF && static_cast<int>(key_idx(v[s])) != r;
+            jr[s] = act[s] ? static_cast<int>(key_idx(v[s])) : 0;
+        }
+        const float* Br = CV ? Xs : X;   // the rows the keys refer to
+        const bool vec4 = (m % 4 == 0) && ((reinterpret_cast<uintptr_t>(Br) & 15) == 0);
+        float dd[E];
+        comp_dist2_rows<E>(xi, Br, m, jr, act, vec4, dd);
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            if (v[s] == KEY_INF) continue;
+            if (!act[s])
+                v[s] = KEY_INF;
+            else if constexpr (CV)
+                v[s] = make_key(dd[s], static_cast<uint32_t>(perm[jr[s]]));
+            else
+                v[s] = make_key(dd[s], static_cast<uint32_t>(jr[s]));
         }
     } else {
         double dd[E];
