@@ -388,17 +388,10 @@ __global__ __launch_bounds__(256) void k_group_boxes(const float* __restrict__ s
 }
 
 // -------------------------------------------------------------------- refine
-__device__ __forceinline__ float comp_dist2(const float* __restrict__ a, const float* __restrict__ b, int m)
-{
-    CompF32 acc;
-    for (int c = 0; c < m; ++c) comp_sqdiff_add(acc, a[c], b[c]);
-    return acc.s + acc.c;
-}
-
-// comp_dist2 of row a against rows b_s = B + j_s m (where act_s), the terms
-// added in the same order; the coordinates are read 16 at a time (float4
-// pieces when vec4; 8 for four key slots), so that a chunk's loads are in
-// flight together.
+// Compensated squared distances (CompF32, comp_sqdiff_add over the columns in
+// order) of row a to the rows b_s = B + j_s m (where act_s); the coordinates
+// are read 16 at a time (float4 pieces when vec4; 8 for four key slots), so
+// that a chunk's loads are in flight together.
 template <int E>
 __device__ __forceinline__ void comp_dist2_rows(const float* __restrict__ a, const float* __restrict__ B, int m,
                                                 const int (&j)[E], const bool (&act)[E], bool vec4, float (&out)[E])

@@ -219,7 +219,9 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
     if (lane == 0 && wmax > 0.f) atomicMax(rmax_bits, __float_as_uint(wmax));
 }
 
-// k_prep_rows for rows of at most PREP_THREAD_M coordinates, by operand row:
+// k_prep_rows for FP32 operands of rows of at most PREP_THREAD_M coordinates,
+// by operand row (the BF16 split terms stay with the wavefront per row, whose
+// 2-byte query operand writes coalesce):
 // thread r prepares operand row r from sample cid[r] (cid null: sample r; a
 // negative entry or r >= n: a padding row of zeros), with the same values as
 // k_prep_rows (|y|^2 summed over the row in column order). Consecutive
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(256) void k_prep_rows_thread(const float* __restric
         const int ib = r, ia = r;
         const float* x = X + static_cast<size_t>(real ? i : 0) * m;
         double nrm = 0.0;
-        if (split == 0) {
+        {
             constexpr int KS = 2, VE = 1;
             float* A = static_cast<float*>(Aq) + static_cast<size_t>(ia) * kpad;
             float* B = static_cast<float*>(Bc);
@@ -283,56 +285,6 @@ __global__ __launch_bounds__(256) void k_prep_rows_thread(const float* __restric
                     if (real) A[c] = (c == m) ? 1.0f : 0.0f;
                     B[bpos(ib, c, kpad, KS, VE)] = (c == m) ? static_cast<float>(nrm) : 0.0f;
                 }
-            }
-        } else {
-            constexpr int KS = 16, VE = 8;
-            uint16_t* A = static_cast<uint16_t*>(Aq) + static_cast<size_t>(ia) * kpad;
-            uint16_t* B = static_cast<uint16_t*>(Bc);
-            for (int c = 0; c < m; ++c) {
-                const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
-                nrm += static_cast<double>(y) * static_cast<double>(y);
-                const uint16_t hi = f32_to_bf16_rne(y);
-                const float r1 = y - bf16_to_f32(hi);
-                const uint16_t mid = f32_to_bf16_rne(r1);
-                const float r2 = r1 - bf16_to_f32(mid);
-                const uint16_t lo = f32_to_bf16_rne(r2);
-                const uint16_t hi2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(hi));
-                const uint16_t mid2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(mid));
-                const uint16_t lo2 = f32_to_bf16_rne(-2.0f * bf16_to_f32(lo));
-                uint16_t a[6], b[6];
-                int P = 1;
-                if (split == 1) {
-                    a[0] = hi2; b[0] = hi;
-                } else if (split == 3) {
-                    a[0] = hi2; b[0] = hi;
-                    a[1] = hi2; b[1] = mid;
-                    a[2] = mid2; b[2] = hi;
-                    P = 3;
-                } else {
-                    a[0] = hi2; b[0] = hi;
-                    a[1] = hi2; b[1] = mid;
-                    a[2] = mid2; b[2] = hi;
-                    a[3] = hi2; b[3] = lo;
-                    a[4] = lo2; b[4] = hi;
-                    a[5] = mid2; b[5] = mid;
-                    P = 6;
-                }
-                for (int t = 0; t < P; ++t) {
-                    if (real) A[t * m + c] = a[t];
-                    B[bpos(ib, t * m + c, kpad, KS, VE)] = b[t];
-                }
-            }
-            const int P = split;
-            const uint16_t n1 = f32_to_bf16_rne(static_cast<float>(nrm));
-            const double r1 = nrm - static_cast<double>(bf16_to_f32(n1));
-            const uint16_t n2 = f32_to_bf16_rne(static_cast<float>(r1));
-            const double r2 = r1 - static_cast<double>(bf16_to_f32(n2));
-            const uint16_t n3 = f32_to_bf16_rne(static_cast<float>(r2));
-            const uint16_t one = f32_to_bf16_rne(1.0f);
-            for (int c = P * m; c < kpad; ++c) {
-                const int t = c - P * m;
-                if (real) A[c] = t < 3 ? one : static_cast<uint16_t>(0);
-                B[bpos(ib, c, kpad, KS, VE)] = t == 0 ? n1 : t == 1 ? n2 : t == 2 ? n3 : static_cast<uint16_t>(0);
             }
         }
         if (real) {
@@ -931,7 +883,7 @@ hipError_t launch_colmean(const float* X, int n, int m, double* colpart, int col
 static void launch_rows(const float* X, int n, int npad, int m, const double* mu, int split, int kpad, void* Aq,
                         void* Bc, float* ynorm2, unsigned* rmax_bits, const int* brow, const int* arow, hipStream_t st)
 {
-    if (m <= PREP_THREAD_M && !brow && !arow)
+    if (m <= PREP_THREAD_M && split == 0 && !brow && !arow)
         hipLaunchKernelGGL(k_prep_rows_thread, dim3((npad + 255) / 256), dim3(256), 0, st, X, n, npad, m, mu, split,
                            kpad, Aq, Bc, ynorm2, rmax_bits, nullptr);
     else
@@ -952,7 +904,7 @@ hipError_t launch_prep_rows_curve(const float* X, int n, int m, const double* mu
                                   hipStream_t st)
 {
     const int npad = (n + 31) / 32 * 32;
-    if (m <= PREP_THREAD_M)
+    if (m <= PREP_THREAD_M && split == 0)
         hipLaunchKernelGGL(k_prep_rows_thread, dim3((npad + 255) / 256), dim3(256), 0, st, X, n, npad, m, mu, split,
                            kpad, Aq, Bc, ynorm2, rmax_bits, cid);
     else
