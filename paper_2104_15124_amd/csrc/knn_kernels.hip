@@ -1146,7 +1146,9 @@ hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstrid
                          const int32_t* perm, hipStream_t st)
 {
     // rows of up to 24 floats stay with one lane per candidate; longer rows are
-    // read by groups of lanes (each lane covers at most 4 float4 pieces)
+    // read by groups of lanes, each lane covering up to 4 float4 pieces (the
+    // fewest lanes per candidate: more candidates per pass, fewer passes and
+    // shorter group reductions)
 #define KVB_REFINE(LPC)                                                                                              \
     do {                                                                                                              \
         if (perm)                                                                                                     \
@@ -1159,9 +1161,11 @@ hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstrid
     if (m <= 24)
         KVB_REFINE(0);
     else if (m <= 64)
-        KVB_REFINE(16);
+        KVB_REFINE(4);
     else if (m <= 128)
-        KVB_REFINE(32);
+        KVB_REFINE(8);
+    else if (m <= 256)
+        KVB_REFINE(16);
     else if (m <= 1024)
         KVB_REFINE(64);
     else
