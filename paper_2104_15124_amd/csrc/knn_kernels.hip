@@ -390,13 +390,13 @@ __global__ __launch_bounds__(256) void k_group_boxes(const float* __restrict__ s
 // -------------------------------------------------------------------- refine
 // Compensated squared distances (CompF32, comp_sqdiff_add over the columns in
 // order) of row a to the rows b_s = B + j_s m (where act_s); the coordinates
-// are read 16 at a time (float4 pieces when vec4; 8 for four key slots), so
-// that a chunk's loads are in flight together.
-template <int E>
-__device__ __forceinline__ void comp_dist2_rows(const float* __restrict__ a, const float* __restrict__ B, int m,
-                                                const int (&j)[E], const bool (&act)[E], bool vec4, float (&out)[E])
+// are read CH at a time (float4 pieces when vec4), so that a chunk's loads
+// are in flight together.
+template <int E, int CH>
+__device__ __forceinline__ void comp_dist2_rows_ch(const float* __restrict__ a, const float* __restrict__ B, int m,
+                                                   const int (&j)[E], const bool (&act)[E], bool vec4,
+                                                   float (&out)[E])
 {
-    constexpr int CH = E >= 4 ? 8 : 16;   // coordinates per chunk
     CompF32 acc[E];
     for (int c0 = 0; c0 < m; c0 += CH) {
         float av[CH], bv[E][CH];
@@ -448,6 +448,19 @@ __device__ __forceinline__ void comp_dist2_rows(const float* __restrict__ a, con
     }
 #pragma unroll
     for (int s = 0; s < E; ++s) out[s] = acc[s].s + acc[s].c;
+}
+
+// the chunk fitted to m (8 coordinates at most for four key slots)
+template <int E>
+__device__ __forceinline__ void comp_dist2_rows(const float* __restrict__ a, const float* __restrict__ B, int m,
+                                                const int (&j)[E], const bool (&act)[E], bool vec4, float (&out)[E])
+{
+    if (m <= 4)
+        comp_dist2_rows_ch<E, 4>(a, B, m, j, act, vec4, out);
+    else if (m <= 8 || E >= 4)
+        comp_dist2_rows_ch<E, 8>(a, B, m, j, act, vec4, out);
+    else
+        comp_dist2_rows_ch<E, 16>(a, B, m, j, act, vec4, out);
 }
 
 __device__ __forceinline__ double dist2_f64(const float* __restrict__ a, const float* __restrict__ b, int m)
