@@ -46,9 +46,9 @@ constexpr int TNQ = 32;      // queries per wavefront
 // one wavefront's LDS state
 struct TreeLds {
     uint64_t buf[TNQ][TBUF];            // per-query buffers of appended keys
-    int cnt[TNQ];                       // their fill
     float tau[TNQ];                     // score thresholds (the lists' kp-th scores; -inf: no query)
     float yq[TNQ];                      // |y_q|^2
+    float thr[TNQ];                     // distance thresholds (score + |y_q|^2, rounded up)
     float box[2 * PR_DIMS];             // the query tile's box
     float bnd[TREE_LEVELS - 1][WAVE];   // walk: bounds of the pending children of level l >= 1 in row l - 1
     uint64_t mask[TREE_LEVELS];         //       pending children
@@ -213,7 +213,6 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
     if (lane < 2 * PR_DIMS) W.box[lane] = crv.tbox[static_cast<size_t>(t0) * 2 * PR_DIMS + lane];
     if (lane < TNQ) {
         W.yq[lane] = q0 + lane < n ? ynorm2[q0 + lane] : 0.f;
-        W.cnt[lane] = 0;
         W.tau[lane] = -INF;
     }
     wave_lds_sync();
@@ -273,11 +272,16 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
     }
     wave_lds_sync();
 
-    // the wavefront's largest distance threshold (score + |y_q|^2, rounded up)
+    // each query's distance threshold (score + |y_q|^2, rounded up) and the
+    // wavefront's largest
+    auto dist_threshold = [](float score, float yq) { return fmaxf(score + yq, 0.f) * (1.f + 4.8e-7f); };
+    if (lane < TNQ) W.thr[lane] = lane < nq_valid ? dist_threshold(W.tau[lane], W.yq[lane]) : -INF;
+    wave_lds_sync();
+    // (read from one lane, so that the compiler sees a wave-uniform value and
+    // keeps the branches on it, and the state they update, scalar)
     auto wave_threshold = [&]() {
-        float t = -INF;
-        if (lane < nq_valid) t = fmaxf(W.tau[lane] + W.yq[lane], 0.f) * (1.f + 4.8e-7f);
-        return wave_max_f32(t);
+        const float t = wave_max_f32(lane < TNQ ? W.thr[lane] : -INF);
+        return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t)));
     };
     float wthr = wave_threshold();
 
@@ -319,7 +323,12 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
     float tauv[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) tauv[r] = W.tau[acc_row(r, half)];
-    uint32_t nonempty = 0;   // queries with buffered entries (wave-uniform)
+    // the buffers' fill, wave-uniform: query q's count in byte q % 4 of cntw[q / 4]
+    // (every index below is a compile-time constant, so they stay in scalar registers)
+    uint32_t cntw[TNQ / 4];
+#pragma unroll
+    for (int i = 0; i < TNQ / 4; ++i) cntw[i] = 0u;
+    auto cnt_of = [&](int q) { return static_cast<int>((cntw[q >> 2] >> (8 * (q & 3))) & 0xFFu); };
     bool thr_dirty = false;
     float tb_cur = 0.f, tb_nxt = 0.f;
     int cur = next_tile(wthr, tb_cur);
@@ -327,13 +336,7 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
     if (cur >= 0) load_tile(cur, bcur);
     while (cur >= 0) {
         if (thr_dirty) {
-            float t = -INF;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int qi = acc_row(r, half);
-                if (qi < nq_valid) t = fmaxf(t, fmaxf(tauv[r] + W.yq[qi], 0.f) * (1.f + 4.8e-7f));
-            }
-            wthr = wave_max_f32(t);
+            wthr = wave_threshold();
             thr_dirty = false;
         }
         const int nxt = next_tile(wthr, tb_nxt);
@@ -354,10 +357,9 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
                     uint64_t mask = __ballot(valid && sc <= tauv[r]);
                     if (!mask) continue;
                     const int qa_ = acc_row(r, 0), qb_ = acc_row(r, 1);
-                    uint32_t ma = static_cast<uint32_t>(mask), mb = static_cast<uint32_t>(mask >> 32);
-                    int ca = ma ? W.cnt[qa_] : 0;
-                    int cb = mb ? W.cnt[qb_] : 0;
-                    const bool fa = ca + __popc(ma) > TBUF, fb = cb + __popc(mb) > TBUF;
+                    int ca = cnt_of(qa_), cb = cnt_of(qb_);
+                    const bool fa = ca + __popc(static_cast<uint32_t>(mask)) > TBUF;
+                    const bool fb = cb + __popc(static_cast<uint32_t>(mask >> 32)) > TBUF;
                     if (fa || fb) {
                         // a full buffer is merged before this tile's keys are added
                         wave_lds_sync();
@@ -365,32 +367,29 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
                             const float nt = merge_query_list<E>(lists_q0 + static_cast<size_t>(qa_) * CAP,
                                                                  &W.buf[qa_][0], ca, kp);
                             if (half == 0) tauv[r] = nt;
+                            if (lane == 0) W.thr[qa_] = dist_threshold(nt, W.yq[qa_]);
                             ca = 0;
+                            cntw[qa_ >> 2] &= ~(0xFFu << (8 * (qa_ & 3)));
                         }
                         if (fb) {
                             const float nt = merge_query_list<E>(lists_q0 + static_cast<size_t>(qb_) * CAP,
                                                                  &W.buf[qb_][0], cb, kp);
                             if (half == 1) tauv[r] = nt;
+                            if (lane == 0) W.thr[qb_] = dist_threshold(nt, W.yq[qb_]);
                             cb = 0;
+                            cntw[qb_ >> 2] &= ~(0xFFu << (8 * (qb_ & 3)));
                         }
                         thr_dirty = true;
                         wave_lds_sync();
                         mask = __ballot(valid && sc <= tauv[r]);
-                        ma = static_cast<uint32_t>(mask);
-                        mb = static_cast<uint32_t>(mask >> 32);
                     }
-                    const uint32_t hm = half ? mb : ma;
-                    if ((hm >> l31) & 1u) {
-                        const int pos = (half ? cb : ca) + __popc(hm & ((1u << l31) - 1u));
-                        W.buf[half ? qb_ : qa_][pos] = make_key(sc, static_cast<uint32_t>(cand));
-                    }
-                    const int na = ca + __popc(ma), nb = cb + __popc(mb);
-                    if (lane == 0 && (ma || fa)) W.cnt[qa_] = na;
-                    if (lane == 32 && (mb || fb)) W.cnt[qb_] = nb;
-                    if (na) nonempty |= 1u << qa_;
-                    else if (fa) nonempty &= ~(1u << qa_);
-                    if (nb) nonempty |= 1u << qb_;
-                    else if (fb) nonempty &= ~(1u << qb_);
+                    const int pa = __popc(static_cast<uint32_t>(mask)), pb = __popc(static_cast<uint32_t>(mask >> 32));
+                    // slot: the half's count plus the rank among the half's passing lanes
+                    // (mbcnt64 counts the lower half's lanes too in the upper half)
+                    const int slot0 = half ? qb_ * TBUF + cb - pa : qa_ * TBUF + ca;
+                    if (valid && sc <= tauv[r]) (&W.buf[0][0])[slot0 + mbcnt64(mask)] = make_key(sc, static_cast<uint32_t>(cand));
+                    cntw[qa_ >> 2] += static_cast<uint32_t>(pa) << (8 * (qa_ & 3));
+                    cntw[qb_ >> 2] += static_cast<uint32_t>(pb) << (8 * (qb_ & 3));
                 }
             }
         }
@@ -401,11 +400,13 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
     }
 
     wave_lds_sync();
-    while (nonempty) {
-        const int q = __builtin_ctz(nonempty);
-        nonempty &= nonempty - 1;
-        merge_query_list<E>(lists_q0 + static_cast<size_t>(q) * CAP, &W.buf[q][0], W.cnt[q], kp);
-        wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < TNQ; ++q) {
+        const int c = cnt_of(q);
+        if (c > 0) {
+            merge_query_list<E>(lists_q0 + static_cast<size_t>(q) * CAP, &W.buf[q][0], c, kp);
+            wave_lds_sync();
+        }
     }
     if (pair_count && lane == 0) atomicAdd(pair_count, pairs);
 

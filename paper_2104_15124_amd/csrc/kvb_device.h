@@ -124,16 +124,37 @@ __device__ __forceinline__ void wave_lds_sync()
 // ---------------------------------------------------------------- bitonic networks
 // Compare-exchange with partner distance j < 64 (partner in another lane) in a
 // bitonic stage of block size kb (ascending where element index & kb == 0).
+// The lanes l of a wavefront with bit j of l clear (j a power of two below
+// 64), as a lane mask.
+__host__ __device__ constexpr uint64_t lanes_bit_clear(int j)
+{
+    return j == 1    ? 0x5555555555555555ull
+           : j == 2  ? 0x3333333333333333ull
+           : j == 4  ? 0x0F0F0F0F0F0F0F0Full
+           : j == 8  ? 0x00FF00FF00FF00FFull
+           : j == 16 ? 0x0000FFFF0000FFFFull
+                     : 0x00000000FFFFFFFFull;
+}
+
+// The lanes that keep the smaller key of their pair are a constant lane mask
+// for each stage and slot (kb, j and s are compile-time constants once the
+// networks are unrolled), so each exchange is one 64-bit compare, a scalar
+// xor with that mask and two selects.
 template <int E, bool DESC = false>
 __device__ __forceinline__ void cx_lanes(uint64_t (&v)[E], int kb, int j, int lane)
 {
+    (void)lane;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-        uint64_t o = shfl_xor_u64(v[s], j);
-        int i = s * WAVE + lane;
-        bool up = ((i & kb) == 0) != DESC;
-        bool lower = (lane & j) == 0;
-        v[s] = (up == lower) ? umin64(v[s], o) : umax64(v[s], o);
+        const uint64_t o = shfl_xor_u64(v[s], j);
+        // element index i = s * 64 + lane sorts ascending in its block where (i & kb) == 0
+        uint64_t up = kb < WAVE ? lanes_bit_clear(kb) : (((s * WAVE) & kb) == 0 ? ~0ull : 0ull);
+        if (DESC) up = ~up;
+        // in an ascending block the lower lane of a pair keeps the smaller key
+        const uint64_t keep_min = ~(up ^ lanes_bit_clear(j));
+        // the partner's key is taken where it is the one to keep
+        const uint64_t take = __ballot(o < v[s]) ^ ~keep_min;
+        v[s] = __builtin_amdgcn_inverse_ballot_w64(take) ? o : v[s];
     }
 }
 
