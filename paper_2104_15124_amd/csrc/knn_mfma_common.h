@@ -57,6 +57,30 @@ __device__ __noinline__ float merge_query_list(uint64_t* __restrict__ dst, const
     return key_dist(list_at<E>(L, kp - 1));
 }
 
+// The same for a buffer of at most 32 keys: they are placed in the upper half
+// of the wavefront and sorted there in descending order by the first five
+// passes of the bitonic network (15 stages instead of 21), which is already
+// the reversed ascending order of the 64-key buffer padded with KEY_INF.
+template <int E>
+__device__ __noinline__ float merge_query_list32(uint64_t* __restrict__ dst, const uint64_t* buf, int cnt, int kp)
+{
+    const int lane = lane_id();
+    uint64_t B[1] = {lane >= 32 && lane - 32 < cnt ? buf[lane - 32] : KEY_INF};
+    uint64_t L[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) L[s] = dst[s * WAVE + lane];
+#pragma unroll
+    for (int kb = 2; kb <= 32; kb <<= 1) {
+#pragma unroll
+        for (int j = kb >> 1; j > 0; j >>= 1) cx_lanes<1>(B, kb, j, lane);
+    }
+    L[E - 1] = umin64(L[E - 1], B[0]);
+    bitonic_merge_asc<E>(L);
+#pragma unroll
+    for (int s = 0; s < E; ++s) dst[s * WAVE + lane] = L[s];
+    return key_dist(list_at<E>(L, kp - 1));
+}
+
 // Lower bound on the squared distance between any query of a workgroup (box
 // qlo..qhi of its projected coordinates) and any sample in the projected box
 // b ([lower corner, upper corner]), from the box gaps g_c. The computed

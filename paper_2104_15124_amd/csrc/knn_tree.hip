@@ -364,7 +364,7 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
                         // a full buffer is merged before this tile's keys are added
                         wave_lds_sync();
                         if (fa) {
-                            const float nt = merge_query_list<E>(lists_q0 + static_cast<size_t>(qa_) * CAP,
+                            const float nt = merge_query_list32<E>(lists_q0 + static_cast<size_t>(qa_) * CAP,
                                                                  &W.buf[qa_][0], ca, kp);
                             if (half == 0) tauv[r] = nt;
                             if (lane == 0) W.thr[qa_] = dist_threshold(nt, W.yq[qa_]);
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
                             cntw[qa_ >> 2] &= ~(0xFFu << (8 * (qa_ & 3)));
                         }
                         if (fb) {
-                            const float nt = merge_query_list<E>(lists_q0 + static_cast<size_t>(qb_) * CAP,
+                            const float nt = merge_query_list32<E>(lists_q0 + static_cast<size_t>(qb_) * CAP,
                                                                  &W.buf[qb_][0], cb, kp);
                             if (half == 1) tauv[r] = nt;
                             if (lane == 0) W.thr[qb_] = dist_threshold(nt, W.yq[qb_]);
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
     for (int q = 0; q < TNQ; ++q) {
         const int c = cnt_of(q);
         if (c > 0) {
-            merge_query_list<E>(lists_q0 + static_cast<size_t>(q) * CAP, &W.buf[q][0], c, kp);
+            merge_query_list32<E>(lists_q0 + static_cast<size_t>(q) * CAP, &W.buf[q][0], c, kp);
             wave_lds_sync();
         }
     }
