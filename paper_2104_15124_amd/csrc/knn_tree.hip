@@ -41,6 +41,8 @@ namespace {
 
 constexpr int TW = 4;        // wavefronts per workgroup (independent)
 constexpr int TBUF = 32;     // per-query LDS buffer entries
+// one tile adds up to 32 keys to a query's buffer right after its merge
+static_assert(TBUF >= 32, "a query's buffer must absorb a whole tile");
 constexpr int TNQ = 32;      // queries per wavefront
 
 // one wavefront's LDS state
@@ -266,9 +268,31 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    for (int q = 0; q < nq_valid; ++q) {
-        const float nt = sort_query_list<E>(lists_q0 + static_cast<size_t>(q) * CAP, kp);
-        if (lane == 0) W.tau[q] = nt;
+    // each list sorted in place, the next one's loads in flight meanwhile
+    // (the 256-key lists keep the plain loop: their inline sort would spill)
+    if constexpr (E > 2) {
+        for (int q = 0; q < nq_valid; ++q) {
+            const float nt = sort_query_list<E>(lists_q0 + static_cast<size_t>(q) * CAP, kp);
+            if (lane == 0) W.tau[q] = nt;
+        }
+    } else {
+        uint64_t Ln[E];
+#pragma unroll
+        for (int s = 0; s < E; ++s) Ln[s] = lists_q0[s * WAVE + lane];
+        for (int q = 0; q < nq_valid; ++q) {
+            uint64_t L[E];
+#pragma unroll
+            for (int s = 0; s < E; ++s) L[s] = Ln[s];
+            if (q + 1 < nq_valid) {
+#pragma unroll
+                for (int s = 0; s < E; ++s) Ln[s] = lists_q0[static_cast<size_t>(q + 1) * CAP + s * WAVE + lane];
+            }
+            bitonic_sort<E>(L);
+#pragma unroll
+            for (int s = 0; s < E; ++s) lists_q0[static_cast<size_t>(q) * CAP + s * WAVE + lane] = L[s];
+            const float nt = key_dist(list_at<E>(L, kp - 1));
+            if (lane == 0) W.tau[q] = nt;
+        }
     }
     wave_lds_sync();
 
@@ -400,13 +424,51 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
     }
 
     wave_lds_sync();
+    if constexpr (E > 2) {
 #pragma unroll
-    for (int q = 0; q < TNQ; ++q) {
-        const int c = cnt_of(q);
-        if (c > 0) {
-            merge_query_list32<E>(lists_q0 + static_cast<size_t>(q) * CAP, &W.buf[q][0], c, kp);
-            wave_lds_sync();
+        for (int q = 0; q < TNQ; ++q) {
+            const int c = cnt_of(q);
+            if (c > 0) {
+                merge_query_list32<E>(lists_q0 + static_cast<size_t>(q) * CAP, &W.buf[q][0], c, kp);
+                wave_lds_sync();
+            }
         }
+    } else {
+        // the last merges, the next list's loads in flight meanwhile (query
+        // q's buffer count moved to lane q, so that the loop need not be unrolled)
+        int cnt_lane = 0;
+#pragma unroll
+        for (int q = 0; q < TNQ; ++q)
+            if (lane == q) cnt_lane = cnt_of(q);
+        uint64_t Ln[E];
+#pragma unroll
+        for (int s = 0; s < E; ++s) Ln[s] = lists_q0[s * WAVE + lane];
+        for (int q = 0; q < nq_valid; ++q) {
+            const int c = __builtin_amdgcn_readlane(cnt_lane, q);
+            uint64_t L[E];
+#pragma unroll
+            for (int s = 0; s < E; ++s) L[s] = Ln[s];
+            if (q + 1 < nq_valid) {
+#pragma unroll
+                for (int s = 0; s < E; ++s) Ln[s] = lists_q0[static_cast<size_t>(q + 1) * CAP + s * WAVE + lane];
+            }
+            if (c > 0) {
+                uint64_t B[1] = {lane >= 32 && lane - 32 < c ? W.buf[q][lane - 32] : KEY_INF};
+#pragma unroll
+                for (int kb = 2; kb <= 32; kb <<= 1) {
+#pragma unroll
+                    for (int j = kb >> 1; j > 0; j >>= 1) cx_lanes<1>(B, kb, j, lane);
+                }
+                L[E - 1] = umin64(L[E - 1], B[0]);
+                bitonic_merge_asc<E>(L);
+#pragma unroll
+                for (int s = 0; s < E; ++s) lists_q0[static_cast<size_t>(q) * CAP + s * WAVE + lane] = L[s];
+            }
+            // the list's kp-th score, for the certificate below
+            const float sl = key_dist(list_at<E>(L, kp - 1));
+            if (lane == 0) W.tau[q] = sl;
+        }
+        wave_lds_sync();
     }
     if (pair_count && lane == 0) atomicAdd(pair_count, pairs);
 
@@ -415,7 +477,7 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
     const double R = static_cast<double>(__uint_as_float(*rmax_bits));
     if (lane < nq_valid) {
         const int qg = q0 + lane;
-        const float sl = key_dist(lists[static_cast<size_t>(qg) * CAP + (kp - 1)]);
+        const float sl = E > 2 ? key_dist(lists[static_cast<size_t>(qg) * CAP + (kp - 1)]) : W.tau[lane];
         const double yi2 = static_cast<double>(ynorm2[qg]);
         const double yi = sqrt(yi2);
         const double Ei = em.gamma * (R + 1.05 * yi) * (R + 1.05 * yi) + em.norm * R * R + em.cross * yi * R + 1e-30;
