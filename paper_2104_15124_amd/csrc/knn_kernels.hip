@@ -10,8 +10,8 @@
 //   select   stream all n candidates through a distance test and keep the
 //            k' = k + margin smallest (distance, index) keys in a register
 //            list (one wavefront owns R rows; lanes hold candidates);
-//   refine   recompute the k' candidates' squared distances with compensated
-//            float32 arithmetic, drop i itself, sort, decide membership at the
+//   refine   recompute the k' candidates' squared distances in float64
+//            (rounded to float32), drop i itself, sort, decide membership at the
 //            k-th neighbour in float64, and check a certificate that no
 //            dropped candidate can be nearer than the k-th kept one;
 //   fallback rows without a certificate are recomputed by an exact float64
@@ -388,16 +388,21 @@ __global__ __launch_bounds__(256) void k_group_boxes(const float* __restrict__ s
 }
 
 // -------------------------------------------------------------------- refine
-// Compensated squared distances (CompF32, comp_sqdiff_add over the columns in
-// order) of row a to the rows b_s = B + j_s m (where act_s); the coordinates
-// are read CH at a time (float4 pieces when vec4), so that a chunk's loads
-// are in flight together.
+// Squared distances of row a to the rows b_s = B + j_s m (where act_s), each
+// accumulated in float64 over the columns in order (the difference of two
+// float32 values is exact in float64) and rounded once to float32: the same
+// operations as dist2_f64, so these agree bit for bit with the exact path's
+// distances. On gfx950 an unpacked float64 FMA issues at the float32 rate,
+// so this costs about three instructions per coordinate. The coordinates are
+// read CH at a time (float4 pieces when vec4), so that a chunk's loads are in
+// flight together.
 template <int E, int CH>
-__device__ __forceinline__ void comp_dist2_rows_ch(const float* __restrict__ a, const float* __restrict__ B, int m,
-                                                   const int (&j)[E], const bool (&act)[E], bool vec4,
-                                                   float (&out)[E])
+__device__ __forceinline__ void dist2_rows_ch(const float* __restrict__ a, const float* __restrict__ B, int m,
+                                              const int (&j)[E], const bool (&act)[E], bool vec4, float (&out)[E])
 {
-    CompF32 acc[E];
+    double acc[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) acc[s] = 0.0;
     for (int c0 = 0; c0 < m; c0 += CH) {
         float av[CH], bv[E][CH];
         if (vec4) {
@@ -442,25 +447,28 @@ __device__ __forceinline__ void comp_dist2_rows_ch(const float* __restrict__ a, 
             if (c0 + t < m) {
 #pragma unroll
                 for (int s = 0; s < E; ++s)
-                    if (act[s]) comp_sqdiff_add(acc[s], av[t], bv[s][t]);
+                    if (act[s]) {
+                        const double d = static_cast<double>(av[t]) - static_cast<double>(bv[s][t]);
+                        acc[s] = fma(d, d, acc[s]);
+                    }
             }
         }
     }
 #pragma unroll
-    for (int s = 0; s < E; ++s) out[s] = acc[s].s + acc[s].c;
+    for (int s = 0; s < E; ++s) out[s] = static_cast<float>(acc[s]);
 }
 
 // the chunk fitted to m (8 coordinates at most for four key slots)
 template <int E>
-__device__ __forceinline__ void comp_dist2_rows(const float* __restrict__ a, const float* __restrict__ B, int m,
-                                                const int (&j)[E], const bool (&act)[E], bool vec4, float (&out)[E])
+__device__ __forceinline__ void dist2_rows(const float* __restrict__ a, const float* __restrict__ B, int m,
+                                           const int (&j)[E], const bool (&act)[E], bool vec4, float (&out)[E])
 {
     if (m <= 4)
-        comp_dist2_rows_ch<E, 4>(a, B, m, j, act, vec4, out);
+        dist2_rows_ch<E, 4>(a, B, m, j, act, vec4, out);
     else if (m <= 8 || E >= 4)
-        comp_dist2_rows_ch<E, 8>(a, B, m, j, act, vec4, out);
+        dist2_rows_ch<E, 8>(a, B, m, j, act, vec4, out);
     else
-        comp_dist2_rows_ch<E, 16>(a, B, m, j, act, vec4, out);
+        dist2_rows_ch<E, 16>(a, B, m, j, act, vec4, out);
 }
 
 __device__ __forceinline__ double dist2_f64(const float* __restrict__ a, const float* __restrict__ b, int m)
@@ -561,11 +569,12 @@ __device__ __forceinline__ void group_distances(const float* __restrict__ X, int
 // squared distance by lb_scale (direct tiles: the kp-th score times
 // 1/(1 + select error); matrix-core tiles: the bound itself, lb_scale = 1).
 // slast == nullptr: no bound (learned routing). LPC == 0: each lane computes
-// its own candidates' distances (compensated float32, short rows); LPC > 0:
-// groups of LPC lanes per candidate (group_distances, long rows). Lists whose
-// recomputed keys are still in ascending order once row i is taken out (the
-// common case after the direct tiles, whose float32 scores differ from the
-// compensated distances only in the last bits) skip the sorting network.
+// its own candidates' distances (float64 sums rounded to float32, short rows);
+// LPC > 0: groups of LPC lanes per candidate (group_distances, long rows).
+// Lists whose recomputed keys are still in ascending order once row i is taken
+// out (the common case after the direct tiles, whose float32 scores differ
+// from the recomputed distances only in the last bits) skip the sorting
+// network.
 //
 // CV (curve-ordered scans): lists and bounds are stored by curve position r, their
 // keys hold curve positions; the candidates are read from the curve-ordered
@@ -611,7 +620,7 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
         const float* Br = CV ? Xs : X;   // the rows the keys refer to
         const bool vec4 = (m % 4 == 0) && ((reinterpret_cast<uintptr_t>(Br) & 15) == 0);
         float dd[E];
-        comp_dist2_rows<E>(xi, Br, m, jr, act, vec4, dd);
+        dist2_rows<E>(xi, Br, m, jr, act, vec4, dd);
 #pragma unroll
         for (int s = 0; s < E; ++s) {
             if (v[s] == KEY_INF) continue;
@@ -676,7 +685,7 @@ __global__ __launch_bounds__(256) void k_refine(const float* __restrict__ X, int
     bool certified = true;
     float bound = __uint_as_float(0x7F800000u);   // upper bound on the true (k-1)-th distance
     if (kk > 0) {
-        // relative error bound of the compensated distances (a few units in
+        // relative error bound of the recomputed distances (a few units in
         // the last place), doubled for the band test
         const float dl = 4.8e-7f;
         const float a = key_dist(list_at<E>(v, kk - 1));

@@ -263,30 +263,4 @@ struct Comp64 {
     __device__ __forceinline__ double value() const { return s + c; }
 };
 
-// Squared distance of two float32 rows with error-free transformations: each
-// difference a - b is split exactly into t + e (two-sum), t*t is split exactly
-// into p + pe (fused multiply-add), and the pieces are accumulated with
-// Neumaier compensation, so the float32 result is close to correctly rounded
-// whatever the dimension.
-struct CompF32 {
-    float s = 0.f, c = 0.f;
-    __device__ __forceinline__ void add(float x)
-    {
-        float t = s + x;
-        c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
-        s = t;
-    }
-};
-
-__device__ __forceinline__ void comp_sqdiff_add(CompF32& acc, float a, float b)
-{
-    float t = a - b;
-    float bb = t - a;
-    float e = (a - (t - bb)) - (b + bb);      // a - b = t + e exactly (two-sum of a and -b)
-    float p = t * t;
-    float pe = fmaf(t, t, -p);                // t*t = p + pe exactly
-    acc.add(p);
-    acc.c += pe + (2.0f * t * e + e * e);
-}
-
 }  // namespace kvb
