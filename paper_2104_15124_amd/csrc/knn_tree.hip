@@ -162,6 +162,17 @@ __device__ __forceinline__ TileGroup climb(TreeLds* Wg, const TreeShape* sh, con
 
 // Waves per SIMD the register file allows: the query fragments and the two
 // candidate tile buffers (3 KS fragments) dominate the kernel's registers.
+// Tiles in flight: three. The third one's fragments (KS x fragment
+// registers) can cost a wavefront per SIMD, and that still pays: on the 8M
+// mixture the BF16 select at three tiles and three wavefronts per SIMD
+// measured 126 ms against 131 ms at two tiles and four; a fourth tile
+// measured no faster than three.
+template <class Tr, int KS>
+constexpr int tree_depth()
+{
+    return 3;
+}
+
 template <class Tr, int KS>
 constexpr int tree_waves()
 {
@@ -354,20 +365,39 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
     for (int i = 0; i < TNQ / 4; ++i) cntw[i] = 0u;
     auto cnt_of = [&](int q) { return static_cast<int>((cntw[q >> 2] >> (8 * (q & 3))) & 0xFFu); };
     bool thr_dirty = false;
-    float tb_cur = 0.f, tb_nxt = 0.f;
-    int cur = next_tile(wthr, tb_cur);
-    frag bcur[KS] = {}, bnxt[KS] = {};
-    if (cur >= 0) load_tile(cur, bcur);
-    while (cur >= 0) {
+    // the tiles' fragments stream into registers DEPTH - 1 tiles ahead of
+    // the products (a tile with no hits is too short to cover the latency
+    // of the next one's loads)
+    constexpr int DEPTH = tree_depth<Tr, KS>();
+    int tq[DEPTH];        // the tiles in flight, the current one first (-1: none)
+    float tbq[DEPTH];     // their bounds when taken
+    frag bq[DEPTH][KS];   // their fragments
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+        tq[d] = -1;
+        tbq[d] = 0.f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) bq[d][s] = {};
+    }
+    tq[0] = next_tile(wthr, tbq[0]);
+    if (tq[0] >= 0) load_tile(tq[0], bq[0]);
+#pragma unroll
+    for (int d = 1; d + 1 < DEPTH; ++d) {
+        if (tq[d - 1] >= 0) tq[d] = next_tile(wthr, tbq[d]);
+        if (tq[d] >= 0) load_tile(tq[d], bq[d]);
+    }
+    while (tq[0] >= 0) {
         if (thr_dirty) {
             wthr = wave_threshold();
             thr_dirty = false;
         }
-        const int nxt = next_tile(wthr, tb_nxt);
-        if (nxt >= 0) load_tile(nxt, bnxt);
+        tq[DEPTH - 1] = tq[DEPTH - 2] >= 0 ? next_tile(wthr, tbq[DEPTH - 1]) : -1;
+        if (tq[DEPTH - 1] >= 0) load_tile(tq[DEPTH - 1], bq[DEPTH - 1]);
+        const int cur = tq[0];
+        const float tb_cur = tbq[0];
         // the current tile may have fallen out of reach since it was taken
         if (tb_cur <= wthr) {
-            f32x16 acc = product(bcur);
+            f32x16 acc = product(bq[0]);
             const int cand = cur * 32 + l31;
             const bool valid = cand < n;
             pairs += static_cast<unsigned long long>(nq_valid) * __popcll(__ballot(valid) & 0xFFFFFFFFull);
@@ -417,10 +447,13 @@ __global__ __launch_bounds__(64 * TW, (tree_waves<Tr, KS>())) void k_select_tree
                 }
             }
         }
-        cur = nxt;
-        tb_cur = tb_nxt;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) bcur[s] = bnxt[s];
+        for (int d = 0; d + 1 < DEPTH; ++d) {
+            tq[d] = tq[d + 1];
+            tbq[d] = tbq[d + 1];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) bq[d][s] = bq[d + 1][s];
+        }
     }
 
     wave_lds_sync();
