@@ -510,7 +510,6 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
     constexpr int PF = (CHUNKS + 64 * WV - 1) / (64 * WV);  // pieces per thread
     __shared__ __attribute__((aligned(16))) frag s_tile[2][KS][2][32];
     __shared__ uint64_t s_buf[WV][NQ][BUF];
-    __shared__ int s_cnt[WV][NQ];
 
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -566,7 +565,6 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
                 for (int t = lane; t < CAP; t += WAVE) lists[static_cast<size_t>(qg) * CAP + t] = KEY_INF;
         }
     }
-    if (lane < NQ) s_cnt[wave][lane] = 0;
     wave_lds_sync();
     const int nq_valid = __popcll(__ballot(lane < NQ && s_qid[wave][lane] >= 0));
     unsigned long long pairs = 0;
@@ -658,7 +656,14 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
         if constexpr (LEARNED) cid_pf = ba.cid[static_cast<size_t>(tile) * 32 + (lane & 31)];
         if constexpr (CURVE) cid_pf = tile * 32 + (lane & 31) < n ? tile * 32 + (lane & 31) : -1;
     }
-    uint32_t nonempty = 0;   // queries with buffered entries (wave-uniform)
+    // the buffers' fill, wave-uniform: query q's count in byte q % 4 of
+    // cntw[q / 4] (every index below is a compile-time constant, so they stay
+    // in scalar registers; BUF <= 64 fits a byte)
+    static_assert(BUF <= 255, "a buffer count must fit a byte");
+    uint32_t cntw[NQ / 4];
+#pragma unroll
+    for (int i = 0; i < NQ / 4; ++i) cntw[i] = 0u;
+    auto cnt_of = [&](int q) { return static_cast<int>((cntw[q >> 2] >> (8 * (q & 3))) & 0xFFu); };
     // lists that start empty are filled by the first tiles without merging
     bool filling = !LEARNED || ba.first;
     const int fill_tiles = CAP / 32;   // the whole list capacity: a tighter first threshold
@@ -677,7 +682,9 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
                         const float y2 = YQ_LDS ? s_yq[wave][acc_row(r, half)] : yq[YQ_LDS ? 0 : r];
                         t = fmaxf(t, fmaxf(tauv[r] + y2, 0.f) * (1.f + 4.8e-7f));
                     }
-                wthr = wave_max_f32(t);
+                // read from one lane: the compiler then sees a wave-uniform
+                // value and keeps the branches on it (and the counts) scalar
+                wthr = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_max_f32(t))));
                 thr_dirty = false;
             }
             if (lane == 0) s_thr[stage][wave] = wthr;
@@ -691,7 +698,7 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
             }
         }
         const int cid_cur = cid_pf;
-        const float wb_cur = wb_pf;
+        const float wb_cur = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wb_pf)));
         __syncthreads();                 // stage visible; the other stage's readers finished a tile ago
         float thr = __uint_as_float(0x7F800000u);
         if constexpr (CURVE) {
@@ -790,8 +797,7 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
             if (mask) {
                 const int qa_ = acc_row(r, 0), qb_ = acc_row(r, 1);
                 uint32_t ma = static_cast<uint32_t>(mask), mb = static_cast<uint32_t>(mask >> 32);
-                int ca = ma ? s_cnt[wave][qa_] : 0;
-                int cb = mb ? s_cnt[wave][qb_] : 0;
+                int ca = cnt_of(qa_), cb = cnt_of(qb_);
                 const bool fa = ca + __popc(ma) > BUF, fb = cb + __popc(mb) > BUF;
                 if (fa || fb) {
                     // a full buffer is merged before this tile's keys are added,
@@ -806,6 +812,7 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
                         if (half == 0) tauv[r] = nt;
                         thr_dirty = true;
                         ca = 0;
+                        cntw[qa_ >> 2] &= ~(0xFFu << (8 * (qa_ & 3)));
                     }
                     if (fb) {
                         const int qg = s_qid[wave][qb_];
@@ -816,37 +823,44 @@ __global__ __launch_bounds__(64 * WV, (MODE == 2 && WV == 4 && curve_pair<Tr, KS
                         if (half == 1) tauv[r] = nt;
                         thr_dirty = true;
                         cb = 0;
+                        cntw[qb_ >> 2] &= ~(0xFFu << (8 * (qb_ & 3)));
                     }
                     wave_lds_sync();
                     mask = __ballot(valid && sc <= tauv[r]);
                     ma = static_cast<uint32_t>(mask);
                     mb = static_cast<uint32_t>(mask >> 32);
                 }
-                const uint32_t hm = half ? mb : ma;
-                const int l31 = lane & 31;
-                if ((hm >> l31) & 1u) {
-                    const int pos = (half ? cb : ca) + __popc(hm & ((1u << l31) - 1u));
-                    s_buf[wave][half ? qb_ : qa_][pos] = make_key(sc, static_cast<uint32_t>(cand));
-                }
-                const int na = ca + __popc(ma), nb = cb + __popc(mb);
-                if (lane == 0 && (ma || fa)) s_cnt[wave][qa_] = na;
-                if (lane == 32 && (mb || fb)) s_cnt[wave][qb_] = nb;
-                if (na) nonempty |= 1u << qa_;
-                else if (fa) nonempty &= ~(1u << qa_);
-                if (nb) nonempty |= 1u << qb_;
-                else if (fb) nonempty &= ~(1u << qb_);
+                // slot: the half's count plus the rank among the half's
+                // passing lanes (mbcnt64 counts the lower half's lanes too in
+                // the upper half)
+                const int pa = __popc(ma), pb = __popc(mb);
+                const int slot0 = half ? qb_ * BUF + cb - pa : qa_ * BUF + ca;
+                if (valid && sc <= tauv[r])
+                    (&s_buf[wave][0][0])[slot0 + mbcnt64(mask)] = make_key(sc, static_cast<uint32_t>(cand));
+                cntw[qa_ >> 2] += static_cast<uint32_t>(pa) << (8 * (qa_ & 3));
+                cntw[qb_ >> 2] += static_cast<uint32_t>(pb) << (8 * (qb_ & 3));
             }
         }
         tile = next;
     }
     wave_lds_sync();
-    while (nonempty) {
-        const int q = __builtin_ctz(nonempty);
-        nonempty &= nonempty - 1;
-        const int qg = s_qid[wave][q];
-        if (qg >= 0)
-            merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][q][0], s_cnt[wave][q], kp);
-        wave_lds_sync();
+    {
+        // the last merges in a loop that is not unrolled: query q's count
+        // moved to lane q
+        int cnt_lane = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (lane == q) cnt_lane = cnt_of(q);
+        uint64_t nonempty = __ballot(cnt_lane > 0);
+        while (nonempty) {
+            const int q = __builtin_ctzll(nonempty);
+            nonempty &= nonempty - 1;
+            const int qg = s_qid[wave][q];
+            if (qg >= 0)
+                merge_query_list<E>(lists + static_cast<size_t>(qg) * CAP, &s_buf[wave][q][0],
+                                    __builtin_amdgcn_readlane(cnt_lane, q), kp);
+            wave_lds_sync();
+        }
     }
     if (pair_count && lane == 0) atomicAdd(pair_count, pairs);
 
