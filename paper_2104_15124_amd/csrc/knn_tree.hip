@@ -21,7 +21,8 @@
 // walk tightens as the lists improve. Every tile
 // reached is one 32 x 32 matrix-core product of the query fragments
 // (registers) and the candidate fragments (read from the tile-major operand;
-// the next tile's reads are issued before the current tile's products). A
+// the reads of the next two tiles are issued before the current tile's
+// products). A
 // score at or below its query's threshold is
 // appended to the query's LDS buffer, which is merged into the list when it
 // may not absorb another tile (the same merge as the workgroup scans); a
