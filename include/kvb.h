@@ -65,6 +65,8 @@ extern "C" {
 #define KVB_E_UNSUPPORTED (-4) /* valid but beyond this build's capacity, or not a gfx950 device */
 #define KVB_E_NOT_TRAINED (-5) /* learned mode requested before a partitioner exists */
 #define KVB_E_IO (-6)        /* partitioner file missing, short or corrupt */
+#define KVB_E_NO_DEVICE (-7) /* a host-only context (kvb_create_host): the arguments passed every check
+                                and nothing ran */
 
 /* ---- k-NN modes ---- */
 #define KVB_KNN_F32 0        /* FP32 distance tiles (direct differences for m <= 8, FP32 MFMA otherwise) */
@@ -109,6 +111,13 @@ typedef struct kvb_ctx_s* kvb_ctx;
 /* Create a context bound to hip_stream (a hipStream_t; NULL = the null stream)
  * on the current device. Fails with KVB_E_UNSUPPORTED on a non-gfx950 device. */
 int kvb_create(kvb_ctx* out, void* hip_stream);
+
+/* Create a context bound to no device (callers: argument screening and tests on a machine without a
+ * GPU; needs no HIP device). Every entry point called with it checks its arguments exactly as with a
+ * device context, returning the same KVB_E_INVALID / KVB_E_UNSUPPORTED / KVB_E_NOT_TRAINED status and
+ * kvb_last_error message, and returns KVB_E_NO_DEVICE (nothing launched, no memory read or written)
+ * where it would start work on the device. Released by kvb_destroy. */
+int kvb_create_host(kvb_ctx* out);
 
 /* Release the context and its scratch. Waits for its stream first. NULL is a no-op. */
 void kvb_destroy(kvb_ctx ctx);

@@ -63,9 +63,23 @@ int kvb_create(kvb_ctx* out, void* hip_stream)
     return KVB_OK;
 }
 
+int kvb_create_host(kvb_ctx* out)
+{
+    if (!out) return KVB_E_INVALID;
+    kvb_ctx ctx = new kvb_ctx_s();
+    ctx->host_only = true;
+    ctx->device = -1;
+    *out = ctx;
+    return KVB_OK;
+}
+
 void kvb_destroy(kvb_ctx ctx)
 {
     if (!ctx) return;
+    if (ctx->host_only) {
+        delete ctx;
+        return;
+    }
     (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (const ProfPair& p : ctx->ev_pending) {
@@ -956,6 +970,7 @@ const char* kvb_version(void) { return "kvb 0.1 (gfx950)"; }
 int kvb_profile_enable(kvb_ctx ctx, int32_t on)
 {
     if (check_ctx(ctx)) return KVB_E_INVALID;
+    KVB_DEVICE_WORK(ctx);
     int rc = prof_collect(ctx);
     if (rc) return rc;
     for (int s = 0; s < KVB_PROF_SLOTS; ++s) {

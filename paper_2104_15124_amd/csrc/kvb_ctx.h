@@ -52,6 +52,7 @@ struct BuildDev {
 struct kvb_ctx_s {
     hipStream_t stream = nullptr;
     int device = 0;
+    bool host_only = false;   // kvb_create_host: validation only, no device work
     std::string err;
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
@@ -99,8 +100,19 @@ inline int fail(kvb_ctx ctx, int code, const char* fmt, ...)
     return code;
 }
 
+// A host-only context (kvb_create_host) stops where device work would start,
+// after all argument checks: at the first KVB_HIP call of an entry point, or
+// at KVB_DEVICE_WORK where an entry point allocates or times on the device
+// by other means.
+#define KVB_DEVICE_WORK(ctx)                                                                   \
+    do {                                                                                       \
+        if ((ctx) && (ctx)->host_only)                                                         \
+            return ::kvbh::fail((ctx), KVB_E_NO_DEVICE, "host-only context: the arguments are valid; nothing ran"); \
+    } while (0)
+
 #define KVB_HIP(ctx, call)                                                                     \
     do {                                                                                       \
+        KVB_DEVICE_WORK(ctx);                                                                  \
         hipError_t e_ = (call);                                                                \
         if (e_ != hipSuccess)                                                                  \
             return ::kvbh::fail((ctx), KVB_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \

@@ -57,6 +57,7 @@ int ceil_log2(int v)
 
 int part_alloc(kvb_ctx ctx, int m, int h1, int h2, int nb, int np)
 {
+    KVB_DEVICE_WORK(ctx);
     part_free(ctx);
     PartState& P = ctx->part;
     P.m = m;

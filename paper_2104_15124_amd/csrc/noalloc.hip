@@ -75,6 +75,7 @@ int kvb_tune_eps_noalloc(kvb_ctx ctx, const int32_t* idx, const float* d2, const
     KVB_REQUIRE(ctx, e_min > 0 && e_max > e_min && std::isfinite(e_max), "need 0 < e_min < e_max < inf");
     KVB_REQUIRE(ctx, aligned(idx) && aligned(d2) && aligned(rho), "idx, d2, rho must be non-null device pointers");
     KVB_REQUIRE(ctx, e_star_host != nullptr, "e_star_host must be non-null");
+    KVB_DEVICE_WORK(ctx);
     void* base = noalloc_scratch(ctx->device);
     if (!base) return fail(ctx, KVB_E_UNSUPPORTED, "no static scratch on device %d", ctx->device);
     const int64_t nnz = n * k;

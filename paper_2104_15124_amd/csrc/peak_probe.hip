@@ -102,6 +102,7 @@ int kvb_peak_probe(kvb_ctx ctx, int32_t kind, double* rate_host, double* ms_host
     if (kvbh::check_ctx(ctx)) return KVB_E_INVALID;
     KVB_REQUIRE(ctx, rate_host != nullptr, "rate_host is required");
     KVB_REQUIRE(ctx, kind >= KVB_PEAK_HBM_COPY && kind <= KVB_PEAK_VALU_FMA, "unknown peak kind %d", kind);
+    KVB_DEVICE_WORK(ctx);
     hipStream_t st = ctx->stream;
     constexpr int BLOCKS = 256 * 16, THREADS = 256, REPS = 5;
     const size_t sink_bytes = sizeof(float) * BLOCKS * THREADS;

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libkvb.so")
 
 # status / enum values mirrored from include/kvb.h
 OK, W_GRID_EDGE, W_FALLBACK = 0, 1, 2
-E_INVALID, E_NOMEM, E_HIP, E_UNSUPPORTED, E_NOT_TRAINED, E_IO = -1, -2, -3, -4, -5, -6
+E_INVALID, E_NOMEM, E_HIP, E_UNSUPPORTED, E_NOT_TRAINED, E_IO, E_NO_DEVICE = -1, -2, -3, -4, -5, -6, -7
 W_NOT_CONVERGED = 3
 KNN_F32, KNN_BF16, KNN_LEARNED = 0, 1, 2
 BW_ADHOC, BW_DENSITY = 0, 1
@@ -32,7 +32,7 @@ OPT_FORCE_FALLBACK, OPT_SCRATCH_LIMIT, OPT_BF16_SPLIT, OPT_N_PROBE, OPT_CURVE_OR
 PATTERNS = {"knn": 0, "union": 1}
 MODES = {"f32": KNN_F32, "bf16": KNN_BF16, "learned": KNN_LEARNED}
 
-EXPORTS = ("kvb_create", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb_knn",
+EXPORTS = ("kvb_create", "kvb_create_host", "kvb_destroy", "kvb_last_error", "kvb_set_option", "kvb_knn",
            "kvb_knn_fallback_rows", "kvb_knn_pairs", "kvb_knn_exact_rows", "kvb_bandwidth",
            "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_build", "kvb_build_info", "kvb_part_init",
            "kvb_part_teacher", "kvb_part_train", "kvb_part_route", "kvb_part_save", "kvb_part_load", "kvb_mlp_forward",
@@ -65,6 +65,7 @@ def load_library(path: str = LIB_PATH):
                        "(run __graft_entry__.build())")
     L = ctypes.CDLL(path)
     L.kvb_create.argtypes = [ctypes.POINTER(_vp), _vp]
+    L.kvb_create_host.argtypes = [ctypes.POINTER(_vp)]
     L.kvb_destroy.argtypes = [_vp]
     L.kvb_destroy.restype = None
     L.kvb_last_error.argtypes = [_vp]
@@ -119,7 +120,7 @@ def load_library(path: str = LIB_PATH):
     L.kvb_profile_read.argtypes = [_vp, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
     L.kvb_profile_name.argtypes = [_i32]
     L.kvb_profile_name.restype = ctypes.c_char_p
-    for name in ("kvb_create", "kvb_set_option", "kvb_knn", "kvb_knn_fallback_rows", "kvb_knn_exact_rows",
+    for name in ("kvb_create", "kvb_create_host", "kvb_set_option", "kvb_knn", "kvb_knn_fallback_rows", "kvb_knn_exact_rows",
                  "kvb_knn_pairs",
                  "kvb_bandwidth",
                  "kvb_grid_scale", "kvb_tune_eps", "kvb_assemble_csr", "kvb_profile_enable",
