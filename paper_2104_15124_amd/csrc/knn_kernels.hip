@@ -819,11 +819,32 @@ constexpr int FB_THREADS = 256;
 constexpr int FB_CHUNK = 1024;
 
 // m <= FB_LDS_M: blocks stage FB_STAGE consecutive samples in LDS (coalesced,
-// row stride m + 1 against bank conflicts) and every wavefront takes listed
-// rows in turn, one staged sample per lane; the summation order is that of
-// dist2_f64.
+// row stride m + 1 against bank conflicts), and the listed rows' coordinates,
+// bounds and ids once per chunk of up to FB_ROW_FLOATS / m rows; every
+// wavefront takes listed rows in turn, one staged sample per lane. A float32
+// distance screens each pair first: it errs from the exact one by at most
+// (m + 3) 2^-24 relative, so a pair whose float32 distance exceeds the bound by
+// (m + 10) 2^-24 cannot be within it; the others are decided in float64 in the
+// summation order of dist2_f64.
 constexpr int FB_STAGE = 64;
-constexpr int FB_LDS_M = 256;
+constexpr int FB_LDS_M = 192;
+constexpr int FB_LDS_BYTES = 60 * 1024;   // LDS per block: the sample stage, then row chunks
+constexpr int FB_ROW_FLOATS = 8192;       // at most this many row coordinates per chunk
+
+// listed rows per LDS chunk: their coordinates (m floats), bound and id each
+__host__ __device__ inline int fb_rows_per_chunk(int m)
+{
+    const int stage = FB_STAGE * (m + 1) * 4;
+    int r = (FB_LDS_BYTES - stage) / (4 * m + 12);
+    r = r < FB_ROW_FLOATS / m ? r : FB_ROW_FLOATS / m;
+    return r < FB_MAX_ROWS ? (r > 1 ? r : 1) : FB_MAX_ROWS;
+}
+size_t fb_collect_lds_bytes(int m)
+{
+    const int rch = fb_rows_per_chunk(m);
+    return sizeof(float) * (static_cast<size_t>(FB_STAGE) * (m + 1) + static_cast<size_t>(rch) * m) +
+           (sizeof(double) + sizeof(int)) * static_cast<size_t>(rch);
+}
 
 __global__ __launch_bounds__(FB_THREADS) void k_fb_collect_lds(const float* __restrict__ X, int n, int m,
                                                                const int* __restrict__ fb_count,
@@ -832,37 +853,147 @@ __global__ __launch_bounds__(FB_THREADS) void k_fb_collect_lds(const float* __re
                                                                int* __restrict__ cnt, double* __restrict__ bd,
                                                                int* __restrict__ bj)
 {
-    __shared__ float xc[FB_STAGE * (FB_LDS_M + 1)];
+    extern __shared__ __attribute__((aligned(16))) unsigned char fb_smem[];
     const int total = min(*fb_count, rows_cap);
     if (total == 0) return;
+    const int rch = fb_rows_per_chunk(m);
+    const int ld = m + 1;
+    double* rb = reinterpret_cast<double*>(fb_smem);                  // [rch] screened bounds
+    float* xc = reinterpret_cast<float*>(rb + rch);                    // [FB_STAGE][m + 1] samples
+    float* xr = xc + FB_STAGE * ld;                                    // [rch][m] listed rows
+    int* ri = reinterpret_cast<int*>(xr + static_cast<size_t>(rch) * m);   // [rch] their ids
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x / WAVE;
-    const int ld = m + 1;
-    for (int c0 = blockIdx.x * FB_STAGE; c0 < n; c0 += gridDim.x * FB_STAGE) {
+    const double slack = 1.0 + (m + 10) * 0x1p-24;
+    for (int r0 = 0; r0 < total; r0 += rch) {
+        const int nr = min(rch, total - r0);
         __syncthreads();
-        for (int e = threadIdx.x; e < FB_STAGE * m; e += FB_THREADS) {
-            const int r = e / m, c = e - r * m;
-            xc[r * ld + c] = c0 + r < n ? X[static_cast<size_t>(c0) * m + e] : 0.f;
+        for (int t = threadIdx.x; t < nr; t += FB_THREADS) {
+            const float B = fb_bound[r0 + t];
+            ri[t] = fb_list[r0 + t];
+            rb[t] = B < __uint_as_float(0x7F800000u) ? static_cast<double>(B) : -1.0;   // -1: no bound
+        }
+        for (int e = threadIdx.x; e < nr * m; e += FB_THREADS) {
+            const int t = e / m, c = e - t * m;
+            xr[e] = X[static_cast<size_t>(fb_list[r0 + t]) * m + c];
+        }
+        for (int c0 = blockIdx.x * FB_STAGE; c0 < n; c0 += gridDim.x * FB_STAGE) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < FB_STAGE * m; e += FB_THREADS) {
+                const int r = e / m, c = e - r * m;
+                xc[r * ld + c] = c0 + r < n ? X[static_cast<size_t>(c0) * m + e] : 0.f;
+            }
+            __syncthreads();
+            const int j = c0 + lane;
+            const float* xj = xc + lane * ld;
+            for (int t = wave; t < nr; t += FB_THREADS / WAVE) {
+                const double B = rb[t];
+                if (B < 0.0) continue;
+                const int i = ri[t];
+                if (j >= n || j == i) continue;
+                const float* xi = xr + t * m;
+                float d32 = 0.f;
+                for (int c = 0; c < m; ++c) {
+                    const float u = xi[c] - xj[c];
+                    d32 = fmaf(u, u, d32);
+                }
+                if (d32 < __uint_as_float(0x7F800000u) && static_cast<double>(d32) > B * slack) continue;
+                double d = 0.0;
+                for (int c = 0; c < m; ++c) {
+                    const double u = static_cast<double>(xi[c]) - static_cast<double>(xj[c]);
+                    d = fma(u, u, d);
+                }
+                if (d <= B) {
+                    const int slot = atomicAdd(&cnt[r0 + t], 1);
+                    if (slot < FB_CAP) {
+                        bd[static_cast<size_t>(r0 + t) * FB_CAP + slot] = d;
+                        bj[static_cast<size_t>(r0 + t) * FB_CAP + slot] = j;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// m <= 16: every wavefront takes its own chunks of 64 samples, one per lane,
+// with the sample's coordinates in registers (read straight from X: a chunk is
+// 64 m consecutive floats), and the listed rows' coordinates, padded to 16,
+// as four broadcast float4 reads from LDS; the padding adds exact zeros to
+// both sums. Screen and decision as in k_fb_collect_lds.
+constexpr int FB_REG_M = 16;
+constexpr int FB_REG_ROWS = 768;   // listed rows per LDS chunk (76 bytes each: 57 KB)
+
+size_t fb_collect_reg_bytes() { return static_cast<size_t>(FB_REG_ROWS) * (FB_REG_M * sizeof(float) + sizeof(double) + sizeof(int)); }
+
+__global__ __launch_bounds__(FB_THREADS) void k_fb_collect_reg(const float* __restrict__ X, int n, int m,
+                                                               const int* __restrict__ fb_count,
+                                                               const int* __restrict__ fb_list,
+                                                               const float* __restrict__ fb_bound, int rows_cap,
+                                                               int* __restrict__ cnt, double* __restrict__ bd,
+                                                               int* __restrict__ bj)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char fb_smem[];
+    const int total = min(*fb_count, rows_cap);
+    if (total == 0) return;
+    float4* xr = reinterpret_cast<float4*>(fb_smem);                                 // [FB_REG_ROWS][4]
+    double* rb = reinterpret_cast<double*>(fb_smem + FB_REG_ROWS * FB_REG_M * 4);    // [FB_REG_ROWS]
+    int* ri = reinterpret_cast<int*>(rb + FB_REG_ROWS);                              // [FB_REG_ROWS]
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x / WAVE;
+    const double slack = 1.0 + (m + 10) * 0x1p-24;
+    for (int r0 = 0; r0 < total; r0 += FB_REG_ROWS) {
+        const int nr = min(FB_REG_ROWS, total - r0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nr; t += FB_THREADS) {
+            const float B = fb_bound[r0 + t];
+            ri[t] = fb_list[r0 + t];
+            rb[t] = B < __uint_as_float(0x7F800000u) ? static_cast<double>(B) : -1.0;   // -1: no bound
+        }
+        float* xrf = reinterpret_cast<float*>(xr);
+        for (int e = threadIdx.x; e < nr * FB_REG_M; e += FB_THREADS) {
+            const int t = e / FB_REG_M, c = e - t * FB_REG_M;
+            xrf[e] = c < m ? X[static_cast<size_t>(fb_list[r0 + t]) * m + c] : 0.f;
         }
         __syncthreads();
-        const int j = c0 + lane;
-        const float* xj = xc + lane * ld;
-        for (int t = wave; t < total; t += FB_THREADS / WAVE) {
-            const float B = fb_bound[t];
-            if (!(B < __uint_as_float(0x7F800000u))) continue;
-            const int i = fb_list[t];
-            if (j >= n || j == i) continue;
-            const float* xi = X + static_cast<size_t>(i) * m;
-            double d = 0.0;
-            for (int c = 0; c < m; ++c) {
-                const double u = static_cast<double>(xi[c]) - static_cast<double>(xj[c]);
-                d = fma(u, u, d);
-            }
-            if (d <= static_cast<double>(B)) {
-                const int slot = atomicAdd(&cnt[t], 1);
-                if (slot < FB_CAP) {
-                    bd[static_cast<size_t>(t) * FB_CAP + slot] = d;
-                    bj[static_cast<size_t>(t) * FB_CAP + slot] = j;
+        for (int c0 = (blockIdx.x * (FB_THREADS / WAVE) + wave) * WAVE; c0 < n;
+             c0 += gridDim.x * FB_THREADS) {
+            const int j = c0 + lane;
+            float xj[FB_REG_M];
+#pragma unroll
+            for (int c = 0; c < FB_REG_M; ++c) xj[c] = (j < n && c < m) ? X[static_cast<size_t>(j) * m + c] : 0.f;
+            for (int t = 0; t < nr; ++t) {
+                const double B = rb[t];
+                if (B < 0.0) continue;
+                float xi[FB_REG_M];
+#pragma unroll
+                for (int q = 0; q < FB_REG_M / 4; ++q) {
+                    const float4 v = xr[t * (FB_REG_M / 4) + q];
+                    xi[4 * q] = v.x;
+                    xi[4 * q + 1] = v.y;
+                    xi[4 * q + 2] = v.z;
+                    xi[4 * q + 3] = v.w;
+                }
+                float d32 = 0.f;
+#pragma unroll
+                for (int c = 0; c < FB_REG_M; ++c) {
+                    const float u = xi[c] - xj[c];
+                    d32 = fmaf(u, u, d32);
+                }
+                const bool near = !(d32 < __uint_as_float(0x7F800000u)) || static_cast<double>(d32) <= B * slack;
+                if (near && j < n && j != ri[t]) {
+                    double d = 0.0;
+#pragma unroll
+                    for (int c = 0; c < FB_REG_M; ++c) {
+                        const double u = static_cast<double>(xi[c]) - static_cast<double>(xj[c]);
+                        d = fma(u, u, d);
+                    }
+                    if (d <= B) {
+                        const int slot = atomicAdd(&cnt[r0 + t], 1);
+                        if (slot < FB_CAP) {
+                            bd[static_cast<size_t>(r0 + t) * FB_CAP + slot] = d;
+                            bj[static_cast<size_t>(r0 + t) * FB_CAP + slot] = j;
+                        }
+                    }
                 }
             }
         }
@@ -1217,10 +1348,16 @@ hipError_t launch_fallback(const float* X, int n, int m, int k, const int* fb_co
     const int cap = fallback_rows_cap(n);
     hipError_t e = hipMemsetAsync(fw.cnt, 0, static_cast<size_t>(cap) * sizeof(int), st);
     if (e != hipSuccess) return e;
-    if (m <= FB_LDS_M) {
+    if (m <= FB_REG_M) {
+        const int waves = (n + WAVE - 1) / WAVE, blocks = (waves + FB_THREADS / WAVE - 1) / (FB_THREADS / WAVE);
+        hipLaunchKernelGGL(k_fb_collect_reg, dim3(blocks < 2048 ? blocks : 2048), dim3(FB_THREADS),
+                           fb_collect_reg_bytes(), st, X, n, m, fb_count, fb_list, fw.bound, cap, fw.cnt, fw.bd,
+                           fw.bj);
+    } else if (m <= FB_LDS_M) {
         const int stages = (n + FB_STAGE - 1) / FB_STAGE;
-        hipLaunchKernelGGL(k_fb_collect_lds, dim3(stages < 2048 ? stages : 2048), dim3(FB_THREADS), 0, st, X, n, m,
-                           fb_count, fb_list, fw.bound, cap, fw.cnt, fw.bd, fw.bj);
+        hipLaunchKernelGGL(k_fb_collect_lds, dim3(stages < 2048 ? stages : 2048), dim3(FB_THREADS),
+                           fb_collect_lds_bytes(m), st, X, n, m, fb_count, fb_list, fw.bound, cap, fw.cnt, fw.bd,
+                           fw.bj);
     } else {
         const int chunks = (n + FB_CHUNK - 1) / FB_CHUNK;
         hipLaunchKernelGGL(k_fb_collect, dim3(chunks < 2048 ? chunks : 2048), dim3(FB_THREADS), 0, st, X, n, m,

@@ -103,7 +103,7 @@ def test_knn_forced_fallback_matches(gpu_lib):
     ctx.close()
 
 
-@pytest.mark.parametrize("mode,m", [("f32", 3), ("bf16", 64), ("f32", 200)])
+@pytest.mark.parametrize("mode,m", [("f32", 3), ("f32", 16), ("bf16", 64), ("bf16", 128), ("f32", 200)])
 def test_knn_forced_fallback_duplicates(gpu_lib, mode, m):
     """Every row through the exact fallback: 1500 copies of one point (their
     bounded-pass buffers overflow, so they take the full scan) among 700
