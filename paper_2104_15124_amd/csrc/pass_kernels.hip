@@ -108,8 +108,6 @@ __device__ __forceinline__ double row_kernel_sum16(const int32_t* __restrict__ i
     return s;
 }
 
-// psi_i = sum_r K_ir / (n (pi e b_i^2)^{d/2}), rho_i = 2 psi_i^beta
-// (Section 2.1 density eqs.; Algorithm 1 caption)
 // Row i spans entries [rowptr_i, rowptr_{i+1}), or [i k, (i + 1) k) when rowptr is null.
 __device__ __forceinline__ int64_t row_begin(const int64_t* __restrict__ rowptr, int i, int k)
 {
@@ -120,6 +118,86 @@ __device__ __forceinline__ int row_length(const int64_t* __restrict__ rowptr, in
     return rowptr ? static_cast<int>(rowptr[i + 1] - rowptr[i]) : k;
 }
 
+// Row sums of the 64 rows [base, base + 64) of a wavefront: four rows at a time,
+// RL lanes per row, each sum formed exactly as row_kernel_sum16 forms it; the sum
+// of row base + t is handed to lane t, so that the per-row epilogue (float64
+// powers) runs once per 64 rows with every lane busy rather than once per four.
+// Rows of a fixed k <= 64 entries issue the next four rows' loads before the
+// current four are summed. w is the width gathered by column (b or rho); rows at
+// or past n sum to 0.
+__device__ __forceinline__ double wave_row_sums(const int32_t* __restrict__ idx, const float* __restrict__ d2,
+                                                const int64_t* __restrict__ rowptr, int n, int k,
+                                                const float* __restrict__ w, double e, int base)
+{
+    constexpr int GROUPS = WAVE / RL;   // rows summed at a time
+    constexpr int ITS = WAVE / GROUPS;
+    const int lane = lane_id();
+    const int g = lane / RL, gl = lane % RL;
+    double mine = 0.0;
+    if (rowptr == nullptr && k <= 4 * RL) {
+        int jv[4];
+        float dv[4];
+        auto load = [&](int it, int (&jo)[4], float (&dout)[4]) {
+            const int i = base + GROUPS * it + g;
+            const size_t rb = static_cast<size_t>(i < n ? i : 0) * k;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int r = gl + u * RL;
+                const bool ok = i < n && r < k;
+                dout[u] = ok ? d2[rb + r] : 0.f;
+                jo[u] = ok ? idx[rb + r] : 0;
+            }
+        };
+        load(0, jv, dv);
+#pragma unroll 1
+        for (int it = 0; it < ITS; ++it) {
+            const int i = base + GROUPS * it + g;
+            float rj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) rj[u] = w[jv[u]];
+            const double wi = static_cast<double>(w[i < n ? i : n - 1]);
+            int jn[4];
+            float dn[4];
+            if (it + 1 < ITS) load(it + 1, jn, dn);
+            const double inv = 1.0 / (e * wi);
+            double s = 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (i < n && gl + u * RL < k) {
+                    const double x = static_cast<double>(dv[u]) * inv / static_cast<double>(rj[u]);
+                    s += static_cast<double>(expf(-static_cast<float>(x)));
+                }
+            }
+#pragma unroll
+            for (int o = 1; o < RL; o <<= 1) s += shfl_xor_f64(s, o);
+            const double t = __longlong_as_double(
+                static_cast<long long>(shfl_u64(static_cast<uint64_t>(__double_as_longlong(s)), RL * (lane % GROUPS))));
+            if (lane / GROUPS == it) mine = t;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                jv[u] = jn[u];
+                dv[u] = dn[u];
+            }
+        }
+        return mine;
+    }
+#pragma unroll 1
+    for (int it = 0; it < ITS; ++it) {
+        const int i = base + GROUPS * it + g;
+        const int ic = i < n ? i : n - 1;
+        const int64_t rb = row_begin(rowptr, ic, k);
+        const double wi = static_cast<double>(w[ic]);
+        const double s = row_kernel_sum16(idx + rb, d2 + rb, i < n ? row_length(rowptr, ic, k) : 0, w,
+                                          1.0 / (e * wi), gl);
+        const double t = __longlong_as_double(
+            static_cast<long long>(shfl_u64(static_cast<uint64_t>(__double_as_longlong(s)), RL * (lane % GROUPS))));
+        if (lane / GROUPS == it) mine = t;
+    }
+    return mine;
+}
+
+// psi_i = sum_r K_ir / (n (pi e b_i^2)^{d/2}), rho_i = 2 psi_i^beta
+// (Section 2.1 density eqs.; Algorithm 1 caption). 64 rows per wavefront.
 __global__ __launch_bounds__(256) void k_density(const int32_t* __restrict__ idx, const float* __restrict__ d2,
                                                  const int64_t* __restrict__ rowptr, int n, int k,
                                                  const float* __restrict__ b, double e,
@@ -127,14 +205,12 @@ __global__ __launch_bounds__(256) void k_density(const int32_t* __restrict__ idx
                                                  float* __restrict__ rho, float* __restrict__ psi)
 {
     if (e_dev) e = *e_dev;
-    const int lane = lane_id();
-    const int i = (blockIdx.x * 256 + threadIdx.x) / RL;
-    const int gl = lane % RL;
-    if (i >= n) return;   // whole lane groups
-    const double bi = static_cast<double>(b[i]);
-    const int64_t rb = row_begin(rowptr, i, k);
-    const double s = row_kernel_sum16(idx + rb, d2 + rb, row_length(rowptr, i, k), b, 1.0 / (e * bi), gl);
-    if (gl == 0) {
+    const int base = (blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * WAVE;
+    if (base >= n) return;
+    const double s = wave_row_sums(idx, d2, rowptr, n, k, b, e, base);
+    const int i = base + lane_id();
+    if (i < n) {
+        const double bi = static_cast<double>(b[i]);
         const double pi = 3.14159265358979323846;
         const double w = static_cast<double>(n) * pow(pi * e * bi * bi, 0.5 * d);
         const double p = s / w;
@@ -406,15 +482,12 @@ __global__ __launch_bounds__(256) void k_qpass(const int32_t* __restrict__ idx, 
                                                double* __restrict__ qa)
 {
     if (e_dev) e = *e_dev;
-    const int lane = lane_id();
-    const int i = (blockIdx.x * 256 + threadIdx.x) / RL;
-    const int gl = lane % RL;
-    if (i >= n) return;   // whole lane groups
-    const double ri = static_cast<double>(rho[i]);
-    const int64_t rb = row_begin(rowptr, i, k);
-    const double s = row_kernel_sum16(idx + rb, d2 + rb, row_length(rowptr, i, k), rho, 1.0 / (e * ri), gl);
-    if (gl == 0) {
-        const double P = 0.5 * ri;
+    const int base = (blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * WAVE;
+    if (base >= n) return;
+    const double s = wave_row_sums(idx, d2, rowptr, n, k, rho, e, base);
+    const int i = base + lane_id();
+    if (i < n) {
+        const double P = 0.5 * static_cast<double>(rho[i]);
         const double q = pow(P, -d) * s;
         qa[i] = pow(q, -alpha);
     }
@@ -630,7 +703,7 @@ hipError_t launch_adhoc_bandwidth(const float* d2, int n, int k, int k0, float* 
 hipError_t launch_density(const int32_t* idx, const float* d2, int n, int k, const float* b, double e,
                           const double* e_dev, double d, double beta, float* rho, float* psi, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_density, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, idx, d2, nullptr, n, k, b,
+    hipLaunchKernelGGL(k_density, dim3((n + 4 * WAVE - 1) / (4 * WAVE)), dim3(256), 0, st, idx, d2, nullptr, n, k, b,
                        e, e_dev, d, beta, rho, psi);
     return hipGetLastError();
 }
@@ -673,7 +746,7 @@ hipError_t launch_grid_scale(const float* ref, const float* rho, int n, double* 
 hipError_t launch_qpass(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
                         const double* e_dev, double alpha, double d, double* qa, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_qpass, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, idx, d2, nullptr, n, k, rho,
+    hipLaunchKernelGGL(k_qpass, dim3((n + 4 * WAVE - 1) / (4 * WAVE)), dim3(256), 0, st, idx, d2, nullptr, n, k, rho,
                        e, e_dev, alpha, d, qa);
     return hipGetLastError();
 }
@@ -721,7 +794,7 @@ hipError_t launch_density_csr(const int64_t* rowptr, const int32_t* col, const f
                               double e, const double* e_dev, double d, double beta, float* rho, float* psi,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL(k_density, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, col, d2, rowptr, n, 0, b,
+    hipLaunchKernelGGL(k_density, dim3((n + 4 * WAVE - 1) / (4 * WAVE)), dim3(256), 0, st, col, d2, rowptr, n, 0, b,
                        e, e_dev, d, beta, rho, psi);
     return hipGetLastError();
 }
@@ -765,7 +838,7 @@ hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* rowid, const int
 hipError_t launch_qpass_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, const float* rho,
                             double e, const double* e_dev, double alpha, double d, double* qa, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_qpass, dim3((n + 256 / RL - 1) / (256 / RL)), dim3(256), 0, st, col, d2, rowptr, n, 0, rho,
+    hipLaunchKernelGGL(k_qpass, dim3((n + 4 * WAVE - 1) / (4 * WAVE)), dim3(256), 0, st, col, d2, rowptr, n, 0, rho,
                        e, e_dev, alpha, d, qa);
     return hipGetLastError();
 }
