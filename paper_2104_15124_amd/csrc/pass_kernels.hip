@@ -493,8 +493,28 @@ __global__ __launch_bounds__(256) void k_qpass(const int32_t* __restrict__ idx, 
     }
 }
 
+// Ascending sort of one 32-bit key per lane across the wavefront: the bitonic
+// network of bitonic_sort with one key per lane, each exchange a compare, a
+// constant lane mask and a select.
+__device__ __forceinline__ uint32_t wave_sort_u32(uint32_t v)
+{
+#pragma unroll
+    for (int kb = 2; kb <= WAVE; kb <<= 1) {
+#pragma unroll
+        for (int j = kb >> 1; j > 0; j >>= 1) {
+            const uint32_t o = xor_lane(v, j);
+            const uint64_t up = kb < WAVE ? lanes_bit_clear(kb) : ~0ull;
+            const uint64_t keep_min = ~(up ^ lanes_bit_clear(j));
+            const uint64_t take = __ballot(o < v) ^ ~keep_min;
+            v = __builtin_amdgcn_inverse_ballot_w64(take) ? o : v;
+        }
+    }
+    return v;
+}
+
 // Kt_ir = K_ir qa_i qa_j (K_ir in float32 as in the row sums), D_i = sum_r Kt_ir
-// (float64, compensated), then the requested
+// (float64: each lane's terms compensated, the lanes added in a fixed xor
+// butterfly), then the requested
 // output kind, the row sorted by column. For KVB_OUT_SYMMETRIC this pass
 // stores Kt and the finishing pass divides by S_i S_j.
 template <int E>
@@ -537,17 +557,43 @@ __global__ __launch_bounds__(256) void k_assemble(const int32_t* __restrict__ id
             acc.add(kt[s]);
         }
     }
-    // fixed-order butterfly of the (sum, compensation) pairs
-    double Ds = acc.s, Dc = acc.c;
+    // the lanes' compensated sums of at most E terms, added in a fixed xor
+    // butterfly (every lane ends with the same D_i; 64 positive float64 terms)
+    double Di = acc.value();
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
-        const double os = shfl_xor_f64(Ds, o), oc = shfl_xor_f64(Dc, o);
-        const double t = Ds + os;
-        Dc += oc + ((fabs(Ds) >= fabs(os)) ? ((Ds - t) + os) : ((os - t) + Ds));
-        Ds = t;
-    }
-    const double Di = Ds + Dc;
+    for (int o = WAVE / 2; o > 0; o >>= 1) Di += shfl_xor_f64(Di, o);
     const double Pi = 0.5 * ri;
+    if (E == 1 && n < (1 << 26)) {
+        // one entry per lane (k <= 64) and columns below 2^26: 32-bit keys
+        // column << 6 | lane, sorted across the wavefront; each value is then
+        // read from the lane its key names
+        float v = 0.f;
+        if (cj[0] >= 0) {
+            double w;
+            if (out_kind == KVB_OUT_MARKOV)
+                w = kt[0] / Di;
+            else if (out_kind == KVB_OUT_GENERATOR)
+                w = (kt[0] / Di - (cj[0] == i ? 1.0 : 0.0)) / (e * Pi * Pi);
+            else
+                w = kt[0];
+            v = static_cast<float>(w);
+        }
+        uint32_t key = cj[0] >= 0 ? ((static_cast<uint32_t>(cj[0]) << 6) | static_cast<uint32_t>(lane)) : ~0u;
+        key = wave_sort_u32(key);
+        const float vs = __uint_as_float(static_cast<uint32_t>(
+            __shfl(static_cast<int>(__float_as_uint(v)), static_cast<int>(key & 63u), WAVE)));
+        if (lane < k) {
+            col[static_cast<size_t>(i) * k + lane] = static_cast<int32_t>(key >> 6);
+            val[static_cast<size_t>(i) * k + lane] = vs;
+        }
+        if (lane == 0) {
+            rowptr[i] = static_cast<int64_t>(i) * k;
+            if (i == n - 1) rowptr[n] = static_cast<int64_t>(n) * k;
+            if (Pout) Pout[i] = Pi;
+            Dout[i] = Di;
+        }
+        return;
+    }
     uint64_t key[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
@@ -602,8 +648,9 @@ __global__ __launch_bounds__(256) void k_symmetric_finish(int64_t nnz, int k, co
 
 // The normalisation over a CSR pattern whose rows are already ordered by
 // column: one wavefront per row of any length. Kt_ir is formed as in
-// k_assemble (lanes strided over the row, compensated float64 sum, the same
-// butterfly); the output value, written in place, takes Kt_ir from registers
+// k_assemble (lanes strided over the row); D_i is a compensated float64 sum,
+// the lanes' (sum, compensation) pairs combined in a fixed butterfly, since a
+// row here may hold thousands of entries; the output value, written in place, takes Kt_ir from registers
 // for a row's first 128 entries and forms it again, identically, beyond. For KVB_OUT_SYMMETRIC the value is Kt and
 // k_symmetric_rows finishes it.
 __global__ __launch_bounds__(256) void k_assemble_rows(const int64_t* __restrict__ rowptr,
