@@ -117,6 +117,19 @@ def test_pipeline_k128_lifted_sphere(gpu_lib):
 
 
 @pytest.mark.parametrize("entry", ["calls", "build"])
+def test_pipeline_mixture_k64_curve_rows(gpu_lib, entry):
+    """The mixture recipe at its own m = 16, k = 64 (n = 20000), every row and
+    entry against the oracle. Through the single call the passes run on the
+    curve-ordered rows (the row pass, the row sums of 64 rows per wavefront,
+    the assembly's 32-bit-key row sort writing rows by sample id); through the
+    separate entry points they run in sample order."""
+    import dataclasses
+    w = dataclasses.replace(workloads.WORKLOADS["gmm_n8m"], n=20000, mode="f32")
+    compare_pipeline(gpu_lib, f"gmm_n20000_k64_{entry}", workloads.make(w.name, seed=3, n=w.n), w, mode="f32",
+                     entry=entry)
+
+
+@pytest.mark.parametrize("entry", ["calls", "build"])
 def test_pipeline_k200_mixture(gpu_lib, entry):
     """k = 200 (margin 56, k + margin = 256: the largest list) on the mixture
     recipe at n = 5000: the widest form of the passes (four row slices per
