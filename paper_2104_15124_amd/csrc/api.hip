@@ -304,7 +304,7 @@ static int knn_run(kvb_ctx ctx, size_t base, const float* X, int64_t n, int32_t 
                 const size_t tile_bytes = size_t(32) * kpad * esz;
                 KVB_HIP(ctx, hipMemsetAsync(static_cast<char*>(Bc) + size_t(ctiles - 1) * tile_bytes, 0, tile_bytes,
                                             ctx->stream));
-                KVB_HIP(ctx, kvb::launch_prep_rows_curve(X, nn, m, mu, split, kpad, Aq, Bc, ynorm2, rmax, cid, pos,
+                KVB_HIP(ctx, kvb::launch_prep_rows_curve(Xs, nn, m, mu, split, kpad, Aq, Bc, ynorm2, rmax,
                                                          ctx->stream));
                 const double u = std::ldexp(1.0, -24);
                 crv.perm = cid;

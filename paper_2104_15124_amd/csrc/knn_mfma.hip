@@ -222,8 +222,8 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
 // k_prep_rows for FP32 operands of rows of at most PREP_THREAD_M coordinates,
 // by operand row (the BF16 split terms stay with the wavefront per row, whose
 // 2-byte query operand writes coalesce):
-// thread r prepares operand row r from sample cid[r] (cid null: sample r; a
-// negative entry or r >= n: a padding row of zeros), with the same values as
+// thread r prepares operand row r from input row r (r >= n: a padding row of
+// zeros), with the same values as
 // k_prep_rows (|y|^2 summed over the row in column order). Consecutive
 // threads then write consecutive query operand rows and, in the candidate
 // operand, whose k-step blocks hold 32 consecutive rows, consecutive
@@ -233,13 +233,12 @@ constexpr int PREP_THREAD_M = 64;
 __global__ __launch_bounds__(256) void k_prep_rows_thread(const float* __restrict__ X, int n, int npad, int m,
                                                           const double* __restrict__ mu, int split, int kpad,
                                                           void* __restrict__ Aq, void* __restrict__ Bc,
-                                                          float* __restrict__ ynorm2, unsigned* __restrict__ rmax_bits,
-                                                          const int* __restrict__ cid)
+                                                          float* __restrict__ ynorm2, unsigned* __restrict__ rmax_bits)
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
     float wmax = 0.f;
     if (r < npad) {
-        const int i = r < n ? (cid ? cid[r] : r) : -1;
+        const int i = r < n ? r : -1;
         const bool real = i >= 0;
         const int ib = r, ia = r;
         const float* x = X + static_cast<size_t>(real ? i : 0) * m;
@@ -899,7 +898,7 @@ static void launch_rows(const float* X, int n, int npad, int m, const double* mu
 {
     if (m <= PREP_THREAD_M && split == 0 && !brow && !arow)
         hipLaunchKernelGGL(k_prep_rows_thread, dim3((npad + 255) / 256), dim3(256), 0, st, X, n, npad, m, mu, split,
-                           kpad, Aq, Bc, ynorm2, rmax_bits, nullptr);
+                           kpad, Aq, Bc, ynorm2, rmax_bits);
     else
         hipLaunchKernelGGL(k_prep_rows, dim3(prep_blocks(npad)), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq,
                            Bc, ynorm2, rmax_bits, brow, arow);
@@ -913,17 +912,13 @@ hipError_t launch_prep_rows(const float* X, int n, int m, const double* mu, int 
     return hipGetLastError();
 }
 
-hipError_t launch_prep_rows_curve(const float* X, int n, int m, const double* mu, int split, int kpad, void* Aq,
-                                  void* Bc, float* ynorm2, unsigned* rmax_bits, const int* cid, const int* pos,
-                                  hipStream_t st)
+// Xs holds the samples in curve order, so operand row p is input row p: the
+// sample-order kernels without row maps, reading and writing rows in order
+hipError_t launch_prep_rows_curve(const float* Xs, int n, int m, const double* mu, int split, int kpad, void* Aq,
+                                  void* Bc, float* ynorm2, unsigned* rmax_bits, hipStream_t st)
 {
     const int npad = (n + 31) / 32 * 32;
-    if (m <= PREP_THREAD_M && split == 0)
-        hipLaunchKernelGGL(k_prep_rows_thread, dim3((npad + 255) / 256), dim3(256), 0, st, X, n, npad, m, mu, split,
-                           kpad, Aq, Bc, ynorm2, rmax_bits, cid);
-    else
-        hipLaunchKernelGGL(k_prep_rows, dim3(prep_blocks(npad)), dim3(256), 0, st, X, n, npad, m, mu, split, kpad, Aq,
-                           Bc, ynorm2, rmax_bits, pos, pos);
+    launch_rows(Xs, n, npad, m, mu, split, kpad, Aq, Bc, ynorm2, rmax_bits, nullptr, nullptr, st);
     return hipGetLastError();
 }
 

@@ -110,10 +110,10 @@ hipError_t launch_prep(const float* X, int n, int m, int split, int kpad, double
 hipError_t launch_colmean(const float* X, int n, int m, double* colpart, int colblocks, double* mu, hipStream_t st);
 hipError_t launch_prep_rows(const float* X, int n, int m, const double* mu, int split, int kpad, void* Aq, void* Bc,
                             float* ynorm2, unsigned* rmax_bits, const int* brow, const int* arow, hipStream_t st);
-// the operands in curve order: operand row p from sample cid[p] (pos = the inverse map)
-hipError_t launch_prep_rows_curve(const float* X, int n, int m, const double* mu, int split, int kpad, void* Aq,
-                                  void* Bc, float* ynorm2, unsigned* rmax_bits, const int* cid, const int* pos,
-                                  hipStream_t st);
+// the operands in curve order: operand row p from Xs[p], the curve-ordered copy
+// of the samples (Xs[p] = X[cid[p]], written by launch_gather_rows), read in order
+hipError_t launch_prep_rows_curve(const float* Xs, int n, int m, const double* mu, int split, int kpad, void* Aq,
+                                  void* Bc, float* ynorm2, unsigned* rmax_bits, hipStream_t st);
 int mfma_kstep(int split);
 int mfma_pick_ksteps(int split, int needed);
 // ba == nullptr: exact all-pairs selection over n rows; otherwise the bucketed
