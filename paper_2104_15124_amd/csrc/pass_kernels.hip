@@ -118,19 +118,29 @@ __device__ __forceinline__ int row_length(const int64_t* __restrict__ rowptr, in
     return rowptr ? static_cast<int>(rowptr[i + 1] - rowptr[i]) : k;
 }
 
-// Row sums of the 64 rows [base, base + 64) of a wavefront: four rows at a time,
-// RL lanes per row, each sum formed exactly as row_kernel_sum16 forms it; the sum
-// of row base + t is handed to lane t, so that the per-row epilogue (float64
-// powers) runs once per 64 rows with every lane busy rather than once per four.
-// Rows of a fixed k <= 64 entries issue the next four rows' loads before the
-// current four are summed. w is the width gathered by column (b or rho); rows at
-// or past n sum to 0.
+// Row sums of the 4 its rows [base, base + 4 its) of a wavefront (its <= 16):
+// four rows at a time, RL lanes per row, each sum formed exactly as
+// row_kernel_sum16 forms it; the sum of row base + t is handed to lane t, so
+// that the per-row epilogue (float64 powers) runs once per 4 its rows with that
+// many lanes busy rather than once per four rows. Rows of a fixed k <= 64
+// entries issue the next four rows' loads before the current four are summed.
+// w is the width gathered by column (b or rho); rows at or past n sum to 0.
+constexpr int ROWSUM_WAVES = 8192;   // fewest wavefronts a launch is given (8 per SIMD)
+
+__host__ __device__ constexpr int rowsum_its(int n)
+{
+    return n >= 16 * 4 * ROWSUM_WAVES ? 16 : (n / (4 * ROWSUM_WAVES) > 1 ? n / (4 * ROWSUM_WAVES) : 1);
+}
+
+// blocks of four wavefronts, 16 rowsum_its(n) rows each
+static int rowsum_blocks(int n) { return (n + 16 * rowsum_its(n) - 1) / (16 * rowsum_its(n)); }
+
 __device__ __forceinline__ double wave_row_sums(const int32_t* __restrict__ idx, const float* __restrict__ d2,
                                                 const int64_t* __restrict__ rowptr, int n, int k,
-                                                const float* __restrict__ w, double e, int base)
+                                                const float* __restrict__ w, double e, int base, int its)
 {
     constexpr int GROUPS = WAVE / RL;   // rows summed at a time
-    constexpr int ITS = WAVE / GROUPS;
+    const int ITS = its;
     const int lane = lane_id();
     const int g = lane / RL, gl = lane % RL;
     double mine = 0.0;
@@ -197,7 +207,8 @@ __device__ __forceinline__ double wave_row_sums(const int32_t* __restrict__ idx,
 }
 
 // psi_i = sum_r K_ir / (n (pi e b_i^2)^{d/2}), rho_i = 2 psi_i^beta
-// (Section 2.1 density eqs.; Algorithm 1 caption). 64 rows per wavefront.
+// (Section 2.1 density eqs.; Algorithm 1 caption). 4 rowsum_its(n) rows per
+// wavefront (64 from n = 2^19 on).
 __global__ __launch_bounds__(256) void k_density(const int32_t* __restrict__ idx, const float* __restrict__ d2,
                                                  const int64_t* __restrict__ rowptr, int n, int k,
                                                  const float* __restrict__ b, double e,
@@ -205,11 +216,12 @@ __global__ __launch_bounds__(256) void k_density(const int32_t* __restrict__ idx
                                                  float* __restrict__ rho, float* __restrict__ psi)
 {
     if (e_dev) e = *e_dev;
-    const int base = (blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * WAVE;
+    const int its = rowsum_its(n);
+    const int base = (blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * 4 * its;
     if (base >= n) return;
-    const double s = wave_row_sums(idx, d2, rowptr, n, k, b, e, base);
+    const double s = wave_row_sums(idx, d2, rowptr, n, k, b, e, base, its);
     const int i = base + lane_id();
-    if (i < n) {
+    if (lane_id() < 4 * its && i < n) {
         const double bi = static_cast<double>(b[i]);
         const double pi = 3.14159265358979323846;
         const double w = static_cast<double>(n) * pow(pi * e * bi * bi, 0.5 * d);
@@ -482,11 +494,12 @@ __global__ __launch_bounds__(256) void k_qpass(const int32_t* __restrict__ idx, 
                                                double* __restrict__ qa)
 {
     if (e_dev) e = *e_dev;
-    const int base = (blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * WAVE;
+    const int its = rowsum_its(n);
+    const int base = (blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * 4 * its;
     if (base >= n) return;
-    const double s = wave_row_sums(idx, d2, rowptr, n, k, rho, e, base);
+    const double s = wave_row_sums(idx, d2, rowptr, n, k, rho, e, base, its);
     const int i = base + lane_id();
-    if (i < n) {
+    if (lane_id() < 4 * its && i < n) {
         const double P = 0.5 * static_cast<double>(rho[i]);
         const double q = pow(P, -d) * s;
         qa[i] = pow(q, -alpha);
@@ -750,7 +763,7 @@ hipError_t launch_adhoc_bandwidth(const float* d2, int n, int k, int k0, float* 
 hipError_t launch_density(const int32_t* idx, const float* d2, int n, int k, const float* b, double e,
                           const double* e_dev, double d, double beta, float* rho, float* psi, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_density, dim3((n + 4 * WAVE - 1) / (4 * WAVE)), dim3(256), 0, st, idx, d2, nullptr, n, k, b,
+    hipLaunchKernelGGL(k_density, dim3(rowsum_blocks(n)), dim3(256), 0, st, idx, d2, nullptr, n, k, b,
                        e, e_dev, d, beta, rho, psi);
     return hipGetLastError();
 }
@@ -793,7 +806,7 @@ hipError_t launch_grid_scale(const float* ref, const float* rho, int n, double* 
 hipError_t launch_qpass(const int32_t* idx, const float* d2, int n, int k, const float* rho, double e,
                         const double* e_dev, double alpha, double d, double* qa, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_qpass, dim3((n + 4 * WAVE - 1) / (4 * WAVE)), dim3(256), 0, st, idx, d2, nullptr, n, k, rho,
+    hipLaunchKernelGGL(k_qpass, dim3(rowsum_blocks(n)), dim3(256), 0, st, idx, d2, nullptr, n, k, rho,
                        e, e_dev, alpha, d, qa);
     return hipGetLastError();
 }
@@ -841,7 +854,7 @@ hipError_t launch_density_csr(const int64_t* rowptr, const int32_t* col, const f
                               double e, const double* e_dev, double d, double beta, float* rho, float* psi,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL(k_density, dim3((n + 4 * WAVE - 1) / (4 * WAVE)), dim3(256), 0, st, col, d2, rowptr, n, 0, b,
+    hipLaunchKernelGGL(k_density, dim3(rowsum_blocks(n)), dim3(256), 0, st, col, d2, rowptr, n, 0, b,
                        e, e_dev, d, beta, rho, psi);
     return hipGetLastError();
 }
@@ -885,7 +898,7 @@ hipError_t launch_chi_csr(const int64_t* rowptr, const int32_t* rowid, const int
 hipError_t launch_qpass_csr(const int64_t* rowptr, const int32_t* col, const float* d2, int n, const float* rho,
                             double e, const double* e_dev, double alpha, double d, double* qa, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_qpass, dim3((n + 4 * WAVE - 1) / (4 * WAVE)), dim3(256), 0, st, col, d2, rowptr, n, 0, rho,
+    hipLaunchKernelGGL(k_qpass, dim3(rowsum_blocks(n)), dim3(256), 0, st, col, d2, rowptr, n, 0, rho,
                        e, e_dev, alpha, d, qa);
     return hipGetLastError();
 }
