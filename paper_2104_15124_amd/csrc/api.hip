@@ -925,7 +925,7 @@ int kvb_build(kvb_ctx ctx, const float* X, int64_t n, int32_t m, int32_t k, int3
         KVB_HIP(ctx, kvb::launch_qpass(pidx, pd2, nn, k, prho, 0.0, &bd->b.e_star, alpha, d, qa, st));
     }
     if (cv_rows)
-        KVB_HIP(ctx, kvb::launch_scatter_samples(cr.cid, nn, pb, b, prho, rho, ppsi, psi, st));
+        KVB_HIP(ctx, kvb::launch_gather_samples(cr.pos, nn, pb, b, prho, rho, ppsi, psi, st));
     {
         Prof pr(ctx, KVB_PROF_ASSEMBLE);
         KVB_HIP(ctx, kvb::launch_assemble(pidx, pd2, nn, k, prho, 0.0, &bd->b.e_star, qa, out_kind, rowptr, col, val,

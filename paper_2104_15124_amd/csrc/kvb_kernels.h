@@ -170,9 +170,9 @@ hipError_t launch_assemble(const int32_t* idx, const float* d2, int n, int k, co
 // the k-NN rows in curve order (row p = sample cid[p]), neighbours as curve positions, and their bandwidths
 hipError_t launch_curve_rows(const int32_t* idx, const float* d2, int n, int k, int k0, const int32_t* cid,
                              const int32_t* pos, int32_t* idx_c, float* d2_c, float* b_c, hipStream_t st);
-// out[cid[p]] = in[p] for up to three vectors (null pointers skipped)
-hipError_t launch_scatter_samples(const int32_t* cid, int n, const float* a_c, float* a, const float* b_c, float* b,
-                                  const float* c_c, float* c, hipStream_t st);
+// out[i] = in[pos[i]] for up to three vectors (null pointers skipped)
+hipError_t launch_gather_samples(const int32_t* pos, int n, const float* a_c, float* a, const float* b_c, float* b,
+                                 const float* c_c, float* c, hipStream_t st);
 
 // learned partitioner: MLP (mlp_kernels.hip)
 hipError_t launch_gemm_nt(const uint16_t* A, int lda, const uint16_t* B, int ldb, int M, int N, int K,

@@ -54,15 +54,18 @@ __global__ __launch_bounds__(256) void k_curve_rows(const int32_t* __restrict__ 
     }
 }
 
-// out[cid[p]] = in[p] for up to three per-sample vectors (null: skipped)
-__global__ __launch_bounds__(256) void k_scatter_samples(const int32_t* __restrict__ cid, int n,
-                                                         const float* __restrict__ a_c, float* __restrict__ a,
-                                                         const float* __restrict__ b_c, float* __restrict__ b,
-                                                         const float* __restrict__ c_c, float* __restrict__ c)
+// out[i] = in[pos[i]] for up to three per-sample vectors (null: skipped): the
+// curve-ordered vectors back in sample order, written in order (the gathers
+// read 4-byte values from arrays small enough to stay in the caches, where
+// the scatter out[cid[p]] = in[p] wrote 4-byte values to random places)
+__global__ __launch_bounds__(256) void k_gather_samples(const int32_t* __restrict__ pos, int n,
+                                                        const float* __restrict__ a_c, float* __restrict__ a,
+                                                        const float* __restrict__ b_c, float* __restrict__ b,
+                                                        const float* __restrict__ c_c, float* __restrict__ c)
 {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= n) return;
-    const int i = cid[p];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int p = pos[i];
     if (a) a[i] = a_c[p];
     if (b) b[i] = b_c[p];
     if (c) c[i] = c_c[p];
@@ -842,10 +845,10 @@ hipError_t launch_curve_rows(const int32_t* idx, const float* d2, int n, int k, 
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_samples(const int32_t* cid, int n, const float* a_c, float* a, const float* b_c, float* b,
-                                  const float* c_c, float* c, hipStream_t st)
+hipError_t launch_gather_samples(const int32_t* pos, int n, const float* a_c, float* a, const float* b_c, float* b,
+                                 const float* c_c, float* c, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scatter_samples, dim3((n + 255) / 256), dim3(256), 0, st, cid, n, a_c, a, b_c, b, c_c, c);
+    hipLaunchKernelGGL(k_gather_samples, dim3((n + 255) / 256), dim3(256), 0, st, pos, n, a_c, a, b_c, b, c_c, c);
     return hipGetLastError();
 }
 
