@@ -143,7 +143,6 @@ __device__ __forceinline__ double wave_row_sums(const int32_t* __restrict__ idx,
                                                 const float* __restrict__ w, double e, int base, int its)
 {
     constexpr int GROUPS = WAVE / RL;   // rows summed at a time
-    const int ITS = its;
     const int lane = lane_id();
     const int g = lane / RL, gl = lane % RL;
     double mine = 0.0;
@@ -163,7 +162,7 @@ __device__ __forceinline__ double wave_row_sums(const int32_t* __restrict__ idx,
         };
         load(0, jv, dv);
 #pragma unroll 1
-        for (int it = 0; it < ITS; ++it) {
+        for (int it = 0; it < its; ++it) {
             const int i = base + GROUPS * it + g;
             float rj[4];
 #pragma unroll
@@ -171,7 +170,7 @@ __device__ __forceinline__ double wave_row_sums(const int32_t* __restrict__ idx,
             const double wi = static_cast<double>(w[i < n ? i : n - 1]);
             int jn[4];
             float dn[4];
-            if (it + 1 < ITS) load(it + 1, jn, dn);
+            if (it + 1 < its) load(it + 1, jn, dn);
             const double inv = 1.0 / (e * wi);
             double s = 0.0;
 #pragma unroll
@@ -195,7 +194,7 @@ __device__ __forceinline__ double wave_row_sums(const int32_t* __restrict__ idx,
         return mine;
     }
 #pragma unroll 1
-    for (int it = 0; it < ITS; ++it) {
+    for (int it = 0; it < its; ++it) {
         const int i = base + GROUPS * it + g;
         const int ic = i < n ? i : n - 1;
         const int64_t rb = row_begin(rowptr, ic, k);
@@ -574,7 +573,8 @@ __global__ __launch_bounds__(256) void k_assemble(const int32_t* __restrict__ id
         }
     }
     // the lanes' compensated sums of at most E terms, added in a fixed xor
-    // butterfly (every lane ends with the same D_i; 64 positive float64 terms)
+    // butterfly (every lane ends with the same D_i; at most 64 E positive
+    // float64 terms)
     double Di = acc.value();
 #pragma unroll
     for (int o = WAVE / 2; o > 0; o >>= 1) Di += shfl_xor_f64(Di, o);
