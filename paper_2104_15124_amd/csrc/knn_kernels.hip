@@ -520,36 +520,79 @@ __device__ __forceinline__ void group_distances(const float* __restrict__ X, int
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         const int cj = (v[s] != KEY_INF) ? static_cast<int>(key_idx(v[s])) : -1;
-        for (int t0 = s * WAVE; t0 < min(kp, (s + 1) * WAVE); t0 += CPW) {
+        const int tend = min(kp, (s + 1) * WAVE);
+        int t0 = s * WAVE;
+        if (vec4) {
+            // two passes at a time: both candidates' pieces are loaded before
+            // either is summed (an invalid slot reads row i and is zeroed)
+            for (; t0 < tend; t0 += 2 * CPW) {
+                const int t1 = t0 + CPW;
+                const int ja = __shfl(cj, (t0 % WAVE) + g, WAVE);
+                const int jb = __shfl(cj, (t1 % WAVE) + g, WAVE);
+                const bool oka = ja >= 0 && ja != i && t0 + g < tend;
+                const bool okb = t1 < tend && jb >= 0 && jb != i && t1 + g < tend;
+                const float* xa = X + static_cast<size_t>(oka ? ja : i) * m;
+                const float* xb = X + static_cast<size_t>(okb ? jb : i) * m;
+                float4 pa[4], pb[4];
+#pragma unroll
+                for (int it = 0; it < 4; ++it) {
+                    const int c = 4 * (gl + LPC * it);
+                    const bool in = it < nit && c < m;
+                    pa[it] = in ? *reinterpret_cast<const float4*>(xa + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    pb[it] = in ? *reinterpret_cast<const float4*>(xb + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                double acca = 0.0, accb = 0.0;
+#pragma unroll
+                for (int it = 0; it < 4; ++it) {
+                    const int c = 4 * (gl + LPC * it);
+                    if (it < nit && c < m) {
+                        const double a0 = static_cast<double>(q4[it].x) - pa[it].x;
+                        const double a1 = static_cast<double>(q4[it].y) - pa[it].y;
+                        const double a2 = static_cast<double>(q4[it].z) - pa[it].z;
+                        const double a3 = static_cast<double>(q4[it].w) - pa[it].w;
+                        acca = fma(a0, a0, acca);
+                        acca = fma(a1, a1, acca);
+                        acca = fma(a2, a2, acca);
+                        acca = fma(a3, a3, acca);
+                        const double b0 = static_cast<double>(q4[it].x) - pb[it].x;
+                        const double b1 = static_cast<double>(q4[it].y) - pb[it].y;
+                        const double b2 = static_cast<double>(q4[it].z) - pb[it].z;
+                        const double b3 = static_cast<double>(q4[it].w) - pb[it].w;
+                        accb = fma(b0, b0, accb);
+                        accb = fma(b1, b1, accb);
+                        accb = fma(b2, b2, accb);
+                        accb = fma(b3, b3, accb);
+                    }
+                }
+                if (!oka) acca = 0.0;
+                if (!okb) accb = 0.0;
+#pragma unroll
+                for (int o = 1; o < LPC; o <<= 1) {
+                    acca += shfl_xor_f64(acca, o);
+                    accb += shfl_xor_f64(accb, o);
+                }
+                // the group leaders' sums go to the owner lanes
+                const int sa = (lane - (t0 % WAVE)) * LPC;
+                const double gota = __shfl(acca, sa >= 0 && sa < WAVE ? sa : 0, WAVE);
+                if (lane >= t0 % WAVE && lane < t0 % WAVE + CPW) d[s] = gota;
+                const int sb = (lane - (t1 % WAVE)) * LPC;
+                const double gotb = __shfl(accb, sb >= 0 && sb < WAVE ? sb : 0, WAVE);
+                if (t1 < tend && lane >= t1 % WAVE && lane < t1 % WAVE + CPW) d[s] = gotb;
+            }
+            continue;
+        }
+        for (; t0 < tend; t0 += CPW) {
             const int owner = (t0 % WAVE) + g;                 // lane holding this group's candidate
             const int j = __shfl(cj, owner, WAVE);
             double acc = 0.0;
             if (j >= 0 && j != i && t0 + g < kp) {
                 const float* xj = X + static_cast<size_t>(j) * m;
-                if (vec4) {
 #pragma unroll
-                    for (int it = 0; it < 4; ++it) {
-                        const int c = 4 * (gl + LPC * it);
-                        if (it < nit && c < m) {
-                            const float4 b = *reinterpret_cast<const float4*>(xj + c);
-                            const double e0 = static_cast<double>(q4[it].x) - b.x;
-                            const double e1 = static_cast<double>(q4[it].y) - b.y;
-                            const double e2 = static_cast<double>(q4[it].z) - b.z;
-                            const double e3 = static_cast<double>(q4[it].w) - b.w;
-                            acc = fma(e0, e0, acc);
-                            acc = fma(e1, e1, acc);
-                            acc = fma(e2, e2, acc);
-                            acc = fma(e3, e3, acc);
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int it = 0; it < QMAX; ++it) {
-                        const int c = gl + LPC * it;
-                        if (it < nit && c < m) {
-                            const double e0 = static_cast<double>(q1[it]) - xj[c];
-                            acc = fma(e0, e0, acc);
-                        }
+                for (int it = 0; it < QMAX; ++it) {
+                    const int c = gl + LPC * it;
+                    if (it < nit && c < m) {
+                        const double e0 = static_cast<double>(q1[it]) - xj[c];
+                        acc = fma(e0, e0, acc);
                     }
                 }
             }
