@@ -291,8 +291,16 @@ __global__ __launch_bounds__(256) void k_prep_rows_thread(const float* __restric
             wmax = static_cast<float>(sqrt(nrm) * (1.0 + 1e-6));
         }
     }
+    // the block's largest norm published with one atomic (one per wavefront
+    // made 125k updates of one address at n = 8M)
+    __shared__ float s_wmax[4];
     wmax = wave_max_f32(wmax);
-    if (lane_id() == 0 && wmax > 0.f) atomicMax(rmax_bits, __float_as_uint(wmax));
+    if (lane_id() == 0) s_wmax[threadIdx.x >> 6] = wmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float bm = fmaxf(fmaxf(s_wmax[0], s_wmax[1]), fmaxf(s_wmax[2], s_wmax[3]));
+        if (bm > 0.f) atomicMax(rmax_bits, __float_as_uint(bm));
+    }
 }
 
 // ------------------------------------------------------------------ select
