@@ -124,6 +124,18 @@ __device__ __forceinline__ size_t bpos(int i, int c, int kpad, int kstep, int ve
 // Rows n..npad-1 pad the last 32-row tile with zeros. With brow non-null the
 // candidate operand row of sample i is written at row brow[i] instead of i
 // (the bucket order of the learned partitioner; npad == n).
+// sum over aligned groups of lpr lanes (16, 32 or 64), every lane of a group
+// receiving it; the xor stages below lpr are those of wave_sum_f64, so where
+// the lanes of a group beyond the row hold 0 the row's sum is the same
+__device__ __forceinline__ double group_sum_f64(double v, int lpr)
+{
+    if (lpr > 32) v += shfl_xor_f64(v, 32);
+    if (lpr > 16) v += shfl_xor_f64(v, 16);
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) v += shfl_xor_f64(v, o);
+    return v;
+}
+
 static int prep_blocks(int npad) { return std::max(1, std::min(4096, (npad + 3) / 4)); }
 
 __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, int n, int npad, int m,
@@ -132,12 +144,18 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
                                                    float* __restrict__ ynorm2, unsigned* __restrict__ rmax_bits,
                                                    const int* __restrict__ brow, const int* __restrict__ arow)
 {
-    // rows are taken in a grid-stride loop; the largest norm is folded per
-    // wavefront and published with one atomic (an atomic per row serialises
-    // millions of updates of one address)
+    // rows are taken in a grid-stride loop, 64 / lpr rows per wavefront (lpr
+    // lanes per row, the power of two >= m from 16 on); the largest norm is
+    // folded per block and published with one atomic (an atomic per row
+    // serialises millions of updates of one address)
     const int lane = lane_id();
+    const int lpr = m <= 16 ? 16 : m <= 32 ? 32 : WAVE;
+    const int rpw = WAVE / lpr, gl = lane % lpr;
     float wmax = 0.f;
-    for (int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); i < npad; i += gridDim.x * 4) {
+    for (int i0 = (blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * rpw; i0 < npad;
+         i0 += gridDim.x * 4 * rpw) {
+        const int i = i0 + lane / lpr;
+        const bool live = i < npad;   // rows past npad (last wavefront): nothing written
         const bool real = i < n;
         const int ib = (brow && real) ? brow[i] : i;   // candidate operand row
         const int ia = (arow && real) ? arow[i] : i;   // query operand row
@@ -147,22 +165,22 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
             constexpr int KS = 2, VE = 1;
             float* A = static_cast<float*>(Aq) + static_cast<size_t>(ia) * kpad;
             float* B = static_cast<float*>(Bc);
-            for (int c = lane; c < m; c += WAVE) {
+            for (int c = gl; c < m; c += lpr) {
                 const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
                 nrm += static_cast<double>(y) * static_cast<double>(y);
                 if (real) A[c] = -2.0f * y;
-                B[bpos(ib, c, kpad, KS, VE)] = y;
+                if (live) B[bpos(ib, c, kpad, KS, VE)] = y;
             }
-            nrm = wave_sum_f64(nrm);
-            for (int c = m + lane; c < kpad; c += WAVE) {
+            nrm = group_sum_f64(nrm, lpr);
+            for (int c = m + gl; c < kpad; c += lpr) {
                 if (real) A[c] = (c == m) ? 1.0f : 0.0f;
-                B[bpos(ib, c, kpad, KS, VE)] = (c == m) ? static_cast<float>(nrm) : 0.0f;
+                if (live) B[bpos(ib, c, kpad, KS, VE)] = (c == m) ? static_cast<float>(nrm) : 0.0f;
             }
         } else {
             constexpr int KS = 16, VE = 8;
             uint16_t* A = static_cast<uint16_t*>(Aq) + static_cast<size_t>(ia) * kpad;
             uint16_t* B = static_cast<uint16_t*>(Bc);
-            for (int c = lane; c < m; c += WAVE) {
+            for (int c = gl; c < m; c += lpr) {
                 const float y = real ? static_cast<float>(static_cast<double>(x[c]) - mu[c]) : 0.0f;
                 nrm += static_cast<double>(y) * static_cast<double>(y);
                 const uint16_t hi = f32_to_bf16_rne(y);
@@ -194,10 +212,10 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
                 }
                 for (int t = 0; t < P; ++t) {
                     if (real) A[t * m + c] = a[t];
-                    B[bpos(ib, t * m + c, kpad, KS, VE)] = b[t];
+                    if (live) B[bpos(ib, t * m + c, kpad, KS, VE)] = b[t];
                 }
             }
-            nrm = wave_sum_f64(nrm);
+            nrm = group_sum_f64(nrm, lpr);
             const int P = split;
             const uint16_t n1 = f32_to_bf16_rne(static_cast<float>(nrm));
             const double r1 = nrm - static_cast<double>(bf16_to_f32(n1));
@@ -205,18 +223,29 @@ __global__ __launch_bounds__(256) void k_prep_rows(const float* __restrict__ X, 
             const double r2 = r1 - static_cast<double>(bf16_to_f32(n2));
             const uint16_t n3 = f32_to_bf16_rne(static_cast<float>(r2));
             const uint16_t one = f32_to_bf16_rne(1.0f);
-            for (int c = P * m + lane; c < kpad; c += WAVE) {
+            for (int c = P * m + gl; c < kpad; c += lpr) {
                 const int t = c - P * m;
                 if (real) A[c] = t < 3 ? one : static_cast<uint16_t>(0);
-                B[bpos(ib, c, kpad, KS, VE)] = t == 0 ? n1 : t == 1 ? n2 : t == 2 ? n3 : static_cast<uint16_t>(0);
+                if (live)
+                    B[bpos(ib, c, kpad, KS, VE)] = t == 0   ? n1
+                                                   : t == 1 ? n2
+                                                   : t == 2 ? n3
+                                                            : static_cast<uint16_t>(0);
             }
         }
-        if (real && lane == 0) {
+        if (real && gl == 0) {
             ynorm2[ia] = static_cast<float>(nrm);   // by query operand row
             wmax = fmaxf(wmax, static_cast<float>(sqrt(nrm) * (1.0 + 1e-6)));
         }
     }
-    if (lane == 0 && wmax > 0.f) atomicMax(rmax_bits, __float_as_uint(wmax));
+    __shared__ float s_wmax[4];
+    wmax = wave_max_f32(wmax);
+    if (lane == 0) s_wmax[threadIdx.x >> 6] = wmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float bm = fmaxf(fmaxf(s_wmax[0], s_wmax[1]), fmaxf(s_wmax[2], s_wmax[3]));
+        if (bm > 0.f) atomicMax(rmax_bits, __float_as_uint(bm));
+    }
 }
 
 // k_prep_rows for FP32 operands of rows of at most PREP_THREAD_M coordinates,
