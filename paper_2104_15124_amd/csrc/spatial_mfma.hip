@@ -280,7 +280,8 @@ __global__ __launch_bounds__(256) void k_zcodes(const float* __restrict__ z, int
 }
 
 // pos[perm[p]] = p; cid[p] = perm[p] for p < n, -1 on the padding up to 32 tiles;
-// zs[p] = z[perm[p]].
+// zs[p] = z[perm[p]]. pos and cid may be null (orders that a later call
+// replaces need only zs).
 __global__ __launch_bounds__(256) void k_curve_maps(const int32_t* __restrict__ perm, int n, int npad,
                                                     const float* __restrict__ z, int32_t* __restrict__ pos,
                                                     int32_t* __restrict__ cid, float* __restrict__ zs)
@@ -289,11 +290,11 @@ __global__ __launch_bounds__(256) void k_curve_maps(const int32_t* __restrict__ 
     if (p >= npad) return;
     if (p < n) {
         const int i = perm[p];
-        pos[i] = p;
-        cid[p] = i;
+        if (pos) pos[i] = p;
+        if (cid) cid[p] = i;
 #pragma unroll
         for (int c = 0; c < PR_DIMS; ++c) zs[static_cast<size_t>(p) * PR_DIMS + c] = z[static_cast<size_t>(i) * PR_DIMS + c];
-    } else {
+    } else if (cid) {
         cid[p] = -1;
     }
 }
@@ -695,7 +696,10 @@ hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, co
                                              8u * PCODE_DIMS, st);
     if (e != hipSuccess) return e;
     const int ntiles = (n + 31) / 32, npad = ntiles * 32;
-    hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, perm, n, npad, z, pos, cid, zs);
+    // with median splits the final order's maps are written at the end; the
+    // splits read only zs
+    hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, perm, n, npad, z,
+                       median_splits ? nullptr : pos, median_splits ? nullptr : cid, zs);
     if (median_splits) {
         // the median splits inside each 4096-tile group of the curve down to
         // 256-tile segments (they read the curve's coordinates; code and scode
@@ -704,8 +708,8 @@ hipError_t launch_curve_order(const float* X, int n, int m, const double* mu, co
         int32_t* split_order = vals;
         hipLaunchKernelGGL(k_kd_group, dim3((n + KG_GROUP - 1) / KG_GROUP), dim3(KG_THREADS), 0, st, perm, zs, n,
                            reinterpret_cast<int32_t*>(code), reinterpret_cast<int32_t*>(scode), split_order);
-        hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, split_order, n, npad, z, pos, cid,
-                           zs);
+        hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, split_order, n, npad, z, nullptr,
+                           nullptr, zs);
         hipLaunchKernelGGL(k_kd_local, dim3((n + KD_GROUP - 1) / KD_GROUP), dim3(KD_THREADS), 0, st, split_order, zs,
                            n);
         hipLaunchKernelGGL(k_curve_maps, dim3((npad + 255) / 256), dim3(256), 0, st, split_order, n, npad, z, pos, cid,
