@@ -362,6 +362,30 @@ __global__ __launch_bounds__(256) void k_gather_rows(const float* __restrict__ X
     Xs[t] = X[static_cast<size_t>(perm[p]) * m + c];
 }
 
+// the same with four coordinates per thread (m a multiple of 4, rows 16-byte aligned)
+__global__ __launch_bounds__(256) void k_gather_rows4(const float4* __restrict__ X, int n, int m4,
+                                                      const int32_t* __restrict__ perm, float4* __restrict__ Xs)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(n) * m4) return;
+    const int p = static_cast<int>(t / m4), c = static_cast<int>(t % m4);
+    Xs[t] = X[static_cast<size_t>(perm[p]) * m4 + c];
+}
+
+// Xs[p] = X[perm[p]], float4 pieces where the rows allow
+static void gather_rows(const float* X, int n, int m, const int32_t* perm, float* Xs, hipStream_t st)
+{
+    const bool v4 =
+        m % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (reinterpret_cast<uintptr_t>(Xs) & 15) == 0;
+    const int64_t tot = static_cast<int64_t>(n) * (v4 ? m / 4 : m);
+    const dim3 grid(static_cast<unsigned>((tot + 255) / 256));
+    if (v4)
+        hipLaunchKernelGGL(k_gather_rows4, grid, dim3(256), 0, st, reinterpret_cast<const float4*>(X), n, m / 4, perm,
+                           reinterpret_cast<float4*>(Xs));
+    else
+        hipLaunchKernelGGL(k_gather_rows, grid, dim3(256), 0, st, X, n, m, perm, Xs);
+}
+
 // Box of `span` consecutive rows starting at row `first` of each group g
 // (rows beyond n are ignored); used for tiles over Xs and for superblocks over
 // tile boxes (span 16, rows = boxes, with `boxes` set).
@@ -1276,9 +1300,7 @@ hipError_t launch_spatial_codes(const float* X, int n, int m, float* bbox_part, 
 hipError_t launch_spatial_layout(const float* X, int n, int m, const int32_t* perm, float* Xs, float* tbox,
                                  float* sbox, hipStream_t st)
 {
-    const int64_t tot = static_cast<int64_t>(n) * m;
-    hipLaunchKernelGGL(k_gather_rows, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st, X, n, m, perm,
-                       Xs);
+    gather_rows(X, n, m, perm, Xs, st);
     const int nt = spatial_tiles(n), ns = spatial_superblocks(n);
     hipLaunchKernelGGL(k_group_boxes, dim3((nt * m + 255) / 256), dim3(256), 0, st, Xs, n, m, TILE, nt, 0, tbox);
     hipLaunchKernelGGL(k_group_boxes, dim3((ns * m + 255) / 256), dim3(256), 0, st, tbox, nt, m, SB_TILES, ns, 1,
@@ -1376,9 +1398,7 @@ hipError_t launch_refine(const float* X, int n, int m, int k, int kp, int kstrid
 
 hipError_t launch_gather_rows(const float* X, int n, int m, const int32_t* perm, float* Xs, hipStream_t st)
 {
-    const int64_t tot = static_cast<int64_t>(n) * m;
-    hipLaunchKernelGGL(k_gather_rows, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st, X, n, m, perm,
-                       Xs);
+    gather_rows(X, n, m, perm, Xs, st);
     return hipGetLastError();
 }
 
